@@ -1,0 +1,307 @@
+"""Plain FP64 CPU oracle for the posterior-precision solves of the spatial GLM.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this module: only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library; it reads only the raw
+synthetic inputs (mask, design, AR coefficients, variances, data, alpha, random
+vectors).
+
+It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
+"Fast Bayesian whole-brain fMRI analysis with spatial 3D priors") defines:
+
+* the masked-grid incidence matrix G_w (here ``D``) with one row per adjacent
+  voxel pair, and the unweighted graph Laplacian D_w = G_w'G_w (here ``G``)
+  -- Section 2 (prior on W_k) and Section 3.1 (the G_w construction);
+* the per-voxel data term B_n, b_n of the AR(P) likelihood by explicit
+  whitening -- Appendix A.2 (temporal likelihood, full conditional of W);
+* the precision of w_r = vec(W') (k-major), Q = diag(alpha) (x) D_w + H'blkdiag(B_n)H
+  -- Section 3, full conditional of w_r, and Appendix A.2;
+* mean solves x = Q^{-1} b -- Section 3.1 (PCG paragraph, relative residual
+  criterion);
+* perturbation samples w = Q^{-1}(b_w + (blkdiag_k sqrt(alpha_k) G_w)' z1
+  + H'L_data H z2) -- Algorithm 2;
+* Cholesky-based mean and sample -- Algorithm 1 (dense, tiny grids only);
+* Hutchinson estimates with Rademacher probes of tr(Q^{-1}), of tr([Q^{-1}]_kk)
+  and of tr(D_w [Q^{-1}]_kk), the trace inside E[W_k D_w W_k'] of Section 3.3
+  (quadratic-form expectation).
+
+Readings where the paper is silent (all repeated in the design notes):
+voxel order is x-fastest raster over in-mask voxels; the stencil has a free
+boundary (the diagonal of D_w is the in-mask degree); edge (n, n+e_d) is
+oriented +1 at n and -1 at n+e_d; z1 carries one N(0,1) entry per regressor
+and edge (K*E in total); the relative residual uses the Euclidean norm over all
+K*N entries of one right-hand side.
+
+Parity status: every function here is pinned by a test that does not re-use it
+(closed forms, brute force, exact rational arithmetic, identities, statistics);
+none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+__all__ = [
+    "Grid", "grid", "data_term_whitening", "precision", "apply", "relres",
+    "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
+    "sample", "hutchinson", "cholesky_mean_and_sample",
+]
+
+
+# ------------------------------------------------------------------ grid / prior
+class Grid:
+    """Mask bookkeeping plus the incidence matrix D and Laplacian G = D'D."""
+
+    def __init__(self, mask: np.ndarray, conn: int):
+        if conn not in (4, 6):
+            raise ValueError("conn must be 4 or 6")
+        m = np.asarray(mask).astype(bool)
+        if m.ndim == 2:
+            m = m[None]
+        self.mask = m
+        self.conn = conn
+        nz, ny, nx = m.shape
+        self.nx, self.ny, self.nz = nx, ny, nz
+        flat = m.ravel()
+        self.lin = np.flatnonzero(flat)                  # compact n -> linear l
+        self.N = int(self.lin.size)
+        self.index = -np.ones(flat.size, dtype=np.int64)  # linear l -> compact n
+        self.index[self.lin] = np.arange(self.N)
+        x = self.lin % nx
+        y = (self.lin // nx) % ny
+        z = self.lin // (nx * ny)
+        self.coords = np.stack([x, y, z], axis=1)
+        dirs = [(1, 0, 0), (0, 1, 0)] + ([(0, 0, 1)] if conn == 6 else [])
+        self.ndirs = len(dirs)
+        # Edge list: for each direction d and voxel n with n+e_d inside the mask,
+        # one edge (n, n+e_d).  Edges are ordered direction-major, then by n.
+        self.edge_dir, self.edge_lo, self.edge_hi = [], [], []
+        for d, (dx, dy, dz) in enumerate(dirs):
+            xx, yy, zz = x + dx, y + dy, z + dz
+            ok = (xx < nx) & (yy < ny) & (zz < nz)
+            far = np.full(self.N, -1, dtype=np.int64)
+            far[ok] = self.index[xx[ok] + nx * (yy[ok] + ny * zz[ok])]
+            keep = far >= 0
+            self.edge_dir.append(np.full(int(keep.sum()), d))
+            self.edge_lo.append(np.flatnonzero(keep))
+            self.edge_hi.append(far[keep])
+        self.edge_dir = np.concatenate(self.edge_dir)
+        self.edge_lo = np.concatenate(self.edge_lo)
+        self.edge_hi = np.concatenate(self.edge_hi)
+        self.E = int(self.edge_lo.size)
+        e = np.arange(self.E)
+        # G_w: one row per adjacent pair, +1 at the first voxel, -1 at the second
+        # (Section 3.1, increments of adjacent voxels are iid normal).
+        self.D = sp.csr_matrix(
+            (np.r_[np.ones(self.E), -np.ones(self.E)],
+             (np.r_[e, e], np.r_[self.edge_lo, self.edge_hi])),
+            shape=(self.E, self.N))
+        # D_w = G_w'G_w: in-mask degree on the diagonal, -1 for adjacent pairs
+        # (Section 2, unweighted graph Laplacian).
+        self.G = (self.D.T @ self.D).tocsr()
+
+
+def grid(mask, conn) -> Grid:
+    return Grid(mask, conn)
+
+
+# --------------------------------------------------------------------- data term
+def data_term_whitening(X: np.ndarray, Y: np.ndarray, ar: np.ndarray, sigma2: np.ndarray):
+    """B_n and b_n of the AR(P) likelihood, conditional on the first P scans.
+
+    Appendix A.2: the residual at scan t is (y_t - x_t W) minus the AR
+    prediction from the P previous residuals, with noise precision
+    lambda_n = 1/sigma2_n.  Written out: the whitening matrix A_n ((T-P) x T)
+    has rows [-a_P .. -a_1, 1]; Xw = A_n X, yw = A_n y_n; B_n = lambda_n Xw'Xw
+    and b_n = lambda_n Xw'yw.  Returns B (N, K, K) and b_w (K, N), the latter in
+    the k-major layout of w_r = vec(W').
+    """
+    T, K = X.shape
+    P, N = ar.shape
+    B = np.empty((N, K, K))
+    bw = np.empty((K, N))
+    for n in range(N):
+        A = np.zeros((T - P, T))
+        for i, t in enumerate(range(P, T)):
+            A[i, t] = 1.0
+            for p in range(1, P + 1):
+                A[i, t - p] = -ar[p - 1, n]
+        Xw = A @ X
+        yw = A @ Y[:, n]
+        lam = 1.0 / sigma2[n]
+        B[n] = lam * (Xw.T @ Xw)
+        bw[:, n] = lam * (Xw.T @ yw)
+    return B, bw
+
+
+# ---------------------------------------------------------------------- operator
+def blocks_kmajor(B: np.ndarray) -> sp.csr_matrix:
+    """H' blkdiag_n(B_n) H: the data term in the k-major (w_r) ordering.
+
+    Entry ((k, n), (j, m)) equals B_n[k, j] when n == m (Section 3 and
+    Appendix A.2, with H the permutation between vec(W) and vec(W'))."""
+    N, K, _ = B.shape
+    return sp.bmat([[sp.diags(B[:, k, j]) for j in range(K)] for k in range(K)]).tocsr()
+
+
+def precision(g: Grid, alpha: np.ndarray, B: np.ndarray) -> sp.csr_matrix:
+    """Q = diag(alpha) (x) D_w + H'blkdiag(B_n)H, size KN x KN, k-major.
+
+    Section 3 (full conditional of w_r) and Appendix A.2 (temporal model)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    prior = sp.kron(sp.diags(alpha), g.G)
+    return (prior + blocks_kmajor(B)).tocsr()
+
+
+def apply(Q: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
+    """y = Q x for one or many right-hand sides laid out (R, K, N) or (K, N)."""
+    x = np.asarray(x, dtype=np.float64)
+    flat = x.reshape(-1, Q.shape[0])
+    return (Q @ flat.T).T.reshape(x.shape)
+
+
+def relres(Q, x, b) -> np.ndarray:
+    """||b - Qx||_2 / ||b||_2 per right-hand side (Section 3.1, PCG stopping rule)."""
+    x = np.asarray(x).reshape(-1, Q.shape[0])
+    b = np.asarray(b).reshape(-1, Q.shape[0])
+    r = b - (Q @ x.T).T
+    nb = np.linalg.norm(b, axis=1)
+    out = np.linalg.norm(r, axis=1) / np.where(nb > 0, nb, 1.0)
+    return np.where(nb > 0, out, 0.0)
+
+
+# ------------------------------------------------------------------------- solve
+def solve_direct(Q: sp.spmatrix, b: np.ndarray) -> np.ndarray:
+    """x = Q^{-1} b by a sparse direct factorisation (small operators only)."""
+    lu = spl.splu(sp.csc_matrix(Q))
+    flat = np.asarray(b, dtype=np.float64).reshape(-1, Q.shape[0])
+    return np.stack([lu.solve(v) for v in flat]).reshape(np.shape(b))
+
+
+def solve_pcg(Q: sp.csr_matrix, b: np.ndarray, tol: float = 1e-13, maxiter: int = 20000,
+              x0: np.ndarray | None = None):
+    """Preconditioned conjugate gradients in FP64 with the diagonal of Q as
+    preconditioner, for one right-hand side, iterated until the relative
+    residual ||b - Qx|| / ||b|| falls below ``tol`` (Section 3.1: PCG with a
+    relative-residual tolerance delta; this is the textbook iteration of the
+    Barrett et al. templates).  Returns (x, iterations, relres)."""
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    dinv = 1.0 / Q.diagonal()
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64).ravel().copy()
+    r = b - Q @ x
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while np.linalg.norm(r) > tol * nb and it < maxiter:
+        q = Q @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        it += 1
+        if it % 50 == 0:                      # guard against recursive-residual drift
+            r = b - Q @ x
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    rr = np.linalg.norm(b - Q @ x) / nb
+    return x, it, rr
+
+
+def solve(Q: sp.csr_matrix, b: np.ndarray, tol: float = 1e-13, direct_limit: int = 20000):
+    """x = Q^{-1} b for b shaped (R, K, N) or (K, N).  A sparse direct solve
+    when KN <= direct_limit, otherwise FP64 PCG to relative residual ``tol``."""
+    b = np.asarray(b, dtype=np.float64)
+    if Q.shape[0] <= direct_limit:
+        return solve_direct(Q, b)
+    flat = b.reshape(-1, Q.shape[0])
+    out = np.stack([solve_pcg(Q, v, tol)[0] for v in flat])
+    return out.reshape(b.shape)
+
+
+# --------------------------------------------------------------------- sampling
+def edge_slots(g: Grid) -> np.ndarray:
+    """For each edge, its slot (d, n_lo) in a z1 array laid out (K, dirs, N)."""
+    return g.edge_dir * g.N + g.edge_lo
+
+
+def perturbation_rhs(g: Grid, alpha, B, bw, z1, z2) -> np.ndarray:
+    """Algorithm 2, step 4:
+    b = (blkdiag_k sqrt(alpha_k) G_w)' z1 + H'L_data H z2 + b_w,
+    with L_data the lower Cholesky factor of blkdiag_n(B_n).
+
+    z1 arrives as (R, K, dirs, N) slots, one per (regressor, direction, voxel);
+    the slot (k, d, n) holds the entry of edge (n, n+e_d) and slots without an
+    edge are ignored.  z2 is (R, K, N); b_w is (K, N).  Returns (R, K, N)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    z1 = np.asarray(z1, dtype=np.float64)
+    z2 = np.asarray(z2, dtype=np.float64)
+    R, K = z2.shape[0], z2.shape[1]
+    N = g.N
+    slots = edge_slots(g)
+    L = np.linalg.cholesky(B)                                  # (N, K, K) lower
+    out = np.empty((R, K, N))
+    for r in range(R):
+        ze = z1[r].reshape(K, -1)[:, slots]                    # (K, E)
+        prior = np.stack([np.sqrt(alpha[k]) * (g.D.T @ ze[k]) for k in range(K)])
+        data = np.einsum("nkj,jn->kn", L, z2[r])
+        out[r] = bw + prior + data
+    return out
+
+
+def perturbation_factor(g: Grid, alpha, B) -> np.ndarray:
+    """Dense S = [(blkdiag_k sqrt(alpha_k) G_w)' | H'L_data H] (KN x (KE + KN));
+    S S' equals Q (the identity behind Algorithm 2).  Tiny grids only."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    N, K, _ = B.shape
+    D = g.D.toarray()
+    L = np.linalg.cholesky(B)
+    left = np.zeros((K * N, K * g.E))
+    right = np.zeros((K * N, K * N))
+    for k in range(K):
+        left[k * N:(k + 1) * N, k * g.E:(k + 1) * g.E] = np.sqrt(alpha[k]) * D.T
+        for j in range(K):
+            right[k * N:(k + 1) * N, j * N:(j + 1) * N] = np.diag(L[:, k, j])
+    return np.hstack([left, right])
+
+
+def sample(g: Grid, alpha, B, bw, z1, z2, tol: float = 1e-13) -> np.ndarray:
+    """Algorithm 2: w = Q^{-1} b with the perturbed right-hand side above."""
+    Q = precision(g, alpha, B)
+    return solve(Q, perturbation_rhs(g, alpha, B, bw, z1, z2), tol)
+
+
+def cholesky_mean_and_sample(Q: sp.spmatrix, bw: np.ndarray, z: np.ndarray):
+    """Algorithm 1 without reordering, dense: Q = L L', L x = b_w, L' mu = x,
+    L' v = z, w = mu + v.  Returns (mu, w).  Tiny operators only."""
+    from scipy.linalg import solve_triangular
+    L = np.linalg.cholesky(Q.toarray())
+    x = solve_triangular(L, np.asarray(bw).ravel(), lower=True)
+    mu = solve_triangular(L.T, x, lower=False)
+    v = solve_triangular(L.T, np.asarray(z).ravel(), lower=False)
+    return mu.reshape(np.shape(bw)), (mu + v).reshape(np.shape(bw))
+
+
+# ---------------------------------------------------------------------- traces
+def hutchinson(g: Grid, Q: sp.csr_matrix, probes: np.ndarray, tol: float = 1e-13,
+               u: np.ndarray | None = None):
+    """Hutchinson estimates from Rademacher probes v_i (m, K, N):
+
+        t   = (1/m) sum_i v_i' Q^{-1} v_i                ~ tr(Q^{-1})
+        t_k = (1/m) sum_i v_ik' [Q^{-1} v_i]_k            ~ tr([Q^{-1}]_kk)
+        g_k = (1/m) sum_i (D_w v_ik)' [Q^{-1} v_i]_k      ~ tr(D_w [Q^{-1}]_kk)
+
+    The last is the trace term of E[W_k D_w W_k'] in Section 3.3.  ``u`` may
+    carry precomputed solutions Q^{-1} v_i.  Returns (t, t_k, g_k, u)."""
+    v = np.asarray(probes, dtype=np.float64)
+    m, K, N = v.shape
+    if u is None:
+        u = solve(Q, v, tol)
+    tk = np.einsum("ikn,ikn->k", v, u) / m
+    gk = np.array([sum((g.G @ v[i, k]) @ u[i, k] for i in range(m)) for k in range(K)]) / m
+    return float(tk.sum()), tk, gk, u
