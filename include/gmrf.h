@@ -1,0 +1,209 @@
+/*
+ * gmrf.h -- C ABI of the MI355X GMRF posterior-precision library.
+ *
+ * The library solves, samples from and estimates traces of the Gaussian
+ * Markov random field posterior of the spatial GLM for fMRI of Siden, Eklund,
+ * Bolin and Villani (Fast Bayesian whole-brain fMRI analysis with spatial 3D
+ * priors):
+ *
+ *   w_r = vec(W') ~ N(Q^{-1} b, Q^{-1}),
+ *   Q   = diag(alpha) (x) D_w  +  H' blkdiag_n(B_n) H           (Section 3,
+ *         full conditional of w_r; Appendix A.2 for the AR(P) data term)
+ *
+ * where D_w = G_w'G_w is the unweighted graph Laplacian of a 3D (6-neighbour)
+ * or 2D (4-neighbour) voxel mask (Section 2 and Section 3.1), B_n is the SPD
+ * K x K data block of voxel n and H is the permutation between voxel-major
+ * and k-major ordering.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every function returns GP_OK (0) or a negative GP_ERR_* code.
+ *    gp_last_error() returns a message for the calling thread's last failure.
+ *    No C++ exception crosses this boundary.
+ *  - Memory: pointers documented as "device" are HIP device pointers on the
+ *    context's device; "host" pointers are ordinary host memory.  The caller
+ *    owns every buffer it passes; the library never frees caller memory.  The
+ *    library owns operator data and solver workspace, charged to the
+ *    context's HBM budget.
+ *  - Ordering: work is issued on the context's HIP stream.  Functions that
+ *    return statistics or host results block until that work has completed;
+ *    the others are stream-ordered and return after enqueueing.
+ *  - Voxels: in-mask voxels are numbered n = 0..N-1 in increasing linear index
+ *    l = x + nx*(y + ny*z) (x fastest).
+ *  - Vectors: a batch of R vectors is contiguous FP64 laid out [R][K][N]; each
+ *    [K][N] slab is the paper's k-major w_r = vec(W') (Section 3).
+ *  - Data blocks: FP64 [N][K][K], row-major, symmetric (the two triangles are
+ *    averaged).
+ *  - Threads: one context must not be used by two threads at once; calls that
+ *    overlap on one context return GP_ERR_BUSY.
+ */
+#ifndef GMRF_H
+#define GMRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GP_OK                 0
+#define GP_ERR_INVALID_ARG   -1  /* bad size, pointer, enum, or state        */
+#define GP_ERR_NOT_SPD       -2  /* a K x K block is not positive definite    */
+#define GP_ERR_OOM           -3  /* HBM budget or device allocation exceeded  */
+#define GP_ERR_BUSY          -4  /* the context is in use by another call     */
+#define GP_ERR_NOT_CONVERGED -5  /* iteration cap reached before tolerance    */
+#define GP_ERR_BREAKDOWN     -6  /* non-finite value or loss of definiteness  */
+#define GP_ERR_DEVICE        -7  /* a HIP runtime call failed                 */
+
+/* ---- preconditioners and precision modes ----------------------------- */
+#define GP_PRECOND_JACOBI        0  /* inverse of diag(Q)                      */
+#define GP_PRECOND_BLOCK_JACOBI  1  /* inverse of each voxel's K x K block of Q */
+
+#define GP_PREC_FP64          0  /* every step in FP64                          */
+#define GP_PREC_FP32_REFINE64 1  /* FP32 inner PCG, FP64 residual/update/test   */
+
+typedef struct gp_ctx gp_ctx;
+typedef struct gp_op gp_op;
+
+/* Solver options.  Initialise with gp_opts_default(). */
+typedef struct gp_opts {
+  double   tol;        /* stop when ||b - Q x||_2 / ||b||_2 <= tol, per right-hand
+                          side, with the residual recomputed in FP64 (Section
+                          3.1, PCG tolerance delta).  Default 1e-8.             */
+  double   inner_tol;  /* FP32 mode: each inner solve reduces its residual by
+                          this factor before the next FP64 refinement step.
+                          Default 1e-4.  Ignored in FP64 mode.                  */
+  int      max_iter;   /* cap on PCG iterations summed over refinement steps
+                          (default 2000)                                        */
+  int      max_outer;  /* cap on FP64 residual evaluations (default 30)         */
+  int      precond;    /* GP_PRECOND_*; default GP_PRECOND_BLOCK_JACOBI          */
+  int      precision;  /* GP_PREC_*; default GP_PREC_FP32_REFINE64              */
+  int      rhs_tile;   /* right-hand sides per workgroup, 0 = automatic          */
+  int      chunk;      /* PCG iterations enqueued between host checks, 0 = auto  */
+  uint64_t seed;       /* reserved for on-device random vectors                  */
+} gp_opts;
+
+/* Per right-hand-side result. */
+typedef struct gp_stats {
+  int    status;       /* GP_OK, GP_ERR_NOT_CONVERGED or GP_ERR_BREAKDOWN        */
+  int    inner_iters;  /* PCG iterations (all refinement steps)                  */
+  int    outer_steps;  /* FP64 residual evaluations                              */
+  int    reserved;
+  double relres;       /* final FP64 ||b - Q x|| / ||b|| (0 when b = 0)          */
+  double time_us;      /* wall time of the whole call, microseconds              */
+} gp_stats;
+
+/* One solve in a batch: R right-hand sides of one operator. */
+typedef struct gp_item {
+  gp_op*        op;
+  int           R;
+  const double* b;     /* device, [R][K][N]                                     */
+  double*       x;     /* device, [R][K][N]; in: start value, out: solution      */
+} gp_item;
+
+void        gp_opts_default(gp_opts* opts);
+const char* gp_last_error(void);
+int         gp_version(void);
+
+/* ---- context ----------------------------------------------------------
+ * gp_ctx_create: bind to HIP device `device`, issue work on `hip_stream`
+ * (a hipStream_t; NULL selects the device's null stream) and cap the bytes
+ * the library may allocate at `hbm_budget` (0 = no cap).                    */
+int gp_ctx_create(int device, void* hip_stream, size_t hbm_budget, gp_ctx** out);
+int gp_ctx_set_stream(gp_ctx* ctx, void* hip_stream);
+/* bytes currently allocated by the library for this context (host out)     */
+int gp_ctx_memory(const gp_ctx* ctx, size_t* used, size_t* budget);
+int gp_ctx_destroy(gp_ctx* ctx);
+
+/* ---- operator ----------------------------------------------------------
+ * gp_op_create: build the masked-grid operator (Section 2: the unweighted
+ * graph Laplacian over in-mask neighbours, free boundary; Section 3.1: one
+ * incidence row per adjacent pair).  mask_host: host, nx*ny*nz bytes, nonzero
+ * = in mask, linear index l = x + nx*(y + ny*z).  conn: 6 (3D) or 4 (2D, then
+ * nz must be 1).  K: regressors, 1..16.  Rejects an empty mask.  The
+ * operator is unusable until gp_op_set_blocks and gp_op_set_alpha succeed.  */
+int gp_op_create(gp_ctx* ctx, const uint8_t* mask_host, int nx, int ny, int nz,
+                 int conn, int K, gp_op** out);
+
+/* gp_op_set_blocks: ingest the data blocks B_n (device, FP64 [N][K][K]; the
+ * X'X (x) diag(lambda) term of Section 3, or the AR(P) blocks of Appendix
+ * A.2) and factor each as B_n = L_n L_n' (the L_data of Algorithm 2).
+ * Returns GP_ERR_NOT_SPD if some block is not positive definite; then
+ * *bad_voxel_host (if non-NULL) receives the smallest failing voxel.
+ * Rebuilds the preconditioner when alpha is already set.                   */
+int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel_host);
+
+/* gp_op_set_alpha: spatial precisions alpha_k >= 0 (host, K doubles; the
+ * prior precision of regressor k, Section 2).  Rebuilds the preconditioner
+ * (the K x K voxel blocks B_n + diag(alpha_k deg_n) and their inverses).     */
+int gp_op_set_alpha(gp_op* op, const double* alpha_host);
+
+/* gp_op_query: any out pointer may be NULL.  N voxels, E adjacent pairs
+ * (rows of G_w), K, and device bytes held by the operator.                  */
+int gp_op_query(const gp_op* op, int64_t* N, int64_t* E, int* K, size_t* bytes);
+
+/* gp_op_voxel_index: device int32 [N] receives the linear index of voxel n. */
+int gp_op_voxel_index(const gp_op* op, int32_t* lin);
+int gp_op_destroy(gp_op* op);
+
+/* ---- operations -------------------------------------------------------- */
+
+/* gp_apply: y = Q x in FP64 for R vectors (device [R][K][N] each); the
+ * product of Section 3's precision with a vector.  Stream-ordered.          */
+int gp_apply(gp_op* op, int R, const double* x, double* y);
+
+/* gp_solve: x = Q^{-1} b for R right-hand sides by preconditioned conjugate
+ * gradients (Section 3.1), stopping each right-hand side when its FP64
+ * relative residual is <= opts->tol.  b: device [R][K][N]; x: device
+ * [R][K][N], read as the start value (the warm start of Section 3.1) and
+ * overwritten with the solution.  A zero b gives x = 0 after no iterations.
+ * stats: host array of R entries (may be NULL).  Returns GP_OK when every
+ * right-hand side converged, else the first failing status.  Blocking.     */
+int gp_solve(gp_op* op, int R, const double* b, double* x, const gp_opts* opts,
+             gp_stats* stats);
+
+/* gp_solve_batch: the solves of n items (uneven operators and R) advanced
+ * together, one grouped launch per kernel and step.  stats: host array of
+ * sum(items[i].R) entries in item order (may be NULL).  Blocking.            */
+int gp_solve_batch(gp_ctx* ctx, int n, const gp_item* items, const gp_opts* opts,
+                   gp_stats* stats);
+
+/* gp_perturb_rhs: Algorithm 2, step 4, for R draws:
+ *   b_r = b_w + (blkdiag_k sqrt(alpha_k) G_w)' z1_r + H' L_data H z2_r.
+ * bw: device [K][N] (shared by all draws); z1: device [R][K][dirs][N] with
+ * dirs = 3 (3D: +x,+y,+z) or 2 (2D: +x,+y), slot (k,d,n) holding the entry of
+ * the adjacent pair (n, n+e_d) -- slots whose n+e_d lies outside the mask are
+ * ignored; z2: device [R][K][N]; b: device [R][K][N] output.  Stream-ordered. */
+int gp_perturb_rhs(gp_op* op, int R, const double* bw, const double* z1,
+                   const double* z2, double* b);
+
+/* gp_sample: Algorithm 2 -- gp_perturb_rhs then gp_solve.  w: device
+ * [R][K][N], in: start values, out: samples.  Blocking.                      */
+int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double* z2,
+              double* w, const gp_opts* opts, gp_stats* stats);
+
+/* gp_probe_rhs: b_i = v_i as FP64 (device int8 [m][K][N] in {-1,+1} to device
+ * FP64 [m][K][N]).  Stream-ordered.                                          */
+int gp_probe_rhs(gp_op* op, int m, const int8_t* probes, double* b);
+
+/* gp_trace_reduce: Hutchinson estimates from probes v_i and solutions
+ * u_i = Q^{-1} v_i (device int8 [m][K][N], device FP64 [m][K][N]):
+ *   tr_total = (1/m) sum_i v_i'u_i                ~ tr(Q^{-1})
+ *   tr_kk[k] = (1/m) sum_i v_ik'u_ik              ~ tr([Q^{-1}]_kk)
+ *   tr_Gkk[k]= (1/m) sum_i (D_w v_ik)'u_ik        ~ tr(D_w [Q^{-1}]_kk)
+ * the last being the trace in E[W_k D_w W_k'] (Section 3.3).  Host outputs
+ * (tr_kk, tr_Gkk: K doubles each; any may be NULL).  Blocking.               */
+int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u,
+                    double* tr_total, double* tr_kk, double* tr_Gkk);
+
+/* gp_trace: gp_probe_rhs, gp_solve from u = 0, gp_trace_reduce.  u: device
+ * FP64 [m][K][N] workspace that receives the solutions.  Blocking.           */
+int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total,
+             double* tr_kk, double* tr_Gkk, const gp_opts* opts, gp_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMRF_H */

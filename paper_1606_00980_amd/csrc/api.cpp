@@ -1,0 +1,850 @@
+// Host runtime behind the C ABI of gmrf.h: contexts with an HBM budget,
+// operator construction, preconditioner set-up and the PCG driver that
+// advances grouped launches of the kernels in pcg.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gmrf.h"
+#include "launch.hpp"
+
+using namespace gp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPTRY(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(GP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct gp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0, used = 0;
+  std::atomic<int> busy{0};
+  // solver workspace arena (grown on demand, reused across calls)
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  // right-hand-side staging for sample/trace
+  double* rhs = nullptr;
+  size_t rhs_cap = 0;
+  // grouped-launch descriptors and phase summaries
+  Prob* d_probs = nullptr;
+  Prob* h_probs = nullptr;
+  size_t probs_cap = 0;
+  int* h_summary = nullptr;
+  size_t summary_cap = 0;
+};
+
+struct gp_op {
+  gp_ctx* ctx = nullptr;
+  int N = 0, K = 0, nx = 0, ny = 0, nz = 0, conn = 0, dirs = 0, ntiles = 0;
+  int64_t E = 0;
+  int* nbr = nullptr;
+  int* lin = nullptr;
+  double* B64 = nullptr;
+  float* B32 = nullptr;
+  double* L64 = nullptr;
+  double* P64 = nullptr;
+  float* P32 = nullptr;
+  int* d_bad = nullptr;
+  double* tr_part = nullptr;
+  size_t tr_cap = 0;
+  double alpha[KMAX] = {0};
+  bool have_blocks = false, have_alpha = false;
+  int pc_built = -1;
+  int pc_want = GP_PRECOND_BLOCK_JACOBI;
+  size_t bytes = 0;
+};
+
+namespace {
+
+struct BusyGuard {
+  gp_ctx* c;
+  bool ok;
+  explicit BusyGuard(gp_ctx* ctx) : c(ctx) {
+    int expect = 0;
+    ok = c->busy.compare_exchange_strong(expect, 1);
+  }
+  ~BusyGuard() {
+    if (ok) c->busy.store(0);
+  }
+};
+
+int set_device(gp_ctx* c) {
+  HIPTRY(hipSetDevice(c->device));
+  return GP_OK;
+}
+
+int dev_alloc(gp_ctx* c, size_t bytes, void** p) {
+  bytes = align_up(std::max<size_t>(bytes, 1), 256);
+  if (c->budget && c->used + bytes > c->budget)
+    return fail(GP_ERR_OOM, "HBM budget exceeded: need " + std::to_string(bytes) + " more bytes, " +
+                                std::to_string(c->budget - c->used) + " left");
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GP_ERR_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  c->used += bytes;
+  return GP_OK;
+}
+
+void dev_free(gp_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  bytes = align_up(std::max<size_t>(bytes, 1), 256);
+  c->used -= std::min(c->used, bytes);
+}
+
+template <typename T>
+int op_alloc(gp_op* op, size_t count, T** p) {
+  const size_t bytes = count * sizeof(T);
+  int st = dev_alloc(op->ctx, bytes, (void**)p);
+  if (st == GP_OK) op->bytes += align_up(std::max<size_t>(bytes, 1), 256);
+  return st;
+}
+
+template <typename T>
+void op_free(gp_op* op, T*& p, size_t count) {
+  if (!p) return;
+  dev_free(op->ctx, p, count * sizeof(T));
+  p = nullptr;
+}
+
+int ensure_ws(gp_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_cap) return GP_OK;
+  if (c->ws) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    dev_free(c, c->ws, c->ws_cap);
+    c->ws = nullptr;
+    c->ws_cap = 0;
+  }
+  const size_t want = align_up(bytes + bytes / 4, 1 << 20);
+  int st = dev_alloc(c, want, &c->ws);
+  if (st != GP_OK) {
+    st = dev_alloc(c, bytes, &c->ws);
+    if (st != GP_OK) return st;
+    c->ws_cap = align_up(bytes, 256);
+    return GP_OK;
+  }
+  c->ws_cap = want;
+  return GP_OK;
+}
+
+int ensure_rhs(gp_ctx* c, size_t count) {
+  if (count <= c->rhs_cap) return GP_OK;
+  if (c->rhs) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    dev_free(c, c->rhs, c->rhs_cap * sizeof(double));
+    c->rhs = nullptr;
+    c->rhs_cap = 0;
+  }
+  int st = dev_alloc(c, count * sizeof(double), (void**)&c->rhs);
+  if (st != GP_OK) return st;
+  c->rhs_cap = count;
+  return GP_OK;
+}
+
+int ensure_probs(gp_ctx* c, size_t n) {
+  if (n <= c->probs_cap) return GP_OK;
+  if (c->d_probs) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
+    (void)hipHostFree(c->h_probs);
+    (void)hipHostFree(c->h_summary);
+    c->d_probs = nullptr;
+    c->h_probs = nullptr;
+    c->h_summary = nullptr;
+  }
+  const size_t cap = std::max<size_t>(n, 16);
+  int st = dev_alloc(c, cap * sizeof(Prob), (void**)&c->d_probs);
+  if (st != GP_OK) return st;
+  HIPTRY(hipHostMalloc((void**)&c->h_probs, cap * sizeof(Prob), hipHostMallocDefault));
+  HIPTRY(hipHostMalloc((void**)&c->h_summary, cap * NSUM * sizeof(int), hipHostMallocDefault));
+  c->probs_cap = cap;
+  return GP_OK;
+}
+
+OpDev op_dev(const gp_op* op) {
+  OpDev d;
+  std::memset(&d, 0, sizeof(d));
+  d.nbr = op->nbr;
+  d.B64 = op->B64;
+  d.B32 = op->B32;
+  d.P64 = op->P64;
+  d.P32 = op->P32;
+  d.L64 = op->L64;
+  d.N = op->N;
+  d.K = op->K;
+  d.ntiles = op->ntiles;
+  d.dirs = op->dirs;
+  for (int k = 0; k < op->K; ++k) {
+    d.alpha64[k] = op->alpha[k];
+    d.alpha32[k] = (float)op->alpha[k];
+  }
+  return d;
+}
+
+int read_bad(gp_op* op, int* bad) {
+  HIPTRY(hipMemcpyAsync(bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, op->ctx->stream));
+  HIPTRY(hipStreamSynchronize(op->ctx->stream));
+  return GP_OK;
+}
+
+int reset_bad(gp_op* op) {
+  static const int big = INT_MAX;
+  HIPTRY(hipMemcpyAsync(op->d_bad, &big, sizeof(int), hipMemcpyHostToDevice, op->ctx->stream));
+  return GP_OK;
+}
+
+int build_precond(gp_op* op, int pc) {
+  if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  int st = reset_bad(op);
+  if (st) return st;
+  const OpDev d = op_dev(op);
+  HIPTRY(launch_precond(op->ctx->stream, d, pc == GP_PRECOND_JACOBI ? PC_JACOBI : PC_BLOCK, op->P64, op->P32,
+                        op->d_bad));
+  int bad = INT_MAX;
+  st = read_bad(op, &bad);
+  if (st) return st;
+  if (bad != INT_MAX) {
+    op->pc_built = -1;
+    return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(bad) + " is not positive definite");
+  }
+  op->pc_built = pc;
+  return GP_OK;
+}
+
+bool valid_opts(const gp_opts& o, std::string* why) {
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return *why = "tol must be positive", false;
+  if (o.precision == GP_PREC_FP32_REFINE64 && !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
+    return *why = "inner_tol must lie in (0, 1)", false;
+  if (o.max_iter < 1) return *why = "max_iter must be >= 1", false;
+  if (o.max_outer < 1) return *why = "max_outer must be >= 1", false;
+  if (o.precond != GP_PRECOND_JACOBI && o.precond != GP_PRECOND_BLOCK_JACOBI)
+    return *why = "unknown preconditioner", false;
+  if (o.precision != GP_PREC_FP64 && o.precision != GP_PREC_FP32_REFINE64) return *why = "unknown precision", false;
+  if (o.rhs_tile < 0 || o.chunk < 0) return *why = "rhs_tile and chunk must be >= 0", false;
+  return true;
+}
+
+struct Item {
+  gp_op* op;
+  int R;
+  const double* b;
+  double* x;
+};
+
+// ------------------------------------------------------------- PCG driver
+int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::string why;
+  if (!valid_opts(o, &why)) return fail(GP_ERR_INVALID_ARG, why);
+  const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  size_t totalR = 0;
+  for (const Item& it : items) {
+    if (!it.op || it.op->ctx != c) return fail(GP_ERR_INVALID_ARG, "item operator missing or from another context");
+    if (it.R < 0) return fail(GP_ERR_INVALID_ARG, "R must be >= 0");
+    if (it.R > 0 && (!it.b || !it.x)) return fail(GP_ERR_INVALID_ARG, "null b or x");
+    if (!it.op->have_blocks || !it.op->have_alpha)
+      return fail(GP_ERR_INVALID_ARG, "operator needs gp_op_set_blocks and gp_op_set_alpha first");
+    totalR += (size_t)it.R;
+  }
+  // preconditioners
+  for (const Item& it : items) {
+    if (it.R > 0 && it.op->pc_built != o.precond) {
+      int st = build_precond(it.op, o.precond);
+      if (st) return st;
+      it.op->pc_want = o.precond;
+    }
+  }
+  // problems, ordered by K so that each K forms one grouped launch
+  std::vector<int> order;
+  for (int i = 0; i < (int)items.size(); ++i)
+    if (items[i].R > 0) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return items[a].op->K < items[b].op->K; });
+  const int np = (int)order.size();
+  if (np == 0) {
+    if (stats) {
+      const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+      for (size_t i = 0; i < totalR; ++i) stats[i] = gp_stats{GP_OK, 0, 0, 0, 0.0, us};
+    }
+    return GP_OK;
+  }
+  // workspace layout
+  struct Layout {
+    size_t vec[6], st, part, counter, summary;
+  };
+  std::vector<Layout> lay(np);
+  size_t off = 0;
+  for (int j = 0; j < np; ++j) {
+    const Item& it = items[order[j]];
+    const size_t nv = (size_t)it.R * it.op->K * it.op->N;
+    for (int v = 0; v < 6; ++v) {
+      lay[j].vec[v] = off;
+      off = align_up(off + nv * tsz, 256);
+    }
+    lay[j].st = off;
+    off = align_up(off + (size_t)it.R * sizeof(RhsState), 256);
+    lay[j].part = off;
+    off = align_up(off + (size_t)NPART * it.R * it.op->ntiles * sizeof(double), 256);
+    lay[j].counter = off;
+    off = align_up(off + sizeof(unsigned), 256);
+  }
+  const size_t sum_off = off;
+  off = align_up(off + (size_t)np * NSUM * sizeof(int), 256);
+  int st = ensure_ws(c, off);
+  if (st) return st;
+  st = ensure_probs(c, np);
+  if (st) return st;
+  char* ws = (char*)c->ws;
+  int* d_summary = (int*)(ws + sum_off);
+  // descriptors
+  struct Group {
+    int K, first, count, W;
+  };
+  std::vector<Group> groups;
+  const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
+  for (int j = 0; j < np; ++j) {
+    const Item& it = items[order[j]];
+    Prob& p = c->h_probs[j];
+    std::memset(&p, 0, sizeof(Prob));
+    p.op = op_dev(it.op);
+    p.b = it.b;
+    p.x = it.x;
+    p.d = ws + lay[j].vec[0];
+    p.r = ws + lay[j].vec[1];
+    p.z = ws + lay[j].vec[2];
+    p.p0 = ws + lay[j].vec[3];
+    p.p1 = ws + lay[j].vec[4];
+    p.q = ws + lay[j].vec[5];
+    p.st = (RhsState*)(ws + lay[j].st);
+    p.part = (double*)(ws + lay[j].part);
+    p.counter = (unsigned*)(ws + lay[j].counter);
+    p.summary = d_summary + (size_t)j * NSUM;
+    p.R = it.R;
+    int rc = o.rhs_tile > 0 ? o.rhs_tile : 8;
+    rc = std::max(1, std::min(std::min(rc, RCMAX), it.R));
+    p.Rc = rc;
+    p.nchunks = (it.R + rc - 1) / rc;
+    p.work_count = it.op->ntiles * p.nchunks;
+    p.cfg = cfg;
+    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0});
+    Group& g = groups.back();
+    p.work_begin = g.W;
+    g.W += p.work_count;
+    g.count += 1;
+  }
+  hipStream_t s = c->stream;
+  HIPTRY(hipMemcpyAsync(c->d_probs, c->h_probs, np * sizeof(Prob), hipMemcpyHostToDevice, s));
+  for (int j = 0; j < np; ++j) {
+    const Item& it = items[order[j]];
+    HIPTRY(hipMemsetAsync(ws + lay[j].st, 0, (size_t)it.R * sizeof(RhsState), s));
+    HIPTRY(hipMemsetAsync(ws + lay[j].counter, 0, sizeof(unsigned), s));
+  }
+  HIPTRY(hipMemsetAsync(d_summary, 0, (size_t)np * NSUM * sizeof(int), s));
+
+  auto launch_outer = [&](bool with_add) -> int {
+    for (const Group& g : groups) {
+      const Prob* dp = c->d_probs + g.first;
+      if (with_add) HIPTRY(f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W) : launch_addsol_f64(s, g.K, dp, g.count, g.W));
+      HIPTRY(f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W)
+                 : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W));
+    }
+    return GP_OK;
+  };
+  int parity = 0;
+  auto launch_inner = [&](int iters) -> int {
+    for (int i = 0; i < iters; ++i) {
+      for (const Group& g : groups) {
+        const Prob* dp = c->d_probs + g.first;
+        HIPTRY(f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, parity)
+                   : launch_matvec_f64(s, g.K, dp, g.count, g.W, parity));
+        HIPTRY(f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, parity)
+                   : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, parity));
+      }
+      parity ^= 1;
+    }
+    return GP_OK;
+  };
+  int n_outer = (int)totalR, n_inner = 0, n_done = 0;
+  auto read_summary = [&]() -> int {
+    HIPTRY(hipMemcpyAsync(c->h_summary, d_summary, (size_t)np * NSUM * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    n_outer = n_inner = n_done = 0;
+    for (int j = 0; j < np; ++j) {
+      n_outer += c->h_summary[j * NSUM + 0];
+      n_inner += c->h_summary[j * NSUM + 1];
+      n_done += c->h_summary[j * NSUM + 2];
+    }
+    return GP_OK;
+  };
+  const int chunk = o.chunk > 0 ? o.chunk : 6;
+  bool first = true;
+  // Hard cap on host rounds: every round either advances an inner iteration or
+  // performs a refinement step, both bounded by max_iter and max_outer.
+  const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
+  long rounds = 0;
+  for (;;) {
+    if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
+    if (n_outer > 0) {
+      st = launch_outer(!first);
+      if (st) return st;
+      first = false;
+      if (n_inner == 0) {
+        st = read_summary();
+        if (st) return st;
+        if (n_inner == 0 && n_outer == 0) break;
+      }
+    }
+    st = launch_inner(chunk);
+    if (st) return st;
+    st = read_summary();
+    if (st) return st;
+    if (n_outer == 0 && n_inner == 0) break;
+  }
+  // results
+  std::vector<RhsState> hs;
+  int ret = GP_OK;
+  std::vector<gp_stats> all(totalR);
+  std::vector<size_t> base(items.size());
+  {
+    size_t b = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+      base[i] = b;
+      b += (size_t)items[i].R;
+    }
+  }
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  for (int j = 0; j < np; ++j) {
+    const Item& it = items[order[j]];
+    hs.resize(it.R);
+    HIPTRY(hipMemcpyAsync(hs.data(), ws + lay[j].st, (size_t)it.R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    const size_t nv = (size_t)it.op->K * it.op->N;
+    for (int r = 0; r < it.R; ++r) {
+      const RhsState& h = hs[r];
+      if (h.zero_b) HIPTRY(hipMemsetAsync(it.x + (size_t)r * nv, 0, nv * sizeof(double), s));
+      gp_stats& g = all[base[order[j]] + r];
+      g.status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
+      g.inner_iters = h.total_it;
+      g.outer_steps = h.outer;
+      g.reserved = 0;
+      g.relres = h.relres;
+      g.time_us = us;
+      if (g.status != GP_OK && ret == GP_OK) ret = g.status;
+    }
+  }
+  HIPTRY(hipStreamSynchronize(s));
+  if (stats) std::memcpy(stats, all.data(), totalR * sizeof(gp_stats));
+  if (ret == GP_ERR_NOT_CONVERGED) return fail(ret, "some right-hand sides did not reach the tolerance");
+  if (ret == GP_ERR_BREAKDOWN) return fail(ret, "PCG breakdown (non-finite value or loss of definiteness)");
+  return ret;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void gp_opts_default(gp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->inner_tol = 1e-4;
+  o->max_iter = 2000;
+  o->max_outer = 30;
+  o->precond = GP_PRECOND_BLOCK_JACOBI;
+  o->precision = GP_PREC_FP32_REFINE64;
+  o->rhs_tile = 0;
+  o->chunk = 0;
+  o->seed = 0;
+}
+
+const char* gp_last_error(void) { return g_err.c_str(); }
+
+int gp_version(void) { return 10000; }
+
+int gp_ctx_create(int device, void* hip_stream, size_t hbm_budget, gp_ctx** out) {
+  if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) {
+    (void)hipGetLastError();
+    return fail(GP_ERR_DEVICE, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(GP_ERR_INVALID_ARG, "device index out of range");
+  gp_ctx* c = new gp_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->budget = hbm_budget;
+  if (int st = set_device(c)) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return GP_OK;
+}
+
+int gp_ctx_set_stream(gp_ctx* c, void* hip_stream) {
+  if (!c) return fail(GP_ERR_INVALID_ARG, "ctx is NULL");
+  BusyGuard g(c);
+  if (!g.ok) return fail(GP_ERR_BUSY, "context busy");
+  c->stream = (hipStream_t)hip_stream;
+  return GP_OK;
+}
+
+int gp_ctx_memory(const gp_ctx* c, size_t* used, size_t* budget) {
+  if (!c) return fail(GP_ERR_INVALID_ARG, "ctx is NULL");
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  return GP_OK;
+}
+
+int gp_ctx_destroy(gp_ctx* c) {
+  if (!c) return GP_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->ws) dev_free(c, c->ws, c->ws_cap);
+  if (c->rhs) dev_free(c, c->rhs, c->rhs_cap * sizeof(double));
+  if (c->d_probs) dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
+  if (c->h_probs) (void)hipHostFree(c->h_probs);
+  if (c->h_summary) (void)hipHostFree(c->h_summary);
+  delete c;
+  return GP_OK;
+}
+
+int gp_op_destroy(gp_op* op);
+
+int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, int conn, int K, gp_op** out) {
+  if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!c || !mask_host) return fail(GP_ERR_INVALID_ARG, "ctx or mask is NULL");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(GP_ERR_INVALID_ARG, "grid dimensions must be >= 1");
+  if (conn != 4 && conn != 6) return fail(GP_ERR_INVALID_ARG, "conn must be 4 or 6");
+  if (K < 1 || K > KMAX) return fail(GP_ERR_INVALID_ARG, "K must lie in [1, 16]");
+  const long ncell = (long)nx * ny * nz;
+  if (ncell >= (long)INT_MAX) return fail(GP_ERR_INVALID_ARG, "grid too large");
+  long N = 0;
+  for (long i = 0; i < ncell; ++i) N += mask_host[i] != 0;
+  if (N == 0) return fail(GP_ERR_INVALID_ARG, "empty mask");
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  gp_op* op = new gp_op();
+  op->ctx = c;
+  op->K = K;
+  op->nx = nx;
+  op->ny = ny;
+  op->nz = nz;
+  op->conn = conn;
+  op->dirs = conn == 6 ? 3 : 2;
+  hipStream_t s = c->stream;
+  const int cpb = grid_cells_per_block();
+  const int nblocks = (int)((ncell + cpb - 1) / cpb);
+  uint8_t* d_mask = nullptr;
+  int *d_counts = nullptr, *d_offsets = nullptr, *d_gridmap = nullptr;
+  unsigned long long* d_edges = nullptr;
+  int st = GP_OK;
+  auto cleanup = [&]() {
+    dev_free(c, d_mask, ncell);
+    dev_free(c, d_counts, nblocks * sizeof(int));
+    dev_free(c, d_offsets, (nblocks + 1) * sizeof(int));
+    dev_free(c, d_gridmap, ncell * sizeof(int));
+    dev_free(c, d_edges, sizeof(unsigned long long));
+  };
+  do {
+    if ((st = dev_alloc(c, ncell, (void**)&d_mask))) break;
+    if ((st = dev_alloc(c, nblocks * sizeof(int), (void**)&d_counts))) break;
+    if ((st = dev_alloc(c, (nblocks + 1) * sizeof(int), (void**)&d_offsets))) break;
+    if ((st = dev_alloc(c, ncell * sizeof(int), (void**)&d_gridmap))) break;
+    if ((st = dev_alloc(c, sizeof(unsigned long long), (void**)&d_edges))) break;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d_mask, mask_host, ncell, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_grid_build(s, d_mask, ncell, d_counts, d_offsets, nblocks)) != hipSuccess) {
+      st = fail(GP_ERR_DEVICE, std::string("grid build: ") + hipGetErrorString(e));
+      break;
+    }
+    int Nd = 0;
+    if ((e = hipMemcpyAsync(&Nd, d_offsets + nblocks, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      st = fail(GP_ERR_DEVICE, std::string("grid count: ") + hipGetErrorString(e));
+      break;
+    }
+    if (Nd != N) {
+      st = fail(GP_ERR_DEVICE, "device voxel count disagrees with the mask");
+      break;
+    }
+    op->N = (int)N;
+    op->ntiles = (int)((N + TILE - 1) / TILE);
+    const size_t NB = (size_t)K * (K + 1) / 2;
+    if ((st = op_alloc(op, 6 * (size_t)N, &op->nbr))) break;
+    if ((st = op_alloc(op, (size_t)N, &op->lin))) break;
+    if ((st = op_alloc(op, NB * N, &op->B64))) break;
+    if ((st = op_alloc(op, NB * N, &op->B32))) break;
+    if ((st = op_alloc(op, NB * N, &op->L64))) break;
+    if ((st = op_alloc(op, NB * N, &op->P64))) break;
+    if ((st = op_alloc(op, NB * N, &op->P32))) break;
+    if ((st = op_alloc(op, 1, &op->d_bad))) break;
+    unsigned long long E = 0;
+    if ((e = hipMemsetAsync(d_edges, 0, sizeof(unsigned long long), s)) != hipSuccess ||
+        (e = launch_grid_index(s, d_mask, ncell, d_offsets, nblocks, d_gridmap, op->lin, op->N, nx, ny, nz, conn,
+                               op->nbr, d_edges)) != hipSuccess ||
+        (e = hipMemcpyAsync(&E, d_edges, sizeof(E), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+      st = fail(GP_ERR_DEVICE, std::string("grid index: ") + hipGetErrorString(e));
+      break;
+    }
+    op->E = (int64_t)E;
+  } while (false);
+  cleanup();
+  if (st) {
+    gp_op_destroy(op);
+    return st;
+  }
+  *out = op;
+  return GP_OK;
+}
+
+int gp_op_destroy(gp_op* op) {
+  if (!op) return GP_OK;
+  gp_ctx* c = op->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  const size_t NB = (size_t)op->K * (op->K + 1) / 2, N = (size_t)op->N;
+  op_free(op, op->nbr, 6 * N);
+  op_free(op, op->lin, N);
+  op_free(op, op->B64, NB * N);
+  op_free(op, op->B32, NB * N);
+  op_free(op, op->L64, NB * N);
+  op_free(op, op->P64, NB * N);
+  op_free(op, op->P32, NB * N);
+  op_free(op, op->d_bad, 1);
+  op_free(op, op->tr_part, op->tr_cap);
+  delete op;
+  return GP_OK;
+}
+
+int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
+  if (bad_voxel) *bad_voxel = -1;
+  if (!op || !B) return fail(GP_ERR_INVALID_ARG, "op or B is NULL");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  if (int st = reset_bad(op)) return st;
+  HIPTRY(launch_pack_blocks(c->stream, op->K, op->N, B, op->B64, op->B32, op->L64, op->d_bad));
+  int bad = INT_MAX;
+  if (int st = read_bad(op, &bad)) return st;
+  op->pc_built = -1;
+  if (bad != INT_MAX) {
+    op->have_blocks = false;
+    if (bad_voxel) *bad_voxel = bad;
+    return fail(GP_ERR_NOT_SPD, "data block of voxel " + std::to_string(bad) + " is not positive definite");
+  }
+  op->have_blocks = true;
+  if (op->have_alpha) return build_precond(op, op->pc_want);
+  return GP_OK;
+}
+
+int gp_op_set_alpha(gp_op* op, const double* alpha) {
+  if (!op || !alpha) return fail(GP_ERR_INVALID_ARG, "op or alpha is NULL");
+  for (int k = 0; k < op->K; ++k)
+    if (!(alpha[k] >= 0.0) || !std::isfinite(alpha[k])) return fail(GP_ERR_INVALID_ARG, "alpha_k must be finite and >= 0");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  for (int k = 0; k < op->K; ++k) op->alpha[k] = alpha[k];
+  op->have_alpha = true;
+  op->pc_built = -1;
+  if (op->have_blocks) return build_precond(op, op->pc_want);
+  return GP_OK;
+}
+
+int gp_op_query(const gp_op* op, int64_t* N, int64_t* E, int* K, size_t* bytes) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (N) *N = op->N;
+  if (E) *E = op->E;
+  if (K) *K = op->K;
+  if (bytes) *bytes = op->bytes;
+  return GP_OK;
+}
+
+int gp_op_voxel_index(const gp_op* op, int32_t* lin) {
+  if (!op || !lin) return fail(GP_ERR_INVALID_ARG, "op or lin is NULL");
+  HIPTRY(hipMemcpyAsync(lin, op->lin, (size_t)op->N * sizeof(int), hipMemcpyDeviceToDevice, op->ctx->stream));
+  return GP_OK;
+}
+
+int gp_apply(gp_op* op, int R, const double* x, double* y) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (R < 0) return fail(GP_ERR_INVALID_ARG, "R must be >= 0");
+  if (R == 0) return GP_OK;
+  if (!x || !y) return fail(GP_ERR_INVALID_ARG, "x or y is NULL");
+  if (x == y) return fail(GP_ERR_INVALID_ARG, "x and y must not alias");
+  if (R > 65535) return fail(GP_ERR_INVALID_ARG, "R too large");
+  if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_apply(c->stream, op_dev(op), R, x, y));
+  return GP_OK;
+}
+
+int gp_solve(gp_op* op, int R, const double* b, double* x, const gp_opts* opts, gp_stats* stats) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  gp_opts o;
+  if (opts) o = *opts; else gp_opts_default(&o);
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  std::vector<Item> items{Item{op, R, b, x}};
+  return run_group(c, items, o, stats);
+}
+
+int gp_solve_batch(gp_ctx* c, int n, const gp_item* items, const gp_opts* opts, gp_stats* stats) {
+  if (!c) return fail(GP_ERR_INVALID_ARG, "ctx is NULL");
+  if (n < 0 || (n > 0 && !items)) return fail(GP_ERR_INVALID_ARG, "bad item list");
+  gp_opts o;
+  if (opts) o = *opts; else gp_opts_default(&o);
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  std::vector<Item> v;
+  for (int i = 0; i < n; ++i) v.push_back(Item{items[i].op, items[i].R, items[i].b, items[i].x});
+  return run_group(c, v, o, stats);
+}
+
+int gp_perturb_rhs(gp_op* op, int R, const double* bw, const double* z1, const double* z2, double* b) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (R < 0 || R > 65535) return fail(GP_ERR_INVALID_ARG, "R out of range");
+  if (R == 0) return GP_OK;
+  if (!bw || !z1 || !z2 || !b) return fail(GP_ERR_INVALID_ARG, "null buffer (on-device random vectors are not available)");
+  if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, b));
+  return GP_OK;
+}
+
+int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double* z2, double* w,
+              const gp_opts* opts, gp_stats* stats) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (R < 0 || R > 65535) return fail(GP_ERR_INVALID_ARG, "R out of range");
+  if (R == 0) return GP_OK;
+  if (!bw || !z1 || !z2 || !w) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  gp_opts o;
+  if (opts) o = *opts; else gp_opts_default(&o);
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  if (int st = ensure_rhs(c, (size_t)R * op->K * op->N)) return st;
+  HIPTRY(launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, c->rhs));
+  std::vector<Item> items{Item{op, R, c->rhs, w}};
+  return run_group(c, items, o, stats);
+}
+
+int gp_probe_rhs(gp_op* op, int m, const int8_t* probes, double* b) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (m < 0) return fail(GP_ERR_INVALID_ARG, "m must be >= 0");
+  if (m == 0) return GP_OK;
+  if (!probes || !b) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_probe_rhs(c->stream, (long)m * op->K * op->N, probes, b));
+  return GP_OK;
+}
+
+static int trace_reduce_impl(gp_op* op, int m, const int8_t* probes, const double* u, double* tr_total,
+                             double* tr_kk, double* tr_Gkk) {
+  gp_ctx* c = op->ctx;
+  const size_t need = (size_t)2 * m * op->K * op->ntiles + (size_t)2 * m * op->K + 1 + 2 * KMAX;
+  if (need > op->tr_cap) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    op_free(op, op->tr_part, op->tr_cap);
+    op->tr_cap = 0;
+    if (int st = op_alloc(op, need, &op->tr_part)) return st;
+    op->tr_cap = need;
+  }
+  double* part = op->tr_part;
+  double* pairbuf = part + (size_t)2 * m * op->K * op->ntiles;
+  double* out = pairbuf + (size_t)2 * m * op->K;
+  HIPTRY(launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
+  std::vector<double> h(1 + 2 * op->K);
+  HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  if (tr_total) *tr_total = h[0];
+  for (int k = 0; k < op->K; ++k) {
+    if (tr_kk) tr_kk[k] = h[1 + k];
+    if (tr_Gkk) tr_Gkk[k] = h[1 + op->K + k];
+  }
+  return GP_OK;
+}
+
+int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u, double* tr_total, double* tr_kk,
+                    double* tr_Gkk) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (m < 1 || m > 65535) return fail(GP_ERR_INVALID_ARG, "m out of range");
+  if (!probes || !u) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  return trace_reduce_impl(op, m, probes, u, tr_total, tr_kk, tr_Gkk);
+}
+
+int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total, double* tr_kk, double* tr_Gkk,
+             const gp_opts* opts, gp_stats* stats) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (m < 1 || m > 65535) return fail(GP_ERR_INVALID_ARG, "m out of range");
+  if (!probes || !u) return fail(GP_ERR_INVALID_ARG, "null buffer (on-device probes are not available)");
+  if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  gp_opts o;
+  if (opts) o = *opts; else gp_opts_default(&o);
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  const size_t nv = (size_t)m * op->K * op->N;
+  if (int st = ensure_rhs(c, nv)) return st;
+  HIPTRY(launch_probe_rhs(c->stream, (long)nv, probes, c->rhs));
+  HIPTRY(hipMemsetAsync(u, 0, nv * sizeof(double), c->stream));
+  std::vector<Item> items{Item{op, m, c->rhs, u}};
+  const int st = run_group(c, items, o, stats);
+  if (st != GP_OK) return st;
+  return trace_reduce_impl(op, m, probes, u, tr_total, tr_kk, tr_Gkk);
+}
+
+}  // extern "C"

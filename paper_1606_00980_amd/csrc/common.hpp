@@ -1,0 +1,84 @@
+// Plain structures shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gp {
+
+constexpr int KMAX = 16;     // largest supported number of regressors
+constexpr int TILE = 256;    // voxels per workgroup in the voxel-parallel kernels
+constexpr int NPART = 3;     // reduction values per (right-hand side, tile)
+constexpr int NSUM = 4;      // summary ints per problem
+constexpr int RCMAX = 16;    // right-hand sides per workgroup, upper bound
+constexpr int PC_JACOBI = 0; // preconditioner kinds as seen by the kernels
+constexpr int PC_BLOCK = 1;
+
+// Life cycle of one right-hand side inside a solve.
+enum Phase : int {
+  PH_OUTER = 0,   // waits for an FP64 residual evaluation (refinement step)
+  PH_INNER = 1,   // inner PCG iterations in progress
+  PH_DONE = 2,    // finished (converged, capped or broken down)
+};
+
+// Status codes mirrored from gmrf.h for device code.
+enum DevStatus : int { ST_OK = 0, ST_NOT_CONVERGED = -5, ST_BREAKDOWN = -6 };
+
+// Per right-hand-side solver state, written only by the finalising workgroup.
+struct RhsState {
+  double bnorm2;    // ||b||^2
+  double rr64;      // last FP64 ||b - Qx||^2
+  double rho;       // r'z of the current inner iteration
+  double a;         // step length of the current inner iteration
+  double beta;      // direction update coefficient
+  double target2;   // inner stop threshold on ||r||^2
+  double relres;    // last FP64 relative residual
+  double spare;
+  int phase, status, inner_it, total_it;
+  int outer, has_d, first, zero_b;
+};
+
+// Device view of one operator.
+struct OpDev {
+  const int* nbr;        // [6][N]: -x,+x,-y,+y,-z,+z neighbour, or the voxel itself
+  const double* B64;     // packed lower triangle of B_n, [K(K+1)/2][N]
+  const float* B32;
+  const double* P64;     // preconditioner: packed inverse block or inverse diagonal
+  const float* P32;
+  const double* L64;     // packed lower Cholesky factor of B_n
+  int N, K, ntiles, dirs;
+  double alpha64[KMAX];
+  float alpha32[KMAX];
+};
+
+struct SolveCfg {
+  double tol, inner_tol;
+  int max_iter, max_outer;
+};
+
+// One member of a grouped launch: an operator with R right-hand sides.
+struct Prob {
+  OpDev op;
+  const double* b;       // FP64 [R][K][N]
+  double* x;             // FP64 [R][K][N]
+  void* d;               // inner vectors in the inner precision, [R][K][N]
+  void* r;
+  void* z;
+  void* p0;
+  void* p1;
+  void* q;
+  RhsState* st;          // [R]
+  double* part;          // [NPART][R][ntiles]
+  unsigned* counter;     // workgroups finished in the current launch
+  int* summary;          // [NSUM]: right-hand sides in each phase
+  int R, Rc, nchunks, work_begin, work_count, spare;
+  SolveCfg cfg;
+};
+
+// Packed index of the symmetric (k, j) entry, lower triangle row-major.
+__host__ __device__ constexpr int pk(int k, int j) {
+  return k >= j ? k * (k + 1) / 2 + j : j * (j + 1) / 2 + k;
+}
+
+}  // namespace gp

@@ -1,0 +1,37 @@
+// Host-side launch entry points of the kernels (one definition per source file).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace gp {
+
+// k_ops.hip
+hipError_t launch_grid_build(hipStream_t s, const uint8_t* mask, long ncell, int* counts, int* offsets,
+                             int nblocks);
+hipError_t launch_grid_index(hipStream_t s, const uint8_t* mask, long ncell, const int* offsets,
+                             int nblocks, int* gridmap, int* lin, int N, int nx, int ny, int nz, int conn,
+                             int* nbr, unsigned long long* edges);
+int grid_cells_per_block();
+hipError_t launch_pack_blocks(hipStream_t s, int K, int N, const double* B, double* B64, float* B32,
+                              double* L64, int* bad);
+hipError_t launch_precond(hipStream_t s, const OpDev& op, int pc, double* P64, float* P32, int* bad);
+hipError_t launch_apply(hipStream_t s, const OpDev& op, int R, const double* x, double* y);
+hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* bw, const double* z1,
+                          const double* z2, double* b);
+hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* b);
+hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, const double* u,
+                        double* part, double* pairbuf, double* out);
+
+// k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that
+// all have K regressors; W = total work items (tiles x right-hand-side chunks).
+hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W);
+hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int parity);
+hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int parity);
+hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W);
+hipError_t launch_refine_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W);
+hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int parity);
+hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int parity);
+hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W);
+
+}  // namespace gp

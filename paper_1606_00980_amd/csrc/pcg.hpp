@@ -1,0 +1,425 @@
+// Preconditioned conjugate gradients with the posterior precision
+//   Q = diag(alpha) (x) D_w + H' blkdiag_n(B_n) H
+// for many right-hand sides and many operators per launch.
+//
+// Operator action at voxel n, regressor k (the k-major entry form of the
+// precision of w_r = vec(W'), Section 3 and Appendix A.2):
+//   (Q v)_{k,n} = alpha_k * sum_d (v_{k,n} - v_{k,nb_d(n)}) + sum_j B_n[k,j] v_{j,n}
+// where nb_d(n) is the neighbour in direction d, or n itself when that
+// neighbour lies outside the mask -- the term then vanishes, which gives the
+// in-mask degree on the Laplacian diagonal (Section 2, free boundary).
+//
+// Iteration (Section 3.1: PCG until ||b - Qx|| / ||b|| <= delta), split into
+// three kernels per step so that each global reduction ends a launch:
+//   refine  (FP64)  : r64 = b - Q x, ||r64||^2, ||b||^2;  r = T(r64), z = M^{-1} r, r'z
+//   matvec  (T)     : p = z + beta p_old (p = z at the first step), q = Q p, p'q
+//   update  (T)     : d += a p, r -= a q, z = M^{-1} r, r'z, r'r
+//   addsol  (FP64)  : x += d once an inner solve has ended
+// The workgroup that finishes last in each launch reduces the per-tile
+// partials in a fixed order and advances every right-hand side's state.
+#pragma once
+#include "device.hpp"
+
+namespace gp {
+
+template <typename T> struct OpT;
+template <> struct OpT<double> {
+  __device__ static const double* B(const OpDev& o) { return o.B64; }
+  __device__ static const double* P(const OpDev& o) { return o.P64; }
+  __device__ static double alpha(const OpDev& o, int k) { return o.alpha64[k]; }
+};
+template <> struct OpT<float> {
+  __device__ static const float* B(const OpDev& o) { return o.B32; }
+  __device__ static const float* P(const OpDev& o) { return o.P32; }
+  __device__ static float alpha(const OpDev& o, int k) { return o.alpha32[k]; }
+};
+
+template <int K> struct Tri { static constexpr int NB = K * (K + 1) / 2; };
+template <int PC, int K> struct PSize { static constexpr int n = PC == PC_BLOCK ? Tri<K>::NB : K; };
+
+template <typename T, int NV>
+__device__ inline void load_soa(const T* __restrict__ A, int N, int n, T (&a)[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a[i] = A[(size_t)i * N + n];
+}
+
+template <typename T, int PC, int K>
+__device__ inline void precond_apply(const T (&P)[PSize<PC, K>::n], const T (&r)[K], T (&z)[K]) {
+  if constexpr (PC == PC_JACOBI) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = P[k] * r[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) s += P[pk(k, j)] * r[j];
+      z[k] = s;
+    }
+  }
+}
+
+// Per-RHS sums held in LDS: s_red[(slot * NV + v) * nwaves + wave].
+template <int NV>
+__device__ inline void wave_deposit(double* s_red, int slot, const double (&acc)[NV]) {
+  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double s = wave_sum(acc[v]);
+    if ((threadIdx.x % WAVE) == 0) s_red[(slot * NV + v) * nw + wv] = s;
+  }
+}
+
+// After the right-hand-side loop: one store per (active RHS, value) of the
+// workgroup's sum, waves added in order.
+template <int NV>
+__device__ inline void flush_partials(const Prob& pr, const double* s_red, int r0, int r1, int tile,
+                                      int want_phase) {
+  __syncthreads();
+  const int nw = blockDim.x / WAVE;
+  const int i = threadIdx.x;
+  if (i < (r1 - r0) * NV) {
+    const int slot = i / NV, v = i % NV, r = r0 + slot;
+    if (pr.st[r].phase == want_phase) {
+      double t = 0.0;
+      for (int j = 0; j < nw; ++j) t += s_red[(slot * NV + v) * nw + j];
+      pr.part[((size_t)v * pr.R + r) * pr.op.ntiles + tile] = t;
+    }
+  }
+}
+
+struct Where {
+  int p, tile, chunk, n, nn;
+  bool valid;
+};
+
+__device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int W) {
+  Where w;
+  const int item = xcd_remap(blockIdx.x, W);
+  w.p = find_prob(probs, nprob, item);
+  const int local = item - probs[w.p].work_begin;
+  const int nch = probs[w.p].nchunks;
+  w.tile = local / nch;
+  w.chunk = local - w.tile * nch;
+  const int N = probs[w.p].op.N;
+  w.n = w.tile * TILE + (int)threadIdx.x;
+  w.valid = w.n < N;
+  w.nn = w.valid ? w.n : N - 1;
+  return w;
+}
+
+__device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
+
+// --------------------------------------------------------------- finalisers
+__device__ inline void finalize_refine(const Prob& pr) {
+  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
+  for (int r = wv; r < pr.R; r += nw) {
+    RhsState& s = pr.st[r];
+    if (s.phase != PH_OUTER) continue;
+    double v[3];
+    sum_partials<3>(pr.part, pr.R, pr.op.ntiles, r, v);
+    if (lane != 0) continue;
+    const double rr = v[0], bb = v[1], rz = v[2];
+    if (s.outer == 0) s.bnorm2 = bb;
+    s.has_d = 0;
+    s.outer += 1;
+    s.rr64 = rr;
+    const double bn2 = s.bnorm2;
+    if (!finite(bn2)) {
+      s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+    } else if (bn2 == 0.0) {
+      s.relres = 0.0; s.zero_b = 1; s.status = ST_OK; s.phase = PH_DONE;
+    } else {
+      const double rel = sqrt(rr / bn2);
+      s.relres = rel;
+      if (!finite(rel)) {
+        s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+      } else if (rel <= pr.cfg.tol) {
+        s.status = ST_OK; s.phase = PH_DONE;
+      } else if (s.outer >= pr.cfg.max_outer || s.total_it >= pr.cfg.max_iter) {
+        s.status = ST_NOT_CONVERGED; s.phase = PH_DONE;
+      } else if (!(rz > 0.0) || !finite(rz)) {
+        s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+      } else {
+        const double it2 = pr.cfg.inner_tol * pr.cfg.inner_tol * rr;
+        const double ot2 = 0.25 * pr.cfg.tol * pr.cfg.tol * bn2;
+        s.target2 = it2 > ot2 ? it2 : ot2;
+        s.rho = rz;
+        s.first = 1;
+        s.inner_it = 0;
+        s.has_d = 1;
+        s.phase = PH_INNER;
+      }
+    }
+  }
+}
+
+__device__ inline void finalize_matvec(const Prob& pr) {
+  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
+  for (int r = wv; r < pr.R; r += nw) {
+    RhsState& s = pr.st[r];
+    if (s.phase != PH_INNER) continue;
+    double v[1];
+    sum_partials<1>(pr.part, pr.R, pr.op.ntiles, r, v);
+    if (lane != 0) continue;
+    const double sigma = v[0];
+    if (!(sigma > 0.0) || !finite(sigma)) {
+      if (s.inner_it == 0) {       // no usable correction yet
+        s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+      } else {                     // keep the correction so far; re-evaluate in FP64
+        s.phase = PH_OUTER;
+      }
+    } else {
+      s.a = s.rho / sigma;
+      s.first = 0;
+    }
+  }
+}
+
+__device__ inline void finalize_update(const Prob& pr) {
+  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
+  for (int r = wv; r < pr.R; r += nw) {
+    RhsState& s = pr.st[r];
+    if (s.phase != PH_INNER) continue;
+    double v[2];
+    sum_partials<2>(pr.part, pr.R, pr.op.ntiles, r, v);
+    if (lane != 0) continue;
+    const double rz = v[0], rr = v[1];
+    s.inner_it += 1;
+    s.total_it += 1;
+    if (!finite(rr) || !finite(rz)) {
+      s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+    } else if (rr <= s.target2 || s.total_it >= pr.cfg.max_iter || !(rz > 0.0)) {
+      s.phase = PH_OUTER;
+    } else {
+      s.beta = rz / s.rho;
+      s.rho = rz;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename T, int PC, int K>
+__global__ __launch_bounds__(TILE) void k_refine(const Prob* __restrict__ probs, int nprob, int W) {
+  constexpr int NB = Tri<K>::NB, NP = PSize<PC, K>::n;
+  __shared__ double s_red[RCMAX * 3 * (TILE / WAVE)];
+  const Where w = locate(probs, nprob, W);
+  const Prob& pr = probs[w.p];
+  const OpDev& op = pr.op;
+  const int N = op.N, nn = w.nn;
+  int nb[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
+  double B[NB];
+  load_soa(op.B64, N, nn, B);
+  T P[NP];
+  load_soa(OpT<T>::P(op), N, nn, P);
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  for (int r = r0; r < r1; ++r) {
+    if (pr.st[r].phase != PH_OUTER) continue;
+    const double* xr = pr.x + (size_t)r * K * N;
+    const double* br = pr.b + (size_t)r * K * N;
+    double xo[K], y[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xo[k] = xr[(size_t)k * N + nn];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s6 = 0.0;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) s6 += xo[k] - xr[(size_t)k * N + nb[d]];
+      y[k] = op.alpha64[k] * s6;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) y[k] += B[pk(k, j)] * xo[j];
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+    T rt[K], z[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double bk = br[(size_t)k * N + nn];
+      const double rk = bk - y[k];
+      acc[0] += rk * rk;
+      acc[1] += bk * bk;
+      rt[k] = (T)rk;
+    }
+    precond_apply<T, PC, K>(P, rt, z);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
+    if (w.valid) {
+      T* rp = (T*)pr.r + (size_t)r * K * N;
+      T* zp = (T*)pr.z + (size_t)r * K * N;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        rp[(size_t)k * N + w.n] = rt[k];
+        zp[(size_t)k * N + w.n] = z[k];
+      }
+    } else {
+      acc[0] = acc[1] = acc[2] = 0.0;
+    }
+    wave_deposit<3>(s_red, r - r0, acc);
+  }
+  flush_partials<3>(pr, s_red, r0, r1, w.tile, PH_OUTER);
+  if (arrive_last(pr)) {
+    finalize_refine(pr);
+    publish_summary(pr);
+  }
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(TILE) void k_matvec(const Prob* __restrict__ probs, int nprob, int W,
+                                                 int parity) {
+  constexpr int NB = Tri<K>::NB;
+  __shared__ double s_red[RCMAX * 1 * (TILE / WAVE)];
+  const Where w = locate(probs, nprob, W);
+  const Prob& pr = probs[w.p];
+  const OpDev& op = pr.op;
+  const int N = op.N, nn = w.nn;
+  int nb[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
+  T B[NB];
+  load_soa(OpT<T>::B(op), N, nn, B);
+  T al[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) al[k] = OpT<T>::alpha(op, k);
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  for (int r = r0; r < r1; ++r) {
+    const RhsState& s = pr.st[r];
+    if (s.phase != PH_INNER) continue;
+    const bool first = s.first != 0;
+    const T beta = (T)s.beta;
+    const size_t off = (size_t)r * K * N;
+    const T* zr = (const T*)pr.z + off;
+    const T* pin = (const T*)(parity ? pr.p1 : pr.p0) + off;
+    T* pout = (T*)(parity ? pr.p0 : pr.p1) + off;
+    T* qr = (T*)pr.q + off;
+    T po[K], qv[K];
+    if (first) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) po[k] = zr[(size_t)k * N + nn];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T s6 = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) s6 += po[k] - zr[(size_t)k * N + nb[d]];
+        qv[k] = al[k] * s6;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) po[k] = zr[(size_t)k * N + nn] + beta * pin[(size_t)k * N + nn];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        T s6 = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          const size_t i = (size_t)k * N + nb[d];
+          s6 += po[k] - (zr[i] + beta * pin[i]);
+        }
+        qv[k] = al[k] * s6;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * po[j];
+    }
+    double acc[1] = {0.0};
+    if (w.valid) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        pout[(size_t)k * N + w.n] = po[k];
+        qr[(size_t)k * N + w.n] = qv[k];
+        acc[0] += (double)po[k] * (double)qv[k];
+      }
+    }
+    wave_deposit<1>(s_red, r - r0, acc);
+  }
+  flush_partials<1>(pr, s_red, r0, r1, w.tile, PH_INNER);
+  if (arrive_last(pr)) {
+    finalize_matvec(pr);
+    publish_summary(pr);
+  }
+}
+
+template <typename T, int PC, int K>
+__global__ __launch_bounds__(TILE) void k_update(const Prob* __restrict__ probs, int nprob, int W,
+                                                 int parity) {
+  constexpr int NP = PSize<PC, K>::n;
+  __shared__ double s_red[RCMAX * 2 * (TILE / WAVE)];
+  const Where w = locate(probs, nprob, W);
+  const Prob& pr = probs[w.p];
+  const OpDev& op = pr.op;
+  const int N = op.N, nn = w.nn;
+  T P[NP];
+  load_soa(OpT<T>::P(op), N, nn, P);
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  for (int r = r0; r < r1; ++r) {
+    const RhsState& s = pr.st[r];
+    if (s.phase != PH_INNER) continue;
+    const T a = (T)s.a;
+    const bool fresh = s.inner_it == 0;
+    const size_t off = (size_t)r * K * N;
+    const T* pc = (const T*)(parity ? pr.p0 : pr.p1) + off;
+    const T* qr = (const T*)pr.q + off;
+    T* dr = (T*)pr.d + off;
+    T* rr = (T*)pr.r + off;
+    T* zr = (T*)pr.z + off;
+    T rv[K], dv[K], z[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)k * N + nn;
+      const T pk_ = pc[i];
+      dv[k] = fresh ? a * pk_ : dr[i] + a * pk_;
+      rv[k] = rr[i] - a * qr[i];
+    }
+    precond_apply<T, PC, K>(P, rv, z);
+    double acc[2] = {0.0, 0.0};
+    if (w.valid) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const size_t i = (size_t)k * N + w.n;
+        dr[i] = dv[k];
+        rr[i] = rv[k];
+        zr[i] = z[k];
+        acc[0] += (double)rv[k] * (double)z[k];
+        acc[1] += (double)rv[k] * (double)rv[k];
+      }
+    }
+    wave_deposit<2>(s_red, r - r0, acc);
+  }
+  flush_partials<2>(pr, s_red, r0, r1, w.tile, PH_INNER);
+  if (arrive_last(pr)) {
+    finalize_update(pr);
+    publish_summary(pr);
+  }
+}
+
+// x += d for right-hand sides whose inner solve has ended.
+template <typename T, int K>
+__global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs, int nprob, int W) {
+  const Where w = locate(probs, nprob, W);
+  const Prob& pr = probs[w.p];
+  if (!w.valid) return;
+  const int N = pr.op.N;
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  for (int r = r0; r < r1; ++r) {
+    const RhsState& s = pr.st[r];
+    if (s.phase != PH_OUTER || !s.has_d) continue;
+    const size_t off = (size_t)r * K * N;
+    const T* dr = (const T*)pr.d + off;
+    double* xr = pr.x + off;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)k * N + w.n;
+      xr[i] += (double)dr[i];
+    }
+  }
+}
+
+}  // namespace gp

@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libgmrf.so (include/gmrf.h).
+
+Functions keep the C names and take device buffers as integers (HIP device
+addresses, e.g. ``tensor.data_ptr()``) or as torch tensors, whose
+``data_ptr()`` is passed.  No computation happens here: every step runs in
+the library's HIP kernels.  Importing this module fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmrf.so")
+
+GP_OK = 0
+GP_ERR_INVALID_ARG = -1
+GP_ERR_NOT_SPD = -2
+GP_ERR_OOM = -3
+GP_ERR_BUSY = -4
+GP_ERR_NOT_CONVERGED = -5
+GP_ERR_BREAKDOWN = -6
+GP_ERR_DEVICE = -7
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "OOM", -4: "BUSY",
+                -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "DEVICE"}
+
+GP_PRECOND_JACOBI = 0
+GP_PRECOND_BLOCK_JACOBI = 1
+GP_PREC_FP64 = 0
+GP_PREC_FP32_REFINE64 = 1
+
+# every symbol the header declares
+EXPORTS = [
+    "gp_opts_default", "gp_last_error", "gp_version",
+    "gp_ctx_create", "gp_ctx_set_stream", "gp_ctx_memory", "gp_ctx_destroy",
+    "gp_op_create", "gp_op_set_blocks", "gp_op_set_alpha", "gp_op_query",
+    "gp_op_voxel_index", "gp_op_destroy",
+    "gp_apply", "gp_solve", "gp_solve_batch", "gp_perturb_rhs", "gp_sample",
+    "gp_probe_rhs", "gp_trace_reduce", "gp_trace",
+]
+
+
+class GpOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("max_outer", ctypes.c_int),
+                ("precond", ctypes.c_int), ("precision", ctypes.c_int),
+                ("rhs_tile", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
+
+
+class GpStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("outer_steps", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("relres", ctypes.c_double), ("time_us", ctypes.c_double)]
+
+
+class GpItem(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("R", ctypes.c_int),
+                ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class GmrfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with "
+                          "`python -m paper_1606_00980_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_double, ctypes.c_size_t)
+    P = ctypes.POINTER
+    sig = {
+        "gp_opts_default": (None, [P(GpOpts)]),
+        "gp_last_error": (ctypes.c_char_p, []),
+        "gp_version": (i32, []),
+        "gp_ctx_create": (i32, [i32, vp, sz, P(vp)]),
+        "gp_ctx_set_stream": (i32, [vp, vp]),
+        "gp_ctx_memory": (i32, [vp, P(sz), P(sz)]),
+        "gp_ctx_destroy": (i32, [vp]),
+        "gp_op_create": (i32, [vp, vp, i32, i32, i32, i32, i32, P(vp)]),
+        "gp_op_set_blocks": (i32, [vp, vp, P(i64)]),
+        "gp_op_set_alpha": (i32, [vp, P(dbl)]),
+        "gp_op_query": (i32, [vp, P(i64), P(i64), P(i32), P(sz)]),
+        "gp_op_voxel_index": (i32, [vp, vp]),
+        "gp_op_destroy": (i32, [vp]),
+        "gp_apply": (i32, [vp, i32, vp, vp]),
+        "gp_solve": (i32, [vp, i32, vp, vp, P(GpOpts), P(GpStats)]),
+        "gp_solve_batch": (i32, [vp, i32, P(GpItem), P(GpOpts), P(GpStats)]),
+        "gp_perturb_rhs": (i32, [vp, i32, vp, vp, vp, vp]),
+        "gp_sample": (i32, [vp, i32, vp, vp, vp, vp, P(GpOpts), P(GpStats)]),
+        "gp_probe_rhs": (i32, [vp, i32, vp, vp]),
+        "gp_trace_reduce": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl)]),
+        "gp_trace": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl), P(GpOpts), P(GpStats)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _ptr(buf) -> int | None:
+    """Device address of a torch tensor (or an int passed through)."""
+    if buf is None:
+        return None
+    if isinstance(buf, int):
+        return buf
+    return buf.data_ptr()
+
+
+def _check(status: int, where: str) -> int:
+    if status != GP_OK:
+        raise GmrfError(status, where, lib.gp_last_error().decode())
+    return status
+
+
+def gp_opts_default(**overrides) -> GpOpts:
+    o = GpOpts()
+    lib.gp_opts_default(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def gp_last_error() -> str:
+    return lib.gp_last_error().decode()
+
+
+def gp_version() -> int:
+    return lib.gp_version()
+
+
+def gp_ctx_create(device: int = 0, stream: int | None = None, hbm_budget: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.gp_ctx_create(device, stream, hbm_budget, ctypes.byref(h)), "gp_ctx_create")
+    return h.value
+
+
+def gp_ctx_set_stream(ctx: int, stream: int | None) -> None:
+    _check(lib.gp_ctx_set_stream(ctx, stream), "gp_ctx_set_stream")
+
+
+def gp_ctx_memory(ctx: int):
+    used, budget = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.gp_ctx_memory(ctx, ctypes.byref(used), ctypes.byref(budget)), "gp_ctx_memory")
+    return used.value, budget.value
+
+
+def gp_ctx_destroy(ctx: int) -> None:
+    _check(lib.gp_ctx_destroy(ctx), "gp_ctx_destroy")
+
+
+def gp_op_create(ctx: int, mask: np.ndarray, conn: int, K: int) -> int:
+    """mask: host array shaped (nz, ny, nx) (or (ny, nx)), nonzero = in mask."""
+    m = np.ascontiguousarray(np.asarray(mask) != 0, dtype=np.uint8)
+    if m.ndim == 2:
+        m = m[None]
+    nz, ny, nx = m.shape
+    h = ctypes.c_void_p()
+    _check(lib.gp_op_create(ctx, m.ctypes.data, nx, ny, nz, conn, K, ctypes.byref(h)),
+           "gp_op_create")
+    return h.value
+
+
+def gp_op_set_blocks(op: int, B) -> None:
+    bad = ctypes.c_int64(-1)
+    st = lib.gp_op_set_blocks(op, _ptr(B), ctypes.byref(bad))
+    if st != GP_OK:
+        err = GmrfError(st, "gp_op_set_blocks", gp_last_error())
+        err.bad_voxel = bad.value
+        raise err
+
+
+def gp_op_set_alpha(op: int, alpha) -> None:
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    _check(lib.gp_op_set_alpha(op, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "gp_op_set_alpha")
+
+
+def gp_op_query(op: int) -> dict:
+    N, E, K, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_size_t()
+    _check(lib.gp_op_query(op, ctypes.byref(N), ctypes.byref(E), ctypes.byref(K),
+                           ctypes.byref(nb)), "gp_op_query")
+    return {"N": N.value, "E": E.value, "K": K.value, "bytes": nb.value}
+
+
+def gp_op_voxel_index(op: int, lin) -> None:
+    _check(lib.gp_op_voxel_index(op, _ptr(lin)), "gp_op_voxel_index")
+
+
+def gp_op_destroy(op: int) -> None:
+    _check(lib.gp_op_destroy(op), "gp_op_destroy")
+
+
+def gp_apply(op: int, R: int, x, y) -> None:
+    _check(lib.gp_apply(op, R, _ptr(x), _ptr(y)), "gp_apply")
+
+
+def _stats_array(n: int):
+    return (GpStats * max(n, 1))()
+
+
+def _stats_list(arr, n: int):
+    return [{"status": arr[i].status, "inner_iters": arr[i].inner_iters,
+             "outer_steps": arr[i].outer_steps, "relres": arr[i].relres,
+             "time_us": arr[i].time_us} for i in range(n)]
+
+
+def gp_solve(op: int, R: int, b, x, opts: GpOpts | None = None, check: bool = True):
+    """Returns (status, per-RHS stats list)."""
+    st_arr = _stats_array(R)
+    o = opts if opts is not None else gp_opts_default()
+    st = lib.gp_solve(op, R, _ptr(b), _ptr(x), ctypes.byref(o), st_arr)
+    if check:
+        _check(st, "gp_solve")
+    return st, _stats_list(st_arr, R)
+
+
+def gp_solve_batch(ctx: int, items, opts: GpOpts | None = None, check: bool = True):
+    """items: list of (op, R, b, x)."""
+    arr = (GpItem * max(len(items), 1))()
+    total = 0
+    for i, (op, R, b, x) in enumerate(items):
+        arr[i].op, arr[i].R, arr[i].b, arr[i].x = op, R, _ptr(b), _ptr(x)
+        total += R
+    st_arr = _stats_array(total)
+    o = opts if opts is not None else gp_opts_default()
+    st = lib.gp_solve_batch(ctx, len(items), arr, ctypes.byref(o), st_arr)
+    if check:
+        _check(st, "gp_solve_batch")
+    return st, _stats_list(st_arr, total)
+
+
+def gp_perturb_rhs(op: int, R: int, bw, z1, z2, b) -> None:
+    _check(lib.gp_perturb_rhs(op, R, _ptr(bw), _ptr(z1), _ptr(z2), _ptr(b)), "gp_perturb_rhs")
+
+
+def gp_sample(op: int, R: int, bw, z1, z2, w, opts: GpOpts | None = None, check: bool = True):
+    st_arr = _stats_array(R)
+    o = opts if opts is not None else gp_opts_default()
+    st = lib.gp_sample(op, R, _ptr(bw), _ptr(z1), _ptr(z2), _ptr(w), ctypes.byref(o), st_arr)
+    if check:
+        _check(st, "gp_sample")
+    return st, _stats_list(st_arr, R)
+
+
+def gp_probe_rhs(op: int, m: int, probes, b) -> None:
+    _check(lib.gp_probe_rhs(op, m, _ptr(probes), _ptr(b)), "gp_probe_rhs")
+
+
+def _trace_out(K: int):
+    return (ctypes.c_double(), (ctypes.c_double * K)(), (ctypes.c_double * K)())
+
+
+def gp_trace_reduce(op: int, m: int, probes, u, K: int):
+    t, tk, gk = _trace_out(K)
+    _check(lib.gp_trace_reduce(op, m, _ptr(probes), _ptr(u), ctypes.byref(t), tk, gk),
+           "gp_trace_reduce")
+    return t.value, np.array(tk[:]), np.array(gk[:])
+
+
+def gp_trace(op: int, m: int, probes, u, K: int, opts: GpOpts | None = None):
+    t, tk, gk = _trace_out(K)
+    st_arr = _stats_array(m)
+    o = opts if opts is not None else gp_opts_default()
+    _check(lib.gp_trace(op, m, _ptr(probes), _ptr(u), ctypes.byref(t), tk, gk,
+                        ctypes.byref(o), st_arr), "gp_trace")
+    return t.value, np.array(tk[:]), np.array(gk[:]), _stats_list(st_arr, m)
