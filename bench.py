@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the posterior-precision hot path on one MI355X.
+
+One step is one pass of the whole path over one batch of synthetic input on
+the 52,740-voxel whole-brain operator (64x64x33 ellipsoid, K = 6, AR(3)):
+ingest the data blocks (pack + per-voxel Cholesky), set alpha (block-Jacobi
+set-up), form 32 perturbed right-hand sides (Algorithm 2) and 32 Rademacher
+probe right-hand sides, solve all 64 in one grouped batch (FP32 inner PCG,
+FP64 refinement to relative residual 1e-8, every right-hand side from zero),
+and reduce the Hutchinson trace estimates.  `value` is solves/s over the
+timed steps with inputs resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--workload batch64|brain_fp64|uneven]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00980_amd", "csrc", f)
+                  for f in ("pcg.hpp", "device.hpp", "common.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-baseline-gpu", action="store_true",
+                    help="skip the plain FP64 single-right-hand-side comparison run")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, copy a buffer of this size 5 times (counter calibration)")
+    return ap.parse_args()
+
+
+def load_library():
+    from paper_1606_00980_amd import build
+    if not os.path.exists(build.OUT):
+        build.build(verbose=False)
+    from paper_1606_00980_amd import gmrf
+    return gmrf
+
+
+class Workload:
+    """Device-resident inputs and the step function of one benchmark workload."""
+
+    def __init__(self, name, g, torch, ctx):
+        from paper_1606_00980_amd import synth
+        self.name, self.g, self.torch, self.ctx = name, g, torch, ctx
+        dev = lambda a: torch.from_numpy(a).cuda()
+        if name in ("batch64", "brain_fp64"):
+            w = synth.brain_3d()
+            self.ws = [w]
+            self.op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+            self.ops = [self.op]
+            self.B = [dev(w.B)]
+            self.alpha = [w.alpha]
+            if name == "batch64":
+                self.S = self.M = 32
+                z1, z2 = w.z(self.S)
+                self.v = dev(w.probes(self.M))
+                self.bw, self.z1, self.z2 = dev(w.bw), dev(z1), dev(z2)
+                self.bs = torch.empty((self.S, w.K, w.N), dtype=torch.float64, device="cuda")
+                self.bp = torch.empty((self.M, w.K, w.N), dtype=torch.float64, device="cuda")
+                self.xs = torch.zeros_like(self.bs)
+                self.xp = torch.zeros_like(self.bp)
+                self.opts = g.gp_opts_default(tol=1e-8)
+                self.solves = self.S + self.M
+            else:
+                self.b = dev(w.bw[None].copy())
+                self.x = torch.zeros_like(self.b)
+                self.opts = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64)
+                self.solves = 1
+        else:   # 16 uneven operators, 8 right-hand sides each (4 samples + 4 probes)
+            self.ws = [synth.uneven_instance(synth.CFG_UNEVEN, i) for i in range(16)]
+            self.ops, self.B, self.alpha, self.items = [], [], [], []
+            self.pert = []
+            for w in self.ws:
+                op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+                self.ops.append(op)
+                self.B.append(dev(w.B))
+                self.alpha.append(w.alpha)
+                z1, z2 = w.z(4)
+                v = dev(w.probes(4))
+                bs = torch.empty((4, w.K, w.N), dtype=torch.float64, device="cuda")
+                bp = torch.empty_like(bs)
+                xs, xp = torch.zeros_like(bs), torch.zeros_like(bp)
+                self.pert.append((op, dev(w.bw), dev(z1), dev(z2), v, bs, bp, xs, xp))
+                self.items += [(op, 4, bs, xs), (op, 4, bp, xp)]
+            self.opts = g.gp_opts_default(tol=1e-8)
+            self.solves = 16 * 8
+        self.last_stats = []
+        self.trace = None
+
+    def step(self):
+        g = self.g
+        for op, B, a in zip(self.ops, self.B, self.alpha):
+            g.gp_op_set_blocks(op, B)
+            g.gp_op_set_alpha(op, a)
+        if self.name == "batch64":
+            g.gp_perturb_rhs(self.op, self.S, self.bw, self.z1, self.z2, self.bs)
+            g.gp_probe_rhs(self.op, self.M, self.v, self.bp)
+            self.xs.zero_()
+            self.xp.zero_()
+            _, self.last_stats = g.gp_solve_batch(
+                self.ctx, [(self.op, self.S, self.bs, self.xs), (self.op, self.M, self.bp, self.xp)],
+                self.opts, check=False)
+            self.trace = g.gp_trace_reduce(self.op, self.M, self.v, self.xp, self.ws[0].K)
+        elif self.name == "brain_fp64":
+            self.x.zero_()
+            _, self.last_stats = g.gp_solve(self.op, 1, self.b, self.x, self.opts, check=False)
+        else:
+            for (op, bw, z1, z2, v, bs, bp, xs, xp) in self.pert:
+                g.gp_perturb_rhs(op, 4, bw, z1, z2, bs)
+                g.gp_probe_rhs(op, 4, v, bp)
+                xs.zero_()
+                xp.zero_()
+            _, self.last_stats = g.gp_solve_batch(self.ctx, self.items, self.opts, check=False)
+            for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(self.pert, self.ws):
+                g.gp_trace_reduce(op, 4, v, xp, w.K)
+
+    def config(self):
+        if self.name == "uneven":
+            Ns = [w.N for w in self.ws]
+            Ks = [w.K for w in self.ws]
+            return {"workload": "uneven16_ellipsoids_32x32x20_to_96x96x60_K2to10_R8",
+                    "operators": 16, "N_total": int(sum(Ns)), "N_min": int(min(Ns)),
+                    "N_max": int(max(Ns)), "K": Ks, "R_per_operator": 8,
+                    "tol": 1e-8, "precond": "block_jacobi", "precision": "fp32_inner_fp64_refine"}
+        w = self.ws[0]
+        if self.name == "brain_fp64":
+            return {"workload": "brain3d_64x64x33_ellipsoid_K6_R1_fp64", "N": w.N, "K": w.K, "R": 1,
+                    "tol": 1e-8, "precond": "block_jacobi", "precision": "fp64"}
+        return {"workload": "brain3d_64x64x33_ellipsoid_K6_R64_fp32refine64", "N": w.N, "K": w.K,
+                "R": 64, "samples": 32, "probes": 32, "tol": 1e-8, "precond": "block_jacobi",
+                "precision": "fp32_inner_fp64_refine",
+                "step": "set_blocks+set_alpha+perturb_rhs(32)+probe_rhs(32)+solve_batch(64)+trace_reduce"}
+
+
+def roofline(prof):
+    """Roofline entry for the kernel kind with the largest total time."""
+    kinds = {k: v for k, v in prof.items() if v["launches"] > 0}
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    d = kinds[dom]
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tf = json.load(f)
+        if tf.get("kernel_source_hash") == kernel_source_hash() and dom in tf.get("kernels", {}):
+            traffic = tf["kernels"][dom]
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 2),
+            "bytes_per_launch": round(d["bytes"] / d["launches"])}
+
+
+def cpu_baseline():
+    """The oracle on the host: Algorithm 2 right-hand sides and FP64 PCG to 1e-13
+    for 16 samples and 16 probes of the same operator, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gmrf_oracle as orc
+    from paper_1606_00980_amd import synth
+    with threadpool_limits(limits=1):
+        w = synth.brain_3d()
+        z1, z2 = w.z(16)
+        v = w.probes(16).astype(np.float64)
+        t0 = time.perf_counter()
+        g = orc.grid(w.mask, w.conn)
+        Q = orc.precision(g, w.alpha, w.B)
+        b = orc.perturbation_rhs(g, w.alpha, w.B, w.bw, z1, z2)
+        orc.solve(Q, b, tol=1e-13)
+        orc.hutchinson(g, Q, v, tol=1e-13)
+        dt = time.perf_counter() - t0
+    return {"value": round(32 / dt, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "brain3d_64x64x33 K=6: operator assembly, 16 Algorithm-2 samples and 16 "
+                      "Hutchinson probes, FP64 PCG to 1e-13 (scipy, 1 thread)",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
+                                   "supported (one process, one MI355X)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    g = load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = g.gp_ctx_create(0, stream, 0)
+    wl = Workload(args.workload, g, torch, ctx)
+    for _ in range(args.warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    g.gp_ctx_profile(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        wl.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.gp_ctx_profile_read(ctx)
+    g.gp_ctx_profile(ctx, False)
+    dt = t1 - t0
+    stats = wl.last_stats
+    ok = all(s["status"] == 0 and s["relres"] <= 1e-8 for s in stats)
+    result = {
+        "metric": "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency",
+        "value": round(wl.solves * args.steps / dt, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.workload == "brain_fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": wl.config(),
+        "roofline": roofline(prof),
+        "cpu_baseline": None,
+        "converged": ok,
+        "max_relres": max(s["relres"] for s in stats),
+        "inner_iters_mean": round(sum(s["inner_iters"] for s in stats) / len(stats), 2),
+        "outer_steps_mean": round(sum(s["outer_steps"] for s in stats) / len(stats), 2),
+        "kernels": {k: {"launches": v["launches"],
+                        "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                        "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+                    for k, v in prof.items() if v["launches"] > 0},
+    }
+    if wl.trace is not None:
+        result["trace_estimate"] = round(wl.trace[0], 6)
+    if args.workload == "batch64" and not args.no_baseline_gpu:
+        base = Workload("brain_fp64", g, torch, ctx)
+        base.step()
+        torch.cuda.synchronize()
+        n = 10
+        tb = time.perf_counter()
+        for _ in range(n):
+            base.x.zero_()
+            g.gp_solve(base.op, 1, base.b, base.x, base.opts)
+        torch.cuda.synchronize()
+        result["gpu_fp64_single_rhs"] = {"value": round(n / (time.perf_counter() - tb), 2),
+                                         "unit": "solves/s",
+                                         "what": "plain FP64 single-RHS PCG, same operator, block Jacobi"}
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline and args.workload == "batch64":
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result))
+    sys.stdout.flush()
+    if not ok:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

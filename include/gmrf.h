@@ -103,6 +103,31 @@ typedef struct gp_item {
   double*       x;     /* device, [R][K][N]; in: start value, out: solution      */
 } gp_item;
 
+/* Kernel kinds reported by the profiler. */
+#define GP_KERNEL_REFINE   0  /* FP64 residual + preconditioned restart        */
+#define GP_KERNEL_MATVEC   1  /* direction update and q = Q p                  */
+#define GP_KERNEL_UPDATE   2  /* solution/residual update, preconditioner      */
+#define GP_KERNEL_ADDSOL   3  /* FP64 solution += inner correction             */
+#define GP_KERNEL_PERTURB  4  /* Algorithm 2 right-hand sides                  */
+#define GP_KERNEL_PRECOND  5  /* preconditioner set-up                         */
+#define GP_KERNEL_PACK     6  /* data-block ingest and Cholesky                */
+#define GP_KERNEL_PROBE    7  /* probe -> FP64 right-hand side                 */
+#define GP_KERNEL_TRACE    8  /* Hutchinson reductions                         */
+#define GP_KERNEL_APPLY    9  /* FP64 y = Q x                                  */
+#define GP_KERNEL_KINDS   10
+
+/* Accumulated per kernel kind while profiling is enabled.  `units` counts
+ * (right-hand side, voxel) pairs processed; `bytes` is the algorithmic HBM
+ * traffic of those launches (each vector, block and factor entry moved once;
+ * neighbour re-reads and index tables excluded); `ms` is the sum of the
+ * launches' durations measured with HIP events on the context's stream.    */
+typedef struct gp_prof {
+  int64_t launches;
+  int64_t units;
+  double  ms;
+  double  bytes;
+} gp_prof;
+
 void        gp_opts_default(gp_opts* opts);
 const char* gp_last_error(void);
 int         gp_version(void);
@@ -116,6 +141,12 @@ int gp_ctx_set_stream(gp_ctx* ctx, void* hip_stream);
 /* bytes currently allocated by the library for this context (host out)     */
 int gp_ctx_memory(const gp_ctx* ctx, size_t* used, size_t* budget);
 int gp_ctx_destroy(gp_ctx* ctx);
+/* gp_ctx_profile: enable (1) or disable (0) per-launch event timing on this
+ * context; enabling clears the accumulated figures.  gp_ctx_profile_read
+ * synchronises the stream and copies the figures of one GP_KERNEL_* kind
+ * into *out (host).                                                          */
+int gp_ctx_profile(gp_ctx* ctx, int enable);
+int gp_ctx_profile_read(gp_ctx* ctx, int kind, gp_prof* out);
 
 /* ---- operator ----------------------------------------------------------
  * gp_op_create: build the masked-grid operator (Section 2: the unweighted

@@ -48,12 +48,16 @@ struct gp_ctx {
   // right-hand-side staging for sample/trace
   double* rhs = nullptr;
   size_t rhs_cap = 0;
-  // grouped-launch descriptors and phase summaries
+  // grouped-launch descriptors
   Prob* d_probs = nullptr;
   Prob* h_probs = nullptr;
   size_t probs_cap = 0;
-  int* h_summary = nullptr;
-  size_t summary_cap = 0;
+  // profiling: event pairs around launches, resolved after the stream drains
+  bool prof_on = false;
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> pending;   // (kind, first event of the pair)
+  gp_prof acc[GP_KERNEL_KINDS] = {};
 };
 
 struct gp_op {
@@ -172,19 +176,70 @@ int ensure_probs(gp_ctx* c, size_t n) {
     HIPTRY(hipStreamSynchronize(c->stream));
     dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
     (void)hipHostFree(c->h_probs);
-    (void)hipHostFree(c->h_summary);
     c->d_probs = nullptr;
     c->h_probs = nullptr;
-    c->h_summary = nullptr;
   }
   const size_t cap = std::max<size_t>(n, 16);
   int st = dev_alloc(c, cap * sizeof(Prob), (void**)&c->d_probs);
   if (st != GP_OK) return st;
   HIPTRY(hipHostMalloc((void**)&c->h_probs, cap * sizeof(Prob), hipHostMallocDefault));
-  HIPTRY(hipHostMalloc((void**)&c->h_summary, cap * NSUM * sizeof(int), hipHostMallocDefault));
   c->probs_cap = cap;
   return GP_OK;
 }
+
+// ------------------------------------------------------------ profiling
+int prof_begin(gp_ctx* c, size_t* slot) {
+  if (c->ev_used + 2 > c->evpool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      HIPTRY(hipEventCreate(&e));
+      c->evpool.push_back(e);
+    }
+  }
+  *slot = c->ev_used;
+  c->ev_used += 2;
+  HIPTRY(hipEventRecord(c->evpool[*slot], c->stream));
+  return GP_OK;
+}
+
+int prof_end(gp_ctx* c, int kind, size_t slot) {
+  HIPTRY(hipEventRecord(c->evpool[slot + 1], c->stream));
+  c->pending.push_back({kind, slot});
+  return GP_OK;
+}
+
+// Waits for the stream and folds the recorded launch durations into acc.
+int prof_resolve(gp_ctx* c) {
+  if (c->pending.empty()) return GP_OK;
+  HIPTRY(hipStreamSynchronize(c->stream));
+  for (auto& pe : c->pending) {
+    float ms = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms, c->evpool[pe.second], c->evpool[pe.second + 1]));
+    c->acc[pe.first].ms += ms;
+    c->acc[pe.first].launches += 1;
+  }
+  c->pending.clear();
+  c->ev_used = 0;
+  return GP_OK;
+}
+
+void prof_add(gp_ctx* c, int kind, double units, double bytes) {
+  if (!c->prof_on) return;
+  c->acc[kind].units += (int64_t)units;
+  c->acc[kind].bytes += bytes;
+}
+
+#define PROFILED(ctx, kind, launch)                                  \
+  do {                                                               \
+    size_t slot_ = 0;                                                \
+    if ((ctx)->prof_on) {                                            \
+      if (int st_ = prof_begin((ctx), &slot_)) return st_;           \
+    }                                                                \
+    HIPTRY(launch);                                                  \
+    if ((ctx)->prof_on) {                                            \
+      if (int st_ = prof_end((ctx), (kind), slot_)) return st_;      \
+    }                                                                \
+  } while (0)
 
 OpDev op_dev(const gp_op* op) {
   OpDev d;
@@ -223,8 +278,13 @@ int build_precond(gp_op* op, int pc) {
   int st = reset_bad(op);
   if (st) return st;
   const OpDev d = op_dev(op);
-  HIPTRY(launch_precond(op->ctx->stream, d, pc == GP_PRECOND_JACOBI ? PC_JACOBI : PC_BLOCK, op->P64, op->P32,
-                        op->d_bad));
+  PROFILED(op->ctx, GP_KERNEL_PRECOND,
+           launch_precond(op->ctx->stream, d, pc == GP_PRECOND_JACOBI ? PC_JACOBI : PC_BLOCK, op->P64, op->P32,
+                          op->d_bad));
+  {
+    const double NB = op->K * (op->K + 1) / 2.0, NP = pc == GP_PRECOND_JACOBI ? op->K : NB;
+    prof_add(op->ctx, GP_KERNEL_PRECOND, op->N, (double)op->N * (NB * 8 + NP * 12));
+  }
   int bad = INT_MAX;
   st = read_bad(op, &bad);
   if (st) return st;
@@ -293,12 +353,22 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     }
     return GP_OK;
   }
-  // workspace layout
+  // workspace layout: the states of all problems are contiguous so that one
+  // copy brings every right-hand side's phase to the host
   struct Layout {
-    size_t vec[6], st, part, counter, summary;
+    size_t vec[6], st, part, prof;
   };
   std::vector<Layout> lay(np);
   size_t off = 0;
+  const size_t st_all = off;
+  {
+    size_t cnt = 0;
+    for (int j = 0; j < np; ++j) {
+      lay[j].st = st_all + cnt * sizeof(RhsState);
+      cnt += (size_t)items[order[j]].R;
+    }
+    off = align_up(st_all + cnt * sizeof(RhsState), 256);
+  }
   for (int j = 0; j < np; ++j) {
     const Item& it = items[order[j]];
     const size_t nv = (size_t)it.R * it.op->K * it.op->N;
@@ -306,27 +376,23 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       lay[j].vec[v] = off;
       off = align_up(off + nv * tsz, 256);
     }
-    lay[j].st = off;
-    off = align_up(off + (size_t)it.R * sizeof(RhsState), 256);
     lay[j].part = off;
     off = align_up(off + (size_t)NPART * it.R * it.op->ntiles * sizeof(double), 256);
-    lay[j].counter = off;
-    off = align_up(off + sizeof(unsigned), 256);
+    lay[j].prof = off;
+    off = align_up(off + NPROF * sizeof(long long), 256);
   }
-  const size_t sum_off = off;
-  off = align_up(off + (size_t)np * NSUM * sizeof(int), 256);
   int st = ensure_ws(c, off);
   if (st) return st;
   st = ensure_probs(c, np);
   if (st) return st;
   char* ws = (char*)c->ws;
-  int* d_summary = (int*)(ws + sum_off);
-  // descriptors
+  // descriptors, one grouped launch per distinct K
   struct Group {
-    int K, first, count, W;
+    int K, first, count, W, F;
   };
   std::vector<Group> groups;
   const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
+  const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < np; ++j) {
     const Item& it = items[order[j]];
     Prob& p = c->h_probs[j];
@@ -342,8 +408,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.q = ws + lay[j].vec[5];
     p.st = (RhsState*)(ws + lay[j].st);
     p.part = (double*)(ws + lay[j].part);
-    p.counter = (unsigned*)(ws + lay[j].counter);
-    p.summary = d_summary + (size_t)j * NSUM;
+    p.prof = c->prof_on ? (long long*)(ws + lay[j].prof) : nullptr;
     p.R = it.R;
     int rc = o.rhs_tile > 0 ? o.rhs_tile : 8;
     rc = std::max(1, std::min(std::min(rc, RCMAX), it.R));
@@ -351,53 +416,64 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.nchunks = (it.R + rc - 1) / rc;
     p.work_count = it.op->ntiles * p.nchunks;
     p.cfg = cfg;
-    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0});
+    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0, 0});
     Group& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
+    p.fin_begin = g.F;
+    g.F += (it.R + fpb - 1) / fpb;
     g.count += 1;
   }
   hipStream_t s = c->stream;
   HIPTRY(hipMemcpyAsync(c->d_probs, c->h_probs, np * sizeof(Prob), hipMemcpyHostToDevice, s));
-  for (int j = 0; j < np; ++j) {
-    const Item& it = items[order[j]];
-    HIPTRY(hipMemsetAsync(ws + lay[j].st, 0, (size_t)it.R * sizeof(RhsState), s));
-    HIPTRY(hipMemsetAsync(ws + lay[j].counter, 0, sizeof(unsigned), s));
-  }
-  HIPTRY(hipMemsetAsync(d_summary, 0, (size_t)np * NSUM * sizeof(int), s));
+  HIPTRY(hipMemsetAsync(ws + st_all, 0, totalR * sizeof(RhsState), s));
+  for (int j = 0; j < np; ++j) HIPTRY(hipMemsetAsync(ws + lay[j].prof, 0, NPROF * sizeof(long long), s));
 
+  int epoch = 0;
   auto launch_outer = [&](bool with_add) -> int {
+    ++epoch;
     for (const Group& g : groups) {
       const Prob* dp = c->d_probs + g.first;
-      if (with_add) HIPTRY(f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W) : launch_addsol_f64(s, g.K, dp, g.count, g.W));
-      HIPTRY(f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W)
-                 : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W));
+      if (with_add)
+        PROFILED(c, GP_KERNEL_ADDSOL,
+                 f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W) : launch_addsol_f64(s, g.K, dp, g.count, g.W));
+      PROFILED(c, GP_KERNEL_REFINE,
+               f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W)
+                   : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W));
+      HIPTRY(launch_finalize(s, 0, dp, g.count, g.F, epoch));
     }
     return GP_OK;
   };
   int parity = 0;
   auto launch_inner = [&](int iters) -> int {
     for (int i = 0; i < iters; ++i) {
+      ++epoch;
       for (const Group& g : groups) {
         const Prob* dp = c->d_probs + g.first;
-        HIPTRY(f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, parity)
-                   : launch_matvec_f64(s, g.K, dp, g.count, g.W, parity));
-        HIPTRY(f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, parity)
-                   : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, parity));
+        PROFILED(c, GP_KERNEL_MATVEC,
+                 f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, parity)
+                     : launch_matvec_f64(s, g.K, dp, g.count, g.W, parity));
+        HIPTRY(launch_finalize(s, 1, dp, g.count, g.F, epoch));
+        PROFILED(c, GP_KERNEL_UPDATE,
+                 f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, parity)
+                     : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, parity));
+        HIPTRY(launch_finalize(s, 2, dp, g.count, g.F, epoch));
       }
       parity ^= 1;
     }
     return GP_OK;
   };
+  // host copy of every right-hand side's state
+  std::vector<RhsState> hs(totalR);
   int n_outer = (int)totalR, n_inner = 0, n_done = 0;
-  auto read_summary = [&]() -> int {
-    HIPTRY(hipMemcpyAsync(c->h_summary, d_summary, (size_t)np * NSUM * sizeof(int), hipMemcpyDeviceToHost, s));
+  auto read_states = [&]() -> int {
+    HIPTRY(hipMemcpyAsync(hs.data(), ws + st_all, totalR * sizeof(RhsState), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     n_outer = n_inner = n_done = 0;
-    for (int j = 0; j < np; ++j) {
-      n_outer += c->h_summary[j * NSUM + 0];
-      n_inner += c->h_summary[j * NSUM + 1];
-      n_done += c->h_summary[j * NSUM + 2];
+    for (const RhsState& h : hs) {
+      n_outer += h.phase == PH_OUTER;
+      n_inner += h.phase == PH_INNER;
+      n_done += h.phase == PH_DONE;
     }
     return GP_OK;
   };
@@ -414,19 +490,18 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       if (st) return st;
       first = false;
       if (n_inner == 0) {
-        st = read_summary();
+        st = read_states();
         if (st) return st;
         if (n_inner == 0 && n_outer == 0) break;
       }
     }
     st = launch_inner(chunk);
     if (st) return st;
-    st = read_summary();
+    st = read_states();
     if (st) return st;
     if (n_outer == 0 && n_inner == 0) break;
   }
-  // results
-  std::vector<RhsState> hs;
+  // results (hs holds the final states, in problem order)
   int ret = GP_OK;
   std::vector<gp_stats> all(totalR);
   std::vector<size_t> base(items.size());
@@ -438,14 +513,12 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     }
   }
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  size_t hpos = 0;
   for (int j = 0; j < np; ++j) {
     const Item& it = items[order[j]];
-    hs.resize(it.R);
-    HIPTRY(hipMemcpyAsync(hs.data(), ws + lay[j].st, (size_t)it.R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
-    HIPTRY(hipStreamSynchronize(s));
     const size_t nv = (size_t)it.op->K * it.op->N;
     for (int r = 0; r < it.R; ++r) {
-      const RhsState& h = hs[r];
+      const RhsState& h = hs[hpos++];
       if (h.zero_b) HIPTRY(hipMemsetAsync(it.x + (size_t)r * nv, 0, nv * sizeof(double), s));
       gp_stats& g = all[base[order[j]] + r];
       g.status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
@@ -458,6 +531,25 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     }
   }
   HIPTRY(hipStreamSynchronize(s));
+  if (c->prof_on) {
+    std::vector<long long> pf(NPROF);
+    for (int j = 0; j < np; ++j) {
+      const Item& it = items[order[j]];
+      HIPTRY(hipMemcpy(pf.data(), ws + lay[j].prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
+      const double N = it.op->N, K = it.op->K, ts = (double)tsz;
+      const double NB = K * (K + 1) / 2, NP = o.precond == GP_PRECOND_JACOBI ? K : NB;
+      prof_add(c, GP_KERNEL_REFINE, pf[PF_REFINE_RHS] * N,
+               pf[PF_REFINE_RHS] * N * K * (16 + 2 * ts) + pf[PF_REFINE_ACT] * N * (NB * 8 + NP * ts));
+      prof_add(c, GP_KERNEL_ADDSOL, pf[PF_ADDSOL_RHS] * N, pf[PF_ADDSOL_RHS] * N * K * (16 + ts));
+      prof_add(c, GP_KERNEL_MATVEC, pf[PF_MATVEC_RHS] * N,
+               (pf[PF_MATVEC_RHS] - pf[PF_MATVEC_FIRST]) * N * 4 * K * ts + pf[PF_MATVEC_FIRST] * N * 3 * K * ts +
+                   pf[PF_MATVEC_ACT] * N * NB * ts);
+      prof_add(c, GP_KERNEL_UPDATE, pf[PF_UPDATE_RHS] * N,
+               (pf[PF_UPDATE_RHS] - pf[PF_UPDATE_FRESH]) * N * 7 * K * ts + pf[PF_UPDATE_FRESH] * N * 6 * K * ts +
+                   pf[PF_UPDATE_ACT] * N * NP * ts);
+    }
+    if (int e = prof_resolve(c)) return e;
+  }
   if (stats) std::memcpy(stats, all.data(), totalR * sizeof(gp_stats));
   if (ret == GP_ERR_NOT_CONVERGED) return fail(ret, "some right-hand sides did not reach the tolerance");
   if (ret == GP_ERR_BREAKDOWN) return fail(ret, "PCG breakdown (non-finite value or loss of definiteness)");
@@ -524,6 +616,29 @@ int gp_ctx_memory(const gp_ctx* c, size_t* used, size_t* budget) {
   return GP_OK;
 }
 
+int gp_ctx_profile(gp_ctx* c, int enable) {
+  if (!c) return fail(GP_ERR_INVALID_ARG, "ctx is NULL");
+  BusyGuard g(c);
+  if (!g.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  if (int st = prof_resolve(c)) return st;
+  c->prof_on = enable != 0;
+  if (enable)
+    for (auto& a : c->acc) a = gp_prof{0, 0, 0.0, 0.0};
+  return GP_OK;
+}
+
+int gp_ctx_profile_read(gp_ctx* c, int kind, gp_prof* out) {
+  if (!c || !out) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (kind < 0 || kind >= GP_KERNEL_KINDS) return fail(GP_ERR_INVALID_ARG, "unknown kernel kind");
+  BusyGuard g(c);
+  if (!g.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  if (int st = prof_resolve(c)) return st;
+  *out = c->acc[kind];
+  return GP_OK;
+}
+
 int gp_ctx_destroy(gp_ctx* c) {
   if (!c) return GP_OK;
   (void)hipSetDevice(c->device);
@@ -532,12 +647,17 @@ int gp_ctx_destroy(gp_ctx* c) {
   if (c->rhs) dev_free(c, c->rhs, c->rhs_cap * sizeof(double));
   if (c->d_probs) dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
   if (c->h_probs) (void)hipHostFree(c->h_probs);
-  if (c->h_summary) (void)hipHostFree(c->h_summary);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   delete c;
   return GP_OK;
 }
 
 int gp_op_destroy(gp_op* op);
+
+static void prof_perturb(gp_op* op, int R) {
+  const double K = op->K, NB = K * (K + 1) / 2, N = op->N;
+  prof_add(op->ctx, GP_KERNEL_PERTURB, R * N, R * N * K * (op->dirs + 2) * 8 + N * (NB + K) * 8);
+}
 
 int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, int conn, int K, gp_op** out) {
   if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
@@ -656,7 +776,11 @@ int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
   if (int st = reset_bad(op)) return st;
-  HIPTRY(launch_pack_blocks(c->stream, op->K, op->N, B, op->B64, op->B32, op->L64, op->d_bad));
+  PROFILED(c, GP_KERNEL_PACK, launch_pack_blocks(c->stream, op->K, op->N, B, op->B64, op->B32, op->L64, op->d_bad));
+  {
+    const double K = op->K, NB = K * (K + 1) / 2;
+    prof_add(c, GP_KERNEL_PACK, op->N, (double)op->N * (K * K * 8 + NB * 20));
+  }
   int bad = INT_MAX;
   if (int st = read_bad(op, &bad)) return st;
   op->pc_built = -1;
@@ -712,7 +836,11 @@ int gp_apply(gp_op* op, int R, const double* x, double* y) {
   BusyGuard guard(c);
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
-  HIPTRY(launch_apply(c->stream, op_dev(op), R, x, y));
+  PROFILED(c, GP_KERNEL_APPLY, launch_apply(c->stream, op_dev(op), R, x, y));
+  {
+    const double K = op->K, NB = K * (K + 1) / 2, N = op->N;
+    prof_add(c, GP_KERNEL_APPLY, R * N, R * N * 2 * K * 8 + N * NB * 8);
+  }
   return GP_OK;
 }
 
@@ -751,7 +879,8 @@ int gp_perturb_rhs(gp_op* op, int R, const double* bw, const double* z1, const d
   BusyGuard guard(c);
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
-  HIPTRY(launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, b));
+  PROFILED(c, GP_KERNEL_PERTURB, launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, b));
+  prof_perturb(op, R);
   return GP_OK;
 }
 
@@ -769,7 +898,8 @@ int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
   if (int st = ensure_rhs(c, (size_t)R * op->K * op->N)) return st;
-  HIPTRY(launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, c->rhs));
+  PROFILED(c, GP_KERNEL_PERTURB, launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, c->rhs));
+  prof_perturb(op, R);
   std::vector<Item> items{Item{op, R, c->rhs, w}};
   return run_group(c, items, o, stats);
 }
@@ -783,7 +913,8 @@ int gp_probe_rhs(gp_op* op, int m, const int8_t* probes, double* b) {
   BusyGuard guard(c);
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
-  HIPTRY(launch_probe_rhs(c->stream, (long)m * op->K * op->N, probes, b));
+  PROFILED(c, GP_KERNEL_PROBE, launch_probe_rhs(c->stream, (long)m * op->K * op->N, probes, b));
+  prof_add(c, GP_KERNEL_PROBE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
   return GP_OK;
 }
 
@@ -801,7 +932,8 @@ static int trace_reduce_impl(gp_op* op, int m, const int8_t* probes, const doubl
   double* part = op->tr_part;
   double* pairbuf = part + (size_t)2 * m * op->K * op->ntiles;
   double* out = pairbuf + (size_t)2 * m * op->K;
-  HIPTRY(launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
+  PROFILED(c, GP_KERNEL_TRACE, launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
+  prof_add(c, GP_KERNEL_TRACE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
   std::vector<double> h(1 + 2 * op->K);
   HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
@@ -839,7 +971,8 @@ int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total
   if (int st = set_device(c)) return st;
   const size_t nv = (size_t)m * op->K * op->N;
   if (int st = ensure_rhs(c, nv)) return st;
-  HIPTRY(launch_probe_rhs(c->stream, (long)nv, probes, c->rhs));
+  PROFILED(c, GP_KERNEL_PROBE, launch_probe_rhs(c->stream, (long)nv, probes, c->rhs));
+  prof_add(c, GP_KERNEL_PROBE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
   HIPTRY(hipMemsetAsync(u, 0, nv * sizeof(double), c->stream));
   std::vector<Item> items{Item{op, m, c->rhs, u}};
   const int st = run_group(c, items, o, stats);

@@ -454,6 +454,19 @@ hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* 
   return hipGetLastError();
 }
 
+hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks, int epoch) {
+  const dim3 g(nblocks), b(FIN_WAVES * WAVE);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_finalize<0>, g, b, 0, s, probs, nprob, epoch); break;
+    case 1: hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, probs, nprob, epoch); break;
+    case 2: hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, probs, nprob, epoch); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int finalize_rhs_per_block() { return FIN_WAVES; }
+
 hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, const double* u,
                         double* part, double* pairbuf, double* out) {
   const dim3 g(op.ntiles, m), b(TILE);

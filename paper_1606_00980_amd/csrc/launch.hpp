@@ -23,6 +23,11 @@ hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* 
 hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, const double* u,
                         double* part, double* pairbuf, double* out);
 
+// Finalising launch after a refine (kind 0), matvec (1) or update (2) launch:
+// nblocks = sum over problems of ceil(R / finalize_rhs_per_block()).
+hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks, int epoch);
+int finalize_rhs_per_block();
+
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that
 // all have K regressors; W = total work items (tiles x right-hand-side chunks).
 hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W);

@@ -15,8 +15,9 @@
 //   matvec  (T)     : p = z + beta p_old (p = z at the first step), q = Q p, p'q
 //   update  (T)     : d += a p, r -= a q, z = M^{-1} r, r'z, r'r
 //   addsol  (FP64)  : x += d once an inner solve has ended
-// The workgroup that finishes last in each launch reduces the per-tile
-// partials in a fixed order and advances every right-hand side's state.
+// Each of those kernels stores per-tile partial sums; a small finalising
+// kernel then reduces them per right-hand side in a fixed order and advances
+// that right-hand side's state, so no workgroup waits on another.
 #pragma once
 #include "device.hpp"
 
@@ -110,90 +111,136 @@ __device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int W)
 
 __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 
+// Does any right-hand side in [r0, r1) sit in `phase`?  (uniform per workgroup)
+__device__ inline bool any_in_phase(const Prob& pr, int r0, int r1, int phase) {
+  for (int r = r0; r < r1; ++r)
+    if (pr.st[r].phase == phase) return true;
+  return false;
+}
+
 // --------------------------------------------------------------- finalisers
-__device__ inline void finalize_refine(const Prob& pr) {
-  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
-  for (int r = wv; r < pr.R; r += nw) {
-    RhsState& s = pr.st[r];
-    if (s.phase != PH_OUTER) continue;
+// Each finaliser advances one right-hand side from the per-tile partials of
+// the launch that just ended; it runs on lane 0 of the wavefront that summed
+// them.  Counters for the profiler are added with integer atomics.
+__device__ inline void prof_add(const Prob& pr, int slot, long long v) {
+  if (pr.prof && v) atomicAdd((unsigned long long*)&pr.prof[slot], (unsigned long long)v);
+}
+
+// Counts launch `epoch` once in slot `act` (launches that had work to do).
+__device__ inline void prof_launch(const Prob& pr, int act, int ep_slot, int epoch) {
+  if (!pr.prof) return;
+  const unsigned long long old = atomicMax((unsigned long long*)&pr.prof[ep_slot], (unsigned long long)epoch);
+  if (old < (unsigned long long)epoch) atomicAdd((unsigned long long*)&pr.prof[act], 1ull);
+}
+
+__device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[3]) {
+  RhsState& s = pr.st[r];
+  const double rr = v[0], bb = v[1], rz = v[2];
+  prof_add(pr, PF_REFINE_RHS, 1);
+  prof_add(pr, PF_ADDSOL_RHS, s.has_d);
+  if (s.outer == 0) s.bnorm2 = bb;
+  s.has_d = 0;
+  s.outer += 1;
+  s.rr64 = rr;
+  const double bn2 = s.bnorm2;
+  if (!finite(bn2)) {
+    s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+  } else if (bn2 == 0.0) {
+    s.relres = 0.0; s.zero_b = 1; s.status = ST_OK; s.phase = PH_DONE;
+  } else {
+    const double rel = sqrt(rr / bn2);
+    s.relres = rel;
+    if (!finite(rel)) {
+      s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+    } else if (rel <= pr.cfg.tol) {
+      s.status = ST_OK; s.phase = PH_DONE;
+    } else if (s.outer >= pr.cfg.max_outer || s.total_it >= pr.cfg.max_iter) {
+      s.status = ST_NOT_CONVERGED; s.phase = PH_DONE;
+    } else if (!(rz > 0.0) || !finite(rz)) {
+      s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+    } else {
+      const double it2 = pr.cfg.inner_tol * pr.cfg.inner_tol * rr;
+      const double ot2 = 0.25 * pr.cfg.tol * pr.cfg.tol * bn2;
+      s.target2 = it2 > ot2 ? it2 : ot2;
+      s.rho = rz;
+      s.first = 1;
+      s.inner_it = 0;
+      s.has_d = 1;
+      s.phase = PH_INNER;
+    }
+  }
+}
+
+__device__ inline void finalize_matvec(const Prob& pr, int r, const double (&v)[1]) {
+  RhsState& s = pr.st[r];
+  prof_add(pr, PF_MATVEC_RHS, 1);
+  prof_add(pr, PF_MATVEC_FIRST, s.first);
+  const double sigma = v[0];
+  if (!(sigma > 0.0) || !finite(sigma)) {
+    if (s.inner_it == 0) {       // no usable correction yet
+      s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+    } else {                     // keep the correction so far; re-evaluate in FP64
+      s.phase = PH_OUTER;
+    }
+  } else {
+    s.a = s.rho / sigma;
+    s.first = 0;
+  }
+}
+
+__device__ inline void finalize_update(const Prob& pr, int r, const double (&v)[2]) {
+  RhsState& s = pr.st[r];
+  prof_add(pr, PF_UPDATE_RHS, 1);
+  prof_add(pr, PF_UPDATE_FRESH, s.inner_it == 0);
+  const double rz = v[0], rr = v[1];
+  s.inner_it += 1;
+  s.total_it += 1;
+  if (!finite(rr) || !finite(rz)) {
+    s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
+  } else if (rr <= s.target2 || s.total_it >= pr.cfg.max_iter || !(rz > 0.0)) {
+    s.phase = PH_OUTER;
+  } else {
+    s.beta = rz / s.rho;
+    s.rho = rz;
+  }
+}
+
+constexpr int FIN_WAVES = 4;   // right-hand sides finalised per workgroup
+
+// One wavefront per right-hand side of one problem: sum that right-hand side's
+// partials over the tiles in a fixed order and advance its state.
+template <int KIND>
+__global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __restrict__ probs, int nprob,
+                                                                int epoch) {
+  const int b = blockIdx.x;
+  int p = 0;
+  while (p + 1 < nprob && b >= probs[p + 1].fin_begin) ++p;
+  const Prob& pr = probs[p];
+  const int r = (b - pr.fin_begin) * FIN_WAVES + (int)(threadIdx.x / WAVE);
+  if (r >= pr.R) return;
+  const int want = KIND == 0 ? PH_OUTER : PH_INNER;
+  if (pr.st[r].phase != want) return;
+  const int lane = threadIdx.x % WAVE;
+  if constexpr (KIND == 0) {
     double v[3];
     sum_partials<3>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane != 0) continue;
-    const double rr = v[0], bb = v[1], rz = v[2];
-    if (s.outer == 0) s.bnorm2 = bb;
-    s.has_d = 0;
-    s.outer += 1;
-    s.rr64 = rr;
-    const double bn2 = s.bnorm2;
-    if (!finite(bn2)) {
-      s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-    } else if (bn2 == 0.0) {
-      s.relres = 0.0; s.zero_b = 1; s.status = ST_OK; s.phase = PH_DONE;
-    } else {
-      const double rel = sqrt(rr / bn2);
-      s.relres = rel;
-      if (!finite(rel)) {
-        s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-      } else if (rel <= pr.cfg.tol) {
-        s.status = ST_OK; s.phase = PH_DONE;
-      } else if (s.outer >= pr.cfg.max_outer || s.total_it >= pr.cfg.max_iter) {
-        s.status = ST_NOT_CONVERGED; s.phase = PH_DONE;
-      } else if (!(rz > 0.0) || !finite(rz)) {
-        s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-      } else {
-        const double it2 = pr.cfg.inner_tol * pr.cfg.inner_tol * rr;
-        const double ot2 = 0.25 * pr.cfg.tol * pr.cfg.tol * bn2;
-        s.target2 = it2 > ot2 ? it2 : ot2;
-        s.rho = rz;
-        s.first = 1;
-        s.inner_it = 0;
-        s.has_d = 1;
-        s.phase = PH_INNER;
-      }
+    if (lane == 0) {
+      prof_launch(pr, PF_REFINE_ACT, PF_REFINE_EPOCH, epoch);
+      finalize_refine(pr, r, v);
     }
-  }
-}
-
-__device__ inline void finalize_matvec(const Prob& pr) {
-  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
-  for (int r = wv; r < pr.R; r += nw) {
-    RhsState& s = pr.st[r];
-    if (s.phase != PH_INNER) continue;
+  } else if constexpr (KIND == 1) {
     double v[1];
     sum_partials<1>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane != 0) continue;
-    const double sigma = v[0];
-    if (!(sigma > 0.0) || !finite(sigma)) {
-      if (s.inner_it == 0) {       // no usable correction yet
-        s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-      } else {                     // keep the correction so far; re-evaluate in FP64
-        s.phase = PH_OUTER;
-      }
-    } else {
-      s.a = s.rho / sigma;
-      s.first = 0;
+    if (lane == 0) {
+      prof_launch(pr, PF_MATVEC_ACT, PF_MATVEC_EPOCH, epoch);
+      finalize_matvec(pr, r, v);
     }
-  }
-}
-
-__device__ inline void finalize_update(const Prob& pr) {
-  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE, lane = threadIdx.x % WAVE;
-  for (int r = wv; r < pr.R; r += nw) {
-    RhsState& s = pr.st[r];
-    if (s.phase != PH_INNER) continue;
+  } else {
     double v[2];
     sum_partials<2>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane != 0) continue;
-    const double rz = v[0], rr = v[1];
-    s.inner_it += 1;
-    s.total_it += 1;
-    if (!finite(rr) || !finite(rz)) {
-      s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-    } else if (rr <= s.target2 || s.total_it >= pr.cfg.max_iter || !(rz > 0.0)) {
-      s.phase = PH_OUTER;
-    } else {
-      s.beta = rz / s.rho;
-      s.rho = rz;
+    if (lane == 0) {
+      prof_launch(pr, PF_UPDATE_ACT, PF_UPDATE_EPOCH, epoch);
+      finalize_update(pr, r, v);
     }
   }
 }
@@ -207,6 +254,9 @@ __global__ __launch_bounds__(TILE) void k_refine(const Prob* __restrict__ probs,
   const Prob& pr = probs[w.p];
   const OpDev& op = pr.op;
   const int N = op.N, nn = w.nn;
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  if (!any_in_phase(pr, r0, r1, PH_OUTER)) return;
   int nb[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
@@ -214,8 +264,6 @@ __global__ __launch_bounds__(TILE) void k_refine(const Prob* __restrict__ probs,
   load_soa(op.B64, N, nn, B);
   T P[NP];
   load_soa(OpT<T>::P(op), N, nn, P);
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
   for (int r = r0; r < r1; ++r) {
     if (pr.st[r].phase != PH_OUTER) continue;
     const double* xr = pr.x + (size_t)r * K * N;
@@ -262,10 +310,6 @@ __global__ __launch_bounds__(TILE) void k_refine(const Prob* __restrict__ probs,
     wave_deposit<3>(s_red, r - r0, acc);
   }
   flush_partials<3>(pr, s_red, r0, r1, w.tile, PH_OUTER);
-  if (arrive_last(pr)) {
-    finalize_refine(pr);
-    publish_summary(pr);
-  }
 }
 
 template <typename T, int K>
@@ -277,6 +321,9 @@ __global__ __launch_bounds__(TILE) void k_matvec(const Prob* __restrict__ probs,
   const Prob& pr = probs[w.p];
   const OpDev& op = pr.op;
   const int N = op.N, nn = w.nn;
+  const int r0 = w.chunk * pr.Rc;
+  const int r1 = min(pr.R, r0 + pr.Rc);
+  if (!any_in_phase(pr, r0, r1, PH_INNER)) return;
   int nb[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
@@ -285,8 +332,6 @@ __global__ __launch_bounds__(TILE) void k_matvec(const Prob* __restrict__ probs,
   T al[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) al[k] = OpT<T>::alpha(op, k);
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
   for (int r = r0; r < r1; ++r) {
     const RhsState& s = pr.st[r];
     if (s.phase != PH_INNER) continue;
@@ -339,10 +384,6 @@ __global__ __launch_bounds__(TILE) void k_matvec(const Prob* __restrict__ probs,
     wave_deposit<1>(s_red, r - r0, acc);
   }
   flush_partials<1>(pr, s_red, r0, r1, w.tile, PH_INNER);
-  if (arrive_last(pr)) {
-    finalize_matvec(pr);
-    publish_summary(pr);
-  }
 }
 
 template <typename T, int PC, int K>
@@ -354,10 +395,11 @@ __global__ __launch_bounds__(TILE) void k_update(const Prob* __restrict__ probs,
   const Prob& pr = probs[w.p];
   const OpDev& op = pr.op;
   const int N = op.N, nn = w.nn;
-  T P[NP];
-  load_soa(OpT<T>::P(op), N, nn, P);
   const int r0 = w.chunk * pr.Rc;
   const int r1 = min(pr.R, r0 + pr.Rc);
+  if (!any_in_phase(pr, r0, r1, PH_INNER)) return;
+  T P[NP];
+  load_soa(OpT<T>::P(op), N, nn, P);
   for (int r = r0; r < r1; ++r) {
     const RhsState& s = pr.st[r];
     if (s.phase != PH_INNER) continue;
@@ -393,10 +435,6 @@ __global__ __launch_bounds__(TILE) void k_update(const Prob* __restrict__ probs,
     wave_deposit<2>(s_red, r - r0, acc);
   }
   flush_partials<2>(pr, s_red, r0, r1, w.tile, PH_INNER);
-  if (arrive_last(pr)) {
-    finalize_update(pr);
-    publish_summary(pr);
-  }
 }
 
 // x += d for right-hand sides whose inner solve has ended.

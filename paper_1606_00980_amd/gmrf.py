@@ -36,6 +36,7 @@ GP_PREC_FP32_REFINE64 = 1
 EXPORTS = [
     "gp_opts_default", "gp_last_error", "gp_version",
     "gp_ctx_create", "gp_ctx_set_stream", "gp_ctx_memory", "gp_ctx_destroy",
+    "gp_ctx_profile", "gp_ctx_profile_read",
     "gp_op_create", "gp_op_set_blocks", "gp_op_set_alpha", "gp_op_query",
     "gp_op_voxel_index", "gp_op_destroy",
     "gp_apply", "gp_solve", "gp_solve_batch", "gp_perturb_rhs", "gp_sample",
@@ -55,6 +56,15 @@ class GpStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("outer_steps", ctypes.c_int), ("reserved", ctypes.c_int),
                 ("relres", ctypes.c_double), ("time_us", ctypes.c_double)]
+
+
+class GpProf(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("units", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KERNEL_KINDS = ["refine", "matvec", "update", "addsol", "perturb", "precond", "pack",
+                "probe", "trace", "apply"]
 
 
 class GpItem(ctypes.Structure):
@@ -84,6 +94,8 @@ def _load() -> ctypes.CDLL:
         "gp_ctx_set_stream": (i32, [vp, vp]),
         "gp_ctx_memory": (i32, [vp, P(sz), P(sz)]),
         "gp_ctx_destroy": (i32, [vp]),
+        "gp_ctx_profile": (i32, [vp, i32]),
+        "gp_ctx_profile_read": (i32, [vp, i32, P(GpProf)]),
         "gp_op_create": (i32, [vp, vp, i32, i32, i32, i32, i32, P(vp)]),
         "gp_op_set_blocks": (i32, [vp, vp, P(i64)]),
         "gp_op_set_alpha": (i32, [vp, P(dbl)]),
@@ -158,6 +170,20 @@ def gp_ctx_memory(ctx: int):
 
 def gp_ctx_destroy(ctx: int) -> None:
     _check(lib.gp_ctx_destroy(ctx), "gp_ctx_destroy")
+
+
+def gp_ctx_profile(ctx: int, enable: bool) -> None:
+    _check(lib.gp_ctx_profile(ctx, 1 if enable else 0), "gp_ctx_profile")
+
+
+def gp_ctx_profile_read(ctx: int) -> dict:
+    """{kind: {launches, units, ms, bytes}} for every kernel kind."""
+    out = {}
+    for i, name in enumerate(KERNEL_KINDS):
+        p = GpProf()
+        _check(lib.gp_ctx_profile_read(ctx, i, ctypes.byref(p)), "gp_ctx_profile_read")
+        out[name] = {"launches": p.launches, "units": p.units, "ms": p.ms, "bytes": p.bytes}
+    return out
 
 
 def gp_op_create(ctx: int, mask: np.ndarray, conn: int, K: int) -> int:
