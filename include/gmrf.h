@@ -82,6 +82,7 @@ typedef struct gp_opts {
   int      precision;  /* GP_PREC_*; default GP_PREC_FP32_REFINE64              */
   int      rhs_tile;   /* right-hand sides per workgroup, 0 = automatic          */
   int      chunk;      /* PCG iterations enqueued between host checks, 0 = auto  */
+  int      wg_per_cu;  /* persistent workgroups per compute unit, 0 = auto       */
   uint64_t seed;       /* reserved for on-device random vectors                  */
 } gp_opts;
 

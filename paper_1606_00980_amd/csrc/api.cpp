@@ -39,6 +39,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct gp_ctx {
   int device = 0;
+  int cus = 256;     // compute units of the device
   hipStream_t stream = nullptr;
   size_t budget = 0, used = 0;
   std::atomic<int> busy{0};
@@ -305,7 +306,7 @@ bool valid_opts(const gp_opts& o, std::string* why) {
   if (o.precond != GP_PRECOND_JACOBI && o.precond != GP_PRECOND_BLOCK_JACOBI)
     return *why = "unknown preconditioner", false;
   if (o.precision != GP_PREC_FP64 && o.precision != GP_PREC_FP32_REFINE64) return *why = "unknown precision", false;
-  if (o.rhs_tile < 0 || o.chunk < 0) return *why = "rhs_tile and chunk must be >= 0", false;
+  if (o.rhs_tile < 0 || o.chunk < 0 || o.wg_per_cu < 0) return *why = "rhs_tile, chunk and wg_per_cu must be >= 0", false;
   return true;
 }
 
@@ -388,7 +389,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   char* ws = (char*)c->ws;
   // descriptors, one grouped launch per distinct K
   struct Group {
-    int K, first, count, W, F;
+    int K, first, count, W, F, nblk;
   };
   std::vector<Group> groups;
   const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
@@ -410,19 +411,25 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.part = (double*)(ws + lay[j].part);
     p.prof = c->prof_on ? (long long*)(ws + lay[j].prof) : nullptr;
     p.R = it.R;
-    int rc = o.rhs_tile > 0 ? o.rhs_tile : 8;
+    int rc = o.rhs_tile > 0 ? o.rhs_tile : 4;
     rc = std::max(1, std::min(std::min(rc, RCMAX), it.R));
     p.Rc = rc;
     p.nchunks = (it.R + rc - 1) / rc;
     p.work_count = it.op->ntiles * p.nchunks;
     p.cfg = cfg;
-    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0, 0});
+    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0, 0, 0});
     Group& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
     p.fin_begin = g.F;
     g.F += (it.R + fpb - 1) / fpb;
     g.count += 1;
+  }
+  // persistent workgroups: wg_per_cu per compute unit, a multiple of the XCD count
+  const int wpc = o.wg_per_cu > 0 ? o.wg_per_cu : 8;
+  for (Group& g : groups) {
+    const int cap = std::max(8, c->cus * wpc / 8 * 8);
+    g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
   }
   hipStream_t s = c->stream;
   HIPTRY(hipMemcpyAsync(c->d_probs, c->h_probs, np * sizeof(Prob), hipMemcpyHostToDevice, s));
@@ -436,10 +443,10 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       const Prob* dp = c->d_probs + g.first;
       if (with_add)
         PROFILED(c, GP_KERNEL_ADDSOL,
-                 f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W) : launch_addsol_f64(s, g.K, dp, g.count, g.W));
+                 f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W, g.nblk) : launch_addsol_f64(s, g.K, dp, g.count, g.W, g.nblk));
       PROFILED(c, GP_KERNEL_REFINE,
-               f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W)
-                   : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W));
+               f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W, g.nblk)
+                   : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W, g.nblk));
       HIPTRY(launch_finalize(s, 0, dp, g.count, g.F, epoch));
     }
     return GP_OK;
@@ -451,12 +458,12 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       for (const Group& g : groups) {
         const Prob* dp = c->d_probs + g.first;
         PROFILED(c, GP_KERNEL_MATVEC,
-                 f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, parity)
-                     : launch_matvec_f64(s, g.K, dp, g.count, g.W, parity));
+                 f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, g.nblk, parity)
+                     : launch_matvec_f64(s, g.K, dp, g.count, g.W, g.nblk, parity));
         HIPTRY(launch_finalize(s, 1, dp, g.count, g.F, epoch));
         PROFILED(c, GP_KERNEL_UPDATE,
-                 f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, parity)
-                     : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, parity));
+                 f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, g.nblk, parity)
+                     : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, g.nblk, parity));
         HIPTRY(launch_finalize(s, 2, dp, g.count, g.F, epoch));
       }
       parity ^= 1;
@@ -572,6 +579,7 @@ void gp_opts_default(gp_opts* o) {
   o->precision = GP_PREC_FP32_REFINE64;
   o->rhs_tile = 0;
   o->chunk = 0;
+  o->wg_per_cu = 0;
   o->seed = 0;
 }
 
@@ -597,6 +605,9 @@ int gp_ctx_create(int device, void* hip_stream, size_t hbm_budget, gp_ctx** out)
     delete c;
     return st;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->cus = cus;
   *out = c;
   return GP_OK;
 }

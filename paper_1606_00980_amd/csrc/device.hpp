@@ -45,9 +45,10 @@ __device__ inline void sum_partials(const double* part, int R, int nt, int r, do
   const int lane = threadIdx.x % WAVE;
 #pragma unroll
   for (int v = 0; v < NV; ++v) s[v] = 0.0;
+  const __attribute__((address_space(1))) double* g = (const __attribute__((address_space(1))) double*)part;
   for (int t = lane; t < nt; t += WAVE) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) s[v] += part[((size_t)v * R + r) * nt + t];
+    for (int v = 0; v < NV; ++v) s[v] += g[((size_t)v * R + r) * nt + t];
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) s[v] = wave_sum(s[v]);

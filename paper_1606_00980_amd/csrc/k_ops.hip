@@ -367,36 +367,37 @@ __global__ __launch_bounds__(TILE) void k_trace_partials(OpDev op, const int8_t*
   }
 }
 
-// One workgroup: out[0] = (1/m) sum_{i,k} vu, out[1+k] = (1/m) sum_i vu_k,
-// out[1+K+k] = (1/m) sum_i (Gv)u_k; each sum in a fixed order.  pairbuf holds
-// the 2*m*K per-(probe, regressor) sums.
-__global__ __launch_bounds__(TILE) void k_trace_final(const double* __restrict__ part, int m, int K,
-                                                      int nt, double* __restrict__ pairbuf,
+// Sums over tiles, one wavefront per (which, probe, regressor) pair:
+// pairbuf[q] = sum_t part[q][t] in a fixed order.
+__global__ __launch_bounds__(TILE) void k_trace_pairs(const double* __restrict__ part, int pairs, int nt,
+                                                      double* __restrict__ pairbuf) {
+  const int q = blockIdx.x * (TILE / WAVE) + (int)(threadIdx.x / WAVE);
+  if (q >= pairs) return;
+  const int lane = threadIdx.x % WAVE;
+  double s = 0.0;
+  for (int t = lane; t < nt; t += WAVE) s += part[(size_t)q * nt + t];
+  s = wave_sum(s);
+  if (lane == 0) pairbuf[q] = s;
+}
+
+// out[0] = (1/m) sum_{i,k} vu, out[1+k] = (1/m) sum_i vu_k,
+// out[1+K+k] = (1/m) sum_i (Gv)u_k, each sum over probes in a fixed order.
+__global__ __launch_bounds__(WAVE) void k_trace_final(const double* __restrict__ pairbuf, int m, int K,
                                                       double* __restrict__ out) {
-  const int wv = threadIdx.x / WAVE, nw = TILE / WAVE, lane = threadIdx.x % WAVE;
-  const int pairs = 2 * m * K;
-  for (int q = wv; q < pairs; q += nw) {
-    double s = 0.0;
-    for (int t = lane; t < nt; t += WAVE) s += part[(size_t)q * nt + t];
-    s = wave_sum(s);
-    if (lane == 0) pairbuf[q] = s;
-  }
-  __threadfence_block();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int k = 0; k < K; ++k) {
-      double a = 0.0, g = 0.0;
-      for (int i = 0; i < m; ++i) {
-        a += pairbuf[(0 * (size_t)m + i) * K + k];
-        g += pairbuf[(1 * (size_t)m + i) * K + k];
-      }
-      out[1 + k] = a / m;
-      out[1 + K + k] = g / m;
-      tot += a;
+  const int k = threadIdx.x;
+  double a = 0.0, g = 0.0;
+  if (k < K) {
+    for (int i = 0; i < m; ++i) {
+      a += pairbuf[(0 * (size_t)m + i) * K + k];
+      g += pairbuf[(1 * (size_t)m + i) * K + k];
     }
-    out[0] = tot / m;
+    out[1 + k] = a / m;
+    out[1 + K + k] = g / m;
   }
+  // total over regressors in order k = 0..K-1
+  double tot = 0.0;
+  for (int j = 0; j < K; ++j) tot += __shfl(a, j, WAVE);
+  if (k == 0) out[0] = tot / m;
 }
 
 // --------------------------------------------------------------- launchers
@@ -476,7 +477,10 @@ hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, 
 #undef X
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_trace_final, dim3(1), dim3(TILE), 0, s, part, m, op.K, op.ntiles, pairbuf, out);
+  const int pairs = 2 * m * op.K;
+  hipLaunchKernelGGL(k_trace_pairs, dim3((pairs + TILE / WAVE - 1) / (TILE / WAVE)), dim3(TILE), 0, s, part, pairs,
+                     op.ntiles, pairbuf);
+  hipLaunchKernelGGL(k_trace_final, dim3(1), dim3(WAVE), 0, s, pairbuf, m, op.K, out);
   return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@ namespace gp {
 
 #define GP_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W) {
-  const dim3 g(W), b(TILE);
+hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk) {
+  const dim3 g(nblk), b(TILE);
   switch (K) {
 #define X(KK)                                                                                   \
   case KK:                                                                                      \
@@ -23,8 +23,8 @@ hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, in
   return hipGetLastError();
 }
 
-hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int parity) {
-  const dim3 g(W), b(TILE);
+hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity) {
+  const dim3 g(nblk), b(TILE);
   switch (K) {
 #define X(KK) case KK: hipLaunchKernelGGL((k_matvec<double, KK>), g, b, 0, s, probs, nprob, W, parity); break;
     GP_K_CASES(X)
@@ -34,8 +34,8 @@ hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob,
   return hipGetLastError();
 }
 
-hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int parity) {
-  const dim3 g(W), b(TILE);
+hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity) {
+  const dim3 g(nblk), b(TILE);
   switch (K) {
 #define X(KK)                                                                                   \
   case KK:                                                                                      \
@@ -51,8 +51,8 @@ hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, in
   return hipGetLastError();
 }
 
-hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W) {
-  const dim3 g(W), b(TILE);
+hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk) {
+  const dim3 g(nblk), b(TILE);
   switch (K) {
 #define X(KK) case KK: hipLaunchKernelGGL((k_addsol<double, KK>), g, b, 0, s, probs, nprob, W); break;
     GP_K_CASES(X)

@@ -29,14 +29,15 @@ hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob
 int finalize_rhs_per_block();
 
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that
-// all have K regressors; W = total work items (tiles x right-hand-side chunks).
-hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W);
-hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int parity);
-hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int parity);
-hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W);
-hipError_t launch_refine_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W);
-hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int parity);
-hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int parity);
-hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W);
+// all have K regressors; W = total work items (tiles x right-hand-side chunks),
+// swept by nblk persistent workgroups (a multiple of 8, one XCD range each).
+hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_refine_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk);
 
 }  // namespace gp

@@ -36,12 +36,17 @@ template <> struct OpT<float> {
 };
 
 template <int K> struct Tri { static constexpr int NB = K * (K + 1) / 2; };
+
+// Minimum resident waves per SIMD requested from the compiler (caps VGPRs):
+// 4 (<= 128 VGPRs) while the per-voxel blocks fit, else 2.
+template <int K> struct Occ { static constexpr int inner = K <= 10 ? 4 : 2; static constexpr int outer = 2; };
 template <int PC, int K> struct PSize { static constexpr int n = PC == PC_BLOCK ? Tri<K>::NB : K; };
 
 template <typename T, int NV>
 __device__ inline void load_soa(const T* __restrict__ A, int N, int n, T (&a)[NV]) {
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)A;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) a[i] = A[(size_t)i * N + n];
+  for (int i = 0; i < NV; ++i) a[i] = g[(size_t)i * N + (unsigned)n];
 }
 
 template <typename T, int PC, int K>
@@ -87,6 +92,7 @@ __device__ inline void flush_partials(const Prob& pr, const double* s_red, int r
       pr.part[((size_t)v * pr.R + r) * pr.op.ntiles + tile] = t;
     }
   }
+  __syncthreads();   // s_red is reused by the next work item
 }
 
 struct Where {
@@ -94,14 +100,32 @@ struct Where {
   bool valid;
 };
 
-__device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int W) {
+// Persistent sweep over the W work items of a grouped launch.  Workgroups are
+// dealt to the XCDs round-robin (workgroup b runs on XCD b % NXCD), so the
+// items are split into NXCD contiguous ranges and the workgroups of one XCD
+// walk their range in order with a stride of their count.  The items being
+// processed at any moment on an XCD are then neighbours in the work order,
+// which keeps the stencil's z-neighbour slices in that XCD's L2.
+struct Sweep {
+  int item, end, step;
+};
+
+__device__ inline Sweep sweep_begin(int W) {
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int base = W / NXCD, rem = W % NXCD;
+  const int start = xcd * base + (xcd < rem ? xcd : rem);
+  const int cnt = base + (xcd < rem ? 1 : 0);
+  return Sweep{start + slot, start + cnt, (int)(gridDim.x / NXCD)};
+}
+
+// Work items of a problem are ordered right-hand-side chunk major, tile minor.
+__device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int item) {
   Where w;
-  const int item = xcd_remap(blockIdx.x, W);
   w.p = find_prob(probs, nprob, item);
   const int local = item - probs[w.p].work_begin;
-  const int nch = probs[w.p].nchunks;
-  w.tile = local / nch;
-  w.chunk = local - w.tile * nch;
+  const int nt = probs[w.p].op.ntiles;
+  w.chunk = local / nt;
+  w.tile = local - w.chunk * nt;
   const int N = probs[w.p].op.N;
   w.n = w.tile * TILE + (int)threadIdx.x;
   w.valid = w.n < N;
@@ -246,216 +270,252 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __res
 }
 
 // ------------------------------------------------------------------ kernels
+// Addressing: every vector access is a wave-uniform base pointer (the slab of
+// one right-hand side and regressor) plus a 32-bit per-lane byte offset, so
+// loads take the scalar-base form and no 64-bit address is kept per lane.
+// Pointers held in the problem descriptors are generic; the casts to the
+// global address space let the compiler emit global (not flat) accesses.
+#define GP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, unsigned off) {
+  return *(const GP_GLOBAL T*)((const GP_GLOBAL char*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, unsigned off, T v) {
+  *(GP_GLOBAL T*)((GP_GLOBAL char*)base + off) = v;
+}
+
+// Byte offsets of the voxel and its six neighbours for element size S.
+template <int S>
+__device__ __forceinline__ void voxel_offsets(const OpDev& op, int nn, unsigned& own, unsigned (&nb)[6]) {
+  own = (unsigned)nn * S;
+  const __attribute__((address_space(1))) int* g = (const __attribute__((address_space(1))) int*)op.nbr;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nb[d] = (unsigned)g[(size_t)d * op.N + (unsigned)nn] * S;
+}
+
 template <typename T, int PC, int K>
-__global__ __launch_bounds__(TILE) void k_refine(const Prob* __restrict__ probs, int nprob, int W) {
+__global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __restrict__ probs, int nprob, int W) {
   constexpr int NB = Tri<K>::NB, NP = PSize<PC, K>::n;
   __shared__ double s_red[RCMAX * 3 * (TILE / WAVE)];
-  const Where w = locate(probs, nprob, W);
-  const Prob& pr = probs[w.p];
-  const OpDev& op = pr.op;
-  const int N = op.N, nn = w.nn;
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
-  if (!any_in_phase(pr, r0, r1, PH_OUTER)) return;
-  int nb[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
-  double B[NB];
-  load_soa(op.B64, N, nn, B);
-  T P[NP];
-  load_soa(OpT<T>::P(op), N, nn, P);
-  for (int r = r0; r < r1; ++r) {
-    if (pr.st[r].phase != PH_OUTER) continue;
-    const double* xr = pr.x + (size_t)r * K * N;
-    const double* br = pr.b + (size_t)r * K * N;
-    double xo[K], y[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) xo[k] = xr[(size_t)k * N + nn];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double s6 = 0.0;
-#pragma unroll
-      for (int d = 0; d < 6; ++d) s6 += xo[k] - xr[(size_t)k * N + nb[d]];
-      y[k] = op.alpha64[k] * s6;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-      for (int j = 0; j < K; ++j) y[k] += B[pk(k, j)] * xo[j];
-    }
-    double acc[3] = {0.0, 0.0, 0.0};
-    T rt[K], z[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double bk = br[(size_t)k * N + nn];
-      const double rk = bk - y[k];
-      acc[0] += rk * rk;
-      acc[1] += bk * bk;
-      rt[k] = (T)rk;
-    }
-    precond_apply<T, PC, K>(P, rt, z);
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
-    if (w.valid) {
-      T* rp = (T*)pr.r + (size_t)r * K * N;
-      T* zp = (T*)pr.z + (size_t)r * K * N;
-#pragma unroll
+  for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
+    const Where w = locate(probs, nprob, sw.item);
+    const Prob& pr = probs[w.p];
+    const OpDev& op = pr.op;
+    const int N = op.N;
+    const int r0 = w.chunk * pr.Rc;
+    const int r1 = min(pr.R, r0 + pr.Rc);
+    if (!any_in_phase(pr, r0, r1, PH_OUTER)) continue;
+    unsigned o8, nb8[6];
+    voxel_offsets<8>(op, w.nn, o8, nb8);
+    const unsigned oT = (unsigned)w.nn * sizeof(T);
+  #pragma unroll 1
+    for (int r = r0; r < r1; ++r) {
+      if (pr.st[r].phase != PH_OUTER) continue;
+      // the voxel's FP64 block and preconditioner are re-read per right-hand
+      // side (cache hits) rather than held in registers across the loop
+      double B[NB];
+      load_soa(op.B64, N, w.nn, B);
+      T P[NP];
+      load_soa(OpT<T>::P(op), N, w.nn, P);
+      const double* xr = pr.x + (size_t)r * K * N;
+      const double* br = pr.b + (size_t)r * K * N;
+      double xo[K], y[K];
+  #pragma unroll
       for (int k = 0; k < K; ++k) {
-        rp[(size_t)k * N + w.n] = rt[k];
-        zp[(size_t)k * N + w.n] = z[k];
+        const double* xk = xr + (size_t)k * N;
+        const double xc = ldo(xk, o8);
+        double s6 = 0.0;
+  #pragma unroll
+        for (int d = 0; d < 6; ++d) s6 += xc - ldo(xk, nb8[d]);
+        xo[k] = xc;
+        y[k] = op.alpha64[k] * s6;
       }
-    } else {
-      acc[0] = acc[1] = acc[2] = 0.0;
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+  #pragma unroll
+        for (int j = 0; j < K; ++j) y[k] += B[pk(k, j)] * xo[j];
+      }
+      double acc[3] = {0.0, 0.0, 0.0};
+      T rt[K], z[K];
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double bk = ldo(br + (size_t)k * N, o8);
+        const double rk = bk - y[k];
+        acc[0] += rk * rk;
+        acc[1] += bk * bk;
+        rt[k] = (T)rk;
+      }
+      precond_apply<T, PC, K>(P, rt, z);
+  #pragma unroll
+      for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
+      if (w.valid) {
+        T* rp = (T*)pr.r + (size_t)r * K * N;
+        T* zp = (T*)pr.z + (size_t)r * K * N;
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+          sto(rp + (size_t)k * N, oT, rt[k]);
+          sto(zp + (size_t)k * N, oT, z[k]);
+        }
+      } else {
+        acc[0] = acc[1] = acc[2] = 0.0;
+      }
+      wave_deposit<3>(s_red, r - r0, acc);
     }
-    wave_deposit<3>(s_red, r - r0, acc);
+    flush_partials<3>(pr, s_red, r0, r1, w.tile, PH_OUTER);
   }
-  flush_partials<3>(pr, s_red, r0, r1, w.tile, PH_OUTER);
 }
 
 template <typename T, int K>
-__global__ __launch_bounds__(TILE) void k_matvec(const Prob* __restrict__ probs, int nprob, int W,
-                                                 int parity) {
+__global__ __launch_bounds__(TILE, Occ<K>::inner) void k_matvec(const Prob* __restrict__ probs, int nprob, int W,
+                                                                int parity) {
   constexpr int NB = Tri<K>::NB;
   __shared__ double s_red[RCMAX * 1 * (TILE / WAVE)];
-  const Where w = locate(probs, nprob, W);
-  const Prob& pr = probs[w.p];
-  const OpDev& op = pr.op;
-  const int N = op.N, nn = w.nn;
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
-  if (!any_in_phase(pr, r0, r1, PH_INNER)) return;
-  int nb[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
-  T B[NB];
-  load_soa(OpT<T>::B(op), N, nn, B);
-  T al[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) al[k] = OpT<T>::alpha(op, k);
-  for (int r = r0; r < r1; ++r) {
-    const RhsState& s = pr.st[r];
-    if (s.phase != PH_INNER) continue;
-    const bool first = s.first != 0;
-    const T beta = (T)s.beta;
-    const size_t off = (size_t)r * K * N;
-    const T* zr = (const T*)pr.z + off;
-    const T* pin = (const T*)(parity ? pr.p1 : pr.p0) + off;
-    T* pout = (T*)(parity ? pr.p0 : pr.p1) + off;
-    T* qr = (T*)pr.q + off;
-    T po[K], qv[K];
-    if (first) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) po[k] = zr[(size_t)k * N + nn];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        T s6 = 0;
-#pragma unroll
-        for (int d = 0; d < 6; ++d) s6 += po[k] - zr[(size_t)k * N + nb[d]];
-        qv[k] = al[k] * s6;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) po[k] = zr[(size_t)k * N + nn] + beta * pin[(size_t)k * N + nn];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        T s6 = 0;
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-          const size_t i = (size_t)k * N + nb[d];
-          s6 += po[k] - (zr[i] + beta * pin[i]);
+  for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
+    const Where w = locate(probs, nprob, sw.item);
+    const Prob& pr = probs[w.p];
+    const OpDev& op = pr.op;
+    const int N = op.N;
+    const int r0 = w.chunk * pr.Rc;
+    const int r1 = min(pr.R, r0 + pr.Rc);
+    if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
+    unsigned o, nb[6];
+    voxel_offsets<sizeof(T)>(op, w.nn, o, nb);
+    T B[NB];
+    load_soa(OpT<T>::B(op), N, w.nn, B);
+  #pragma unroll 1
+    for (int r = r0; r < r1; ++r) {
+      const RhsState& s = pr.st[r];
+      if (s.phase != PH_INNER) continue;
+      const bool first = s.first != 0;
+      const T beta = (T)s.beta;
+      const size_t off = (size_t)r * K * N;
+      const T* zr = (const T*)pr.z + off;
+      const T* pin = (const T*)(parity ? pr.p1 : pr.p0) + off;
+      T* pout = (T*)(parity ? pr.p0 : pr.p1) + off;
+      T* qr = (T*)pr.q + off;
+      T po[K], qv[K];
+      if (first) {
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const T* zk = zr + (size_t)k * N;
+          const T pc = ldo(zk, o);
+          T s6 = 0;
+  #pragma unroll
+          for (int d = 0; d < 6; ++d) s6 += pc - ldo(zk, nb[d]);
+          po[k] = pc;
+          qv[k] = OpT<T>::alpha(op, k) * s6;
         }
-        qv[k] = al[k] * s6;
+      } else {
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const T* zk = zr + (size_t)k * N;
+          const T* pk_ = pin + (size_t)k * N;
+          const T pc = ldo(zk, o) + beta * ldo(pk_, o);
+          T s6 = 0;
+  #pragma unroll
+          for (int d = 0; d < 6; ++d) s6 += pc - (ldo(zk, nb[d]) + beta * ldo(pk_, nb[d]));
+          po[k] = pc;
+          qv[k] = OpT<T>::alpha(op, k) * s6;
+        }
       }
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-      for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * po[j];
-    }
-    double acc[1] = {0.0};
-    if (w.valid) {
-#pragma unroll
+  #pragma unroll
       for (int k = 0; k < K; ++k) {
-        pout[(size_t)k * N + w.n] = po[k];
-        qr[(size_t)k * N + w.n] = qv[k];
-        acc[0] += (double)po[k] * (double)qv[k];
+  #pragma unroll
+        for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * po[j];
       }
+      double acc[1] = {0.0};
+      if (w.valid) {
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+          sto(pout + (size_t)k * N, o, po[k]);
+          sto(qr + (size_t)k * N, o, qv[k]);
+          acc[0] += (double)po[k] * (double)qv[k];
+        }
+      }
+      wave_deposit<1>(s_red, r - r0, acc);
     }
-    wave_deposit<1>(s_red, r - r0, acc);
+    flush_partials<1>(pr, s_red, r0, r1, w.tile, PH_INNER);
   }
-  flush_partials<1>(pr, s_red, r0, r1, w.tile, PH_INNER);
 }
 
 template <typename T, int PC, int K>
-__global__ __launch_bounds__(TILE) void k_update(const Prob* __restrict__ probs, int nprob, int W,
-                                                 int parity) {
+__global__ __launch_bounds__(TILE, Occ<K>::inner) void k_update(const Prob* __restrict__ probs, int nprob, int W,
+                                                                int parity) {
   constexpr int NP = PSize<PC, K>::n;
   __shared__ double s_red[RCMAX * 2 * (TILE / WAVE)];
-  const Where w = locate(probs, nprob, W);
-  const Prob& pr = probs[w.p];
-  const OpDev& op = pr.op;
-  const int N = op.N, nn = w.nn;
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
-  if (!any_in_phase(pr, r0, r1, PH_INNER)) return;
-  T P[NP];
-  load_soa(OpT<T>::P(op), N, nn, P);
-  for (int r = r0; r < r1; ++r) {
-    const RhsState& s = pr.st[r];
-    if (s.phase != PH_INNER) continue;
-    const T a = (T)s.a;
-    const bool fresh = s.inner_it == 0;
-    const size_t off = (size_t)r * K * N;
-    const T* pc = (const T*)(parity ? pr.p0 : pr.p1) + off;
-    const T* qr = (const T*)pr.q + off;
-    T* dr = (T*)pr.d + off;
-    T* rr = (T*)pr.r + off;
-    T* zr = (T*)pr.z + off;
-    T rv[K], dv[K], z[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const size_t i = (size_t)k * N + nn;
-      const T pk_ = pc[i];
-      dv[k] = fresh ? a * pk_ : dr[i] + a * pk_;
-      rv[k] = rr[i] - a * qr[i];
-    }
-    precond_apply<T, PC, K>(P, rv, z);
-    double acc[2] = {0.0, 0.0};
-    if (w.valid) {
-#pragma unroll
+  for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
+    const Where w = locate(probs, nprob, sw.item);
+    const Prob& pr = probs[w.p];
+    const OpDev& op = pr.op;
+    const int N = op.N;
+    const int r0 = w.chunk * pr.Rc;
+    const int r1 = min(pr.R, r0 + pr.Rc);
+    if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
+    T P[NP];
+    load_soa(OpT<T>::P(op), N, w.nn, P);
+    const unsigned o = (unsigned)w.nn * sizeof(T);
+  #pragma unroll 1
+    for (int r = r0; r < r1; ++r) {
+      const RhsState& s = pr.st[r];
+      if (s.phase != PH_INNER) continue;
+      const T a = (T)s.a;
+      const bool fresh = s.inner_it == 0;
+      const size_t off = (size_t)r * K * N;
+      const T* pc = (const T*)(parity ? pr.p0 : pr.p1) + off;
+      const T* qr = (const T*)pr.q + off;
+      T* dr = (T*)pr.d + off;
+      T* rr = (T*)pr.r + off;
+      T* zr = (T*)pr.z + off;
+      T rv[K], dv[K], z[K];
+  #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const size_t i = (size_t)k * N + w.n;
-        dr[i] = dv[k];
-        rr[i] = rv[k];
-        zr[i] = z[k];
-        acc[0] += (double)rv[k] * (double)z[k];
-        acc[1] += (double)rv[k] * (double)rv[k];
+        const size_t kb = (size_t)k * N;
+        const T pk_ = ldo(pc + kb, o);
+        dv[k] = fresh ? a * pk_ : ldo(dr + kb, o) + a * pk_;
+        rv[k] = ldo(rr + kb, o) - a * ldo(qr + kb, o);
       }
+      precond_apply<T, PC, K>(P, rv, z);
+      double acc[2] = {0.0, 0.0};
+      if (w.valid) {
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const size_t kb = (size_t)k * N;
+          sto(dr + kb, o, dv[k]);
+          sto(rr + kb, o, rv[k]);
+          sto(zr + kb, o, z[k]);
+          acc[0] += (double)rv[k] * (double)z[k];
+          acc[1] += (double)rv[k] * (double)rv[k];
+        }
+      }
+      wave_deposit<2>(s_red, r - r0, acc);
     }
-    wave_deposit<2>(s_red, r - r0, acc);
+    flush_partials<2>(pr, s_red, r0, r1, w.tile, PH_INNER);
   }
-  flush_partials<2>(pr, s_red, r0, r1, w.tile, PH_INNER);
 }
 
 // x += d for right-hand sides whose inner solve has ended.
 template <typename T, int K>
 __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs, int nprob, int W) {
-  const Where w = locate(probs, nprob, W);
-  const Prob& pr = probs[w.p];
-  if (!w.valid) return;
-  const int N = pr.op.N;
-  const int r0 = w.chunk * pr.Rc;
-  const int r1 = min(pr.R, r0 + pr.Rc);
-  for (int r = r0; r < r1; ++r) {
-    const RhsState& s = pr.st[r];
-    if (s.phase != PH_OUTER || !s.has_d) continue;
-    const size_t off = (size_t)r * K * N;
-    const T* dr = (const T*)pr.d + off;
-    double* xr = pr.x + off;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const size_t i = (size_t)k * N + w.n;
-      xr[i] += (double)dr[i];
+  for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
+    const Where w = locate(probs, nprob, sw.item);
+    const Prob& pr = probs[w.p];
+    if (!w.valid) continue;
+    const int N = pr.op.N;
+    const int r0 = w.chunk * pr.Rc;
+    const int r1 = min(pr.R, r0 + pr.Rc);
+    const unsigned oT = (unsigned)w.n * sizeof(T), o8 = (unsigned)w.n * 8u;
+    for (int r = r0; r < r1; ++r) {
+      const RhsState& s = pr.st[r];
+      if (s.phase != PH_OUTER || !s.has_d) continue;
+      const size_t off = (size_t)r * K * N;
+      const T* dr = (const T*)pr.d + off;
+      double* xr = pr.x + off;
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const size_t kb = (size_t)k * N;
+        sto(xr + kb, o8, ldo(xr + kb, o8) + (double)ldo(dr + kb, oT));
+      }
     }
   }
 }

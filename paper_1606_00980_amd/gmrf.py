@@ -49,7 +49,7 @@ class GpOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rhs_tile", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("wg_per_cu", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
 class GpStats(ctypes.Structure):
