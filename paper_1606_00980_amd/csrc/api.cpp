@@ -9,6 +9,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -59,6 +60,10 @@ struct gp_ctx {
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> pending;   // (kind, first event of the pair)
   gp_prof acc[GP_KERNEL_KINDS] = {};
+  // captured launch sequences, keyed by the grouped-launch layout
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  bool use_graphs = true;
 };
 
 struct gp_op {
@@ -436,39 +441,87 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   HIPTRY(hipMemsetAsync(ws + st_all, 0, totalR * sizeof(RhsState), s));
   for (int j = 0; j < np; ++j) HIPTRY(hipMemsetAsync(ws + lay[j].prof, 0, NPROF * sizeof(long long), s));
 
-  int epoch = 0;
-  auto launch_outer = [&](bool with_add) -> int {
-    ++epoch;
+  // One round = [x += d, refine, finalise] then a chunk of inner iterations
+  // [matvec, finalise, update, finalise] x chunk.  Without profiling both are
+  // captured once per launch layout and replayed as graphs.
+  int chunk = o.chunk > 0 ? o.chunk : 6;
+  const bool graphs = c->use_graphs && !c->prof_on;
+  if (graphs && (chunk & 1)) ++chunk;   // even chunks return the direction buffers to parity 0
+  auto enqueue_outer = [&](hipStream_t q) -> int {
     for (const Group& g : groups) {
       const Prob* dp = c->d_probs + g.first;
-      if (with_add)
-        PROFILED(c, GP_KERNEL_ADDSOL,
-                 f32 ? launch_addsol_f32(s, g.K, dp, g.count, g.W, g.nblk) : launch_addsol_f64(s, g.K, dp, g.count, g.W, g.nblk));
+      PROFILED(c, GP_KERNEL_ADDSOL,
+               f32 ? launch_addsol_f32(q, g.K, dp, g.count, g.W, g.nblk)
+                   : launch_addsol_f64(q, g.K, dp, g.count, g.W, g.nblk));
       PROFILED(c, GP_KERNEL_REFINE,
-               f32 ? launch_refine_f32(s, o.precond, g.K, dp, g.count, g.W, g.nblk)
-                   : launch_refine_f64(s, o.precond, g.K, dp, g.count, g.W, g.nblk));
-      HIPTRY(launch_finalize(s, 0, dp, g.count, g.F, epoch));
+               f32 ? launch_refine_f32(q, o.precond, g.K, dp, g.count, g.W, g.nblk)
+                   : launch_refine_f64(q, o.precond, g.K, dp, g.count, g.W, g.nblk));
+      HIPTRY(launch_finalize(q, 0, dp, g.count, g.F));
     }
     return GP_OK;
   };
   int parity = 0;
-  auto launch_inner = [&](int iters) -> int {
+  auto enqueue_inner = [&](hipStream_t q, int iters) -> int {
     for (int i = 0; i < iters; ++i) {
-      ++epoch;
       for (const Group& g : groups) {
         const Prob* dp = c->d_probs + g.first;
         PROFILED(c, GP_KERNEL_MATVEC,
-                 f32 ? launch_matvec_f32(s, g.K, dp, g.count, g.W, g.nblk, parity)
-                     : launch_matvec_f64(s, g.K, dp, g.count, g.W, g.nblk, parity));
-        HIPTRY(launch_finalize(s, 1, dp, g.count, g.F, epoch));
+                 f32 ? launch_matvec_f32(q, g.K, dp, g.count, g.W, g.nblk, parity)
+                     : launch_matvec_f64(q, g.K, dp, g.count, g.W, g.nblk, parity));
+        HIPTRY(launch_finalize(q, 1, dp, g.count, g.F));
         PROFILED(c, GP_KERNEL_UPDATE,
-                 f32 ? launch_update_f32(s, o.precond, g.K, dp, g.count, g.W, g.nblk, parity)
-                     : launch_update_f64(s, o.precond, g.K, dp, g.count, g.W, g.nblk, parity));
-        HIPTRY(launch_finalize(s, 2, dp, g.count, g.F, epoch));
+                 f32 ? launch_update_f32(q, o.precond, g.K, dp, g.count, g.W, g.nblk, parity)
+                     : launch_update_f64(q, o.precond, g.K, dp, g.count, g.W, g.nblk, parity));
+        HIPTRY(launch_finalize(q, 2, dp, g.count, g.F));
       }
       parity ^= 1;
     }
     return GP_OK;
+  };
+  std::string layout_key;
+  if (graphs) {
+    layout_key = std::to_string((uintptr_t)c->d_probs) + (f32 ? "f" : "d") + std::to_string(o.precond);
+    for (const Group& g : groups)
+      layout_key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.W) + "," +
+                    std::to_string(g.F) + "," + std::to_string(g.nblk);
+  }
+  auto replay = [&](const std::string& key, const std::function<int(hipStream_t)>& enqueue) -> int {
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      if (c->graphs.size() >= 64) {
+        HIPTRY(hipStreamSynchronize(s));
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+      }
+      HIPTRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int est = enqueue(c->cap_stream);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (est != GP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return est;
+      }
+      HIPTRY(e);
+      hipGraphExec_t exec = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPTRY(ei);
+      it = c->graphs.emplace(key, exec).first;
+    }
+    HIPTRY(hipGraphLaunch(it->second, s));
+    return GP_OK;
+  };
+  auto launch_outer = [&]() -> int {
+    if (!graphs) return enqueue_outer(s);
+    return replay(layout_key + "|outer", [&](hipStream_t q) { return enqueue_outer(q); });
+  };
+  auto launch_inner = [&](int iters) -> int {
+    if (!graphs) return enqueue_inner(s, iters);
+    parity = 0;
+    const int st2 = replay(layout_key + "|inner" + std::to_string(iters),
+                           [&](hipStream_t q) { return enqueue_inner(q, iters); });
+    parity = 0;
+    return st2;
   };
   // host copy of every right-hand side's state
   std::vector<RhsState> hs(totalR);
@@ -484,8 +537,6 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     }
     return GP_OK;
   };
-  const int chunk = o.chunk > 0 ? o.chunk : 6;
-  bool first = true;
   // Hard cap on host rounds: every round either advances an inner iteration or
   // performs a refinement step, both bounded by max_iter and max_outer.
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
@@ -493,9 +544,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   for (;;) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
     if (n_outer > 0) {
-      st = launch_outer(!first);
+      st = launch_outer();
       if (st) return st;
-      first = false;
       if (n_inner == 0) {
         st = read_states();
         if (st) return st;
@@ -608,6 +658,11 @@ int gp_ctx_create(int device, void* hip_stream, size_t hbm_budget, gp_ctx** out)
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(GP_ERR_DEVICE, "could not create the capture stream");
+  }
   *out = c;
   return GP_OK;
 }
@@ -659,6 +714,8 @@ int gp_ctx_destroy(gp_ctx* c) {
   if (c->d_probs) dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
   if (c->h_probs) (void)hipHostFree(c->h_probs);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return GP_OK;
 }

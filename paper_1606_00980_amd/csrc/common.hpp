@@ -10,12 +10,11 @@ namespace gp {
 constexpr int KMAX = 16;     // largest supported number of regressors
 constexpr int TILE = 256;    // voxels per workgroup in the voxel-parallel kernels
 constexpr int NPART = 3;     // reduction values per (right-hand side, tile)
-constexpr int NPROF = 12;    // profiling counters per problem
+constexpr int NPROF = 10;    // profiling counters per problem
 // profiling counter slots (right-hand sides processed, launches with work)
 enum ProfSlot : int {
   PF_REFINE_RHS = 0, PF_REFINE_ACT, PF_ADDSOL_RHS, PF_MATVEC_RHS, PF_MATVEC_FIRST,
   PF_MATVEC_ACT, PF_UPDATE_RHS, PF_UPDATE_FRESH, PF_UPDATE_ACT,
-  PF_REFINE_EPOCH, PF_MATVEC_EPOCH, PF_UPDATE_EPOCH,
 };
 constexpr int RCMAX = 16;    // right-hand sides per workgroup, upper bound
 constexpr int PC_JACOBI = 0; // preconditioner kinds as seen by the kernels

@@ -455,12 +455,12 @@ hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* 
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks, int epoch) {
+hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks) {
   const dim3 g(nblocks), b(FIN_WAVES * WAVE);
   switch (kind) {
-    case 0: hipLaunchKernelGGL(k_finalize<0>, g, b, 0, s, probs, nprob, epoch); break;
-    case 1: hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, probs, nprob, epoch); break;
-    case 2: hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, probs, nprob, epoch); break;
+    case 0: hipLaunchKernelGGL(k_finalize<0>, g, b, 0, s, probs, nprob); break;
+    case 1: hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, probs, nprob); break;
+    case 2: hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, probs, nprob); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

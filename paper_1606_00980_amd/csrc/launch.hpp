@@ -25,7 +25,7 @@ hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, 
 
 // Finalising launch after a refine (kind 0), matvec (1) or update (2) launch:
 // nblocks = sum over problems of ceil(R / finalize_rhs_per_block()).
-hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks, int epoch);
+hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks);
 int finalize_rhs_per_block();
 
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that

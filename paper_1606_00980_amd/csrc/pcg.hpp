@@ -150,11 +150,12 @@ __device__ inline void prof_add(const Prob& pr, int slot, long long v) {
   if (pr.prof && v) atomicAdd((unsigned long long*)&pr.prof[slot], (unsigned long long)v);
 }
 
-// Counts launch `epoch` once in slot `act` (launches that had work to do).
-__device__ inline void prof_launch(const Prob& pr, int act, int ep_slot, int epoch) {
-  if (!pr.prof) return;
-  const unsigned long long old = atomicMax((unsigned long long*)&pr.prof[ep_slot], (unsigned long long)epoch);
-  if (old < (unsigned long long)epoch) atomicAdd((unsigned long long*)&pr.prof[act], 1ull);
+// Counts a launch in slot `act` when any right-hand side of the problem is in
+// `phase`; called by the workgroup holding the problem's first work item
+// while no finaliser can be changing the states.
+__device__ inline void prof_launch(const Prob& pr, int act, int phase) {
+  if (pr.prof && threadIdx.x == 0 && any_in_phase(pr, 0, pr.R, phase))
+    atomicAdd((unsigned long long*)&pr.prof[act], 1ull);
 }
 
 __device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[3]) {
@@ -234,8 +235,7 @@ constexpr int FIN_WAVES = 4;   // right-hand sides finalised per workgroup
 // One wavefront per right-hand side of one problem: sum that right-hand side's
 // partials over the tiles in a fixed order and advance its state.
 template <int KIND>
-__global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __restrict__ probs, int nprob,
-                                                                int epoch) {
+__global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __restrict__ probs, int nprob) {
   const int b = blockIdx.x;
   int p = 0;
   while (p + 1 < nprob && b >= probs[p + 1].fin_begin) ++p;
@@ -248,24 +248,15 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __res
   if constexpr (KIND == 0) {
     double v[3];
     sum_partials<3>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane == 0) {
-      prof_launch(pr, PF_REFINE_ACT, PF_REFINE_EPOCH, epoch);
-      finalize_refine(pr, r, v);
-    }
+    if (lane == 0) finalize_refine(pr, r, v);
   } else if constexpr (KIND == 1) {
     double v[1];
     sum_partials<1>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane == 0) {
-      prof_launch(pr, PF_MATVEC_ACT, PF_MATVEC_EPOCH, epoch);
-      finalize_matvec(pr, r, v);
-    }
+    if (lane == 0) finalize_matvec(pr, r, v);
   } else {
     double v[2];
     sum_partials<2>(pr.part, pr.R, pr.op.ntiles, r, v);
-    if (lane == 0) {
-      prof_launch(pr, PF_UPDATE_ACT, PF_UPDATE_EPOCH, epoch);
-      finalize_update(pr, r, v);
-    }
+    if (lane == 0) finalize_update(pr, r, v);
   }
 }
 
@@ -303,6 +294,7 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
     const Prob& pr = probs[w.p];
     const OpDev& op = pr.op;
     const int N = op.N;
+    if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_REFINE_ACT, PH_OUTER);
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!any_in_phase(pr, r0, r1, PH_OUTER)) continue;
@@ -376,6 +368,7 @@ __global__ __launch_bounds__(TILE, Occ<K>::inner) void k_matvec(const Prob* __re
     const Prob& pr = probs[w.p];
     const OpDev& op = pr.op;
     const int N = op.N;
+    if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_MATVEC_ACT, PH_INNER);
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
@@ -449,6 +442,7 @@ __global__ __launch_bounds__(TILE, Occ<K>::inner) void k_update(const Prob* __re
     const Prob& pr = probs[w.p];
     const OpDev& op = pr.op;
     const int N = op.N;
+    if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_UPDATE_ACT, PH_INNER);
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;

@@ -397,3 +397,30 @@ def test_deterministic_and_batch_invariant(g, ctx, torch_cuda):
     alone = torch_cuda.zeros_like(bd[2:3])
     g.gp_solve(op.h, 1, bd[2:3].contiguous(), alone, opts(g))
     assert torch_cuda.equal(alone[0], xa[2])
+
+
+def test_graph_replays_match_eager(g, ctx, torch_cuda):
+    """Solver rounds replayed from captured graphs (profiling off) give bitwise
+    the eager result (profiling on launches kernel by kernel), over several
+    alternating calls with other device work in between."""
+    torch = torch_cuda
+    w = synth.tiny((15, 12, 9), 6, 3, seed=19)
+    op = Op(g, ctx, torch, w)
+    b = w.rhs(5)
+    bd = dev(torch, b)
+    o = opts(g, tol=1e-8, rhs_tile=2)
+    g.gp_ctx_profile(ctx, True)
+    xe = torch.zeros_like(bd)
+    g.gp_solve(op.h, 5, bd, xe, o)
+    g.gp_ctx_profile(ctx, False)
+    for rep in range(4):
+        xg = torch.zeros_like(bd)
+        g.gp_solve(op.h, 5, bd, xg, o)
+        assert torch.equal(xg, xe), rep
+        _ = (bd * 2.0).sum().item()          # unrelated eager work and a sync
+        g.gp_ctx_profile(ctx, True)
+        xe2 = torch.zeros_like(bd)
+        g.gp_solve(op.h, 5, bd, xe2, o)
+        g.gp_ctx_profile(ctx, False)
+        assert torch.equal(xe2, xe), rep
+    check_solutions(xe.cpu().numpy(), orc.solve(op.Q, b), w.K, w.N)
