@@ -83,7 +83,8 @@ typedef struct gp_opts {
   int      rhs_tile;   /* right-hand sides per workgroup, 0 = automatic          */
   int      chunk;      /* PCG iterations enqueued between host checks, 0 = auto  */
   int      wg_per_cu;  /* persistent workgroups per compute unit, 0 = auto       */
-  uint64_t seed;       /* reserved for on-device random vectors                  */
+  uint64_t seed;       /* Philox key used when gp_sample / gp_trace are given no
+                          random vectors (see gp_rng_normal)                     */
 } gp_opts;
 
 /* Per right-hand-side result. */
@@ -212,7 +213,9 @@ int gp_perturb_rhs(gp_op* op, int R, const double* bw, const double* z1,
                    const double* z2, double* b);
 
 /* gp_sample: Algorithm 2 -- gp_perturb_rhs then gp_solve.  w: device
- * [R][K][N], in: start values, out: samples.  Blocking.                      */
+ * [R][K][N], in: start values, out: samples.  When z1 and z2 are both NULL
+ * they are drawn on the device: z1 = gp_rng_normal(opts->seed, stream 1),
+ * z2 = gp_rng_normal(opts->seed, stream 2), in the layouts above.  Blocking. */
 int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double* z2,
               double* w, const gp_opts* opts, gp_stats* stats);
 
@@ -231,9 +234,28 @@ int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u,
                     double* tr_total, double* tr_kk, double* tr_Gkk);
 
 /* gp_trace: gp_probe_rhs, gp_solve from u = 0, gp_trace_reduce.  u: device
- * FP64 [m][K][N] workspace that receives the solutions.  Blocking.           */
+ * FP64 [m][K][N] workspace that receives the solutions.  When probes is NULL
+ * they are drawn on the device: gp_rng_rademacher(opts->seed, stream 3).
+ * Blocking.                                                                  */
 int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total,
              double* tr_kk, double* tr_Gkk, const gp_opts* opts, gp_stats* stats);
+
+/* ---- random vectors ----------------------------------------------------
+ * Counter-based Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw,
+ * SC'11), keyed by `seed` (key words = low, high 32 bits) with counter
+ * (q low, q high, stream low, stream high) for block q.  These supply the
+ * N(0, I) vectors z1, z2 of Algorithm 2 (steps 2-3) and Rademacher probes.
+ *  gp_rng_normal     : out[e], e < n, device FP64.  Pair q = e/2 takes the
+ *                      block's words w0..w3, u1 = (((w1:w0) >> 11) + 0.5) 2^-53,
+ *                      u2 likewise from (w3:w2); out[2q] = sqrt(-2 ln u1)
+ *                      cos(2 pi u2), out[2q+1] = sqrt(-2 ln u1) sin(2 pi u2).
+ *  gp_rng_rademacher : out[e], device int8; bit e % 128 of block q = e/128
+ *                      (w0 least significant) gives +1 when set, else -1.
+ *  gp_rng_raw        : the 4 words of blocks 0..nblocks-1, device uint32.
+ * Stream-ordered.                                                          */
+int gp_rng_normal(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double* out);
+int gp_rng_rademacher(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, int8_t* out);
+int gp_rng_raw(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out);
 
 #ifdef __cplusplus
 }

@@ -47,9 +47,13 @@ struct gp_ctx {
   // solver workspace arena (grown on demand, reused across calls)
   void* ws = nullptr;
   size_t ws_cap = 0;
-  // right-hand-side staging for sample/trace
+  // right-hand-side staging for sample/trace, and on-device random vectors
   double* rhs = nullptr;
   size_t rhs_cap = 0;
+  double* zbuf = nullptr;
+  size_t zcap = 0;
+  int8_t* pbuf = nullptr;
+  size_t pcap = 0;
   // grouped-launch descriptors
   Prob* d_probs = nullptr;
   Prob* h_probs = nullptr;
@@ -173,6 +177,21 @@ int ensure_rhs(gp_ctx* c, size_t count) {
   int st = dev_alloc(c, count * sizeof(double), (void**)&c->rhs);
   if (st != GP_OK) return st;
   c->rhs_cap = count;
+  return GP_OK;
+}
+
+template <typename T>
+int ensure_buf(gp_ctx* c, T*& buf, size_t& cap, size_t count) {
+  if (count <= cap) return GP_OK;
+  if (buf) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    dev_free(c, buf, cap * sizeof(T));
+    buf = nullptr;
+    cap = 0;
+  }
+  int st = dev_alloc(c, count * sizeof(T), (void**)&buf);
+  if (st != GP_OK) return st;
+  cap = count;
   return GP_OK;
 }
 
@@ -711,6 +730,8 @@ int gp_ctx_destroy(gp_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   if (c->ws) dev_free(c, c->ws, c->ws_cap);
   if (c->rhs) dev_free(c, c->rhs, c->rhs_cap * sizeof(double));
+  if (c->zbuf) dev_free(c, c->zbuf, c->zcap * sizeof(double));
+  if (c->pbuf) dev_free(c, c->pbuf, c->pcap * sizeof(int8_t));
   if (c->d_probs) dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
   if (c->h_probs) (void)hipHostFree(c->h_probs);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
@@ -957,7 +978,8 @@ int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double
   if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
   if (R < 0 || R > 65535) return fail(GP_ERR_INVALID_ARG, "R out of range");
   if (R == 0) return GP_OK;
-  if (!bw || !z1 || !z2 || !w) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  if (!bw || !w) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  if ((z1 == nullptr) != (z2 == nullptr)) return fail(GP_ERR_INVALID_ARG, "z1 and z2 must both be given or both NULL");
   if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
   gp_opts o;
   if (opts) o = *opts; else gp_opts_default(&o);
@@ -966,6 +988,14 @@ int gp_sample(gp_op* op, int R, const double* bw, const double* z1, const double
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
   if (int st = ensure_rhs(c, (size_t)R * op->K * op->N)) return st;
+  if (!z1) {
+    const size_t n1 = (size_t)R * op->K * op->dirs * op->N, n2 = (size_t)R * op->K * op->N;
+    if (int st = ensure_buf(c, c->zbuf, c->zcap, n1 + n2)) return st;
+    HIPTRY(launch_rng_normal(c->stream, o.seed, 1, n1, c->zbuf));
+    HIPTRY(launch_rng_normal(c->stream, o.seed, 2, n2, c->zbuf + n1));
+    z1 = c->zbuf;
+    z2 = c->zbuf + n1;
+  }
   PROFILED(c, GP_KERNEL_PERTURB, launch_perturb(c->stream, op_dev(op), R, bw, z1, z2, c->rhs));
   prof_perturb(op, R);
   std::vector<Item> items{Item{op, R, c->rhs, w}};
@@ -1013,6 +1043,27 @@ static int trace_reduce_impl(gp_op* op, int m, const int8_t* probes, const doubl
   return GP_OK;
 }
 
+int gp_rng_normal(gp_ctx* c, uint64_t seed, uint64_t stream, size_t n, double* out) {
+  if (!c || (n > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_rng_normal(c->stream, seed, stream, n, out));
+  return GP_OK;
+}
+
+int gp_rng_rademacher(gp_ctx* c, uint64_t seed, uint64_t stream, size_t n, int8_t* out) {
+  if (!c || (n > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_rng_rademacher(c->stream, seed, stream, n, out));
+  return GP_OK;
+}
+
+int gp_rng_raw(gp_ctx* c, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out) {
+  if (!c || (nblocks > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_rng_raw(c->stream, seed, stream, nblocks, out));
+  return GP_OK;
+}
+
 int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u, double* tr_total, double* tr_kk,
                     double* tr_Gkk) {
   if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
@@ -1029,7 +1080,7 @@ int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total
              const gp_opts* opts, gp_stats* stats) {
   if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
   if (m < 1 || m > 65535) return fail(GP_ERR_INVALID_ARG, "m out of range");
-  if (!probes || !u) return fail(GP_ERR_INVALID_ARG, "null buffer (on-device probes are not available)");
+  if (!u) return fail(GP_ERR_INVALID_ARG, "null buffer");
   if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
   gp_opts o;
   if (opts) o = *opts; else gp_opts_default(&o);
@@ -1038,6 +1089,11 @@ int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
   const size_t nv = (size_t)m * op->K * op->N;
+  if (!probes) {
+    if (int st = ensure_buf(c, c->pbuf, c->pcap, nv)) return st;
+    HIPTRY(launch_rng_rademacher(c->stream, o.seed, 3, nv, c->pbuf));
+    probes = c->pbuf;
+  }
   if (int st = ensure_rhs(c, nv)) return st;
   PROFILED(c, GP_KERNEL_PROBE, launch_probe_rhs(c->stream, (long)nv, probes, c->rhs));
   prof_add(c, GP_KERNEL_PROBE, (double)m * op->N, (double)m * op->N * op->K * 9.0);

@@ -28,6 +28,11 @@ hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, 
 hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks);
 int finalize_rhs_per_block();
 
+// k_rng.hip: Philox4x32-10 normals, Rademacher signs and raw words
+hipError_t launch_rng_normal(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double* out);
+hipError_t launch_rng_rademacher(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, int8_t* out);
+hipError_t launch_rng_raw(hipStream_t s, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out);
+
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that
 // all have K regressors; W = total work items (tiles x right-hand-side chunks),
 // swept by nblk persistent workgroups (a multiple of 8, one XCD range each).

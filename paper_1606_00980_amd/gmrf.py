@@ -41,6 +41,7 @@ EXPORTS = [
     "gp_op_voxel_index", "gp_op_destroy",
     "gp_apply", "gp_solve", "gp_solve_batch", "gp_perturb_rhs", "gp_sample",
     "gp_probe_rhs", "gp_trace_reduce", "gp_trace",
+    "gp_rng_normal", "gp_rng_rademacher", "gp_rng_raw",
 ]
 
 
@@ -110,6 +111,9 @@ def _load() -> ctypes.CDLL:
         "gp_probe_rhs": (i32, [vp, i32, vp, vp]),
         "gp_trace_reduce": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl)]),
         "gp_trace": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl), P(GpOpts), P(GpStats)]),
+        "gp_rng_normal": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
+        "gp_rng_rademacher": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
+        "gp_rng_raw": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -302,3 +306,15 @@ def gp_trace(op: int, m: int, probes, u, K: int, opts: GpOpts | None = None):
     _check(lib.gp_trace(op, m, _ptr(probes), _ptr(u), ctypes.byref(t), tk, gk,
                         ctypes.byref(o), st_arr), "gp_trace")
     return t.value, np.array(tk[:]), np.array(gk[:]), _stats_list(st_arr, m)
+
+
+def gp_rng_normal(ctx: int, seed: int, stream: int, n: int, out) -> None:
+    _check(lib.gp_rng_normal(ctx, seed, stream, n, _ptr(out)), "gp_rng_normal")
+
+
+def gp_rng_rademacher(ctx: int, seed: int, stream: int, n: int, out) -> None:
+    _check(lib.gp_rng_rademacher(ctx, seed, stream, n, _ptr(out)), "gp_rng_rademacher")
+
+
+def gp_rng_raw(ctx: int, seed: int, stream: int, nblocks: int, out) -> None:
+    _check(lib.gp_rng_raw(ctx, seed, stream, nblocks, _ptr(out)), "gp_rng_raw")

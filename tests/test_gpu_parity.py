@@ -424,3 +424,48 @@ def test_graph_replays_match_eager(g, ctx, torch_cuda):
         g.gp_ctx_profile(ctx, False)
         assert torch.equal(xe2, xe), rep
     check_solutions(xe.cpu().numpy(), orc.solve(op.Q, b), w.K, w.N)
+
+
+# ----------------------------------------------------------- random vectors
+def test_philox_matches_oracle_twin(g, ctx, torch_cuda):
+    from oracle import philox
+    torch = torch_cuda
+    for seed, stream, n in ((0, 0, 1), (12345, 7, 1001), (2 ** 40 + 3, 2 ** 33 + 5, 70001)):
+        nb = (n + 3) // 4
+        raw = torch.empty(4 * nb, dtype=torch.int32, device="cuda")
+        g.gp_rng_raw(ctx, seed, stream, nb, raw)
+        ref = philox.philox4x32_10(np.arange(nb, dtype=np.uint64), seed, stream).ravel()
+        torch.cuda.synchronize()
+        assert np.array_equal(raw.cpu().numpy().view(np.uint32), ref)
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        g.gp_rng_normal(ctx, seed, stream, n, z)
+        zr = philox.normal(seed, stream, n)
+        torch.cuda.synchronize()
+        assert np.allclose(z.cpu().numpy(), zr, rtol=1e-12, atol=1e-13)
+        v = torch.empty(n, dtype=torch.int8, device="cuda")
+        g.gp_rng_rademacher(ctx, seed, stream, n, v)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), philox.rademacher(seed, stream, n))
+
+
+def test_sample_and_trace_with_device_random_vectors(g, ctx, torch_cuda):
+    from oracle import philox
+    torch = torch_cuda
+    w = synth.tiny((11, 10, 7), 6, 3, seed=20)
+    op = Op(g, ctx, torch, w)
+    R, seed = 3, 777
+    o = opts(g, tol=1e-9, seed=seed)
+    ws = torch.zeros((R, w.K, w.N), dtype=torch.float64, device="cuda")
+    g.gp_sample(op.h, R, dev(torch, w.bw), None, None, ws, o)
+    n1 = R * w.K * 3 * w.N
+    z1 = philox.normal(seed, 1, n1).reshape(R, w.K, 3, w.N)
+    z2 = philox.normal(seed, 2, R * w.K * w.N).reshape(R, w.K, w.N)
+    ref = orc.sample(op.grid, w.alpha, w.B, w.bw, z1, z2)
+    check_solutions(ws.cpu().numpy(), ref, w.K, w.N)
+    m = 7
+    u = torch.empty((m, w.K, w.N), dtype=torch.float64, device="cuda")
+    t, tk, gk, _ = g.gp_trace(op.h, m, None, u, w.K, o)
+    v = philox.rademacher(seed, 3, m * w.K * w.N).reshape(m, w.K, w.N)
+    t_ref, tk_ref, gk_ref, _ = orc.hutchinson(op.grid, op.Q, v)
+    assert abs(t - t_ref) <= REL_ERR * abs(t_ref)
+    assert np.allclose(tk, tk_ref, rtol=REL_ERR) and np.allclose(gk, gk_ref, rtol=REL_ERR)
