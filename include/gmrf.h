@@ -257,6 +257,77 @@ int gp_rng_normal(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double*
 int gp_rng_rademacher(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, int8_t* out);
 int gp_rng_raw(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out);
 
+/* ---- serving ---------------------------------------------------------------
+ * A request loop over resident operators: requests (solve, sample, trace) are
+ * submitted from any thread, admitted in arrival order while the server's HBM
+ * budget and right-hand-side slots allow, join the running grouped solve at
+ * the next round boundary (continuous batching) and retire one by one.  The
+ * server runs on its own thread and HIP stream and holds its context busy
+ * until destroyed; its operators must not be modified meanwhile.  Results do
+ * not depend on which other requests share a round (batch-invariant
+ * reductions).
+ *
+ * Request kinds, all on operator `op_index` with b_w = bw[op_index]:
+ *  GP_REQ_SOLVE : x = Q^{-1}(b_w + n), n = gp_rng_normal(seed, stream 4)   (R = 1)
+ *  GP_REQ_SAMPLE: Algorithm 2 with z1, z2 = gp_rng_normal(seed, 1), (seed, 2)  (R = 1)
+ *  GP_REQ_TRACE : Hutchinson with cfg.probes Rademacher probes
+ *                 gp_rng_rademacher(seed, 3); u = Q^{-1} v                 (R = probes)
+ * `out` (device FP64 [R][K][N], may be NULL) receives x, the sample or u.   */
+#define GP_REQ_SOLVE  0
+#define GP_REQ_SAMPLE 1
+#define GP_REQ_TRACE  2
+
+typedef struct gp_server gp_server;
+
+typedef struct gp_server_cfg {
+  size_t  hbm_budget;      /* bytes of request workspace held at once (default 16 GiB) */
+  int     max_active_rhs;  /* right-hand-side slots advanced together (default 1024)   */
+  int     chunk;           /* inner iterations per round (default 4)                  */
+  int     probes;          /* probes per trace request (default 16)                   */
+  gp_opts opts;            /* solver options for every request                       */
+} gp_server_cfg;
+
+typedef struct gp_request {
+  int      kind;           /* GP_REQ_*                                                */
+  int      op_index;       /* index into the server's operators                      */
+  uint64_t seed;           /* Philox key of the request's random vectors             */
+  double*  out;            /* device result buffer or NULL                           */
+} gp_request;
+
+typedef struct gp_result {
+  uint64_t ticket;
+  int      kind, op_index, status, rhs;  /* status: GP_OK or the first failing one */
+  int      iters_max, reserved;
+  double   relres_max;
+  double   latency_us;     /* submit -> result available                             */
+  double   queue_us;       /* submit -> admitted                                     */
+  double   trace_total;    /* GP_REQ_TRACE: estimates as in gp_trace_reduce          */
+  double   trace_kk[16];
+  double   trace_Gkk[16];
+} gp_result;
+
+typedef struct gp_server_stats {
+  int64_t submitted, completed, rhs_solved, peak_active_rhs;
+  double  p50_us, p99_us, mean_us, max_us;  /* latency over completed requests        */
+  double  elapsed_s;                        /* first submit -> last completion        */
+  double  solves_per_s, requests_per_s;
+} gp_server_stats;
+
+void gp_server_cfg_default(gp_server_cfg* cfg);
+/* ops: host array of nops operators of ctx (blocks and alpha set); bw: host
+ * array of nops device pointers to FP64 [K][N] data right-hand sides.        */
+int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* const* bw,
+                     const gp_server_cfg* cfg, gp_server** out);
+/* thread-safe; returns at once with a ticket (host out)                      */
+int gp_server_submit(gp_server* srv, const gp_request* req, uint64_t* ticket);
+/* copies up to max finished results into out (host), *n receives the count  */
+int gp_server_poll(gp_server* srv, gp_result* out, int max, int* n);
+/* waits until every submitted request has finished (timeout_ms < 0: no limit);
+ * GP_ERR_BUSY on timeout                                                     */
+int gp_server_drain(gp_server* srv, int timeout_ms);
+int gp_server_get_stats(gp_server* srv, gp_server_stats* out);
+int gp_server_destroy(gp_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,10 +16,13 @@
 
 #include "gmrf.h"
 #include "launch.hpp"
+#include "runtime.hpp"
 
 using namespace gp;
+using namespace gp::rt;
 
-namespace {
+namespace gp {
+namespace rt {
 
 thread_local std::string g_err;
 
@@ -27,83 +30,6 @@ int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
-
-#define HIPTRY(call)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (call);                                                                   \
-    if (e_ != hipSuccess) return fail(GP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-}  // namespace
-
-struct gp_ctx {
-  int device = 0;
-  int cus = 256;     // compute units of the device
-  hipStream_t stream = nullptr;
-  size_t budget = 0, used = 0;
-  std::atomic<int> busy{0};
-  // solver workspace arena (grown on demand, reused across calls)
-  void* ws = nullptr;
-  size_t ws_cap = 0;
-  // right-hand-side staging for sample/trace, and on-device random vectors
-  double* rhs = nullptr;
-  size_t rhs_cap = 0;
-  double* zbuf = nullptr;
-  size_t zcap = 0;
-  int8_t* pbuf = nullptr;
-  size_t pcap = 0;
-  // grouped-launch descriptors
-  Prob* d_probs = nullptr;
-  Prob* h_probs = nullptr;
-  size_t probs_cap = 0;
-  // profiling: event pairs around launches, resolved after the stream drains
-  bool prof_on = false;
-  std::vector<hipEvent_t> evpool;
-  size_t ev_used = 0;
-  std::vector<std::pair<int, size_t>> pending;   // (kind, first event of the pair)
-  gp_prof acc[GP_KERNEL_KINDS] = {};
-  // captured launch sequences, keyed by the grouped-launch layout
-  hipStream_t cap_stream = nullptr;
-  std::map<std::string, hipGraphExec_t> graphs;
-  bool use_graphs = true;
-};
-
-struct gp_op {
-  gp_ctx* ctx = nullptr;
-  int N = 0, K = 0, nx = 0, ny = 0, nz = 0, conn = 0, dirs = 0, ntiles = 0;
-  int64_t E = 0;
-  int* nbr = nullptr;
-  int* lin = nullptr;
-  double* B64 = nullptr;
-  float* B32 = nullptr;
-  double* L64 = nullptr;
-  double* P64 = nullptr;
-  float* P32 = nullptr;
-  int* d_bad = nullptr;
-  double* tr_part = nullptr;
-  size_t tr_cap = 0;
-  double alpha[KMAX] = {0};
-  bool have_blocks = false, have_alpha = false;
-  int pc_built = -1;
-  int pc_want = GP_PRECOND_BLOCK_JACOBI;
-  size_t bytes = 0;
-};
-
-namespace {
-
-struct BusyGuard {
-  gp_ctx* c;
-  bool ok;
-  explicit BusyGuard(gp_ctx* ctx) : c(ctx) {
-    int expect = 0;
-    ok = c->busy.compare_exchange_strong(expect, 1);
-  }
-  ~BusyGuard() {
-    if (ok) c->busy.store(0);
-  }
-};
 
 int set_device(gp_ctx* c) {
   HIPTRY(hipSetDevice(c->device));
@@ -632,7 +558,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   return ret;
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace gp
 
 // =================================================================== C ABI
 extern "C" {

@@ -320,6 +320,12 @@ __global__ __launch_bounds__(TILE) void k_perturb(OpDev op, const double* __rest
   }
 }
 
+// b[r][i] += bw[i] for R right-hand sides of length kn.
+__global__ void k_add_broadcast(long total, long kn, const double* __restrict__ bw, double* __restrict__ b) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) b[i] += bw[i % kn];
+}
+
 __global__ void k_probe_rhs(long total, const int8_t* __restrict__ v, double* __restrict__ b) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < total) b[i] = (double)v[i];
@@ -446,6 +452,13 @@ hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* b
 #undef X
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_add_broadcast(hipStream_t s, int R, long kn, const double* bw, double* b) {
+  const long total = (long)R * kn;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_add_broadcast, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, total, kn, bw, b);
   return hipGetLastError();
 }
 

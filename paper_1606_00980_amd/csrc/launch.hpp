@@ -20,6 +20,7 @@ hipError_t launch_apply(hipStream_t s, const OpDev& op, int R, const double* x, 
 hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* bw, const double* z1,
                           const double* z2, double* b);
 hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* b);
+hipError_t launch_add_broadcast(hipStream_t s, int R, long kn, const double* bw, double* b);
 hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, const double* u,
                         double* part, double* pairbuf, double* out);
 

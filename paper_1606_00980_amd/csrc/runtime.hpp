@@ -1,0 +1,109 @@
+// Internal host runtime shared by the C ABI (api.cpp) and the serving loop
+// (server.cpp): context and operator records, allocation under the context's
+// HBM budget, error reporting.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+#include "gmrf.h"
+
+namespace gp {
+namespace rt {
+
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string& msg);
+
+}  // namespace rt
+}  // namespace gp
+
+#define HIPTRY(call)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess) return gp::rt::fail(GP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct gp_ctx {
+  int device = 0;
+  int cus = 256;     // compute units of the device
+  hipStream_t stream = nullptr;
+  size_t budget = 0, used = 0;
+  std::atomic<int> busy{0};
+  // solver workspace arena (grown on demand, reused across calls)
+  void* ws = nullptr;
+  size_t ws_cap = 0;
+  // right-hand-side staging for sample/trace, and on-device random vectors
+  double* rhs = nullptr;
+  size_t rhs_cap = 0;
+  double* zbuf = nullptr;
+  size_t zcap = 0;
+  int8_t* pbuf = nullptr;
+  size_t pcap = 0;
+  // grouped-launch descriptors
+  gp::Prob* d_probs = nullptr;
+  gp::Prob* h_probs = nullptr;
+  size_t probs_cap = 0;
+  // profiling: event pairs around launches, resolved after the stream drains
+  bool prof_on = false;
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> pending;   // (kind, first event of the pair)
+  gp_prof acc[GP_KERNEL_KINDS] = {};
+  // captured launch sequences, keyed by the grouped-launch layout
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  bool use_graphs = true;
+};
+
+struct gp_op {
+  gp_ctx* ctx = nullptr;
+  int N = 0, K = 0, nx = 0, ny = 0, nz = 0, conn = 0, dirs = 0, ntiles = 0;
+  int64_t E = 0;
+  int* nbr = nullptr;
+  int* lin = nullptr;
+  double* B64 = nullptr;
+  float* B32 = nullptr;
+  double* L64 = nullptr;
+  double* P64 = nullptr;
+  float* P32 = nullptr;
+  int* d_bad = nullptr;
+  double* tr_part = nullptr;
+  size_t tr_cap = 0;
+  double alpha[gp::KMAX] = {0};
+  bool have_blocks = false, have_alpha = false;
+  int pc_built = -1;
+  int pc_want = GP_PRECOND_BLOCK_JACOBI;
+  size_t bytes = 0;
+};
+
+namespace gp {
+namespace rt {
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct BusyGuard {
+  gp_ctx* c;
+  bool ok;
+  explicit BusyGuard(gp_ctx* ctx) : c(ctx) {
+    int expect = 0;
+    ok = c->busy.compare_exchange_strong(expect, 1);
+  }
+  ~BusyGuard() {
+    if (ok) c->busy.store(0);
+  }
+};
+
+int set_device(gp_ctx* c);
+int dev_alloc(gp_ctx* c, size_t bytes, void** p);
+void dev_free(gp_ctx* c, void* p, size_t bytes);
+OpDev op_dev(const gp_op* op);
+int build_precond(gp_op* op, int pc);
+bool valid_opts(const gp_opts& o, std::string* why);
+
+}  // namespace rt
+}  // namespace gp

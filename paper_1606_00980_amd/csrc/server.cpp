@@ -1,0 +1,563 @@
+// Serving loop: resident operators, admission by HBM budget, continuous
+// batching of solve / sample / trace requests into the grouped PCG launches,
+// per-request latency.
+//
+// The worker thread repeats rounds.  A round admits waiting requests (FIFO,
+// while the byte budget and the right-hand-side slot table allow), prepares
+// their right-hand sides on the device, rebuilds the grouped-launch
+// descriptors when the active set changed, runs one refinement step and
+// `chunk` inner iterations for every active right-hand side, copies the
+// state table to the host and retires every request whose right-hand sides
+// are all done.  Requests therefore join and leave the running batch at
+// round boundaries, and the kernels' batch-invariant reductions make a
+// request's result independent of its company.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "gmrf.h"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+using namespace gp;
+using namespace gp::rt;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+  uint64_t ticket = 0;
+  gp_request r{};
+  gp_op* op = nullptr;
+  const double* bw = nullptr;
+  int R = 1;
+  int slot0 = -1;
+  char* mem = nullptr;      // one allocation holding every buffer below
+  size_t bytes = 0;
+  double *b = nullptr, *x = nullptr, *part = nullptr, *tr = nullptr;
+  void* vec[6] = {};
+  int8_t* probes = nullptr;
+  Clock::time_point t_submit, t_admit;
+};
+
+double us_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::micro>(b - a).count();
+}
+
+}  // namespace
+
+struct gp_server {
+  gp_ctx* ctx = nullptr;
+  std::vector<gp_op*> ops;
+  std::vector<const double*> bw;
+  gp_server_cfg cfg{};
+  bool f32 = true;
+  size_t tsz = 4;
+  hipStream_t stream = nullptr;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> pending;
+  std::vector<Req*> active;
+  std::deque<gp_result> finished;
+  bool stop = false;
+  int fatal = GP_OK;
+  std::string fatal_msg;
+  uint64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, rhs_solved = 0, peak_active = 0;
+  size_t bytes_in_use = 0;
+  std::vector<double> latencies;
+  Clock::time_point t_first{}, t_last{};
+  bool any_submitted = false;
+  // device state table, one RhsState per right-hand-side slot
+  RhsState* d_states = nullptr;
+  std::vector<RhsState> h_states;
+  std::vector<char> slot_used;
+  // grouped-launch descriptors
+  Prob* d_probs = nullptr;
+  Prob* h_probs = nullptr;
+  int probs_cap = 0;
+  bool layout_dirty = true;
+  struct Group {
+    int K, first, count, W, F, nblk;
+  };
+  std::vector<Group> groups;
+  std::vector<Req*> order;   // active requests in descriptor order
+};
+
+namespace {
+
+int find_slots(gp_server* s, int R) {
+  const int cap = (int)s->slot_used.size();
+  int run = 0;
+  for (int i = 0; i < cap; ++i) {
+    run = s->slot_used[i] ? 0 : run + 1;
+    if (run == R) return i - R + 1;
+  }
+  return -1;
+}
+
+size_t request_bytes(const gp_server* s, const gp_op* op, int R, int kind) {
+  const size_t nv = (size_t)R * op->K * op->N;
+  size_t b = 0;
+  b += align_up(2 * nv * sizeof(double), 256);                                     // b, x
+  b += 6 * align_up(nv * s->tsz, 256);                                             // inner vectors
+  b += align_up((size_t)NPART * R * op->ntiles * sizeof(double), 256);              // partials
+  if (kind == GP_REQ_SAMPLE) b += align_up((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double), 256);
+  if (kind == GP_REQ_TRACE) {
+    b += align_up(nv, 256);                                                         // probes
+    b += align_up(((size_t)2 * R * op->K * op->ntiles + 2 * (size_t)R * op->K + 1 + 2 * KMAX) * sizeof(double), 256);
+  }
+  return b;
+}
+
+// Allocates a request's buffers and prepares its right-hand sides.
+int admit(gp_server* s, Req* q) {
+  hipStream_t st = s->stream;
+  gp_op* op = q->op;
+  const size_t nv = (size_t)q->R * op->K * op->N;
+  HIPTRY(hipMallocAsync((void**)&q->mem, q->bytes, st));
+  char* p = q->mem;
+  auto take = [&](size_t n) {
+    char* r = p;
+    p += align_up(n, 256);
+    return r;
+  };
+  q->b = (double*)take(2 * nv * sizeof(double));
+  q->x = q->b + nv;
+  for (int v = 0; v < 6; ++v) q->vec[v] = take(nv * s->tsz);
+  q->part = (double*)take((size_t)NPART * q->R * op->ntiles * sizeof(double));
+  double* z = nullptr;
+  if (q->r.kind == GP_REQ_SAMPLE) z = (double*)take((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double));
+  if (q->r.kind == GP_REQ_TRACE) {
+    q->probes = (int8_t*)take(nv);
+    q->tr = (double*)take(((size_t)2 * q->R * op->K * op->ntiles + 2 * (size_t)q->R * op->K + 1 + 2 * KMAX) *
+                          sizeof(double));
+  }
+  const OpDev d = op_dev(op);
+  const size_t kn = (size_t)op->K * op->N;
+  switch (q->r.kind) {
+    case GP_REQ_SOLVE:
+      HIPTRY(launch_rng_normal(st, q->r.seed, 4, kn, q->b));
+      HIPTRY(launch_add_broadcast(st, 1, (long)kn, q->bw, q->b));
+      break;
+    case GP_REQ_SAMPLE: {
+      const size_t n1 = (size_t)op->dirs * kn;
+      HIPTRY(launch_rng_normal(st, q->r.seed, 1, n1, z));
+      HIPTRY(launch_rng_normal(st, q->r.seed, 2, kn, z + n1));
+      HIPTRY(launch_perturb(st, d, 1, q->bw, z, z + n1, q->b));
+      break;
+    }
+    default:
+      HIPTRY(launch_rng_rademacher(st, q->r.seed, 3, nv, q->probes));
+      HIPTRY(launch_probe_rhs(st, (long)nv, q->probes, q->b));
+      break;
+  }
+  HIPTRY(hipMemsetAsync(q->x, 0, nv * sizeof(double), st));
+  HIPTRY(hipMemsetAsync(s->d_states + q->slot0, 0, (size_t)q->R * sizeof(RhsState), st));
+  return GP_OK;
+}
+
+int ensure_descriptors(gp_server* s, int n) {
+  if (n <= s->probs_cap) return GP_OK;
+  HIPTRY(hipStreamSynchronize(s->stream));
+  if (s->d_probs) (void)hipFree(s->d_probs);
+  if (s->h_probs) (void)hipHostFree(s->h_probs);
+  s->probs_cap = std::max(n, 2 * s->probs_cap);
+  HIPTRY(hipMalloc((void**)&s->d_probs, (size_t)s->probs_cap * sizeof(Prob)));
+  HIPTRY(hipHostMalloc((void**)&s->h_probs, (size_t)s->probs_cap * sizeof(Prob), hipHostMallocDefault));
+  return GP_OK;
+}
+
+int rebuild_layout(gp_server* s) {
+  s->order = s->active;
+  std::stable_sort(s->order.begin(), s->order.end(), [](Req* a, Req* b) { return a->op->K < b->op->K; });
+  if (int st = ensure_descriptors(s, (int)s->order.size())) return st;
+  s->groups.clear();
+  const gp_opts& o = s->cfg.opts;
+  const SolveCfg cfg{o.tol, s->f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
+  const int fpb = finalize_rhs_per_block();
+  for (int j = 0; j < (int)s->order.size(); ++j) {
+    Req* q = s->order[j];
+    Prob& p = s->h_probs[j];
+    std::memset(&p, 0, sizeof(Prob));
+    p.op = op_dev(q->op);
+    p.b = q->b;
+    p.x = q->x;
+    p.d = q->vec[0];
+    p.r = q->vec[1];
+    p.z = q->vec[2];
+    p.p0 = q->vec[3];
+    p.p1 = q->vec[4];
+    p.q = q->vec[5];
+    p.st = s->d_states + q->slot0;
+    p.part = q->part;
+    p.prof = nullptr;
+    p.R = q->R;
+    int rc = o.rhs_tile > 0 ? o.rhs_tile : 4;
+    rc = std::max(1, std::min(std::min(rc, RCMAX), q->R));
+    p.Rc = rc;
+    p.nchunks = (q->R + rc - 1) / rc;
+    p.work_count = q->op->ntiles * p.nchunks;
+    p.cfg = cfg;
+    if (s->groups.empty() || s->groups.back().K != q->op->K)
+      s->groups.push_back(gp_server::Group{q->op->K, j, 0, 0, 0, 0});
+    auto& g = s->groups.back();
+    p.work_begin = g.W;
+    g.W += p.work_count;
+    p.fin_begin = g.F;
+    g.F += (q->R + fpb - 1) / fpb;
+    g.count += 1;
+  }
+  const int wpc = o.wg_per_cu > 0 ? o.wg_per_cu : 8;
+  for (auto& g : s->groups) g.nblk = std::min(std::max(8, s->ctx->cus * wpc / 8 * 8), (g.W + 7) / 8 * 8);
+  HIPTRY(hipMemcpyAsync(s->d_probs, s->h_probs, s->order.size() * sizeof(Prob), hipMemcpyHostToDevice, s->stream));
+  s->layout_dirty = false;
+  return GP_OK;
+}
+
+int run_round(gp_server* s) {
+  hipStream_t st = s->stream;
+  const int pc = s->cfg.opts.precond;
+  const bool f32 = s->f32;
+  for (const auto& g : s->groups) {
+    const Prob* dp = s->d_probs + g.first;
+    HIPTRY(f32 ? launch_addsol_f32(st, g.K, dp, g.count, g.W, g.nblk) : launch_addsol_f64(st, g.K, dp, g.count, g.W, g.nblk));
+    HIPTRY(f32 ? launch_refine_f32(st, pc, g.K, dp, g.count, g.W, g.nblk)
+               : launch_refine_f64(st, pc, g.K, dp, g.count, g.W, g.nblk));
+    HIPTRY(launch_finalize(st, 0, dp, g.count, g.F));
+  }
+  int parity = 0;
+  for (int i = 0; i < s->cfg.chunk; ++i) {
+    for (const auto& g : s->groups) {
+      const Prob* dp = s->d_probs + g.first;
+      HIPTRY(f32 ? launch_matvec_f32(st, g.K, dp, g.count, g.W, g.nblk, parity)
+                 : launch_matvec_f64(st, g.K, dp, g.count, g.W, g.nblk, parity));
+      HIPTRY(launch_finalize(st, 1, dp, g.count, g.F));
+      HIPTRY(f32 ? launch_update_f32(st, pc, g.K, dp, g.count, g.W, g.nblk, parity)
+                 : launch_update_f64(st, pc, g.K, dp, g.count, g.W, g.nblk, parity));
+      HIPTRY(launch_finalize(st, 2, dp, g.count, g.F));
+    }
+    parity ^= 1;
+  }
+  // a request's direction vectors are double-buffered by launch parity; an
+  // even chunk returns every right-hand side to buffer 0 for the next round
+  HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
+                        hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  return GP_OK;
+}
+
+// Finishes request q (all its right-hand sides are done): trace reduction,
+// result copy, statistics; frees its memory and slots.
+int retire(gp_server* s, Req* q, gp_result* res) {
+  hipStream_t st = s->stream;
+  gp_op* op = q->op;
+  std::memset(res, 0, sizeof(*res));
+  res->ticket = q->ticket;
+  res->kind = q->r.kind;
+  res->op_index = q->r.op_index;
+  res->rhs = q->R;
+  res->status = GP_OK;
+  for (int r = 0; r < q->R; ++r) {
+    const RhsState& h = s->h_states[q->slot0 + r];
+    if (h.status != GP_OK && res->status == GP_OK) res->status = h.status;
+    res->iters_max = std::max(res->iters_max, h.total_it);
+    res->relres_max = std::max(res->relres_max, h.relres);
+  }
+  const size_t nv = (size_t)q->R * op->K * op->N;
+  if (q->r.kind == GP_REQ_TRACE) {
+    double* part = q->tr;
+    double* pairbuf = part + (size_t)2 * q->R * op->K * op->ntiles;
+    double* out = pairbuf + (size_t)2 * q->R * op->K;
+    HIPTRY(launch_trace(st, op_dev(op), q->R, q->probes, q->x, part, pairbuf, out));
+    std::vector<double> h(1 + 2 * op->K);
+    HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    res->trace_total = h[0];
+    for (int k = 0; k < op->K; ++k) {
+      res->trace_kk[k] = h[1 + k];
+      res->trace_Gkk[k] = h[1 + op->K + k];
+    }
+  }
+  if (q->r.out) HIPTRY(hipMemcpyAsync(q->r.out, q->x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPTRY(hipFreeAsync(q->mem, st));
+  HIPTRY(hipStreamSynchronize(st));
+  for (int r = 0; r < q->R; ++r) s->slot_used[q->slot0 + r] = 0;
+  const auto now = Clock::now();
+  res->latency_us = us_between(q->t_submit, now);
+  res->queue_us = us_between(q->t_submit, q->t_admit);
+  return GP_OK;
+}
+
+void worker_main(gp_server* s) {
+  if (hipSetDevice(s->ctx->device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fatal = GP_ERR_DEVICE;
+    s->fatal_msg = "server thread could not select the device";
+    s->cv_done.notify_all();
+    return;
+  }
+  for (;;) {
+    std::vector<Req*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->active.empty()) s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+      if (s->stop && s->pending.empty() && s->active.empty()) return;
+      while (!s->pending.empty()) {
+        Req* q = s->pending.front();
+        if (s->bytes_in_use + q->bytes > s->cfg.hbm_budget) break;
+        const int slot = find_slots(s, q->R);
+        if (slot < 0) break;
+        for (int r = 0; r < q->R; ++r) s->slot_used[slot + r] = 1;
+        q->slot0 = slot;
+        s->bytes_in_use += q->bytes;
+        s->pending.pop_front();
+        admitted.push_back(q);
+      }
+    }
+    int err = GP_OK;
+    for (Req* q : admitted) {
+      q->t_admit = Clock::now();
+      if ((err = admit(s, q)) != GP_OK) break;
+      s->active.push_back(q);
+      s->layout_dirty = true;
+    }
+    int64_t live = 0;
+    for (Req* q : s->active) live += q->R;
+    s->peak_active = std::max(s->peak_active, live);
+    if (err == GP_OK && !s->active.empty()) {
+      if (s->layout_dirty) err = rebuild_layout(s);
+      if (err == GP_OK) err = run_round(s);
+    }
+    std::vector<gp_result> done;
+    if (err == GP_OK) {
+      std::vector<Req*> still;
+      for (Req* q : s->active) {
+        bool all = true;
+        for (int r = 0; r < q->R && all; ++r) all = s->h_states[q->slot0 + r].phase == PH_DONE;
+        if (!all) {
+          still.push_back(q);
+          continue;
+        }
+        gp_result res;
+        if ((err = retire(s, q, &res)) != GP_OK) break;
+        done.push_back(res);
+        s->layout_dirty = true;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->bytes_in_use -= q->bytes;
+        delete q;
+      }
+      if (err == GP_OK) s->active.swap(still);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (err != GP_OK) {
+      s->fatal = err;
+      s->fatal_msg = gp_last_error();
+      s->stop = true;
+      s->cv_done.notify_all();
+      return;
+    }
+    for (gp_result& r : done) {
+      s->latencies.push_back(r.latency_us);
+      s->completed += 1;
+      s->rhs_solved += r.rhs;
+      s->finished.push_back(r);
+      s->t_last = Clock::now();
+    }
+    if (!done.empty()) s->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_server_cfg_default(gp_server_cfg* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->hbm_budget = (size_t)16 << 30;
+  c->max_active_rhs = 1024;
+  c->chunk = 4;
+  c->probes = 16;
+  gp_opts_default(&c->opts);
+}
+
+int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* const* bw, const gp_server_cfg* cfg,
+                     gp_server** out) {
+  if (!out) return fail(GP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx || nops < 1 || !ops || !bw) return fail(GP_ERR_INVALID_ARG, "ctx, ops or bw missing");
+  gp_server_cfg c;
+  if (cfg) c = *cfg; else gp_server_cfg_default(&c);
+  std::string why;
+  if (!valid_opts(c.opts, &why)) return fail(GP_ERR_INVALID_ARG, why);
+  if (c.max_active_rhs < 1 || c.chunk < 2 || (c.chunk & 1) || c.probes < 1 || c.probes > c.max_active_rhs)
+    return fail(GP_ERR_INVALID_ARG, "max_active_rhs >= 1, even chunk >= 2 and 1 <= probes <= max_active_rhs required");
+  for (int i = 0; i < nops; ++i) {
+    if (!ops[i] || ops[i]->ctx != ctx || !bw[i]) return fail(GP_ERR_INVALID_ARG, "operator or b_w missing");
+    if (!ops[i]->have_blocks || !ops[i]->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+  }
+  int expect = 0;
+  if (!ctx->busy.compare_exchange_strong(expect, 1)) return fail(GP_ERR_BUSY, "context busy");
+  gp_server* s = new gp_server();
+  s->ctx = ctx;
+  s->cfg = c;
+  s->f32 = c.opts.precision == GP_PREC_FP32_REFINE64;
+  s->tsz = s->f32 ? sizeof(float) : sizeof(double);
+  s->ops.assign(ops, ops + nops);
+  s->bw.assign(bw, bw + nops);
+  s->h_states.resize(c.max_active_rhs);
+  s->slot_used.assign(c.max_active_rhs, 0);
+  auto bail = [&](int st) {
+    if (s->d_states) (void)hipFree(s->d_states);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    ctx->busy.store(0);
+    return st;
+  };
+  if (int st = set_device(ctx)) return bail(st);
+  for (gp_op* op : s->ops)
+    if (op->pc_built != c.opts.precond)
+      if (int st = build_precond(op, c.opts.precond)) return bail(st);
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(GP_ERR_DEVICE, "could not create the server stream"));
+  if (hipMalloc((void**)&s->d_states, (size_t)c.max_active_rhs * sizeof(RhsState)) != hipSuccess)
+    return bail(fail(GP_ERR_OOM, "could not allocate the state table"));
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return GP_OK;
+}
+
+int gp_server_submit(gp_server* s, const gp_request* req, uint64_t* ticket) {
+  if (!s || !req) return fail(GP_ERR_INVALID_ARG, "server or request is NULL");
+  if (req->kind < GP_REQ_SOLVE || req->kind > GP_REQ_TRACE) return fail(GP_ERR_INVALID_ARG, "unknown request kind");
+  if (req->op_index < 0 || req->op_index >= (int)s->ops.size()) return fail(GP_ERR_INVALID_ARG, "op_index out of range");
+  Req* q = new Req();
+  q->r = *req;
+  q->op = s->ops[req->op_index];
+  q->bw = s->bw[req->op_index];
+  q->R = req->kind == GP_REQ_TRACE ? s->cfg.probes : 1;
+  q->bytes = request_bytes(s, q->op, q->R, req->kind);
+  if (q->bytes > s->cfg.hbm_budget) {
+    delete q;
+    return fail(GP_ERR_OOM, "request needs more memory than the server's budget");
+  }
+  q->t_submit = Clock::now();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->fatal != GP_OK) {
+    delete q;
+    return fail(s->fatal, "server stopped: " + s->fatal_msg);
+  }
+  if (s->stop) {
+    delete q;
+    return fail(GP_ERR_INVALID_ARG, "server is stopping");
+  }
+  q->ticket = s->next_ticket++;
+  if (!s->any_submitted) {
+    s->any_submitted = true;
+    s->t_first = q->t_submit;
+  }
+  s->submitted += 1;
+  s->pending.push_back(q);
+  if (ticket) *ticket = q->ticket;
+  s->cv_work.notify_one();
+  return GP_OK;
+}
+
+int gp_server_poll(gp_server* s, gp_result* out, int max, int* n) {
+  if (!s || !n || (max > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  int k = 0;
+  while (k < max && !s->finished.empty()) {
+    out[k++] = s->finished.front();
+    s->finished.pop_front();
+  }
+  *n = k;
+  if (s->fatal != GP_OK && k == 0) return fail(s->fatal, "server stopped: " + s->fatal_msg);
+  return GP_OK;
+}
+
+int gp_server_drain(gp_server* s, int timeout_ms) {
+  if (!s) return fail(GP_ERR_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto ready = [&] { return s->fatal != GP_OK || s->completed == s->submitted; };
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
+    return fail(GP_ERR_BUSY, "requests still running");
+  }
+  if (s->fatal != GP_OK) return fail(s->fatal, "server stopped: " + s->fatal_msg);
+  return GP_OK;
+}
+
+int gp_server_get_stats(gp_server* s, gp_server_stats* out) {
+  if (!s || !out) return fail(GP_ERR_INVALID_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->rhs_solved = s->rhs_solved;
+  out->peak_active_rhs = s->peak_active;
+  if (!s->latencies.empty()) {
+    std::vector<double> v = s->latencies;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t i = (size_t)std::min<double>(v.size() - 1, std::max(0.0, std::ceil(p * v.size()) - 1));
+      return v[i];
+    };
+    out->p50_us = pct(0.50);
+    out->p99_us = pct(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_us = sum / v.size();
+    out->max_us = v.back();
+    out->elapsed_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    if (out->elapsed_s > 0) {
+      out->solves_per_s = s->rhs_solved / out->elapsed_s;
+      out->requests_per_s = s->completed / out->elapsed_s;
+    }
+  }
+  return GP_OK;
+}
+
+int gp_server_destroy(gp_server* s) {
+  if (!s) return GP_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->ctx->device);
+  (void)hipStreamSynchronize(s->stream);
+  for (Req* q : s->active) {
+    if (q->mem) (void)hipFreeAsync(q->mem, s->stream);
+    delete q;
+  }
+  for (Req* q : s->pending) delete q;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->d_probs) (void)hipFree(s->d_probs);
+  if (s->h_probs) (void)hipHostFree(s->h_probs);
+  if (s->d_states) (void)hipFree(s->d_states);
+  (void)hipStreamDestroy(s->stream);
+  s->ctx->busy.store(0);
+  delete s;
+  return GP_OK;
+}
+
+}  // extern "C"

@@ -42,7 +42,11 @@ EXPORTS = [
     "gp_apply", "gp_solve", "gp_solve_batch", "gp_perturb_rhs", "gp_sample",
     "gp_probe_rhs", "gp_trace_reduce", "gp_trace",
     "gp_rng_normal", "gp_rng_rademacher", "gp_rng_raw",
+    "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
+    "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
 ]
+
+GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
 
 
 class GpOpts(ctypes.Structure):
@@ -71,6 +75,34 @@ KERNEL_KINDS = ["refine", "matvec", "update", "addsol", "perturb", "precond", "p
 class GpItem(ctypes.Structure):
     _fields_ = [("op", ctypes.c_void_p), ("R", ctypes.c_int),
                 ("b", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class GpServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active_rhs", ctypes.c_int),
+                ("chunk", ctypes.c_int), ("probes", ctypes.c_int), ("opts", GpOpts)]
+
+
+class GpRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("op_index", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+
+
+class GpResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("kind", ctypes.c_int), ("op_index", ctypes.c_int),
+                ("status", ctypes.c_int), ("rhs", ctypes.c_int), ("iters_max", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("relres_max", ctypes.c_double),
+                ("latency_us", ctypes.c_double), ("queue_us", ctypes.c_double),
+                ("trace_total", ctypes.c_double), ("trace_kk", ctypes.c_double * 16),
+                ("trace_Gkk", ctypes.c_double * 16)]
+
+
+class GpServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rhs_solved", ctypes.c_int64), ("peak_active_rhs", ctypes.c_int64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("requests_per_s", ctypes.c_double)]
 
 
 class GmrfError(RuntimeError):
@@ -114,6 +146,13 @@ def _load() -> ctypes.CDLL:
         "gp_rng_normal": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
         "gp_rng_rademacher": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
         "gp_rng_raw": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
+        "gp_server_cfg_default": (None, [P(GpServerCfg)]),
+        "gp_server_create": (i32, [vp, i32, P(vp), P(vp), P(GpServerCfg), P(vp)]),
+        "gp_server_submit": (i32, [vp, P(GpRequest), P(ctypes.c_uint64)]),
+        "gp_server_poll": (i32, [vp, P(GpResult), i32, P(i32)]),
+        "gp_server_drain": (i32, [vp, i32]),
+        "gp_server_get_stats": (i32, [vp, P(GpServerStats)]),
+        "gp_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -318,3 +357,59 @@ def gp_rng_rademacher(ctx: int, seed: int, stream: int, n: int, out) -> None:
 
 def gp_rng_raw(ctx: int, seed: int, stream: int, nblocks: int, out) -> None:
     _check(lib.gp_rng_raw(ctx, seed, stream, nblocks, _ptr(out)), "gp_rng_raw")
+
+
+def gp_server_cfg_default(**overrides) -> GpServerCfg:
+    c = GpServerCfg()
+    lib.gp_server_cfg_default(ctypes.byref(c))
+    for k, v in overrides.items():
+        if k == "opts":
+            c.opts = v
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def gp_server_create(ctx: int, ops, bws, cfg: GpServerCfg | None = None) -> int:
+    n = len(ops)
+    oa = (ctypes.c_void_p * n)(*ops)
+    ba = (ctypes.c_void_p * n)(*[_ptr(b) for b in bws])
+    h = ctypes.c_void_p()
+    c = cfg if cfg is not None else gp_server_cfg_default()
+    _check(lib.gp_server_create(ctx, n, oa, ba, ctypes.byref(c), ctypes.byref(h)), "gp_server_create")
+    return h.value
+
+
+def gp_server_submit(srv: int, kind: int, op_index: int, seed: int, out=None) -> int:
+    r = GpRequest(kind, op_index, seed, _ptr(out))
+    t = ctypes.c_uint64()
+    _check(lib.gp_server_submit(srv, ctypes.byref(r), ctypes.byref(t)), "gp_server_submit")
+    return t.value
+
+
+def _result_dict(r: GpResult) -> dict:
+    return {"ticket": r.ticket, "kind": r.kind, "op_index": r.op_index, "status": r.status,
+            "rhs": r.rhs, "iters_max": r.iters_max, "relres_max": r.relres_max,
+            "latency_us": r.latency_us, "queue_us": r.queue_us, "trace_total": r.trace_total,
+            "trace_kk": list(r.trace_kk), "trace_Gkk": list(r.trace_Gkk)}
+
+
+def gp_server_poll(srv: int, max_results: int = 256) -> list:
+    arr = (GpResult * max_results)()
+    n = ctypes.c_int()
+    _check(lib.gp_server_poll(srv, arr, max_results, ctypes.byref(n)), "gp_server_poll")
+    return [_result_dict(arr[i]) for i in range(n.value)]
+
+
+def gp_server_drain(srv: int, timeout_ms: int = -1) -> None:
+    _check(lib.gp_server_drain(srv, timeout_ms), "gp_server_drain")
+
+
+def gp_server_get_stats(srv: int) -> dict:
+    s = GpServerStats()
+    _check(lib.gp_server_get_stats(srv, ctypes.byref(s)), "gp_server_get_stats")
+    return {f: getattr(s, f) for f, _ in GpServerStats._fields_}
+
+
+def gp_server_destroy(srv: int) -> None:
+    _check(lib.gp_server_destroy(srv), "gp_server_destroy")

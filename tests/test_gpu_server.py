@@ -1,0 +1,119 @@
+"""Serving loop: every result equals the oracle's, and is bitwise the same
+whether the request ran alone or among others (continuous batching with
+batch-invariant reductions); admission by HBM budget."""
+import numpy as np
+import pytest
+
+from oracle import gmrf_oracle as orc
+from oracle import philox
+from paper_1606_00980_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(built_library):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1606_00980_amd import gmrf as g
+    ctx = g.gp_ctx_create(0, torch.cuda.current_stream().cuda_stream, 0)
+    ws = [synth.tiny((13, 11, 7), 6, 2, seed=31), synth.tiny((16, 12, 8), 6, 5, seed=32),
+          synth.tiny((12, 10, 1), 4, 3, seed=33)]
+    ops, bws, keep = [], [], []
+    for w in ws:
+        op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+        B = torch.from_numpy(w.B).cuda()
+        g.gp_op_set_blocks(op, B)
+        g.gp_op_set_alpha(op, w.alpha)
+        bw = torch.from_numpy(w.bw).cuda()
+        ops.append(op)
+        bws.append(bw)
+        keep.append(B)
+    yield g, torch, ctx, ws, ops, bws
+    for op in ops:
+        g.gp_op_destroy(op)
+    g.gp_ctx_destroy(ctx)
+
+
+PROBES = 4
+
+
+def run(g, torch, ctx, ws, ops, bws, reqs, budget=1 << 30):
+    cfg = g.gp_server_cfg_default(probes=PROBES, hbm_budget=budget,
+                                  opts=g.gp_opts_default(tol=1e-9))
+    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    outs, tickets = [], []
+    try:
+        for kind, oi, seed in reqs:
+            w = ws[oi]
+            R = PROBES if kind == g.GP_REQ_TRACE else 1
+            out = torch.zeros((R, w.K, w.N), dtype=torch.float64, device="cuda")
+            outs.append(out)
+            tickets.append(g.gp_server_submit(srv, kind, oi, seed, out))
+        g.gp_server_drain(srv, 60000)
+        res = {r["ticket"]: r for r in g.gp_server_poll(srv, 1024)}
+        stats = g.gp_server_get_stats(srv)
+    finally:
+        g.gp_server_destroy(srv)
+    torch.cuda.synchronize()
+    return [res[t] for t in tickets], [o.cpu().numpy() for o in outs], stats
+
+
+def oracle_result(g, w, kind, seed):
+    grid = orc.grid(w.mask, w.conn)
+    Q = orc.precision(grid, w.alpha, w.B)
+    n = w.K * w.N
+    if kind == g.GP_REQ_SOLVE:
+        b = w.bw + philox.normal(seed, 4, n).reshape(w.K, w.N)
+        return orc.solve(Q, b[None]), None
+    if kind == g.GP_REQ_SAMPLE:
+        z1 = philox.normal(seed, 1, grid.ndirs * n).reshape(1, w.K, grid.ndirs, w.N)
+        z2 = philox.normal(seed, 2, n).reshape(1, w.K, w.N)
+        return orc.sample(grid, w.alpha, w.B, w.bw, z1, z2), None
+    v = philox.rademacher(seed, 3, PROBES * n).reshape(PROBES, w.K, w.N)
+    t, tk, gk, u = orc.hutchinson(grid, Q, v)
+    return u, (t, tk, gk)
+
+
+def test_server_mix_matches_alone_and_oracle(env):
+    g, torch, ctx, ws, ops, bws = env
+    kinds = [g.GP_REQ_SOLVE, g.GP_REQ_SAMPLE, g.GP_REQ_TRACE]
+    reqs = [(kinds[i % 3], (i * 7) % 3, 1000 + i) for i in range(15)]
+    res, outs, stats = run(g, torch, ctx, ws, ops, bws, reqs)
+    assert stats["completed"] == len(reqs) and stats["p99_us"] >= stats["p50_us"] > 0
+    assert all(r["status"] == 0 and r["relres_max"] <= 1e-9 for r in res)
+    for (kind, oi, seed), r, out in zip(reqs, res, outs):
+        alone_res, alone_out, _ = run(g, torch, ctx, ws, ops, bws, [(kind, oi, seed)])
+        assert np.array_equal(alone_out[0], out), (kind, oi, seed)
+        if kind == g.GP_REQ_TRACE:
+            assert alone_res[0]["trace_total"] == r["trace_total"]
+    for (kind, oi, seed), r, out in list(zip(reqs, res, outs))[:6]:
+        w = ws[oi]
+        ref, tr = oracle_result(g, w, kind, seed)
+        ref = ref.reshape(out.shape)
+        for i in range(out.shape[0]):
+            assert np.linalg.norm(out[i] - ref[i]) <= 1e-6 * np.linalg.norm(ref[i])
+        if tr is not None:
+            assert abs(r["trace_total"] - tr[0]) <= 1e-6 * abs(tr[0])
+            assert np.allclose(r["trace_kk"][:w.K], tr[1], rtol=1e-6)
+            assert np.allclose(r["trace_Gkk"][:w.K], tr[2], rtol=1e-6)
+
+
+def test_server_admission_budget(env):
+    g, torch, ctx, ws, ops, bws = env
+    reqs = [(g.GP_REQ_SAMPLE, i % 3, 2000 + i) for i in range(6)]
+    full, full_out, _ = run(g, torch, ctx, ws, ops, bws, reqs)
+    # a budget that holds about one request at a time still completes all of them
+    tight, tight_out, st = run(g, torch, ctx, ws, ops, bws, reqs, budget=300_000)
+    assert st["completed"] == 6 and st["peak_active_rhs"] <= 2
+    for a, b in zip(full_out, tight_out):
+        assert np.array_equal(a, b)
+    cfg = g.gp_server_cfg_default(probes=PROBES, hbm_budget=1000)
+    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    try:
+        with pytest.raises(g.GmrfError) as e:
+            g.gp_server_submit(srv, g.GP_REQ_SOLVE, 0, 1)
+        assert e.value.status == g.GP_ERR_OOM
+    finally:
+        g.gp_server_destroy(srv)
