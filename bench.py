@@ -44,7 +44,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven"])
+    ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven", "serve"])
+    ap.add_argument("--duration", type=float, default=20.0,
+                    help="serve: seconds of Poisson arrivals (the full stream is 300)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="serve: skip the sequential FP64 replay of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-baseline-gpu", action="store_true",
                     help="skip the plain FP64 single-right-hand-side comparison run")
@@ -92,7 +97,10 @@ class Workload:
                 self.opts = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64)
                 self.solves = 1
         else:   # 16 uneven operators, 8 right-hand sides each (4 samples + 4 probes)
-            self.ws = [synth.uneven_instance(synth.CFG_UNEVEN, i) for i in range(16)]
+            self.ws = []
+            for i in range(16):
+                self.ws.append(synth.uneven_instance(synth.CFG_UNEVEN, i))
+                log(f"operator {i + 1}/16 generated: N={self.ws[-1].N} K={self.ws[-1].K}")
             self.ops, self.B, self.alpha, self.items = [], [], [], []
             self.pert = []
             for w in self.ws:
@@ -200,6 +208,132 @@ def cpu_baseline():
             "seconds": round(dt, 2)}
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def serve_schedule(duration, rate, nops):
+    """Poisson arrivals: (arrival s, kind, operator, seed) for the serving run."""
+    import numpy as np
+    from paper_1606_00980_amd import synth
+    rng = np.random.default_rng([synth.CFG_SERVE, 6, 0])
+    t, out, i = 0.0, [], 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        out.append((t, int(rng.integers(0, 3)), int(rng.integers(0, nops)), 10_000 + i))
+        i += 1
+
+
+def main_serve(args, g, torch, ctx):
+    """24 resident uneven operators, Poisson requests (solve / sample / 16-probe
+    trace, uniform), served with continuous batching; then the same stream
+    replayed one request at a time through plain FP64 PCG."""
+    from paper_1606_00980_amd import synth
+    ws = []
+    for i in range(24):
+        ws.append(synth.uneven_instance(synth.CFG_SERVE, 100 + i))
+        log(f"operator {i + 1}/24 generated: N={ws[-1].N} K={ws[-1].K}")
+    ops, bws, keep = [], [], []
+    for w in ws:
+        op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+        B = torch.from_numpy(w.B).cuda()
+        g.gp_op_set_blocks(op, B)
+        g.gp_op_set_alpha(op, w.alpha)
+        ops.append(op)
+        bws.append(torch.from_numpy(w.bw).cuda())
+        keep.append(B)
+    sched = serve_schedule(args.duration, args.rate, len(ops))
+    cfg = g.gp_server_cfg_default(probes=16, hbm_budget=64 << 30, max_active_rhs=4096)
+    # warm-up: one request of each kind on the largest operator
+    big = max(range(len(ws)), key=lambda i: ws[i].N * ws[i].K)
+    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    for kind in range(3):
+        g.gp_server_submit(srv, kind, big, 1 + kind)
+    g.gp_server_drain(srv, 120000)
+    g.gp_server_destroy(srv)
+    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    log(f"serving {len(sched)} requests over {args.duration} s")
+    t0 = time.perf_counter()
+    for (t, kind, oi, seed) in sched:
+        now = time.perf_counter() - t0
+        if t > now:
+            time.sleep(t - now)
+        g.gp_server_submit(srv, kind, oi, seed)
+    g.gp_server_drain(srv, 600000)
+    res = g.gp_server_poll(srv, len(sched) + 16)
+    st = g.gp_server_get_stats(srv)
+    g.gp_server_destroy(srv)
+    ok = all(r["status"] == 0 and r["relres_max"] <= 1e-8 for r in res) and len(res) == len(sched)
+    out = {
+        "metric": "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency",
+        "value": round(st["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(sched), "warmup": 3, "ms_per_step": round(st["mean_us"] / 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "serve_poisson_24_uneven_operators", "rate_per_s": args.rate,
+                   "duration_s": args.duration, "requests": len(sched),
+                   "mix": "uniform over solve / Algorithm-2 sample / 16-probe trace",
+                   "N": [w.N for w in ws], "K": [w.K for w in ws], "tol": 1e-8},
+        "serving": {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+                    "mean_ms": round(st["mean_us"] / 1e3, 3), "max_ms": round(st["max_us"] / 1e3, 3),
+                    "requests_per_s": round(st["requests_per_s"], 2),
+                    "peak_active_rhs": st["peak_active_rhs"], "all_converged": ok},
+    }
+    log(f"served: p50 {st['p50_us'] / 1e3:.2f} ms, p99 {st['p99_us'] / 1e3:.2f} ms")
+    if not args.no_sequential:
+        seq = sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s=max(30.0, 2 * args.duration))
+        out["sequential_fp64"] = seq
+    print(json.dumps(out))
+    sys.stdout.flush()
+    if not ok:
+        sys.exit(1)
+
+
+def sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s):
+    """The same arrivals handled one request at a time by plain FP64 PCG
+    (block Jacobi): latency = completion - arrival, stopped after budget_s."""
+    import numpy as np
+    o = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64)
+    lat, solves, done = [], 0, 0
+    t0 = time.perf_counter()
+    for (t, kind, oi, seed) in sched:
+        now = time.perf_counter() - t0
+        if now > budget_s:
+            break
+        if t > now:
+            time.sleep(t - now)
+        w, op = ws[oi], ops[oi]
+        o.seed = seed
+        if kind == 0:
+            b = torch.empty((1, w.K, w.N), dtype=torch.float64, device="cuda")
+            g.gp_rng_normal(ctx, seed, 4, w.K * w.N, b)
+            b += bws[oi]
+            x = torch.zeros_like(b)
+            g.gp_solve(op, 1, b, x, o)
+            solves += 1
+        elif kind == 1:
+            x = torch.zeros((1, w.K, w.N), dtype=torch.float64, device="cuda")
+            g.gp_sample(op, 1, bws[oi], None, None, x, o)
+            solves += 1
+        else:
+            u = torch.empty((16, w.K, w.N), dtype=torch.float64, device="cuda")
+            g.gp_trace(op, 16, None, u, w.K, o)
+            solves += 16
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - t)
+        done += 1
+    el = time.perf_counter() - t0
+    lat.sort()
+    pct = lambda p: lat[min(len(lat) - 1, max(0, int(np.ceil(p * len(lat))) - 1))] if lat else None
+    return {"requests_done": done, "requests_offered": len(sched), "elapsed_s": round(el, 2),
+            "solves_per_s": round(solves / el, 2),
+            "p50_ms": round(1e3 * pct(0.5), 3) if lat else None,
+            "p99_ms": round(1e3 * pct(0.99), 3) if lat else None}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -211,6 +345,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     ctx = g.gp_ctx_create(0, stream, 0)
+    if args.workload == "serve":
+        main_serve(args, g, torch, ctx)
+        return
     wl = Workload(args.workload, g, torch, ctx)
     for _ in range(args.warmup):
         wl.step()
