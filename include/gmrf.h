@@ -61,6 +61,10 @@ extern "C" {
 #define GP_PRECOND_JACOBI        0  /* inverse of diag(Q)                      */
 #define GP_PRECOND_BLOCK_JACOBI  1  /* inverse of each voxel's K x K block of Q */
 
+#define GP_MATVEC_AUTO    0  /* the tuned choice, else the raster kernel        */
+#define GP_MATVEC_RASTER  1  /* one voxel per thread, neighbours via an index table */
+#define GP_MATVEC_ZMARCH  2  /* (x, y) footprints walking z, slices in LDS      */
+
 #define GP_PREC_FP64          0  /* every step in FP64                          */
 #define GP_PREC_FP32_REFINE64 1  /* FP32 inner PCG, FP64 residual/update/test   */
 
@@ -83,6 +87,7 @@ typedef struct gp_opts {
   int      rhs_tile;   /* right-hand sides per workgroup, 0 = automatic          */
   int      chunk;      /* PCG iterations enqueued between host checks, 0 = auto  */
   int      wg_per_cu;  /* persistent workgroups per compute unit, 0 = auto       */
+  int      matvec;     /* GP_MATVEC_*: inner matvec kernel, 0 = automatic        */
   uint64_t seed;       /* Philox key used when gp_sample / gp_trace are given no
                           random vectors (see gp_rng_normal)                     */
 } gp_opts;

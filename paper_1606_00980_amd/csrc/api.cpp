@@ -201,6 +201,10 @@ OpDev op_dev(const gp_op* op) {
   d.P64 = op->P64;
   d.P32 = op->P32;
   d.L64 = op->L64;
+  d.gmap = op->gmap;
+  d.nx = op->nx;
+  d.ny = op->ny;
+  d.nz = op->nz;
   d.N = op->N;
   d.K = op->K;
   d.ntiles = op->ntiles;
@@ -256,8 +260,50 @@ bool valid_opts(const gp_opts& o, std::string* why) {
   if (o.precond != GP_PRECOND_JACOBI && o.precond != GP_PRECOND_BLOCK_JACOBI)
     return *why = "unknown preconditioner", false;
   if (o.precision != GP_PREC_FP64 && o.precision != GP_PREC_FP32_REFINE64) return *why = "unknown precision", false;
+  if (o.matvec < GP_MATVEC_AUTO || o.matvec > GP_MATVEC_ZMARCH) return *why = "unknown matvec kernel", false;
   if (o.rhs_tile < 0 || o.chunk < 0 || o.wg_per_cu < 0) return *why = "rhs_tile, chunk and wg_per_cu must be >= 0", false;
   return true;
+}
+
+Plan plan_problem(const gp_op* op, int R, const gp_opts& o, int cus) {
+  Plan pl{};
+  int rc = o.rhs_tile > 0 ? o.rhs_tile : 4;
+  rc = std::max(1, std::min(std::min(rc, RCMAX), R));
+  pl.Rc = rc;
+  pl.nchunks = (R + rc - 1) / rc;
+  pl.work_count = op->ntiles * pl.nchunks;
+  pl.mv_mode = o.matvec == GP_MATVEC_ZMARCH ? 1 : 0;
+  if (pl.mv_mode) {
+    const int nxt = (op->nx + 63) / 64;
+    pl.nyt = (op->ny + 3) / 4;
+    const int zr = zm_rhs_per_block(op->K);
+    pl.mv_nchunks = (R + zr - 1) / zr;
+    // enough footprint x segment x chunk items to fill the device, segments of >= 4 slices
+    const long base = (long)nxt * pl.nyt * pl.mv_nchunks;
+    const long target = 8L * cus;
+    const int nseg_want = (int)std::max<long>(1, (target + base - 1) / base);
+    pl.zs = std::max(4, (op->nz + nseg_want - 1) / nseg_want);
+    if (const char* e = getenv("GMRF_ZSLICES")) pl.zs = std::max(1, atoi(e));
+    pl.nseg = (op->nz + pl.zs - 1) / pl.zs;
+    pl.mv_tiles = nxt * pl.nyt * pl.nseg;
+    pl.mv_count = pl.mv_tiles * pl.mv_nchunks;
+  }
+  pl.pstride = std::max(op->ntiles, pl.mv_tiles);
+  return pl;
+}
+
+void apply_plan(Prob& p, const Plan& pl) {
+  p.Rc = pl.Rc;
+  p.nchunks = pl.nchunks;
+  p.work_count = pl.work_count;
+  p.pstride = pl.pstride;
+  p.mv_mode = pl.mv_mode;
+  p.zs = pl.zs;
+  p.nseg = pl.nseg;
+  p.nyt = pl.nyt;
+  p.mv_tiles = pl.mv_tiles;
+  p.mv_nchunks = pl.mv_nchunks;
+  p.mv_count = pl.mv_count;
 }
 
 struct Item {
@@ -310,6 +356,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     size_t vec[6], st, part, prof;
   };
   std::vector<Layout> lay(np);
+  std::vector<Plan> plans(np);
+  for (int j = 0; j < np; ++j) plans[j] = plan_problem(items[order[j]].op, items[order[j]].R, o, c->cus);
   size_t off = 0;
   const size_t st_all = off;
   {
@@ -328,7 +376,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       off = align_up(off + nv * tsz, 256);
     }
     lay[j].part = off;
-    off = align_up(off + (size_t)NPART * it.R * it.op->ntiles * sizeof(double), 256);
+    off = align_up(off + (size_t)NPART * it.R * plans[j].pstride * sizeof(double), 256);
     lay[j].prof = off;
     off = align_up(off + NPROF * sizeof(long long), 256);
   }
@@ -339,7 +387,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   char* ws = (char*)c->ws;
   // descriptors, one grouped launch per distinct K
   struct Group {
-    int K, first, count, W, F, nblk;
+    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode;
   };
   std::vector<Group> groups;
   const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
@@ -361,16 +409,15 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.part = (double*)(ws + lay[j].part);
     p.prof = c->prof_on ? (long long*)(ws + lay[j].prof) : nullptr;
     p.R = it.R;
-    int rc = o.rhs_tile > 0 ? o.rhs_tile : 4;
-    rc = std::max(1, std::min(std::min(rc, RCMAX), it.R));
-    p.Rc = rc;
-    p.nchunks = (it.R + rc - 1) / rc;
-    p.work_count = it.op->ntiles * p.nchunks;
+    apply_plan(p, plans[j]);
     p.cfg = cfg;
-    if (groups.empty() || groups.back().K != it.op->K) groups.push_back(Group{it.op->K, j, 0, 0, 0, 0});
+    if (groups.empty() || groups.back().K != it.op->K)
+      groups.push_back(Group{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode});
     Group& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
+    p.mv_begin = g.Wmv;
+    g.Wmv += p.mv_count;
     p.fin_begin = g.F;
     g.F += (it.R + fpb - 1) / fpb;
     g.count += 1;
@@ -380,6 +427,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   for (Group& g : groups) {
     const int cap = std::max(8, c->cus * wpc / 8 * 8);
     g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
+    g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
   }
   hipStream_t s = c->stream;
   HIPTRY(hipMemcpyAsync(c->d_probs, c->h_probs, np * sizeof(Prob), hipMemcpyHostToDevice, s));
@@ -410,9 +458,14 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     for (int i = 0; i < iters; ++i) {
       for (const Group& g : groups) {
         const Prob* dp = c->d_probs + g.first;
-        PROFILED(c, GP_KERNEL_MATVEC,
-                 f32 ? launch_matvec_f32(q, g.K, dp, g.count, g.W, g.nblk, parity)
-                     : launch_matvec_f64(q, g.K, dp, g.count, g.W, g.nblk, parity));
+        if (g.mv_mode)
+          PROFILED(c, GP_KERNEL_MATVEC,
+                   f32 ? launch_matvec_zm_f32(q, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity)
+                       : launch_matvec_zm_f64(q, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity));
+        else
+          PROFILED(c, GP_KERNEL_MATVEC,
+                   f32 ? launch_matvec_f32(q, g.K, dp, g.count, g.W, g.nblk, parity)
+                       : launch_matvec_f64(q, g.K, dp, g.count, g.W, g.nblk, parity));
         HIPTRY(launch_finalize(q, 1, dp, g.count, g.F));
         PROFILED(c, GP_KERNEL_UPDATE,
                  f32 ? launch_update_f32(q, o.precond, g.K, dp, g.count, g.W, g.nblk, parity)
@@ -428,7 +481,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     layout_key = std::to_string((uintptr_t)c->d_probs) + (f32 ? "f" : "d") + std::to_string(o.precond);
     for (const Group& g : groups)
       layout_key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.W) + "," +
-                    std::to_string(g.F) + "," + std::to_string(g.nblk);
+                    std::to_string(g.F) + "," + std::to_string(g.nblk) + "," + std::to_string(g.mv_mode) + "," +
+                    std::to_string(g.Wmv) + "," + std::to_string(g.nblk_mv);
   }
   auto replay = [&](const std::string& key, const std::function<int(hipStream_t)>& enqueue) -> int {
     auto it = c->graphs.find(key);
@@ -576,6 +630,7 @@ void gp_opts_default(gp_opts* o) {
   o->rhs_tile = 0;
   o->chunk = 0;
   o->wg_per_cu = 0;
+  o->matvec = GP_MATVEC_AUTO;
   o->seed = 0;
 }
 
@@ -709,14 +764,15 @@ int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, in
     dev_free(c, d_mask, ncell);
     dev_free(c, d_counts, nblocks * sizeof(int));
     dev_free(c, d_offsets, (nblocks + 1) * sizeof(int));
-    dev_free(c, d_gridmap, ncell * sizeof(int));
     dev_free(c, d_edges, sizeof(unsigned long long));
   };
   do {
     if ((st = dev_alloc(c, ncell, (void**)&d_mask))) break;
     if ((st = dev_alloc(c, nblocks * sizeof(int), (void**)&d_counts))) break;
     if ((st = dev_alloc(c, (nblocks + 1) * sizeof(int), (void**)&d_offsets))) break;
-    if ((st = dev_alloc(c, ncell * sizeof(int), (void**)&d_gridmap))) break;
+    if ((st = op_alloc(op, (size_t)ncell, &d_gridmap))) break;
+    op->gmap = d_gridmap;
+    op->ncell = (size_t)ncell;
     if ((st = dev_alloc(c, sizeof(unsigned long long), (void**)&d_edges))) break;
     hipError_t e;
     if ((e = hipMemcpyAsync(d_mask, mask_host, ncell, hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -779,6 +835,7 @@ int gp_op_destroy(gp_op* op) {
   op_free(op, op->P64, NB * N);
   op_free(op, op->P32, NB * N);
   op_free(op, op->d_bad, 1);
+  op_free(op, op->gmap, op->ncell);
   op_free(op, op->tr_part, op->tr_cap);
   delete op;
   return GP_OK;

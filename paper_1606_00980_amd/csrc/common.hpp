@@ -52,7 +52,9 @@ struct OpDev {
   const double* P64;     // preconditioner: packed inverse block or inverse diagonal
   const float* P32;
   const double* L64;     // packed lower Cholesky factor of B_n
+  const int* gmap;       // [nz][ny][nx]: voxel number, or -1 outside the mask
   int N, K, ntiles, dirs;
+  int nx, ny, nz, spare;
   double alpha64[KMAX];
   float alpha32[KMAX];
 };
@@ -74,10 +76,13 @@ struct Prob {
   void* p1;
   void* q;
   RhsState* st;          // [R]
-  double* part;          // [NPART][R][ntiles]
+  double* part;          // [NPART][R][pstride]
   long long* prof;       // [NPROF] work counters, or null when not profiling
   int R, Rc, nchunks, work_begin, work_count;
   int fin_begin;         // first finalising workgroup of this problem
+  int pstride;           // partials per (value, right-hand side): max(raster, z-march tiles)
+  // z-marching matvec (mv_mode = 1): footprint tiles x segments of zs slices
+  int mv_mode, zs, nseg, nyt, mv_tiles, mv_nchunks, mv_begin, mv_count;
   SolveCfg cfg;
 };
 

@@ -41,14 +41,14 @@ __device__ inline int find_prob(const Prob* __restrict__ probs, int nprob, int w
 // fixed order (strided per lane, then a butterfly): the result depends only on
 // the operator's tiling, never on which other right-hand sides share the launch.
 template <int NV>
-__device__ inline void sum_partials(const double* part, int R, int nt, int r, double (&s)[NV]) {
+__device__ inline void sum_partials(const double* part, int R, int stride, int nt, int r, double (&s)[NV]) {
   const int lane = threadIdx.x % WAVE;
 #pragma unroll
   for (int v = 0; v < NV; ++v) s[v] = 0.0;
   const __attribute__((address_space(1))) double* g = (const __attribute__((address_space(1))) double*)part;
   for (int t = lane; t < nt; t += WAVE) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) s[v] += g[((size_t)v * R + r) * nt + t];
+    for (int v = 0; v < NV; ++v) s[v] += g[((size_t)v * R + r) * stride + t];
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) s[v] = wave_sum(s[v]);

@@ -1,6 +1,7 @@
 // Launchers of the PCG kernels with inner precision float.
 #include "launch.hpp"
 #include "pcg.hpp"
+#include "zm.hpp"
 
 namespace gp {
 
@@ -32,6 +33,26 @@ hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob,
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_matvec_zm_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity) {
+  const dim3 g(nblk), b(ZFX * ZFY);
+  switch (K) {
+#define X(KK) case KK: hipLaunchKernelGGL((k_matvec_zm<float, KK>), g, b, 0, s, probs, nprob, W, parity); break;
+    GP_K_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int zm_rhs_per_block(int K) {
+  switch (K) {
+#define X(KK) case KK: return ZRc<KK>::v;
+    GP_K_CASES(X)
+#undef X
+    default: return 1;
+  }
 }
 
 hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity) {

@@ -1,6 +1,7 @@
 // Launchers of the PCG kernels with inner precision double.
 #include "launch.hpp"
 #include "pcg.hpp"
+#include "zm.hpp"
 
 namespace gp {
 
@@ -27,6 +28,17 @@ hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob,
   const dim3 g(nblk), b(TILE);
   switch (K) {
 #define X(KK) case KK: hipLaunchKernelGGL((k_matvec<double, KK>), g, b, 0, s, probs, nprob, W, parity); break;
+    GP_K_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_matvec_zm_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity) {
+  const dim3 g(nblk), b(ZFX * ZFY);
+  switch (K) {
+#define X(KK) case KK: hipLaunchKernelGGL((k_matvec_zm<double, KK>), g, b, 0, s, probs, nprob, W, parity); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -40,6 +40,10 @@ hipError_t launch_rng_raw(hipStream_t s, uint64_t seed, uint64_t stream, size_t 
 hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
 hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_matvec_zm_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_matvec_zm_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+// right-hand sides per z-marching workgroup for K regressors
+int zm_rhs_per_block(int K);
 hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_refine_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);

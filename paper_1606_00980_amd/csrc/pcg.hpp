@@ -89,7 +89,7 @@ __device__ inline void flush_partials(const Prob& pr, const double* s_red, int r
     if (pr.st[r].phase == want_phase) {
       double t = 0.0;
       for (int j = 0; j < nw; ++j) t += s_red[(slot * NV + v) * nw + j];
-      pr.part[((size_t)v * pr.R + r) * pr.op.ntiles + tile] = t;
+      pr.part[((size_t)v * pr.R + r) * pr.pstride + tile] = t;
     }
   }
   __syncthreads();   // s_red is reused by the next work item
@@ -247,15 +247,15 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __res
   const int lane = threadIdx.x % WAVE;
   if constexpr (KIND == 0) {
     double v[3];
-    sum_partials<3>(pr.part, pr.R, pr.op.ntiles, r, v);
+    sum_partials<3>(pr.part, pr.R, pr.pstride, pr.op.ntiles, r, v);
     if (lane == 0) finalize_refine(pr, r, v);
   } else if constexpr (KIND == 1) {
     double v[1];
-    sum_partials<1>(pr.part, pr.R, pr.op.ntiles, r, v);
+    sum_partials<1>(pr.part, pr.R, pr.pstride, pr.mv_mode ? pr.mv_tiles : pr.op.ntiles, r, v);
     if (lane == 0) finalize_matvec(pr, r, v);
   } else {
     double v[2];
-    sum_partials<2>(pr.part, pr.R, pr.op.ntiles, r, v);
+    sum_partials<2>(pr.part, pr.R, pr.pstride, pr.op.ntiles, r, v);
     if (lane == 0) finalize_update(pr, r, v);
   }
 }

@@ -72,6 +72,8 @@ struct gp_op {
   double* P64 = nullptr;
   float* P32 = nullptr;
   int* d_bad = nullptr;
+  int* gmap = nullptr;      // [nz][ny][nx] voxel number or -1
+  size_t ncell = 0;
   double* tr_part = nullptr;
   size_t tr_cap = 0;
   double alpha[gp::KMAX] = {0};
@@ -97,6 +99,16 @@ struct BusyGuard {
     if (ok) c->busy.store(0);
   }
 };
+
+// Work decomposition of one problem (operator + R right-hand sides) for the
+// grouped launches: raster tiles for refine/update, and for the inner matvec
+// either the same tiles or z-marching footprints.
+struct Plan {
+  int Rc, nchunks, work_count, pstride;
+  int mv_mode, zs, nseg, nyt, mv_tiles, mv_nchunks, mv_count;
+};
+Plan plan_problem(const gp_op* op, int R, const gp_opts& o, int cus);
+void apply_plan(Prob& p, const Plan& pl);
 
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);

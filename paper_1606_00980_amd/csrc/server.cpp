@@ -87,7 +87,7 @@ struct gp_server {
   int probs_cap = 0;
   bool layout_dirty = true;
   struct Group {
-    int K, first, count, W, F, nblk;
+    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode;
   };
   std::vector<Group> groups;
   std::vector<Req*> order;   // active requests in descriptor order
@@ -107,10 +107,11 @@ int find_slots(gp_server* s, int R) {
 
 size_t request_bytes(const gp_server* s, const gp_op* op, int R, int kind) {
   const size_t nv = (size_t)R * op->K * op->N;
+  const Plan pl = plan_problem(op, R, s->cfg.opts, s->ctx->cus);
   size_t b = 0;
   b += align_up(2 * nv * sizeof(double), 256);                                     // b, x
   b += 6 * align_up(nv * s->tsz, 256);                                             // inner vectors
-  b += align_up((size_t)NPART * R * op->ntiles * sizeof(double), 256);              // partials
+  b += align_up((size_t)NPART * R * pl.pstride * sizeof(double), 256);              // partials
   if (kind == GP_REQ_SAMPLE) b += align_up((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double), 256);
   if (kind == GP_REQ_TRACE) {
     b += align_up(nv, 256);                                                         // probes
@@ -134,7 +135,8 @@ int admit(gp_server* s, Req* q) {
   q->b = (double*)take(2 * nv * sizeof(double));
   q->x = q->b + nv;
   for (int v = 0; v < 6; ++v) q->vec[v] = take(nv * s->tsz);
-  q->part = (double*)take((size_t)NPART * q->R * op->ntiles * sizeof(double));
+  q->part = (double*)take((size_t)NPART * q->R * plan_problem(op, q->R, s->cfg.opts, s->ctx->cus).pstride *
+                          sizeof(double));
   double* z = nullptr;
   if (q->r.kind == GP_REQ_SAMPLE) z = (double*)take((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double));
   if (q->r.kind == GP_REQ_TRACE) {
@@ -202,23 +204,26 @@ int rebuild_layout(gp_server* s) {
     p.part = q->part;
     p.prof = nullptr;
     p.R = q->R;
-    int rc = o.rhs_tile > 0 ? o.rhs_tile : 4;
-    rc = std::max(1, std::min(std::min(rc, RCMAX), q->R));
-    p.Rc = rc;
-    p.nchunks = (q->R + rc - 1) / rc;
-    p.work_count = q->op->ntiles * p.nchunks;
+    const Plan pl = plan_problem(q->op, q->R, o, s->ctx->cus);
+    apply_plan(p, pl);
     p.cfg = cfg;
     if (s->groups.empty() || s->groups.back().K != q->op->K)
-      s->groups.push_back(gp_server::Group{q->op->K, j, 0, 0, 0, 0});
+      s->groups.push_back(gp_server::Group{q->op->K, j, 0, 0, 0, 0, 0, 0, pl.mv_mode});
     auto& g = s->groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
+    p.mv_begin = g.Wmv;
+    g.Wmv += p.mv_count;
     p.fin_begin = g.F;
     g.F += (q->R + fpb - 1) / fpb;
     g.count += 1;
   }
   const int wpc = o.wg_per_cu > 0 ? o.wg_per_cu : 8;
-  for (auto& g : s->groups) g.nblk = std::min(std::max(8, s->ctx->cus * wpc / 8 * 8), (g.W + 7) / 8 * 8);
+  for (auto& g : s->groups) {
+    const int cap = std::max(8, s->ctx->cus * wpc / 8 * 8);
+    g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
+    g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
+  }
   HIPTRY(hipMemcpyAsync(s->d_probs, s->h_probs, s->order.size() * sizeof(Prob), hipMemcpyHostToDevice, s->stream));
   s->layout_dirty = false;
   return GP_OK;
@@ -239,8 +244,12 @@ int run_round(gp_server* s) {
   for (int i = 0; i < s->cfg.chunk; ++i) {
     for (const auto& g : s->groups) {
       const Prob* dp = s->d_probs + g.first;
-      HIPTRY(f32 ? launch_matvec_f32(st, g.K, dp, g.count, g.W, g.nblk, parity)
-                 : launch_matvec_f64(st, g.K, dp, g.count, g.W, g.nblk, parity));
+      if (g.mv_mode)
+        HIPTRY(f32 ? launch_matvec_zm_f32(st, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity)
+                   : launch_matvec_zm_f64(st, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity));
+      else
+        HIPTRY(f32 ? launch_matvec_f32(st, g.K, dp, g.count, g.W, g.nblk, parity)
+                   : launch_matvec_f64(st, g.K, dp, g.count, g.W, g.nblk, parity));
       HIPTRY(launch_finalize(st, 1, dp, g.count, g.F));
       HIPTRY(f32 ? launch_update_f32(st, pc, g.K, dp, g.count, g.W, g.nblk, parity)
                  : launch_update_f64(st, pc, g.K, dp, g.count, g.W, g.nblk, parity));

@@ -1,0 +1,217 @@
+// Z-marching variant of the PCG direction/matvec step (same arithmetic as
+// k_matvec in pcg.hpp):  p = z + beta p_old,  q = Q p,  partial p'q.
+//
+// A workgroup owns a 64 x 4 (x, y) footprint of the grid, a segment of z
+// slices and a few right-hand sides.  It walks the slices upwards: the own
+// voxel's values at z-1, z and z+1 stay in registers, the in-plane
+// neighbours come from a one-cell-halo copy of the slice in LDS, and the
+// voxel's block B_n is loaded once per slice for all of the workgroup's
+// right-hand sides.  Every vector entry is then fetched about once per
+// launch (plus the segment's two boundary slices and the halo, which the
+// neighbouring workgroups have just fetched), instead of once per neighbour
+// as in the raster kernel, whose z-neighbour slice lies beyond the L2 reuse
+// distance when many right-hand sides stream together.
+#pragma once
+#include "pcg.hpp"
+
+namespace gp {
+
+constexpr int ZFX = 64;   // footprint width: one wavefront per grid row
+constexpr int ZFY = 4;    // footprint height: four rows per workgroup
+
+// right-hand sides per z-marching workgroup
+template <int K> struct ZRc { static constexpr int v = K <= 4 ? 4 : (K <= 8 ? 2 : 1); };
+
+// Waits for this workgroup's LDS traffic and meets the other wavefronts,
+// without waiting for outstanding global loads (the prefetch of the next
+// slice stays in flight across the barrier).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+struct ZWhere {
+  int p, chunk, tile, seg, yt, xt;
+};
+
+// Work items of a problem: tile major ((xt, yt, seg)), right-hand-side chunk
+// minor, so consecutive items share the footprint's blocks in L2.
+__device__ inline ZWhere zlocate(const Prob* __restrict__ probs, int nprob, int item) {
+  ZWhere w;
+  int p = 0;
+  while (p + 1 < nprob && item >= probs[p + 1].mv_begin) ++p;
+  w.p = p;
+  const Prob& pr = probs[p];
+  int local = item - pr.mv_begin;
+  w.chunk = local % pr.mv_nchunks;
+  local /= pr.mv_nchunks;
+  w.tile = local;
+  w.seg = local % pr.nseg;
+  local /= pr.nseg;
+  w.yt = local % pr.nyt;
+  w.xt = local / pr.nyt;
+  return w;
+}
+
+template <typename T, int K>
+__global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict__ probs, int nprob, int W,
+                                                          int parity) {
+  constexpr int NB = Tri<K>::NB;
+  constexpr int RC = ZRc<K>::v;
+  constexpr int ROWS = ZFY + 2, COLS = ZFX + 2;
+  __shared__ T s_p[RC * K][ROWS][COLS];
+  __shared__ int s_n[ROWS][COLS];
+  __shared__ double s_red[RC][ZFY];
+  const int lane = threadIdx.x % ZFX, ty = threadIdx.x / ZFX;
+  for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
+    const ZWhere w = zlocate(probs, nprob, sw.item);
+    const Prob& pr = probs[w.p];
+    const OpDev& op = pr.op;
+    const int r0 = w.chunk * RC;
+    const int r1 = min(pr.R, r0 + RC);
+    if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
+    if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_MATVEC_ACT, PH_INNER);
+    const int N = op.N, nx = op.nx, ny = op.ny, nz = op.nz;
+    const bool zc = op.dirs == 3;   // 4-neighbour operators do not couple slices
+    const __attribute__((address_space(1))) int* gm = (const __attribute__((address_space(1))) int*)op.gmap;
+    bool act[RC], first[RC];
+    T beta[RC];
+    const T* zb[RC];
+    const T* pb[RC];
+    T* po[RC];
+    T* qo[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const int r = r0 + i;
+      act[i] = r < r1 && pr.st[r].phase == PH_INNER;
+      first[i] = act[i] && pr.st[r].first != 0;
+      beta[i] = act[i] ? (T)pr.st[r].beta : (T)0;
+      const size_t off = (size_t)(r < r1 ? r : r0) * K * N;
+      zb[i] = (const T*)pr.z + off;
+      pb[i] = (const T*)(parity ? pr.p1 : pr.p0) + off;
+      po[i] = (T*)(parity ? pr.p0 : pr.p1) + off;
+      qo[i] = (T*)pr.q + off;
+    }
+    // p = z + beta p_old of right-hand side i, regressor k, voxel m
+    auto pval = [&](int i, int k, int m) -> T {
+      const unsigned o = (unsigned)m * sizeof(T);
+      const T zv = ldo(zb[i] + (size_t)k * N, o);
+      return first[i] ? zv : zv + beta[i] * ldo(pb[i] + (size_t)k * N, o);
+    };
+    auto cell = [&](int xx, int yy, int zz) -> int {
+      return (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) ? gm[((size_t)zz * ny + yy) * nx + xx]
+                                                                              : -1;
+    };
+    const int x0 = w.xt * ZFX, y0 = w.yt * ZFY;
+    const int zs = w.seg * pr.zs, ze = min(nz, zs + pr.zs);
+    const int x = x0 + lane, y = y0 + ty;
+    int n_prv = cell(x, y, zs - 1), n_cur = cell(x, y, zs);
+    T v_prv[RC][K], v_cur[RC][K];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        v_prv[i][k] = (act[i] && n_prv >= 0) ? pval(i, k, n_prv) : (T)0;
+        v_cur[i][k] = (act[i] && n_cur >= 0) ? pval(i, k, n_cur) : (T)0;
+      }
+    }
+    double acc[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) acc[i] = 0.0;
+#pragma unroll 1
+    for (int z = zs; z < ze; ++z) {
+      // prefetch the own voxel one slice up (the +z neighbour of this step)
+      const int n_nxt = cell(x, y, z + 1);
+      T v_nxt[RC][K];
+#pragma unroll
+      for (int i = 0; i < RC; ++i) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v_nxt[i][k] = (act[i] && n_nxt >= 0) ? pval(i, k, n_nxt) : (T)0;
+      }
+      // the slice with a one-cell halo into LDS
+      s_n[ty + 1][lane + 1] = n_cur;
+#pragma unroll
+      for (int i = 0; i < RC; ++i) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s_p[i * K + k][ty + 1][lane + 1] = v_cur[i][k];
+      }
+      auto halo = [&](int row, int col, int xx, int yy) {
+        const int m = cell(xx, yy, z);
+        s_n[row][col] = m;
+        if (m >= 0) {
+#pragma unroll
+          for (int i = 0; i < RC; ++i) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) s_p[i * K + k][row][col] = act[i] ? pval(i, k, m) : (T)0;
+          }
+        }
+      };
+      if (ty == 0) halo(0, lane + 1, x, y0 - 1);
+      if (ty == ZFY - 1) halo(ROWS - 1, lane + 1, x, y0 + ZFY);
+      if (lane == 0) halo(ty + 1, 0, x0 - 1, y);
+      if (lane == ZFX - 1) halo(ty + 1, COLS - 1, x0 + ZFX, y);
+      lds_barrier();
+      if (n_cur >= 0) {
+        T B[NB];
+        load_soa(OpT<T>::B(op), N, n_cur, B);
+        const int nb_n[4] = {s_n[ty + 1][lane], s_n[ty + 1][lane + 2], s_n[ty][lane + 1], s_n[ty + 2][lane + 1]};
+        const unsigned o = (unsigned)n_cur * sizeof(T);
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+          if (!act[i]) continue;
+          T qv[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int pl = i * K + k;
+            const T c = v_cur[i][k];
+            T s6 = 0;
+            if (nb_n[0] >= 0) s6 += c - s_p[pl][ty + 1][lane];
+            if (nb_n[1] >= 0) s6 += c - s_p[pl][ty + 1][lane + 2];
+            if (nb_n[2] >= 0) s6 += c - s_p[pl][ty][lane + 1];
+            if (nb_n[3] >= 0) s6 += c - s_p[pl][ty + 2][lane + 1];
+            if (zc && n_prv >= 0) s6 += c - v_prv[i][k];
+            if (zc && n_nxt >= 0) s6 += c - v_nxt[i][k];
+            qv[k] = OpT<T>::alpha(op, k) * s6;
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * v_cur[i][j];
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            sto(po[i] + (size_t)k * N, o, v_cur[i][k]);
+            sto(qo[i] + (size_t)k * N, o, qv[k]);
+            acc[i] += (double)v_cur[i][k] * (double)qv[k];
+          }
+        }
+      }
+      lds_barrier();
+      n_prv = n_cur;
+      n_cur = n_nxt;
+#pragma unroll
+      for (int i = 0; i < RC; ++i) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          v_prv[i][k] = v_cur[i][k];
+          v_cur[i][k] = v_nxt[i][k];
+        }
+      }
+    }
+    // per right-hand side: wavefront butterfly, then the rows in order
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+      const double s = wave_sum(acc[i]);
+      if (lane == 0) s_red[i][ty] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < RC) {
+      const int i = threadIdx.x, r = r0 + i;
+      if (r < r1 && act[i]) {
+        double t = 0.0;
+        for (int j = 0; j < ZFY; ++j) t += s_red[i][j];
+        pr.part[((size_t)0 * pr.R + r) * pr.pstride + w.tile] = t;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace gp

@@ -29,6 +29,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "OOM", -4: "BUSY"
 
 GP_PRECOND_JACOBI = 0
 GP_PRECOND_BLOCK_JACOBI = 1
+GP_MATVEC_AUTO, GP_MATVEC_RASTER, GP_MATVEC_ZMARCH = 0, 1, 2
 GP_PREC_FP64 = 0
 GP_PREC_FP32_REFINE64 = 1
 
@@ -54,7 +55,8 @@ class GpOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("max_outer", ctypes.c_int),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rhs_tile", ctypes.c_int), ("chunk", ctypes.c_int),
-                ("wg_per_cu", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("wg_per_cu", ctypes.c_int), ("matvec", ctypes.c_int),
+                ("seed", ctypes.c_uint64)]
 
 
 class GpStats(ctypes.Structure):

@@ -145,9 +145,10 @@ def test_perturb_rhs_matches_oracle(g, ctx, torch_cuda):
         assert np.max(np.abs(b.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("matvec", ["raster", "zmarch"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("precond", ["jacobi", "block"])
-def test_small_solves_all_modes(g, ctx, torch_cuda, precision, precond):
+def test_small_solves_all_modes(g, ctx, torch_cuda, precision, precond, matvec):
     """Several tiles plus a ragged tail; R = 11 with 4 right-hand sides per workgroup."""
     w = synth.tiny((21, 19, 9), 6, 4, seed=5)
     assert w.N % 256 != 0 and w.N > 3 * 256
@@ -156,7 +157,8 @@ def test_small_solves_all_modes(g, ctx, torch_cuda, precision, precond):
     b = w.rhs(R)
     o = opts(g, tol=1e-8, rhs_tile=4,
              precond=g.GP_PRECOND_JACOBI if precond == "jacobi" else g.GP_PRECOND_BLOCK_JACOBI,
-             precision=g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64)
+             precision=g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64,
+             matvec=g.GP_MATVEC_RASTER if matvec == "raster" else g.GP_MATVEC_ZMARCH)
     bd = dev(torch_cuda, b)
     x = torch_cuda.zeros_like(bd)
     st, stats = g.gp_solve(op.h, R, bd, x, o)
@@ -469,3 +471,37 @@ def test_sample_and_trace_with_device_random_vectors(g, ctx, torch_cuda):
     t_ref, tk_ref, gk_ref, _ = orc.hutchinson(op.grid, op.Q, v)
     assert abs(t - t_ref) <= REL_ERR * abs(t_ref)
     assert np.allclose(tk, tk_ref, rtol=REL_ERR) and np.allclose(gk, gk_ref, rtol=REL_ERR)
+
+
+@pytest.mark.parametrize("zslices", [None, "1", "2", "5"])
+@pytest.mark.parametrize("K", [1, 3, 10])
+def test_zmarch_tiling_edges(g, ctx, torch_cuda, zslices, K):
+    """Footprints wider than one x tile (x halo), rows not a multiple of the
+    footprint height, z segments of 1..5 slices, 2D masks; z-march and raster
+    kernels both reach the oracle."""
+    import os
+    torch = torch_cuda
+    w = synth.tiny((70, 9, 13), 6, K, seed=22) if K != 1 else synth.tiny((70, 9, 13), 6, 1, seed=22)
+    w2 = synth.tiny((67, 11, 1), 4, 2, seed=23)
+    old = os.environ.get("GMRF_ZSLICES")
+    try:
+        if zslices is None:
+            os.environ.pop("GMRF_ZSLICES", None)
+        else:
+            os.environ["GMRF_ZSLICES"] = zslices
+        for ww in (w, w2):
+            op = Op(g, ctx, torch, ww)
+            b = ww.rhs(5)
+            bd = dev(torch, b)
+            ref = orc.solve(op.Q, b)
+            for mv in (g.GP_MATVEC_ZMARCH, g.GP_MATVEC_RASTER):
+                for prec in (g.GP_PREC_FP32_REFINE64, g.GP_PREC_FP64):
+                    x = torch.zeros_like(bd)
+                    st, stats = g.gp_solve(op.h, 5, bd, x, opts(g, tol=1e-9, matvec=mv, precision=prec))
+                    assert all(s["relres"] <= 1e-9 for s in stats)
+                    check_solutions(x.cpu().numpy(), ref, ww.K, ww.N)
+    finally:
+        if old is None:
+            os.environ.pop("GMRF_ZSLICES", None)
+        else:
+            os.environ["GMRF_ZSLICES"] = old
