@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-sequential", action="store_true",
                     help="serve: skip the sequential FP64 replay of the same stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch configuration instead of autotuning it first")
     ap.add_argument("--no-baseline-gpu", action="store_true",
                     help="skip the plain FP64 single-right-hand-side comparison run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -146,6 +148,21 @@ class Workload:
             _, self.last_stats = g.gp_solve_batch(self.ctx, self.items, self.opts, check=False)
             for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(self.pert, self.ws):
                 g.gp_trace_reduce(op, 4, v, xp, w.K)
+
+    def autotune(self):
+        """Tune the launch configuration for each (operator, right-hand-side
+        count) this workload solves; later solves pick it up."""
+        g = self.g
+        for op, B, a in zip(self.ops, self.B, self.alpha):
+            g.gp_op_set_blocks(op, B)
+            g.gp_op_set_alpha(op, a)
+        R = {"batch64": 32, "brain_fp64": 1, "uneven": 4}[self.name]
+        out = []
+        for op in self.ops:
+            b = g.gp_autotune(op, R, self.opts)
+            out.append({"rhs_tile": b.rhs_tile, "wg_per_cu": b.wg_per_cu,
+                        "matvec": "zmarch" if b.matvec == g.GP_MATVEC_ZMARCH else "raster"})
+        return out[0] if len(out) == 1 else out
 
     def config(self):
         if self.name == "uneven":
@@ -349,6 +366,10 @@ def main():
         main_serve(args, g, torch, ctx)
         return
     wl = Workload(args.workload, g, torch, ctx)
+    tuned = None
+    if not args.no_autotune:
+        tuned = wl.autotune()
+        log(f"autotuned: {tuned}")
     for _ in range(args.warmup):
         wl.step()
     torch.cuda.synchronize()
@@ -384,7 +405,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.workload == "brain_fp64" else "f32+f64",
         "data": "synthetic",
-        "config": wl.config(),
+        "config": dict(wl.config(), launch=tuned if tuned is not None else "default"),
         "roofline": roofline(prof),
         "cpu_baseline": None,
         "converged": ok,

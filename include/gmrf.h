@@ -245,6 +245,19 @@ int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u,
 int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total,
              double* tr_kk, double* tr_Gkk, const gp_opts* opts, gp_stats* stats);
 
+/* ---- autotuning -----------------------------------------------------------
+ * gp_autotune: time every launch configuration (right-hand sides per
+ * workgroup 1/2/4/8, persistent workgroups per compute unit 4/8, raster or
+ * z-marching matvec) with full solves of R random right-hand sides on this
+ * operator under *base (host; NULL = defaults), keep the fastest in the
+ * context for (K, log2 N, R rounded up to a power of two, precision,
+ * preconditioner) and copy it into *best (host, may be NULL).  Later solves
+ * whose rhs_tile / wg_per_cu / matvec are left automatic use it.  Blocking.
+ * gp_tune_save / gp_tune_load: the context's table as a JSON file.          */
+int gp_autotune(gp_op* op, int R, const gp_opts* base, gp_opts* best);
+int gp_tune_save(gp_ctx* ctx, const char* path);
+int gp_tune_load(gp_ctx* ctx, const char* path);
+
 /* ---- random vectors ----------------------------------------------------
  * Counter-based Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw,
  * SC'11), keyed by `seed` (key words = low, high 32 bits) with counter

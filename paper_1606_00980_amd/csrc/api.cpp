@@ -357,7 +357,11 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   };
   std::vector<Layout> lay(np);
   std::vector<Plan> plans(np);
-  for (int j = 0; j < np; ++j) plans[j] = plan_problem(items[order[j]].op, items[order[j]].R, o, c->cus);
+  std::vector<gp_opts> popts(np);
+  for (int j = 0; j < np; ++j) {
+    popts[j] = tuned_opts(c, items[order[j]].op, items[order[j]].R, o);
+    plans[j] = plan_problem(items[order[j]].op, items[order[j]].R, popts[j], c->cus);
+  }
   size_t off = 0;
   const size_t st_all = off;
   {
@@ -387,7 +391,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   char* ws = (char*)c->ws;
   // descriptors, one grouped launch per distinct K
   struct Group {
-    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode;
+    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode, wpc;
   };
   std::vector<Group> groups;
   const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
@@ -409,10 +413,16 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.part = (double*)(ws + lay[j].part);
     p.prof = c->prof_on ? (long long*)(ws + lay[j].prof) : nullptr;
     p.R = it.R;
+    if (!groups.empty() && groups.back().K == it.op->K && groups.back().mv_mode != plans[j].mv_mode) {
+      // one matvec kernel per grouped launch: follow the group's first problem
+      gp_opts oj = popts[j];
+      oj.matvec = groups.back().mv_mode ? GP_MATVEC_ZMARCH : GP_MATVEC_RASTER;
+      plans[j] = plan_problem(it.op, it.R, oj, c->cus);
+    }
     apply_plan(p, plans[j]);
     p.cfg = cfg;
     if (groups.empty() || groups.back().K != it.op->K)
-      groups.push_back(Group{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode});
+      groups.push_back(Group{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode, popts[j].wg_per_cu});
     Group& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
@@ -423,8 +433,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     g.count += 1;
   }
   // persistent workgroups: wg_per_cu per compute unit, a multiple of the XCD count
-  const int wpc = o.wg_per_cu > 0 ? o.wg_per_cu : 8;
   for (Group& g : groups) {
+    const int wpc = g.wpc > 0 ? g.wpc : 8;
     const int cap = std::max(8, c->cus * wpc / 8 * 8);
     g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
     g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
@@ -479,6 +489,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   std::string layout_key;
   if (graphs) {
     layout_key = std::to_string((uintptr_t)c->d_probs) + (f32 ? "f" : "d") + std::to_string(o.precond);
+    for (int j = 0; j < np; ++j) layout_key += ":" + std::to_string(plans[j].Rc);
     for (const Group& g : groups)
       layout_key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.W) + "," +
                     std::to_string(g.F) + "," + std::to_string(g.nblk) + "," + std::to_string(g.mv_mode) + "," +

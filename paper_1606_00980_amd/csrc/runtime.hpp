@@ -28,6 +28,12 @@ int fail(int code, const std::string& msg);
     if (e_ != hipSuccess) return gp::rt::fail(GP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// One autotuned launch configuration (see tune.cpp).
+struct TuneEntry {
+  int rhs_tile = 0, wg_per_cu = 0, matvec = 0;
+  double us = 0.0;
+};
+
 struct gp_ctx {
   int device = 0;
   int cus = 256;     // compute units of the device
@@ -58,6 +64,8 @@ struct gp_ctx {
   hipStream_t cap_stream = nullptr;
   std::map<std::string, hipGraphExec_t> graphs;
   bool use_graphs = true;
+  // autotuned configurations keyed by tune_key()
+  std::map<std::string, TuneEntry> tuned;
 };
 
 struct gp_op {
@@ -108,6 +116,12 @@ struct Plan {
   int mv_mode, zs, nseg, nyt, mv_tiles, mv_nchunks, mv_count;
 };
 Plan plan_problem(const gp_op* op, int R, const gp_opts& o, int cus);
+// Cache key of a tuned configuration: K, log2 N, R rounded up to a power of
+// two, precision and preconditioner.
+std::string tune_key(const gp_op* op, int R, const gp_opts& o);
+// o with its automatic (zero) launch fields filled from the context's tuned
+// entry for (op, R), when there is one.
+gp_opts tuned_opts(const gp_ctx* c, const gp_op* op, int R, const gp_opts& o);
 void apply_plan(Prob& p, const Plan& pl);
 
 int set_device(gp_ctx* c);

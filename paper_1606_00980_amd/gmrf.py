@@ -45,6 +45,7 @@ EXPORTS = [
     "gp_rng_normal", "gp_rng_rademacher", "gp_rng_raw",
     "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
+    "gp_autotune", "gp_tune_save", "gp_tune_load",
 ]
 
 GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
@@ -155,6 +156,9 @@ def _load() -> ctypes.CDLL:
         "gp_server_drain": (i32, [vp, i32]),
         "gp_server_get_stats": (i32, [vp, P(GpServerStats)]),
         "gp_server_destroy": (i32, [vp]),
+        "gp_autotune": (i32, [vp, i32, P(GpOpts), P(GpOpts)]),
+        "gp_tune_save": (i32, [vp, ctypes.c_char_p]),
+        "gp_tune_load": (i32, [vp, ctypes.c_char_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -415,3 +419,18 @@ def gp_server_get_stats(srv: int) -> dict:
 
 def gp_server_destroy(srv: int) -> None:
     _check(lib.gp_server_destroy(srv), "gp_server_destroy")
+
+
+def gp_autotune(op: int, R: int, base: GpOpts | None = None) -> GpOpts:
+    b = base if base is not None else gp_opts_default()
+    best = GpOpts()
+    _check(lib.gp_autotune(op, R, ctypes.byref(b), ctypes.byref(best)), "gp_autotune")
+    return best
+
+
+def gp_tune_save(ctx: int, path: str) -> None:
+    _check(lib.gp_tune_save(ctx, path.encode()), "gp_tune_save")
+
+
+def gp_tune_load(ctx: int, path: str) -> None:
+    _check(lib.gp_tune_load(ctx, path.encode()), "gp_tune_load")

@@ -505,3 +505,26 @@ def test_zmarch_tiling_edges(g, ctx, torch_cuda, zslices, K):
             os.environ.pop("GMRF_ZSLICES", None)
         else:
             os.environ["GMRF_ZSLICES"] = old
+
+
+def test_autotune_and_table_round_trip(g, ctx, torch_cuda, tmp_path):
+    torch = torch_cuda
+    w = synth.tiny((20, 16, 9), 6, 4, seed=24)
+    op = Op(g, ctx, torch, w)
+    best = g.gp_autotune(op.h, 6, g.gp_opts_default(tol=1e-8))
+    assert best.rhs_tile in (1, 2, 4, 8) and best.wg_per_cu in (4, 8)
+    assert best.matvec in (g.GP_MATVEC_RASTER, g.GP_MATVEC_ZMARCH)
+    path = str(tmp_path / "tune.json")
+    g.gp_tune_save(ctx, path)
+    text = open(path).read()
+    assert '"rhs_tile": %d' % best.rhs_tile in text
+    ctx2 = g.gp_ctx_create(0, torch.cuda.current_stream().cuda_stream, 0)
+    try:
+        g.gp_tune_load(ctx2, path)
+    finally:
+        g.gp_ctx_destroy(ctx2)
+    # a solve with automatic launch options now uses the tuned entry
+    b = w.rhs(6)
+    x = torch.zeros((6, w.K, w.N), dtype=torch.float64, device="cuda")
+    g.gp_solve(op.h, 6, dev(torch, b), x, opts(g, tol=1e-8))
+    check_solutions(x.cpu().numpy(), orc.solve(op.Q, b), w.K, w.N)
