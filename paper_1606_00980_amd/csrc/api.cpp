@@ -306,6 +306,63 @@ void apply_plan(Prob& p, const Plan& pl) {
   p.mv_count = pl.mv_count;
 }
 
+void size_groups(std::vector<LaunchGroup>& gs, int cus) {
+  for (LaunchGroup& g : gs) {
+    const int wpc = g.wpc > 0 ? g.wpc : 8;
+    const int cap = std::max(8, cus * wpc / 8 * 8);
+    g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
+    g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
+  }
+}
+
+#define PROFILED_IF(on, ctx, kind, launch)                    \
+  do {                                                        \
+    if (on) {                                                 \
+      PROFILED(ctx, kind, launch);                            \
+    } else {                                                  \
+      HIPTRY(launch);                                         \
+    }                                                         \
+  } while (0)
+
+int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, bool profiled) {
+  const bool pf = profiled && c->prof_on;
+  for (const LaunchGroup& g : gs) {
+    const Prob* dp = d_probs + g.first;
+    PROFILED_IF(pf, c, GP_KERNEL_ADDSOL,
+                f32 ? launch_addsol_f32(q, g.K, dp, g.count, g.W, g.nblk)
+                    : launch_addsol_f64(q, g.K, dp, g.count, g.W, g.nblk));
+    PROFILED_IF(pf, c, GP_KERNEL_REFINE,
+                f32 ? launch_refine_f32(q, pc, g.K, dp, g.count, g.W, g.nblk)
+                    : launch_refine_f64(q, pc, g.K, dp, g.count, g.W, g.nblk));
+    HIPTRY(launch_finalize(q, 0, dp, g.count, g.F));
+  }
+  return GP_OK;
+}
+
+int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, int iters, bool profiled) {
+  const bool pf = profiled && c->prof_on;
+  for (int i = 0; i < iters; ++i) {
+    for (const LaunchGroup& g : gs) {
+      const Prob* dp = d_probs + g.first;
+      if (g.mv_mode)
+        PROFILED_IF(pf, c, GP_KERNEL_MATVEC,
+                    f32 ? launch_matvec_zm_f32(q, pc, g.K, dp, g.count, g.Wmv, g.nblk_mv)
+                        : launch_matvec_zm_f64(q, pc, g.K, dp, g.count, g.Wmv, g.nblk_mv));
+      else
+        PROFILED_IF(pf, c, GP_KERNEL_MATVEC,
+                    f32 ? launch_matvec_f32(q, pc, g.K, dp, g.count, g.W, g.nblk)
+                        : launch_matvec_f64(q, pc, g.K, dp, g.count, g.W, g.nblk));
+      HIPTRY(launch_finalize(q, 1, dp, g.count, g.F));
+      PROFILED_IF(pf, c, GP_KERNEL_UPDATE,
+                  f32 ? launch_update_f32(q, pc, g.K, dp, g.count, g.W, g.nblk)
+                      : launch_update_f64(q, pc, g.K, dp, g.count, g.W, g.nblk));
+    }
+  }
+  return GP_OK;
+}
+
 struct Item {
   gp_op* op;
   int R;
@@ -353,7 +410,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // workspace layout: the states of all problems are contiguous so that one
   // copy brings every right-hand side's phase to the host
   struct Layout {
-    size_t vec[6], st, part, prof;
+    size_t vec[NVEC], st, part, prof;
   };
   std::vector<Layout> lay(np);
   std::vector<Plan> plans(np);
@@ -375,7 +432,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   for (int j = 0; j < np; ++j) {
     const Item& it = items[order[j]];
     const size_t nv = (size_t)it.R * it.op->K * it.op->N;
-    for (int v = 0; v < 6; ++v) {
+    for (int v = 0; v < NVEC; ++v) {
       lay[j].vec[v] = off;
       off = align_up(off + nv * tsz, 256);
     }
@@ -390,10 +447,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   if (st) return st;
   char* ws = (char*)c->ws;
   // descriptors, one grouped launch per distinct K
-  struct Group {
-    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode, wpc;
-  };
-  std::vector<Group> groups;
+  std::vector<LaunchGroup> groups;
   const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < np; ++j) {
@@ -405,10 +459,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     p.x = it.x;
     p.d = ws + lay[j].vec[0];
     p.r = ws + lay[j].vec[1];
-    p.z = ws + lay[j].vec[2];
-    p.p0 = ws + lay[j].vec[3];
-    p.p1 = ws + lay[j].vec[4];
-    p.q = ws + lay[j].vec[5];
+    p.p = ws + lay[j].vec[2];
+    p.q = ws + lay[j].vec[3];
     p.st = (RhsState*)(ws + lay[j].st);
     p.part = (double*)(ws + lay[j].part);
     p.prof = c->prof_on ? (long long*)(ws + lay[j].prof) : nullptr;
@@ -422,8 +474,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     apply_plan(p, plans[j]);
     p.cfg = cfg;
     if (groups.empty() || groups.back().K != it.op->K)
-      groups.push_back(Group{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode, popts[j].wg_per_cu});
-    Group& g = groups.back();
+      groups.push_back(LaunchGroup{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode, popts[j].wg_per_cu});
+    LaunchGroup& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
     p.mv_begin = g.Wmv;
@@ -432,65 +484,22 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     g.F += (it.R + fpb - 1) / fpb;
     g.count += 1;
   }
-  // persistent workgroups: wg_per_cu per compute unit, a multiple of the XCD count
-  for (Group& g : groups) {
-    const int wpc = g.wpc > 0 ? g.wpc : 8;
-    const int cap = std::max(8, c->cus * wpc / 8 * 8);
-    g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
-    g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
-  }
+  size_groups(groups, c->cus);
   hipStream_t s = c->stream;
   HIPTRY(hipMemcpyAsync(c->d_probs, c->h_probs, np * sizeof(Prob), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(ws + st_all, 0, totalR * sizeof(RhsState), s));
   for (int j = 0; j < np; ++j) HIPTRY(hipMemsetAsync(ws + lay[j].prof, 0, NPROF * sizeof(long long), s));
 
   // One round = [x += d, refine, finalise] then a chunk of inner iterations
-  // [matvec, finalise, update, finalise] x chunk.  Without profiling both are
-  // captured once per launch layout and replayed as graphs.
-  int chunk = o.chunk > 0 ? o.chunk : 6;
+  // [matvec, finalise, update] x chunk.  Without profiling both are captured
+  // once per launch layout and replayed as graphs.
+  const int chunk = o.chunk > 0 ? o.chunk : 6;
   const bool graphs = c->use_graphs && !c->prof_on;
-  if (graphs && (chunk & 1)) ++chunk;   // even chunks return the direction buffers to parity 0
-  auto enqueue_outer = [&](hipStream_t q) -> int {
-    for (const Group& g : groups) {
-      const Prob* dp = c->d_probs + g.first;
-      PROFILED(c, GP_KERNEL_ADDSOL,
-               f32 ? launch_addsol_f32(q, g.K, dp, g.count, g.W, g.nblk)
-                   : launch_addsol_f64(q, g.K, dp, g.count, g.W, g.nblk));
-      PROFILED(c, GP_KERNEL_REFINE,
-               f32 ? launch_refine_f32(q, o.precond, g.K, dp, g.count, g.W, g.nblk)
-                   : launch_refine_f64(q, o.precond, g.K, dp, g.count, g.W, g.nblk));
-      HIPTRY(launch_finalize(q, 0, dp, g.count, g.F));
-    }
-    return GP_OK;
-  };
-  int parity = 0;
-  auto enqueue_inner = [&](hipStream_t q, int iters) -> int {
-    for (int i = 0; i < iters; ++i) {
-      for (const Group& g : groups) {
-        const Prob* dp = c->d_probs + g.first;
-        if (g.mv_mode)
-          PROFILED(c, GP_KERNEL_MATVEC,
-                   f32 ? launch_matvec_zm_f32(q, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity)
-                       : launch_matvec_zm_f64(q, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity));
-        else
-          PROFILED(c, GP_KERNEL_MATVEC,
-                   f32 ? launch_matvec_f32(q, g.K, dp, g.count, g.W, g.nblk, parity)
-                       : launch_matvec_f64(q, g.K, dp, g.count, g.W, g.nblk, parity));
-        HIPTRY(launch_finalize(q, 1, dp, g.count, g.F));
-        PROFILED(c, GP_KERNEL_UPDATE,
-                 f32 ? launch_update_f32(q, o.precond, g.K, dp, g.count, g.W, g.nblk, parity)
-                     : launch_update_f64(q, o.precond, g.K, dp, g.count, g.W, g.nblk, parity));
-        HIPTRY(launch_finalize(q, 2, dp, g.count, g.F));
-      }
-      parity ^= 1;
-    }
-    return GP_OK;
-  };
   std::string layout_key;
   if (graphs) {
     layout_key = std::to_string((uintptr_t)c->d_probs) + (f32 ? "f" : "d") + std::to_string(o.precond);
     for (int j = 0; j < np; ++j) layout_key += ":" + std::to_string(plans[j].Rc);
-    for (const Group& g : groups)
+    for (const LaunchGroup& g : groups)
       layout_key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.W) + "," +
                     std::to_string(g.F) + "," + std::to_string(g.nblk) + "," + std::to_string(g.mv_mode) + "," +
                     std::to_string(g.Wmv) + "," + std::to_string(g.nblk_mv);
@@ -521,17 +530,16 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     HIPTRY(hipGraphLaunch(it->second, s));
     return GP_OK;
   };
+  const int pc = o.precond;
   auto launch_outer = [&]() -> int {
-    if (!graphs) return enqueue_outer(s);
-    return replay(layout_key + "|outer", [&](hipStream_t q) { return enqueue_outer(q); });
+    if (!graphs) return enqueue_outer(c, s, f32, pc, groups, c->d_probs, true);
+    return replay(layout_key + "|outer",
+                  [&](hipStream_t q) { return enqueue_outer(c, q, f32, pc, groups, c->d_probs, false); });
   };
   auto launch_inner = [&](int iters) -> int {
-    if (!graphs) return enqueue_inner(s, iters);
-    parity = 0;
-    const int st2 = replay(layout_key + "|inner" + std::to_string(iters),
-                           [&](hipStream_t q) { return enqueue_inner(q, iters); });
-    parity = 0;
-    return st2;
+    if (!graphs) return enqueue_inner(c, s, f32, pc, groups, c->d_probs, iters, true);
+    return replay(layout_key + "|inner" + std::to_string(iters),
+                  [&](hipStream_t q) { return enqueue_inner(c, q, f32, pc, groups, c->d_probs, iters, false); });
   };
   // host copy of every right-hand side's state
   std::vector<RhsState> hs(totalR);
@@ -605,12 +613,18 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       HIPTRY(hipMemcpy(pf.data(), ws + lay[j].prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
       const double N = it.op->N, K = it.op->K, ts = (double)tsz;
       const double NB = K * (K + 1) / 2, NP = o.precond == GP_PRECOND_JACOBI ? K : NB;
+      // algorithmic bytes: every vector entry, block and preconditioner entry
+      // a launch needs, read or written once
       prof_add(c, GP_KERNEL_REFINE, pf[PF_REFINE_RHS] * N,
                pf[PF_REFINE_RHS] * N * K * (16 + 2 * ts) + pf[PF_REFINE_ACT] * N * (NB * 8 + NP * ts));
-      prof_add(c, GP_KERNEL_ADDSOL, pf[PF_ADDSOL_RHS] * N, pf[PF_ADDSOL_RHS] * N * K * (16 + ts));
+      // x read and written; d and/or the pending step's p read
+      const double addsol_rhs = std::max(pf[PF_ADDSOL_D], pf[PF_ADDSOL_P]);
+      prof_add(c, GP_KERNEL_ADDSOL, addsol_rhs * N,
+               addsol_rhs * N * K * 16 + (pf[PF_ADDSOL_D] + pf[PF_ADDSOL_P]) * N * K * ts);
+      // p and r read, q written; blocks and preconditioner once per launch
       prof_add(c, GP_KERNEL_MATVEC, pf[PF_MATVEC_RHS] * N,
-               (pf[PF_MATVEC_RHS] - pf[PF_MATVEC_FIRST]) * N * 4 * K * ts + pf[PF_MATVEC_FIRST] * N * 3 * K * ts +
-                   pf[PF_MATVEC_ACT] * N * NB * ts);
+               pf[PF_MATVEC_RHS] * N * 3 * K * ts + pf[PF_MATVEC_ACT] * N * (NB + NP) * ts);
+      // p, q, r, d read (d not on the first step), d, r, p written
       prof_add(c, GP_KERNEL_UPDATE, pf[PF_UPDATE_RHS] * N,
                (pf[PF_UPDATE_RHS] - pf[PF_UPDATE_FRESH]) * N * 7 * K * ts + pf[PF_UPDATE_FRESH] * N * 6 * K * ts +
                    pf[PF_UPDATE_ACT] * N * NP * ts);

@@ -9,11 +9,11 @@ namespace gp {
 
 constexpr int KMAX = 16;     // largest supported number of regressors
 constexpr int TILE = 256;    // voxels per workgroup in the voxel-parallel kernels
-constexpr int NPART = 3;     // reduction values per (right-hand side, tile)
+constexpr int NPART = 7;     // reduction values per (right-hand side, tile), at most
 constexpr int NPROF = 10;    // profiling counters per problem
 // profiling counter slots (right-hand sides processed, launches with work)
 enum ProfSlot : int {
-  PF_REFINE_RHS = 0, PF_REFINE_ACT, PF_ADDSOL_RHS, PF_MATVEC_RHS, PF_MATVEC_FIRST,
+  PF_REFINE_RHS = 0, PF_REFINE_ACT, PF_ADDSOL_D, PF_ADDSOL_P, PF_MATVEC_RHS,
   PF_MATVEC_ACT, PF_UPDATE_RHS, PF_UPDATE_FRESH, PF_UPDATE_ACT,
 };
 constexpr int RCMAX = 16;    // right-hand sides per workgroup, upper bound
@@ -34,14 +34,17 @@ enum DevStatus : int { ST_OK = 0, ST_NOT_CONVERGED = -5, ST_BREAKDOWN = -6 };
 struct RhsState {
   double bnorm2;    // ||b||^2
   double rr64;      // last FP64 ||b - Qx||^2
-  double rho;       // r'z of the current inner iteration
-  double a;         // step length of the current inner iteration
-  double beta;      // direction update coefficient
+  double rho;       // r'z of the next inner iteration (three-term expansion)
+  double a;         // step length of the last inner iteration
+  double beta;      // direction update coefficient of the next iteration
   double target2;   // inner stop threshold on ||r||^2
   double relres;    // last FP64 relative residual
   double spare;
   int phase, status, inner_it, total_it;
-  int outer, has_d, first, zero_b;
+  int outer;
+  int has_d;        // the inner correction d holds a valid sum
+  int pend;         // a * p of the last iteration is still to be added to x
+  int zero_b;
 };
 
 // Device view of one operator.
@@ -71,9 +74,7 @@ struct Prob {
   double* x;             // FP64 [R][K][N]
   void* d;               // inner vectors in the inner precision, [R][K][N]
   void* r;
-  void* z;
-  void* p0;
-  void* p1;
+  void* p;
   void* q;
   RhsState* st;          // [R]
   double* part;          // [NPART][R][pstride]

@@ -473,7 +473,6 @@ hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob
   switch (kind) {
     case 0: hipLaunchKernelGGL(k_finalize<0>, g, b, 0, s, probs, nprob); break;
     case 1: hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, probs, nprob); break;
-    case 2: hipLaunchKernelGGL(k_finalize<2>, g, b, 0, s, probs, nprob); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -24,7 +24,7 @@ hipError_t launch_add_broadcast(hipStream_t s, int R, long kn, const double* bw,
 hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, const double* u,
                         double* part, double* pairbuf, double* out);
 
-// Finalising launch after a refine (kind 0), matvec (1) or update (2) launch:
+// Finalising launch after a refine (kind 0) or matvec (1) launch:
 // nblocks = sum over problems of ceil(R / finalize_rhs_per_block()).
 hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks);
 int finalize_rhs_per_block();
@@ -36,18 +36,19 @@ hipError_t launch_rng_raw(hipStream_t s, uint64_t seed, uint64_t stream, size_t 
 
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that
 // all have K regressors; W = total work items (tiles x right-hand-side chunks),
-// swept by nblk persistent workgroups (a multiple of 8, one XCD range each).
+// swept by nblk persistent workgroups (a multiple of 8, one XCD range each);
+// pc = PC_JACOBI or PC_BLOCK.
 hipError_t launch_refine_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
-hipError_t launch_matvec_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
-hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
-hipError_t launch_matvec_zm_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
-hipError_t launch_matvec_zm_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
-// right-hand sides per z-marching workgroup for K regressors
-int zm_rhs_per_block(int K);
+hipError_t launch_matvec_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_matvec_zm_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_update_f64(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_addsol_f64(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_refine_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
-hipError_t launch_matvec_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
-hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk, int parity);
+hipError_t launch_matvec_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_matvec_zm_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
+hipError_t launch_update_f32(hipStream_t s, int pc, int K, const Prob* probs, int nprob, int W, int nblk);
 hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk);
+// right-hand sides per z-marching workgroup for K regressors
+int zm_rhs_per_block(int K);
 
 }  // namespace gp

@@ -9,15 +9,24 @@
 // neighbour lies outside the mask -- the term then vanishes, which gives the
 // in-mask degree on the Laplacian diagonal (Section 2, free boundary).
 //
-// Iteration (Section 3.1: PCG until ||b - Qx|| / ||b|| <= delta), split into
-// three kernels per step so that each global reduction ends a launch:
-//   refine  (FP64)  : r64 = b - Q x, ||r64||^2, ||b||^2;  r = T(r64), z = M^{-1} r, r'z
-//   matvec  (T)     : p = z + beta p_old (p = z at the first step), q = Q p, p'q
-//   update  (T)     : d += a p, r -= a q, z = M^{-1} r, r'z, r'r
-//   addsol  (FP64)  : x += d once an inner solve has ended
-// Each of those kernels stores per-tile partial sums; a small finalising
-// kernel then reduces them per right-hand side in a fixed order and advances
-// that right-hand side's state, so no workgroup waits on another.
+// Iteration (Section 3.1: PCG until ||b - Qx|| / ||b|| <= delta), in the
+// form that needs one global reduction per inner step: the next residual's
+// norms come from three-term expansions in inner products that the matvec
+// launch already forms (D'Azevedo, Eijkhout and Romine, LAPACK Working Note
+// 56, 1993), so the direction p is built by the elementwise update and the
+// stencil gathers p alone.
+//   refine  (FP64)  : r64 = b - Q x, ||r64||^2, ||b||^2;  r = T(r64), p = M^{-1} r, r'p
+//   matvec  (T)     : q = Q p;  with z = M^{-1} r and t = M^{-1} q at the voxel:
+//                     p'q, r'z, q'z, q't, r'r, q'r, q'q
+//   finalise        : a = r'z / p'q,
+//                     rho' = r'z - 2a q'z + a^2 q't   (= r_new' M^{-1} r_new)
+//                     rr'  = r'r - 2a q'r + a^2 q'q   (= ||r_new||^2)
+//                     stop the inner solve on rr' or a cap, else beta = rho' / r'z
+//   update  (T)     : d += a p,  r -= a q,  p = M^{-1} r + beta p   (no reduction)
+//   addsol  (FP64)  : x += d (+ a p of a final step) once an inner solve has ended
+// The matvec and refine kernels store per-tile partial sums; a small
+// finalising kernel then reduces them per right-hand side in a fixed order and
+// advances that right-hand side's state, so no workgroup waits on another.
 #pragma once
 #include "device.hpp"
 
@@ -64,6 +73,78 @@ __device__ inline void precond_apply(const T (&P)[PSize<PC, K>::n], const T (&r)
     }
   }
 }
+
+// z = M^{-1} r at voxel n with the preconditioner's entries streamed from
+// memory (for K too large to hold the block in registers).
+template <typename T, int PC, int K>
+__device__ inline void precond_apply_mem(const T* __restrict__ P, int N, int n, const T (&r)[K], T (&z)[K]) {
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)P;
+  if constexpr (PC == PC_JACOBI) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = g[(size_t)k * N + (unsigned)n] * r[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int j = 0; j <= k; ++j) {
+        const T p = g[(size_t)pk(k, j) * N + (unsigned)n];
+        z[k] += p * r[j];
+        if (j != k) z[j] += p * r[k];
+      }
+    }
+  }
+}
+
+// r'M^{-1}r, q'M^{-1}r and q'M^{-1}q at voxel n, with the preconditioner's
+// entries streamed from memory (each used once, none held across the loop).
+template <typename T, int PC, int K>
+__device__ inline void precond_forms(const T* __restrict__ P, int N, int n, const T (&r)[K], const T (&q)[K],
+                                     T& rr, T& qr, T& qq) {
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)P;
+  rr = qr = qq = 0;
+  if constexpr (PC == PC_JACOBI) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const T p = g[(size_t)k * N + (unsigned)n];
+      rr += p * r[k] * r[k];
+      qr += p * q[k] * r[k];
+      qq += p * q[k] * q[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int j = 0; j <= k; ++j) {
+        const T p = g[(size_t)pk(k, j) * N + (unsigned)n];
+        if (j == k) {
+          rr += p * r[k] * r[k];
+          qr += p * q[k] * r[k];
+          qq += p * q[k] * q[k];
+        } else {
+          rr += 2 * p * r[k] * r[j];
+          qr += p * (q[k] * r[j] + q[j] * r[k]);
+          qq += 2 * p * q[k] * q[j];
+        }
+      }
+    }
+  }
+}
+
+// Blocks held in registers across a work item's right-hand sides while they
+// fit; larger K streams them per right-hand side (cache hits).
+template <int K> struct HoldB { static constexpr bool v = K <= 6; };
+// Regressors whose neighbour gathers may be in flight together in the matvec.
+template <typename T, int K> struct GatherG { static constexpr int v = (sizeof(T) == 4 && K >= 12) ? 4 : K; };
+// The update kernel holds the preconditioner in registers while it fits.
+template <typename T, int PC, int K> struct HoldP {
+  static constexpr bool v = PC == PC_JACOBI || (sizeof(T) == 4 ? K <= 12 : K <= 8);
+};
+
+// Resident-wave request of the matvec kernel: 4 per SIMD (<= 128 VGPRs) while
+// its per-voxel vectors fit, else 2.
+template <typename T, int K> struct OccMV { static constexpr int v = sizeof(T) == 4 ? (K <= 11 ? 4 : 2) : (K <= 5 ? 4 : 2); };
 
 // Per-RHS sums held in LDS: s_red[(slot * NV + v) * nwaves + wave].
 template <int NV>
@@ -162,9 +243,11 @@ __device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[
   RhsState& s = pr.st[r];
   const double rr = v[0], bb = v[1], rz = v[2];
   prof_add(pr, PF_REFINE_RHS, 1);
-  prof_add(pr, PF_ADDSOL_RHS, s.has_d);
+  prof_add(pr, PF_ADDSOL_D, s.has_d);
+  prof_add(pr, PF_ADDSOL_P, s.pend);
   if (s.outer == 0) s.bnorm2 = bb;
   s.has_d = 0;
+  s.pend = 0;
   s.outer += 1;
   s.rr64 = rr;
   const double bn2 = s.bnorm2;
@@ -188,45 +271,42 @@ __device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[
       const double ot2 = 0.25 * pr.cfg.tol * pr.cfg.tol * bn2;
       s.target2 = it2 > ot2 ? it2 : ot2;
       s.rho = rz;
-      s.first = 1;
       s.inner_it = 0;
-      s.has_d = 1;
       s.phase = PH_INNER;
     }
   }
 }
 
-__device__ inline void finalize_matvec(const Prob& pr, int r, const double (&v)[1]) {
+// v = (p'q, r'z, q'z, q't, r'r, q'r, q'q) of the step just taken.
+__device__ inline void finalize_matvec(const Prob& pr, int r, const double (&v)[7]) {
   RhsState& s = pr.st[r];
   prof_add(pr, PF_MATVEC_RHS, 1);
-  prof_add(pr, PF_MATVEC_FIRST, s.first);
-  const double sigma = v[0];
-  if (!(sigma > 0.0) || !finite(sigma)) {
-    if (s.inner_it == 0) {       // no usable correction yet
-      s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-    } else {                     // keep the correction so far; re-evaluate in FP64
-      s.phase = PH_OUTER;
+  const double sigma = v[0], rz = v[1];
+  if (!(sigma > 0.0) || !finite(sigma) || !(rz > 0.0) || !finite(rz)) {
+    if (s.inner_it == 0) {
+      s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;   // no usable correction
+    } else {
+      s.phase = PH_OUTER;   // keep the correction so far; re-evaluate in FP64
     }
-  } else {
-    s.a = s.rho / sigma;
-    s.first = 0;
+    return;
   }
-}
-
-__device__ inline void finalize_update(const Prob& pr, int r, const double (&v)[2]) {
-  RhsState& s = pr.st[r];
-  prof_add(pr, PF_UPDATE_RHS, 1);
-  prof_add(pr, PF_UPDATE_FRESH, s.inner_it == 0);
-  const double rz = v[0], rr = v[1];
+  const double a = rz / sigma;
+  const double rho = rz - 2.0 * a * v[2] + a * a * v[3];
+  const double rr = v[4] - 2.0 * a * v[5] + a * a * v[6];
+  s.a = a;
   s.inner_it += 1;
   s.total_it += 1;
-  if (!finite(rr) || !finite(rz)) {
+  if (!finite(rho) || !finite(rr) || !finite(a)) {
     s.has_d = 0; s.status = ST_BREAKDOWN; s.phase = PH_DONE;
-  } else if (rr <= s.target2 || s.total_it >= pr.cfg.max_iter || !(rz > 0.0)) {
+  } else if (rr <= s.target2 || s.total_it >= pr.cfg.max_iter || !(rho > 0.0)) {
+    s.pend = 1;             // the final step a p is added to x with d
     s.phase = PH_OUTER;
   } else {
-    s.beta = rz / s.rho;
-    s.rho = rz;
+    prof_add(pr, PF_UPDATE_RHS, 1);
+    prof_add(pr, PF_UPDATE_FRESH, s.inner_it == 1);
+    s.beta = rho / rz;
+    s.rho = rho;
+    s.has_d = 1;            // the update launch writes d
   }
 }
 
@@ -249,14 +329,10 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __res
     double v[3];
     sum_partials<3>(pr.part, pr.R, pr.pstride, pr.op.ntiles, r, v);
     if (lane == 0) finalize_refine(pr, r, v);
-  } else if constexpr (KIND == 1) {
-    double v[1];
-    sum_partials<1>(pr.part, pr.R, pr.pstride, pr.mv_mode ? pr.mv_tiles : pr.op.ntiles, r, v);
-    if (lane == 0) finalize_matvec(pr, r, v);
   } else {
-    double v[2];
-    sum_partials<2>(pr.part, pr.R, pr.pstride, pr.op.ntiles, r, v);
-    if (lane == 0) finalize_update(pr, r, v);
+    double v[7];
+    sum_partials<7>(pr.part, pr.R, pr.pstride, pr.mv_mode ? pr.mv_tiles : pr.op.ntiles, r, v);
+    if (lane == 0) finalize_matvec(pr, r, v);
   }
 }
 
@@ -343,11 +419,11 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
       for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
       if (w.valid) {
         T* rp = (T*)pr.r + (size_t)r * K * N;
-        T* zp = (T*)pr.z + (size_t)r * K * N;
+        T* pp = (T*)pr.p + (size_t)r * K * N;   // first direction p = M^{-1} r
   #pragma unroll
         for (int k = 0; k < K; ++k) {
           sto(rp + (size_t)k * N, oT, rt[k]);
-          sto(zp + (size_t)k * N, oT, z[k]);
+          sto(pp + (size_t)k * N, oT, z[k]);
         }
       } else {
         acc[0] = acc[1] = acc[2] = 0.0;
@@ -358,11 +434,11 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
   }
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(TILE, Occ<K>::inner) void k_matvec(const Prob* __restrict__ probs, int nprob, int W,
-                                                                int parity) {
+// q = Q p and the seven inner products of the step (see the header comment).
+template <typename T, int PC, int K>
+__global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* __restrict__ probs, int nprob, int W) {
   constexpr int NB = Tri<K>::NB;
-  __shared__ double s_red[RCMAX * 1 * (TILE / WAVE)];
+  __shared__ double s_red[RCMAX * NPART * (TILE / WAVE)];
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
     const Where w = locate(probs, nprob, sw.item);
     const Prob& pr = probs[w.p];
@@ -374,69 +450,77 @@ __global__ __launch_bounds__(TILE, Occ<K>::inner) void k_matvec(const Prob* __re
     if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
     unsigned o, nb[6];
     voxel_offsets<sizeof(T)>(op, w.nn, o, nb);
-    T B[NB];
-    load_soa(OpT<T>::B(op), N, w.nn, B);
+    T Bh[HoldB<K>::v ? NB : 1];
+    if constexpr (HoldB<K>::v) load_soa(OpT<T>::B(op), N, w.nn, Bh);
   #pragma unroll 1
     for (int r = r0; r < r1; ++r) {
-      const RhsState& s = pr.st[r];
-      if (s.phase != PH_INNER) continue;
-      const bool first = s.first != 0;
-      const T beta = (T)s.beta;
+      if (pr.st[r].phase != PH_INNER) continue;
       const size_t off = (size_t)r * K * N;
-      const T* zr = (const T*)pr.z + off;
-      const T* pin = (const T*)(parity ? pr.p1 : pr.p0) + off;
-      T* pout = (T*)(parity ? pr.p0 : pr.p1) + off;
-      T* qr = (T*)pr.q + off;
-      T po[K], qv[K];
-      if (first) {
-  #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const T* zk = zr + (size_t)k * N;
-          const T pc = ldo(zk, o);
-          T s6 = 0;
-  #pragma unroll
-          for (int d = 0; d < 6; ++d) s6 += pc - ldo(zk, nb[d]);
-          po[k] = pc;
-          qv[k] = OpT<T>::alpha(op, k) * s6;
-        }
-      } else {
-  #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const T* zk = zr + (size_t)k * N;
-          const T* pk_ = pin + (size_t)k * N;
-          const T pc = ldo(zk, o) + beta * ldo(pk_, o);
-          T s6 = 0;
-  #pragma unroll
-          for (int d = 0; d < 6; ++d) s6 += pc - (ldo(zk, nb[d]) + beta * ldo(pk_, nb[d]));
-          po[k] = pc;
-          qv[k] = OpT<T>::alpha(op, k) * s6;
-        }
-      }
+      const T* pp = (const T*)pr.p + off;
+      const T* rp = (const T*)pr.r + off;
+      T* qp = (T*)pr.q + off;
+      T pc[K], qv[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
+        const T* pk_ = pp + (size_t)k * N;
+        const T c = ldo(pk_, o);
+        T s6 = 0;
   #pragma unroll
-        for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * po[j];
+        for (int d = 0; d < 6; ++d) s6 += c - ldo(pk_, nb[d]);
+        pc[k] = c;
+        qv[k] = OpT<T>::alpha(op, k) * s6;
+        // bound the gathers in flight (GatherG<T, K> regressors at a time)
+        if constexpr (GatherG<T, K>::v < K)
+          if ((k + 1) % GatherG<T, K>::v == 0) __builtin_amdgcn_sched_barrier(0);
       }
-      double acc[1] = {0.0};
+      if constexpr (HoldB<K>::v) {
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+  #pragma unroll
+          for (int j = 0; j < K; ++j) qv[k] += Bh[pk(k, j)] * pc[j];
+        }
+      } else {
+        const __attribute__((address_space(1))) T* Bg = (const __attribute__((address_space(1))) T*)OpT<T>::B(op);
+  #pragma unroll
+        for (int k = 0; k < K; ++k) {
+  #pragma unroll
+          for (int j = 0; j <= k; ++j) {
+            const T bkj = Bg[(size_t)pk(k, j) * N + (unsigned)w.nn];
+            qv[k] += bkj * pc[j];
+            if (j != k) qv[j] += bkj * pc[k];
+          }
+        }
+      }
+      T rv[K];
+  #pragma unroll
+      for (int k = 0; k < K; ++k) rv[k] = ldo(rp + (size_t)k * N, o);
+      T rPr, qPr, qPq;
+      precond_forms<T, PC, K>(OpT<T>::P(op), N, w.nn, rv, qv, rPr, qPr, qPq);
+      double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (w.valid) {
   #pragma unroll
         for (int k = 0; k < K; ++k) {
-          sto(pout + (size_t)k * N, o, po[k]);
-          sto(qr + (size_t)k * N, o, qv[k]);
-          acc[0] += (double)po[k] * (double)qv[k];
+          sto(qp + (size_t)k * N, o, qv[k]);
+          const double pd = pc[k], qd = qv[k], rd = rv[k];
+          acc[0] += pd * qd;
+          acc[4] += rd * rd;
+          acc[5] += qd * rd;
+          acc[6] += qd * qd;
         }
+        acc[1] = rPr;
+        acc[2] = qPr;
+        acc[3] = qPq;
       }
-      wave_deposit<1>(s_red, r - r0, acc);
+      wave_deposit<NPART>(s_red, r - r0, acc);
     }
-    flush_partials<1>(pr, s_red, r0, r1, w.tile, PH_INNER);
+    flush_partials<NPART>(pr, s_red, r0, r1, w.tile, PH_INNER);
   }
 }
 
+// d += a p,  r -= a q,  p = M^{-1} r + beta p  for right-hand sides that go on.
 template <typename T, int PC, int K>
-__global__ __launch_bounds__(TILE, Occ<K>::inner) void k_update(const Prob* __restrict__ probs, int nprob, int W,
-                                                                int parity) {
+__global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* __restrict__ probs, int nprob, int W) {
   constexpr int NP = PSize<PC, K>::n;
-  __shared__ double s_red[RCMAX * 2 * (TILE / WAVE)];
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
     const Where w = locate(probs, nprob, sw.item);
     const Prob& pr = probs[w.p];
@@ -445,50 +529,44 @@ __global__ __launch_bounds__(TILE, Occ<K>::inner) void k_update(const Prob* __re
     if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_UPDATE_ACT, PH_INNER);
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
-    if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
-    T P[NP];
-    load_soa(OpT<T>::P(op), N, w.nn, P);
-    const unsigned o = (unsigned)w.nn * sizeof(T);
+    if (!w.valid || !any_in_phase(pr, r0, r1, PH_INNER)) continue;
+    constexpr bool hold = HoldP<T, PC, K>::v;
+    T P[hold ? NP : 1];
+    if constexpr (hold) load_soa(OpT<T>::P(op), N, w.n, P);
+    const unsigned o = (unsigned)w.n * sizeof(T);
   #pragma unroll 1
     for (int r = r0; r < r1; ++r) {
       const RhsState& s = pr.st[r];
       if (s.phase != PH_INNER) continue;
-      const T a = (T)s.a;
-      const bool fresh = s.inner_it == 0;
+      const T a = (T)s.a, beta = (T)s.beta;
+      const bool fresh = s.inner_it == 1;
       const size_t off = (size_t)r * K * N;
-      const T* pc = (const T*)(parity ? pr.p0 : pr.p1) + off;
-      const T* qr = (const T*)pr.q + off;
-      T* dr = (T*)pr.d + off;
-      T* rr = (T*)pr.r + off;
-      T* zr = (T*)pr.z + off;
-      T rv[K], dv[K], z[K];
+      T* pp = (T*)pr.p + off;
+      const T* qp = (const T*)pr.q + off;
+      T* dp = (T*)pr.d + off;
+      T* rp = (T*)pr.r + off;
+      T pv[K], rv[K], z[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
         const size_t kb = (size_t)k * N;
-        const T pk_ = ldo(pc + kb, o);
-        dv[k] = fresh ? a * pk_ : ldo(dr + kb, o) + a * pk_;
-        rv[k] = ldo(rr + kb, o) - a * ldo(qr + kb, o);
+        pv[k] = ldo(pp + kb, o);
+        const T dv = fresh ? a * pv[k] : ldo(dp + kb, o) + a * pv[k];
+        rv[k] = ldo(rp + kb, o) - a * ldo(qp + kb, o);
+        sto(dp + kb, o, dv);
+        sto(rp + kb, o, rv[k]);
       }
-      precond_apply<T, PC, K>(P, rv, z);
-      double acc[2] = {0.0, 0.0};
-      if (w.valid) {
+      if constexpr (hold)
+        precond_apply<T, PC, K>(P, rv, z);
+      else
+        precond_apply_mem<T, PC, K>(OpT<T>::P(op), N, w.n, rv, z);
   #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const size_t kb = (size_t)k * N;
-          sto(dr + kb, o, dv[k]);
-          sto(rr + kb, o, rv[k]);
-          sto(zr + kb, o, z[k]);
-          acc[0] += (double)rv[k] * (double)z[k];
-          acc[1] += (double)rv[k] * (double)rv[k];
-        }
-      }
-      wave_deposit<2>(s_red, r - r0, acc);
+      for (int k = 0; k < K; ++k) sto(pp + (size_t)k * N, o, z[k] + beta * pv[k]);
     }
-    flush_partials<2>(pr, s_red, r0, r1, w.tile, PH_INNER);
   }
 }
 
-// x += d for right-hand sides whose inner solve has ended.
+// x += d (when valid) + a p (when the last step is pending) for right-hand
+// sides whose inner solve has ended.
 template <typename T, int K>
 __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs, int nprob, int W) {
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
@@ -501,14 +579,20 @@ __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs,
     const unsigned oT = (unsigned)w.n * sizeof(T), o8 = (unsigned)w.n * 8u;
     for (int r = r0; r < r1; ++r) {
       const RhsState& s = pr.st[r];
-      if (s.phase != PH_OUTER || !s.has_d) continue;
+      if (s.phase != PH_OUTER || !(s.has_d || s.pend)) continue;
+      const bool hd = s.has_d != 0, hp = s.pend != 0;
+      const double a = s.a;
       const size_t off = (size_t)r * K * N;
       const T* dr = (const T*)pr.d + off;
+      const T* pp = (const T*)pr.p + off;
       double* xr = pr.x + off;
   #pragma unroll
       for (int k = 0; k < K; ++k) {
         const size_t kb = (size_t)k * N;
-        sto(xr + kb, o8, ldo(xr + kb, o8) + (double)ldo(dr + kb, oT));
+        double v = ldo(xr + kb, o8);
+        if (hd) v += (double)ldo(dr + kb, oT);
+        if (hp) v += a * (double)ldo(pp + kb, oT);
+        sto(xr + kb, o8, v);
       }
     }
   }

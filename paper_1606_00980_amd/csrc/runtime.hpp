@@ -124,6 +124,25 @@ std::string tune_key(const gp_op* op, int R, const gp_opts& o);
 gp_opts tuned_opts(const gp_ctx* c, const gp_op* op, int R, const gp_opts& o);
 void apply_plan(Prob& p, const Plan& pl);
 
+// One grouped launch per distinct K: problems [first, first + count) of the
+// descriptor array, W raster work items (Wmv for a z-marching matvec), F
+// finalising workgroups, nblk (nblk_mv) persistent workgroups.
+struct LaunchGroup {
+  int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode, wpc;
+};
+// Number of inner vectors (d, r, p, q) per right-hand side in the inner precision.
+constexpr int NVEC = 4;
+// Persistent workgroup counts of every group: wg_per_cu (default 8) per
+// compute unit, a multiple of the XCD count, no more than the work items.
+void size_groups(std::vector<LaunchGroup>& gs, int cus);
+// Enqueue on stream q, for every group: [x += d, refine, finalise] (the
+// outer step of a solver round), or iters x [matvec, finalise, update].
+// With `profiled` and profiling on, each launch is timed with events.
+int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, bool profiled);
+int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, int iters, bool profiled);
+
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);
 void dev_free(gp_ctx* c, void* p, size_t bytes);

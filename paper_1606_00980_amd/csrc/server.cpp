@@ -43,7 +43,7 @@ struct Req {
   char* mem = nullptr;      // one allocation holding every buffer below
   size_t bytes = 0;
   double *b = nullptr, *x = nullptr, *part = nullptr, *tr = nullptr;
-  void* vec[6] = {};
+  void* vec[NVEC] = {};
   int8_t* probes = nullptr;
   Clock::time_point t_submit, t_admit;
 };
@@ -86,10 +86,7 @@ struct gp_server {
   Prob* h_probs = nullptr;
   int probs_cap = 0;
   bool layout_dirty = true;
-  struct Group {
-    int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode;
-  };
-  std::vector<Group> groups;
+  std::vector<LaunchGroup> groups;
   std::vector<Req*> order;   // active requests in descriptor order
 };
 
@@ -110,7 +107,7 @@ size_t request_bytes(const gp_server* s, const gp_op* op, int R, int kind) {
   const Plan pl = plan_problem(op, R, s->cfg.opts, s->ctx->cus);
   size_t b = 0;
   b += align_up(2 * nv * sizeof(double), 256);                                     // b, x
-  b += 6 * align_up(nv * s->tsz, 256);                                             // inner vectors
+  b += NVEC * align_up(nv * s->tsz, 256);                                          // inner vectors
   b += align_up((size_t)NPART * R * pl.pstride * sizeof(double), 256);              // partials
   if (kind == GP_REQ_SAMPLE) b += align_up((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double), 256);
   if (kind == GP_REQ_TRACE) {
@@ -134,7 +131,7 @@ int admit(gp_server* s, Req* q) {
   };
   q->b = (double*)take(2 * nv * sizeof(double));
   q->x = q->b + nv;
-  for (int v = 0; v < 6; ++v) q->vec[v] = take(nv * s->tsz);
+  for (int v = 0; v < NVEC; ++v) q->vec[v] = take(nv * s->tsz);
   q->part = (double*)take((size_t)NPART * q->R * plan_problem(op, q->R, s->cfg.opts, s->ctx->cus).pstride *
                           sizeof(double));
   double* z = nullptr;
@@ -196,10 +193,8 @@ int rebuild_layout(gp_server* s) {
     p.x = q->x;
     p.d = q->vec[0];
     p.r = q->vec[1];
-    p.z = q->vec[2];
-    p.p0 = q->vec[3];
-    p.p1 = q->vec[4];
-    p.q = q->vec[5];
+    p.p = q->vec[2];
+    p.q = q->vec[3];
     p.st = s->d_states + q->slot0;
     p.part = q->part;
     p.prof = nullptr;
@@ -208,7 +203,7 @@ int rebuild_layout(gp_server* s) {
     apply_plan(p, pl);
     p.cfg = cfg;
     if (s->groups.empty() || s->groups.back().K != q->op->K)
-      s->groups.push_back(gp_server::Group{q->op->K, j, 0, 0, 0, 0, 0, 0, pl.mv_mode});
+      s->groups.push_back(LaunchGroup{q->op->K, j, 0, 0, 0, 0, 0, 0, pl.mv_mode, o.wg_per_cu});
     auto& g = s->groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
@@ -218,12 +213,7 @@ int rebuild_layout(gp_server* s) {
     g.F += (q->R + fpb - 1) / fpb;
     g.count += 1;
   }
-  const int wpc = o.wg_per_cu > 0 ? o.wg_per_cu : 8;
-  for (auto& g : s->groups) {
-    const int cap = std::max(8, s->ctx->cus * wpc / 8 * 8);
-    g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
-    g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
-  }
+  size_groups(s->groups, s->ctx->cus);
   HIPTRY(hipMemcpyAsync(s->d_probs, s->h_probs, s->order.size() * sizeof(Prob), hipMemcpyHostToDevice, s->stream));
   s->layout_dirty = false;
   return GP_OK;
@@ -232,33 +222,8 @@ int rebuild_layout(gp_server* s) {
 int run_round(gp_server* s) {
   hipStream_t st = s->stream;
   const int pc = s->cfg.opts.precond;
-  const bool f32 = s->f32;
-  for (const auto& g : s->groups) {
-    const Prob* dp = s->d_probs + g.first;
-    HIPTRY(f32 ? launch_addsol_f32(st, g.K, dp, g.count, g.W, g.nblk) : launch_addsol_f64(st, g.K, dp, g.count, g.W, g.nblk));
-    HIPTRY(f32 ? launch_refine_f32(st, pc, g.K, dp, g.count, g.W, g.nblk)
-               : launch_refine_f64(st, pc, g.K, dp, g.count, g.W, g.nblk));
-    HIPTRY(launch_finalize(st, 0, dp, g.count, g.F));
-  }
-  int parity = 0;
-  for (int i = 0; i < s->cfg.chunk; ++i) {
-    for (const auto& g : s->groups) {
-      const Prob* dp = s->d_probs + g.first;
-      if (g.mv_mode)
-        HIPTRY(f32 ? launch_matvec_zm_f32(st, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity)
-                   : launch_matvec_zm_f64(st, g.K, dp, g.count, g.Wmv, g.nblk_mv, parity));
-      else
-        HIPTRY(f32 ? launch_matvec_f32(st, g.K, dp, g.count, g.W, g.nblk, parity)
-                   : launch_matvec_f64(st, g.K, dp, g.count, g.W, g.nblk, parity));
-      HIPTRY(launch_finalize(st, 1, dp, g.count, g.F));
-      HIPTRY(f32 ? launch_update_f32(st, pc, g.K, dp, g.count, g.W, g.nblk, parity)
-                 : launch_update_f64(st, pc, g.K, dp, g.count, g.W, g.nblk, parity));
-      HIPTRY(launch_finalize(st, 2, dp, g.count, g.F));
-    }
-    parity ^= 1;
-  }
-  // a request's direction vectors are double-buffered by launch parity; an
-  // even chunk returns every right-hand side to buffer 0 for the next round
+  if (int e = enqueue_outer(s->ctx, st, s->f32, pc, s->groups, s->d_probs, false)) return e;
+  if (int e = enqueue_inner(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, false)) return e;
   HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
                         hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
@@ -409,8 +374,8 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
   if (cfg) c = *cfg; else gp_server_cfg_default(&c);
   std::string why;
   if (!valid_opts(c.opts, &why)) return fail(GP_ERR_INVALID_ARG, why);
-  if (c.max_active_rhs < 1 || c.chunk < 2 || (c.chunk & 1) || c.probes < 1 || c.probes > c.max_active_rhs)
-    return fail(GP_ERR_INVALID_ARG, "max_active_rhs >= 1, even chunk >= 2 and 1 <= probes <= max_active_rhs required");
+  if (c.max_active_rhs < 1 || c.chunk < 1 || c.probes < 1 || c.probes > c.max_active_rhs)
+    return fail(GP_ERR_INVALID_ARG, "max_active_rhs >= 1, chunk >= 1 and 1 <= probes <= max_active_rhs required");
   for (int i = 0; i < nops; ++i) {
     if (!ops[i] || ops[i]->ctx != ctx || !bw[i]) return fail(GP_ERR_INVALID_ARG, "operator or b_w missing");
     if (!ops[i]->have_blocks || !ops[i]->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");

@@ -1,5 +1,5 @@
-// Z-marching variant of the PCG direction/matvec step (same arithmetic as
-// k_matvec in pcg.hpp):  p = z + beta p_old,  q = Q p,  partial p'q.
+// Z-marching variant of the PCG matvec step (same arithmetic as k_matvec in
+// pcg.hpp):  q = Q p and the seven per-tile inner products of the step.
 //
 // A workgroup owns a 64 x 4 (x, y) footprint of the grid, a segment of z
 // slices and a few right-hand sides.  It walks the slices upwards: the own
@@ -50,15 +50,14 @@ __device__ inline ZWhere zlocate(const Prob* __restrict__ probs, int nprob, int 
   return w;
 }
 
-template <typename T, int K>
-__global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict__ probs, int nprob, int W,
-                                                          int parity) {
+template <typename T, int PC, int K>
+__global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict__ probs, int nprob, int W) {
   constexpr int NB = Tri<K>::NB;
   constexpr int RC = ZRc<K>::v;
   constexpr int ROWS = ZFY + 2, COLS = ZFX + 2;
   __shared__ T s_p[RC * K][ROWS][COLS];
   __shared__ int s_n[ROWS][COLS];
-  __shared__ double s_red[RC][ZFY];
+  __shared__ double s_red[RC * NPART][ZFY];
   const int lane = threadIdx.x % ZFX, ty = threadIdx.x / ZFX;
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
     const ZWhere w = zlocate(probs, nprob, sw.item);
@@ -71,29 +70,22 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
     const int N = op.N, nx = op.nx, ny = op.ny, nz = op.nz;
     const bool zc = op.dirs == 3;   // 4-neighbour operators do not couple slices
     const __attribute__((address_space(1))) int* gm = (const __attribute__((address_space(1))) int*)op.gmap;
-    bool act[RC], first[RC];
-    T beta[RC];
-    const T* zb[RC];
+    bool act[RC];
     const T* pb[RC];
-    T* po[RC];
+    const T* rb[RC];
     T* qo[RC];
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
       const int r = r0 + i;
       act[i] = r < r1 && pr.st[r].phase == PH_INNER;
-      first[i] = act[i] && pr.st[r].first != 0;
-      beta[i] = act[i] ? (T)pr.st[r].beta : (T)0;
       const size_t off = (size_t)(r < r1 ? r : r0) * K * N;
-      zb[i] = (const T*)pr.z + off;
-      pb[i] = (const T*)(parity ? pr.p1 : pr.p0) + off;
-      po[i] = (T*)(parity ? pr.p0 : pr.p1) + off;
+      pb[i] = (const T*)pr.p + off;
+      rb[i] = (const T*)pr.r + off;
       qo[i] = (T*)pr.q + off;
     }
-    // p = z + beta p_old of right-hand side i, regressor k, voxel m
+    // direction p of right-hand side i, regressor k, voxel m
     auto pval = [&](int i, int k, int m) -> T {
-      const unsigned o = (unsigned)m * sizeof(T);
-      const T zv = ldo(zb[i] + (size_t)k * N, o);
-      return first[i] ? zv : zv + beta[i] * ldo(pb[i] + (size_t)k * N, o);
+      return ldo(pb[i] + (size_t)k * N, (unsigned)m * sizeof(T));
     };
     auto cell = [&](int xx, int yy, int zz) -> int {
       return (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) ? gm[((size_t)zz * ny + yy) * nx + xx]
@@ -112,9 +104,12 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
         v_cur[i][k] = (act[i] && n_cur >= 0) ? pval(i, k, n_cur) : (T)0;
       }
     }
-    double acc[RC];
+    double acc[RC][NPART];
 #pragma unroll
-    for (int i = 0; i < RC; ++i) acc[i] = 0.0;
+    for (int i = 0; i < RC; ++i) {
+#pragma unroll
+      for (int v = 0; v < NPART; ++v) acc[i][v] = 0.0;
+    }
 #pragma unroll 1
     for (int z = zs; z < ze; ++z) {
       // prefetch the own voxel one slice up (the +z neighbour of this step)
@@ -175,12 +170,23 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
 #pragma unroll
             for (int j = 0; j < K; ++j) qv[k] += B[pk(k, j)] * v_cur[i][j];
           }
+          T rv[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) rv[k] = ldo(rb[i] + (size_t)k * N, o);
+          T rPr, qPr, qPq;
+          precond_forms<T, PC, K>(OpT<T>::P(op), N, n_cur, rv, qv, rPr, qPr, qPq);
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            sto(po[i] + (size_t)k * N, o, v_cur[i][k]);
             sto(qo[i] + (size_t)k * N, o, qv[k]);
-            acc[i] += (double)v_cur[i][k] * (double)qv[k];
+            const double pd = v_cur[i][k], qd = qv[k], rd = rv[k];
+            acc[i][0] += pd * qd;
+            acc[i][4] += rd * rd;
+            acc[i][5] += qd * rd;
+            acc[i][6] += qd * qd;
           }
+          acc[i][1] += rPr;
+          acc[i][2] += qPr;
+          acc[i][3] += qPq;
         }
       }
       lds_barrier();
@@ -195,19 +201,22 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
         }
       }
     }
-    // per right-hand side: wavefront butterfly, then the rows in order
+    // per right-hand side and value: wavefront butterfly, then the rows in order
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
-      const double s = wave_sum(acc[i]);
-      if (lane == 0) s_red[i][ty] = s;
+#pragma unroll
+      for (int v = 0; v < NPART; ++v) {
+        const double s = wave_sum(acc[i][v]);
+        if (lane == 0) s_red[i * NPART + v][ty] = s;
+      }
     }
     __syncthreads();
-    if (threadIdx.x < RC) {
-      const int i = threadIdx.x, r = r0 + i;
+    if (threadIdx.x < RC * NPART) {
+      const int i = threadIdx.x / NPART, v = threadIdx.x % NPART, r = r0 + i;
       if (r < r1 && act[i]) {
         double t = 0.0;
-        for (int j = 0; j < ZFY; ++j) t += s_red[i][j];
-        pr.part[((size_t)0 * pr.R + r) * pr.pstride + w.tile] = t;
+        for (int j = 0; j < ZFY; ++j) t += s_red[i * NPART + v][j];
+        pr.part[((size_t)v * pr.R + r) * pr.pstride + w.tile] = t;
       }
     }
     __syncthreads();
