@@ -91,12 +91,12 @@ class Workload:
                 self.bp = torch.empty((self.M, w.K, w.N), dtype=torch.float64, device="cuda")
                 self.xs = torch.zeros_like(self.bs)
                 self.xp = torch.zeros_like(self.bp)
-                self.opts = g.gp_opts_default(tol=1e-8)
+                self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
                 self.solves = self.S + self.M
             else:
                 self.b = dev(w.bw[None].copy())
                 self.x = torch.zeros_like(self.b)
-                self.opts = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64)
+                self.opts = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64, zero_guess=1)
                 self.solves = 1
         else:   # 16 uneven operators, 8 right-hand sides each (4 samples + 4 probes)
             self.ws = []
@@ -117,7 +117,7 @@ class Workload:
                 xs, xp = torch.zeros_like(bs), torch.zeros_like(bp)
                 self.pert.append((op, dev(w.bw), dev(z1), dev(z2), v, bs, bp, xs, xp))
                 self.items += [(op, 4, bs, xs), (op, 4, bp, xp)]
-            self.opts = g.gp_opts_default(tol=1e-8)
+            self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
             self.solves = 16 * 8
         self.last_stats = []
         self.trace = None
@@ -130,21 +130,16 @@ class Workload:
         if self.name == "batch64":
             g.gp_perturb_rhs(self.op, self.S, self.bw, self.z1, self.z2, self.bs)
             g.gp_probe_rhs(self.op, self.M, self.v, self.bp)
-            self.xs.zero_()
-            self.xp.zero_()
             _, self.last_stats = g.gp_solve_batch(
                 self.ctx, [(self.op, self.S, self.bs, self.xs), (self.op, self.M, self.bp, self.xp)],
                 self.opts, check=False)
             self.trace = g.gp_trace_reduce(self.op, self.M, self.v, self.xp, self.ws[0].K)
         elif self.name == "brain_fp64":
-            self.x.zero_()
             _, self.last_stats = g.gp_solve(self.op, 1, self.b, self.x, self.opts, check=False)
         else:
             for (op, bw, z1, z2, v, bs, bp, xs, xp) in self.pert:
                 g.gp_perturb_rhs(op, 4, bw, z1, z2, bs)
                 g.gp_probe_rhs(op, 4, v, bp)
-                xs.zero_()
-                xp.zero_()
             _, self.last_stats = g.gp_solve_batch(self.ctx, self.items, self.opts, check=False)
             for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(self.pert, self.ws):
                 g.gp_trace_reduce(op, 4, v, xp, w.K)

@@ -88,6 +88,9 @@ typedef struct gp_opts {
   int      chunk;      /* PCG iterations enqueued between host checks, 0 = auto  */
   int      wg_per_cu;  /* persistent workgroups per compute unit, 0 = auto       */
   int      matvec;     /* GP_MATVEC_*: inner matvec kernel, 0 = automatic        */
+  int      zero_guess; /* 1: the start value is zero -- x is not read on entry
+                          (only written), which saves a pass over it; 0: x holds
+                          the start value (default)                              */
   uint64_t seed;       /* Philox key used when gp_sample / gp_trace are given no
                           random vectors (see gp_rng_normal)                     */
 } gp_opts;

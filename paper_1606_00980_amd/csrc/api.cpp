@@ -363,6 +363,19 @@ int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
   return GP_OK;
 }
 
+int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, int chunk, bool profiled) {
+  if (!f32) {
+    if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
+    return enqueue_inner(c, q, f32, pc, gs, d_probs, chunk, profiled);
+  }
+  for (int i = 0; i < chunk; ++i) {
+    if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
+    if (int e = enqueue_inner(c, q, f32, pc, gs, d_probs, 1, profiled)) return e;
+  }
+  return GP_OK;
+}
+
 struct Item {
   gp_op* op;
   int R;
@@ -448,7 +461,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   char* ws = (char*)c->ws;
   // descriptors, one grouped launch per distinct K
   std::vector<LaunchGroup> groups;
-  const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
+  const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < np; ++j) {
     const Item& it = items[order[j]];
@@ -531,27 +544,30 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     return GP_OK;
   };
   const int pc = o.precond;
-  auto launch_outer = [&]() -> int {
-    if (!graphs) return enqueue_outer(c, s, f32, pc, groups, c->d_probs, true);
-    return replay(layout_key + "|outer",
-                  [&](hipStream_t q) { return enqueue_outer(c, q, f32, pc, groups, c->d_probs, false); });
-  };
-  auto launch_inner = [&](int iters) -> int {
-    if (!graphs) return enqueue_inner(c, s, f32, pc, groups, c->d_probs, iters, true);
-    return replay(layout_key + "|inner" + std::to_string(iters),
-                  [&](hipStream_t q) { return enqueue_inner(c, q, f32, pc, groups, c->d_probs, iters, false); });
+  // rounds of round_len iterations; with FP64 inner solves a round in which no
+  // right-hand side iterates is the outer step alone
+  int round_len = chunk;
+  auto launch_round = [&](bool outer_only) -> int {
+    if (outer_only) {
+      if (!graphs) return enqueue_outer(c, s, f32, pc, groups, c->d_probs, true);
+      return replay(layout_key + "|outer",
+                    [&](hipStream_t q) { return enqueue_outer(c, q, f32, pc, groups, c->d_probs, false); });
+    }
+    const int n = round_len;
+    if (!graphs) return enqueue_round(c, s, f32, pc, groups, c->d_probs, n, true);
+    return replay(layout_key + "|round" + std::to_string(n),
+                  [&](hipStream_t q) { return enqueue_round(c, q, f32, pc, groups, c->d_probs, n, false); });
   };
   // host copy of every right-hand side's state
   std::vector<RhsState> hs(totalR);
-  int n_outer = (int)totalR, n_inner = 0, n_done = 0;
+  int n_outer = (int)totalR, n_inner = 0;
   auto read_states = [&]() -> int {
     HIPTRY(hipMemcpyAsync(hs.data(), ws + st_all, totalR * sizeof(RhsState), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
-    n_outer = n_inner = n_done = 0;
+    n_outer = n_inner = 0;
     for (const RhsState& h : hs) {
       n_outer += h.phase == PH_OUTER;
       n_inner += h.phase == PH_INNER;
-      n_done += h.phase == PH_DONE;
     }
     return GP_OK;
   };
@@ -559,22 +575,33 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // performs a refinement step, both bounded by max_iter and max_outer.
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
-  for (;;) {
-    if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
-    if (n_outer > 0) {
-      st = launch_outer();
-      if (st) return st;
-      if (n_inner == 0) {
-        st = read_states();
-        if (st) return st;
-        if (n_inner == 0 && n_outer == 0) break;
-      }
+  // With FP32 inner solves and an automatic chunk, the next round is as long
+  // as the active right-hand sides are expected to need: per right-hand side,
+  // the iterations left in its inner solve (from the mean length of its
+  // completed ones), plus the refinement slot, plus one more inner solve when
+  // the residual after this one (about relres * inner_tol) is still above tol.
+  auto plan_round = [&]() -> int {
+    if (!f32 || o.chunk > 0) return chunk;
+    int need = 1;
+    for (const RhsState& h : hs) {
+      if (h.phase == PH_DONE) continue;
+      const bool inner = h.phase == PH_INNER;
+      const int done_solves = inner ? h.outer - 1 : h.outer;
+      if (done_solves <= 0) return chunk;   // no completed inner solve yet
+      const int est = (h.total_it - (inner ? h.inner_it : 0) + done_solves - 1) / done_solves;
+      int rem = inner ? std::max(1, est - h.inner_it) + 1 : 1;
+      if (h.relres * o.inner_tol > o.tol) rem += est;
+      need = std::max(need, rem);
     }
-    st = launch_inner(chunk);
+    return std::min(need, 2 * chunk);
+  };
+  while (n_outer > 0 || n_inner > 0) {
+    if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
+    st = launch_round(!f32 && n_inner == 0);
     if (st) return st;
     st = read_states();
     if (st) return st;
-    if (n_outer == 0 && n_inner == 0) break;
+    round_len = plan_round();
   }
   // results (hs holds the final states, in problem order)
   int ret = GP_OK;
@@ -594,7 +621,9 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     const size_t nv = (size_t)it.op->K * it.op->N;
     for (int r = 0; r < it.R; ++r) {
       const RhsState& h = hs[hpos++];
-      if (h.zero_b) HIPTRY(hipMemsetAsync(it.x + (size_t)r * nv, 0, nv * sizeof(double), s));
+      // b = 0, or a zero start value never updated (ended at the first refinement)
+      if (h.zero_b || (o.zero_guess && h.outer <= 1))
+        HIPTRY(hipMemsetAsync(it.x + (size_t)r * nv, 0, nv * sizeof(double), s));
       gp_stats& g = all[base[order[j]] + r];
       g.status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
       g.inner_iters = h.total_it;
@@ -818,6 +847,10 @@ int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, in
     op->N = (int)N;
     op->ntiles = (int)((N + TILE - 1) / TILE);
     const size_t NB = (size_t)K * (K + 1) / 2;
+    if (NB * (size_t)N * sizeof(double) > 0xFFFFFFFFull) {
+      st = fail(GP_ERR_INVALID_ARG, "K(K+1)/2 * N * 8 bytes must stay below 4 GiB (32-bit buffer offsets)");
+      break;
+    }
     if ((st = op_alloc(op, 6 * (size_t)N, &op->nbr))) break;
     if ((st = op_alloc(op, (size_t)N, &op->lin))) break;
     if ((st = op_alloc(op, NB * N, &op->B64))) break;
@@ -1106,7 +1139,7 @@ int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total
   if (int st = ensure_rhs(c, nv)) return st;
   PROFILED(c, GP_KERNEL_PROBE, launch_probe_rhs(c->stream, (long)nv, probes, c->rhs));
   prof_add(c, GP_KERNEL_PROBE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
-  HIPTRY(hipMemsetAsync(u, 0, nv * sizeof(double), c->stream));
+  o.zero_guess = 1;   // u starts at zero and is only written
   std::vector<Item> items{Item{op, m, c->rhs, u}};
   const int st = run_group(c, items, o, stats);
   if (st != GP_OK) return st;

@@ -65,6 +65,8 @@ struct OpDev {
 struct SolveCfg {
   double tol, inner_tol;
   int max_iter, max_outer;
+  int zero_guess;   // start value zero: x neither read by the first refinement nor by the first x += d
+  int spare;
 };
 
 // One member of a grouped launch: an operator with R right-hand sides.

@@ -30,6 +30,45 @@ __device__ inline int xcd_remap(int bid, int W) {
   return xcd * base + (xcd < rem ? xcd : rem) + slot;
 }
 
+// Raw buffer access: a wave-uniform descriptor (base address, size in bytes)
+// held in scalar registers, a per-lane 32-bit byte offset and a wave-uniform
+// byte offset.  Address arithmetic then stays off the vector ALU.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;   // raw buffer, 32-bit data format (gfx9)
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, size_t bytes) {
+  const unsigned n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)n, RSRC_WORD3);
+}
+template <typename T> __device__ __forceinline__ T bload(Rsrc r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ float bload<float>(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ int bload<int>(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(int, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(Rsrc r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(Rsrc r, unsigned voff, unsigned soff, double v) {
+  using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, soff, 0);
+}
+
+// A [rows][N] array (one right-hand side's [K][N] vector, or a packed [NB][N]
+// block array) of T: row i of voxel n is ld(i, n * sizeof(T)).
+template <typename T> struct Slab {
+  Rsrc rs;
+  unsigned row;   // N * sizeof(T), the byte stride of a row
+  __device__ __forceinline__ Slab(const void* base, int rows, int N)
+      : rs(make_rsrc(base, (size_t)rows * N * sizeof(T))), row((unsigned)N * (unsigned)sizeof(T)) {}
+  __device__ __forceinline__ T ld(int i, unsigned voff) const { return bload<T>(rs, voff, (unsigned)i * row); }
+  __device__ __forceinline__ void st(int i, unsigned voff, T v) const { bstore(rs, voff, (unsigned)i * row, v); }
+};
+
 // Which problem of a grouped launch owns work item w.
 __device__ inline int find_prob(const Prob* __restrict__ probs, int nprob, int w) {
   int p = 0;

@@ -58,6 +58,12 @@ __device__ inline void load_soa(const T* __restrict__ A, int N, int n, T (&a)[NV
   for (int i = 0; i < NV; ++i) a[i] = g[(size_t)i * N + (unsigned)n];
 }
 
+template <typename T, int NV>
+__device__ inline void load_soa(const Slab<T>& A, unsigned voff, T (&a)[NV]) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a[i] = A.ld(i, voff);
+}
+
 template <typename T, int PC, int K>
 __device__ inline void precond_apply(const T (&P)[PSize<PC, K>::n], const T (&r)[K], T (&z)[K]) {
   if constexpr (PC == PC_JACOBI) {
@@ -77,11 +83,10 @@ __device__ inline void precond_apply(const T (&P)[PSize<PC, K>::n], const T (&r)
 // z = M^{-1} r at voxel n with the preconditioner's entries streamed from
 // memory (for K too large to hold the block in registers).
 template <typename T, int PC, int K>
-__device__ inline void precond_apply_mem(const T* __restrict__ P, int N, int n, const T (&r)[K], T (&z)[K]) {
-  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)P;
+__device__ inline void precond_apply_mem(const Slab<T>& P, unsigned voff, const T (&r)[K], T (&z)[K]) {
   if constexpr (PC == PC_JACOBI) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) z[k] = g[(size_t)k * N + (unsigned)n] * r[k];
+    for (int k = 0; k < K; ++k) z[k] = P.ld(k, voff) * r[k];
   } else {
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = 0;
@@ -89,7 +94,7 @@ __device__ inline void precond_apply_mem(const T* __restrict__ P, int N, int n, 
     for (int k = 0; k < K; ++k) {
 #pragma unroll
       for (int j = 0; j <= k; ++j) {
-        const T p = g[(size_t)pk(k, j) * N + (unsigned)n];
+        const T p = P.ld(pk(k, j), voff);
         z[k] += p * r[j];
         if (j != k) z[j] += p * r[k];
       }
@@ -100,43 +105,70 @@ __device__ inline void precond_apply_mem(const T* __restrict__ P, int N, int n, 
 // r'M^{-1}r, q'M^{-1}r and q'M^{-1}q at voxel n, with the preconditioner's
 // entries streamed from memory (each used once, none held across the loop).
 template <typename T, int PC, int K>
-__device__ inline void precond_forms(const T* __restrict__ P, int N, int n, const T (&r)[K], const T (&q)[K],
-                                     T& rr, T& qr, T& qq) {
-  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)P;
+__device__ inline void precond_forms(const Slab<T>& P, unsigned voff, const T (&r)[K], const T (&q)[K], T& rr,
+                                     T& qr, T& qq) {
   rr = qr = qq = 0;
   if constexpr (PC == PC_JACOBI) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const T p = g[(size_t)k * N + (unsigned)n];
+      const T p = P.ld(k, voff);
       rr += p * r[k] * r[k];
       qr += p * q[k] * r[k];
       qq += p * q[k] * q[k];
     }
   } else {
+    // u = M^{-1} r and v = M^{-1} q from the packed symmetric block, each
+    // entry loaded once; then r'u, q'u and q'v
+    T u[K], v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = v[k] = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
       for (int j = 0; j <= k; ++j) {
-        const T p = g[(size_t)pk(k, j) * N + (unsigned)n];
-        if (j == k) {
-          rr += p * r[k] * r[k];
-          qr += p * q[k] * r[k];
-          qq += p * q[k] * q[k];
-        } else {
-          rr += 2 * p * r[k] * r[j];
-          qr += p * (q[k] * r[j] + q[j] * r[k]);
-          qq += 2 * p * q[k] * q[j];
+        const T p = P.ld(pk(k, j), voff);
+        u[k] += p * r[j];
+        v[k] += p * q[j];
+        if (j != k) {
+          u[j] += p * r[k];
+          v[j] += p * q[k];
         }
       }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rr += r[k] * u[k];
+      qr += q[k] * u[k];
+      qq += q[k] * v[k];
     }
   }
 }
 
-// Blocks held in registers across a work item's right-hand sides while they
-// fit; larger K streams them per right-hand side (cache hits).
+// The same forms from a preconditioner block held in registers.
+template <typename T, int PC, int K>
+__device__ inline void precond_forms_reg(const T (&P)[PSize<PC, K>::n], const T (&r)[K], const T (&q)[K], T& rr,
+                                         T& qr, T& qq) {
+  T u[K], v[K];
+  precond_apply<T, PC, K>(P, r, u);
+  precond_apply<T, PC, K>(P, q, v);
+  rr = qr = qq = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    rr += r[k] * u[k];
+    qr += q[k] * u[k];
+    qq += q[k] * v[k];
+  }
+}
+
+// Blocks (and, in the matvec, the preconditioner) held in registers across a
+// work item's right-hand sides while they fit; larger K streams them per
+// right-hand side (cache hits).
 template <int K> struct HoldB { static constexpr bool v = K <= 6; };
 // Regressors whose neighbour gathers may be in flight together in the matvec.
 template <typename T, int K> struct GatherG { static constexpr int v = (sizeof(T) == 4 && K >= 12) ? 4 : K; };
+// The refine kernel holds the FP64 block and the preconditioner in registers
+// across a work item's right-hand sides while they fit.
+template <typename T, int K> struct HoldRefine { static constexpr bool v = K <= 6; };
 // The update kernel holds the preconditioner in registers while it fits.
 template <typename T, int PC, int K> struct HoldP {
   static constexpr bool v = PC == PC_JACOBI || (sizeof(T) == 4 ? K <= 12 : K <= 8);
@@ -144,17 +176,39 @@ template <typename T, int PC, int K> struct HoldP {
 
 // Resident-wave request of the matvec kernel: 4 per SIMD (<= 128 VGPRs) while
 // its per-voxel vectors fit, else 2.
-template <typename T, int K> struct OccMV { static constexpr int v = sizeof(T) == 4 ? (K <= 11 ? 4 : 2) : (K <= 5 ? 4 : 2); };
+template <typename T, int K> struct OccMV { static constexpr int v = sizeof(T) == 4 ? (K <= 10 ? 4 : 2) : (K <= 5 ? 4 : 2); };
 
 // Per-RHS sums held in LDS: s_red[(slot * NV + v) * nwaves + wave].
+// The NV values are summed over the wavefront together: M halving exchanges
+// (distances 32, 16, ... for the next power of two 2^M >= NV) leave every lane
+// with a partial of value lane >> (6 - M), and a butterfly over the remaining
+// distances completes it.  The order of the additions is fixed.
 template <int NV>
 __device__ inline void wave_deposit(double* s_red, int slot, const double (&acc)[NV]) {
-  const int wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  constexpr int M = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : 3;
+  constexpr int NP = 1 << M;
+  static_assert(NV <= 8, "at most 8 values per deposit");
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  double a[NP];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double s = wave_sum(acc[v]);
-    if ((threadIdx.x % WAVE) == 0) s_red[(slot * NV + v) * nw + wv] = s;
+  for (int i = 0; i < NP; ++i) a[i] = i < NV ? acc[i] : 0.0;
+#pragma unroll
+  for (int st = 0; st < M; ++st) {
+    const int dist = 32 >> st;
+    const int half = NP >> (st + 1);
+    const bool hi = (lane & dist) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double keep = hi ? a[i + half] : a[i];
+      const double send = hi ? a[i] : a[i + half];
+      a[i] = keep + __shfl_xor(send, dist, WAVE);
+    }
   }
+  double e = a[0];
+#pragma unroll
+  for (int dist = 32 >> M; dist > 0; dist >>= 1) e += __shfl_xor(e, dist, WAVE);
+  const int idx = lane >> (6 - M);
+  if ((lane & ((64 >> M) - 1)) == 0 && idx < NV) s_red[(slot * NV + idx) * nw + wv] = e;
 }
 
 // After the right-hand-side loop: one store per (active RHS, value) of the
@@ -170,7 +224,7 @@ __device__ inline void flush_partials(const Prob& pr, const double* s_red, int r
     if (pr.st[r].phase == want_phase) {
       double t = 0.0;
       for (int j = 0; j < nw; ++j) t += s_red[(slot * NV + v) * nw + j];
-      pr.part[((size_t)v * pr.R + r) * pr.pstride + tile] = t;
+      *(__attribute__((address_space(1))) double*)&pr.part[((size_t)v * pr.R + r) * pr.pstride + tile] = t;
     }
   }
   __syncthreads();   // s_red is reused by the next work item
@@ -199,15 +253,25 @@ __device__ inline Sweep sweep_begin(int W) {
   return Sweep{start + slot, start + cnt, (int)(gridDim.x / NXCD)};
 }
 
-// Work items of a problem are ordered right-hand-side chunk major, tile minor.
+// Work items of a problem: the voxel tiles are cut into NXCD contiguous
+// blocks (slabs of slices, the voxels being numbered slice by slice); items
+// run block major, then right-hand-side chunk, then tile.  With the sweep
+// above, each XCD then owns about one block for every chunk: the block's
+// matrices and preconditioner stay in that XCD's L2 across all chunks, and the
+// stencil's z-neighbours lie in the same block except at its two faces.
 __device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int item) {
   Where w;
   w.p = find_prob(probs, nprob, item);
-  const int local = item - probs[w.p].work_begin;
-  const int nt = probs[w.p].op.ntiles;
-  w.chunk = local / nt;
-  w.tile = local - w.chunk * nt;
-  const int N = probs[w.p].op.N;
+  const Prob& pr = probs[w.p];
+  const int local = item - pr.work_begin;
+  const int nt = pr.op.ntiles, nc = pr.nchunks;
+  const int tb = (nt + NXCD - 1) / NXCD;          // tiles per block
+  const int b = local / (nc * tb);
+  const int j = local - b * nc * tb;
+  const int ntb = min(tb, nt - b * tb);           // tiles in block b (the last may be short)
+  w.chunk = j / ntb;
+  w.tile = b * tb + (j - w.chunk * ntb);
+  const int N = pr.op.N;
   w.n = w.tile * TILE + (int)threadIdx.x;
   w.valid = w.n < N;
   w.nn = w.valid ? w.n : N - 1;
@@ -337,28 +401,89 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_finalize(const Prob* __res
 }
 
 // ------------------------------------------------------------------ kernels
-// Addressing: every vector access is a wave-uniform base pointer (the slab of
-// one right-hand side and regressor) plus a 32-bit per-lane byte offset, so
-// loads take the scalar-base form and no 64-bit address is kept per lane.
-// Pointers held in the problem descriptors are generic; the casts to the
-// global address space let the compiler emit global (not flat) accesses.
-#define GP_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ T ldo(const T* base, unsigned off) {
-  return *(const GP_GLOBAL T*)((const GP_GLOBAL char*)base + off);
-}
-template <typename T>
-__device__ __forceinline__ void sto(T* base, unsigned off, T v) {
-  *(GP_GLOBAL T*)((GP_GLOBAL char*)base + off) = v;
+// Addressing: every array is read through a buffer descriptor (Slab): the
+// voxel's byte offset is the per-lane operand, the regressor (or packed
+// block entry) row is a wave-uniform scalar offset.
+
+// Byte offsets of the six neighbours of voxel nn for element size S.
+template <int S>
+__device__ __forceinline__ void voxel_offsets(const OpDev& op, int nn, unsigned (&nb)[6]) {
+  const Slab<int> nbr(op.nbr, 6, op.N);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nb[d] = (unsigned)nbr.ld(d, (unsigned)nn * 4u) * S;
 }
 
-// Byte offsets of the voxel and its six neighbours for element size S.
-template <int S>
-__device__ __forceinline__ void voxel_offsets(const OpDev& op, int nn, unsigned& own, unsigned (&nb)[6]) {
-  own = (unsigned)nn * S;
-  const __attribute__((address_space(1))) int* g = (const __attribute__((address_space(1))) int*)op.nbr;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) nb[d] = (unsigned)g[(size_t)d * op.N + (unsigned)nn] * S;
+// y += S x for a symmetric K x K block S given by its packed entries
+// s(i) = S[k][j], i = pk(k, j), each read once.
+template <int K, typename V, typename GetS>
+__device__ __forceinline__ void sym_apply(const GetS& s, const V (&x)[K], V (&y)[K]) {
+  #pragma unroll
+  for (int k = 0; k < K; ++k) {
+  #pragma unroll
+    for (int j = 0; j <= k; ++j) {
+      const V v = s(pk(k, j));
+      y[k] += v * x[j];
+      if (j != k) y[j] += v * x[k];
+    }
+  }
+}
+
+// Refinement of right-hand side r at voxel w.nn: r64 = b - Q x (Q x = 0 for a
+// zero start value), r = T(r64), p = M^{-1} r; acc = (||r64||^2, ||b||^2, r'p).
+// getB(i), getP(i): packed entry i of the voxel's FP64 block and preconditioner.
+template <typename T, int PC, int K, typename GetB, typename GetP>
+__device__ __forceinline__ void refine_rhs(const Prob& pr, const Where& w, int r, bool x0, const unsigned (&nb8)[6],
+                                           const GetB& getB, const GetP& getP, double (&acc)[3]) {
+  const OpDev& op = pr.op;
+  const int N = op.N;
+  const unsigned o8 = (unsigned)w.nn * 8u, oT = (unsigned)w.nn * sizeof(T);
+  const size_t off = (size_t)r * K * N;
+  const Slab<double> xs(pr.x + off, K, N), bs(pr.b + off, K, N);
+  double y[K];
+  #pragma unroll
+  for (int k = 0; k < K; ++k) y[k] = 0.0;
+  if (!x0) {
+    double xo[K];
+  #pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double xc = xs.ld(k, o8);
+      double s6 = 0.0;
+  #pragma unroll
+      for (int d = 0; d < 6; ++d) s6 += xc - xs.ld(k, nb8[d]);
+      xo[k] = xc;
+      y[k] = op.alpha64[k] * s6;
+    }
+    sym_apply<K>(getB, xo, y);
+  }
+  acc[0] = acc[1] = acc[2] = 0.0;
+  T rt[K], z[K];
+  #pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double bk = bs.ld(k, o8);
+    const double rk = bk - y[k];
+    acc[0] += rk * rk;
+    acc[1] += bk * bk;
+    rt[k] = (T)rk;
+    z[k] = 0;
+  }
+  if constexpr (PC == PC_JACOBI) {
+  #pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = getP(k) * rt[k];
+  } else {
+    sym_apply<K>(getP, rt, z);
+  }
+  #pragma unroll
+  for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
+  if (w.valid) {
+    const Slab<T> rs((T*)pr.r + off, K, N), ps((T*)pr.p + off, K, N);   // first direction p = M^{-1} r
+  #pragma unroll
+    for (int k = 0; k < K; ++k) {
+      rs.st(k, oT, rt[k]);
+      ps.st(k, oT, z[k]);
+    }
+  } else {
+    acc[0] = acc[1] = acc[2] = 0.0;
+  }
 }
 
 template <typename T, int PC, int K>
@@ -374,61 +499,38 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!any_in_phase(pr, r0, r1, PH_OUTER)) continue;
-    unsigned o8, nb8[6];
-    voxel_offsets<8>(op, w.nn, o8, nb8);
-    const unsigned oT = (unsigned)w.nn * sizeof(T);
-  #pragma unroll 1
-    for (int r = r0; r < r1; ++r) {
-      if (pr.st[r].phase != PH_OUTER) continue;
-      // the voxel's FP64 block and preconditioner are re-read per right-hand
-      // side (cache hits) rather than held in registers across the loop
+    unsigned nb8[6];
+    voxel_offsets<8>(op, w.nn, nb8);
+    const unsigned o8 = (unsigned)w.nn * 8u, oT = (unsigned)w.nn * sizeof(T);
+    const Slab<double> Bs(op.B64, NB, N);
+    const Slab<T> Ps(OpT<T>::P(op), NP, N);
+    if constexpr (HoldRefine<T, K>::v) {
+      // the voxel's FP64 block and preconditioner, in registers across the
+      // work item's right-hand sides
       double B[NB];
-      load_soa(op.B64, N, w.nn, B);
       T P[NP];
-      load_soa(OpT<T>::P(op), N, w.nn, P);
-      const double* xr = pr.x + (size_t)r * K * N;
-      const double* br = pr.b + (size_t)r * K * N;
-      double xo[K], y[K];
-  #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double* xk = xr + (size_t)k * N;
-        const double xc = ldo(xk, o8);
-        double s6 = 0.0;
-  #pragma unroll
-        for (int d = 0; d < 6; ++d) s6 += xc - ldo(xk, nb8[d]);
-        xo[k] = xc;
-        y[k] = op.alpha64[k] * s6;
+      load_soa(Bs, o8, B);
+      load_soa(Ps, oT, P);
+      const auto getB = [&](int i) { return B[i]; };
+      const auto getP = [&](int i) { return P[i]; };
+  #pragma unroll 1
+      for (int r = r0; r < r1; ++r) {
+        if (pr.st[r].phase != PH_OUTER) continue;
+        double acc[3];
+        refine_rhs<T, PC, K>(pr, w, r, pr.cfg.zero_guess && pr.st[r].outer == 0, nb8, getB, getP, acc);
+        wave_deposit<3>(s_red, r - r0, acc);
       }
-  #pragma unroll
-      for (int k = 0; k < K; ++k) {
-  #pragma unroll
-        for (int j = 0; j < K; ++j) y[k] += B[pk(k, j)] * xo[j];
+    } else {
+      // streamed per right-hand side (cache hits)
+      const auto getB = [&](int i) { return Bs.ld(i, o8); };
+      const auto getP = [&](int i) { return Ps.ld(i, oT); };
+  #pragma unroll 1
+      for (int r = r0; r < r1; ++r) {
+        if (pr.st[r].phase != PH_OUTER) continue;
+        double acc[3];
+        refine_rhs<T, PC, K>(pr, w, r, pr.cfg.zero_guess && pr.st[r].outer == 0, nb8, getB, getP, acc);
+        wave_deposit<3>(s_red, r - r0, acc);
       }
-      double acc[3] = {0.0, 0.0, 0.0};
-      T rt[K], z[K];
-  #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double bk = ldo(br + (size_t)k * N, o8);
-        const double rk = bk - y[k];
-        acc[0] += rk * rk;
-        acc[1] += bk * bk;
-        rt[k] = (T)rk;
-      }
-      precond_apply<T, PC, K>(P, rt, z);
-  #pragma unroll
-      for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)z[k];
-      if (w.valid) {
-        T* rp = (T*)pr.r + (size_t)r * K * N;
-        T* pp = (T*)pr.p + (size_t)r * K * N;   // first direction p = M^{-1} r
-  #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          sto(rp + (size_t)k * N, oT, rt[k]);
-          sto(pp + (size_t)k * N, oT, z[k]);
-        }
-      } else {
-        acc[0] = acc[1] = acc[2] = 0.0;
-      }
-      wave_deposit<3>(s_red, r - r0, acc);
     }
     flush_partials<3>(pr, s_red, r0, r1, w.tile, PH_OUTER);
   }
@@ -437,7 +539,7 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
 // q = Q p and the seven inner products of the step (see the header comment).
 template <typename T, int PC, int K>
 __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* __restrict__ probs, int nprob, int W) {
-  constexpr int NB = Tri<K>::NB;
+  constexpr int NB = Tri<K>::NB, NP = PSize<PC, K>::n;
   __shared__ double s_red[RCMAX * NPART * (TILE / WAVE)];
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
     const Where w = locate(probs, nprob, sw.item);
@@ -448,25 +550,27 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
-    unsigned o, nb[6];
-    voxel_offsets<sizeof(T)>(op, w.nn, o, nb);
-    T Bh[HoldB<K>::v ? NB : 1];
-    if constexpr (HoldB<K>::v) load_soa(OpT<T>::B(op), N, w.nn, Bh);
+    unsigned nb[6];
+    voxel_offsets<sizeof(T)>(op, w.nn, nb);
+    const unsigned o = (unsigned)w.nn * sizeof(T);
+    const Slab<T> Bs(OpT<T>::B(op), NB, N), Ps(OpT<T>::P(op), NP, N);
+    T Bh[HoldB<K>::v ? NB : 1], Ph[HoldB<K>::v ? NP : 1];
+    if constexpr (HoldB<K>::v) {
+      load_soa(Bs, o, Bh);
+      load_soa(Ps, o, Ph);
+    }
   #pragma unroll 1
     for (int r = r0; r < r1; ++r) {
       if (pr.st[r].phase != PH_INNER) continue;
       const size_t off = (size_t)r * K * N;
-      const T* pp = (const T*)pr.p + off;
-      const T* rp = (const T*)pr.r + off;
-      T* qp = (T*)pr.q + off;
+      const Slab<T> ps((const T*)pr.p + off, K, N), rs((const T*)pr.r + off, K, N), qs((T*)pr.q + off, K, N);
       T pc[K], qv[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const T* pk_ = pp + (size_t)k * N;
-        const T c = ldo(pk_, o);
+        const T c = ps.ld(k, o);
         T s6 = 0;
   #pragma unroll
-        for (int d = 0; d < 6; ++d) s6 += c - ldo(pk_, nb[d]);
+        for (int d = 0; d < 6; ++d) s6 += c - ps.ld(k, nb[d]);
         pc[k] = c;
         qv[k] = OpT<T>::alpha(op, k) * s6;
         // bound the gathers in flight (GatherG<T, K> regressors at a time)
@@ -480,12 +584,11 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
           for (int j = 0; j < K; ++j) qv[k] += Bh[pk(k, j)] * pc[j];
         }
       } else {
-        const __attribute__((address_space(1))) T* Bg = (const __attribute__((address_space(1))) T*)OpT<T>::B(op);
   #pragma unroll
         for (int k = 0; k < K; ++k) {
   #pragma unroll
           for (int j = 0; j <= k; ++j) {
-            const T bkj = Bg[(size_t)pk(k, j) * N + (unsigned)w.nn];
+            const T bkj = Bs.ld(pk(k, j), o);
             qv[k] += bkj * pc[j];
             if (j != k) qv[j] += bkj * pc[k];
           }
@@ -493,23 +596,32 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
       }
       T rv[K];
   #pragma unroll
-      for (int k = 0; k < K; ++k) rv[k] = ldo(rp + (size_t)k * N, o);
+      for (int k = 0; k < K; ++k) rv[k] = rs.ld(k, o);
       T rPr, qPr, qPq;
-      precond_forms<T, PC, K>(OpT<T>::P(op), N, w.nn, rv, qv, rPr, qPr, qPq);
+      if constexpr (HoldB<K>::v)
+        precond_forms_reg<T, PC, K>(Ph, rv, qv, rPr, qPr, qPq);
+      else
+        precond_forms<T, PC, K>(Ps, o, rv, qv, rPr, qPr, qPq);
+      // the voxel's terms of the seven sums, in T; added up in double
+      T spq = 0, srr = 0, sqr = 0, sqq = 0;
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        spq += pc[k] * qv[k];
+        srr += rv[k] * rv[k];
+        sqr += qv[k] * rv[k];
+        sqq += qv[k] * qv[k];
+      }
       double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (w.valid) {
   #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          sto(qp + (size_t)k * N, o, qv[k]);
-          const double pd = pc[k], qd = qv[k], rd = rv[k];
-          acc[0] += pd * qd;
-          acc[4] += rd * rd;
-          acc[5] += qd * rd;
-          acc[6] += qd * qd;
-        }
+        for (int k = 0; k < K; ++k) qs.st(k, o, qv[k]);
+        acc[0] = spq;
         acc[1] = rPr;
         acc[2] = qPr;
         acc[3] = qPq;
+        acc[4] = srr;
+        acc[5] = sqr;
+        acc[6] = sqq;
       }
       wave_deposit<NPART>(s_red, r - r0, acc);
     }
@@ -530,10 +642,11 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* _
     const int r0 = w.chunk * pr.Rc;
     const int r1 = min(pr.R, r0 + pr.Rc);
     if (!w.valid || !any_in_phase(pr, r0, r1, PH_INNER)) continue;
+    const unsigned o = (unsigned)w.n * sizeof(T);
+    const Slab<T> Ps(OpT<T>::P(op), NP, N);
     constexpr bool hold = HoldP<T, PC, K>::v;
     T P[hold ? NP : 1];
-    if constexpr (hold) load_soa(OpT<T>::P(op), N, w.n, P);
-    const unsigned o = (unsigned)w.n * sizeof(T);
+    if constexpr (hold) load_soa(Ps, o, P);
   #pragma unroll 1
     for (int r = r0; r < r1; ++r) {
       const RhsState& s = pr.st[r];
@@ -541,32 +654,30 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* _
       const T a = (T)s.a, beta = (T)s.beta;
       const bool fresh = s.inner_it == 1;
       const size_t off = (size_t)r * K * N;
-      T* pp = (T*)pr.p + off;
-      const T* qp = (const T*)pr.q + off;
-      T* dp = (T*)pr.d + off;
-      T* rp = (T*)pr.r + off;
+      const Slab<T> ps((T*)pr.p + off, K, N), qs((const T*)pr.q + off, K, N), ds((T*)pr.d + off, K, N),
+          rs((T*)pr.r + off, K, N);
       T pv[K], rv[K], z[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const size_t kb = (size_t)k * N;
-        pv[k] = ldo(pp + kb, o);
-        const T dv = fresh ? a * pv[k] : ldo(dp + kb, o) + a * pv[k];
-        rv[k] = ldo(rp + kb, o) - a * ldo(qp + kb, o);
-        sto(dp + kb, o, dv);
-        sto(rp + kb, o, rv[k]);
+        pv[k] = ps.ld(k, o);
+        const T dv = fresh ? a * pv[k] : ds.ld(k, o) + a * pv[k];
+        rv[k] = rs.ld(k, o) - a * qs.ld(k, o);
+        ds.st(k, o, dv);
+        rs.st(k, o, rv[k]);
       }
       if constexpr (hold)
         precond_apply<T, PC, K>(P, rv, z);
       else
-        precond_apply_mem<T, PC, K>(OpT<T>::P(op), N, w.n, rv, z);
+        precond_apply_mem<T, PC, K>(Ps, o, rv, z);
   #pragma unroll
-      for (int k = 0; k < K; ++k) sto(pp + (size_t)k * N, o, z[k] + beta * pv[k]);
+      for (int k = 0; k < K; ++k) ps.st(k, o, z[k] + beta * pv[k]);
     }
   }
 }
 
 // x += d (when valid) + a p (when the last step is pending) for right-hand
-// sides whose inner solve has ended.
+// sides whose inner solve has ended; x = d + a p after the first inner solve
+// from a zero start value.
 template <typename T, int K>
 __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs, int nprob, int W) {
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
@@ -579,20 +690,20 @@ __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs,
     const unsigned oT = (unsigned)w.n * sizeof(T), o8 = (unsigned)w.n * 8u;
     for (int r = r0; r < r1; ++r) {
       const RhsState& s = pr.st[r];
-      if (s.phase != PH_OUTER || !(s.has_d || s.pend)) continue;
+      // with a zero start value, the first x += d writes x without reading it
+      const bool fresh = pr.cfg.zero_guess && s.outer == 1;
+      if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh)) continue;
       const bool hd = s.has_d != 0, hp = s.pend != 0;
       const double a = s.a;
       const size_t off = (size_t)r * K * N;
-      const T* dr = (const T*)pr.d + off;
-      const T* pp = (const T*)pr.p + off;
-      double* xr = pr.x + off;
+      const Slab<T> ds((const T*)pr.d + off, K, N), ps((const T*)pr.p + off, K, N);
+      const Slab<double> xs(pr.x + off, K, N);
   #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const size_t kb = (size_t)k * N;
-        double v = ldo(xr + kb, o8);
-        if (hd) v += (double)ldo(dr + kb, oT);
-        if (hp) v += a * (double)ldo(pp + kb, oT);
-        sto(xr + kb, o8, v);
+        double v = fresh ? 0.0 : xs.ld(k, o8);
+        if (hd) v += (double)ds.ld(k, oT);
+        if (hp) v += a * (double)ps.ld(k, oT);
+        xs.st(k, o8, v);
       }
     }
   }

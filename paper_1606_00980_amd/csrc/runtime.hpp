@@ -142,6 +142,13 @@ int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
                   const Prob* d_probs, bool profiled);
 int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, int iters, bool profiled);
+// One solver round of `chunk` iterations.  With FP32 inner solves, which end
+// every few iterations, every iteration carries the outer step
+// ([x += d, refine, finalise] for right-hand sides waiting on it), so a
+// right-hand side never idles until the next round; with FP64 inner solves the
+// outer step opens the round only.
+int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                  const Prob* d_probs, int chunk, bool profiled);
 
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);

@@ -5,8 +5,8 @@
 // The worker thread repeats rounds.  A round admits waiting requests (FIFO,
 // while the byte budget and the right-hand-side slot table allow), prepares
 // their right-hand sides on the device, rebuilds the grouped-launch
-// descriptors when the active set changed, runs one refinement step and
-// `chunk` inner iterations for every active right-hand side, copies the
+// descriptors when the active set changed, runs one solver round of `chunk`
+// iterations (refinement steps included) for every active right-hand side, copies the
 // state table to the host and retires every request whose right-hand sides
 // are all done.  Requests therefore join and leave the running batch at
 // round boundaries, and the kernels' batch-invariant reductions make a
@@ -160,7 +160,6 @@ int admit(gp_server* s, Req* q) {
       HIPTRY(launch_probe_rhs(st, (long)nv, q->probes, q->b));
       break;
   }
-  HIPTRY(hipMemsetAsync(q->x, 0, nv * sizeof(double), st));
   HIPTRY(hipMemsetAsync(s->d_states + q->slot0, 0, (size_t)q->R * sizeof(RhsState), st));
   return GP_OK;
 }
@@ -182,7 +181,7 @@ int rebuild_layout(gp_server* s) {
   if (int st = ensure_descriptors(s, (int)s->order.size())) return st;
   s->groups.clear();
   const gp_opts& o = s->cfg.opts;
-  const SolveCfg cfg{o.tol, s->f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer};
+  const SolveCfg cfg{o.tol, s->f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, 1, 0};   // x starts at zero
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < (int)s->order.size(); ++j) {
     Req* q = s->order[j];
@@ -222,8 +221,7 @@ int rebuild_layout(gp_server* s) {
 int run_round(gp_server* s) {
   hipStream_t st = s->stream;
   const int pc = s->cfg.opts.precond;
-  if (int e = enqueue_outer(s->ctx, st, s->f32, pc, s->groups, s->d_probs, false)) return e;
-  if (int e = enqueue_inner(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, false)) return e;
+  if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, false)) return e;
   HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
                         hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
@@ -248,6 +246,13 @@ int retire(gp_server* s, Req* q, gp_result* res) {
     res->relres_max = std::max(res->relres_max, h.relres);
   }
   const size_t nv = (size_t)q->R * op->K * op->N;
+  // x starts at zero and is first written by the first x += d: right-hand
+  // sides that ended at their first refinement (b = 0 among them) get zeros
+  const size_t nr = (size_t)op->K * op->N;
+  for (int r = 0; r < q->R; ++r) {
+    const RhsState& h = s->h_states[q->slot0 + r];
+    if (h.zero_b || h.outer <= 1) HIPTRY(hipMemsetAsync(q->x + r * nr, 0, nr * sizeof(double), st));
+  }
   if (q->r.kind == GP_REQ_TRACE) {
     double* part = q->tr;
     double* pairbuf = part + (size_t)2 * q->R * op->K * op->ntiles;

@@ -71,22 +71,19 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
     const bool zc = op.dirs == 3;   // 4-neighbour operators do not couple slices
     const __attribute__((address_space(1))) int* gm = (const __attribute__((address_space(1))) int*)op.gmap;
     bool act[RC];
-    const T* pb[RC];
-    const T* rb[RC];
-    T* qo[RC];
+    Rsrc pb[RC], rb[RC], qb[RC];
+    const unsigned row = (unsigned)N * sizeof(T);
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
       const int r = r0 + i;
       act[i] = r < r1 && pr.st[r].phase == PH_INNER;
       const size_t off = (size_t)(r < r1 ? r : r0) * K * N;
-      pb[i] = (const T*)pr.p + off;
-      rb[i] = (const T*)pr.r + off;
-      qo[i] = (T*)pr.q + off;
+      pb[i] = Slab<T>((const T*)pr.p + off, K, N).rs;
+      rb[i] = Slab<T>((const T*)pr.r + off, K, N).rs;
+      qb[i] = Slab<T>((T*)pr.q + off, K, N).rs;
     }
     // direction p of right-hand side i, regressor k, voxel m
-    auto pval = [&](int i, int k, int m) -> T {
-      return ldo(pb[i] + (size_t)k * N, (unsigned)m * sizeof(T));
-    };
+    auto pval = [&](int i, int k, int m) -> T { return bload<T>(pb[i], (unsigned)m * sizeof(T), (unsigned)k * row); };
     auto cell = [&](int xx, int yy, int zz) -> int {
       return (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) ? gm[((size_t)zz * ny + yy) * nx + xx]
                                                                               : -1;
@@ -145,7 +142,7 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
       lds_barrier();
       if (n_cur >= 0) {
         T B[NB];
-        load_soa(OpT<T>::B(op), N, n_cur, B);
+        load_soa(Slab<T>(OpT<T>::B(op), NB, N), (unsigned)n_cur * sizeof(T), B);
         const int nb_n[4] = {s_n[ty + 1][lane], s_n[ty + 1][lane + 2], s_n[ty][lane + 1], s_n[ty + 2][lane + 1]};
         const unsigned o = (unsigned)n_cur * sizeof(T);
 #pragma unroll
@@ -172,21 +169,25 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
           }
           T rv[K];
 #pragma unroll
-          for (int k = 0; k < K; ++k) rv[k] = ldo(rb[i] + (size_t)k * N, o);
+          for (int k = 0; k < K; ++k) rv[k] = bload<T>(rb[i], o, (unsigned)k * row);
           T rPr, qPr, qPq;
-          precond_forms<T, PC, K>(OpT<T>::P(op), N, n_cur, rv, qv, rPr, qPr, qPq);
+          precond_forms<T, PC, K>(Slab<T>(OpT<T>::P(op), PSize<PC, K>::n, N), o, rv, qv, rPr, qPr, qPq);
+          T spq = 0, srr = 0, sqr = 0, sqq = 0;
 #pragma unroll
           for (int k = 0; k < K; ++k) {
-            sto(qo[i] + (size_t)k * N, o, qv[k]);
-            const double pd = v_cur[i][k], qd = qv[k], rd = rv[k];
-            acc[i][0] += pd * qd;
-            acc[i][4] += rd * rd;
-            acc[i][5] += qd * rd;
-            acc[i][6] += qd * qd;
+            bstore(qb[i], o, (unsigned)k * row, qv[k]);
+            spq += v_cur[i][k] * qv[k];
+            srr += rv[k] * rv[k];
+            sqr += qv[k] * rv[k];
+            sqq += qv[k] * qv[k];
           }
+          acc[i][0] += spq;
           acc[i][1] += rPr;
           acc[i][2] += qPr;
           acc[i][3] += qPq;
+          acc[i][4] += srr;
+          acc[i][5] += sqr;
+          acc[i][6] += sqq;
         }
       }
       lds_barrier();
@@ -201,15 +202,9 @@ __global__ __launch_bounds__(ZFX * ZFY) void k_matvec_zm(const Prob* __restrict_
         }
       }
     }
-    // per right-hand side and value: wavefront butterfly, then the rows in order
+    // per right-hand side: the values summed over each wavefront, then the rows in order
 #pragma unroll
-    for (int i = 0; i < RC; ++i) {
-#pragma unroll
-      for (int v = 0; v < NPART; ++v) {
-        const double s = wave_sum(acc[i][v]);
-        if (lane == 0) s_red[i * NPART + v][ty] = s;
-      }
-    }
+    for (int i = 0; i < RC; ++i) wave_deposit<NPART>(&s_red[0][0], i, acc[i]);
     __syncthreads();
     if (threadIdx.x < RC * NPART) {
       const int i = threadIdx.x / NPART, v = threadIdx.x % NPART, r = r0 + i;

@@ -57,7 +57,7 @@ class GpOpts(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rhs_tile", ctypes.c_int), ("chunk", ctypes.c_int),
                 ("wg_per_cu", ctypes.c_int), ("matvec", ctypes.c_int),
-                ("seed", ctypes.c_uint64)]
+                ("zero_guess", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
 class GpStats(ctypes.Structure):

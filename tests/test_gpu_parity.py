@@ -366,6 +366,33 @@ def test_warm_start_converges_immediately(g, ctx, torch_cuda):
     assert stats[0]["inner_iters"] == 0 and stats[0]["outer_steps"] == 1
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_zero_guess_ignores_x_on_entry(g, ctx, torch_cuda, precision):
+    """zero_guess = 1: x is never read, so NaN on entry changes nothing; the
+    result equals the solve from an explicit zero start value bit for bit, and
+    right-hand sides that end at their first refinement (b = 0; a cap of one
+    refinement) leave zeros."""
+    w = synth.tiny((13, 11, 7), 6, 3, seed=23)
+    op = Op(g, ctx, torch_cuda, w)
+    prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+    b = w.rhs(5)
+    b[3] = 0.0
+    bd = dev(torch_cuda, b)
+    x0 = torch_cuda.zeros_like(bd)
+    g.gp_solve(op.h, 5, bd, x0, opts(g, precision=prec), check=False)
+    xg = torch_cuda.full_like(bd, float("nan"))
+    st, stats = g.gp_solve(op.h, 5, bd, xg, opts(g, precision=prec, zero_guess=1), check=False)
+    assert torch_cuda.equal(xg, x0)
+    assert all(s["status"] == g.GP_OK for s in stats)
+    assert torch_cuda.count_nonzero(xg[3]).item() == 0
+    check_solutions(xg.cpu().numpy(), orc.solve(op.Q, b), w.K, w.N)
+    # one refinement allowed: every right-hand side stops at it, x = 0
+    xc = torch_cuda.full_like(bd, float("nan"))
+    st, stats = g.gp_solve(op.h, 5, bd, xc, opts(g, precision=prec, zero_guess=1, max_outer=1), check=False)
+    assert st == g.GP_ERR_NOT_CONVERGED
+    assert torch_cuda.count_nonzero(xc).item() == 0
+
+
 def test_invalid_arguments_and_budget(g, torch_cuda):
     h = g.gp_ctx_create(0, torch_cuda.cuda.current_stream().cuda_stream, 4096)
     mask = np.ones((4, 4, 4), dtype=np.uint8)
