@@ -173,12 +173,13 @@ int gp_op_create(gp_ctx* ctx, const uint8_t* mask_host, int nx, int ny, int nz,
  * A.2) and factor each as B_n = L_n L_n' (the L_data of Algorithm 2).
  * Returns GP_ERR_NOT_SPD if some block is not positive definite; then
  * *bad_voxel_host (if non-NULL) receives the smallest failing voxel.
- * Rebuilds the preconditioner when alpha is already set.                   */
+ * Marks the preconditioner stale; the next solve rebuilds it.              */
 int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel_host);
 
 /* gp_op_set_alpha: spatial precisions alpha_k >= 0 (host, K doubles; the
- * prior precision of regressor k, Section 2).  Rebuilds the preconditioner
- * (the K x K voxel blocks B_n + diag(alpha_k deg_n) and their inverses).     */
+ * prior precision of regressor k, Section 2).  Marks the preconditioner (the
+ * K x K voxel blocks B_n + diag(alpha_k deg_n) and their inverses) stale; the
+ * next solve rebuilds it, and reports GP_ERR_NOT_SPD if a block fails.       */
 int gp_op_set_alpha(gp_op* op, const double* alpha_host);
 
 /* gp_op_query: any out pointer may be NULL.  N voxels, E adjacent pairs

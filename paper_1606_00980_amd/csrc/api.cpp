@@ -364,13 +364,10 @@ int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
 }
 
 int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
-                  const Prob* d_probs, int chunk, bool profiled) {
-  if (!f32) {
-    if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
-    return enqueue_inner(c, q, f32, pc, gs, d_probs, chunk, profiled);
-  }
+                  const Prob* d_probs, int chunk, uint64_t outer_mask, bool profiled) {
   for (int i = 0; i < chunk; ++i) {
-    if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
+    if (i < 64 && ((outer_mask >> i) & 1))
+      if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
     if (int e = enqueue_inner(c, q, f32, pc, gs, d_probs, 1, profiled)) return e;
   }
   return GP_OK;
@@ -547,6 +544,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // rounds of round_len iterations; with FP64 inner solves a round in which no
   // right-hand side iterates is the outer step alone
   int round_len = chunk;
+  uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
   auto launch_round = [&](bool outer_only) -> int {
     if (outer_only) {
       if (!graphs) return enqueue_outer(c, s, f32, pc, groups, c->d_probs, true);
@@ -554,9 +552,10 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
                     [&](hipStream_t q) { return enqueue_outer(c, q, f32, pc, groups, c->d_probs, false); });
     }
     const int n = round_len;
-    if (!graphs) return enqueue_round(c, s, f32, pc, groups, c->d_probs, n, true);
-    return replay(layout_key + "|round" + std::to_string(n),
-                  [&](hipStream_t q) { return enqueue_round(c, q, f32, pc, groups, c->d_probs, n, false); });
+    const uint64_t m = round_mask;
+    if (!graphs) return enqueue_round(c, s, f32, pc, groups, c->d_probs, n, m, true);
+    return replay(layout_key + "|round" + std::to_string(n) + "/" + std::to_string(m),
+                  [&](hipStream_t q) { return enqueue_round(c, q, f32, pc, groups, c->d_probs, n, m, false); });
   };
   // host copy of every right-hand side's state
   std::vector<RhsState> hs(totalR);
@@ -575,25 +574,46 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // performs a refinement step, both bounded by max_iter and max_outer.
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
-  // With FP32 inner solves and an automatic chunk, the next round is as long
-  // as the active right-hand sides are expected to need: per right-hand side,
-  // the iterations left in its inner solve (from the mean length of its
-  // completed ones), plus the refinement slot, plus one more inner solve when
-  // the residual after this one (about relres * inner_tol) is still above tol.
-  auto plan_round = [&]() -> int {
-    if (!f32 || o.chunk > 0) return chunk;
+  // With FP32 inner solves and an automatic chunk, the next round is planned
+  // from each right-hand side's completed inner solves (their mean length
+  // est): the slot in which its current inner solve should end, the refinement
+  // in the slot after it, one more inner solve when the residual after this
+  // one (about relres * inner_tol) is still above tol.  The round lasts until
+  // the last expected refinement; the outer step is placed in the first slot
+  // and around every expected refinement.  Before any history: `chunk` slots,
+  // the outer step first.
+  auto plan_round = [&]() {
+    round_len = chunk;
+    round_mask = 1;
+    if (!f32 || o.chunk > 0) {
+      round_mask = f32 ? ~0ull : 1ull;
+      return;
+    }
     int need = 1;
+    uint64_t mask = 1;
+    auto mark = [&](int slot) {   // 1-based slot that should carry the outer step
+      for (int t = slot - 1; t <= slot + 1; ++t)
+        if (t >= 1 && t <= 64) mask |= 1ull << (t - 1);
+    };
     for (const RhsState& h : hs) {
       if (h.phase == PH_DONE) continue;
       const bool inner = h.phase == PH_INNER;
       const int done_solves = inner ? h.outer - 1 : h.outer;
-      if (done_solves <= 0) return chunk;   // no completed inner solve yet
-      const int est = (h.total_it - (inner ? h.inner_it : 0) + done_solves - 1) / done_solves;
-      int rem = inner ? std::max(1, est - h.inner_it) + 1 : 1;
-      if (h.relres * o.inner_tol > o.tol) rem += est;
-      need = std::max(need, rem);
+      if (done_solves <= 0) {   // no history yet
+        need = std::max(need, chunk);
+        continue;
+      }
+      const int est = std::max(1, (h.total_it - (inner ? h.inner_it : 0) + done_solves - 1) / done_solves);
+      int refine_slot = inner ? std::max(1, est - h.inner_it) + 1 : 1;
+      mark(refine_slot);
+      if (h.relres * o.inner_tol > o.tol) {
+        refine_slot += est;
+        mark(refine_slot);
+      }
+      need = std::max(need, refine_slot);
     }
-    return std::min(need, 2 * chunk);
+    round_len = std::min(need, 2 * chunk);
+    round_mask = mask;
   };
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
@@ -601,7 +621,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     if (st) return st;
     st = read_states();
     if (st) return st;
-    round_len = plan_round();
+    plan_round();
   }
   // results (hs holds the final states, in problem order)
   int ret = GP_OK;
@@ -921,7 +941,6 @@ int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
     return fail(GP_ERR_NOT_SPD, "data block of voxel " + std::to_string(bad) + " is not positive definite");
   }
   op->have_blocks = true;
-  if (op->have_alpha) return build_precond(op, op->pc_want);
   return GP_OK;
 }
 
@@ -936,7 +955,6 @@ int gp_op_set_alpha(gp_op* op, const double* alpha) {
   for (int k = 0; k < op->K; ++k) op->alpha[k] = alpha[k];
   op->have_alpha = true;
   op->pc_built = -1;
-  if (op->have_blocks) return build_precond(op, op->pc_want);
   return GP_OK;
 }
 

@@ -142,13 +142,13 @@ int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
                   const Prob* d_probs, bool profiled);
 int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, int iters, bool profiled);
-// One solver round of `chunk` iterations.  With FP32 inner solves, which end
-// every few iterations, every iteration carries the outer step
-// ([x += d, refine, finalise] for right-hand sides waiting on it), so a
-// right-hand side never idles until the next round; with FP64 inner solves the
-// outer step opens the round only.
+// One solver round of `chunk` iterations.  Iteration i (0-based) is preceded
+// by the outer step ([x += d, refine, finalise] for right-hand sides waiting
+// on it) when bit i of outer_mask is set: with FP32 inner solves, which end
+// every few iterations, the host places it where inner solves are expected to
+// end, so a right-hand side rarely idles until the next round.
 int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
-                  const Prob* d_probs, int chunk, bool profiled);
+                  const Prob* d_probs, int chunk, uint64_t outer_mask, bool profiled);
 
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);

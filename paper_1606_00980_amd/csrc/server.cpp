@@ -221,7 +221,9 @@ int rebuild_layout(gp_server* s) {
 int run_round(gp_server* s) {
   hipStream_t st = s->stream;
   const int pc = s->cfg.opts.precond;
-  if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, false)) return e;
+  // requests join and finish at different times: the outer step precedes every iteration
+  if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, s->f32 ? ~0ull : 1ull, false))
+    return e;
   HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
                         hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
