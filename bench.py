@@ -57,6 +57,13 @@ def parse():
                     help="skip the plain FP64 single-right-hand-side comparison run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, copy a buffer of this size 5 times (counter calibration)")
+    ap.add_argument("--no-bandwidth-sweep", action="store_true",
+                    help="skip the working-set sweep on the largest uneven operator")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="reduce two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of a "
+                         "'--copy-probe-mib' run to per-launch HBM bytes per kernel kind, write "
+                         "profiles/traffic_pmc.json and exit")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="with --traffic-from: the copy probe size")
     return ap.parse_args()
 
 
@@ -193,6 +200,104 @@ def roofline(prof):
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 2),
             "bytes_per_launch": round(d["bytes"] / d["launches"])}
+
+
+KERNEL_KIND_OF = [("k_matvec_zm", "matvec"), ("k_matvec", "matvec"), ("k_update", "update"),
+                  ("k_refine", "refine"), ("k_addsol", "addsol"), ("k_perturb", "perturb"),
+                  ("k_probe_rhs", "probe"), ("k_precond", "precond"), ("k_pack_blocks", "pack")]
+
+
+def traffic_from(fetch_csv, write_csv, copy_mib):
+    """Per-launch HBM traffic of each kernel kind from rocprofv3 counter files.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+    counters read for the calibration copy (copy_mib MiB read and written per
+    dispatch); the launches of a kind are averaged as the profiler's
+    bytes-per-launch figure is.
+    """
+    import csv
+
+    def load(path):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fetch, write = load(fetch_csv), load(write_csv)
+    copy_bytes = copy_mib * float(1 << 20)
+
+    def factor(per):
+        big = [v for k, vs in per.items() if "copyBuffer" in k for v in vs if v > 0.25 * copy_bytes]
+        if not big:
+            raise SystemExit("no calibration copy dispatches found")
+        big.sort()
+        return copy_bytes / big[len(big) // 2]
+
+    ff, fw = factor(fetch), factor(write)
+    kinds = {}
+    for name, vs in fetch.items():
+        kind = next((kd for pat, kd in KERNEL_KIND_OF if pat in name), None)
+        if kind is None:
+            continue
+        ws = write.get(name, [])
+        d = kinds.setdefault(kind, {"fetch": [], "write": []})
+        d["fetch"] += vs
+        d["write"] += ws
+    out = {}
+    for kind, d in kinds.items():
+        fb = ff * sum(d["fetch"]) / len(d["fetch"])
+        wb = fw * sum(d["write"]) / max(1, len(d["write"]))
+        out[kind] = {"bytes_per_launch": round(fb + wb), "fetch_bytes": round(fb), "write_bytes": round(wb),
+                     "launches": len(d["fetch"])}
+    res = {"kernel_source_hash": kernel_source_hash(), "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+           "copy_mib": copy_mib, "kernels": out,
+           "note": "FETCH_SIZE / WRITE_SIZE per dispatch x (copy bytes / counter reading of the copy), "
+                   "averaged over a kind's launches"}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def bandwidth_sweep(g, torch, ctx):
+    """Matvec and update bandwidth over a working-set sweep on the largest
+    uneven operator (96x96x60 grid, 60% ellipsoid fill, K = 10), R = 1..64
+    right-hand sides b = b_w + N(0, 1) drawn on the device; the 256 MB MALL
+    boundary is marked.  One full FP32+FP64 solve per R, profiled."""
+    from paper_1606_00980_amd import synth
+    w = synth.uneven_instance(synth.CFG_UNEVEN, 0, dims=(96, 96, 60), fill=0.6, K=10)
+    log(f"bandwidth sweep operator: N={w.N} K={w.K}")
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    g.gp_op_set_blocks(op, torch.from_numpy(w.B).cuda())
+    g.gp_op_set_alpha(op, w.alpha)
+    bw = torch.from_numpy(w.bw).cuda()
+    opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
+    rows = []
+    for R in (1, 4, 16, 64):
+        b = torch.empty((R, w.K, w.N), dtype=torch.float64, device="cuda")
+        g.gp_rng_normal(ctx, 7, 4, b.numel(), b)
+        b += bw
+        x = torch.empty_like(b)
+        g.gp_solve(op, R, b, x, opts, check=False)
+        torch.cuda.synchronize()
+        g.gp_ctx_profile(ctx, True)
+        _, stats = g.gp_solve(op, R, b, x, opts, check=False)
+        prof = g.gp_ctx_profile_read(ctx)
+        g.gp_ctx_profile(ctx, False)
+        row = {"R": R, "converged": all(s_["status"] == 0 for s_ in stats)}
+        for kind in ("matvec", "update", "refine"):
+            v = prof[kind]
+            if v["launches"]:
+                gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+                row[kind] = {"avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                             "bytes_per_launch": round(v["bytes"] / v["launches"]),
+                             "GBps": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+        row["beyond_mall"] = row["matvec"]["bytes_per_launch"] > 256e6
+        rows.append(row)
+        log(f"bandwidth sweep R={R}: matvec {row['matvec']['GBps']} GB/s, update {row['update']['GBps']} GB/s")
+        del b, x
+    g.gp_op_destroy(op)
+    return {"workload": f"uneven_largest_96x96x60_fill0.6_K10_N{w.N}", "N": w.N, "K": w.K,
+            "mall_bytes": 256e6, "sweep": rows}
 
 
 def cpu_baseline():
@@ -348,6 +453,9 @@ def sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_mib)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
                                    "supported (one process, one MI355X)", "n_gpus": args.gpus}))
@@ -428,6 +536,11 @@ def main():
         result["gpu_fp64_single_rhs"] = {"value": round(n / (time.perf_counter() - tb), 2),
                                          "unit": "solves/s",
                                          "what": "plain FP64 single-RHS PCG, same operator, block Jacobi"}
+    if args.workload == "batch64" and not args.no_bandwidth_sweep:
+        result["bandwidth_sweep"] = bandwidth_sweep(g, torch, ctx)
+        big = result["bandwidth_sweep"]["sweep"][-1]
+        result["roofline_beyond_mall"] = {"kernel": "matvec", "R": big["R"], **big["matvec"],
+                                          "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

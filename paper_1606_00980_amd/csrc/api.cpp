@@ -272,6 +272,9 @@ Plan plan_problem(const gp_op* op, int R, const gp_opts& o, int cus) {
   pl.Rc = rc;
   pl.nchunks = (R + rc - 1) / rc;
   pl.work_count = op->ntiles * pl.nchunks;
+  pl.Rco = std::min(rc, 4);
+  pl.nchunks_o = (R + pl.Rco - 1) / pl.Rco;
+  pl.work_count_o = op->ntiles * pl.nchunks_o;
   pl.mv_mode = o.matvec == GP_MATVEC_ZMARCH ? 1 : 0;
   if (pl.mv_mode) {
     const int nxt = (op->nx + 63) / 64;
@@ -296,6 +299,9 @@ void apply_plan(Prob& p, const Plan& pl) {
   p.Rc = pl.Rc;
   p.nchunks = pl.nchunks;
   p.work_count = pl.work_count;
+  p.Rco = pl.Rco;
+  p.nchunks_o = pl.nchunks_o;
+  p.work_count_o = pl.work_count_o;
   p.pstride = pl.pstride;
   p.mv_mode = pl.mv_mode;
   p.zs = pl.zs;
@@ -312,6 +318,7 @@ void size_groups(std::vector<LaunchGroup>& gs, int cus) {
     const int cap = std::max(8, cus * wpc / 8 * 8);
     g.nblk = std::min(cap, (g.W + 7) / 8 * 8);
     g.nblk_mv = std::min(cap, (g.Wmv + 7) / 8 * 8);
+    g.nblk_o = std::min(cap, (g.Wo + 7) / 8 * 8);
   }
 }
 
@@ -330,11 +337,11 @@ int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
   for (const LaunchGroup& g : gs) {
     const Prob* dp = d_probs + g.first;
     PROFILED_IF(pf, c, GP_KERNEL_ADDSOL,
-                f32 ? launch_addsol_f32(q, g.K, dp, g.count, g.W, g.nblk)
-                    : launch_addsol_f64(q, g.K, dp, g.count, g.W, g.nblk));
+                f32 ? launch_addsol_f32(q, g.K, dp, g.count, g.Wo, g.nblk_o)
+                    : launch_addsol_f64(q, g.K, dp, g.count, g.Wo, g.nblk_o));
     PROFILED_IF(pf, c, GP_KERNEL_REFINE,
-                f32 ? launch_refine_f32(q, pc, g.K, dp, g.count, g.W, g.nblk)
-                    : launch_refine_f64(q, pc, g.K, dp, g.count, g.W, g.nblk));
+                f32 ? launch_refine_f32(q, pc, g.K, dp, g.count, g.Wo, g.nblk_o)
+                    : launch_refine_f64(q, pc, g.K, dp, g.count, g.Wo, g.nblk_o));
     HIPTRY(launch_finalize(q, 0, dp, g.count, g.F));
   }
   return GP_OK;
@@ -484,10 +491,12 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     apply_plan(p, plans[j]);
     p.cfg = cfg;
     if (groups.empty() || groups.back().K != it.op->K)
-      groups.push_back(LaunchGroup{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode, popts[j].wg_per_cu});
+      groups.push_back(LaunchGroup{it.op->K, j, 0, 0, 0, 0, 0, 0, plans[j].mv_mode, popts[j].wg_per_cu, 0, 0});
     LaunchGroup& g = groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
+    p.work_begin_o = g.Wo;
+    g.Wo += p.work_count_o;
     p.mv_begin = g.Wmv;
     g.Wmv += p.mv_count;
     p.fin_begin = g.F;
@@ -512,7 +521,8 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     for (const LaunchGroup& g : groups)
       layout_key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.W) + "," +
                     std::to_string(g.F) + "," + std::to_string(g.nblk) + "," + std::to_string(g.mv_mode) + "," +
-                    std::to_string(g.Wmv) + "," + std::to_string(g.nblk_mv);
+                    std::to_string(g.Wmv) + "," + std::to_string(g.nblk_mv) + "," + std::to_string(g.Wo) + "," +
+                    std::to_string(g.nblk_o);
   }
   auto replay = [&](const std::string& key, const std::function<int(hipStream_t)>& enqueue) -> int {
     auto it = c->graphs.find(key);
@@ -664,12 +674,16 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       const double NB = K * (K + 1) / 2, NP = o.precond == GP_PRECOND_JACOBI ? K : NB;
       // algorithmic bytes: every vector entry, block and preconditioner entry
       // a launch needs, read or written once
+      // x (unless the start value is zero) and b read, r and p written
       prof_add(c, GP_KERNEL_REFINE, pf[PF_REFINE_RHS] * N,
-               pf[PF_REFINE_RHS] * N * K * (16 + 2 * ts) + pf[PF_REFINE_ACT] * N * (NB * 8 + NP * ts));
-      // x read and written; d and/or the pending step's p read
-      const double addsol_rhs = std::max(pf[PF_ADDSOL_D], pf[PF_ADDSOL_P]);
+               pf[PF_REFINE_RHS] * N * K * (16 + 2 * ts) - pf[PF_REFINE_X0] * N * K * 8 +
+                   pf[PF_REFINE_ACT] * N * (NB * 8 + NP * ts));
+      // x read (not on the first step from a zero start value) and written; d
+      // and/or the pending step's p read
+      const double addsol_rhs = std::max<double>(std::max(pf[PF_ADDSOL_D], pf[PF_ADDSOL_P]), pf[PF_ADDSOL_FRESH]);
       prof_add(c, GP_KERNEL_ADDSOL, addsol_rhs * N,
-               addsol_rhs * N * K * 16 + (pf[PF_ADDSOL_D] + pf[PF_ADDSOL_P]) * N * K * ts);
+               addsol_rhs * N * K * 16 - pf[PF_ADDSOL_FRESH] * N * K * 8 +
+                   (pf[PF_ADDSOL_D] + pf[PF_ADDSOL_P]) * N * K * ts);
       // p and r read, q written; blocks and preconditioner once per launch
       prof_add(c, GP_KERNEL_MATVEC, pf[PF_MATVEC_RHS] * N,
                pf[PF_MATVEC_RHS] * N * 3 * K * ts + pf[PF_MATVEC_ACT] * N * (NB + NP) * ts);

@@ -10,11 +10,13 @@ namespace gp {
 constexpr int KMAX = 16;     // largest supported number of regressors
 constexpr int TILE = 256;    // voxels per workgroup in the voxel-parallel kernels
 constexpr int NPART = 7;     // reduction values per (right-hand side, tile), at most
-constexpr int NPROF = 10;    // profiling counters per problem
+constexpr int NPROF = 12;    // profiling counters per problem
 // profiling counter slots (right-hand sides processed, launches with work)
 enum ProfSlot : int {
   PF_REFINE_RHS = 0, PF_REFINE_ACT, PF_ADDSOL_D, PF_ADDSOL_P, PF_MATVEC_RHS,
   PF_MATVEC_ACT, PF_UPDATE_RHS, PF_UPDATE_FRESH, PF_UPDATE_ACT,
+  PF_REFINE_X0,      // refinements with a zero start value (x not read)
+  PF_ADDSOL_FRESH,   // first x += d from a zero start value (x written, not read)
 };
 constexpr int RCMAX = 16;    // right-hand sides per workgroup, upper bound
 constexpr int PC_JACOBI = 0; // preconditioner kinds as seen by the kernels
@@ -81,7 +83,8 @@ struct Prob {
   RhsState* st;          // [R]
   double* part;          // [NPART][R][pstride]
   long long* prof;       // [NPROF] work counters, or null when not profiling
-  int R, Rc, nchunks, work_begin, work_count;
+  int R, Rc, nchunks, work_begin, work_count;   // matvec / update: Rc right-hand sides per work item
+  int Rco, nchunks_o, work_begin_o, work_count_o;   // refine / addsol: Rco per work item
   int fin_begin;         // first finalising workgroup of this problem
   int pstride;           // partials per (value, right-hand side): max(raster, z-march tiles)
   // z-marching matvec (mv_mode = 1): footprint tiles x segments of zs slices

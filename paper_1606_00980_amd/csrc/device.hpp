@@ -69,10 +69,12 @@ template <typename T> struct Slab {
   __device__ __forceinline__ void st(int i, unsigned voff, T v) const { bstore(rs, voff, (unsigned)i * row, v); }
 };
 
-// Which problem of a grouped launch owns work item w.
+// Which problem of a grouped launch owns work item w (of the inner or the
+// outer work decomposition).
+template <bool OUTER = false>
 __device__ inline int find_prob(const Prob* __restrict__ probs, int nprob, int w) {
   int p = 0;
-  while (p + 1 < nprob && w >= probs[p + 1].work_begin) ++p;
+  while (p + 1 < nprob && w >= (OUTER ? probs[p + 1].work_begin_o : probs[p + 1].work_begin)) ++p;
   return p;
 }
 

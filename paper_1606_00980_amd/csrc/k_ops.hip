@@ -293,8 +293,12 @@ __global__ __launch_bounds__(TILE) void k_perturb(OpDev op, const double* __rest
                                                   double* __restrict__ b) {
   constexpr int NB = Tri<K>::NB;
   const int N = op.N, dirs = op.dirs;
-  const int n = blockIdx.x * TILE + threadIdx.x;
-  const int r = blockIdx.y;
+  // items (right-hand side, tile), right-hand side major, in contiguous ranges
+  // per XCD: the lower neighbours' z1 values were just read by the same XCD
+  const int W = gridDim.x;
+  const int item = xcd_remap(blockIdx.x, W);
+  const int r = item / op.ntiles, tile = item - r * op.ntiles;
+  const int n = tile * TILE + threadIdx.x;
   if (n >= N) return;
   int nb[6];
 #pragma unroll
@@ -445,7 +449,7 @@ hipError_t launch_apply(hipStream_t s, const OpDev& op, int R, const double* x, 
 
 hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* bw, const double* z1,
                           const double* z2, double* b) {
-  const dim3 g((op.N + TILE - 1) / TILE, R), bl(TILE);
+  const dim3 g((unsigned)((long)op.ntiles * R)), bl(TILE);
   switch (op.K) {
 #define X(KK) case KK: hipLaunchKernelGGL(k_perturb<KK>, g, bl, 0, s, op, bw, z1, z2, b); break;
     GP_K_CASES(X)

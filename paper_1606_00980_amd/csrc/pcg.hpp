@@ -163,7 +163,7 @@ __device__ inline void precond_forms_reg(const T (&P)[PSize<PC, K>::n], const T 
 // Blocks (and, in the matvec, the preconditioner) held in registers across a
 // work item's right-hand sides while they fit; larger K streams them per
 // right-hand side (cache hits).
-template <int K> struct HoldB { static constexpr bool v = K <= 6; };
+template <typename T, int K> struct HoldB { static constexpr bool v = sizeof(T) == 4 ? K <= 10 : K <= 8; };
 // Regressors whose neighbour gathers may be in flight together in the matvec.
 template <typename T, int K> struct GatherG { static constexpr int v = (sizeof(T) == 4 && K >= 12) ? 4 : K; };
 // The refine kernel holds the FP64 block and the preconditioner in registers
@@ -176,7 +176,7 @@ template <typename T, int PC, int K> struct HoldP {
 
 // Resident-wave request of the matvec kernel: 4 per SIMD (<= 128 VGPRs) while
 // its per-voxel vectors fit, else 2.
-template <typename T, int K> struct OccMV { static constexpr int v = sizeof(T) == 4 ? (K <= 10 ? 4 : 2) : (K <= 5 ? 4 : 2); };
+template <typename T, int K> struct OccMV { static constexpr int v = sizeof(T) == 4 ? (K <= 6 ? 4 : 2) : (K <= 5 ? 4 : 2); };
 
 // Per-RHS sums held in LDS: s_red[(slot * NV + v) * nwaves + wave].
 // The NV values are summed over the wavefront together: M halving exchanges
@@ -232,6 +232,7 @@ __device__ inline void flush_partials(const Prob& pr, const double* s_red, int r
 
 struct Where {
   int p, tile, chunk, n, nn;
+  int r0, r1;   // right-hand sides [r0, r1) of the work item
   bool valid;
 };
 
@@ -259,18 +260,23 @@ __device__ inline Sweep sweep_begin(int W) {
 // above, each XCD then owns about one block for every chunk: the block's
 // matrices and preconditioner stay in that XCD's L2 across all chunks, and the
 // stencil's z-neighbours lie in the same block except at its two faces.
+// The refine and addsol kernels (OUTER) use their own right-hand-side chunks.
+template <bool OUTER = false>
 __device__ inline Where locate(const Prob* __restrict__ probs, int nprob, int item) {
   Where w;
-  w.p = find_prob(probs, nprob, item);
+  w.p = find_prob<OUTER>(probs, nprob, item);
   const Prob& pr = probs[w.p];
-  const int local = item - pr.work_begin;
-  const int nt = pr.op.ntiles, nc = pr.nchunks;
+  const int local = item - (OUTER ? pr.work_begin_o : pr.work_begin);
+  const int nt = pr.op.ntiles, nc = OUTER ? pr.nchunks_o : pr.nchunks;
   const int tb = (nt + NXCD - 1) / NXCD;          // tiles per block
   const int b = local / (nc * tb);
   const int j = local - b * nc * tb;
   const int ntb = min(tb, nt - b * tb);           // tiles in block b (the last may be short)
   w.chunk = j / ntb;
   w.tile = b * tb + (j - w.chunk * ntb);
+  const int rc = OUTER ? pr.Rco : pr.Rc;
+  w.r0 = w.chunk * rc;
+  w.r1 = min(pr.R, w.r0 + rc);
   const int N = pr.op.N;
   w.n = w.tile * TILE + (int)threadIdx.x;
   w.valid = w.n < N;
@@ -309,6 +315,8 @@ __device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[
   prof_add(pr, PF_REFINE_RHS, 1);
   prof_add(pr, PF_ADDSOL_D, s.has_d);
   prof_add(pr, PF_ADDSOL_P, s.pend);
+  prof_add(pr, PF_REFINE_X0, pr.cfg.zero_guess && s.outer == 0);
+  prof_add(pr, PF_ADDSOL_FRESH, pr.cfg.zero_guess && s.outer == 1);
   if (s.outer == 0) s.bnorm2 = bb;
   s.has_d = 0;
   s.pend = 0;
@@ -491,13 +499,12 @@ __global__ __launch_bounds__(TILE, Occ<K>::outer) void k_refine(const Prob* __re
   constexpr int NB = Tri<K>::NB, NP = PSize<PC, K>::n;
   __shared__ double s_red[RCMAX * 3 * (TILE / WAVE)];
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
-    const Where w = locate(probs, nprob, sw.item);
+    const Where w = locate<true>(probs, nprob, sw.item);
     const Prob& pr = probs[w.p];
     const OpDev& op = pr.op;
     const int N = op.N;
     if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_REFINE_ACT, PH_OUTER);
-    const int r0 = w.chunk * pr.Rc;
-    const int r1 = min(pr.R, r0 + pr.Rc);
+    const int r0 = w.r0, r1 = w.r1;
     if (!any_in_phase(pr, r0, r1, PH_OUTER)) continue;
     unsigned nb8[6];
     voxel_offsets<8>(op, w.nn, nb8);
@@ -547,15 +554,14 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
     const OpDev& op = pr.op;
     const int N = op.N;
     if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_MATVEC_ACT, PH_INNER);
-    const int r0 = w.chunk * pr.Rc;
-    const int r1 = min(pr.R, r0 + pr.Rc);
+    const int r0 = w.r0, r1 = w.r1;
     if (!any_in_phase(pr, r0, r1, PH_INNER)) continue;
     unsigned nb[6];
     voxel_offsets<sizeof(T)>(op, w.nn, nb);
     const unsigned o = (unsigned)w.nn * sizeof(T);
     const Slab<T> Bs(OpT<T>::B(op), NB, N), Ps(OpT<T>::P(op), NP, N);
-    T Bh[HoldB<K>::v ? NB : 1], Ph[HoldB<K>::v ? NP : 1];
-    if constexpr (HoldB<K>::v) {
+    T Bh[HoldB<T, K>::v ? NB : 1], Ph[HoldB<T, K>::v ? NP : 1];
+    if constexpr (HoldB<T, K>::v) {
       load_soa(Bs, o, Bh);
       load_soa(Ps, o, Ph);
     }
@@ -577,7 +583,7 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
         if constexpr (GatherG<T, K>::v < K)
           if ((k + 1) % GatherG<T, K>::v == 0) __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (HoldB<K>::v) {
+      if constexpr (HoldB<T, K>::v) {
   #pragma unroll
         for (int k = 0; k < K; ++k) {
   #pragma unroll
@@ -598,7 +604,7 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_matvec(const Prob* _
   #pragma unroll
       for (int k = 0; k < K; ++k) rv[k] = rs.ld(k, o);
       T rPr, qPr, qPq;
-      if constexpr (HoldB<K>::v)
+      if constexpr (HoldB<T, K>::v)
         precond_forms_reg<T, PC, K>(Ph, rv, qv, rPr, qPr, qPq);
       else
         precond_forms<T, PC, K>(Ps, o, rv, qv, rPr, qPr, qPq);
@@ -639,8 +645,7 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* _
     const OpDev& op = pr.op;
     const int N = op.N;
     if (w.tile == 0 && w.chunk == 0) prof_launch(pr, PF_UPDATE_ACT, PH_INNER);
-    const int r0 = w.chunk * pr.Rc;
-    const int r1 = min(pr.R, r0 + pr.Rc);
+    const int r0 = w.r0, r1 = w.r1;
     if (!w.valid || !any_in_phase(pr, r0, r1, PH_INNER)) continue;
     const unsigned o = (unsigned)w.n * sizeof(T);
     const Slab<T> Ps(OpT<T>::P(op), NP, N);
@@ -681,12 +686,11 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* _
 template <typename T, int K>
 __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs, int nprob, int W) {
   for (Sweep sw = sweep_begin(W); sw.item < sw.end; sw.item += sw.step) {
-    const Where w = locate(probs, nprob, sw.item);
+    const Where w = locate<true>(probs, nprob, sw.item);
     const Prob& pr = probs[w.p];
     if (!w.valid) continue;
     const int N = pr.op.N;
-    const int r0 = w.chunk * pr.Rc;
-    const int r1 = min(pr.R, r0 + pr.Rc);
+    const int r0 = w.r0, r1 = w.r1;
     const unsigned oT = (unsigned)w.n * sizeof(T), o8 = (unsigned)w.n * 8u;
     for (int r = r0; r < r1; ++r) {
       const RhsState& s = pr.st[r];

@@ -109,10 +109,12 @@ struct BusyGuard {
 };
 
 // Work decomposition of one problem (operator + R right-hand sides) for the
-// grouped launches: raster tiles for refine/update, and for the inner matvec
-// either the same tiles or z-marching footprints.
+// grouped launches: raster tiles x chunks of Rc right-hand sides for the
+// matvec and update (the matvec may instead use z-marching footprints), and
+// tiles x chunks of Rco <= 4 for refine and addsol, which prefer short chunks.
 struct Plan {
   int Rc, nchunks, work_count, pstride;
+  int Rco, nchunks_o, work_count_o;
   int mv_mode, zs, nseg, nyt, mv_tiles, mv_nchunks, mv_count;
 };
 Plan plan_problem(const gp_op* op, int R, const gp_opts& o, int cus);
@@ -129,6 +131,7 @@ void apply_plan(Prob& p, const Plan& pl);
 // finalising workgroups, nblk (nblk_mv) persistent workgroups.
 struct LaunchGroup {
   int K, first, count, W, F, nblk, Wmv, nblk_mv, mv_mode, wpc;
+  int Wo, nblk_o;   // refine / addsol work items and workgroups
 };
 // Number of inner vectors (d, r, p, q) per right-hand side in the inner precision.
 constexpr int NVEC = 4;

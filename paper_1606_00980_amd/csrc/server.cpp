@@ -202,10 +202,12 @@ int rebuild_layout(gp_server* s) {
     apply_plan(p, pl);
     p.cfg = cfg;
     if (s->groups.empty() || s->groups.back().K != q->op->K)
-      s->groups.push_back(LaunchGroup{q->op->K, j, 0, 0, 0, 0, 0, 0, pl.mv_mode, o.wg_per_cu});
+      s->groups.push_back(LaunchGroup{q->op->K, j, 0, 0, 0, 0, 0, 0, pl.mv_mode, o.wg_per_cu, 0, 0});
     auto& g = s->groups.back();
     p.work_begin = g.W;
     g.W += p.work_count;
+    p.work_begin_o = g.Wo;
+    g.Wo += p.work_count_o;
     p.mv_begin = g.Wmv;
     g.Wmv += p.mv_count;
     p.fin_begin = g.F;

@@ -76,7 +76,7 @@ int gp_autotune(gp_op* op, int R, const gp_opts* base, gp_opts* best) {
     int rc, wpc, mv;
   };
   std::vector<Cand> cands;
-  for (int rc : {1, 2, 4, 8})
+  for (int rc : {1, 2, 4, 8, 16})
     if (rc <= R || rc == 1)
       for (int wpc : {4, 8})
         for (int mv : {GP_MATVEC_RASTER, GP_MATVEC_ZMARCH}) cands.push_back({rc, wpc, mv});

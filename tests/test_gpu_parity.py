@@ -539,7 +539,7 @@ def test_autotune_and_table_round_trip(g, ctx, torch_cuda, tmp_path):
     w = synth.tiny((20, 16, 9), 6, 4, seed=24)
     op = Op(g, ctx, torch, w)
     best = g.gp_autotune(op.h, 6, g.gp_opts_default(tol=1e-8))
-    assert best.rhs_tile in (1, 2, 4, 8) and best.wg_per_cu in (4, 8)
+    assert best.rhs_tile in (1, 2, 4, 8, 16) and best.wg_per_cu in (4, 8)
     assert best.matvec in (g.GP_MATVEC_RASTER, g.GP_MATVEC_ZMARCH)
     path = str(tmp_path / "tune.json")
     g.gp_tune_save(ctx, path)
