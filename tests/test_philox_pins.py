@@ -1,8 +1,26 @@
-"""Statistical pins of the oracle's Philox4x32-10 twin (the GPU generator is
-compared with it bit for bit in the GPU tests)."""
+"""Pins of the oracle's Philox4x32-10 twin: the generator's published
+known-answer vectors, and statistical checks of the derived uniforms, normals
+and signs (the GPU generator is compared with the twin bit for bit in the GPU
+tests)."""
+import os
+
 import numpy as np
 
 from oracle import philox
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def test_known_answer_vectors():
+    """Counter (c0, c1, c2, c3) = (block lo, block hi, stream lo, stream hi),
+    key (k0, k1) = (seed lo, seed hi): the published outputs, word for word."""
+    rows = [line.split() for line in open(GOLDEN) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        c0, c1, c2, c3, k0, k1, *out = (int(v, 16) for v in row)
+        q = np.array([c0 | (c1 << 32)], dtype=np.uint64)
+        got = philox.philox4x32_10(q, seed=k0 | (k1 << 32), stream=c2 | (c3 << 32))[0]
+        assert [int(v) for v in got] == out
 
 
 def test_uniform_words_chi_square():
