@@ -372,11 +372,38 @@ int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
 
 int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, int chunk, uint64_t outer_mask, bool profiled) {
+  if (chunk == 0)   // the outer step alone
+    return (outer_mask & 1) ? enqueue_outer(c, q, f32, pc, gs, d_probs, profiled) : GP_OK;
   for (int i = 0; i < chunk; ++i) {
     if (i < 64 && ((outer_mask >> i) & 1))
       if (int e = enqueue_outer(c, q, f32, pc, gs, d_probs, profiled)) return e;
     if (int e = enqueue_inner(c, q, f32, pc, gs, d_probs, 1, profiled)) return e;
   }
+  return GP_OK;
+}
+
+int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                           const Prob* d_probs, int chunk, uint64_t outer_mask) {
+  if (gs.size() <= 1) return enqueue_round(c, q, f32, pc, gs, d_probs, chunk, outer_mask, false);
+  while (c->branch.size() < gs.size()) {
+    hipStream_t b = nullptr;
+    HIPTRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    c->branch.push_back(b);
+  }
+  while (c->branch_ev.size() < gs.size() + 1) {
+    hipEvent_t e = nullptr;
+    HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->branch_ev.push_back(e);
+  }
+  HIPTRY(hipEventRecord(c->branch_ev[0], q));
+  for (size_t g = 0; g < gs.size(); ++g) {
+    hipStream_t b = c->branch[g];
+    HIPTRY(hipStreamWaitEvent(b, c->branch_ev[0], 0));
+    const std::vector<LaunchGroup> one{gs[g]};
+    if (int e = enqueue_round(c, b, f32, pc, one, d_probs, chunk, outer_mask, false)) return e;
+    HIPTRY(hipEventRecord(c->branch_ev[1 + g], b));
+  }
+  for (size_t g = 0; g < gs.size(); ++g) HIPTRY(hipStreamWaitEvent(q, c->branch_ev[1 + g], 0));
   return GP_OK;
 }
 
@@ -559,13 +586,13 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
     if (outer_only) {
       if (!graphs) return enqueue_outer(c, s, f32, pc, groups, c->d_probs, true);
       return replay(layout_key + "|outer",
-                    [&](hipStream_t q) { return enqueue_outer(c, q, f32, pc, groups, c->d_probs, false); });
+                    [&](hipStream_t q) { return enqueue_round_branched(c, q, f32, pc, groups, c->d_probs, 0, 1); });
     }
     const int n = round_len;
     const uint64_t m = round_mask;
     if (!graphs) return enqueue_round(c, s, f32, pc, groups, c->d_probs, n, m, true);
     return replay(layout_key + "|round" + std::to_string(n) + "/" + std::to_string(m),
-                  [&](hipStream_t q) { return enqueue_round(c, q, f32, pc, groups, c->d_probs, n, m, false); });
+                  [&](hipStream_t q) { return enqueue_round_branched(c, q, f32, pc, groups, c->d_probs, n, m); });
   };
   // host copy of every right-hand side's state
   std::vector<RhsState> hs(totalR);
@@ -807,6 +834,8 @@ int gp_ctx_destroy(gp_ctx* c) {
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipStream_t b : c->branch) (void)hipStreamDestroy(b);
+  for (hipEvent_t e : c->branch_ev) (void)hipEventDestroy(e);
   delete c;
   return GP_OK;
 }

@@ -62,6 +62,10 @@ struct gp_ctx {
   gp_prof acc[GP_KERNEL_KINDS] = {};
   // captured launch sequences, keyed by the grouped-launch layout
   hipStream_t cap_stream = nullptr;
+  // branch streams and fork/join events for capturing the launch groups of a
+  // round as parallel graph branches (default priority, non-blocking)
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> branch_ev;   // [0] fork, [1 + g] join of branch g
   std::map<std::string, hipGraphExec_t> graphs;
   bool use_graphs = true;
   // autotuned configurations keyed by tune_key()
@@ -145,13 +149,19 @@ int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
                   const Prob* d_probs, bool profiled);
 int enqueue_inner(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, int iters, bool profiled);
-// One solver round of `chunk` iterations.  Iteration i (0-based) is preceded
+// One solver round of `chunk` iterations (chunk = 0: the outer step alone,
+// when bit 0 of outer_mask is set).  Iteration i (0-based) is preceded
 // by the outer step ([x += d, refine, finalise] for right-hand sides waiting
 // on it) when bit i of outer_mask is set: with FP32 inner solves, which end
 // every few iterations, the host places it where inner solves are expected to
 // end, so a right-hand side rarely idles until the next round.
 int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, int chunk, uint64_t outer_mask, bool profiled);
+// The same round with each launch group on a branch stream forked from q and
+// joined back into it (used while capturing, so that the groups of an uneven
+// batch become parallel graph branches).
+int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                           const Prob* d_probs, int chunk, uint64_t outer_mask);
 
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);
