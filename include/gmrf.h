@@ -70,6 +70,7 @@ extern "C" {
 
 typedef struct gp_ctx gp_ctx;
 typedef struct gp_op gp_op;
+typedef struct gp_data gp_data;
 
 /* Solver options.  Initialise with gp_opts_default(). */
 typedef struct gp_opts {
@@ -124,7 +125,8 @@ typedef struct gp_item {
 #define GP_KERNEL_PROBE    7  /* probe -> FP64 right-hand side                 */
 #define GP_KERNEL_TRACE    8  /* Hutchinson reductions                         */
 #define GP_KERNEL_APPLY    9  /* FP64 y = Q x                                  */
-#define GP_KERNEL_KINDS   10
+#define GP_KERNEL_DATA    10  /* data tensors and data-term assembly          */
+#define GP_KERNEL_KINDS   11
 
 /* Accumulated per kernel kind while profiling is enabled.  `units` counts
  * (right-hand side, voxel) pairs processed; `bytes` is the algorithmic HBM
@@ -175,6 +177,32 @@ int gp_op_create(gp_ctx* ctx, const uint8_t* mask_host, int nx, int ny, int nz,
  * *bad_voxel_host (if non-NULL) receives the smallest failing voxel.
  * Marks the preconditioner stale; the next solve rebuilds it.              */
 int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel_host);
+
+/* ---- data term on the device (Appendix A.2, Appendix B) ------------------
+ * gp_data_create: precompute, once per dataset, the time-summed data of the
+ * AR(P) likelihood conditional on the first P scans (Appendix A.2, the tensors
+ * it isolates from the Gibbs loop): globally X'X, R = X'X~ and S = X~X~, per
+ * voxel Y_n'X, B~_n = Y_n'X~ + d_n X and D_n = d_n X~, where X~ is the lagged
+ * design (lag p+1 in slot p) and d_n the lagged data.  X_host: host, T x K
+ * row-major, the design of the operator's K regressors.  Y: device, FP64
+ * [T][N], the data of the operator's voxels in its voxel order.  Requires
+ * 0 <= P <= 4, T > P and T*K <= 8192.  The tensors live on the device under
+ * the context's budget until gp_data_destroy.  Blocking.                  */
+int gp_data_create(gp_op* op, int T, int P, const double* X_host, const double* Y, gp_data** out);
+
+/* gp_data_assemble: the data term from the tensors, for noise precisions
+ * lambda (device, N) and Ns >= 1 draws of the AR coefficients A (device,
+ * [Ns][P][N]; NULL when P = 0):
+ *   B_n = lambda_n (X'X - mean_j [R a + (R a)' - a' S a]),
+ *   b_n = lambda_n (Y_n'X - mean_j [a' B~_n - a' D_n a]),   a = A[j][.][n]
+ * -- the full conditional of W for Ns = 1 (Appendix A.2) and its SVB
+ * expectation over Monte Carlo draws for Ns > 1 (Appendix B).  The blocks
+ * are installed in the operator as gp_op_set_blocks does (factorised,
+ * GP_ERR_NOT_SPD with *bad_voxel_host on failure); b_n is written to bw
+ * (device, FP64 [K][N], the k-major b_w; may be NULL).  Blocking.          */
+int gp_data_assemble(gp_data* d, const double* lambda, int Ns, const double* A, double* bw,
+                     int64_t* bad_voxel_host);
+int gp_data_destroy(gp_data* d);
 
 /* gp_op_set_alpha: spatial precisions alpha_k >= 0 (host, K doubles; the
  * prior precision of regressor k, Section 2).  Marks the preconditioner (the

@@ -14,6 +14,11 @@ It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
   -- Section 2 (prior on W_k) and Section 3.1 (the G_w construction);
 * the per-voxel data term B_n, b_n of the AR(P) likelihood by explicit
   whitening -- Appendix A.2 (temporal likelihood, full conditional of W);
+* the time-summed data tensors of Appendix A.2 (Y_n'X, X'X, R = X'X~,
+  S = X~X~, B~_n = Y_n'X~ + d_n X, D_n = d_n X~) and the data term assembled
+  from them, and its SVB expectation over Monte Carlo draws of the AR
+  coefficients -- Appendix A.2 (full conditional of W) and Appendix B
+  (expectations b_w^SVB, B~^SVB);
 * the precision of w_r = vec(W') (k-major), Q = diag(alpha) (x) D_w + H'blkdiag(B_n)H
   -- Section 3, full conditional of w_r, and Appendix A.2;
 * mean solves x = Q^{-1} b -- Section 3.1 (PCG paragraph, relative residual
@@ -43,7 +48,8 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spl
 
 __all__ = [
-    "Grid", "grid", "data_term_whitening", "precision", "apply", "relres",
+    "Grid", "grid", "data_term_whitening", "data_term_mc", "data_tensors", "data_term_from_tensors",
+    "precision", "apply", "relres",
     "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
     "sample", "hutchinson", "cholesky_mean_and_sample",
 ]
@@ -132,6 +138,70 @@ def data_term_whitening(X: np.ndarray, Y: np.ndarray, ar: np.ndarray, sigma2: np
         lam = 1.0 / sigma2[n]
         B[n] = lam * (Xw.T @ Xw)
         bw[:, n] = lam * (Xw.T @ yw)
+    return B, bw
+
+
+def data_term_mc(X: np.ndarray, Y: np.ndarray, A: np.ndarray, lam: np.ndarray):
+    """Average of the whitening data term over Monte Carlo draws of the AR
+    coefficients with the noise precision held at lam -- the SVB expectations
+    b_w^SVB and the data part of B~^SVB of Appendix B, which are the plain
+    mean of the full-conditional quantities over the draws A[j] (P, N) because
+    lambda enters linearly.  A has shape (Ns, P, N)."""
+    Ns = A.shape[0]
+    B = 0.0
+    bw = 0.0
+    for j in range(Ns):
+        Bj, bj = data_term_whitening(X, Y, A[j], 1.0 / lam)
+        B = B + Bj
+        bw = bw + bj
+    return B / Ns, bw / Ns
+
+
+def data_tensors(X: np.ndarray, Y: np.ndarray, P: int):
+    """The time-summed data of Appendix A.2, conditional on the first P scans.
+
+    With the lagged design X~[t] (P x K, row p = X[t-p]) and lagged data
+    d_t (P, entry p = y[t-p]) over scans t = P..T-1 (0-based), and X, y at
+    those scans:
+      XX = X'X (K x K); R = X'X~ (K x K x P); S = X~X~ (P x K x K x P);
+      YX[n] = Y_n'X (K); Bt[n] = Y_n'X~ + d_n X (P x K); Dt[n] = d_n X~ (P x K x P).
+    Returns (XX, R, S, YX (N, K), Bt (N, P, K), Dt (N, P, K, P)).
+    """
+    T, K = X.shape
+    N = Y.shape[1]
+    ts = np.arange(P, T)
+    Xt = np.stack([X[ts - p] for p in range(1, P + 1)], axis=1)          # (T-P, P, K)
+    Xc = X[ts]                                                             # (T-P, K)
+    XX = Xc.T @ Xc
+    R = np.einsum("tk,tpj->kjp", Xc, Xt)
+    S = np.einsum("tpk,tqj->pkjq", Xt, Xt)
+    YX = np.empty((N, K)); Bt = np.empty((N, P, K)); Dt = np.empty((N, P, K, P))
+    for n in range(N):
+        y = Y[ts, n]
+        d = np.stack([Y[ts - p, n] for p in range(1, P + 1)], axis=1)     # (T-P, P)
+        YX[n] = y @ Xc
+        Bt[n] = np.einsum("t,tpk->pk", y, Xt) + d.T @ Xc
+        Dt[n] = np.einsum("tp,tqk->pkq", d, Xt)
+    return XX, R, S, YX, Bt, Dt
+
+
+def data_term_from_tensors(tensors, A: np.ndarray, lam: np.ndarray):
+    """Appendix A.2 (and its Appendix B expectation over draws A (Ns, P, N)):
+    B_n = lambda_n (X'X - mean_j [R A_n + (R A_n)' - A_n' S A_n]),
+    b_n = lambda_n (Y_n'X - mean_j [A_n' B~_n - A_n' D_n A_n])."""
+    XX, R, S, YX, Bt, Dt = tensors
+    N, K = YX.shape
+    Ns = A.shape[0]
+    B = np.empty((N, K, K)); bw = np.empty((K, N))
+    for n in range(N):
+        Bd = np.zeros((K, K)); bd = np.zeros(K)
+        for j in range(Ns):
+            a = A[j, :, n]
+            RA = np.einsum("kjp,p->kj", R, a)
+            Bd += RA + RA.T - np.einsum("p,pkjq,q->kj", a, S, a)
+            bd += a @ Bt[n] - np.einsum("p,pkq,q->k", a, Dt[n], a)
+        B[n] = lam[n] * (XX - Bd / Ns)
+        bw[:, n] = lam[n] * (YX[n] - bd / Ns)
     return B, bw
 
 

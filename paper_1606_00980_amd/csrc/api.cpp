@@ -180,17 +180,6 @@ void prof_add(gp_ctx* c, int kind, double units, double bytes) {
   c->acc[kind].bytes += bytes;
 }
 
-#define PROFILED(ctx, kind, launch)                                  \
-  do {                                                               \
-    size_t slot_ = 0;                                                \
-    if ((ctx)->prof_on) {                                            \
-      if (int st_ = prof_begin((ctx), &slot_)) return st_;           \
-    }                                                                \
-    HIPTRY(launch);                                                  \
-    if ((ctx)->prof_on) {                                            \
-      if (int st_ = prof_end((ctx), (kind), slot_)) return st_;      \
-    }                                                                \
-  } while (0)
 
 OpDev op_dev(const gp_op* op) {
   OpDev d;
@@ -969,6 +958,16 @@ int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
   BusyGuard guard(c);
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
+  return install_blocks(op, B, bad_voxel);
+}
+
+}  // extern "C"
+
+namespace gp {
+namespace rt {
+
+int install_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
+  gp_ctx* c = op->ctx;
   if (int st = reset_bad(op)) return st;
   PROFILED(c, GP_KERNEL_PACK, launch_pack_blocks(c->stream, op->K, op->N, B, op->B64, op->B32, op->L64, op->d_bad));
   {
@@ -986,6 +985,11 @@ int gp_op_set_blocks(gp_op* op, const double* B, int64_t* bad_voxel) {
   op->have_blocks = true;
   return GP_OK;
 }
+
+}  // namespace rt
+}  // namespace gp
+
+extern "C" {
 
 int gp_op_set_alpha(gp_op* op, const double* alpha) {
   if (!op || !alpha) return fail(GP_ERR_INVALID_ARG, "op or alpha is NULL");

@@ -29,6 +29,13 @@ hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, 
 hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks);
 int finalize_rhs_per_block();
 
+// k_data.hip: time-summed AR(P) data tensors and the data term assembled from them
+hipError_t launch_data_tensors(hipStream_t s, int T, int K, int P, int N, const double* X, const double* Y,
+                               double* G, double* YX, double* Bt, double* Dt);
+hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* YX,
+                                const double* Bt, const double* Dt, const double* lambda, const double* A,
+                                double* Bout, double* bw);
+
 // k_rng.hip: Philox4x32-10 normals, Rademacher signs and raw words
 hipError_t launch_rng_normal(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double* out);
 hipError_t launch_rng_rademacher(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, int8_t* out);

@@ -163,11 +163,31 @@ int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
 int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                            const Prob* d_probs, int chunk, uint64_t outer_mask);
 
+// Per-launch event timing while profiling is on (gp_ctx_profile).
+int prof_begin(gp_ctx* c, size_t* slot);
+int prof_end(gp_ctx* c, int kind, size_t slot);
+int prof_resolve(gp_ctx* c);
+void prof_add(gp_ctx* c, int kind, double units, double bytes);
+#define PROFILED(ctx, kind, launch)                                  \
+  do {                                                               \
+    size_t slot_ = 0;                                                \
+    if ((ctx)->prof_on) {                                            \
+      if (int st_ = prof_begin((ctx), &slot_)) return st_;           \
+    }                                                                \
+    HIPTRY(launch);                                                  \
+    if ((ctx)->prof_on) {                                            \
+      if (int st_ = prof_end((ctx), (kind), slot_)) return st_;      \
+    }                                                                \
+  } while (0)
+
 int set_device(gp_ctx* c);
 int dev_alloc(gp_ctx* c, size_t bytes, void** p);
 void dev_free(gp_ctx* c, void* p, size_t bytes);
 OpDev op_dev(const gp_op* op);
 int build_precond(gp_op* op, int pc);
+// Pack, factor and SPD-check device blocks B ([N][K][K] FP64) into op, as
+// gp_op_set_blocks does (the caller holds the context).
+int install_blocks(gp_op* op, const double* B, int64_t* bad_voxel);
 bool valid_opts(const gp_opts& o, std::string* why);
 
 }  // namespace rt

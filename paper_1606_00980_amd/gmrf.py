@@ -46,6 +46,7 @@ EXPORTS = [
     "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
     "gp_autotune", "gp_tune_save", "gp_tune_load",
+    "gp_data_create", "gp_data_assemble", "gp_data_destroy",
 ]
 
 GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
@@ -72,7 +73,7 @@ class GpProf(ctypes.Structure):
 
 
 KERNEL_KINDS = ["refine", "matvec", "update", "addsol", "perturb", "precond", "pack",
-                "probe", "trace", "apply"]
+                "probe", "trace", "apply", "data"]
 
 
 class GpItem(ctypes.Structure):
@@ -159,6 +160,9 @@ def _load() -> ctypes.CDLL:
         "gp_autotune": (i32, [vp, i32, P(GpOpts), P(GpOpts)]),
         "gp_tune_save": (i32, [vp, ctypes.c_char_p]),
         "gp_tune_load": (i32, [vp, ctypes.c_char_p]),
+        "gp_data_create": (i32, [vp, i32, i32, P(dbl), vp, P(vp)]),
+        "gp_data_assemble": (i32, [vp, vp, i32, vp, vp, P(i64)]),
+        "gp_data_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -254,6 +258,28 @@ def gp_op_set_blocks(op: int, B) -> None:
         err = GmrfError(st, "gp_op_set_blocks", gp_last_error())
         err.bad_voxel = bad.value
         raise err
+
+
+def gp_data_create(op: int, T: int, P: int, X, Y) -> int:
+    """X: host (T, K) array; Y: device (T, N) FP64 tensor."""
+    x = np.ascontiguousarray(X, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib.gp_data_create(op, T, P, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(Y),
+                              ctypes.byref(h)), "gp_data_create")
+    return h.value
+
+
+def gp_data_assemble(d: int, lam, Ns: int, A, bw=None) -> None:
+    bad = ctypes.c_int64(-1)
+    st = lib.gp_data_assemble(d, _ptr(lam), Ns, _ptr(A), _ptr(bw), ctypes.byref(bad))
+    if st != GP_OK:
+        err = GmrfError(st, "gp_data_assemble", gp_last_error())
+        err.bad_voxel = bad.value
+        raise err
+
+
+def gp_data_destroy(d: int) -> None:
+    _check(lib.gp_data_destroy(d), "gp_data_destroy")
 
 
 def gp_op_set_alpha(op: int, alpha) -> None:

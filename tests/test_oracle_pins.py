@@ -154,45 +154,59 @@ def test_golden_perturbation():
 
 
 # ------------------------------------------------------------------ data term
-def tensor_route(X, Y, ar, sigma2):
-    """Appendix A.2 precomputed-tensor form:
-    B_n = lambda_n (X'X - R A_n - (R A_n)' + A_n' S A_n),
-    b_n = lambda_n (Y_n'X - A_n' B~_n + A_n' D_n A_n), with the lagged design
-    Xt[t] (P x K) and lagged data d_t (P), over scans t = P..T-1."""
-    T, K = X.shape
-    P, N = ar.shape
-    ts = np.arange(P, T)
-    Xt = np.stack([X[ts - p] for p in range(1, P + 1)], axis=1)          # (T-P, P, K)
-    Xc = X[ts]                                                             # (T-P, K)
-    XX = Xc.T @ Xc
-    Rt = np.einsum("tk,tpj->kjp", Xc, Xt)                                  # K x K x P
-    S = np.einsum("tpk,tqj->pkjq", Xt, Xt)                                 # P x K x K x P
-    Bs = np.empty((N, K, K)); bs = np.empty((K, N))
-    for n in range(N):
-        a = ar[:, n]
-        y = Y[ts, n]
-        d = np.stack([Y[ts - p, n] for p in range(1, P + 1)], axis=1)     # (T-P, P)
-        RA = np.einsum("kjp,p->kj", Rt, a)
-        ASA = np.einsum("p,pkjq,q->kj", a, S, a)
-        lam = 1.0 / sigma2[n]
-        Bs[n] = lam * (XX - RA - RA.T + ASA)
-        Bn = y @ Xt.reshape(len(ts), -1)
-        Bn = Bn.reshape(P, K) + d.T @ Xc                                     # P x K
-        Dn = np.einsum("tp,tqk->pkq", d, Xt)                                 # P x K x P
-        bs[:, n] = lam * (y @ Xc - a @ Bn + np.einsum("p,pkq,q->k", a, Dn, a))
-    return Bs, bs
-
-
 @pytest.mark.parametrize("P", [1, 3])
 def test_data_term_whitening_equals_tensor_route(P):
     w = synth.tiny((6, 5, 4), 6, 4, seed=P, T=50, P=P)
     B1, b1 = orc.data_term_whitening(w.X, w.Y, w.ar, w.sigma2)
-    B2, b2 = tensor_route(w.X, w.Y, w.ar, w.sigma2)
+    B2, b2 = orc.data_term_from_tensors(orc.data_tensors(w.X, w.Y, P), w.ar[None], 1.0 / w.sigma2)
     assert np.allclose(B1, B2, rtol=1e-12, atol=1e-12 * np.abs(B1).max())
     assert np.allclose(b1, b2, rtol=1e-12, atol=1e-12 * np.abs(b1).max())
     # the generator's data term is the same quantity
     assert np.allclose(w.B, B1, rtol=1e-11, atol=1e-11 * np.abs(B1).max())
     assert np.allclose(w.bw, b1, rtol=1e-11, atol=1e-11 * np.abs(b1).max())
+
+
+def test_data_tensors_by_brute_force():
+    """Each tensor entry as a plain double loop over scans (t, p, q)."""
+    w = synth.tiny((4, 3, 2), 6, 3, seed=5, T=30, P=2)
+    P, (T, K) = 2, w.X.shape
+    XX, R, S, YX, Bt, Dt = orc.data_tensors(w.X, w.Y, P)
+    X, Y = w.X, w.Y
+    for k in range(K):
+        for j in range(K):
+            assert np.isclose(XX[k, j], sum(X[t, k] * X[t, j] for t in range(P, T)))
+            for p in range(P):
+                assert np.isclose(R[k, j, p], sum(X[t, k] * X[t - p - 1, j] for t in range(P, T)))
+                for q in range(P):
+                    assert np.isclose(S[p, k, j, q], sum(X[t - p - 1, k] * X[t - q - 1, j] for t in range(P, T)))
+    for n in (0, w.N - 1):
+        for k in range(K):
+            assert np.isclose(YX[n, k], sum(Y[t, n] * X[t, k] for t in range(P, T)))
+            for p in range(P):
+                assert np.isclose(Bt[n, p, k], sum(Y[t, n] * X[t - p - 1, k] + Y[t - p - 1, n] * X[t, k]
+                                                   for t in range(P, T)))
+                for q in range(P):
+                    assert np.isclose(Dt[n, p, k, q], sum(Y[t - p - 1, n] * X[t - q - 1, k] for t in range(P, T)))
+
+
+def test_data_term_mc_average():
+    """The SVB expectation over draws is the mean of the full-conditional data
+    terms: equal draws give the single-draw term, and it is linear in lambda;
+    the tensor route gives the same average."""
+    w = synth.tiny((5, 4, 3), 6, 3, seed=8, T=40, P=3)
+    lam = 1.0 / w.sigma2
+    A = np.stack([w.ar, w.ar, w.ar])
+    B1, b1 = orc.data_term_mc(w.X, w.Y, A, lam)
+    B0, b0 = orc.data_term_whitening(w.X, w.Y, w.ar, w.sigma2)
+    assert np.allclose(B1, B0, rtol=1e-13) and np.allclose(b1, b0, rtol=1e-13)
+    rng = np.random.default_rng(3)
+    A = w.ar[None] + 0.1 * rng.standard_normal((4,) + w.ar.shape)
+    B2, b2 = orc.data_term_mc(w.X, w.Y, A, 2.0 * lam)
+    B3, b3 = orc.data_term_mc(w.X, w.Y, A, lam)
+    assert np.allclose(B2, 2 * B3, rtol=1e-13) and np.allclose(b2, 2 * b3, rtol=1e-13)
+    B4, b4 = orc.data_term_from_tensors(orc.data_tensors(w.X, w.Y, 3), A, lam)
+    assert np.allclose(B4, B3, rtol=1e-11, atol=1e-11 * np.abs(B3).max())
+    assert np.allclose(b4, b3, rtol=1e-11, atol=1e-11 * np.abs(b3).max())
 
 
 def test_slice_workload_data_term():
