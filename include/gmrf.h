@@ -202,7 +202,56 @@ int gp_data_create(gp_op* op, int T, int P, const double* X_host, const double* 
  * (device, FP64 [K][N], the k-major b_w; may be NULL).  Blocking.          */
 int gp_data_assemble(gp_data* d, const double* lambda, int Ns, const double* A, double* bw,
                      int64_t* bad_voxel_host);
+
+/* gp_data_lambda: the noise-precision posterior (Appendix A.2, full
+ * conditional of lambda; Appendix B for its SVB form): per voxel, the mean
+ * over Ns pairs (W^j, A^j) of the whitened residual sum of squares
+ *   rss_n = Y'Y - 2Y'XW + W'X'XW - 2Y'd'A + A'dd'A + 2A'B~W - 2W'(RA)W
+ *           - 2A'(DW)A + W'(A'SA)W        (W = W^j_{.,n}, A = A^j_{.,n}),
+ * then lambda_n ~ Ga(scale u1t_n, shape u2t) with 1/u1t_n = rss_n/2 + 1/u1 and
+ * u2t = (T-P)/2 + u2; mean = u1t_n * u2t.  W: device [Ns][K][N] (the k-major
+ * samples); A: device [Ns][P][N] (NULL when P = 0).  Outputs (device, N
+ * doubles each, any may be NULL): rss, scale, mean.  Blocking.            */
+int gp_data_lambda(gp_data* d, int Ns, const double* W, const double* A, double u1, double u2, double* rss,
+                   double* scale, double* mean);
 int gp_data_destroy(gp_data* d);
+
+/* Gamma prior parameters of alpha_k ~ Ga(q1, q2) and lambda_n ~ Ga(u1, u2)
+ * (scale, shape; Section 2).  gp_hyper_default: the values the paper uses,
+ * q1 = u1 = 10, q2 = u2 = 0.1.                                               */
+typedef struct gp_hyper {
+  double q1, q2, u1, u2;
+} gp_hyper;
+void gp_hyper_default(gp_hyper* h);
+
+/* gp_svb_step: one iteration of the spatial VB scheme for W, alpha and lambda
+ * with the AR coefficients held at Ns given draws (Section 3.3, Appendix B):
+ *   1. the data term with the current mean noise precisions lambda (device N)
+ *      and the draws A (device [Ns][P][N], NULL when P = 0), into the operator
+ *      and bw_work (device [K][N]);
+ *   2. alpha_host (K) as the spatial precisions;
+ *   3. Ns samples of q(W) by Algorithm 2 into W (device [Ns][K][N]), which
+ *      holds the previous samples as warm starts; z1, z2 as in gp_sample (the
+ *      same vectors every iteration, or NULL for device draws from
+ *      opts->seed, which repeat when the seed does);
+ *   4. alpha_host <- the posterior means of gp_alpha_posterior over the Ns
+ *      samples; lambda <- the posterior means of gp_data_lambda over the Ns
+ *      pairs (W^j, A^j).
+ * prior: NULL for gp_hyper_default.  stats: Ns entries of the sampling
+ * solves.  Blocking.                                                          */
+int gp_svb_step(gp_data* d, int Ns, const double* A, const double* z1, const double* z2, double* W,
+                double* lambda, double* alpha_host, const gp_hyper* prior, double* bw_work,
+                const gp_opts* opts, gp_stats* stats);
+
+/* gp_alpha_posterior: the spatial-precision posterior (Section 3.2 full
+ * conditional; Section 3.3 and Appendix B for the SVB Monte Carlo form):
+ * qf[r][k] = W_k D_w W_k' = ||G_w W_k'||^2 of each of R samples W (device,
+ * [R][K][N]), then alpha_k ~ Ga(scale_k, shape) with
+ * 1/scale_k = mean_r qf[r][k] / 2 + 1/q1 and shape = N/2 + q2; mean_k =
+ * scale_k * shape.  Outputs on the host: qf (R*K, may be NULL), scale (K),
+ * mean (K).  Blocking.                                                       */
+int gp_alpha_posterior(gp_op* op, int R, const double* W, double q1, double q2, double* qf_host,
+                       double* scale_host, double* mean_host);
 
 /* gp_op_set_alpha: spatial precisions alpha_k >= 0 (host, K doubles; the
  * prior precision of regressor k, Section 2).  Marks the preconditioner (the

@@ -26,6 +26,12 @@ It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
 * perturbation samples w = Q^{-1}(b_w + (blkdiag_k sqrt(alpha_k) G_w)' z1
   + H'L_data H z2) -- Algorithm 2;
 * Cholesky-based mean and sample -- Algorithm 1 (dense, tiny grids only);
+* the hyperparameter statistics and conjugate Gamma posteriors: the spatial
+  quadratic forms W_k D_w W_k' and 1/q~1k = W_k D_w W_k'/2 + 1/q1,
+  q~2 = N/2 + q2 (Section 3.2 full conditionals, Section 3.3 / Appendix B SVB
+  with the Monte Carlo mean over samples), and the whitened residual sum of
+  squares with 1/u~1n = rss_n/2 + 1/u1, u~2 = (T-P)/2 + u2 (Appendix A.2,
+  full conditional of lambda), Ga(scale, shape) with mean scale * shape;
 * Hutchinson estimates with Rademacher probes of tr(Q^{-1}), of tr([Q^{-1}]_kk)
   and of tr(D_w [Q^{-1}]_kk), the trace inside E[W_k D_w W_k'] of Section 3.3
   (quadratic-form expectation).
@@ -49,6 +55,8 @@ import scipy.sparse.linalg as spl
 
 __all__ = [
     "Grid", "grid", "data_term_whitening", "data_term_mc", "data_tensors", "data_term_from_tensors",
+    "data_tensors_noise", "quadform", "residual_ss", "residual_ss_from_tensors", "alpha_posterior",
+    "lambda_posterior", "svb_step",
     "precision", "apply", "relres",
     "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
     "sample", "hutchinson", "cholesky_mean_and_sample",
@@ -185,6 +193,19 @@ def data_tensors(X: np.ndarray, Y: np.ndarray, P: int):
     return XX, R, S, YX, Bt, Dt
 
 
+def data_tensors_noise(Y: np.ndarray, P: int):
+    """Per-voxel data tensors of the lambda full conditional (Appendix A.2),
+    over scans t = P..T-1: YY_n = y'y, dY_n[p] = sum_t y[t-1-p] y[t],
+    dd_n[p][q] = sum_t y[t-1-p] y[t-1-q].  Returns (YY (N), dY (N, P), dd (N, P, P))."""
+    T, N = Y.shape
+    ts = np.arange(P, T)
+    YY = np.einsum("tn,tn->n", Y[ts], Y[ts])
+    d = np.stack([Y[ts - p] for p in range(1, P + 1)], axis=1) if P > 0 else np.zeros((len(ts), 0, N))
+    dY = np.einsum("tpn,tn->np", d, Y[ts])
+    dd = np.einsum("tpn,tqn->npq", d, d)
+    return YY, dY, dd
+
+
 def data_term_from_tensors(tensors, A: np.ndarray, lam: np.ndarray):
     """Appendix A.2 (and its Appendix B expectation over draws A (Ns, P, N)):
     B_n = lambda_n (X'X - mean_j [R A_n + (R A_n)' - A_n' S A_n]),
@@ -203,6 +224,68 @@ def data_term_from_tensors(tensors, A: np.ndarray, lam: np.ndarray):
         B[n] = lam[n] * (XX - Bd / Ns)
         bw[:, n] = lam[n] * (YX[n] - bd / Ns)
     return B, bw
+
+
+# ------------------------------------------------------- hyperparameter statistics
+def quadform(g: Grid, W: np.ndarray) -> np.ndarray:
+    """W_k D_w W_k' = ||G_w W_k'||^2 for every sample r and regressor k of
+    W (R, K, N) in the k-major layout: the statistic of the alpha_k full
+    conditional (Section 3.2) and of its SVB Monte Carlo approximation."""
+    R, K, _ = W.shape
+    out = np.empty((R, K))
+    for r in range(R):
+        for k in range(K):
+            e = g.D @ W[r, k]
+            out[r, k] = e @ e
+    return out
+
+
+def residual_ss(X: np.ndarray, Y: np.ndarray, W: np.ndarray, ar: np.ndarray) -> np.ndarray:
+    """Whitened residual sum of squares per voxel, conditional on the first P
+    scans (Appendix A.2): rss_n = ||A_n (y_n - X w_n)||^2 with the whitening
+    rows [-a_P .. -a_1 1]; W is (K, N), ar is (P, N)."""
+    T, K = X.shape
+    P, N = ar.shape
+    e = Y - X @ W                                   # (T, N) residuals
+    out = np.empty(N)
+    for n in range(N):
+        w = e[P:, n].copy()
+        for p in range(1, P + 1):
+            w -= ar[p - 1, n] * e[P - p:T - p, n]
+        out[n] = w @ w
+    return out
+
+
+def residual_ss_from_tensors(tensors, extra, W: np.ndarray, ar: np.ndarray) -> np.ndarray:
+    """The bracket of the lambda full conditional in the tensor form of
+    Appendix A.2: Y'Y - 2Y'XW + W'X'XW - 2Y'd'A + A'dd'A + 2A'B~W
+    - 2W'(RA)W - 2A'(DW)A + W'(A'SA)W, with the extra per-voxel tensors
+    extra = (YY (N), dY (N, P) = d_n y_n, dd (N, P, P) = d_n d_n')."""
+    XX, R, S, YX, Bt, Dt = tensors
+    YY, dY, dd = extra
+    N = YY.shape[0]
+    out = np.empty(N)
+    for n in range(N):
+        w, a = W[:, n], ar[:, n]
+        RA = np.einsum("kjp,p->kj", R, a)
+        DW = np.einsum("pkq,k->pq", Dt[n], w)
+        ASA = np.einsum("p,pkjq,q->kj", a, S, a)
+        out[n] = (YY[n] - 2 * YX[n] @ w + w @ XX @ w - 2 * dY[n] @ a + a @ dd[n] @ a
+                  + 2 * a @ Bt[n] @ w - 2 * w @ RA @ w - 2 * a @ DW @ a + w @ ASA @ w)
+    return out
+
+
+def alpha_posterior(qf_mean: np.ndarray, N: int, q1: float, q2: float):
+    """Ga(q~1k, q~2) of alpha_k: 1/q~1k = qf_k/2 + 1/q1, q~2 = N/2 + q2
+    (qf_k = W_k D_w W_k', or its mean over samples for SVB)."""
+    q1t = 1.0 / (0.5 * np.asarray(qf_mean, dtype=float) + 1.0 / q1)
+    return q1t, N / 2.0 + q2
+
+
+def lambda_posterior(rss_mean: np.ndarray, T: int, P: int, u1: float, u2: float):
+    """Ga(u~1n, u~2) of lambda_n: 1/u~1n = rss_n/2 + 1/u1, u~2 = (T-P)/2 + u2."""
+    u1t = 1.0 / (0.5 * np.asarray(rss_mean, dtype=float) + 1.0 / u1)
+    return u1t, (T - P) / 2.0 + u2
 
 
 # ---------------------------------------------------------------------- operator
@@ -355,6 +438,25 @@ def cholesky_mean_and_sample(Q: sp.spmatrix, bw: np.ndarray, z: np.ndarray):
     mu = solve_triangular(L.T, x, lower=False)
     v = solve_triangular(L.T, np.asarray(z).ravel(), lower=False)
     return mu.reshape(np.shape(bw)), (mu + v).reshape(np.shape(bw))
+
+
+# ------------------------------------------------------------------ SVB iteration
+def svb_step(g: Grid, X, Y, A, z1, z2, alpha, lam, q1=10.0, q2=0.1, u1=10.0, u2=0.1, tol: float = 1e-13):
+    """One spatial-VB iteration with the AR coefficients held at the draws A
+    (Ns, P, N) (Section 3.3, Appendix B), in the paper's order: the data term
+    with the mean noise precisions lam and the draws; Ns Algorithm-2 samples
+    of q(W) with the random vectors z1 (Ns, K, dirs, N), z2 (Ns, K, N); the
+    posterior means of alpha (Monte Carlo mean of W_k D_w W_k') and of lambda
+    (Monte Carlo mean of the whitened residual sum of squares).
+    Returns (W (Ns, K, N), alpha_mean (K), lam_mean (N))."""
+    T = X.shape[0]
+    P = A.shape[1]
+    B, bw = data_term_mc(X, Y, A, lam)
+    W = sample(g, alpha, B, bw, z1, z2, tol)
+    q1t, q2t = alpha_posterior(quadform(g, W).mean(axis=0), g.N, q1, q2)
+    rss = np.mean([residual_ss(X, Y, W[j], A[j]) for j in range(W.shape[0])], axis=0)
+    u1t, u2t = lambda_posterior(rss, T, P, u1, u2)
+    return W, q1t * q2t, u1t * u2t
 
 
 # ---------------------------------------------------------------------- traces

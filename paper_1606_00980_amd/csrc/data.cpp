@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <string>
+#include <vector>
 
 #include "gmrf.h"
 #include "launch.hpp"
@@ -24,7 +25,10 @@ struct gp_data {
   double* Bt = nullptr;   // [P][K][N]
   double* Dt = nullptr;   // [P][K][P][N]
   double* Bw = nullptr;   // [N][K][K] assembled blocks, before packing
-  size_t nX = 0, nG = 0, nYX = 0, nBt = 0, nDt = 0, nBw = 0;
+  double* YY = nullptr;   // [N]
+  double* dY = nullptr;   // [P][N]
+  double* dd = nullptr;   // [P][P][N]
+  size_t nX = 0, nG = 0, nYX = 0, nBt = 0, nDt = 0, nBw = 0, nYY = 0, ndY = 0, ndd = 0;
 };
 
 namespace {
@@ -37,6 +41,9 @@ void release(gp_data* d) {
   dev_free(c, d->Bt, d->nBt * sizeof(double));
   dev_free(c, d->Dt, d->nDt * sizeof(double));
   dev_free(c, d->Bw, d->nBw * sizeof(double));
+  dev_free(c, d->YY, d->nYY * sizeof(double));
+  dev_free(c, d->dY, d->ndY * sizeof(double));
+  dev_free(c, d->dd, d->ndd * sizeof(double));
   delete d;
 }
 
@@ -68,17 +75,24 @@ int gp_data_create(gp_op* op, int T, int P, const double* X_host, const double* 
   d->nBt = std::max<size_t>(1, (size_t)P * K * N);
   d->nDt = std::max<size_t>(1, (size_t)P * K * P * N);
   d->nBw = (size_t)N * K * K;
+  d->nYY = (size_t)N;
+  d->ndY = std::max<size_t>(1, (size_t)P * N);
+  d->ndd = std::max<size_t>(1, (size_t)P * P * N);
   int st = GP_OK;
   if ((st = dev_alloc(c, d->nX * sizeof(double), (void**)&d->X)) || (st = dev_alloc(c, d->nG * sizeof(double), (void**)&d->G)) ||
       (st = dev_alloc(c, d->nYX * sizeof(double), (void**)&d->YX)) ||
       (st = dev_alloc(c, d->nBt * sizeof(double), (void**)&d->Bt)) ||
       (st = dev_alloc(c, d->nDt * sizeof(double), (void**)&d->Dt)) ||
-      (st = dev_alloc(c, d->nBw * sizeof(double), (void**)&d->Bw))) {
+      (st = dev_alloc(c, d->nBw * sizeof(double), (void**)&d->Bw)) ||
+      (st = dev_alloc(c, d->nYY * sizeof(double), (void**)&d->YY)) ||
+      (st = dev_alloc(c, d->ndY * sizeof(double), (void**)&d->dY)) ||
+      (st = dev_alloc(c, d->ndd * sizeof(double), (void**)&d->dd))) {
     release(d);
     return st;
   }
   hipError_t e = hipMemcpyAsync(d->X, X_host, d->nX * sizeof(double), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_data_tensors(c->stream, T, K, P, N, d->X, Y, d->G, d->YX, d->Bt, d->Dt);
+  if (e == hipSuccess)
+    e = launch_data_tensors(c->stream, T, K, P, N, d->X, Y, d->G, d->YX, d->Bt, d->Dt, d->YY, d->dY, d->dd);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     release(d);
@@ -107,6 +121,89 @@ int gp_data_assemble(gp_data* d, const double* lambda, int Ns, const double* A, 
     prof_add(c, GP_KERNEL_DATA, N, (double)N * per * 8.0);
   }
   return install_blocks(op, d->Bw, bad_voxel);
+}
+
+int gp_data_lambda(gp_data* d, int Ns, const double* W, const double* A, double u1, double u2, double* rss,
+                   double* scale, double* mean) {
+  if (!d || !W) return fail(GP_ERR_INVALID_ARG, "data or W is NULL");
+  if (Ns < 1) return fail(GP_ERR_INVALID_ARG, "Ns must be >= 1");
+  if (d->P > 0 && !A) return fail(GP_ERR_INVALID_ARG, "A is NULL while P > 0");
+  if (!(u1 > 0.0) || !(u2 >= 0.0)) return fail(GP_ERR_INVALID_ARG, "u1 > 0 and u2 >= 0 required");
+  gp_ctx* c = d->op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  const double u2t = 0.5 * (d->T - d->P) + u2;
+  PROFILED(c, GP_KERNEL_DATA,
+           launch_data_rss(c->stream, d->K, d->P, d->N, Ns, d->G, d->YX, d->Bt, d->Dt, d->YY, d->dY, d->dd, W, A, u1,
+                           u2t, rss, scale, mean));
+  {
+    const double K = d->K, P = d->P;
+    prof_add(c, GP_KERNEL_DATA, d->N,
+             (double)d->N * 8.0 * (K + P * K + P * K * P + 1 + P + P * P + Ns * (K + P) + 3));
+  }
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+int gp_alpha_posterior(gp_op* op, int R, const double* W, double q1, double q2, double* qf_host, double* scale_host,
+                       double* mean_host) {
+  if (!op || !W || !scale_host || !mean_host) return fail(GP_ERR_INVALID_ARG, "null argument");
+  if (R < 1) return fail(GP_ERR_INVALID_ARG, "R must be >= 1");
+  if (!(q1 > 0.0) || !(q2 >= 0.0)) return fail(GP_ERR_INVALID_ARG, "q1 > 0 and q2 >= 0 required");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  const int K = op->K, nrk = R * K, nt = quadform_tiles(op->N);
+  const size_t bytes = ((size_t)nrk * nt + nrk) * sizeof(double);
+  double* buf = nullptr;
+  if (int st = dev_alloc(c, bytes, (void**)&buf)) return st;
+  std::vector<double> qf(nrk);
+  hipError_t e = launch_quadform(c->stream, op_dev(op), R, W, buf, buf + (size_t)nrk * nt);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(qf.data(), buf + (size_t)nrk * nt, nrk * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, buf, bytes);
+  if (e != hipSuccess) return fail(GP_ERR_DEVICE, std::string("quadratic forms: ") + hipGetErrorString(e));
+  const double shape = 0.5 * op->N + q2;
+  for (int k = 0; k < K; ++k) {
+    double m = 0.0;
+    for (int r = 0; r < R; ++r) m += qf[(size_t)r * K + k];
+    m /= R;
+    scale_host[k] = 1.0 / (0.5 * m + 1.0 / q1);
+    mean_host[k] = scale_host[k] * shape;
+  }
+  if (qf_host) std::copy(qf.begin(), qf.end(), qf_host);
+  return GP_OK;
+}
+
+void gp_hyper_default(gp_hyper* h) {
+  if (!h) return;
+  h->q1 = 10.0;
+  h->q2 = 0.1;
+  h->u1 = 10.0;
+  h->u2 = 0.1;
+}
+
+int gp_svb_step(gp_data* d, int Ns, const double* A, const double* z1, const double* z2, double* W, double* lambda,
+                double* alpha_host, const gp_hyper* prior, double* bw_work, const gp_opts* opts, gp_stats* stats) {
+  if (!d || !W || !lambda || !alpha_host || !bw_work) return fail(GP_ERR_INVALID_ARG, "null argument");
+  if (Ns < 1) return fail(GP_ERR_INVALID_ARG, "Ns must be >= 1");
+  gp_hyper h;
+  if (prior) h = *prior; else gp_hyper_default(&h);
+  gp_op* op = d->op;
+  // q(W): data term with the current lambda and AR draws, prior alpha
+  if (int st = gp_data_assemble(d, lambda, Ns, A, bw_work, nullptr)) return st;
+  if (int st = gp_op_set_alpha(op, alpha_host)) return st;
+  // Ns samples by Algorithm 2, warm-started from W, with the caller's (fixed) random vectors
+  if (int st = gp_sample(op, Ns, bw_work, z1, z2, W, opts, stats)) return st;
+  // alpha and lambda from the samples' Monte Carlo statistics
+  std::vector<double> scale(op->K), mean(op->K);
+  if (int st = gp_alpha_posterior(op, Ns, W, h.q1, h.q2, nullptr, scale.data(), mean.data())) return st;
+  if (int st = gp_data_lambda(d, Ns, W, A, h.u1, h.u2, nullptr, nullptr, lambda)) return st;
+  std::copy(mean.begin(), mean.end(), alpha_host);
+  return GP_OK;
 }
 
 int gp_data_destroy(gp_data* d) {

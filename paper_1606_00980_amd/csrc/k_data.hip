@@ -10,9 +10,15 @@
 // Appendix B),
 //   B_n = lambda_n (XX - mean_j [R a + (R a)' - a' S a]),  a = A^j_n
 //   b_n = lambda_n (YX_n - mean_j [a' Bt_n - a' Dt_n a]).
+// The lambda full conditional also needs YY_n = y'y, dY_n[p] = sum_t y[t-1-p] y[t]
+// and dd_n[p][q] = sum_t y[t-1-p] y[t-1-q]; its bracket is the whitened
+// residual sum of squares
+//   rss_n = YY - 2 YX'w + w'XXw - 2 dY'a + a'dd a + 2 a'Bt w - 2 w'(R a)w
+//           - 2 a'(Dt w)a + w'(a'S a)w.
 // Layouts (device, voxel fastest): Y [T][N]; YX [K][N]; Bt [P][K][N];
-// Dt [P][K][P][N]; globals [XX | R | S] with R[k][l][p], S[p][k][l][q];
-// A [Ns][P][N]; output blocks [N][K][K] (both triangles) and b_w [K][N].
+// Dt [P][K][P][N]; YY [N]; dY [P][N]; dd [P][P][N]; globals [XX | R | S] with
+// R[k][l][p], S[p][k][l][q]; A [Ns][P][N]; W [Ns][K][N]; output blocks
+// [N][K][K] (both triangles) and b_w [K][N].
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -45,11 +51,13 @@ __global__ __launch_bounds__(DT) void k_data_globals(int T, int K, int P, const 
   G[e] = s;
 }
 
-// blockIdx.y = tensor entry (YX, then Bt, then Dt); threads over voxels.
+// blockIdx.y = tensor entry (YX, Bt, Dt, YY, dY, dd in that order); threads over voxels.
 // The design is staged in LDS (T*K doubles, dynamic).
 __global__ __launch_bounds__(DT) void k_data_tensors(int T, int K, int P, int N, const double* __restrict__ X,
                                                      const double* __restrict__ Y, double* __restrict__ YX,
-                                                     double* __restrict__ Bt, double* __restrict__ Dt) {
+                                                     double* __restrict__ Bt, double* __restrict__ Dt,
+                                                     double* __restrict__ YY, double* __restrict__ dY,
+                                                     double* __restrict__ dd) {
   extern __shared__ double sX[];
   for (int i = threadIdx.x; i < T * K; i += DT) sX[i] = X[i];
   __syncthreads();
@@ -67,10 +75,21 @@ __global__ __launch_bounds__(DT) void k_data_tensors(int T, int K, int P, int N,
     for (int t = P; t < T; ++t)
       s += y[(size_t)t * N + n] * sX[(t - 1 - p) * K + k] + y[(size_t)(t - 1 - p) * N + n] * sX[t * K + k];
     Bt[(size_t)i * N + n] = s;
-  } else {
+  } else if (e < K + P * K + P * K * P) {
     const int i = e - K - P * K, p = i / (K * P), k = (i / P) % K, q = i % P;
     for (int t = P; t < T; ++t) s += y[(size_t)(t - 1 - p) * N + n] * sX[(t - 1 - q) * K + k];
     Dt[(size_t)i * N + n] = s;
+  } else if (e == K + P * K + P * K * P) {
+    for (int t = P; t < T; ++t) s += y[(size_t)t * N + n] * y[(size_t)t * N + n];
+    YY[n] = s;
+  } else if (e < K + P * K + P * K * P + 1 + P) {
+    const int p = e - (K + P * K + P * K * P + 1);
+    for (int t = P; t < T; ++t) s += y[(size_t)(t - 1 - p) * N + n] * y[(size_t)t * N + n];
+    dY[(size_t)p * N + n] = s;
+  } else {
+    const int i = e - (K + P * K + P * K * P + 1 + P), p = i / P, q = i % P;
+    for (int t = P; t < T; ++t) s += y[(size_t)(t - 1 - p) * N + n] * y[(size_t)(t - 1 - q) * N + n];
+    dd[(size_t)i * N + n] = s;
   }
 }
 
@@ -126,16 +145,135 @@ __global__ __launch_bounds__(DT) void k_data_assemble(int K, int P, int N, int N
   }
 }
 
+// One thread per voxel: the Monte Carlo mean over the Ns pairs (W^j, A^j) of
+// the residual quadratic form, then the Gamma posterior of lambda_n:
+// 1/u1t = rss/2 + 1/u1, mean = u1t * u2t (u2t = (T-P)/2 + u2).
+__global__ __launch_bounds__(DT) void k_data_rss(int K, int P, int N, int Ns, const double* __restrict__ G,
+                                                 const double* __restrict__ YX, const double* __restrict__ Bt,
+                                                 const double* __restrict__ Dt, const double* __restrict__ YY,
+                                                 const double* __restrict__ dY, const double* __restrict__ dd,
+                                                 const double* __restrict__ Wall, const double* __restrict__ A,
+                                                 double u1, double u2t, double* __restrict__ rss_out,
+                                                 double* __restrict__ scale, double* __restrict__ mean) {
+  extern __shared__ double sG[];
+  const int nG = K * K + K * K * P + P * K * K * P;
+  for (int i = threadIdx.x; i < nG; i += DT) sG[i] = G[i];
+  __syncthreads();
+  const int n = blockIdx.x * DT + threadIdx.x;
+  if (n >= N) return;
+  const double* XX = sG;
+  const double* R = sG + K * K;
+  const double* S = R + K * K * P;
+  double w[KMAX], a[4];
+  double tot = 0.0;
+  for (int j = 0; j < Ns; ++j) {
+    for (int k = 0; k < K; ++k) w[k] = Wall[((size_t)j * K + k) * N + n];
+    for (int p = 0; p < P; ++p) a[p] = A[((size_t)j * P + p) * N + n];
+    double v = YY[n];
+    for (int k = 0; k < K; ++k) {
+      double xw = 0.0;
+      for (int l = 0; l < K; ++l) xw += XX[k * K + l] * w[l];
+      v += w[k] * xw - 2.0 * YX[(size_t)k * N + n] * w[k];
+    }
+    for (int p = 0; p < P; ++p) {
+      v -= 2.0 * dY[(size_t)p * N + n] * a[p];
+      for (int q = 0; q < P; ++q) v += a[p] * dd[((size_t)p * P + q) * N + n] * a[q];
+      for (int k = 0; k < K; ++k) {
+        v += 2.0 * a[p] * Bt[((size_t)p * K + k) * N + n] * w[k];
+        for (int q = 0; q < P; ++q) v -= 2.0 * a[p] * Dt[(((size_t)p * K + k) * P + q) * N + n] * w[k] * a[q];
+      }
+    }
+    for (int k = 0; k < K; ++k) {
+      for (int l = 0; l < K; ++l) {
+        double ra = 0.0, asa = 0.0;
+        for (int p = 0; p < P; ++p) {
+          ra += R[(k * K + l) * P + p] * a[p];
+          for (int q = 0; q < P; ++q) asa += a[p] * S[((p * K + k) * K + l) * P + q] * a[q];
+        }
+        v += w[k] * (asa - 2.0 * ra) * w[l];
+      }
+    }
+    tot += v;
+  }
+  const double rss = tot / Ns;
+  const double u1t = 1.0 / (0.5 * rss + 1.0 / u1);
+  if (rss_out) rss_out[n] = rss;
+  if (scale) scale[n] = u1t;
+  if (mean) mean[n] = u1t * u2t;
+}
+
+// Per (sample r, regressor k, tile): sum over the tile's voxels of the squared
+// differences to the in-mask +x, +y, +z neighbours (one term per adjacent
+// pair, so the total is W_k D_w W_k').  Fixed-order workgroup reduction.
+__global__ __launch_bounds__(DT) void k_quadform_partials(OpDev op, const double* __restrict__ W,
+                                                          double* __restrict__ part) {
+  __shared__ double s_red[DT / 64];
+  const int N = op.N;
+  const int tile = blockIdx.x, rk = blockIdx.y;
+  const int n = tile * DT + threadIdx.x;
+  double v = 0.0;
+  if (n < N) {
+    const double* w = W + (size_t)rk * N;
+    const double c = w[n];
+    for (int d = 0; d < op.dirs; ++d) {
+      const int m = op.nbr[(size_t)(2 * d + 1) * N + n];
+      if (m != n) {
+        const double e = c - w[m];
+        v += e * e;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x / 64] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < DT / 64; ++i) t += s_red[i];
+    part[(size_t)rk * gridDim.x + tile] = t;
+  }
+}
+
+// One wavefront per (r, k): the tile partials in a fixed order.
+__global__ __launch_bounds__(64) void k_quadform_final(int nrk, int ntiles, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+  const int rk = blockIdx.x;
+  if (rk >= nrk) return;
+  double v = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += 64) v += part[(size_t)rk * ntiles + t];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (threadIdx.x == 0) out[rk] = v;
+}
+
 }  // namespace
 
 hipError_t launch_data_tensors(hipStream_t s, int T, int K, int P, int N, const double* X, const double* Y,
-                               double* G, double* YX, double* Bt, double* Dt) {
+                               double* G, double* YX, double* Bt, double* Dt, double* YY, double* dY, double* dd) {
   const int nG = K * K + K * K * P + P * K * K * P;
   hipLaunchKernelGGL(k_data_globals, dim3((nG + DT - 1) / DT), dim3(DT), 0, s, T, K, P, X, G);
   if (hipError_t e = hipGetLastError()) return e;
-  const int entries = K + P * K + P * K * P;
+  const int entries = K + P * K + P * K * P + 1 + P + P * P;
   hipLaunchKernelGGL(k_data_tensors, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)T * K * sizeof(double), s,
-                     T, K, P, N, X, Y, YX, Bt, Dt);
+                     T, K, P, N, X, Y, YX, Bt, Dt, YY, dY, dd);
+  return hipGetLastError();
+}
+
+hipError_t launch_data_rss(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* YX,
+                           const double* Bt, const double* Dt, const double* YY, const double* dY, const double* dd,
+                           const double* W, const double* A, double u1, double u2t, double* rss, double* scale,
+                           double* mean) {
+  const int nG = K * K + K * K * P + P * K * K * P;
+  hipLaunchKernelGGL(k_data_rss, dim3((N + DT - 1) / DT), dim3(DT), (size_t)nG * sizeof(double), s, K, P, N, Ns, G, YX,
+                     Bt, Dt, YY, dY, dd, W, A, u1, u2t, rss, scale, mean);
+  return hipGetLastError();
+}
+
+int quadform_tiles(int N) { return (N + DT - 1) / DT; }
+
+hipError_t launch_quadform(hipStream_t s, const OpDev& op, int R, const double* W, double* part, double* out) {
+  const int nt = quadform_tiles(op.N), nrk = R * op.K;
+  hipLaunchKernelGGL(k_quadform_partials, dim3(nt, nrk), dim3(DT), 0, s, op, W, part);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(k_quadform_final, dim3(nrk), dim3(64), 0, s, nrk, nt, part, out);
   return hipGetLastError();
 }
 

@@ -31,7 +31,14 @@ int finalize_rhs_per_block();
 
 // k_data.hip: time-summed AR(P) data tensors and the data term assembled from them
 hipError_t launch_data_tensors(hipStream_t s, int T, int K, int P, int N, const double* X, const double* Y,
-                               double* G, double* YX, double* Bt, double* Dt);
+                               double* G, double* YX, double* Bt, double* Dt, double* YY, double* dY, double* dd);
+hipError_t launch_data_rss(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* YX,
+                           const double* Bt, const double* Dt, const double* YY, const double* dY, const double* dd,
+                           const double* W, const double* A, double u1, double u2t, double* rss, double* scale,
+                           double* mean);
+// W_k D_w W_k' for R samples: partials [R*K][quadform_tiles(N)], out [R*K] (device)
+int quadform_tiles(int N);
+hipError_t launch_quadform(hipStream_t s, const OpDev& op, int R, const double* W, double* part, double* out);
 hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* YX,
                                 const double* Bt, const double* Dt, const double* lambda, const double* A,
                                 double* Bout, double* bw);

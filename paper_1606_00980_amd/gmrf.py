@@ -46,7 +46,8 @@ EXPORTS = [
     "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
     "gp_autotune", "gp_tune_save", "gp_tune_load",
-    "gp_data_create", "gp_data_assemble", "gp_data_destroy",
+    "gp_data_create", "gp_data_assemble", "gp_data_lambda", "gp_data_destroy", "gp_alpha_posterior",
+    "gp_hyper_default", "gp_svb_step",
 ]
 
 GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
@@ -109,6 +110,11 @@ class GpServerStats(ctypes.Structure):
                 ("requests_per_s", ctypes.c_double)]
 
 
+class GpHyper(ctypes.Structure):
+    _fields_ = [("q1", ctypes.c_double), ("q2", ctypes.c_double), ("u1", ctypes.c_double),
+                ("u2", ctypes.c_double)]
+
+
 class GmrfError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -163,6 +169,10 @@ def _load() -> ctypes.CDLL:
         "gp_data_create": (i32, [vp, i32, i32, P(dbl), vp, P(vp)]),
         "gp_data_assemble": (i32, [vp, vp, i32, vp, vp, P(i64)]),
         "gp_data_destroy": (i32, [vp]),
+        "gp_data_lambda": (i32, [vp, i32, vp, vp, dbl, dbl, vp, vp, vp]),
+        "gp_alpha_posterior": (i32, [vp, i32, vp, dbl, dbl, P(dbl), P(dbl), P(dbl)]),
+        "gp_hyper_default": (None, [P(GpHyper)]),
+        "gp_svb_step": (i32, [vp, i32, vp, vp, vp, vp, vp, P(dbl), P(GpHyper), vp, P(GpOpts), P(GpStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -276,6 +286,44 @@ def gp_data_assemble(d: int, lam, Ns: int, A, bw=None) -> None:
         err = GmrfError(st, "gp_data_assemble", gp_last_error())
         err.bad_voxel = bad.value
         raise err
+
+
+def gp_data_lambda(d: int, Ns: int, W, A, u1: float, u2: float, rss=None, scale=None, mean=None) -> None:
+    _check(lib.gp_data_lambda(d, Ns, _ptr(W), _ptr(A), u1, u2, _ptr(rss), _ptr(scale), _ptr(mean)),
+           "gp_data_lambda")
+
+
+def gp_alpha_posterior(op: int, R: int, W, q1: float, q2: float, K: int):
+    """Returns (qf (R, K), scale (K), mean (K)) as numpy arrays."""
+    qf = np.empty(R * K); sc = np.empty(K); mn = np.empty(K)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.gp_alpha_posterior(op, R, _ptr(W), q1, q2, qf.ctypes.data_as(dp), sc.ctypes.data_as(dp),
+                                  mn.ctypes.data_as(dp)), "gp_alpha_posterior")
+    return qf.reshape(R, K), sc, mn
+
+
+def gp_hyper_default(**overrides) -> GpHyper:
+    h = GpHyper()
+    lib.gp_hyper_default(ctypes.byref(h))
+    for k, v in overrides.items():
+        setattr(h, k, v)
+    return h
+
+
+def gp_svb_step(d: int, Ns: int, A, z1, z2, W, lam, alpha, bw_work, prior: GpHyper | None = None,
+                opts: GpOpts | None = None, check: bool = True):
+    """One SVB iteration; alpha (numpy, K) and lam / W (device) are updated in
+    place.  Returns (status, per-sample stats)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    st_arr = _stats_array(Ns)
+    o = opts if opts is not None else gp_opts_default()
+    st = lib.gp_svb_step(d, Ns, _ptr(A), _ptr(z1), _ptr(z2), _ptr(W), _ptr(lam),
+                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         ctypes.byref(prior) if prior is not None else None, _ptr(bw_work), ctypes.byref(o), st_arr)
+    if check:
+        _check(st, "gp_svb_step")
+    alpha[:] = a
+    return st, _stats_list(st_arr, Ns)
 
 
 def gp_data_destroy(d: int) -> None:

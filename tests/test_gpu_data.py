@@ -1,6 +1,7 @@
-"""GPU parity of the data term assembled on the device (Appendix A.2 tensors,
-Appendix B Monte Carlo expectation) against the oracle's explicit-whitening
-definition, through the C ABI."""
+"""GPU parity, through the C ABI, of the data term assembled on the device
+(Appendix A.2 tensors, Appendix B Monte Carlo expectation) against the
+oracle's explicit-whitening definition, and of the hyperparameter updates
+(alpha and lambda posteriors, one SVB iteration) against the oracle's."""
 import numpy as np
 import pytest
 
@@ -125,6 +126,89 @@ def test_assembly_whole_brain(g, ctx, torch_cuda):
             g.gp_data_assemble(d, dev(torch_cuda, 1.0 / w.sigma2), 1, dev(torch_cuda, w.ar[None]), bw)
             assert np.allclose(bw.cpu().numpy(), w.bw, rtol=1e-10, atol=1e-10 * np.abs(w.bw).max())
             check_operator(g, torch_cuda, op, w, w.B, tol=1e-10)
+        finally:
+            g.gp_data_destroy(d)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
+
+
+# --------------------------------------------------- hyperparameter statistics
+def test_alpha_posterior_matches_oracle(g, ctx, torch_cuda):
+    for dims, conn in (((15, 12, 9), 6), ((20, 17, 1), 4)):
+        w = synth.tiny(dims, conn, 4, seed=51)
+        op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+        try:
+            W = np.random.default_rng(3).standard_normal((3, w.K, w.N)) + w.W_true[None]
+            qf, scale, mean = g.gp_alpha_posterior(op, 3, dev(torch_cuda, W), 10.0, 0.1, w.K)
+            grid = orc.grid(w.mask, w.conn)
+            qf_ref = orc.quadform(grid, W)
+            assert np.allclose(qf, qf_ref, rtol=1e-12)
+            s1, s2 = orc.alpha_posterior(qf_ref.mean(axis=0), w.N, 10.0, 0.1)
+            assert np.allclose(scale, s1, rtol=1e-12) and np.allclose(mean, s1 * s2, rtol=1e-12)
+        finally:
+            torch_cuda.cuda.synchronize()
+            g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("P", [0, 1, 3])
+def test_lambda_posterior_matches_oracle(g, ctx, torch_cuda, P):
+    w = synth.tiny((12, 10, 6), 6, 5, seed=61 + P, T=64, P=max(P, 1))
+    ar = w.ar[:P] if P > 0 else np.zeros((0, w.N))
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    try:
+        d = g.gp_data_create(op, w.X.shape[0], P, w.X, dev(torch_cuda, w.Y))
+        try:
+            rng = np.random.default_rng(9)
+            Ns = 2
+            W = w.W_true[None] + 0.1 * rng.standard_normal((Ns, w.K, w.N))
+            A = ar[None] + 0.05 * rng.standard_normal((Ns,) + ar.shape)
+            rss = torch_cuda.empty(w.N, dtype=torch_cuda.float64, device="cuda")
+            scale, mean = torch_cuda.empty_like(rss), torch_cuda.empty_like(rss)
+            g.gp_data_lambda(d, Ns, dev(torch_cuda, W), dev(torch_cuda, A) if P > 0 else None, 10.0, 0.1,
+                             rss, scale, mean)
+            ref = np.mean([orc.residual_ss(w.X, w.Y, W[j], A[j]) for j in range(Ns)], axis=0)
+            assert np.allclose(rss.cpu().numpy(), ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+            s1, s2 = orc.lambda_posterior(ref, w.X.shape[0], P, 10.0, 0.1)
+            assert np.allclose(scale.cpu().numpy(), s1, rtol=1e-9)
+            assert np.allclose(mean.cpu().numpy(), s1 * s2, rtol=1e-9)
+        finally:
+            g.gp_data_destroy(d)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
+
+
+def test_svb_steps_match_oracle(g, ctx, torch_cuda):
+    """Two SVB iterations (fixed random vectors, warm starts, AR draws held)
+    against the oracle's steps fed the same inputs."""
+    w = synth.tiny((14, 11, 7), 6, 3, seed=71, T=60, P=2)
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    try:
+        d = g.gp_data_create(op, w.X.shape[0], 2, w.X, dev(torch_cuda, w.Y))
+        try:
+            rng = np.random.default_rng(5)
+            Ns = 3
+            A = w.ar[None] + 0.05 * rng.standard_normal((Ns,) + w.ar.shape)
+            z1 = rng.standard_normal((Ns, w.K, 3, w.N))
+            z2 = rng.standard_normal((Ns, w.K, w.N))
+            alpha = np.array([1.0, 1.0, 1.0])
+            lam = 1.0 / w.sigma2.copy()
+            grid = orc.grid(w.mask, w.conn)
+            Wd = torch_cuda.zeros((Ns, w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            lam_d = dev(torch_cuda, lam)
+            bw = torch_cuda.empty((w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            a_gpu = alpha.copy()
+            a_ref, l_ref = alpha.copy(), lam.copy()
+            opts = g.gp_opts_default(tol=1e-10)
+            for it in range(2):
+                st, stats = g.gp_svb_step(d, Ns, dev(torch_cuda, A), dev(torch_cuda, z1), dev(torch_cuda, z2), Wd,
+                                          lam_d, a_gpu, bw, opts=opts)
+                assert all(s["status"] == g.GP_OK for s in stats)
+                W_ref, a_ref, l_ref = orc.svb_step(grid, w.X, w.Y, A, z1, z2, a_ref, l_ref)
+                assert np.linalg.norm(Wd.cpu().numpy() - W_ref) <= 1e-7 * np.linalg.norm(W_ref), it
+                assert np.allclose(a_gpu, a_ref, rtol=1e-6), (it, a_gpu, a_ref)
+                assert np.allclose(lam_d.cpu().numpy(), l_ref, rtol=1e-6), it
         finally:
             g.gp_data_destroy(d)
     finally:

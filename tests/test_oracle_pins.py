@@ -209,6 +209,144 @@ def test_data_term_mc_average():
     assert np.allclose(b4, b3, rtol=1e-11, atol=1e-11 * np.abs(b3).max())
 
 
+# ----------------------------------------------------- hyperparameter statistics
+def test_quadform_brute_force_over_grid_cells():
+    """W_k D_w W_k' as a loop over in-mask cells and their +x, +y, +z
+    neighbours in the mask (one term per adjacent pair)."""
+    for dims, conn in (((6, 5, 4), 6), ((7, 6, 1), 4)):
+        w = synth.tiny(dims, conn, 3, seed=11)
+        g = orc.grid(w.mask, conn)
+        W = np.random.default_rng(0).standard_normal((2, 3, w.N))
+        mask = w.mask.astype(bool)
+        idx = -np.ones(mask.shape, int)
+        idx[mask] = np.arange(w.N)
+        nz, ny, nx = mask.shape
+        ref = np.zeros((2, 3))
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    if not mask[z, y, x]:
+                        continue
+                    for dz, dy, dx in ((0, 0, 1), (0, 1, 0), (1, 0, 0)):
+                        z2, y2, x2 = z + dz, y + dy, x + dx
+                        if z2 < nz and y2 < ny and x2 < nx and mask[z2, y2, x2]:
+                            ref += (W[:, :, idx[z, y, x]] - W[:, :, idx[z2, y2, x2]]) ** 2
+        assert np.allclose(orc.quadform(g, W), ref, rtol=1e-13)
+
+
+@pytest.mark.parametrize("P", [1, 3])
+def test_residual_ss_identities(P):
+    """rss_n = yw'yw - 2 (b_n/lambda)'w + w'(B_n/lambda) w with the whitening data
+    term; the tensor form of the lambda full conditional gives the same; and a
+    noise-free Y = XW gives zero."""
+    w = synth.tiny((5, 4, 3), 6, 4, seed=20 + P, T=45, P=P)
+    Wt = np.random.default_rng(P).standard_normal((w.K, w.N)) + w.W_true
+    rss = orc.residual_ss(w.X, w.Y, Wt, w.ar)
+    B, bw = orc.data_term_whitening(w.X, w.Y, w.ar, np.ones(w.N))
+    T = w.X.shape[0]
+    for n in range(0, w.N, 7):
+        A = np.zeros((T - P, T))
+        for i, t in enumerate(range(P, T)):
+            A[i, t] = 1.0
+            for p in range(1, P + 1):
+                A[i, t - p] = -w.ar[p - 1, n]
+        yw = A @ w.Y[:, n]
+        ref = yw @ yw - 2 * bw[:, n] @ Wt[:, n] + Wt[:, n] @ B[n] @ Wt[:, n]
+        assert np.isclose(rss[n], ref, rtol=1e-10)
+    tens = orc.data_tensors(w.X, w.Y, P)
+    extra = orc.data_tensors_noise(w.Y, P)
+    assert np.allclose(orc.residual_ss_from_tensors(tens, extra, Wt, w.ar), rss, rtol=1e-9,
+                       atol=1e-9 * np.abs(rss).max())
+    assert np.allclose(orc.residual_ss(w.X, w.X @ Wt, Wt, w.ar), 0.0, atol=1e-12)
+
+
+def test_gamma_posteriors_by_numerical_integration():
+    """Mean of the unnormalised full conditional, integrated on a fine grid:
+    p(alpha | W) ~ alpha^(q2-1) e^(-alpha/q1) * alpha^(N/2) e^(-alpha qf/2);
+    p(lambda | .) ~ lambda^(u2-1) e^(-lambda/u1) * lambda^((T-P)/2) e^(-lambda rss/2).
+    Ga(scale, shape) has mean scale * shape."""
+    for qf, N, c1, c2 in ((37.5, 120, 10.0, 0.1), (2.0, 9, 10.0, 0.1), (400.0, 1000, 3.0, 2.0)):
+        s1, s2 = orc.alpha_posterior(np.array([qf]), N, c1, c2)
+        x = np.linspace(1e-9, 60 * s1[0] * s2, 400001)
+        logp = (c2 - 1 + N / 2.0) * np.log(x) - x / c1 - x * qf / 2.0
+        wgt = np.exp(logp - logp.max())
+        assert np.isclose((x * wgt).sum() / wgt.sum(), s1[0] * s2, rtol=1e-6)
+    for rss, T, P in ((55.0, 200, 3), (3.0, 30, 1)):
+        s1, s2 = orc.lambda_posterior(np.array([rss]), T, P, 10.0, 0.1)
+        x = np.linspace(1e-9, 60 * s1[0] * s2, 400001)
+        logp = (0.1 - 1 + (T - P) / 2.0) * np.log(x) - x / 10.0 - x * rss / 2.0
+        wgt = np.exp(logp - logp.max())
+        assert np.isclose((x * wgt).sum() / wgt.sum(), s1[0] * s2, rtol=1e-6)
+
+
+def test_svb_step_against_dense_recomputation():
+    """One SVB step on a tiny grid, recomputed densely and independently: the
+    precision assembled entry by entry from (alpha, B, D_w), the perturbed
+    right-hand side from an explicit incidence matrix and Cholesky factors,
+    dense solves, and the statistics by plain loops."""
+    w = synth.tiny((4, 3, 2), 6, 2, seed=13, T=30, P=1)
+    g = orc.grid(w.mask, 6)
+    N, K, T, P = w.N, w.K, w.X.shape[0], 1
+    rng = np.random.default_rng(4)
+    Ns = 2
+    A = w.ar[None] + 0.05 * rng.standard_normal((Ns, P, N))
+    lam = 1.0 / w.sigma2
+    alpha = np.array([0.7, 2.5])
+    z1 = rng.standard_normal((Ns, K, 3, N))
+    z2 = rng.standard_normal((Ns, K, N))
+    W, a_mean, l_mean = orc.svb_step(g, w.X, w.Y, A, z1, z2, alpha, lam)
+    # dense recomputation
+    mask = w.mask.astype(bool)
+    idx = -np.ones(mask.shape, int); idx[mask] = np.arange(N)
+    nz, ny, nx = mask.shape
+    edges = []      # (n, m, slot d) for m = n + e_d in the mask
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if mask[z, y, x]:
+                    for d, (dz, dy, dx) in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+                        z2_, y2, x2 = z + dz, y + dy, x + dx
+                        if z2_ < nz and y2 < ny and x2 < nx and mask[z2_, y2, x2]:
+                            edges.append((idx[z, y, x], idx[z2_, y2, x2], d))
+    Dm = np.zeros((len(edges), N))
+    for e, (n, m, _) in enumerate(edges):
+        Dm[e, n], Dm[e, m] = 1.0, -1.0
+    Lap = Dm.T @ Dm
+    Bd = np.zeros((N, K, K)); bd = np.zeros((K, N))
+    for j in range(Ns):
+        for n in range(N):
+            Aw = np.zeros((T - P, T))
+            for i, t in enumerate(range(P, T)):
+                Aw[i, t], Aw[i, t - 1] = 1.0, -A[j, 0, n]
+            Xw, yw = Aw @ w.X, Aw @ w.Y[:, n]
+            Bd[n] += lam[n] * Xw.T @ Xw / Ns
+            bd[:, n] += lam[n] * Xw.T @ yw / Ns
+    Qd = np.zeros((K * N, K * N))
+    for k in range(K):
+        Qd[k * N:(k + 1) * N, k * N:(k + 1) * N] += alpha[k] * Lap
+        for l in range(K):
+            Qd[k * N + np.arange(N), l * N + np.arange(N)] += Bd[:, k, l]
+    Wd = np.empty((Ns, K, N))
+    for j in range(Ns):
+        rhs = bd.copy()
+        for k in range(K):
+            ze = np.array([z1[j, k, dd, n] for (n, m, dd) in edges])
+            rhs[k] += np.sqrt(alpha[k]) * Dm.T @ ze
+        for n in range(N):
+            rhs[:, n] += np.linalg.cholesky(Bd[n]) @ z2[j, :, n]
+        Wd[j] = np.linalg.solve(Qd, rhs.ravel()).reshape(K, N)
+    assert np.allclose(W, Wd, rtol=1e-9, atol=1e-9 * np.abs(Wd).max())
+    qf = np.array([[Wd[j, k] @ Lap @ Wd[j, k] for k in range(K)] for j in range(Ns)]).mean(axis=0)
+    assert np.allclose(a_mean, (N / 2 + 0.1) / (qf / 2 + 1 / 10.0), rtol=1e-9)
+    rss = np.zeros(N)
+    for j in range(Ns):
+        e = w.Y - w.X @ Wd[j]
+        for n in range(N):
+            r = e[1:, n] - A[j, 0, n] * e[:-1, n]
+            rss[n] += r @ r / Ns
+    assert np.allclose(l_mean, ((T - P) / 2 + 0.1) / (rss / 2 + 1 / 10.0), rtol=1e-8)
+
+
 def test_slice_workload_data_term():
     w = synth.slice_2d()
     idx = np.random.default_rng(1).choice(w.N, 40, replace=False)
