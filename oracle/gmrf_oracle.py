@@ -32,6 +32,10 @@ It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
   with the Monte Carlo mean over samples), and the whitened residual sum of
   squares with 1/u~1n = rss_n/2 + 1/u1, u~2 = (T-P)/2 + u2 (Appendix A.2,
   full conditional of lambda), Ga(scale, shape) with mean scale * shape;
+* the incomplete Cholesky preconditioner M of Algorithm 2 (steps 6-7) as a
+  block IC(0) factor (K x K voxel blocks, zero fill outside Q's block
+  pattern) under a given voxel order, here the red-black two-colour order,
+  and PCG with it (Section 3.1);
 * Hutchinson estimates with Rademacher probes of tr(Q^{-1}), of tr([Q^{-1}]_kk)
   and of tr(D_w [Q^{-1}]_kk), the trace inside E[W_k D_w W_k'] of Section 3.3
   (quadratic-form expectation).
@@ -60,6 +64,7 @@ __all__ = [
     "precision", "apply", "relres",
     "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
     "sample", "hutchinson", "cholesky_mean_and_sample",
+    "redblack_order", "ic0_block", "ic0_redblack", "ic0_solve", "redblack_start", "solve_pcg_ic0",
 ]
 
 
@@ -375,6 +380,137 @@ def solve(Q: sp.csr_matrix, b: np.ndarray, tol: float = 1e-13, direct_limit: int
     flat = b.reshape(-1, Q.shape[0])
     out = np.stack([solve_pcg(Q, v, tol)[0] for v in flat])
     return out.reshape(b.shape)
+
+
+# ------------------------------------------------ incomplete Cholesky (block IC(0))
+def redblack_order(g: Grid) -> np.ndarray:
+    """Voxel order of the two-colour (red-black) numbering: voxels with even
+    x + y + z ("red") in increasing n, then those with odd x + y + z ("black").
+    Adjacent voxels differ by one in exactly one coordinate, so no edge joins
+    two voxels of one colour."""
+    red = (g.coords.sum(axis=1) % 2) == 0
+    return np.r_[np.flatnonzero(red), np.flatnonzero(~red)]
+
+
+def ic0_block(g: Grid, Q: sp.spmatrix, K: int, order: np.ndarray):
+    """Incomplete Cholesky factor with zero fill, in K x K voxel blocks, of the
+    precision Q (k-major, KN x KN) under the voxel order ``order`` -- the
+    preconditioner M of Algorithm 2 (step 6), with the incomplete Cholesky of
+    Section 3.1 taken blockwise on the grid graph.
+
+    Block (n, m) of Q holds the entries ((k, n), (j, m)); it is non-zero when
+    n == m or n, m are adjacent, which is the pattern L may use.  Elimination
+    runs over the voxels in ``order``: the pivot block is factored by Cholesky,
+    the blocks below it become A_ij L_jj^{-T}, and the Schur update
+    A_il -= L_ij L_lj' is kept only where (i, l) lies in the pattern; fill
+    outside it is dropped.  Dense and slow: tiny grids only.
+
+    Returns (L, perm): L is the sparse lower-triangular factor in the permuted
+    voxel-major order, row ``p*K + k`` for voxel order[p], regressor k; perm
+    maps that permuted index to the k-major index ``k*N + n``."""
+    N = g.N
+    Qd = np.asarray(Q.todense()).reshape(K, N, K, N)
+    pos = np.empty(N, dtype=np.int64)
+    pos[order] = np.arange(N)
+    adj = [set() for _ in range(N)]                 # adjacency in permuted positions
+    for lo, hi in zip(g.edge_lo, g.edge_hi):
+        adj[pos[lo]].add(pos[hi])
+        adj[pos[hi]].add(pos[lo])
+
+    def block(i, j):
+        return Qd[:, order[i], :, order[j]].copy()
+
+    A = {}
+    for i in range(N):
+        A[(i, i)] = block(i, i)
+        for j in adj[i]:
+            if j < i:
+                A[(i, j)] = block(i, j)
+    L = {}
+    for j in range(N):
+        Ljj = np.linalg.cholesky(A[(j, j)])
+        L[(j, j)] = Ljj
+        below = sorted(i for i in adj[j] if i > j)
+        for i in below:
+            # L_ij = A_ij L_jj^{-T}, i.e. L_jj L_ij' = A_ij'
+            L[(i, j)] = np.linalg.solve(Ljj, A[(i, j)].T).T
+        for i in below:
+            for l in below:
+                if l <= i and (i, l) in A:
+                    A[(i, l)] -= L[(i, j)] @ L[(l, j)].T
+    rows, cols, vals = [], [], []
+    for (i, j), blk in L.items():
+        for k in range(K):
+            for c in range(K):
+                if blk[k, c] != 0.0 or (i == j and k == c):
+                    rows.append(i * K + k)
+                    cols.append(j * K + c)
+                    vals.append(blk[k, c])
+    Lp = sp.csr_matrix((vals, (rows, cols)), shape=(N * K, N * K))
+    perm = (np.arange(K)[None, :] * N + order[:, None]).ravel()   # p*K + k -> k*N + order[p]
+    return Lp, perm
+
+
+def ic0_redblack(g: Grid, alpha: np.ndarray, B: np.ndarray):
+    """Block IC(0) of Q = diag(alpha) (x) D_w + H'blkdiag(B_n)H on the
+    red-black voxel order.  Returns (L, perm) as ic0_block."""
+    K = B.shape[1]
+    return ic0_block(g, precision(g, alpha, B), K, redblack_order(g))
+
+
+def ic0_solve(L: sp.csr_matrix, perm: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = M^{-1} r with M = L L': a forward solve with L and a backward solve
+    with L' in the permuted order."""
+    rp = np.asarray(r, dtype=np.float64).ravel()[perm]
+    y = spl.spsolve_triangular(L, rp, lower=True)
+    zp = spl.spsolve_triangular(sp.csr_matrix(L.T), y, lower=False)
+    z = np.empty_like(zp)
+    z[perm] = zp
+    return z
+
+
+def redblack_start(g: Grid, Q: sp.spmatrix, b: np.ndarray, x0: np.ndarray) -> np.ndarray:
+    """Start value with the black entries of x0 and the red entries solved from
+    the red rows of Q x = b, so that those rows of b - Q x vanish."""
+    K = Q.shape[0] // g.N
+    red = (g.coords.sum(axis=1) % 2) == 0
+    R_idx = (np.arange(K)[:, None] * g.N + np.flatnonzero(red)[None, :]).ravel()
+    B_idx = (np.arange(K)[:, None] * g.N + np.flatnonzero(~red)[None, :]).ravel()
+    Qc = sp.csr_matrix(Q)
+    x = np.asarray(x0, dtype=np.float64).ravel().copy()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    rhs = b[R_idx] - Qc[R_idx][:, B_idx] @ x[B_idx]
+    x[R_idx] = spl.spsolve(sp.csc_matrix(Qc[R_idx][:, R_idx]), rhs)
+    return x
+
+
+def solve_pcg_ic0(Q: sp.csr_matrix, b: np.ndarray, L: sp.csr_matrix, perm: np.ndarray, tol: float = 1e-13,
+                  maxiter: int = 20000, x0: np.ndarray | None = None):
+    """PCG (Barrett et al. templates) with the incomplete Cholesky
+    preconditioner M = L L' of Algorithm 2, steps 6-7, for one right-hand side,
+    until ||r|| <= tol ||b|| on the recursively updated residual (Section 3.1,
+    relative-residual tolerance delta).  Returns (x, iterations, relres)."""
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64).ravel().copy()
+    r = b - Q @ x
+    z = ic0_solve(L, perm, r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while np.linalg.norm(r) > tol * nb and it < maxiter:
+        q = Q @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        it += 1
+        z = ic0_solve(L, perm, r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, np.linalg.norm(b - Q @ x) / nb
 
 
 # --------------------------------------------------------------------- sampling
