@@ -60,6 +60,16 @@ extern "C" {
 /* ---- preconditioners and precision modes ----------------------------- */
 #define GP_PRECOND_JACOBI        0  /* inverse of diag(Q)                      */
 #define GP_PRECOND_BLOCK_JACOBI  1  /* inverse of each voxel's K x K block of Q */
+/* Incomplete Cholesky factor of Q with zero fill in K x K voxel blocks, on the
+ * two-colour voxel order (even x + y + z first) -- the preconditioner M of
+ * Algorithm 2 (steps 6-7) and Section 3.1, with the red-black order in place
+ * of a fill-reducing one.  PCG with it is carried out as the equivalent
+ * half-size PCG on the Schur complement of the odd voxels with its diagonal
+ * blocks as preconditioner; the even voxels are solved exactly from their rows
+ * (start values included), so the reported residual is that of the whole
+ * system.  Needs R <= 65535 per call; not available to gp_autotune or the
+ * serving loop.                                                           */
+#define GP_PRECOND_RB_IC0        2
 
 #define GP_MATVEC_AUTO    0  /* the tuned choice, else the raster kernel        */
 #define GP_MATVEC_RASTER  1  /* one voxel per thread, neighbours via an index table */

@@ -218,6 +218,7 @@ int reset_bad(gp_op* op) {
 }
 
 int build_precond(gp_op* op, int pc) {
+  if (pc == GP_PRECOND_RB_IC0) return rb_build(op);
   if (!op->have_blocks || !op->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
   int st = reset_bad(op);
   if (st) return st;
@@ -246,7 +247,7 @@ bool valid_opts(const gp_opts& o, std::string* why) {
     return *why = "inner_tol must lie in (0, 1)", false;
   if (o.max_iter < 1) return *why = "max_iter must be >= 1", false;
   if (o.max_outer < 1) return *why = "max_outer must be >= 1", false;
-  if (o.precond != GP_PRECOND_JACOBI && o.precond != GP_PRECOND_BLOCK_JACOBI)
+  if (o.precond != GP_PRECOND_JACOBI && o.precond != GP_PRECOND_BLOCK_JACOBI && o.precond != GP_PRECOND_RB_IC0)
     return *why = "unknown preconditioner", false;
   if (o.precision != GP_PREC_FP64 && o.precision != GP_PREC_FP32_REFINE64) return *why = "unknown precision", false;
   if (o.matvec < GP_MATVEC_AUTO || o.matvec > GP_MATVEC_ZMARCH) return *why = "unknown matvec kernel", false;
@@ -404,6 +405,34 @@ struct Item {
 };
 
 // ------------------------------------------------------------- PCG driver
+int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue) {
+  hipStream_t s = c->stream;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= 64) {
+      HIPTRY(hipStreamSynchronize(s));
+      for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+      c->graphs.clear();
+    }
+    HIPTRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int est = enqueue(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (est != GP_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return est;
+    }
+    HIPTRY(e);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPTRY(ei);
+    it = c->graphs.emplace(key, exec).first;
+  }
+  HIPTRY(hipGraphLaunch(it->second, s));
+  return GP_OK;
+}
+
 int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   std::string why;
@@ -426,6 +455,25 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       if (st) return st;
       it.op->pc_want = o.precond;
     }
+  }
+  // the red-black incomplete Cholesky preconditioner has a solver of its own,
+  // run operator by operator
+  if (o.precond == GP_PRECOND_RB_IC0) {
+    int ret = GP_OK;
+    std::string msg;
+    size_t base = 0;
+    for (const Item& it : items) {
+      if (it.R > 0) {
+        const int st = rb_solve(c, it.op, it.R, it.b, it.x, o, stats ? stats + base : nullptr);
+        if (st != GP_OK && st != GP_ERR_NOT_CONVERGED && st != GP_ERR_BREAKDOWN) return st;
+        if (st != GP_OK && ret == GP_OK) {
+          ret = st;
+          msg = gp_last_error();
+        }
+      }
+      base += (size_t)it.R;
+    }
+    return ret == GP_OK ? GP_OK : fail(ret, msg);
   }
   // problems, ordered by K so that each K forms one grouped launch
   std::vector<int> order;
@@ -541,30 +589,7 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
                     std::to_string(g.nblk_o);
   }
   auto replay = [&](const std::string& key, const std::function<int(hipStream_t)>& enqueue) -> int {
-    auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-      if (c->graphs.size() >= 64) {
-        HIPTRY(hipStreamSynchronize(s));
-        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-        c->graphs.clear();
-      }
-      HIPTRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      const int est = enqueue(c->cap_stream);
-      hipGraph_t graph = nullptr;
-      const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
-      if (est != GP_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return est;
-      }
-      HIPTRY(e);
-      hipGraphExec_t exec = nullptr;
-      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      HIPTRY(ei);
-      it = c->graphs.emplace(key, exec).first;
-    }
-    HIPTRY(hipGraphLaunch(it->second, s));
-    return GP_OK;
+    return graph_replay(c, key, enqueue);
   };
   const int pc = o.precond;
   // rounds of round_len iterations; with FP64 inner solves a round in which no
@@ -947,6 +972,7 @@ int gp_op_destroy(gp_op* op) {
   op_free(op, op->d_bad, 1);
   op_free(op, op->gmap, op->ncell);
   op_free(op, op->tr_part, op->tr_cap);
+  rb_release(op);
   delete op;
   return GP_OK;
 }

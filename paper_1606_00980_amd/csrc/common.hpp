@@ -92,6 +92,26 @@ struct Prob {
   SolveCfg cfg;
 };
 
+// Device view of the red-black split of an operator for the incomplete
+// Cholesky preconditioner: voxels with even x + y + z ("red") and odd
+// ("black"), each numbered compactly in increasing voxel order.  Adjacent
+// voxels always have different colours.
+struct RbDev {
+  const int* blk;        // [NB] voxel of black position i
+  const int* red;        // [NR] voxel of red position j
+  const int* nbB;        // [6][NB] red position of each neighbour of black i, or -1
+  const int* nbR;        // [6][NR] black position of each neighbour of red j, or -1
+  const double* D64;     // [NBt][NB] packed Q_mm = B_m + diag(alpha) deg_m (black)
+  const float* D32;
+  const double* S64;     // [NBt][NB] packed inverse of the Schur block S_m (black)
+  const float* S32;
+  const double* P64;     // [NBt][NR] packed inverse of Q_nn (red)
+  const float* P32;
+  int NB, NR, ntB, ntR, N, K;
+  double alpha64[KMAX];
+  float alpha32[KMAX];
+};
+
 // Packed index of the symmetric (k, j) entry, lower triangle row-major.
 __host__ __device__ constexpr int pk(int k, int j) {
   return k >= j ? k * (k + 1) / 2 + j : j * (j + 1) / 2 + k;

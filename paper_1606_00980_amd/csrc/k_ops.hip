@@ -14,6 +14,7 @@
 #include "device.hpp"
 #include "launch.hpp"
 #include "pcg.hpp"
+#include "spd.hpp"
 
 namespace gp {
 
@@ -208,45 +209,12 @@ __global__ __launch_bounds__(TILE) void k_precond(OpDev op, int pc, double* __re
     return;
   }
   // Cholesky M = L L', then M^{-1} = L^{-T} L^{-1}.
-  double L[NB];
-  bool ok = true;
+  double inv[NB];
+  const bool ok = spd_inverse<K>(a, inv);
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    double dj = a[pk(j, j)];
-#pragma unroll
-    for (int l = 0; l < j; ++l) dj -= L[pk(j, l)] * L[pk(j, l)];
-    ok = ok && (dj > 0.0) && (dj == dj);
-    const double ljj = sqrt(dj > 0.0 ? dj : 1.0);
-    L[pk(j, j)] = ljj;
-#pragma unroll
-    for (int i = j + 1; i < K; ++i) {
-      double v = a[pk(i, j)];
-#pragma unroll
-      for (int l = 0; l < j; ++l) v -= L[pk(i, l)] * L[pk(j, l)];
-      L[pk(i, j)] = v / ljj;
-    }
-  }
-  double Li[NB];   // lower-triangular inverse of L, by forward substitution per column
-#pragma unroll
-  for (int c = 0; c < K; ++c) {
-#pragma unroll
-    for (int i = c; i < K; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int l = c; l < i; ++l) v -= L[pk(i, l)] * Li[pk(l, c)];
-      Li[pk(i, c)] = v / L[pk(i, i)];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-#pragma unroll
-    for (int j = 0; j <= i; ++j) {
-      double v = 0.0;
-#pragma unroll
-      for (int l = i; l < K; ++l) v += Li[pk(l, i)] * Li[pk(l, j)];
-      P64[(size_t)pk(i, j) * N + n] = v;
-      P32[(size_t)pk(i, j) * N + n] = (float)v;
-    }
+  for (int i = 0; i < NB; ++i) {
+    P64[(size_t)i * N + n] = inv[i];
+    P32[(size_t)i * N + n] = (float)inv[i];
   }
   if (!ok) atomicMin(bad, n);
 }

@@ -1,0 +1,309 @@
+// Host side of the red-black incomplete Cholesky preconditioner (the M of
+// Algorithm 2, steps 6-7, as a zero-fill factor in K x K voxel blocks on the
+// two-colour voxel order): the colour split of an operator, the set-up of the
+// red inverses and black Schur blocks, and the driver of the half-size PCG on
+// the black Schur complement that PCG with this M reduces to (the algebra is
+// stated at the top of k_rbic.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gmrf.h"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace gp {
+namespace rt {
+
+struct RbData {
+  int NB = 0, NR = 0, ntB = 0, ntR = 0;
+  int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr;
+  double *D64 = nullptr, *S64 = nullptr, *P64 = nullptr;
+  float *D32 = nullptr, *S32 = nullptr, *P32 = nullptr;
+  RbDev* d_desc = nullptr;   // device copies of the descriptors a solver round reads
+  Prob* d_prob = nullptr;
+  RbDev h_desc{};            // their host sources (kept alive for the asynchronous copies)
+  Prob h_prob{};
+  std::vector<std::pair<void*, size_t>> allocs;
+};
+
+namespace {
+
+template <typename P>
+int rb_alloc(gp_ctx* c, RbData* d, size_t count, P** p) {
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(P);
+  void* v = nullptr;
+  if (int st = dev_alloc(c, bytes, &v)) return st;
+  d->allocs.emplace_back(v, bytes);
+  *p = (P*)v;
+  return GP_OK;
+}
+
+RbDev rb_dev(const gp_op* op) {
+  const RbData& d = *op->rb;
+  RbDev v;
+  std::memset(&v, 0, sizeof(v));
+  v.blk = d.blk;
+  v.red = d.red;
+  v.nbB = d.nbB;
+  v.nbR = d.nbR;
+  v.D64 = d.D64;
+  v.D32 = d.D32;
+  v.S64 = d.S64;
+  v.S32 = d.S32;
+  v.P64 = d.P64;
+  v.P32 = d.P32;
+  v.NB = d.NB;
+  v.NR = d.NR;
+  v.ntB = d.ntB;
+  v.ntR = d.ntR;
+  v.N = op->N;
+  v.K = op->K;
+  for (int k = 0; k < op->K; ++k) {
+    v.alpha64[k] = op->alpha[k];
+    v.alpha32[k] = (float)op->alpha[k];
+  }
+  return v;
+}
+
+// Colour every voxel by the parity of x + y + z, number each colour in
+// increasing voxel order, and tabulate each voxel's neighbours by their
+// position in the other colour.
+int build_lists(gp_op* op) {
+  gp_ctx* c = op->ctx;
+  const int N = op->N;
+  std::vector<int> lin(N), nbr((size_t)6 * N);
+  HIPTRY(hipMemcpyAsync(lin.data(), op->lin, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipMemcpyAsync(nbr.data(), op->nbr, (size_t)6 * N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  std::vector<int> colour(N), pos(N), blk, red;
+  const long nx = op->nx, ny = op->ny;
+  for (int n = 0; n < N; ++n) {
+    const long l = lin[n];
+    const long x = l % nx, y = (l / nx) % ny, z = l / (nx * ny);
+    colour[n] = (int)((x + y + z) & 1);
+    std::vector<int>& list = colour[n] ? blk : red;
+    pos[n] = (int)list.size();
+    list.push_back(n);
+  }
+  RbData* d = new RbData();
+  op->rb = d;
+  d->NB = (int)blk.size();
+  d->NR = (int)red.size();
+  d->ntB = (d->NB + TILE - 1) / TILE;
+  d->ntR = (d->NR + TILE - 1) / TILE;
+  auto table = [&](const std::vector<int>& list, std::vector<int>& out) -> bool {
+    const size_t n = list.size();
+    out.assign(6 * n, -1);
+    for (size_t i = 0; i < n; ++i) {
+      const int v = list[i];
+      for (int dd = 0; dd < 6; ++dd) {
+        const int u = nbr[(size_t)dd * N + v];
+        if (u == v) continue;
+        if (colour[u] == colour[v]) return false;
+        out[(size_t)dd * n + i] = pos[u];
+      }
+    }
+    return true;
+  };
+  std::vector<int> nbB, nbR;
+  if (!table(blk, nbB) || !table(red, nbR)) return fail(GP_ERR_INVALID_ARG, "voxel graph is not two-colourable");
+  const size_t NBt = (size_t)op->K * (op->K + 1) / 2;
+  int st = GP_OK;
+  if ((st = rb_alloc(c, d, blk.size(), &d->blk)) || (st = rb_alloc(c, d, red.size(), &d->red)) ||
+      (st = rb_alloc(c, d, nbB.size(), &d->nbB)) || (st = rb_alloc(c, d, nbR.size(), &d->nbR)) ||
+      (st = rb_alloc(c, d, NBt * d->NB, &d->D64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->D32)) ||
+      (st = rb_alloc(c, d, NBt * d->NB, &d->S64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->S32)) ||
+      (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)) ||
+      (st = rb_alloc(c, d, 1, &d->d_desc)) || (st = rb_alloc(c, d, 1, &d->d_prob)))
+    return st;
+  auto up = [&](int* dst, const std::vector<int>& src) {
+    return src.empty() ? hipSuccess
+                       : hipMemcpyAsync(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  };
+  HIPTRY(up(d->blk, blk));
+  HIPTRY(up(d->red, red));
+  HIPTRY(up(d->nbB, nbB));
+  HIPTRY(up(d->nbR, nbR));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  return GP_OK;
+}
+
+// The launches of one solver round for inner precision T.
+template <typename T>
+struct Round {
+  gp_ctx* c;
+  const RbDev& h;
+  const RbData& d;
+  int R, pstride, ntBR;
+  RhsState* st;
+  double *part, *bb, *c64, *xB, *u64;
+  T *dv, *rv, *pv, *qv, *uv;
+
+  // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
+  int outer(hipStream_t q) const {
+    PROFILED(c, GP_KERNEL_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, st, xB, dv, pv));
+    PROFILED(c, GP_KERNEL_REFINE, launch_rb_red(q, h, d.d_desc, R, st, PH_OUTER, xB, u64));
+    PROFILED(c, GP_KERNEL_REFINE, launch_rb_refine(q, h, d.d_desc, R, st, c64, xB, u64, rv, pv, part, pstride));
+    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntBR));
+    return GP_OK;
+  }
+  // q = S p with the seven inner products, finalise, update
+  int inner(hipStream_t q) const {
+    PROFILED(c, GP_KERNEL_MATVEC, launch_rb_red(q, h, d.d_desc, R, st, PH_INNER, pv, uv));
+    PROFILED(c, GP_KERNEL_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, st, pv, uv, rv, qv, part, pstride));
+    HIPTRY(launch_rb_finalize(q, 1, R, d.d_prob, bb, h.ntB, ntBR));
+    PROFILED(c, GP_KERNEL_UPDATE, launch_rb_update(q, h, d.d_desc, R, st, dv, rv, pv, qv));
+    return GP_OK;
+  }
+  // FP64 inner solves: the outer step, then `chunk` iterations.  FP32 inner
+  // solves end every few iterations, so every iteration is preceded by the
+  // outer step (its launches do nothing for right-hand sides not waiting).
+  int round(hipStream_t q, bool f32, int chunk, bool outer_only) const {
+    if (outer_only) return outer(q);
+    if (!f32)
+      if (int e = outer(q)) return e;
+    for (int i = 0; i < chunk; ++i) {
+      if (f32)
+        if (int e = outer(q)) return e;
+      if (int e = inner(q)) return e;
+    }
+    return GP_OK;
+  }
+};
+
+}  // namespace
+
+void rb_release(gp_op* op) {
+  if (!op->rb) return;
+  for (auto& a : op->rb->allocs) dev_free(op->ctx, a.first, a.second);
+  delete op->rb;
+  op->rb = nullptr;
+}
+
+int rb_build(gp_op* op) {
+  gp_ctx* c = op->ctx;
+  if (!op->rb) {
+    if (int st = build_lists(op)) {
+      rb_release(op);
+      return st;
+    }
+  }
+  RbData& d = *op->rb;
+  const RbDev h = rb_dev(op);
+  if (int st = reset_bad(op)) return st;
+  PROFILED(c, GP_KERNEL_PRECOND, launch_rb_setup(c->stream, h, op->B64, d.P64, d.P32, d.D64, d.D32, d.S64, d.S32,
+                                                  op->d_bad));
+  int bad = INT_MAX;
+  if (int st = read_bad(op, &bad)) return st;
+  if (bad != INT_MAX) {
+    op->pc_built = -1;
+    return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(bad) + " is not positive definite");
+  }
+  op->pc_built = GP_PRECOND_RB_IC0;
+  return GP_OK;
+}
+
+int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_opts& o, gp_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (R > 65535) return fail(GP_ERR_INVALID_ARG, "R must not exceed 65535 with the red-black preconditioner");
+  if (!op->rb || op->pc_built != GP_PRECOND_RB_IC0) return fail(GP_ERR_INVALID_ARG, "preconditioner not built");
+  RbData& d = *op->rb;
+  const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  const int K = op->K, ntBR = d.ntB + d.ntR, pstride = std::max(d.ntB, 1);
+  const size_t nbv = (size_t)R * K * d.NB, nrv = (size_t)R * K * d.NR;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + std::max<size_t>(bytes, 1), 256);
+    return at;
+  };
+  const size_t o_st = take((size_t)R * sizeof(RhsState)), o_part = take((size_t)NPART * R * pstride * 8),
+               o_bb = take((size_t)R * std::max(ntBR, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
+               o_u64 = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
+               o_q = take(nbv * tsz), o_u = take(nrv * tsz);
+  if (int st = ensure_ws(c, off)) return st;
+  char* ws = (char*)c->ws;
+  hipStream_t s = c->stream;
+  RhsState* sts = (RhsState*)(ws + o_st);
+  double* part = (double*)(ws + o_part);
+  double* bb = (double*)(ws + o_bb);
+  double* c64 = (double*)(ws + o_c);
+  double* xB = (double*)(ws + o_x);
+  double* u64 = (double*)(ws + o_u64);
+
+  d.h_desc = rb_dev(op);
+  std::memset(&d.h_prob, 0, sizeof(Prob));
+  d.h_prob.st = sts;
+  d.h_prob.part = part;
+  d.h_prob.R = R;
+  d.h_prob.pstride = pstride;
+  d.h_prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, 0, 0};
+  HIPTRY(hipMemcpyAsync(d.d_desc, &d.h_desc, sizeof(RbDev), hipMemcpyHostToDevice, s));
+  HIPTRY(hipMemcpyAsync(d.d_prob, &d.h_prob, sizeof(Prob), hipMemcpyHostToDevice, s));
+  HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
+  // c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials (t = D_R^{-1} b_R borrows u64)
+  PROFILED(c, GP_KERNEL_REFINE, launch_rb_split(s, d.h_desc, R, b, x, o.zero_guess ? 1 : 0, u64, c64, xB, bb));
+
+  const int chunk = o.chunk > 0 ? o.chunk : 8;
+  const bool graphs = c->use_graphs && !c->prof_on;
+  const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
+                          std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
+                          std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(chunk);
+  auto run_round = [&](bool outer_only) -> int {
+    auto enq = [&](hipStream_t q) -> int {
+      if (f32) {
+        const Round<float> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
+                              (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
+                              (float*)(ws + o_u)};
+        return rd.round(q, true, chunk, outer_only);
+      }
+      const Round<double> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
+                             (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
+                             (double*)(ws + o_u)};
+      return rd.round(q, false, chunk, outer_only);
+    };
+    if (!graphs) return enq(s);
+    return graph_replay(c, key + (outer_only ? "|outer" : "|round"), enq);
+  };
+
+  std::vector<RhsState> hs(R);
+  int n_outer = R, n_inner = 0;
+  const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
+  long rounds = 0;
+  while (n_outer > 0 || n_inner > 0) {
+    if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
+    if (int st = run_round(!f32 && n_inner == 0)) return st;
+    HIPTRY(hipMemcpyAsync(hs.data(), sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipStreamSynchronize(s));
+    n_outer = n_inner = 0;
+    for (const RhsState& h : hs) {
+      n_outer += h.phase == PH_OUTER;
+      n_inner += h.phase == PH_INNER;
+    }
+  }
+  PROFILED(c, GP_KERNEL_ADDSOL, launch_rb_recover(s, d.h_desc, R, sts, b, xB, x));
+  HIPTRY(hipStreamSynchronize(s));
+  if (c->prof_on)
+    if (int e = prof_resolve(c)) return e;
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  int ret = GP_OK;
+  for (int r = 0; r < R; ++r) {
+    const RhsState& h = hs[r];
+    const int status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
+    if (stats) stats[r] = gp_stats{status, h.total_it, h.outer, 0, h.relres, us};
+    if (status != GP_OK && ret == GP_OK) ret = status;
+  }
+  if (ret == GP_ERR_NOT_CONVERGED) return fail(ret, "some right-hand sides did not reach the tolerance");
+  if (ret == GP_ERR_BREAKDOWN) return fail(ret, "PCG breakdown (non-finite value or loss of definiteness)");
+  return ret;
+}
+
+}  // namespace rt
+}  // namespace gp

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <functional>
 #include <map>
 #include <string>
 #include <utility>
@@ -72,6 +73,12 @@ struct gp_ctx {
   std::map<std::string, TuneEntry> tuned;
 };
 
+namespace gp {
+namespace rt {
+struct RbData;
+}  // namespace rt
+}  // namespace gp
+
 struct gp_op {
   gp_ctx* ctx = nullptr;
   int N = 0, K = 0, nx = 0, ny = 0, nz = 0, conn = 0, dirs = 0, ntiles = 0;
@@ -92,6 +99,7 @@ struct gp_op {
   bool have_blocks = false, have_alpha = false;
   int pc_built = -1;
   int pc_want = GP_PRECOND_BLOCK_JACOBI;
+  gp::rt::RbData* rb = nullptr;   // red-black split and its preconditioner, built on first use
   size_t bytes = 0;
 };
 
@@ -185,10 +193,23 @@ int dev_alloc(gp_ctx* c, size_t bytes, void** p);
 void dev_free(gp_ctx* c, void* p, size_t bytes);
 OpDev op_dev(const gp_op* op);
 int build_precond(gp_op* op, int pc);
+// Grow the context's solver workspace to at least `bytes`.
+int ensure_ws(gp_ctx* c, size_t bytes);
+// The operator's failure flag: reset to INT_MAX, and read (waits for the stream).
+int reset_bad(gp_op* op);
+int read_bad(gp_op* op, int* bad);
 // Pack, factor and SPD-check device blocks B ([N][K][K] FP64) into op, as
 // gp_op_set_blocks does (the caller holds the context).
 int install_blocks(gp_op* op, const double* B, int64_t* bad_voxel);
 bool valid_opts(const gp_opts& o, std::string* why);
+// Launch the graph cached under key on the context's stream, capturing it
+// first from enqueue(capture stream) when absent (at most 64 are kept).
+int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue);
+// Red-black incomplete Cholesky preconditioner (rbic.cpp): set-up for op, the
+// solve of R right-hand sides, and release of its data.
+int rb_build(gp_op* op);
+int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_opts& o, gp_stats* stats);
+void rb_release(gp_op* op);
 
 }  // namespace rt
 }  // namespace gp

@@ -383,6 +383,8 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
   if (cfg) c = *cfg; else gp_server_cfg_default(&c);
   std::string why;
   if (!valid_opts(c.opts, &why)) return fail(GP_ERR_INVALID_ARG, why);
+  if (c.opts.precond == GP_PRECOND_RB_IC0)
+    return fail(GP_ERR_INVALID_ARG, "the serving loop supports the Jacobi and block-Jacobi preconditioners");
   if (c.max_active_rhs < 1 || c.chunk < 1 || c.probes < 1 || c.probes > c.max_active_rhs)
     return fail(GP_ERR_INVALID_ARG, "max_active_rhs >= 1, chunk >= 1 and 1 <= probes <= max_active_rhs required");
   for (int i = 0; i < nops; ++i) {

@@ -1,0 +1,57 @@
+// Inverse of a small symmetric positive definite block held packed (lower
+// triangle, row-major) in registers: Cholesky A = L L', then
+// A^{-1} = L^{-T} L^{-1}.
+#pragma once
+#include "common.hpp"
+
+namespace gp {
+
+// Writes the packed inverse of the packed SPD block a into inv and returns
+// whether every pivot was positive and finite.  A failed pivot is replaced by
+// one so that the arithmetic stays finite.
+template <int K>
+__device__ inline bool spd_inverse(const double (&a)[K * (K + 1) / 2], double (&inv)[K * (K + 1) / 2]) {
+  constexpr int NB = K * (K + 1) / 2;
+  double L[NB];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double dj = a[pk(j, j)];
+#pragma unroll
+    for (int l = 0; l < j; ++l) dj -= L[pk(j, l)] * L[pk(j, l)];
+    ok = ok && (dj > 0.0) && (dj == dj);
+    const double ljj = sqrt(dj > 0.0 ? dj : 1.0);
+    L[pk(j, j)] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < K; ++i) {
+      double v = a[pk(i, j)];
+#pragma unroll
+      for (int l = 0; l < j; ++l) v -= L[pk(i, l)] * L[pk(j, l)];
+      L[pk(i, j)] = v / ljj;
+    }
+  }
+  double Li[NB];   // lower-triangular inverse of L, by forward substitution per column
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+#pragma unroll
+    for (int i = c; i < K; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = c; l < i; ++l) v -= L[pk(i, l)] * Li[pk(l, c)];
+      Li[pk(i, c)] = v / L[pk(i, i)];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = i; l < K; ++l) v += Li[pk(l, i)] * Li[pk(l, j)];
+      inv[pk(i, j)] = v;
+    }
+  }
+  return ok;
+}
+
+}  // namespace gp

@@ -60,6 +60,8 @@ int gp_autotune(gp_op* op, int R, const gp_opts* base, gp_opts* best) {
   if (base) o = *base; else gp_opts_default(&o);
   std::string why;
   if (!valid_opts(o, &why)) return fail(GP_ERR_INVALID_ARG, why);
+  if (o.precond == GP_PRECOND_RB_IC0)
+    return fail(GP_ERR_INVALID_ARG, "autotuning covers the Jacobi and block-Jacobi solver only");
   gp_ctx* c = op->ctx;
   const size_t nv = (size_t)R * op->K * op->N;
   double* buf = nullptr;

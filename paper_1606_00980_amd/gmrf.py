@@ -29,6 +29,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "OOM", -4: "BUSY"
 
 GP_PRECOND_JACOBI = 0
 GP_PRECOND_BLOCK_JACOBI = 1
+GP_PRECOND_RB_IC0 = 2
 GP_MATVEC_AUTO, GP_MATVEC_RASTER, GP_MATVEC_ZMARCH = 0, 1, 2
 GP_PREC_FP64 = 0
 GP_PREC_FP32_REFINE64 = 1
