@@ -3,11 +3,13 @@
 
 One step is one pass of the whole path over one batch of synthetic input on
 the 52,740-voxel whole-brain operator (64x64x33 ellipsoid, K = 6, AR(3)):
-ingest the data blocks (pack + per-voxel Cholesky), set alpha (block-Jacobi
-set-up), form 32 perturbed right-hand sides (Algorithm 2) and 32 Rademacher
-probe right-hand sides, solve all 64 in one grouped batch (FP32 inner PCG,
-FP64 refinement to relative residual 1e-8, every right-hand side from zero),
-and reduce the Hutchinson trace estimates.  `value` is solves/s over the
+assemble the data term on the device (blocks packed and factored), set alpha
+(preconditioner set-up), form 32 perturbed right-hand sides (Algorithm 2) and
+32 Rademacher probe right-hand sides, solve all 64 in one batch (FP32 inner
+PCG, FP64 refinement to relative residual 1e-8, every right-hand side from
+zero) preconditioned by the incomplete Cholesky factor on the red-black voxel
+order (--precond block_jacobi for the block-Jacobi solver), and reduce the
+Hutchinson trace estimates.  `value` is solves/s over the
 timed steps with inputs resident in HBM.
 
     python bench.py [--steps K] [--warmup W] [--workload batch64|brain_fp64|uneven]
@@ -30,7 +32,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00980_amd", "csrc", f)
-                  for f in ("pcg.hpp", "device.hpp", "common.hpp")]
+                  for f in ("pcg.hpp", "device.hpp", "common.hpp", "k_rbic.hip", "spd.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -47,6 +49,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven", "serve"])
+    ap.add_argument("--precond", default="rb_ic0", choices=["rb_ic0", "block_jacobi"],
+                    help="batch64: the incomplete Cholesky factor on the red-black order (default) "
+                         "or block Jacobi")
+    ap.add_argument("--no-precond-compare", action="store_true",
+                    help="batch64: skip the solve-only comparison of preconditioners and precisions")
     ap.add_argument("--duration", type=float, default=20.0,
                     help="serve: seconds of Poisson arrivals (the full stream is 300)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
@@ -80,9 +87,11 @@ def load_library():
 class Workload:
     """Device-resident inputs and the step function of one benchmark workload."""
 
-    def __init__(self, name, g, torch, ctx):
+    def __init__(self, name, g, torch, ctx, precond="block_jacobi"):
         from paper_1606_00980_amd import synth
         self.name, self.g, self.torch, self.ctx = name, g, torch, ctx
+        self.precond = precond
+        pc = g.GP_PRECOND_RB_IC0 if precond == "rb_ic0" else g.GP_PRECOND_BLOCK_JACOBI
         dev = lambda a: torch.from_numpy(a).cuda()
         self.data = None
         if name in ("batch64", "brain_fp64"):
@@ -107,7 +116,7 @@ class Workload:
                 self.bp = torch.empty((self.M, w.K, w.N), dtype=torch.float64, device="cuda")
                 self.xs = torch.zeros_like(self.bs)
                 self.xp = torch.zeros_like(self.bp)
-                self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
+                self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=pc)
                 self.solves = self.S + self.M
             else:
                 self.b = dev(w.bw[None].copy())
@@ -192,7 +201,7 @@ class Workload:
             return {"workload": "brain3d_64x64x33_ellipsoid_K6_R1_fp64", "N": w.N, "K": w.K, "R": 1,
                     "tol": 1e-8, "precond": "block_jacobi", "precision": "fp64"}
         return {"workload": "brain3d_64x64x33_ellipsoid_K6_R64_fp32refine64", "N": w.N, "K": w.K,
-                "R": 64, "samples": 32, "probes": 32, "tol": 1e-8, "precond": "block_jacobi",
+                "R": 64, "samples": 32, "probes": 32, "tol": 1e-8, "precond": self.precond,
                 "precision": "fp32_inner_fp64_refine",
                 "step": "data_assemble+set_alpha+perturb_rhs(32)+probe_rhs(32)+solve_batch(64)+trace_reduce"}
 
@@ -215,7 +224,10 @@ def roofline(prof):
             "bytes_per_launch": round(d["bytes"] / d["launches"])}
 
 
-KERNEL_KIND_OF = [("k_matvec_zm", "matvec"), ("k_matvec", "matvec"), ("k_update", "update"),
+KERNEL_KIND_OF = [("k_rb_red", "rb_red"), ("k_rb_matvec", "rb_matvec"), ("k_rb_update", "rb_update"),
+                  ("k_rb_refine", "rb_refine"), ("k_rb_addsol", "rb_addsol"), ("k_rb_split", "rb_edge"),
+                  ("k_rb_recover", "rb_edge"), ("k_rb_setup", "precond"),
+                  ("k_matvec_zm", "matvec"), ("k_matvec", "matvec"), ("k_update", "update"),
                   ("k_refine", "refine"), ("k_addsol", "addsol"), ("k_perturb", "perturb"),
                   ("k_probe_rhs", "probe"), ("k_precond", "precond"), ("k_pack_blocks", "pack")]
 
@@ -311,6 +323,41 @@ def bandwidth_sweep(g, torch, ctx):
     g.gp_op_destroy(op)
     return {"workload": f"uneven_largest_96x96x60_fill0.6_K10_N{w.N}", "N": w.N, "K": w.K,
             "mall_bytes": 256e6, "sweep": rows}
+
+
+def precond_compare(g, torch, ctx, wl):
+    """The step's 64-right-hand-side solve alone (graphs, no profiling) with
+    each preconditioner and inner precision: time, solves/s and iterations.
+    Block Jacobi runs with its autotuned launch configuration."""
+    w = wl.ws[0]
+    g.gp_data_assemble(wl.data, wl.lam, 1, wl.A, wl.bw)
+    g.gp_op_set_alpha(wl.op, wl.alpha[0])
+    g.gp_perturb_rhs(wl.op, wl.S, wl.bw, wl.z1, wl.z2, wl.bs)
+    g.gp_probe_rhs(wl.op, wl.M, wl.v, wl.bp)
+    out = []
+    for name, pc, prec in (("rb_ic0", g.GP_PRECOND_RB_IC0, g.GP_PREC_FP32_REFINE64),
+                           ("rb_ic0", g.GP_PRECOND_RB_IC0, g.GP_PREC_FP64),
+                           ("block_jacobi", g.GP_PRECOND_BLOCK_JACOBI, g.GP_PREC_FP32_REFINE64),
+                           ("block_jacobi", g.GP_PRECOND_BLOCK_JACOBI, g.GP_PREC_FP64)):
+        o = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=pc, precision=prec)
+        if pc == g.GP_PRECOND_BLOCK_JACOBI:
+            g.gp_autotune(wl.op, wl.S, o)
+        items = [(wl.op, wl.S, wl.bs, wl.xs), (wl.op, wl.M, wl.bp, wl.xp)]
+        for _ in range(3):
+            g.gp_solve_batch(ctx, items, o)
+        torch.cuda.synchronize()
+        n = 20
+        t0 = time.perf_counter()
+        for _ in range(n):
+            _, st = g.gp_solve_batch(ctx, items, o)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out.append({"precond": name, "precision": "fp32_inner_fp64_refine" if prec else "fp64",
+                    "ms_per_solve_batch": round(dt * 1e3, 3), "solves_per_s": round(wl.solves / dt, 1),
+                    "inner_iters_mean": round(sum(s["inner_iters"] for s in st) / len(st), 2),
+                    "max_relres": max(s["relres"] for s in st)})
+        log(f"compare {out[-1]}")
+    return {"what": "solve_batch of the step's 64 right-hand sides alone, tol 1e-8, zero start", "runs": out}
 
 
 def cpu_baseline():
@@ -481,9 +528,9 @@ def main():
     if args.workload == "serve":
         main_serve(args, g, torch, ctx)
         return
-    wl = Workload(args.workload, g, torch, ctx)
+    wl = Workload(args.workload, g, torch, ctx, args.precond if args.workload == "batch64" else "block_jacobi")
     tuned = None
-    if not args.no_autotune:
+    if not args.no_autotune and wl.precond != "rb_ic0":
         tuned = wl.autotune()
         log(f"autotuned: {tuned}")
     for _ in range(args.warmup):
@@ -549,6 +596,8 @@ def main():
         result["gpu_fp64_single_rhs"] = {"value": round(n / (time.perf_counter() - tb), 2),
                                          "unit": "solves/s",
                                          "what": "plain FP64 single-RHS PCG, same operator, block Jacobi"}
+    if args.workload == "batch64" and not args.no_precond_compare:
+        result["precond_compare"] = precond_compare(g, torch, ctx, wl)
     if args.workload == "batch64" and not args.no_bandwidth_sweep:
         result["bandwidth_sweep"] = bandwidth_sweep(g, torch, ctx)
         big = result["bandwidth_sweep"]["sweep"][-1]

@@ -405,6 +405,50 @@ struct Item {
 };
 
 // ------------------------------------------------------------- PCG driver
+// With FP32 inner solves and an automatic chunk, the next round is planned
+// from each right-hand side's completed inner solves (their mean length est):
+// the slot in which its current inner solve should end, the refinement in the
+// slot after it, one more inner solve when the residual after this one (about
+// relres * inner_tol) is still above tol.  The round lasts until the last
+// expected refinement; the outer step is placed in the first slot and around
+// every expected refinement.  Before any history: `chunk` slots, the outer
+// step first.  A fixed chunk places the outer step in every slot (FP32) or the
+// first (FP64).
+void plan_round(const std::vector<RhsState>& hs, const gp_opts& o, bool f32, int chunk, int* round_len,
+                uint64_t* round_mask) {
+  *round_len = chunk;
+  *round_mask = 1;
+  if (!f32 || o.chunk > 0) {
+    *round_mask = f32 ? ~0ull : 1ull;
+    return;
+  }
+  int need = 1;
+  uint64_t mask = 1;
+  auto mark = [&](int slot) {   // 1-based slot that should carry the outer step
+    for (int t = slot - 1; t <= slot + 1; ++t)
+      if (t >= 1 && t <= 64) mask |= 1ull << (t - 1);
+  };
+  for (const RhsState& h : hs) {
+    if (h.phase == PH_DONE) continue;
+    const bool inner = h.phase == PH_INNER;
+    const int done_solves = inner ? h.outer - 1 : h.outer;
+    if (done_solves <= 0) {   // no history yet
+      need = std::max(need, chunk);
+      continue;
+    }
+    const int est = std::max(1, (h.total_it - (inner ? h.inner_it : 0) + done_solves - 1) / done_solves);
+    int refine_slot = inner ? std::max(1, est - h.inner_it) + 1 : 1;
+    mark(refine_slot);
+    if (h.relres * o.inner_tol > o.tol) {
+      refine_slot += est;
+      mark(refine_slot);
+    }
+    need = std::max(need, refine_slot);
+  }
+  *round_len = std::min(need, 2 * chunk);
+  *round_mask = mask;
+}
+
 int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue) {
   hipStream_t s = c->stream;
   auto it = c->graphs.find(key);
@@ -459,20 +503,32 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // the red-black incomplete Cholesky preconditioner has a solver of its own,
   // run operator by operator
   if (o.precond == GP_PRECOND_RB_IC0) {
-    int ret = GP_OK;
-    std::string msg;
+    std::vector<gp_stats> all(totalR);
+    std::vector<gp_op*> ops;
+    std::vector<std::vector<RbItem>> per_op;
     size_t base = 0;
     for (const Item& it : items) {
       if (it.R > 0) {
-        const int st = rb_solve(c, it.op, it.R, it.b, it.x, o, stats ? stats + base : nullptr);
-        if (st != GP_OK && st != GP_ERR_NOT_CONVERGED && st != GP_ERR_BREAKDOWN) return st;
-        if (st != GP_OK && ret == GP_OK) {
-          ret = st;
-          msg = gp_last_error();
+        const size_t gi = std::find(ops.begin(), ops.end(), it.op) - ops.begin();
+        if (gi == ops.size()) {
+          ops.push_back(it.op);
+          per_op.emplace_back();
         }
+        per_op[gi].push_back(RbItem{it.R, it.b, it.x, all.data() + base});
       }
       base += (size_t)it.R;
     }
+    int ret = GP_OK;
+    std::string msg;
+    for (size_t gi = 0; gi < ops.size(); ++gi) {
+      const int st = rb_solve(c, ops[gi], per_op[gi], o);
+      if (st != GP_OK && st != GP_ERR_NOT_CONVERGED && st != GP_ERR_BREAKDOWN) return st;
+      if (st != GP_OK && ret == GP_OK) {
+        ret = st;
+        msg = gp_last_error();
+      }
+    }
+    if (stats) std::memcpy(stats, all.data(), totalR * sizeof(gp_stats));
     return ret == GP_OK ? GP_OK : fail(ret, msg);
   }
   // problems, ordered by K so that each K forms one grouped launch
@@ -625,54 +681,14 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
   // performs a refinement step, both bounded by max_iter and max_outer.
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
-  // With FP32 inner solves and an automatic chunk, the next round is planned
-  // from each right-hand side's completed inner solves (their mean length
-  // est): the slot in which its current inner solve should end, the refinement
-  // in the slot after it, one more inner solve when the residual after this
-  // one (about relres * inner_tol) is still above tol.  The round lasts until
-  // the last expected refinement; the outer step is placed in the first slot
-  // and around every expected refinement.  Before any history: `chunk` slots,
-  // the outer step first.
-  auto plan_round = [&]() {
-    round_len = chunk;
-    round_mask = 1;
-    if (!f32 || o.chunk > 0) {
-      round_mask = f32 ? ~0ull : 1ull;
-      return;
-    }
-    int need = 1;
-    uint64_t mask = 1;
-    auto mark = [&](int slot) {   // 1-based slot that should carry the outer step
-      for (int t = slot - 1; t <= slot + 1; ++t)
-        if (t >= 1 && t <= 64) mask |= 1ull << (t - 1);
-    };
-    for (const RhsState& h : hs) {
-      if (h.phase == PH_DONE) continue;
-      const bool inner = h.phase == PH_INNER;
-      const int done_solves = inner ? h.outer - 1 : h.outer;
-      if (done_solves <= 0) {   // no history yet
-        need = std::max(need, chunk);
-        continue;
-      }
-      const int est = std::max(1, (h.total_it - (inner ? h.inner_it : 0) + done_solves - 1) / done_solves);
-      int refine_slot = inner ? std::max(1, est - h.inner_it) + 1 : 1;
-      mark(refine_slot);
-      if (h.relres * o.inner_tol > o.tol) {
-        refine_slot += est;
-        mark(refine_slot);
-      }
-      need = std::max(need, refine_slot);
-    }
-    round_len = std::min(need, 2 * chunk);
-    round_mask = mask;
-  };
+  auto plan = [&]() { plan_round(hs, o, f32, chunk, &round_len, &round_mask); };
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
     st = launch_round(!f32 && n_inner == 0);
     if (st) return st;
     st = read_states();
     if (st) return st;
-    plan_round();
+    plan();
   }
   // results (hs holds the final states, in problem order)
   int ret = GP_OK;

@@ -107,7 +107,10 @@ struct RbDev {
   const float* S32;
   const double* P64;     // [NBt][NR] packed inverse of Q_nn (red)
   const float* P32;
+  long long* prof;       // [NPROF] work counters while profiling, else null
   int NB, NR, ntB, ntR, N, K;
+  int zero_start;        // the start value is zero: x is not read
+  int spare;
   double alpha64[KMAX];
   float alpha32[KMAX];
 };

@@ -88,6 +88,20 @@ __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>&
   }
 }
 
+// While profiling: one count in `slot` per launch in which some right-hand
+// side is in `phase` (the launches that move the blocks), taken by workgroup
+// (0, 0) before any state can change.
+__device__ inline void count_launch(const RbDev& rb, const RhsState* st, int phase, int slot) {
+  if (rb.prof && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    for (int r = 0; r < (int)gridDim.y; ++r) {
+      if (st[r].phase == phase) {
+        atomicAdd((unsigned long long*)&rb.prof[slot], 1ull);
+        break;
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void load_nb(const int* tab, int n, int i, int (&nb)[6]) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = tab[(size_t)d * n + i];
@@ -190,8 +204,8 @@ __global__ __launch_bounds__(TILE) void k_rb_split_red(RbDev rb, const double* _
   block_sums<1>(acc, bbpart, 0, (size_t)r * ntBR + rb.ntB + blockIdx.x);
 }
 
-// Black voxels: c = b_m + alpha .* sum_{n ~ m} t_n, x_B = x_m (zero for a
-// zero start value), and the black part of ||b||^2 into bbpart[r][tile].
+// Black voxels: c = b_m + alpha .* sum_{n ~ m} t_n, x_B = x_m (not written
+// for a zero start value), and the black part of ||b||^2 into bbpart[r][tile].
 template <int K>
 __global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double* __restrict__ b,
                                                          const double* __restrict__ x, int zero_guess,
@@ -215,10 +229,7 @@ __global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double*
       acc[0] += bk * bk;
       cs.st(k, oi, bk + rb.alpha64[k] * s[k]);
     }
-    if (zero_guess) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) xs.st(k, oi, 0.0);
-    } else {
+    if (!zero_guess) {   // from a zero start value x_B is first written by x_B = d (+ a p)
       const Slab<double> xu(x + ur, K, rb.N);
 #pragma unroll
       for (int k = 0; k < K; ++k) xs.st(k, oi, xu.ld(k, om));
@@ -236,6 +247,7 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, 
   const RbDev& rb = *rbp;
   const int r = blockIdx.y, j = blockIdx.x * TILE + threadIdx.x;
   if (st[r].phase != want || j >= rb.NR) return;
+  if (want == PH_OUTER && rb.zero_start && st[r].outer == 0) return;   // x_B = 0: S x_B = 0
   int nb[6];
   load_nb(rb.nbR, rb.NR, j, nb);
   const Slab<T> vs(v + (size_t)r * K * rb.NB, K, rb.NB), us(u + (size_t)r * K * rb.NR, K, rb.NR);
@@ -261,6 +273,7 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
                                                     int pstride) {
   const RbDev& rb = *rbp;
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
+  count_launch(rb, st, PH_OUTER, PF_REFINE_ACT);
   if (st[r].phase != PH_OUTER) return;
   double acc[3] = {0.0, 0.0, 0.0};
   if (i < rb.NB) {
@@ -271,16 +284,21 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     const Slab<double> Ds(rb.D64, Tri<K>::NB, rb.NB), Ss(rb.S64, Tri<K>::NB, rb.NB);
     const Slab<T> rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB);
     const unsigned o8 = (unsigned)i * 8u, oT = (unsigned)i * (unsigned)sizeof(T);
-    double xv[K], y[K], s[K], r64[K], z[K];
+    double r64[K], z[K];
+    if (rb.zero_start && st[r].outer == 0) {   // x_B = 0: r = c
 #pragma unroll
-    for (int k = 0; k < K; ++k) xv[k] = xs.ld(k, o8);
-    packed_apply<double, K>(Ds, o8, xv, y);
-    neighbour_sum<double, K>(nb, us, s);
+      for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8);
+    } else {
+      double xv[K], y[K], s[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      r64[k] = cs.ld(k, o8) - (y[k] - rb.alpha64[k] * s[k]);
-      acc[0] += r64[k] * r64[k];
+      for (int k = 0; k < K; ++k) xv[k] = xs.ld(k, o8);
+      packed_apply<double, K>(Ds, o8, xv, y);
+      neighbour_sum<double, K>(nb, us, s);
+#pragma unroll
+      for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8) - (y[k] - rb.alpha64[k] * s[k]);
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0] += r64[k] * r64[k];
     packed_apply<double, K>(Ss, o8, r64, z);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -302,6 +320,7 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
                                                     double* __restrict__ part, int R, int pstride) {
   const RbDev& rb = *rbp;
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
+  count_launch(rb, st, PH_INNER, PF_MATVEC_ACT);
   if (st[r].phase != PH_INNER) return;
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (i < rb.NB) {
@@ -350,6 +369,7 @@ __global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rb
                                                     const T* __restrict__ qv) {
   const RbDev& rb = *rbp;
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
+  count_launch(rb, st, PH_INNER, PF_UPDATE_ACT);
   const RhsState& s = st[r];
   if (s.phase != PH_INNER || i >= rb.NB) return;
   const T a = (T)s.a, beta = (T)s.beta;
@@ -380,7 +400,9 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
   const RbDev& rb = *rbp;
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
   const RhsState& s = st[r];
-  if (s.phase != PH_OUTER || !(s.has_d || s.pend) || i >= rb.NB) return;
+  // with a zero start value, the first x_B += d writes x_B without reading it
+  const bool fresh = rb.zero_start && s.outer == 1;
+  if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh) || i >= rb.NB) return;
   const bool hd = s.has_d != 0, hp = s.pend != 0;
   const double a = s.a;
   const size_t off = (size_t)r * K * rb.NB;
@@ -389,7 +411,7 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
   const unsigned o8 = (unsigned)i * 8u, oT = (unsigned)i * (unsigned)sizeof(T);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double v = xs.ld(k, o8);
+    double v = fresh ? 0.0 : xs.ld(k, o8);
     if (hd) v += (double)ds.ld(k, oT);
     if (hp) v += a * (double)ps.ld(k, oT);
     xs.st(k, o8, v);
@@ -406,6 +428,8 @@ __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* _
                                                      double* __restrict__ x) {
   const int r = blockIdx.y;
   const bool zero = st[r].zero_b != 0;
+  // from a zero start value, x_B holds nothing until the first x_B += d
+  const bool xzero = rb.zero_start && st[r].outer <= 1;
   const size_t ur = (size_t)r * K * rb.N;
   const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB), xu(x + ur, K, rb.N);
   if ((int)blockIdx.x < rb.ntR) {
@@ -422,7 +446,12 @@ __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* _
       load_nb(rb.nbR, rb.NR, j, nb);
       const Slab<double> bs(b + ur, K, rb.N), Ps(rb.P64, Tri<K>::NB, rb.NR);
       double s[K];
-      neighbour_sum<double, K>(nb, xs, s);
+      if (xzero) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] = 0.0;
+      } else {
+        neighbour_sum<double, K>(nb, xs, s);
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) s[k] = bs.ld(k, on) + rb.alpha64[k] * s[k];
       packed_apply<double, K>(Ps, (unsigned)j * 8u, s, v);
@@ -434,7 +463,7 @@ __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* _
     if (i >= rb.NB) return;
     const unsigned om = (unsigned)rb.blk[i] * 8u, oi = (unsigned)i * 8u;
 #pragma unroll
-    for (int k = 0; k < K; ++k) xu.st(k, om, zero ? 0.0 : xs.ld(k, oi));
+    for (int k = 0; k < K; ++k) xu.st(k, om, (zero || xzero) ? 0.0 : xs.ld(k, oi));
   }
 }
 

@@ -147,35 +147,68 @@ struct Round {
 
   // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
   int outer(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, st, xB, dv, pv));
-    PROFILED(c, GP_KERNEL_REFINE, launch_rb_red(q, h, d.d_desc, R, st, PH_OUTER, xB, u64));
-    PROFILED(c, GP_KERNEL_REFINE, launch_rb_refine(q, h, d.d_desc, R, st, c64, xB, u64, rv, pv, part, pstride));
+    PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, st, xB, dv, pv));
+    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, st, PH_OUTER, xB, u64));
+    PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, st, c64, xB, u64, rv, pv, part, pstride));
     HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntBR));
     return GP_OK;
   }
   // q = S p with the seven inner products, finalise, update
   int inner(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_MATVEC, launch_rb_red(q, h, d.d_desc, R, st, PH_INNER, pv, uv));
-    PROFILED(c, GP_KERNEL_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, st, pv, uv, rv, qv, part, pstride));
+    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, st, PH_INNER, pv, uv));
+    PROFILED(c, GP_KERNEL_RB_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, st, pv, uv, rv, qv, part, pstride));
     HIPTRY(launch_rb_finalize(q, 1, R, d.d_prob, bb, h.ntB, ntBR));
-    PROFILED(c, GP_KERNEL_UPDATE, launch_rb_update(q, h, d.d_desc, R, st, dv, rv, pv, qv));
+    PROFILED(c, GP_KERNEL_RB_UPDATE, launch_rb_update(q, h, d.d_desc, R, st, dv, rv, pv, qv));
     return GP_OK;
   }
-  // FP64 inner solves: the outer step, then `chunk` iterations.  FP32 inner
-  // solves end every few iterations, so every iteration is preceded by the
-  // outer step (its launches do nothing for right-hand sides not waiting).
-  int round(hipStream_t q, bool f32, int chunk, bool outer_only) const {
-    if (outer_only) return outer(q);
-    if (!f32)
-      if (int e = outer(q)) return e;
-    for (int i = 0; i < chunk; ++i) {
-      if (f32)
+  // `len` iterations, iteration i preceded by the outer step when bit i of
+  // `mask` is set; len = 0: the outer step alone.
+  int round(hipStream_t q, int len, uint64_t mask) const {
+    if (len == 0) return outer(q);
+    for (int i = 0; i < len; ++i) {
+      if (i < 64 && ((mask >> i) & 1))
         if (int e = outer(q)) return e;
       if (int e = inner(q)) return e;
     }
     return GP_OK;
   }
 };
+
+// Algorithmic HBM bytes of the launches of one solve, from the work counters:
+// every vector entry a launch needs read or written once (a gathered
+// neighbour vector counted once), the blocks once per launch with work.
+void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, const std::vector<long long>& pf) {
+  const RbData& d = *op->rb;
+  const double K = op->K, NB = d.NB, NR = d.NR, N = op->N, ts = (double)tsz, NBt = K * (K + 1) / 2;
+  const double mv = (double)pf[PF_MATVEC_RHS], ref = (double)pf[PF_REFINE_RHS];
+  // red stage: the black vector read, u written; the red inverses
+  const double ref_x = ref - (double)pf[PF_REFINE_X0];   // refinements from a non-zero x
+  prof_add(c, GP_KERNEL_RB_RED, (mv + ref_x) * NR,
+           mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts + ref_x * K * (NB + NR) * 8 +
+               pf[PF_REFINE_ACT] * NBt * NR * 8);
+  // black stage: p, u, r read, q written; Q_mm and the Schur inverses
+  prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
+  // p, q, r, d read (d not on the first step), d, r, p written; Schur inverses
+  const double up = (double)pf[PF_UPDATE_RHS], fresh = (double)pf[PF_UPDATE_FRESH];
+  prof_add(c, GP_KERNEL_RB_UPDATE, up * NB,
+           (up - fresh) * 7 * K * NB * ts + fresh * 6 * K * NB * ts + pf[PF_UPDATE_ACT] * NBt * NB * ts);
+  // c, x_B, u64 read (c alone from a zero start value), r and p written; FP64
+  // Q_mm (not from a zero start value) and Schur inverses
+  const double x0 = (double)pf[PF_REFINE_X0];
+  prof_add(c, GP_KERNEL_RB_REFINE, ref * NB,
+           ref * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) - x0 * K * (NB + NR) * 8 +
+               pf[PF_REFINE_ACT] * 2 * NBt * NB * 8);
+  // x_B read (not on the first step from a zero start value) and written, d
+  // and/or the pending step's p read
+  const double ad = (double)pf[PF_ADDSOL_D], ap = (double)pf[PF_ADDSOL_P], af = (double)pf[PF_ADDSOL_FRESH];
+  const double an = std::max(std::max(ad, ap), af);
+  prof_add(c, GP_KERNEL_RB_ADDSOL, an * NB, an * K * NB * 16 - af * K * NB * 8 + (ad + ap) * K * NB * ts);
+  // split: b read, t written and read, x read and x_B written (unless the start
+  // value is zero), c written; recovery: x_B and red b read, x written; the
+  // red inverses twice
+  prof_add(c, GP_KERNEL_RB_EDGE, 2.0 * R * N,
+           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + R * K * 8 * (NB + NR + N) + 2 * NBt * NR * 8);
+}
 
 }  // namespace
 
@@ -209,9 +242,13 @@ int rb_build(gp_op* op) {
   return GP_OK;
 }
 
-int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_opts& o, gp_stats* stats) {
+int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_opts& o) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (R > 65535) return fail(GP_ERR_INVALID_ARG, "R must not exceed 65535 with the red-black preconditioner");
+  long Rl = 0;
+  for (const RbItem& it : items) Rl += it.R;
+  if (Rl > 65535) return fail(GP_ERR_INVALID_ARG, "at most 65535 right-hand sides per operator with the red-black preconditioner");
+  const int R = (int)Rl;
+  if (R == 0) return GP_OK;
   if (!op->rb || op->pc_built != GP_PRECOND_RB_IC0) return fail(GP_ERR_INVALID_ARG, "preconditioner not built");
   RbData& d = *op->rb;
   const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
@@ -227,7 +264,7 @@ int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_o
   const size_t o_st = take((size_t)R * sizeof(RhsState)), o_part = take((size_t)NPART * R * pstride * 8),
                o_bb = take((size_t)R * std::max(ntBR, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
                o_u64 = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
-               o_q = take(nbv * tsz), o_u = take(nrv * tsz);
+               o_q = take(nbv * tsz), o_u = take(nrv * tsz), o_prof = take(NPROF * sizeof(long long));
   if (int st = ensure_ws(c, off)) return st;
   char* ws = (char*)c->ws;
   hipStream_t s = c->stream;
@@ -238,48 +275,66 @@ int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_o
   double* xB = (double*)(ws + o_x);
   double* u64 = (double*)(ws + o_u64);
 
+  long long* prof = c->prof_on ? (long long*)(ws + o_prof) : nullptr;
   d.h_desc = rb_dev(op);
+  d.h_desc.prof = prof;
+  d.h_desc.zero_start = o.zero_guess ? 1 : 0;
   std::memset(&d.h_prob, 0, sizeof(Prob));
+  d.h_prob.prof = prof;
   d.h_prob.st = sts;
   d.h_prob.part = part;
   d.h_prob.R = R;
   d.h_prob.pstride = pstride;
-  d.h_prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, 0, 0};
+  d.h_prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
   HIPTRY(hipMemcpyAsync(d.d_desc, &d.h_desc, sizeof(RbDev), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemcpyAsync(d.d_prob, &d.h_prob, sizeof(Prob), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
-  // c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials (t = D_R^{-1} b_R borrows u64)
-  PROFILED(c, GP_KERNEL_REFINE, launch_rb_split(s, d.h_desc, R, b, x, o.zero_guess ? 1 : 0, u64, c64, xB, bb));
+  if (prof) HIPTRY(hipMemsetAsync(prof, 0, NPROF * sizeof(long long), s));
+  // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials (t = D_R^{-1} b_R borrows u64)
+  {
+    size_t r0 = 0;
+    for (const RbItem& it : items) {
+      if (it.R > 0)
+        PROFILED(c, GP_KERNEL_RB_EDGE,
+                 launch_rb_split(s, d.h_desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, u64 + r0 * K * d.NR,
+                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntBR));
+      r0 += (size_t)it.R;
+    }
+  }
 
   const int chunk = o.chunk > 0 ? o.chunk : 8;
   const bool graphs = c->use_graphs && !c->prof_on;
   const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
                           std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
-                          std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(chunk);
-  auto run_round = [&](bool outer_only) -> int {
+                          std::to_string(R) + "," + (f32 ? "f" : "d");
+  auto run_round = [&](int len, uint64_t mask) -> int {
     auto enq = [&](hipStream_t q) -> int {
       if (f32) {
         const Round<float> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
                               (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
                               (float*)(ws + o_u)};
-        return rd.round(q, true, chunk, outer_only);
+        return rd.round(q, len, mask);
       }
       const Round<double> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
                              (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
                              (double*)(ws + o_u)};
-      return rd.round(q, false, chunk, outer_only);
+      return rd.round(q, len, mask);
     };
     if (!graphs) return enq(s);
-    return graph_replay(c, key + (outer_only ? "|outer" : "|round"), enq);
+    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask), enq);
   };
 
+  // rounds planned as for the main solver: the outer step first, then
+  // iterations with the outer step where inner solves are expected to end
   std::vector<RhsState> hs(R);
   int n_outer = R, n_inner = 0;
+  int round_len = chunk;
+  uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
-    if (int st = run_round(!f32 && n_inner == 0)) return st;
+    if (int st = (!f32 && n_inner == 0) ? run_round(0, 1) : run_round(round_len, round_mask)) return st;
     HIPTRY(hipMemcpyAsync(hs.data(), sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     n_outer = n_inner = 0;
@@ -287,18 +342,35 @@ int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_o
       n_outer += h.phase == PH_OUTER;
       n_inner += h.phase == PH_INNER;
     }
+    plan_round(hs, o, f32, chunk, &round_len, &round_mask);
   }
-  PROFILED(c, GP_KERNEL_ADDSOL, launch_rb_recover(s, d.h_desc, R, sts, b, xB, x));
+  {
+    size_t r0 = 0;
+    for (const RbItem& it : items) {
+      if (it.R > 0)
+        PROFILED(c, GP_KERNEL_RB_EDGE,
+                 launch_rb_recover(s, d.h_desc, it.R, sts + r0, it.b, xB + r0 * K * d.NB, it.x));
+      r0 += (size_t)it.R;
+    }
+  }
   HIPTRY(hipStreamSynchronize(s));
-  if (c->prof_on)
+  if (prof) {
+    std::vector<long long> pf(NPROF);
+    HIPTRY(hipMemcpy(pf.data(), prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
+    rb_account(c, op, R, tsz, o.zero_guess != 0, pf);
     if (int e = prof_resolve(c)) return e;
+  }
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   int ret = GP_OK;
-  for (int r = 0; r < R; ++r) {
-    const RhsState& h = hs[r];
-    const int status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
-    if (stats) stats[r] = gp_stats{status, h.total_it, h.outer, 0, h.relres, us};
-    if (status != GP_OK && ret == GP_OK) ret = status;
+  size_t r0 = 0;
+  for (const RbItem& it : items) {
+    for (int r = 0; r < it.R; ++r) {
+      const RhsState& h = hs[r0 + r];
+      const int status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
+      if (it.stats) it.stats[r] = gp_stats{status, h.total_it, h.outer, 0, h.relres, us};
+      if (status != GP_OK && ret == GP_OK) ret = status;
+    }
+    r0 += (size_t)it.R;
   }
   if (ret == GP_ERR_NOT_CONVERGED) return fail(ret, "some right-hand sides did not reach the tolerance");
   if (ret == GP_ERR_BREAKDOWN) return fail(ret, "PCG breakdown (non-finite value or loss of definiteness)");

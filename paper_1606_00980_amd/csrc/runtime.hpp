@@ -202,13 +202,27 @@ int read_bad(gp_op* op, int* bad);
 // gp_op_set_blocks does (the caller holds the context).
 int install_blocks(gp_op* op, const double* B, int64_t* bad_voxel);
 bool valid_opts(const gp_opts& o, std::string* why);
+// Length and outer-step mask (bit i: the outer step precedes iteration i) of
+// the next solver round, planned from the right-hand sides' states.
+void plan_round(const std::vector<RhsState>& hs, const gp_opts& o, bool f32, int chunk, int* round_len,
+                uint64_t* round_mask);
 // Launch the graph cached under key on the context's stream, capturing it
 // first from enqueue(capture stream) when absent (at most 64 are kept).
 int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue);
 // Red-black incomplete Cholesky preconditioner (rbic.cpp): set-up for op, the
 // solve of R right-hand sides, and release of its data.
 int rb_build(gp_op* op);
-int rb_solve(gp_ctx* c, gp_op* op, int R, const double* b, double* x, const gp_opts& o, gp_stats* stats);
+// One caller batch item of an operator: R right-hand sides b, solutions x,
+// and where their statistics go.
+struct RbItem {
+  int R;
+  const double* b;
+  double* x;
+  gp_stats* stats;
+};
+// Solves every item of op in one red-black PCG run (their right-hand sides
+// stacked, at most 65535).
+int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_opts& o);
 void rb_release(gp_op* op);
 
 }  // namespace rt

@@ -75,7 +75,8 @@ class GpProf(ctypes.Structure):
 
 
 KERNEL_KINDS = ["refine", "matvec", "update", "addsol", "perturb", "precond", "pack",
-                "probe", "trace", "apply", "data"]
+                "probe", "trace", "apply", "data", "rb_red", "rb_matvec", "rb_update", "rb_refine",
+                "rb_addsol", "rb_edge"]
 
 
 class GpItem(ctypes.Structure):

@@ -234,3 +234,34 @@ def test_autotune_and_server_reject_the_incomplete_factor(g, ctx, torch_cuda):
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_items_of_one_operator_are_solved_together(g, ctx, torch_cuda, precision):
+    """Two batch items of one operator (stacked into one run), a zero start
+    value with x holding NaN on entry, b = 0 in the last right-hand side of
+    each item, and a stats array in item order."""
+    w = synth.tiny((21, 17, 9), 6, 3, seed=43)
+    op = make_op(g, ctx, torch_cuda, w)
+    try:
+        tol = 1e-10
+        b1, b2 = rhs(w, 2, 13), rhs(w, 3, 14)
+        nan = float("nan")
+        x1 = torch_cuda.full(b1.shape, nan, dtype=torch_cuda.float64, device="cuda")
+        x2 = torch_cuda.full(b2.shape, nan, dtype=torch_cuda.float64, device="cuda")
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, zero_guess=1)
+        st, stats = g.gp_solve_batch(ctx, [(op, 2, dev(torch_cuda, b1), x1), (op, 3, dev(torch_cuda, b2), x2)], o)
+        assert len(stats) == 5 and all(s["status"] == g.GP_OK for s in stats)
+        assert stats[1]["inner_iters"] == 0 and stats[4]["inner_iters"] == 0   # b = 0
+        Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
+        for b, x in ((b1, x1), (b2, x2)):
+            xs = x.cpu().numpy()
+            assert np.all(np.isfinite(xs)) and np.all(orc.relres(Q, xs, b) <= tol)
+            assert np.all(xs[-1] == 0.0)
+            ref = orc.solve_direct(Q, b)
+            for r in range(b.shape[0] - 1):
+                assert np.linalg.norm(xs[r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r])
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
