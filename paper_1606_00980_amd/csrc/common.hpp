@@ -101,6 +101,7 @@ struct RbDev {
   const int* red;        // [NR] voxel of red position j
   const int* nbB;        // [6][NB] red position of each neighbour of black i, or -1
   const int* nbR;        // [6][NR] black position of each neighbour of red j, or -1
+  const int* vpos;       // [N] 2 * (position in its colour) + colour (1 = black)
   const double* D64;     // [NBt][NB] packed Q_mm = B_m + diag(alpha) deg_m (black)
   const float* D32;
   const double* S64;     // [NBt][NB] packed inverse of the Schur block S_m (black)
@@ -109,8 +110,8 @@ struct RbDev {
   const float* P32;
   long long* prof;       // [NPROF] work counters while profiling, else null
   int NB, NR, ntB, ntR, N, K;
+  int ntN;               // tiles of 256 voxels over all N (split, recovery, ||b||^2 partials)
   int zero_start;        // the start value is zero: x is not read
-  int spare;
   double alpha64[KMAX];
   float alpha32[KMAX];
 };

@@ -52,6 +52,7 @@ __device__ inline void block_sums(double (&v)[NV], double* part, size_t vstride,
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();   // a previous call's readers are done with sh
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) sh[i][wv] = v[i];
@@ -90,10 +91,10 @@ __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>&
 
 // While profiling: one count in `slot` per launch in which some right-hand
 // side is in `phase` (the launches that move the blocks), taken by workgroup
-// (0, 0) before any state can change.
-__device__ inline void count_launch(const RbDev& rb, const RhsState* st, int phase, int slot) {
-  if (rb.prof && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    for (int r = 0; r < (int)gridDim.y; ++r) {
+// 0 before any state can change.
+__device__ inline void count_launch(const RbDev& rb, const RhsState* st, int R, int phase, int slot) {
+  if (rb.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int r = 0; r < R; ++r) {
       if (st[r].phase == phase) {
         atomicAdd((unsigned long long*)&rb.prof[slot], 1ull);
         break;
@@ -101,6 +102,49 @@ __device__ inline void count_launch(const RbDev& rb, const RhsState* st, int pha
     }
   }
 }
+
+// Work item of a solver-round launch: one tile of 256 voxels of one colour and
+// a chunk of Rc right-hand sides.  Items are numbered tile-major (the chunks of
+// a tile adjacent) and dealt to the XCDs in contiguous ranges, so that the
+// chunks of a tile, which read the same blocks, and neighbouring tiles, whose
+// vectors the stencil gathers, share an XCD's L2.
+struct RbWork {
+  int tile, r0, r1;
+};
+__device__ inline RbWork rb_work(int ntiles, int R, int Rc) {
+  const int nch = (R + Rc - 1) / Rc;
+  const int wi = xcd_remap(blockIdx.x, ntiles * nch);
+  RbWork o;
+  o.tile = wi / nch;
+  o.r0 = (wi % nch) * Rc;
+  o.r1 = min(R, o.r0 + Rc);
+  return o;
+}
+
+// A voxel's packed symmetric K x K block, held in registers across the
+// right-hand sides of a work item when HOLD, else read per use.
+template <typename T, int K, bool HOLD>
+struct Packed {
+  Slab<T> s;
+  unsigned o;
+  T v[HOLD ? Tri<K>::NB : 1];
+  __device__ __forceinline__ Packed(const T* base, int n, unsigned off) : s(base, Tri<K>::NB, n), o(off) {
+    if constexpr (HOLD) {
+#pragma unroll
+      for (int e = 0; e < Tri<K>::NB; ++e) v[e] = s.ld(e, o);
+    }
+  }
+  __device__ __forceinline__ T operator()(int e) const {
+    if constexpr (HOLD)
+      return v[e];
+    else
+      return s.ld(e, o);
+  }
+};
+// Hold NBLK blocks when they take at most 96 registers.
+template <typename T, int K, int NBLK> struct HoldRb {
+  static constexpr bool v = NBLK * Tri<K>::NB * (int)sizeof(T) <= 384;
+};
 
 __device__ __forceinline__ void load_nb(const int* tab, int n, int i, int (&nb)[6]) {
 #pragma unroll
@@ -178,173 +222,221 @@ __global__ __launch_bounds__(TILE) void k_rb_setup_black(RbDev rb, const double*
 }
 
 // ------------------------------------------------------------------ solve
-// Red voxels: t = Q_nn^{-1} b_n, and the red part of ||b||^2 into
-// bbpart[r][ntB + tile].
+// Split, in voxel order (reads of b and x coalesced): red voxels t = Q_nn^{-1}
+// b_n, black voxels c = b_m and x_B = x_m (x_B not written for a zero start
+// value); the per-tile partials of ||b||^2 into bbpart[r][tile].
 template <int K>
-__global__ __launch_bounds__(TILE) void k_rb_split_red(RbDev rb, const double* __restrict__ b,
-                                                       double* __restrict__ t, double* __restrict__ bbpart) {
-  const int r = blockIdx.y, j = blockIdx.x * TILE + threadIdx.x;
+__global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, const double* __restrict__ b,
+                                                          const double* __restrict__ x, int zero_guess,
+                                                          double* __restrict__ t, double* __restrict__ c,
+                                                          double* __restrict__ xB, double* __restrict__ bbpart) {
+  const int r = blockIdx.y, n = blockIdx.x * TILE + threadIdx.x;
   double acc[1] = {0.0};
-  if (j < rb.NR) {
-    const int n = rb.red[j];
-    const Slab<double> bs(b + (size_t)r * K * rb.N, K, rb.N), ts(t + (size_t)r * K * rb.NR, K, rb.NR);
-    const Slab<double> Ps(rb.P64, Tri<K>::NB, rb.NR);
-    const unsigned on = (unsigned)n * 8u, oj = (unsigned)j * 8u;
-    double bv[K], tv[K];
+  if (n < rb.N) {
+    const size_t ur = (size_t)r * K * rb.N;
+    const Slab<double> bs(b + ur, K, rb.N);
+    const unsigned on = (unsigned)n * 8u;
+    const int vp = rb.vpos[n], pos = vp >> 1;
+    const unsigned op = (unsigned)pos * 8u;
+    double bv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       bv[k] = bs.ld(k, on);
       acc[0] += bv[k] * bv[k];
     }
-    packed_apply<double, K>(Ps, oj, bv, tv);
+    if ((vp & 1) == 0) {   // red
+      const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR);
+      const Packed<double, K, false> P(rb.P64, rb.NR, op);
+      double tv[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ts.st(k, oj, tv[k]);
+      for (int k = 0; k < K; ++k) tv[k] = 0.0;
+      sym_apply<K>(P, bv, tv);
+#pragma unroll
+      for (int k = 0; k < K; ++k) ts.st(k, op, tv[k]);
+    } else {               // black
+      const Slab<double> cs(c + (size_t)r * K * rb.NB, K, rb.NB);
+#pragma unroll
+      for (int k = 0; k < K; ++k) cs.st(k, op, bv[k]);
+      if (!zero_guess) {   // from a zero start value x_B is first written by x_B = d (+ a p)
+        const Slab<double> xu(x + ur, K, rb.N), xs(xB + (size_t)r * K * rb.NB, K, rb.NB);
+#pragma unroll
+        for (int k = 0; k < K; ++k) xs.st(k, op, xu.ld(k, on));
+      }
+    }
   }
-  const int ntBR = rb.ntB + rb.ntR;
-  block_sums<1>(acc, bbpart, 0, (size_t)r * ntBR + rb.ntB + blockIdx.x);
+  block_sums<1>(acc, bbpart, 0, (size_t)r * rb.ntN + blockIdx.x);
 }
 
-// Black voxels: c = b_m + alpha .* sum_{n ~ m} t_n, x_B = x_m (not written
-// for a zero start value), and the black part of ||b||^2 into bbpart[r][tile].
+// Black voxels: c += alpha .* sum_{n ~ m} t_n, which makes
+// c = b_B - E' D_R^{-1} b_R.
 template <int K>
-__global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double* __restrict__ b,
-                                                         const double* __restrict__ x, int zero_guess,
-                                                         const double* __restrict__ t, double* __restrict__ c,
-                                                         double* __restrict__ xB, double* __restrict__ bbpart) {
+__global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double* __restrict__ t,
+                                                         double* __restrict__ c) {
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  double acc[1] = {0.0};
-  if (i < rb.NB) {
-    const int m = rb.blk[i];
-    int nb[6];
-    load_nb(rb.nbB, rb.NB, i, nb);
-    const size_t ur = (size_t)r * K * rb.N;
-    const Slab<double> bs(b + ur, K, rb.N), ts(t + (size_t)r * K * rb.NR, K, rb.NR);
-    const Slab<double> cs(c + (size_t)r * K * rb.NB, K, rb.NB), xs(xB + (size_t)r * K * rb.NB, K, rb.NB);
-    const unsigned om = (unsigned)m * 8u, oi = (unsigned)i * 8u;
-    double s[K];
-    neighbour_sum<double, K>(nb, ts, s);
+  if (i >= rb.NB) return;
+  int nb[6];
+  load_nb(rb.nbB, rb.NB, i, nb);
+  const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), cs(c + (size_t)r * K * rb.NB, K, rb.NB);
+  const unsigned oi = (unsigned)i * 8u;
+  double s[K];
+  neighbour_sum<double, K>(nb, ts, s);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double bk = bs.ld(k, om);
-      acc[0] += bk * bk;
-      cs.st(k, oi, bk + rb.alpha64[k] * s[k]);
-    }
-    if (!zero_guess) {   // from a zero start value x_B is first written by x_B = d (+ a p)
-      const Slab<double> xu(x + ur, K, rb.N);
-#pragma unroll
-      for (int k = 0; k < K; ++k) xs.st(k, oi, xu.ld(k, om));
-    }
-  }
-  const int ntBR = rb.ntB + rb.ntR;
-  block_sums<1>(acc, bbpart, 0, (size_t)r * ntBR + blockIdx.x);
+  for (int k = 0; k < K; ++k) cs.st(k, oi, cs.ld(k, oi) + rb.alpha64[k] * s[k]);
+}
+
+// Right-hand side r takes part in the red stage of phase `want` (nothing to do
+// for the first refinement from a zero start value: S 0 = 0).
+__device__ __forceinline__ bool red_active(const RbDev& rb, const RhsState& s, int want) {
+  return s.phase == want && !(want == PH_OUTER && rb.zero_start && s.outer == 0);
 }
 
 // Red stage of S v for right-hand sides in phase `want`:
 // u_n = Q_nn^{-1} (alpha .* sum_{m ~ n} v_m).
-template <typename T, int K>
-__global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st, int want,
-                                                 const T* __restrict__ v, T* __restrict__ u) {
+template <typename T, int K, bool HOLD>
+__global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
+                                                 int want, const T* __restrict__ v, T* __restrict__ u, int R,
+                                                 int Rc) {
   const RbDev& rb = *rbp;
-  const int r = blockIdx.y, j = blockIdx.x * TILE + threadIdx.x;
-  if (st[r].phase != want || j >= rb.NR) return;
-  if (want == PH_OUTER && rb.zero_start && st[r].outer == 0) return;   // x_B = 0: S x_B = 0
+  const RbWork w = rb_work(rb.ntR, R, Rc);
+  const int j = w.tile * TILE + threadIdx.x;
+  bool any = false;
+  for (int r = w.r0; r < w.r1; ++r) any = any || red_active(rb, st[r], want);
+  if (!any || j >= rb.NR) return;
   int nb[6];
   load_nb(rb.nbR, rb.NR, j, nb);
-  const Slab<T> vs(v + (size_t)r * K * rb.NB, K, rb.NB), us(u + (size_t)r * K * rb.NR, K, rb.NR);
-  const Slab<T> Ps(RbT<T>::P(rb), Tri<K>::NB, rb.NR);
   const unsigned oj = (unsigned)j * (unsigned)sizeof(T);
-  T s[K], y[K];
-  neighbour_sum<T, K>(nb, vs, s);
+  const Packed<T, K, HOLD> P(RbT<T>::P(rb), rb.NR, oj);
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    if (!red_active(rb, st[r], want)) continue;
+    const Slab<T> vs(v + (size_t)r * K * rb.NB, K, rb.NB), us(u + (size_t)r * K * rb.NR, K, rb.NR);
+    T s[K], y[K];
+    neighbour_sum<T, K>(nb, vs, s);
 #pragma unroll
-  for (int k = 0; k < K; ++k) s[k] *= RbT<T>::alpha(rb, k);
-  packed_apply<T, K>(Ps, oj, s, y);
+    for (int k = 0; k < K; ++k) {
+      s[k] *= RbT<T>::alpha(rb, k);
+      y[k] = 0;
+    }
+    sym_apply<K>(P, s, y);
 #pragma unroll
-  for (int k = 0; k < K; ++k) us.st(k, oj, y[k]);
+    for (int k = 0; k < K; ++k) us.st(k, oj, y[k]);
+  }
 }
 
 // FP64 refinement at the black voxels of right-hand sides waiting on it:
 // r64 = c - S x_B (u64 from the red stage on x_B), r = T(r64),
 // p = T(blkdiag(S)^{-1} r64); partials ||r64||^2 (slot 0) and r64' p (slot 2).
-template <typename T, int K>
+template <typename T, int K, bool HOLD>
 __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
                                                     const double* __restrict__ c, const double* __restrict__ xB,
                                                     const double* __restrict__ u64, T* __restrict__ rv,
-                                                    T* __restrict__ pv, double* __restrict__ part, int R,
+                                                    T* __restrict__ pv, double* __restrict__ part, int R, int Rc,
                                                     int pstride) {
   const RbDev& rb = *rbp;
-  const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  count_launch(rb, st, PH_OUTER, PF_REFINE_ACT);
-  if (st[r].phase != PH_OUTER) return;
-  double acc[3] = {0.0, 0.0, 0.0};
-  if (i < rb.NB) {
-    int nb[6];
-    load_nb(rb.nbB, rb.NB, i, nb);
+  count_launch(rb, st, R, PH_OUTER, PF_REFINE_ACT);
+  const RbWork w = rb_work(rb.ntB, R, Rc);
+  bool any = false;
+  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_OUTER;
+  if (!any) return;
+  const int i = w.tile * TILE + threadIdx.x;
+  const bool valid = i < rb.NB;
+  const int ii = valid ? i : 0;   // lanes past the end compute on voxel 0 and contribute nothing
+  int nb[6];
+  load_nb(rb.nbB, rb.NB, ii, nb);
+  const unsigned o8 = (unsigned)ii * 8u, oT = (unsigned)ii * (unsigned)sizeof(T);
+  const Packed<double, K, HOLD> D(rb.D64, rb.NB, o8), S(rb.S64, rb.NB, o8);
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    const RhsState& sr = st[r];
+    if (sr.phase != PH_OUTER) continue;
     const size_t off = (size_t)r * K * rb.NB;
     const Slab<double> cs(c + off, K, rb.NB), xs(xB + off, K, rb.NB), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
-    const Slab<double> Ds(rb.D64, Tri<K>::NB, rb.NB), Ss(rb.S64, Tri<K>::NB, rb.NB);
     const Slab<T> rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB);
-    const unsigned o8 = (unsigned)i * 8u, oT = (unsigned)i * (unsigned)sizeof(T);
     double r64[K], z[K];
-    if (rb.zero_start && st[r].outer == 0) {   // x_B = 0: r = c
+    if (rb.zero_start && sr.outer == 0) {   // x_B = 0: r = c
 #pragma unroll
       for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8);
     } else {
       double xv[K], y[K], s[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) xv[k] = xs.ld(k, o8);
-      packed_apply<double, K>(Ds, o8, xv, y);
+      for (int k = 0; k < K; ++k) {
+        xv[k] = xs.ld(k, o8);
+        y[k] = 0.0;
+      }
+      sym_apply<K>(D, xv, y);
       neighbour_sum<double, K>(nb, us, s);
 #pragma unroll
       for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8) - (y[k] - rb.alpha64[k] * s[k]);
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[0] += r64[k] * r64[k];
-    packed_apply<double, K>(Ss, o8, r64, z);
+    double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      acc[2] += r64[k] * z[k];
-      rs.st(k, oT, (T)r64[k]);
-      ps.st(k, oT, (T)z[k]);
+      acc[0] += r64[k] * r64[k];
+      z[k] = 0.0;
     }
+    sym_apply<K>(S, r64, z);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[2] += r64[k] * z[k];
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        rs.st(k, oT, (T)r64[k]);
+        ps.st(k, oT, (T)z[k]);
+      }
+    } else {
+      acc[0] = acc[2] = 0.0;
+    }
+    block_sums<3>(acc, part, (size_t)R * pstride, (size_t)r * pstride + w.tile);
   }
-  block_sums<3>(acc, part, (size_t)R * pstride, (size_t)r * pstride + blockIdx.x);
 }
 
 // Black stage of q = S p with the seven inner products of the one-reduction
 // iteration, z = blkdiag(S)^{-1} r and t = blkdiag(S)^{-1} q at the voxel:
 // p'q, r'z, q'z, q't, r'r, q'r, q'q.
-template <typename T, int K>
+template <typename T, int K, bool HOLD>
 __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
                                                     const T* __restrict__ pv, const T* __restrict__ u,
                                                     const T* __restrict__ rv, T* __restrict__ qv,
-                                                    double* __restrict__ part, int R, int pstride) {
+                                                    double* __restrict__ part, int R, int Rc, int pstride) {
   const RbDev& rb = *rbp;
-  const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  count_launch(rb, st, PH_INNER, PF_MATVEC_ACT);
-  if (st[r].phase != PH_INNER) return;
-  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (i < rb.NB) {
-    int nb[6];
-    load_nb(rb.nbB, rb.NB, i, nb);
+  count_launch(rb, st, R, PH_INNER, PF_MATVEC_ACT);
+  const RbWork w = rb_work(rb.ntB, R, Rc);
+  bool any = false;
+  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
+  if (!any) return;
+  const int i = w.tile * TILE + threadIdx.x;
+  const bool valid = i < rb.NB;
+  const int ii = valid ? i : 0;
+  int nb[6];
+  load_nb(rb.nbB, rb.NB, ii, nb);
+  const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
+  const Packed<T, K, HOLD> D(RbT<T>::D(rb), rb.NB, oT), S(RbT<T>::S(rb), rb.NB, oT);
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    if (st[r].phase != PH_INNER) continue;
     const size_t off = (size_t)r * K * rb.NB;
     const Slab<T> ps(pv + off, K, rb.NB), rs(rv + off, K, rb.NB), qs(qv + off, K, rb.NB);
     const Slab<T> us(u + (size_t)r * K * rb.NR, K, rb.NR);
-    const Slab<T> Ds(RbT<T>::D(rb), Tri<K>::NB, rb.NB), Ss(RbT<T>::S(rb), Tri<K>::NB, rb.NB);
-    const unsigned oT = (unsigned)i * (unsigned)sizeof(T);
     T p[K], y[K], s[K], q[K], rr[K], z[K], t[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) p[k] = ps.ld(k, oT);
-    packed_apply<T, K>(Ds, oT, p, y);
+    for (int k = 0; k < K; ++k) {
+      p[k] = ps.ld(k, oT);
+      y[k] = 0;
+    }
+    sym_apply<K>(D, p, y);
     neighbour_sum<T, K>(nb, us, s);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       q[k] = y[k] - RbT<T>::alpha(rb, k) * s[k];
-      qs.st(k, oT, q[k]);
       rr[k] = rs.ld(k, oT);
       z[k] = t[k] = 0;
     }
-    sym_apply<K>([&](int e) { return Ss.ld(e, oT); }, rr, z);
-    sym_apply<K>([&](int e) { return Ss.ld(e, oT); }, q, t);
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) qs.st(k, oT, q[k]);
+    }
+    sym_apply<K>(S, rr, z);
+    sym_apply<K>(S, q, t);
     T a[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -356,39 +448,48 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
       a[5] += q[k] * rr[k];
       a[6] += q[k] * q[k];
     }
+    double acc[7];
 #pragma unroll
-    for (int e = 0; e < 7; ++e) acc[e] = (double)a[e];
+    for (int e = 0; e < 7; ++e) acc[e] = valid ? (double)a[e] : 0.0;
+    block_sums<7>(acc, part, (size_t)R * pstride, (size_t)r * pstride + w.tile);
   }
-  block_sums<7>(acc, part, (size_t)R * pstride, (size_t)r * pstride + blockIdx.x);
 }
 
 // d += a p (d = a p on the first step), r -= a q, p = blkdiag(S)^{-1} r + beta p.
-template <typename T, int K>
-__global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st, T* __restrict__ dv,
-                                                    T* __restrict__ rv, T* __restrict__ pv,
-                                                    const T* __restrict__ qv) {
+template <typename T, int K, bool HOLD>
+__global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
+                                                    T* __restrict__ dv, T* __restrict__ rv, T* __restrict__ pv,
+                                                    const T* __restrict__ qv, int R, int Rc) {
   const RbDev& rb = *rbp;
-  const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  count_launch(rb, st, PH_INNER, PF_UPDATE_ACT);
-  const RhsState& s = st[r];
-  if (s.phase != PH_INNER || i >= rb.NB) return;
-  const T a = (T)s.a, beta = (T)s.beta;
-  const bool fresh = s.inner_it == 1;
-  const size_t off = (size_t)r * K * rb.NB;
-  const Slab<T> ds(dv + off, K, rb.NB), rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB), qs(qv + off, K, rb.NB);
-  const Slab<T> Ss(RbT<T>::S(rb), Tri<K>::NB, rb.NB);
+  count_launch(rb, st, R, PH_INNER, PF_UPDATE_ACT);
+  const RbWork w = rb_work(rb.ntB, R, Rc);
+  const int i = w.tile * TILE + threadIdx.x;
+  bool any = false;
+  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
+  if (!any || i >= rb.NB) return;
   const unsigned oT = (unsigned)i * (unsigned)sizeof(T);
-  T p[K], rn[K], z[K];
+  const Packed<T, K, HOLD> S(RbT<T>::S(rb), rb.NB, oT);
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    const RhsState& s = st[r];
+    if (s.phase != PH_INNER) continue;
+    const T a = (T)s.a, beta = (T)s.beta;
+    const bool fresh = s.inner_it == 1;
+    const size_t off = (size_t)r * K * rb.NB;
+    const Slab<T> ds(dv + off, K, rb.NB), rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB), qs(qv + off, K, rb.NB);
+    T p[K], rn[K], z[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    p[k] = ps.ld(k, oT);
-    ds.st(k, oT, fresh ? a * p[k] : ds.ld(k, oT) + a * p[k]);
-    rn[k] = rs.ld(k, oT) - a * qs.ld(k, oT);
-    rs.st(k, oT, rn[k]);
+    for (int k = 0; k < K; ++k) {
+      p[k] = ps.ld(k, oT);
+      ds.st(k, oT, fresh ? a * p[k] : ds.ld(k, oT) + a * p[k]);
+      rn[k] = rs.ld(k, oT) - a * qs.ld(k, oT);
+      rs.st(k, oT, rn[k]);
+      z[k] = 0;
+    }
+    sym_apply<K>(S, rn, z);
+#pragma unroll
+    for (int k = 0; k < K; ++k) ps.st(k, oT, z[k] + beta * p[k]);
   }
-  packed_apply<T, K>(Ss, oT, rn, z);
-#pragma unroll
-  for (int k = 0; k < K; ++k) ps.st(k, oT, z[k] + beta * p[k]);
 }
 
 // x_B += d (when valid) + a p (when the last step is pending) for right-hand
@@ -396,84 +497,87 @@ __global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rb
 template <typename T, int K>
 __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
                                                     double* __restrict__ xB, const T* __restrict__ dv,
-                                                    const T* __restrict__ pv) {
+                                                    const T* __restrict__ pv, int R, int Rc) {
   const RbDev& rb = *rbp;
-  const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  const RhsState& s = st[r];
-  // with a zero start value, the first x_B += d writes x_B without reading it
-  const bool fresh = rb.zero_start && s.outer == 1;
-  if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh) || i >= rb.NB) return;
-  const bool hd = s.has_d != 0, hp = s.pend != 0;
-  const double a = s.a;
-  const size_t off = (size_t)r * K * rb.NB;
-  const Slab<double> xs(xB + off, K, rb.NB);
-  const Slab<T> ds(dv + off, K, rb.NB), ps(pv + off, K, rb.NB);
+  const RbWork w = rb_work(rb.ntB, R, Rc);
+  const int i = w.tile * TILE + threadIdx.x;
+  if (i >= rb.NB) return;
   const unsigned o8 = (unsigned)i * 8u, oT = (unsigned)i * (unsigned)sizeof(T);
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    const RhsState& s = st[r];
+    // with a zero start value, the first x_B += d writes x_B without reading it
+    const bool fresh = rb.zero_start && s.outer == 1;
+    if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh)) continue;
+    const bool hd = s.has_d != 0, hp = s.pend != 0;
+    const double a = s.a;
+    const size_t off = (size_t)r * K * rb.NB;
+    const Slab<double> xs(xB + off, K, rb.NB);
+    const Slab<T> ds(dv + off, K, rb.NB), ps(pv + off, K, rb.NB);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double v = fresh ? 0.0 : xs.ld(k, o8);
-    if (hd) v += (double)ds.ld(k, oT);
-    if (hp) v += a * (double)ps.ld(k, oT);
-    xs.st(k, o8, v);
+    for (int k = 0; k < K; ++k) {
+      double v = fresh ? 0.0 : xs.ld(k, o8);
+      if (hd) v += (double)ds.ld(k, oT);
+      if (hp) v += a * (double)ps.ld(k, oT);
+      xs.st(k, o8, v);
+    }
   }
 }
 
-// Writes the solution in the caller's layout: x_m = x_B at the black voxels,
-// x_n = Q_nn^{-1} (b_n + alpha .* sum_{m ~ n} x_m) at the red ones (zero for
-// a right-hand side with b = 0).  Workgroups [0, ntR) take red tiles, the rest
-// black tiles.
+// Writes the solution in the caller's layout, in voxel order (writes of x
+// coalesced): x_m = x_B at the black voxels, x_n = Q_nn^{-1} (b_n + alpha .*
+// sum_{m ~ n} x_m) at the red ones; zero for a right-hand side with b = 0.
 template <int K>
 __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* __restrict__ st,
                                                      const double* __restrict__ b, const double* __restrict__ xB,
                                                      double* __restrict__ x) {
-  const int r = blockIdx.y;
+  const int r = blockIdx.y, n = blockIdx.x * TILE + threadIdx.x;
+  if (n >= rb.N) return;
   const bool zero = st[r].zero_b != 0;
   // from a zero start value, x_B holds nothing until the first x_B += d
   const bool xzero = rb.zero_start && st[r].outer <= 1;
   const size_t ur = (size_t)r * K * rb.N;
   const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB), xu(x + ur, K, rb.N);
-  if ((int)blockIdx.x < rb.ntR) {
-    const int j = blockIdx.x * TILE + threadIdx.x;
-    if (j >= rb.NR) return;
-    const int n = rb.red[j];
-    const unsigned on = (unsigned)n * 8u;
-    double v[K];
-    if (zero) {
+  const unsigned on = (unsigned)n * 8u;
+  const int vp = rb.vpos[n], pos = vp >> 1;
+  const unsigned op = (unsigned)pos * 8u;
+  double v[K];
+  if (zero) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
+  } else if (vp & 1) {   // black
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = xzero ? 0.0 : xs.ld(k, op);
+  } else {               // red
+    const Slab<double> bs(b + ur, K, rb.N);
+    double s[K];
+    if (xzero) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) s[k] = 0.0;
     } else {
       int nb[6];
-      load_nb(rb.nbR, rb.NR, j, nb);
-      const Slab<double> bs(b + ur, K, rb.N), Ps(rb.P64, Tri<K>::NB, rb.NR);
-      double s[K];
-      if (xzero) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) s[k] = 0.0;
-      } else {
-        neighbour_sum<double, K>(nb, xs, s);
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) s[k] = bs.ld(k, on) + rb.alpha64[k] * s[k];
-      packed_apply<double, K>(Ps, (unsigned)j * 8u, s, v);
+      load_nb(rb.nbR, rb.NR, pos, nb);
+      neighbour_sum<double, K>(nb, xs, s);
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) xu.st(k, on, v[k]);
-  } else {
-    const int i = (blockIdx.x - rb.ntR) * TILE + threadIdx.x;
-    if (i >= rb.NB) return;
-    const unsigned om = (unsigned)rb.blk[i] * 8u, oi = (unsigned)i * 8u;
-#pragma unroll
-    for (int k = 0; k < K; ++k) xu.st(k, om, (zero || xzero) ? 0.0 : xs.ld(k, oi));
+    for (int k = 0; k < K; ++k) {
+      s[k] = bs.ld(k, on) + rb.alpha64[k] * s[k];
+      v[k] = 0.0;
+    }
+    const Packed<double, K, false> P(rb.P64, rb.NR, op);
+    sym_apply<K>(P, s, v);
   }
+#pragma unroll
+  for (int k = 0; k < K; ++k) xu.st(k, on, v[k]);
 }
 
 // One wavefront per right-hand side: reduce the black tiles' partials in a
 // fixed order and advance the state with the main solver's rules.  For the
-// refinement the ||b||^2 slot comes from the split partials (both colours).
+// refinement the ||b||^2 slot comes from the split partials (ntN voxel tiles).
 template <int KIND>
 __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_rb_finalize(const Prob* __restrict__ prp,
                                                                   const double* __restrict__ bbpart, int ntB,
-                                                                  int ntBR) {
+                                                                  int ntN) {
   const Prob& pr = *prp;
   const int r = blockIdx.x * FIN_WAVES + (int)(threadIdx.x / WAVE);
   if (r >= pr.R) return;
@@ -482,7 +586,7 @@ __global__ __launch_bounds__(FIN_WAVES * WAVE) void k_rb_finalize(const Prob* __
   if constexpr (KIND == 0) {
     double v[3], bb[1];
     sum_partials<3>(pr.part, pr.R, pr.pstride, ntB, r, v);
-    sum_partials<1>(bbpart, 1, ntBR, ntBR, r, bb);
+    sum_partials<1>(bbpart, 1, ntN, ntN, r, bb);
     v[1] = bb[0];
     if (lane == 0) finalize_refine(pr, r, v);
   } else {
@@ -518,58 +622,29 @@ hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, do
 
 hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
                            double* t, double* c, double* xB, double* bbpart) {
-#define X(KK)                                                                                        \
-  case KK:                                                                                           \
-    if (rb.ntR > 0) hipLaunchKernelGGL(k_rb_split_red<KK>, grid2(rb.ntR, R), dim3(TILE), 0, s, rb, b, t, bbpart); \
-    if (rb.ntB > 0)                                                                                  \
-      hipLaunchKernelGGL(k_rb_split_black<KK>, grid2(rb.ntB, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, \
-                         xB, bbpart);                                                                \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_rb_red_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, int want, const T* v, T* u) {
-  if (rb.ntR == 0) return hipSuccess;
-#define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_red<T, KK>), grid2(rb.ntR, R), dim3(TILE), 0, s, rbd, st, want, v, u); break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, int want,
-                         const double* v, double* u) {
-  return launch_rb_red_t<double>(s, rb, rbd, R, st, want, v, u);
-}
-hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, int want,
-                         const float* v, float* u) {
-  return launch_rb_red_t<float>(s, rb, rbd, R, st, want, v, u);
-}
-
-template <typename T>
-hipError_t launch_rb_refine_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, const double* c,
-                              const double* xB, const double* u64, T* r, T* p, double* part, int pstride) {
-  if (rb.ntB == 0) return hipSuccess;
-#define X(KK)                                                                                          \
-  case KK:                                                                                             \
-    hipLaunchKernelGGL((k_rb_refine<T, KK>), grid2(rb.ntB, R), dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, \
-                       R, pstride);                                                                    \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_rb_matvec_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, const T* p, const T* u,
-                              const T* r, T* q, double* part, int pstride) {
-  if (rb.ntB == 0) return hipSuccess;
 #define X(KK)                                                                                              \
   case KK:                                                                                                 \
-    hipLaunchKernelGGL((k_rb_matvec<T, KK>), grid2(rb.ntB, R), dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, \
-                       pstride);                                                                           \
+    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, xB, \
+                       bbpart);                                                                            \
+    if (rb.ntB > 0) hipLaunchKernelGGL(k_rb_split_black<KK>, grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c);  \
+    break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+inline unsigned rb_grid(int ntiles, int R, int Rc) { return (unsigned)ntiles * (unsigned)((R + Rc - 1) / Rc); }
+
+template <typename T>
+hipError_t launch_rb_red_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
+                           int want, const T* v, T* u) {
+  if (rb.ntR == 0) return hipSuccess;
+  const dim3 g(rb_grid(rb.ntR, R, Rc));
+#define X(KK) \
+  case KK: if (Rc > 1 && HoldRb<T, KK, 1>::v)                                                                 \
+      hipLaunchKernelGGL((k_rb_red<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);        \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_rb_red<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);       \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -577,43 +652,94 @@ hipError_t launch_rb_matvec_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, 
 }
 
 template <typename T>
-hipError_t launch_rb_update_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, T* d, T* r, T* p,
-                              const T* q) {
+hipError_t launch_rb_refine_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
+                              const double* c, const double* xB, const double* u64, T* r, T* p, double* part,
+                              int pstride) {
   if (rb.ntB == 0) return hipSuccess;
-#define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_update<T, KK>), grid2(rb.ntB, R), dim3(TILE), 0, s, rbd, st, d, r, p, q); break;
+  const dim3 g(rb_grid(rb.ntB, R, Rc));
+#define X(KK)                                                                                                \
+  case KK:                                                                                                   \
+    if (Rc > 1 && HoldRb<double, KK, 2>::v)                                                                  \
+      hipLaunchKernelGGL((k_rb_refine<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R, Rc, \
+                         pstride);                                                                           \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_rb_refine<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R,    \
+                         Rc, pstride);                                                                       \
+    break;
   RB_K_SWITCH(rb.K, X)
 #undef X
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rb_addsol_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, double* xB, const T* d,
-                              const T* p) {
+hipError_t launch_rb_matvec_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
+                              const T* p, const T* u, const T* r, T* q, double* part, int pstride) {
   if (rb.ntB == 0) return hipSuccess;
-#define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_addsol<T, KK>), grid2(rb.ntB, R), dim3(TILE), 0, s, rbd, st, xB, d, p); break;
+  const dim3 g(rb_grid(rb.ntB, R, Rc));
+#define X(KK)                                                                                                  \
+  case KK:                                                                                                     \
+    if (Rc > 1 && HoldRb<T, KK, 2>::v)                                                                         \
+      hipLaunchKernelGGL((k_rb_matvec<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc, pstride); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_rb_matvec<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc,   \
+                         pstride);                                                                             \
+    break;
   RB_K_SWITCH(rb.K, X)
 #undef X
   return hipGetLastError();
 }
 
-#define RB_INST(T)                                                                                          \
-  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, const double* c,    \
-                              const double* xB, const double* u64, T* r, T* p, double* part, int pstride) {  \
-    return launch_rb_refine_t<T>(s, rb, rbd, R, st, c, xB, u64, r, p, part, pstride);                           \
-  }                                                                                                         \
-  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, const T* p,         \
-                              const T* u, const T* r, T* q, double* part, int pstride) {                     \
-    return launch_rb_matvec_t<T>(s, rb, rbd, R, st, p, u, r, q, part, pstride);                                  \
-  }                                                                                                         \
-  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, T* d, T* r, T* p,   \
-                              const T* q) {                                                                 \
-    return launch_rb_update_t<T>(s, rb, rbd, R, st, d, r, p, q);                                                 \
-  }                                                                                                         \
-  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, double* xB,         \
-                              const T* d, const T* p) {                                                     \
-    return launch_rb_addsol_t<T>(s, rb, rbd, R, st, xB, d, p);                                                   \
+template <typename T>
+hipError_t launch_rb_update_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
+                              T* d, T* r, T* p, const T* q) {
+  if (rb.ntB == 0) return hipSuccess;
+  const dim3 g(rb_grid(rb.ntB, R, Rc));
+#define X(KK) \
+  case KK:                                                                                                    \
+    if (Rc > 1 && HoldRb<T, KK, 1>::v)                                                                        \
+      hipLaunchKernelGGL((k_rb_update<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);        \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_rb_update<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);       \
+    break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rb_addsol_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
+                              double* xB, const T* d, const T* p) {
+  if (rb.ntB == 0) return hipSuccess;
+  const dim3 g(rb_grid(rb.ntB, R, Rc));
+#define X(KK) \
+  case KK: hipLaunchKernelGGL((k_rb_addsol<T, KK>), g, dim3(TILE), 0, s, rbd, st, xB, d, p, R, Rc); break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+#define RB_INST(T)                                                                                           \
+  hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st, \
+                           int want, const T* v, T* u) {                                                     \
+    return launch_rb_red_t<T>(s, rb, rbd, R, Rc, st, want, v, u);                                            \
+  }                                                                                                          \
+  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
+                              const RhsState* st, const double* c, const double* xB, const double* u64, T* r, \
+                              T* p, double* part, int pstride) {                                             \
+    return launch_rb_refine_t<T>(s, rb, rbd, R, Rc, st, c, xB, u64, r, p, part, pstride);                    \
+  }                                                                                                          \
+  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
+                              const RhsState* st, const T* p, const T* u, const T* r, T* q, double* part,     \
+                              int pstride) {                                                                 \
+    return launch_rb_matvec_t<T>(s, rb, rbd, R, Rc, st, p, u, r, q, part, pstride);                          \
+  }                                                                                                          \
+  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
+                              const RhsState* st, T* d, T* r, T* p, const T* q) {                            \
+    return launch_rb_update_t<T>(s, rb, rbd, R, Rc, st, d, r, p, q);                                         \
+  }                                                                                                          \
+  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
+                              const RhsState* st, double* xB, const T* d, const T* p) {                      \
+    return launch_rb_addsol_t<T>(s, rb, rbd, R, Rc, st, xB, d, p);                                           \
   }
 RB_INST(double)
 RB_INST(float)
@@ -621,22 +747,21 @@ RB_INST(float)
 
 hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
                              const double* xB, double* x) {
-  const int tiles = rb.ntR + rb.ntB;
-  if (tiles == 0) return hipSuccess;
+  if (rb.ntN == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(tiles, R), dim3(TILE), 0, s, rb, st, b, xB, x); break;
+  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, b, xB, x); break;
   RB_K_SWITCH(rb.K, X)
 #undef X
   return hipGetLastError();
 }
 
 hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
-                              int ntBR) {
+                              int ntN) {
   const int g = (R + FIN_WAVES - 1) / FIN_WAVES;
   if (kind == 0)
-    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntBR);
+    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
   else
-    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntBR);
+    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
   return hipGetLastError();
 }
 

@@ -74,26 +74,26 @@ hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, do
                            double* D64, float* D32, double* S64, float* S32, int* bad);
 hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
                            double* t, double* c, double* xB, double* bbpart);
-hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, int want,
-                         const double* v, double* u);
-hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st, int want,
-                         const float* v, float* u);
+// Rc: right-hand sides per workgroup in the solver-round launches.
 #define GP_RB_DECL(T)                                                                                      \
-  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st,  \
-                              const double* c, const double* xB, const double* u64, T* r, T* p, double* part, \
+  hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,                \
+                           const RhsState* st, int want, const T* v, T* u);                                \
+  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
+                              const RhsState* st, const double* c, const double* xB, const double* u64, T* r, \
+                              T* p, double* part, int pstride);                                            \
+  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
+                              const RhsState* st, const T* p, const T* u, const T* r, T* q, double* part,   \
                               int pstride);                                                                \
-  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st,  \
-                              const T* p, const T* u, const T* r, T* q, double* part, int pstride);        \
-  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st,  \
-                              T* d, T* r, T* p, const T* q);                                               \
-  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, const RhsState* st,  \
-                              double* xB, const T* d, const T* p);
+  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
+                              const RhsState* st, T* d, T* r, T* p, const T* q);                           \
+  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
+                              const RhsState* st, double* xB, const T* d, const T* p);
 GP_RB_DECL(double)
 GP_RB_DECL(float)
 #undef GP_RB_DECL
 hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
                              const double* xB, double* x);
 hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
-                              int ntBR);
+                              int ntN);
 
 }  // namespace gp

@@ -21,14 +21,17 @@ namespace gp {
 namespace rt {
 
 struct RbData {
-  int NB = 0, NR = 0, ntB = 0, ntR = 0;
-  int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr;
+  int NB = 0, NR = 0, ntB = 0, ntR = 0, ntN = 0;
+  int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr, *vpos = nullptr;
   double *D64 = nullptr, *S64 = nullptr, *P64 = nullptr;
   float *D32 = nullptr, *S32 = nullptr, *P32 = nullptr;
   RbDev* d_desc = nullptr;   // device copies of the descriptors a solver round reads
   Prob* d_prob = nullptr;
   RbDev h_desc{};            // their host sources (kept alive for the asynchronous copies)
   Prob h_prob{};
+  // shape of the last FP32 solve: mean inner-solve length and refinements
+  // (the first round of the next solve is planned from it)
+  int hist_est = 0, hist_outer = 0;
   std::vector<std::pair<void*, size_t>> allocs;
 };
 
@@ -52,6 +55,7 @@ RbDev rb_dev(const gp_op* op) {
   v.red = d.red;
   v.nbB = d.nbB;
   v.nbR = d.nbR;
+  v.vpos = d.vpos;
   v.D64 = d.D64;
   v.D32 = d.D32;
   v.S64 = d.S64;
@@ -62,6 +66,7 @@ RbDev rb_dev(const gp_op* op) {
   v.NR = d.NR;
   v.ntB = d.ntB;
   v.ntR = d.ntR;
+  v.ntN = d.ntN;
   v.N = op->N;
   v.K = op->K;
   for (int k = 0; k < op->K; ++k) {
@@ -97,6 +102,9 @@ int build_lists(gp_op* op) {
   d->NR = (int)red.size();
   d->ntB = (d->NB + TILE - 1) / TILE;
   d->ntR = (d->NR + TILE - 1) / TILE;
+  d->ntN = (N + TILE - 1) / TILE;
+  std::vector<int> vpos(N);
+  for (int n = 0; n < N; ++n) vpos[n] = 2 * pos[n] + colour[n];
   auto table = [&](const std::vector<int>& list, std::vector<int>& out) -> bool {
     const size_t n = list.size();
     out.assign(6 * n, -1);
@@ -117,6 +125,7 @@ int build_lists(gp_op* op) {
   int st = GP_OK;
   if ((st = rb_alloc(c, d, blk.size(), &d->blk)) || (st = rb_alloc(c, d, red.size(), &d->red)) ||
       (st = rb_alloc(c, d, nbB.size(), &d->nbB)) || (st = rb_alloc(c, d, nbR.size(), &d->nbR)) ||
+      (st = rb_alloc(c, d, vpos.size(), &d->vpos)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->D64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->D32)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->S64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->S32)) ||
       (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)) ||
@@ -130,6 +139,7 @@ int build_lists(gp_op* op) {
   HIPTRY(up(d->red, red));
   HIPTRY(up(d->nbB, nbB));
   HIPTRY(up(d->nbR, nbR));
+  HIPTRY(up(d->vpos, vpos));
   HIPTRY(hipStreamSynchronize(c->stream));
   return GP_OK;
 }
@@ -140,25 +150,25 @@ struct Round {
   gp_ctx* c;
   const RbDev& h;
   const RbData& d;
-  int R, pstride, ntBR;
+  int R, Rc, Rco, pstride, ntN;   // Rco: right-hand sides per workgroup of the outer step
   RhsState* st;
   double *part, *bb, *c64, *xB, *u64;
   T *dv, *rv, *pv, *qv, *uv;
 
   // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
   int outer(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, st, xB, dv, pv));
-    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, st, PH_OUTER, xB, u64));
-    PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, st, c64, xB, u64, rv, pv, part, pstride));
-    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntBR));
+    PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, Rco, st, xB, dv, pv));
+    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, Rco, st, PH_OUTER, xB, u64));
+    PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, Rco, st, c64, xB, u64, rv, pv, part, pstride));
+    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
     return GP_OK;
   }
   // q = S p with the seven inner products, finalise, update
   int inner(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, st, PH_INNER, pv, uv));
-    PROFILED(c, GP_KERNEL_RB_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, st, pv, uv, rv, qv, part, pstride));
-    HIPTRY(launch_rb_finalize(q, 1, R, d.d_prob, bb, h.ntB, ntBR));
-    PROFILED(c, GP_KERNEL_RB_UPDATE, launch_rb_update(q, h, d.d_desc, R, st, dv, rv, pv, qv));
+    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, Rc, st, PH_INNER, pv, uv));
+    PROFILED(c, GP_KERNEL_RB_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, Rc, st, pv, uv, rv, qv, part, pstride));
+    HIPTRY(launch_rb_finalize(q, 1, R, d.d_prob, bb, h.ntB, ntN));
+    PROFILED(c, GP_KERNEL_RB_UPDATE, launch_rb_update(q, h, d.d_desc, R, Rc, st, dv, rv, pv, qv));
     return GP_OK;
   }
   // `len` iterations, iteration i preceded by the outer step when bit i of
@@ -253,7 +263,7 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   RbData& d = *op->rb;
   const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
-  const int K = op->K, ntBR = d.ntB + d.ntR, pstride = std::max(d.ntB, 1);
+  const int K = op->K, ntN = d.ntN, pstride = std::max(d.ntB, 1);
   const size_t nbv = (size_t)R * K * d.NB, nrv = (size_t)R * K * d.NR;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -262,7 +272,7 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
     return at;
   };
   const size_t o_st = take((size_t)R * sizeof(RhsState)), o_part = take((size_t)NPART * R * pstride * 8),
-               o_bb = take((size_t)R * std::max(ntBR, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
+               o_bb = take((size_t)R * std::max(ntN, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
                o_u64 = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
                o_q = take(nbv * tsz), o_u = take(nrv * tsz), o_prof = take(NPROF * sizeof(long long));
   if (int st = ensure_ws(c, off)) return st;
@@ -297,25 +307,38 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
       if (it.R > 0)
         PROFILED(c, GP_KERNEL_RB_EDGE,
                  launch_rb_split(s, d.h_desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, u64 + r0 * K * d.NR,
-                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntBR));
+                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN));
       r0 += (size_t)it.R;
     }
   }
 
   const int chunk = o.chunk > 0 ? o.chunk : 8;
+  // right-hand sides per workgroup: the largest of 8, 4, 2 that still leaves
+  // at least 1024 workgroups (four per compute unit), else 1
+  int Rc = o.rhs_tile > 0 ? std::min(o.rhs_tile, RCMAX) : 1;
+  if (o.rhs_tile <= 0)
+    for (int cand : {8, 4, 2})
+      if ((long)d.ntB * ((R + cand - 1) / cand) >= 1024) {
+        Rc = cand;
+        break;
+      }
+  Rc = std::max(1, std::min(Rc, R));
+  // the FP64 outer step holds no blocks across right-hand sides (register
+  // pressure): one per workgroup
+  const int Rco = 1;
   const bool graphs = c->use_graphs && !c->prof_on;
   const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
                           std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
-                          std::to_string(R) + "," + (f32 ? "f" : "d");
+                          std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(Rc);
   auto run_round = [&](int len, uint64_t mask) -> int {
     auto enq = [&](hipStream_t q) -> int {
       if (f32) {
-        const Round<float> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
+        const Round<float> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                               (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
                               (float*)(ws + o_u)};
         return rd.round(q, len, mask);
       }
-      const Round<double> rd{c, d.h_desc, d, R, pstride, ntBR, sts, part, bb, c64, xB, u64,
+      const Round<double> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                              (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
                              (double*)(ws + o_u)};
       return rd.round(q, len, mask);
@@ -330,6 +353,20 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   int n_outer = R, n_inner = 0;
   int round_len = chunk;
   uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
+  if (f32 && o.chunk <= 0 && d.hist_est > 0) {
+    // the previous solve's shape: refinements expected every hist_est
+    // iterations, the outer step placed around each (as the planned rounds do)
+    uint64_t mask = 1;
+    int need = 1;
+    for (int k = 1; k < d.hist_outer; ++k) {
+      const int slot = k * d.hist_est + 1;
+      for (int t = slot - 1; t <= slot + 1; ++t)
+        if (t >= 1 && t <= 64) mask |= 1ull << (t - 1);
+      need = slot;
+    }
+    round_len = std::max(1, std::min(need, 2 * chunk));
+    round_mask = mask;
+  }
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
   while (n_outer > 0 || n_inner > 0) {
@@ -359,6 +396,15 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
     HIPTRY(hipMemcpy(pf.data(), prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
     rb_account(c, op, R, tsz, o.zero_guess != 0, pf);
     if (int e = prof_resolve(c)) return e;
+  }
+  if (f32) {
+    int est = 0, outer = 0;
+    for (const RhsState& h : hs) {
+      if (h.outer >= 2) est = std::max(est, (h.total_it + h.outer - 2) / (h.outer - 1));
+      outer = std::max(outer, h.outer);
+    }
+    d.hist_est = est;
+    d.hist_outer = outer;
   }
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   int ret = GP_OK;
