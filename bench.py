@@ -224,7 +224,8 @@ def roofline(prof):
             "bytes_per_launch": round(d["bytes"] / d["launches"])}
 
 
-KERNEL_KIND_OF = [("k_rb_red", "rb_red"), ("k_rb_matvec", "rb_matvec"), ("k_rb_update", "rb_update"),
+KERNEL_KIND_OF = [("k_rb_red<double", "rb_red64"), ("k_rb_red", "rb_red"), ("k_rb_matvec", "rb_matvec"),
+                  ("k_rb_update", "rb_update"),
                   ("k_rb_refine", "rb_refine"), ("k_rb_addsol", "rb_addsol"), ("k_rb_split", "rb_edge"),
                   ("k_rb_recover", "rb_edge"), ("k_rb_setup", "precond"),
                   ("k_matvec_zm", "matvec"), ("k_matvec", "matvec"), ("k_update", "update"),

@@ -137,13 +137,14 @@ typedef struct gp_item {
 #define GP_KERNEL_APPLY    9  /* FP64 y = Q x                                  */
 #define GP_KERNEL_DATA    10  /* data tensors and data-term assembly          */
 /* red-black incomplete Cholesky solver (GP_PRECOND_RB_IC0)                   */
-#define GP_KERNEL_RB_RED     11  /* even-voxel stage u = Q_nn^{-1}(alpha .* sum v) */
+#define GP_KERNEL_RB_RED     11  /* even-voxel stage u = Q_nn^{-1}(alpha .* sum v) of an inner step */
 #define GP_KERNEL_RB_MATVEC  12  /* odd-voxel stage q = S p, inner products    */
 #define GP_KERNEL_RB_UPDATE  13  /* d, r, p update on the odd voxels           */
 #define GP_KERNEL_RB_REFINE  14  /* FP64 residual of the Schur system          */
 #define GP_KERNEL_RB_ADDSOL  15  /* FP64 odd-voxel solution += correction      */
 #define GP_KERNEL_RB_EDGE    16  /* split of b and x, recovery of the solution */
-#define GP_KERNEL_KINDS   17
+#define GP_KERNEL_RB_RED64   17  /* even-voxel stage of the FP64 refinement     */
+#define GP_KERNEL_KINDS   18
 
 /* Accumulated per kernel kind while profiling is enabled.  `units` counts
  * (right-hand side, voxel) pairs processed; `bytes` is the algorithmic HBM

@@ -158,7 +158,7 @@ struct Round {
   // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
   int outer(hipStream_t q) const {
     PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, Rco, st, xB, dv, pv));
-    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, Rco, st, PH_OUTER, xB, u64));
+    PROFILED(c, GP_KERNEL_RB_RED64, launch_rb_red(q, h, d.d_desc, R, Rco, st, PH_OUTER, xB, u64));
     PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, Rco, st, c64, xB, u64, rv, pv, part, pstride));
     HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
     return GP_OK;
@@ -192,10 +192,10 @@ void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, 
   const double K = op->K, NB = d.NB, NR = d.NR, N = op->N, ts = (double)tsz, NBt = K * (K + 1) / 2;
   const double mv = (double)pf[PF_MATVEC_RHS], ref = (double)pf[PF_REFINE_RHS];
   // red stage: the black vector read, u written; the red inverses
-  const double ref_x = ref - (double)pf[PF_REFINE_X0];   // refinements from a non-zero x
-  prof_add(c, GP_KERNEL_RB_RED, (mv + ref_x) * NR,
-           mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts + ref_x * K * (NB + NR) * 8 +
-               pf[PF_REFINE_ACT] * NBt * NR * 8);
+  prof_add(c, GP_KERNEL_RB_RED, mv * NR, mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts);
+  // the same in FP64 on x_B for refinements from a non-zero x
+  const double ref_x = ref - (double)pf[PF_REFINE_X0];
+  prof_add(c, GP_KERNEL_RB_RED64, ref_x * NR, ref_x * K * (NB + NR) * 8 + pf[PF_REFINE_ACT] * NBt * NR * 8);
   // black stage: p, u, r read, q written; Q_mm and the Schur inverses
   prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
   // p, q, r, d read (d not on the first step), d, r, p written; Schur inverses
