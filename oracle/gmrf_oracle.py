@@ -36,6 +36,11 @@ It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
   block IC(0) factor (K x K voxel blocks, zero fill outside Q's block
   pattern) under a given voxel order, here the red-black two-colour order,
   and PCG with it (Section 3.1);
+* the full conditional of the AR coefficients A (Appendix A.2): its data
+  part from the lagged residuals of Y - XW (an AR(P) regression per voxel)
+  and in the tensor form, its Monte Carlo SVB expectation over draws of W, the
+  operator with K = P, prior precisions beta and D_a = D_w, and one SVB
+  iteration over W, A and the hyperparameters (Section 3.3, Appendix B);
 * Hutchinson estimates with Rademacher probes of tr(Q^{-1}), of tr([Q^{-1}]_kk)
   and of tr(D_w [Q^{-1}]_kk), the trace inside E[W_k D_w W_k'] of Section 3.3
   (quadratic-form expectation).
@@ -60,7 +65,7 @@ import scipy.sparse.linalg as spl
 __all__ = [
     "Grid", "grid", "data_term_whitening", "data_term_mc", "data_tensors", "data_term_from_tensors",
     "data_tensors_noise", "quadform", "residual_ss", "residual_ss_from_tensors", "alpha_posterior",
-    "lambda_posterior", "svb_step",
+    "lambda_posterior", "svb_step", "ar_term_residuals", "ar_term_mc", "ar_term_from_tensors", "svb_step_ar",
     "precision", "apply", "relres",
     "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
     "sample", "hutchinson", "cholesky_mean_and_sample",
@@ -291,6 +296,85 @@ def lambda_posterior(rss_mean: np.ndarray, T: int, P: int, u1: float, u2: float)
     """Ga(u~1n, u~2) of lambda_n: 1/u~1n = rss_n/2 + 1/u1, u~2 = (T-P)/2 + u2."""
     u1t = 1.0 / (0.5 * np.asarray(rss_mean, dtype=float) + 1.0 / u1)
     return u1t, (T - P) / 2.0 + u2
+
+
+# --------------------------------------------------------- AR coefficients A
+def ar_term_residuals(X: np.ndarray, Y: np.ndarray, W: np.ndarray, lam: np.ndarray, P: int):
+    """Data part of the full conditional of the AR coefficients (Appendix A.2,
+    full conditional of A), conditional on the first P scans: with the
+    residuals e = Y - X W and, for voxel n, the P x (T-P) matrix E_n of lagged
+    residuals (row p - 1 holds e[t-p] for t = P..T-1), the likelihood is
+    Gaussian in A_n with precision J_n = lambda_n E_n E_n' and linear term
+    b_n = lambda_n E_n e_n[P:].  W is (K, N).  Returns (J (N, P, P), b (P, N))."""
+    T = X.shape[0]
+    N = Y.shape[1]
+    e = Y - X @ W
+    J = np.empty((N, P, P))
+    b = np.empty((P, N))
+    for n in range(N):
+        E = np.stack([e[P - p:T - p, n] for p in range(1, P + 1)])      # (P, T-P)
+        J[n] = lam[n] * E @ E.T
+        b[:, n] = lam[n] * E @ e[P:, n]
+    return J, b
+
+
+def ar_term_mc(X: np.ndarray, Y: np.ndarray, Wd: np.ndarray, lam: np.ndarray, P: int):
+    """The SVB expectation of the above over Monte Carlo draws Wd (Ns, K, N) of
+    W (Appendix B): the mean over draws of J_n and of b_n."""
+    Js, bs = zip(*[ar_term_residuals(X, Y, Wd[j], lam, P) for j in range(Wd.shape[0])])
+    return np.mean(Js, axis=0), np.mean(bs, axis=0)
+
+
+def ar_term_from_tensors(tensors, extra, Wd: np.ndarray, lam: np.ndarray):
+    """The tensor form of Appendix A.2 (full conditional of A), averaged over
+    draws Wd (Ns, K, N):
+      J_n = lambda_n mean_j [d_n d_n' - D_n W - (D_n W)' + W' S W],
+      b_n = lambda_n mean_j [Y_n'd_n' - W' B~_n' + W' R W],   W = Wd[j][:, n],
+    with (D_n W)[p][q] = sum_k D_n[p][k][q] W_k, (W'SW)[p][q] = sum_kl W_k S[p][k][l][q] W_l,
+    (W'B~')[p] = sum_k B~_n[p][k] W_k and (W'RW)[p] = sum_kl W_k R[k][l][p] W_l."""
+    XX, R, S, YX, Bt, Dt = tensors
+    YY, dY, dd = extra
+    N, P = dY.shape
+    Ns = Wd.shape[0]
+    J = np.zeros((N, P, P))
+    b = np.zeros((P, N))
+    for n in range(N):
+        for j in range(Ns):
+            w = Wd[j][:, n]
+            DW = np.einsum("pkq,k->pq", Dt[n], w)
+            WSW = np.einsum("k,pklq,l->pq", w, S, w)
+            J[n] += dd[n] - DW - DW.T + WSW
+            b[:, n] += dY[n] - Bt[n] @ w + np.einsum("k,klp,l->p", w, R, w)
+        J[n] *= lam[n] / Ns
+        b[:, n] *= lam[n] / Ns
+    return J, b
+
+
+def svb_step_ar(g: Grid, X, Y, A, z1w, z2w, z1a, z2a, alpha, beta, lam, q1=10.0, q2=0.1, r1=10000.0,
+                r2=0.1, u1=10.0, u2=0.1, tol: float = 1e-13):
+    """One spatial-VB iteration with the AR coefficients (Section 3.3, Appendix
+    B), in the order W, A, then the hyperparameters:
+      q(W): the data term with the mean lambda and the draws A (Ns, P, N); Ns
+            Algorithm-2 samples with z1w, z2w and prior precisions alpha;
+      q(A): the A data term with the new W draws; Ns Algorithm-2 samples on
+            the operator with K = P, prior precisions beta and D_a = D_w, with
+            z1a (Ns, P, dirs, N), z2a (Ns, P, N);
+      alpha_k, beta_p: Gamma posterior means from the Monte Carlo mean of the
+            spatial quadratic forms (r1, r2 the prior of beta);
+      lambda_n: Gamma posterior mean from the Monte Carlo mean of the whitened
+            residual sum of squares over the pairs (W^j, A^j).
+    Returns (W, A, alpha_mean, beta_mean, lam_mean)."""
+    T = X.shape[0]
+    P = A.shape[1]
+    B, bw = data_term_mc(X, Y, A, lam)
+    Wn = sample(g, alpha, B, bw, z1w, z2w, tol)
+    J, ba = ar_term_mc(X, Y, Wn, lam, P)
+    An = sample(g, beta, J, ba, z1a, z2a, tol)
+    q1t, q2t = alpha_posterior(quadform(g, Wn).mean(axis=0), g.N, q1, q2)
+    r1t, r2t = alpha_posterior(quadform(g, An).mean(axis=0), g.N, r1, r2)
+    rss = np.mean([residual_ss(X, Y, Wn[j], An[j]) for j in range(Wn.shape[0])], axis=0)
+    u1t, u2t = lambda_posterior(rss, T, P, u1, u2)
+    return Wn, An, q1t * q2t, r1t * r2t, u1t * u2t
 
 
 # ---------------------------------------------------------------------- operator
