@@ -232,13 +232,34 @@ int gp_data_assemble(gp_data* d, const double* lambda, int Ns, const double* A, 
  * doubles each, any may be NULL): rss, scale, mean.  Blocking.            */
 int gp_data_lambda(gp_data* d, int Ns, const double* W, const double* A, double u1, double u2, double* rss,
                    double* scale, double* mean);
+
+/* gp_data_assemble_ar: the system of the AR coefficients (Appendix A.2, full
+ * conditional of A; Appendix B for its SVB expectation over Ns >= 1 draws of
+ * W), for noise precisions lambda (device, N) and draws W (device,
+ * [Ns][K][N]):
+ *   J_n  = lambda_n mean_j [d_n d_n' - D_n w - (D_n w)' + w' S w],
+ *   b_an = lambda_n mean_j [Y_n'd_n' - w' B~_n' + w' R w],        w = W[j][.][n],
+ * with (D_n w)[p][q] = sum_k D_n[p][k][q] w_k, (w'Sw)[p][q] =
+ * sum_kl w_k S[p][k][l][q] w_l, (w'B~')[p] = sum_k B~_n[p][k] w_k and
+ * (w'Rw)[p] = sum_kl w_k R[k][l][p] w_l.  The P x P blocks J_n are installed
+ * in op_a as gp_op_set_blocks does (factorised, GP_ERR_NOT_SPD with
+ * *bad_voxel_host on failure): op_a is an operator with K = P built on the
+ * same mask as the data's operator (same nx, ny, nz and N), whose alpha plays
+ * the prior precisions beta of A, so that op_a is
+ *   J~ = diag(beta) (x) D_a + H_a' blkdiag_n(J_n) H_a   with D_a = D_w,
+ * and every solver, sampler and trace entry point applies to it.  b_a is
+ * written to ba (device [P][N], the p-major vec(A'); may be NULL).  Requires
+ * P >= 1.  Blocking.                                                        */
+int gp_data_assemble_ar(gp_data* d, gp_op* op_a, const double* lambda, int Ns, const double* W, double* ba,
+                        int64_t* bad_voxel_host);
 int gp_data_destroy(gp_data* d);
 
-/* Gamma prior parameters of alpha_k ~ Ga(q1, q2) and lambda_n ~ Ga(u1, u2)
- * (scale, shape; Section 2).  gp_hyper_default: the values the paper uses,
- * q1 = u1 = 10, q2 = u2 = 0.1.                                               */
+/* Gamma prior parameters of alpha_k ~ Ga(q1, q2), lambda_n ~ Ga(u1, u2) and
+ * of the AR-coefficient precisions beta_p ~ Ga(r1, r2) (scale, shape;
+ * Section 2).  gp_hyper_default: the values the paper uses, q1 = u1 = 10,
+ * r1 = 10000, q2 = u2 = r2 = 0.1.                                          */
 typedef struct gp_hyper {
-  double q1, q2, u1, u2;
+  double q1, q2, u1, u2, r1, r2;
 } gp_hyper;
 void gp_hyper_default(gp_hyper* h);
 
@@ -261,13 +282,37 @@ int gp_svb_step(gp_data* d, int Ns, const double* A, const double* z1, const dou
                 double* lambda, double* alpha_host, const gp_hyper* prior, double* bw_work,
                 const gp_opts* opts, gp_stats* stats);
 
+/* gp_svb_step_ar: one iteration of the spatial VB scheme over W, the AR
+ * coefficients A and the precisions alpha, beta, lambda (Section 3.3,
+ * Appendix B), in the order:
+ *   1. q(W) as steps 1-3 of gp_svb_step, with the draws A (device [Ns][P][N])
+ *      and alpha_host (K), samples into W (device [Ns][K][N], warm starts),
+ *      random vectors z1w, z2w;
+ *   2. q(A): gp_data_assemble_ar with lambda and the new W into op_a and
+ *      ba_work (device [P][N]), beta_host (P) as op_a's spatial precisions,
+ *      Ns samples by Algorithm 2 into A (warm starts), random vectors z1a
+ *      ([Ns][P][dirs][N]), z2a ([Ns][P][N]);
+ *   3. alpha_host <- gp_alpha_posterior means over W (q1, q2); beta_host <-
+ *      gp_alpha_posterior means over A on op_a (r1, r2); lambda <- the
+ *      gp_data_lambda means over the pairs (W^j, A^j) (u1, u2).
+ * z1w, z2w, z1a, z2a: all given or all NULL (device draws: W's from
+ * opts->seed as in gp_sample, A's from that seed XOR 0x9E3779B97F4A7C15).
+ * prior: NULL for gp_hyper_default.  stats_w, stats_a: Ns entries each (may
+ * be NULL).  Requires P >= 1.  Blocking.                                    */
+int gp_svb_step_ar(gp_data* d, gp_op* op_a, int Ns, const double* z1w, const double* z2w, double* W,
+                   const double* z1a, const double* z2a, double* A, double* lambda, double* alpha_host,
+                   double* beta_host, const gp_hyper* prior, double* bw_work, double* ba_work,
+                   const gp_opts* opts, gp_stats* stats_w, gp_stats* stats_a);
+
 /* gp_alpha_posterior: the spatial-precision posterior (Section 3.2 full
  * conditional; Section 3.3 and Appendix B for the SVB Monte Carlo form):
  * qf[r][k] = W_k D_w W_k' = ||G_w W_k'||^2 of each of R samples W (device,
  * [R][K][N]), then alpha_k ~ Ga(scale_k, shape) with
  * 1/scale_k = mean_r qf[r][k] / 2 + 1/q1 and shape = N/2 + q2; mean_k =
  * scale_k * shape.  Outputs on the host: qf (R*K, may be NULL), scale (K),
- * mean (K).  Blocking.                                                       */
+ * mean (K).  On an AR-coefficient operator (K = P, see gp_data_assemble_ar)
+ * with samples of A and (r1, r2) it is the posterior of beta (Appendix A.2,
+ * full conditional of beta), which has the same form.  Blocking.            */
 int gp_alpha_posterior(gp_op* op, int R, const double* W, double q1, double q2, double* qf_host,
                        double* scale_host, double* mean_host);
 

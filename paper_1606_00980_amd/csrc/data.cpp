@@ -28,7 +28,8 @@ struct gp_data {
   double* YY = nullptr;   // [N]
   double* dY = nullptr;   // [P][N]
   double* dd = nullptr;   // [P][P][N]
-  size_t nX = 0, nG = 0, nYX = 0, nBt = 0, nDt = 0, nBw = 0, nYY = 0, ndY = 0, ndd = 0;
+  double* Ja = nullptr;   // [N][P][P] assembled AR-coefficient blocks (allocated on first use)
+  size_t nX = 0, nG = 0, nYX = 0, nBt = 0, nDt = 0, nBw = 0, nYY = 0, ndY = 0, ndd = 0, nJa = 0;
 };
 
 namespace {
@@ -44,6 +45,7 @@ void release(gp_data* d) {
   dev_free(c, d->YY, d->nYY * sizeof(double));
   dev_free(c, d->dY, d->ndY * sizeof(double));
   dev_free(c, d->dd, d->ndd * sizeof(double));
+  dev_free(c, d->Ja, d->nJa * sizeof(double));
   delete d;
 }
 
@@ -184,6 +186,43 @@ void gp_hyper_default(gp_hyper* h) {
   h->q2 = 0.1;
   h->u1 = 10.0;
   h->u2 = 0.1;
+  h->r1 = 10000.0;
+  h->r2 = 0.1;
+}
+
+int gp_data_assemble_ar(gp_data* d, gp_op* op_a, const double* lambda, int Ns, const double* W, double* ba,
+                        int64_t* bad_voxel) {
+  if (bad_voxel) *bad_voxel = -1;
+  if (!d || !op_a || !lambda || !W) return fail(GP_ERR_INVALID_ARG, "data, op_a, lambda or W is NULL");
+  if (Ns < 1) return fail(GP_ERR_INVALID_ARG, "Ns must be >= 1");
+  if (d->P < 1) return fail(GP_ERR_INVALID_ARG, "the data have no AR coefficients (P = 0)");
+  const gp_op* op = d->op;
+  if (op_a->ctx != op->ctx) return fail(GP_ERR_INVALID_ARG, "op_a belongs to another context");
+  if (op_a->K != d->P) return fail(GP_ERR_INVALID_ARG, "op_a must have K = P");
+  if (op_a->N != op->N || op_a->nx != op->nx || op_a->ny != op->ny || op_a->nz != op->nz)
+    return fail(GP_ERR_INVALID_ARG, "op_a must be built on the data operator's mask");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  const int K = d->K, P = d->P, N = d->N;
+  if (!d->Ja) {
+    d->nJa = (size_t)N * P * P;
+    if (int st = dev_alloc(c, d->nJa * sizeof(double), (void**)&d->Ja)) {
+      d->nJa = 0;
+      return st;
+    }
+  }
+  PROFILED(c, GP_KERNEL_DATA,
+           launch_data_assemble_ar(c->stream, K, P, N, Ns, d->G, d->Bt, d->Dt, d->dY, d->dd, lambda, W, d->Ja, ba));
+  {
+    // tensors (B~, D, dY, dd), lambda and the draws read, blocks (both
+    // triangles) and b_a written
+    const double per = (double)P * K + (double)P * K * P + P + (double)P * P + 1 + (double)Ns * K + (double)P * P +
+                       (ba ? P : 0);
+    prof_add(c, GP_KERNEL_DATA, N, (double)N * per * 8.0);
+  }
+  return install_blocks(op_a, d->Ja, bad_voxel);
 }
 
 int gp_svb_step(gp_data* d, int Ns, const double* A, const double* z1, const double* z2, double* W, double* lambda,
@@ -203,6 +242,41 @@ int gp_svb_step(gp_data* d, int Ns, const double* A, const double* z1, const dou
   if (int st = gp_alpha_posterior(op, Ns, W, h.q1, h.q2, nullptr, scale.data(), mean.data())) return st;
   if (int st = gp_data_lambda(d, Ns, W, A, h.u1, h.u2, nullptr, nullptr, lambda)) return st;
   std::copy(mean.begin(), mean.end(), alpha_host);
+  return GP_OK;
+}
+
+int gp_svb_step_ar(gp_data* d, gp_op* op_a, int Ns, const double* z1w, const double* z2w, double* W,
+                   const double* z1a, const double* z2a, double* A, double* lambda, double* alpha_host,
+                   double* beta_host, const gp_hyper* prior, double* bw_work, double* ba_work,
+                   const gp_opts* opts, gp_stats* stats_w, gp_stats* stats_a) {
+  if (!d || !op_a || !W || !A || !lambda || !alpha_host || !beta_host || !bw_work || !ba_work)
+    return fail(GP_ERR_INVALID_ARG, "null argument");
+  if (Ns < 1) return fail(GP_ERR_INVALID_ARG, "Ns must be >= 1");
+  if (d->P < 1) return fail(GP_ERR_INVALID_ARG, "the data have no AR coefficients (P = 0)");
+  const bool given = z1w && z2w && z1a && z2a;
+  if (!given && (z1w || z2w || z1a || z2a))
+    return fail(GP_ERR_INVALID_ARG, "z1w, z2w, z1a, z2a must all be given or all NULL");
+  gp_hyper h;
+  if (prior) h = *prior; else gp_hyper_default(&h);
+  gp_op* op = d->op;
+  // q(W): data term with the current lambda and AR draws, prior alpha, samples
+  if (int st = gp_data_assemble(d, lambda, Ns, A, bw_work, nullptr)) return st;
+  if (int st = gp_op_set_alpha(op, alpha_host)) return st;
+  if (int st = gp_sample(op, Ns, bw_work, z1w, z2w, W, opts, stats_w)) return st;
+  // q(A): the AR-coefficient system with the new W draws, prior beta, samples
+  if (int st = gp_data_assemble_ar(d, op_a, lambda, Ns, W, ba_work, nullptr)) return st;
+  if (int st = gp_op_set_alpha(op_a, beta_host)) return st;
+  gp_opts oa;
+  if (opts) oa = *opts; else gp_opts_default(&oa);
+  if (!given) oa.seed = oa.seed ^ 0x9E3779B97F4A7C15ull;   // a stream of draws different from W's
+  if (int st = gp_sample(op_a, Ns, ba_work, z1a, z2a, A, &oa, stats_a)) return st;
+  // alpha, beta and lambda from the samples' Monte Carlo statistics
+  std::vector<double> scale(std::max(op->K, op_a->K)), am(op->K), bm(op_a->K);
+  if (int st = gp_alpha_posterior(op, Ns, W, h.q1, h.q2, nullptr, scale.data(), am.data())) return st;
+  if (int st = gp_alpha_posterior(op_a, Ns, A, h.r1, h.r2, nullptr, scale.data(), bm.data())) return st;
+  if (int st = gp_data_lambda(d, Ns, W, A, h.u1, h.u2, nullptr, nullptr, lambda)) return st;
+  std::copy(am.begin(), am.end(), alpha_host);
+  std::copy(bm.begin(), bm.end(), beta_host);
   return GP_OK;
 }
 

@@ -202,6 +202,67 @@ __global__ __launch_bounds__(DT) void k_data_rss(int K, int P, int N, int Ns, co
   if (mean) mean[n] = u1t * u2t;
 }
 
+// The AR-coefficient system (full conditional of A, Appendix A.2; its SVB
+// expectation over Ns draws W^j for Ns > 1): blockIdx.y = output entry,
+// packed (p, q), q <= p, of
+//   J_n = lambda_n (dd_n - mean_j [D_n w + (D_n w)' - w' S w]),
+// then p of
+//   b_n = lambda_n (dY_n - mean_j [Bt_n w - w' R w]),          w = W^j_n,
+// with (D_n w)[p][q] = sum_k Dt[p][k][q] w_k, (w'Sw)[p][q] = sum_kl w_k S[p][k][l][q] w_l,
+// (Bt w)[p] = sum_k Bt[p][k] w_k, (w'Rw)[p] = sum_kl w_k R[k][l][p] w_l.  Globals in LDS.
+__global__ __launch_bounds__(DT) void k_data_assemble_ar(int K, int P, int N, int Ns, const double* __restrict__ G,
+                                                         const double* __restrict__ Bt, const double* __restrict__ Dt,
+                                                         const double* __restrict__ dY,
+                                                         const double* __restrict__ dd,
+                                                         const double* __restrict__ lambda,
+                                                         const double* __restrict__ W, double* __restrict__ Jout,
+                                                         double* __restrict__ ba) {
+  extern __shared__ double sG[];
+  const int nG = K * K + K * K * P + P * K * K * P;
+  for (int i = threadIdx.x; i < nG; i += DT) sG[i] = G[i];
+  __syncthreads();
+  const int n = blockIdx.x * DT + threadIdx.x;
+  if (n >= N) return;
+  const double* R = sG + K * K;
+  const double* S = R + K * K * P;
+  const int e = blockIdx.y, NBp = P * (P + 1) / 2;
+  const double lam = lambda[n];
+  double acc = 0.0;   // sum over draws of the W-dependent part
+  if (e < NBp) {
+    int p = 0;
+    while ((p + 1) * (p + 2) / 2 <= e) ++p;
+    const int q = e - p * (p + 1) / 2;
+    for (int j = 0; j < Ns; ++j) {
+      double dw = 0.0, wsw = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double wk = W[((size_t)j * K + k) * N + n];
+        dw += (Dt[(((size_t)p * K + k) * P + q) * N + n] + Dt[(((size_t)q * K + k) * P + p) * N + n]) * wk;
+        double sw = 0.0;
+        for (int l = 0; l < K; ++l) sw += S[((p * K + k) * K + l) * P + q] * W[((size_t)j * K + l) * N + n];
+        wsw += wk * sw;
+      }
+      acc += dw - wsw;
+    }
+    const double v = lam * (dd[((size_t)p * P + q) * N + n] - acc / Ns);
+    Jout[((size_t)n * P + p) * P + q] = v;
+    Jout[((size_t)n * P + q) * P + p] = v;
+  } else {
+    const int p = e - NBp;
+    for (int j = 0; j < Ns; ++j) {
+      double bw = 0.0, wrw = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double wk = W[((size_t)j * K + k) * N + n];
+        bw += Bt[((size_t)p * K + k) * N + n] * wk;
+        double rw = 0.0;
+        for (int l = 0; l < K; ++l) rw += R[(k * K + l) * P + p] * W[((size_t)j * K + l) * N + n];
+        wrw += wk * rw;
+      }
+      acc += bw - wrw;
+    }
+    if (ba) ba[(size_t)p * N + n] = lam * (dY[(size_t)p * N + n] - acc / Ns);
+  }
+}
+
 // Per (sample r, regressor k, tile): sum over the tile's voxels of the squared
 // differences to the in-mask +x, +y, +z neighbours (one term per adjacent
 // pair, so the total is W_k D_w W_k').  Fixed-order workgroup reduction.
@@ -284,6 +345,16 @@ hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, cons
   const int entries = K * (K + 1) / 2 + K;
   hipLaunchKernelGGL(k_data_assemble, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)nG * sizeof(double), s, K,
                      P, N, Ns, G, YX, Bt, Dt, lambda, A, Bout, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_data_assemble_ar(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* Bt,
+                                   const double* Dt, const double* dY, const double* dd, const double* lambda,
+                                   const double* W, double* Jout, double* ba) {
+  const int nG = K * K + K * K * P + P * K * K * P;
+  const int entries = P * (P + 1) / 2 + P;
+  hipLaunchKernelGGL(k_data_assemble_ar, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)nG * sizeof(double), s,
+                     K, P, N, Ns, G, Bt, Dt, dY, dd, lambda, W, Jout, ba);
   return hipGetLastError();
 }
 

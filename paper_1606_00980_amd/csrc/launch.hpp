@@ -39,6 +39,10 @@ hipError_t launch_data_rss(hipStream_t s, int K, int P, int N, int Ns, const dou
 // W_k D_w W_k' for R samples: partials [R*K][quadform_tiles(N)], out [R*K] (device)
 int quadform_tiles(int N);
 hipError_t launch_quadform(hipStream_t s, const OpDev& op, int R, const double* W, double* part, double* out);
+// J_n [N][P][P] (both triangles) and b_a [P][N] (may be null) of the AR-coefficient system
+hipError_t launch_data_assemble_ar(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* Bt,
+                                   const double* Dt, const double* dY, const double* dd, const double* lambda,
+                                   const double* W, double* Jout, double* ba);
 hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, const double* G, const double* YX,
                                 const double* Bt, const double* Dt, const double* lambda, const double* A,
                                 double* Bout, double* bw);

@@ -48,7 +48,7 @@ EXPORTS = [
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
     "gp_autotune", "gp_tune_save", "gp_tune_load",
     "gp_data_create", "gp_data_assemble", "gp_data_lambda", "gp_data_destroy", "gp_alpha_posterior",
-    "gp_hyper_default", "gp_svb_step",
+    "gp_hyper_default", "gp_svb_step", "gp_data_assemble_ar", "gp_svb_step_ar",
 ]
 
 GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
@@ -114,7 +114,7 @@ class GpServerStats(ctypes.Structure):
 
 class GpHyper(ctypes.Structure):
     _fields_ = [("q1", ctypes.c_double), ("q2", ctypes.c_double), ("u1", ctypes.c_double),
-                ("u2", ctypes.c_double)]
+                ("u2", ctypes.c_double), ("r1", ctypes.c_double), ("r2", ctypes.c_double)]
 
 
 class GmrfError(RuntimeError):
@@ -175,6 +175,9 @@ def _load() -> ctypes.CDLL:
         "gp_alpha_posterior": (i32, [vp, i32, vp, dbl, dbl, P(dbl), P(dbl), P(dbl)]),
         "gp_hyper_default": (None, [P(GpHyper)]),
         "gp_svb_step": (i32, [vp, i32, vp, vp, vp, vp, vp, P(dbl), P(GpHyper), vp, P(GpOpts), P(GpStats)]),
+        "gp_data_assemble_ar": (i32, [vp, vp, vp, i32, vp, vp, P(i64)]),
+        "gp_svb_step_ar": (i32, [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, P(dbl), P(dbl), P(GpHyper), vp, vp,
+                                 P(GpOpts), P(GpStats), P(GpStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -288,6 +291,36 @@ def gp_data_assemble(d: int, lam, Ns: int, A, bw=None) -> None:
         err = GmrfError(st, "gp_data_assemble", gp_last_error())
         err.bad_voxel = bad.value
         raise err
+
+
+def gp_data_assemble_ar(d: int, op_a: int, lam, Ns: int, W, ba=None) -> None:
+    bad = ctypes.c_int64(-1)
+    st = lib.gp_data_assemble_ar(d, op_a, _ptr(lam), Ns, _ptr(W), _ptr(ba), ctypes.byref(bad))
+    if st != GP_OK:
+        err = GmrfError(st, "gp_data_assemble_ar", gp_last_error())
+        err.bad_voxel = bad.value
+        raise err
+
+
+def gp_svb_step_ar(d: int, op_a: int, Ns: int, z1w, z2w, W, z1a, z2a, A, lam, alpha, beta, bw_work, ba_work,
+                   prior: GpHyper | None = None, opts: GpOpts | None = None, check: bool = True):
+    """One SVB iteration over W, A, alpha, beta and lambda; alpha and beta
+    (numpy) and W, A, lam (device) are updated in place.  Returns (status,
+    W-sampling stats, A-sampling stats)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    sw, sa = _stats_array(Ns), _stats_array(Ns)
+    o = opts if opts is not None else gp_opts_default()
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.gp_svb_step_ar(d, op_a, Ns, _ptr(z1w), _ptr(z2w), _ptr(W), _ptr(z1a), _ptr(z2a), _ptr(A), _ptr(lam),
+                            a.ctypes.data_as(dp), b.ctypes.data_as(dp),
+                            ctypes.byref(prior) if prior is not None else None, _ptr(bw_work), _ptr(ba_work),
+                            ctypes.byref(o), sw, sa)
+    if check:
+        _check(st, "gp_svb_step_ar")
+    alpha[:] = a
+    beta[:] = b
+    return st, _stats_list(sw, Ns), _stats_list(sa, Ns)
 
 
 def gp_data_lambda(d: int, Ns: int, W, A, u1: float, u2: float, rss=None, scale=None, mean=None) -> None:

@@ -214,3 +214,118 @@ def test_svb_steps_match_oracle(g, ctx, torch_cuda):
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+# ------------------------------------------------------ AR-coefficient system
+@pytest.mark.parametrize("P", [1, 3])
+@pytest.mark.parametrize("Ns", [1, 3])
+def test_ar_system_matches_oracle(g, ctx, torch_cuda, P, Ns):
+    """J_n and b_a against the lagged-residual regression (its SVB mean over
+    Ns draws of W), the installed operator diag(beta) (x) D_w + H'blkdiag(J)H
+    through an FP64 apply, and a solve for A."""
+    w = synth.tiny((13, 11, 7), 6, 4, seed=81 + P, T=70, P=P)
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    op_a = g.gp_op_create(ctx, w.mask, w.conn, P)
+    try:
+        d = g.gp_data_create(op, w.X.shape[0], P, w.X, dev(torch_cuda, w.Y))
+        try:
+            rng = np.random.default_rng(19)
+            lam = (1.0 / w.sigma2) * rng.uniform(0.5, 2.0, w.N)
+            Wd = w.W_true[None] + 0.2 * rng.standard_normal((Ns, w.K, w.N))
+            ba = torch_cuda.empty((P, w.N), dtype=torch_cuda.float64, device="cuda")
+            g.gp_data_assemble_ar(d, op_a, dev(torch_cuda, lam), Ns, dev(torch_cuda, Wd), ba)
+            J_ref, b_ref = orc.ar_term_mc(w.X, w.Y, Wd, lam, P)
+            assert np.allclose(ba.cpu().numpy(), b_ref, rtol=1e-9, atol=1e-9 * np.abs(b_ref).max())
+            beta = np.array([3.0, 0.4, 1.7][:P])
+            g.gp_op_set_alpha(op_a, beta)
+            grid = orc.grid(w.mask, w.conn)
+            Qa = orc.precision(grid, beta, J_ref)
+            x = np.random.default_rng(2).standard_normal((2, P, w.N))
+            y = torch_cuda.empty((2, P, w.N), dtype=torch_cuda.float64, device="cuda")
+            g.gp_apply(op_a, 2, dev(torch_cuda, x), y)
+            ref = orc.apply(Qa, x)
+            assert np.abs(y.cpu().numpy() - ref).max() <= 1e-9 * np.abs(ref).max()
+            a = torch_cuda.zeros((1, P, w.N), dtype=torch_cuda.float64, device="cuda")
+            for pc in (g.GP_PRECOND_BLOCK_JACOBI, g.GP_PRECOND_RB_IC0):
+                a.zero_()
+                g.gp_solve(op_a, 1, ba[None].contiguous(), a, g.gp_opts_default(tol=1e-10, precond=pc))
+                sol = orc.solve_direct(Qa, b_ref[None])
+                assert np.linalg.norm(a.cpu().numpy() - sol) <= 1e-6 * np.linalg.norm(sol)
+        finally:
+            g.gp_data_destroy(d)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op_a)
+        g.gp_op_destroy(op)
+
+
+def test_ar_system_rejects_bad_arguments(g, ctx, torch_cuda):
+    w = synth.tiny((9, 8, 5), 6, 3, seed=91, T=40, P=2)
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    op_bad = g.gp_op_create(ctx, w.mask, w.conn, 3)      # K != P
+    other = synth.tiny((10, 8, 5), 6, 2, seed=92)
+    op_other = g.gp_op_create(ctx, other.mask, other.conn, 2)
+    try:
+        lam = dev(torch_cuda, 1.0 / w.sigma2)
+        Wd = dev(torch_cuda, w.W_true[None])
+        d = g.gp_data_create(op, w.X.shape[0], 2, w.X, dev(torch_cuda, w.Y))
+        d0 = g.gp_data_create(op, w.X.shape[0], 0, w.X, dev(torch_cuda, w.Y))
+        try:
+            for bad_op, data in ((op_bad, d), (op_other, d), (op_bad, d0)):
+                with pytest.raises(g.GmrfError) as e:
+                    g.gp_data_assemble_ar(data, bad_op, lam, 1, Wd)
+                assert e.value.status == g.GP_ERR_INVALID_ARG
+        finally:
+            g.gp_data_destroy(d)
+            g.gp_data_destroy(d0)
+    finally:
+        torch_cuda.cuda.synchronize()
+        for o in (op, op_bad, op_other):
+            g.gp_op_destroy(o)
+
+
+def test_svb_steps_with_ar_match_oracle(g, ctx, torch_cuda):
+    """Two SVB iterations over W, A, alpha, beta and lambda (fixed random
+    vectors, warm starts) against the oracle's steps fed the same inputs."""
+    w = synth.tiny((14, 11, 7), 6, 3, seed=97, T=60, P=2)
+    P = 2
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    op_a = g.gp_op_create(ctx, w.mask, w.conn, P)
+    try:
+        d = g.gp_data_create(op, w.X.shape[0], P, w.X, dev(torch_cuda, w.Y))
+        try:
+            rng = np.random.default_rng(6)
+            Ns = 3
+            dirs = 3
+            z1w, z2w = rng.standard_normal((Ns, w.K, dirs, w.N)), rng.standard_normal((Ns, w.K, w.N))
+            z1a, z2a = rng.standard_normal((Ns, P, dirs, w.N)), rng.standard_normal((Ns, P, w.N))
+            A0 = w.ar[None, :P] + 0.05 * rng.standard_normal((Ns, P, w.N))
+            alpha, beta = np.array([1.0, 1.0, 1.0]), np.array([5.0, 5.0])
+            lam = 1.0 / w.sigma2.copy()
+            grid = orc.grid(w.mask, w.conn)
+            Wd = torch_cuda.zeros((Ns, w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            Ad = dev(torch_cuda, A0)
+            lam_d = dev(torch_cuda, lam)
+            bw = torch_cuda.empty((w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            ba = torch_cuda.empty((P, w.N), dtype=torch_cuda.float64, device="cuda")
+            a_gpu, b_gpu = alpha.copy(), beta.copy()
+            A_ref, a_ref, b_ref, l_ref = A0.copy(), alpha.copy(), beta.copy(), lam.copy()
+            opts = g.gp_opts_default(tol=1e-10)
+            for it in range(2):
+                st, sw, sa = g.gp_svb_step_ar(d, op_a, Ns, dev(torch_cuda, z1w), dev(torch_cuda, z2w), Wd,
+                                              dev(torch_cuda, z1a), dev(torch_cuda, z2a), Ad, lam_d, a_gpu, b_gpu,
+                                              bw, ba, opts=opts)
+                assert all(s["status"] == g.GP_OK for s in sw + sa)
+                W_ref, A_ref, a_ref, b_ref, l_ref = orc.svb_step_ar(grid, w.X, w.Y, A_ref, z1w, z2w, z1a, z2a,
+                                                                    a_ref, b_ref, l_ref)
+                assert np.linalg.norm(Wd.cpu().numpy() - W_ref) <= 1e-7 * np.linalg.norm(W_ref), it
+                assert np.linalg.norm(Ad.cpu().numpy() - A_ref) <= 1e-7 * np.linalg.norm(A_ref), it
+                assert np.allclose(a_gpu, a_ref, rtol=1e-6), (it, a_gpu, a_ref)
+                assert np.allclose(b_gpu, b_ref, rtol=1e-6), (it, b_gpu, b_ref)
+                assert np.allclose(lam_d.cpu().numpy(), l_ref, rtol=1e-6), it
+        finally:
+            g.gp_data_destroy(d)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op_a)
+        g.gp_op_destroy(op)
