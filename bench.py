@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00980_amd", "csrc", f)
-                  for f in ("pcg.hpp", "device.hpp", "common.hpp", "k_rbic.hip", "spd.hpp")]
+                  for f in ("pcg.hpp", "device.hpp", "common.hpp", "rbic.hpp", "k_rbic_f32.hip", "k_rbic_f64.hip",
+                            "spd.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -54,6 +55,8 @@ def parse():
                          "or block Jacobi")
     ap.add_argument("--no-precond-compare", action="store_true",
                     help="batch64: skip the solve-only comparison of preconditioners and precisions")
+    ap.add_argument("--no-ar-step", action="store_true",
+                    help="batch64: skip the timing of the AR-coefficient step")
     ap.add_argument("--duration", type=float, default=20.0,
                     help="serve: seconds of Poisson arrivals (the full stream is 300)")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
@@ -361,6 +364,52 @@ def precond_compare(g, torch, ctx, wl):
     return {"what": "solve_batch of the step's 64 right-hand sides alone, tol 1e-8, zero start", "runs": out}
 
 
+def ar_step(g, torch, ctx, wl, n=10):
+    """The AR-coefficient step of an SVB iteration on the whole-brain operator
+    (P = 3): assemble the A system from the step's 32 samples of W and the
+    noise precisions, set beta, draw 32 samples of A by Algorithm 2 (device
+    random vectors, red-black incomplete Cholesky, FP32 inner / FP64
+    refinement to 1e-8) and form beta's posterior."""
+    w = wl.ws[0]
+    P = wl.A.shape[1]
+    op_a = g.gp_op_create(ctx, w.mask, w.conn, P)
+    try:
+        S = wl.S
+        ba = torch.empty((P, w.N), dtype=torch.float64, device="cuda")
+        A = torch.zeros((S, P, w.N), dtype=torch.float64, device="cuda")
+        beta = np.full(P, 5.0)
+        # from zero each time: repeating the step with the same W, lambda and
+        # random vectors would make a warm start exact
+        o = g.gp_opts_default(tol=1e-8, precond=g.GP_PRECOND_RB_IC0, seed=11, zero_guess=1)
+
+        def one():
+            g.gp_data_assemble_ar(wl.data, op_a, wl.lam, S, wl.xs, ba)
+            g.gp_op_set_alpha(op_a, beta)
+            _, st = g.gp_sample(op_a, S, ba, None, None, A, o)
+            g.gp_alpha_posterior(op_a, S, A, 10000.0, 0.1, P)
+            return st
+
+        for _ in range(2):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            st = one()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out = {"what": "assemble the A system from 32 W samples + set beta + 32 Algorithm-2 samples of A "
+                       "(red-black incomplete Cholesky, FP32 inner / FP64 refinement, tol 1e-8, from zero) "
+                       "+ beta posterior", "P": P, "ms_per_step": round(dt * 1e3, 3),
+               "samples_per_s": round(S / dt, 1),
+               "inner_iters_mean": round(sum(x["inner_iters"] for x in st) / len(st), 2),
+               "converged": all(x["status"] == 0 for x in st)}
+        log(f"ar step {out}")
+        return out
+    finally:
+        torch.cuda.synchronize()
+        g.gp_op_destroy(op_a)
+
+
 def cpu_baseline():
     """The oracle on the host: Algorithm 2 right-hand sides and FP64 PCG to 1e-13
     for 16 samples and 16 probes of the same operator, one thread."""
@@ -597,6 +646,8 @@ def main():
         result["gpu_fp64_single_rhs"] = {"value": round(n / (time.perf_counter() - tb), 2),
                                          "unit": "solves/s",
                                          "what": "plain FP64 single-RHS PCG, same operator, block Jacobi"}
+    if args.workload == "batch64" and not args.no_ar_step:
+        result["ar_step"] = ar_step(g, torch, ctx, wl)
     if args.workload == "batch64" and not args.no_precond_compare:
         result["precond_compare"] = precond_compare(g, torch, ctx, wl)
     if args.workload == "batch64" and not args.no_bandwidth_sweep:

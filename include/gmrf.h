@@ -183,7 +183,7 @@ int gp_ctx_profile_read(gp_ctx* ctx, int kind, gp_prof* out);
  * graph Laplacian over in-mask neighbours, free boundary; Section 3.1: one
  * incidence row per adjacent pair).  mask_host: host, nx*ny*nz bytes, nonzero
  * = in mask, linear index l = x + nx*(y + ny*z).  conn: 6 (3D) or 4 (2D, then
- * nz must be 1).  K: regressors, 1..16.  Rejects an empty mask.  The
+ * nz must be 1).  K: regressors, 1..24.  Rejects an empty mask.  The
  * operator is unusable until gp_op_set_blocks and gp_op_set_alpha succeed.  */
 int gp_op_create(gp_ctx* ctx, const uint8_t* mask_host, int nx, int ny, int nz,
                  int conn, int K, gp_op** out);

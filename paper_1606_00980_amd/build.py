@@ -20,8 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgmrf.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["k_pcg_f32.hip", "k_pcg_f64.hip", "k_ops.hip", "k_rng.hip", "k_data.hip", "k_rbic.hip", "api.cpp",
-           "server.cpp", "tune.cpp", "data.cpp", "rbic.cpp"]
+SOURCES = ["k_pcg_f32.hip", "k_pcg_f64.hip", "k_ops.hip", "k_rng.hip", "k_data.hip", "k_rbic_f32.hip",
+           "k_rbic_f64.hip", "api.cpp", "server.cpp", "tune.cpp", "data.cpp", "rbic.cpp"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.

@@ -883,7 +883,7 @@ int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, in
   if (!c || !mask_host) return fail(GP_ERR_INVALID_ARG, "ctx or mask is NULL");
   if (nx < 1 || ny < 1 || nz < 1) return fail(GP_ERR_INVALID_ARG, "grid dimensions must be >= 1");
   if (conn != 4 && conn != 6) return fail(GP_ERR_INVALID_ARG, "conn must be 4 or 6");
-  if (K < 1 || K > KMAX) return fail(GP_ERR_INVALID_ARG, "K must lie in [1, 16]");
+  if (K < 1 || K > KMAX) return fail(GP_ERR_INVALID_ARG, "K must lie in [1, 24]");
   const long ncell = (long)nx * ny * nz;
   if (ncell >= (long)INT_MAX) return fail(GP_ERR_INVALID_ARG, "grid too large");
   long N = 0;

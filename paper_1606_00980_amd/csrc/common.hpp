@@ -7,7 +7,7 @@
 
 namespace gp {
 
-constexpr int KMAX = 16;     // largest supported number of regressors
+constexpr int KMAX = 24;     // largest supported number of regressors
 constexpr int TILE = 256;    // voxels per workgroup in the voxel-parallel kernels
 constexpr int NPART = 7;     // reduction values per (right-hand side, tile), at most
 constexpr int NPROF = 12;    // profiling counters per problem

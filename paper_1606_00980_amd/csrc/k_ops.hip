@@ -153,30 +153,37 @@ __global__ __launch_bounds__(TILE) void k_pack_blocks(int N, const double* __res
 #pragma unroll
     for (int j = 0; j <= k; ++j) a[pk(k, j)] = 0.5 * (Bn[k * K + j] + Bn[j * K + k]);
   }
-  double L[NB];
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < K; ++j) {
-    double dj = a[pk(j, j)];
-#pragma unroll
-    for (int l = 0; l < j; ++l) dj -= L[pk(j, l)] * L[pk(j, l)];
-    ok = ok && (dj > 0.0) && (dj == dj);
-    const double ljj = sqrt(dj > 0.0 ? dj : 1.0);
-    L[pk(j, j)] = ljj;
-#pragma unroll
-    for (int i = j + 1; i < K; ++i) {
-      double v = a[pk(i, j)];
-#pragma unroll
-      for (int l = 0; l < j; ++l) v -= L[pk(i, l)] * L[pk(j, l)];
-      L[pk(i, j)] = v / ljj;
-    }
-  }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     B64[(size_t)i * N + n] = a[i];
     B32[(size_t)i * N + n] = (float)a[i];
-    L64[(size_t)i * N + n] = L[i];
   }
+  double L[NB];
+  bool ok = true;
+  if constexpr (K <= KREG) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double dj = a[pk(j, j)];
+#pragma unroll
+      for (int l = 0; l < j; ++l) dj -= L[pk(j, l)] * L[pk(j, l)];
+      ok = ok && (dj > 0.0) && (dj == dj);
+      const double ljj = sqrt(dj > 0.0 ? dj : 1.0);
+      L[pk(j, j)] = ljj;
+#pragma unroll
+      for (int i = j + 1; i < K; ++i) {
+        double v = a[pk(i, j)];
+#pragma unroll
+        for (int l = 0; l < j; ++l) v -= L[pk(i, l)] * L[pk(j, l)];
+        L[pk(i, j)] = v / ljj;
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < NB; ++i) L[i] = a[i];
+    ok = cholesky_dyn(K, L);
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) L64[(size_t)i * N + n] = L[i];
   if (!ok) atomicMin(bad, n);
 }
 
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(TILE) void k_precond(OpDev op, int pc, double* __re
   }
   // Cholesky M = L L', then M^{-1} = L^{-T} L^{-1}.
   double inv[NB];
-  const bool ok = spd_inverse<K>(a, inv);
+  const bool ok = spd_inverse_any<K>(a, inv);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     P64[(size_t)i * N + n] = inv[i];
@@ -379,7 +386,9 @@ __global__ __launch_bounds__(WAVE) void k_trace_final(const double* __restrict__
 }
 
 // --------------------------------------------------------------- launchers
-#define GP_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define GP_K_CASES(X)                                                                                  \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+      X(20) X(21) X(22) X(23) X(24)
 
 hipError_t launch_pack_blocks(hipStream_t s, int K, int N, const double* B, double* B64, float* B32,
                               double* L64, int* bad) {

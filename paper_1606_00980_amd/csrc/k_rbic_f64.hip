@@ -1,0 +1,57 @@
+// Red-black incomplete Cholesky: set-up, split, recovery and finalisation
+// launches, and the solver-round launches with FP64 inner vectors (the
+// kernels are in rbic.hpp; the FP32 round launches are in k_rbic_f32.hip).
+#include "rbic.hpp"
+
+namespace gp {
+
+hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, double* P64, float* P32,
+                           double* D64, float* D32, double* S64, float* S32, int* bad) {
+  const int gr = (rb.NR + TILE - 1) / TILE, gb = (rb.NB + TILE - 1) / TILE;
+#define X(KK)                                                                                         \
+  case KK:                                                                                            \
+    if (gr > 0) hipLaunchKernelGGL(k_rb_setup_red<KK>, dim3(gr), dim3(TILE), 0, s, rb, B64, P64, P32, bad); \
+    if (gb > 0)                                                                                       \
+      hipLaunchKernelGGL(k_rb_setup_black<KK>, dim3(gb), dim3(TILE), 0, s, rb, B64, D64, D32, S64, S32, bad); \
+    break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
+                           double* t, double* c, double* xB, double* bbpart) {
+#define X(KK)                                                                                              \
+  case KK:                                                                                                 \
+    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, xB, \
+                       bbpart);                                                                            \
+    if (rb.ntB > 0) hipLaunchKernelGGL(k_rb_split_black<KK>, grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c);  \
+    break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+RB_INST(double)
+
+hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
+                             const double* xB, double* x) {
+  if (rb.ntN == 0) return hipSuccess;
+#define X(KK) \
+  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, b, xB, x); break;
+  RB_K_SWITCH(rb.K, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
+                              int ntN) {
+  const int g = (R + FIN_WAVES - 1) / FIN_WAVES;
+  if (kind == 0)
+    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
+  else
+    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
+  return hipGetLastError();
+}
+
+}  // namespace gp

@@ -69,7 +69,7 @@ hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob,
 // right-hand sides per z-marching workgroup for K regressors
 int zm_rhs_per_block(int K);
 
-// k_rbic.hip: red-black incomplete Cholesky.  Vectors of the black system are
+// k_rbic_f32.hip / k_rbic_f64.hip: red-black incomplete Cholesky.  Vectors of the black system are
 // [R][K][NB], red ones [R][K][NR]; grids are (tiles of 256 voxels, R).  rb is
 // the host copy (grid sizes, K), rbd the same descriptor in device memory,
 // which the kernels of a solver round read so that rounds can be replayed as

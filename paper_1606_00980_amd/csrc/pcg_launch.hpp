@@ -8,7 +8,9 @@
 
 namespace gp {
 
-#define GP_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define GP_K_CASES(X)                                                                                  \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+      X(20) X(21) X(22) X(23) X(24)
 
 // Kernel templated on <T, PC, K> launched with (probs, nprob, W).
 #define GP_PC_SWITCH(KERNEL, BLOCKDIM)                                                         \

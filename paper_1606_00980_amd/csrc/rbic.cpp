@@ -3,7 +3,7 @@
 // two-colour voxel order): the colour split of an operator, the set-up of the
 // red inverses and black Schur blocks, and the driver of the half-size PCG on
 // the black Schur complement that PCG with this M reduces to (the algebra is
-// stated at the top of k_rbic.hip).
+// stated at the top of rbic.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,4 +1,4 @@
-// Incomplete Cholesky preconditioning on the red-black voxel order (the
+// Kernels of the incomplete Cholesky preconditioning on the red-black voxel order (the
 // preconditioner M of Algorithm 2, steps 6-7, as a zero-fill factor in K x K
 // voxel blocks).
 //
@@ -20,6 +20,7 @@
 //   black stage : (S v)_m = Q_mm v_m - alpha .* sum_{n ~ m} u_n    (black voxels)
 // and recovers x_R = Q_nn^{-1} (b_n + alpha .* sum_{m ~ n} x_m) at the end,
 // which makes the red residual rows vanish, so ||b - Q x|| = ||c_B - S x_B||.
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(TILE) void k_rb_setup_red(RbDev rb, const double* _
   load_soa(B64, rb.N, n, a);
 #pragma unroll
   for (int k = 0; k < K; ++k) a[pk(k, k)] += rb.alpha64[k] * (double)deg;
-  const bool ok = spd_inverse<K>(a, inv);
+  const bool ok = spd_inverse_any<K>(a, inv);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     P64[(size_t)i * rb.NR + j] = inv[i];
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(TILE) void k_rb_setup_black(RbDev rb, const double*
         a[pk(k, l)] -= rb.alpha64[k] * rb.alpha64[l] * rb.P64[(size_t)pk(k, l) * rb.NR + nb[d]];
     }
   }
-  const bool ok = spd_inverse<K>(a, inv);
+  const bool ok = spd_inverse_any<K>(a, inv);
 #pragma unroll
   for (int e = 0; e < NB; ++e) {
     S64[(size_t)e * rb.NB + i] = inv[e];
@@ -602,49 +603,36 @@ inline dim3 grid2(int tiles, int R) { return dim3((unsigned)tiles, (unsigned)R);
 
 #define RB_K_SWITCH(K, X)                                                                            \
   switch (K) {                                                                                       \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)         \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
+        X(19) X(20) X(21) X(22) X(23) X(24)                                                            \
     default: return hipErrorInvalidValue;                                                            \
   }
 
-hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, double* P64, float* P32,
-                           double* D64, float* D32, double* S64, float* S32, int* bad) {
-  const int gr = (rb.NR + TILE - 1) / TILE, gb = (rb.NB + TILE - 1) / TILE;
-#define X(KK)                                                                                         \
-  case KK:                                                                                            \
-    if (gr > 0) hipLaunchKernelGGL(k_rb_setup_red<KK>, dim3(gr), dim3(TILE), 0, s, rb, B64, P64, P32, bad); \
-    if (gb > 0)                                                                                       \
-      hipLaunchKernelGGL(k_rb_setup_black<KK>, dim3(gb), dim3(TILE), 0, s, rb, B64, D64, D32, S64, S32, bad); \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
-                           double* t, double* c, double* xB, double* bbpart) {
-#define X(KK)                                                                                              \
-  case KK:                                                                                                 \
-    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, xB, \
-                       bbpart);                                                                            \
-    if (rb.ntB > 0) hipLaunchKernelGGL(k_rb_split_black<KK>, grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c);  \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
 inline unsigned rb_grid(int ntiles, int R, int Rc) { return (unsigned)ntiles * (unsigned)((R + Rc - 1) / Rc); }
+
+// Launches KERN<T, KK, true> (blocks held across a work item's right-hand
+// sides) when a work item has several right-hand sides and NBLK blocks of
+// element type TB fit the register budget, else KERN<T, KK, false>; the held
+// variant is only instantiated where it can be chosen.
+#define RB_HOLD_LAUNCH(KERN, KK, NBLK, TB, ...)                                  \
+  do {                                                                           \
+    if constexpr (HoldRb<TB, KK, NBLK>::v) {                                     \
+      if (Rc > 1) {                                                              \
+        hipLaunchKernelGGL((KERN<T, KK, true>), __VA_ARGS__);                    \
+        break;                                                                   \
+      }                                                                          \
+    }                                                                            \
+    hipLaunchKernelGGL((KERN<T, KK, false>), __VA_ARGS__);                       \
+  } while (0)
 
 template <typename T>
 hipError_t launch_rb_red_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
                            int want, const T* v, T* u) {
   if (rb.ntR == 0) return hipSuccess;
   const dim3 g(rb_grid(rb.ntR, R, Rc));
-#define X(KK) \
-  case KK: if (Rc > 1 && HoldRb<T, KK, 1>::v)                                                                 \
-      hipLaunchKernelGGL((k_rb_red<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);        \
-    else                                                                                                 \
-      hipLaunchKernelGGL((k_rb_red<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);       \
+#define X(KK)                                                                                   \
+  case KK:                                                                                      \
+    RB_HOLD_LAUNCH(k_rb_red, KK, 1, T, g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);         \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -657,14 +645,10 @@ hipError_t launch_rb_refine_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, 
                               int pstride) {
   if (rb.ntB == 0) return hipSuccess;
   const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK)                                                                                                \
-  case KK:                                                                                                   \
-    if (Rc > 1 && HoldRb<double, KK, 2>::v)                                                                  \
-      hipLaunchKernelGGL((k_rb_refine<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R, Rc, \
-                         pstride);                                                                           \
-    else                                                                                                     \
-      hipLaunchKernelGGL((k_rb_refine<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R,    \
-                         Rc, pstride);                                                                       \
+#define X(KK)                                                                                                 \
+  case KK:                                                                                                    \
+    RB_HOLD_LAUNCH(k_rb_refine, KK, 2, double, g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R, Rc,    \
+                   pstride);                                                                                  \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -676,13 +660,9 @@ hipError_t launch_rb_matvec_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, 
                               const T* p, const T* u, const T* r, T* q, double* part, int pstride) {
   if (rb.ntB == 0) return hipSuccess;
   const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK)                                                                                                  \
-  case KK:                                                                                                     \
-    if (Rc > 1 && HoldRb<T, KK, 2>::v)                                                                         \
-      hipLaunchKernelGGL((k_rb_matvec<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc, pstride); \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_rb_matvec<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc,   \
-                         pstride);                                                                             \
+#define X(KK)                                                                                             \
+  case KK:                                                                                                \
+    RB_HOLD_LAUNCH(k_rb_matvec, KK, 2, T, g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc, pstride); \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -694,12 +674,9 @@ hipError_t launch_rb_update_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, 
                               T* d, T* r, T* p, const T* q) {
   if (rb.ntB == 0) return hipSuccess;
   const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK) \
-  case KK:                                                                                                    \
-    if (Rc > 1 && HoldRb<T, KK, 1>::v)                                                                        \
-      hipLaunchKernelGGL((k_rb_update<T, KK, true>), g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);        \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_rb_update<T, KK, false>), g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);       \
+#define X(KK)                                                                                 \
+  case KK:                                                                                    \
+    RB_HOLD_LAUNCH(k_rb_update, KK, 1, T, g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);    \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -741,28 +718,4 @@ hipError_t launch_rb_addsol_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, 
                               const RhsState* st, double* xB, const T* d, const T* p) {                      \
     return launch_rb_addsol_t<T>(s, rb, rbd, R, Rc, st, xB, d, p);                                           \
   }
-RB_INST(double)
-RB_INST(float)
-#undef RB_INST
-
-hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
-                             const double* xB, double* x) {
-  if (rb.ntN == 0) return hipSuccess;
-#define X(KK) \
-  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, b, xB, x); break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
-                              int ntN) {
-  const int g = (R + FIN_WAVES - 1) / FIN_WAVES;
-  if (kind == 0)
-    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
-  else
-    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
-  return hipGetLastError();
-}
-
 }  // namespace gp

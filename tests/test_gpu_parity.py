@@ -329,6 +329,42 @@ def test_k16_and_slices_without_z_coupling(g, ctx, torch_cuda):
     g.gp_op_destroy(h)
 
 
+@pytest.mark.parametrize("K", [15, 23])
+def test_large_k_every_preconditioner_and_precision(g, ctx, torch_cuda, K):
+    """The paper's real-data regressor counts: solves with each
+    preconditioner in both precisions, an Algorithm-2 sample, and the data
+    term assembled on the device with AR(2), against the oracle."""
+    w = synth.tiny((9, 8, 4), 6, K, seed=13 + K, T=120, P=2)
+    op = Op(g, ctx, torch_cuda, w)
+    b = w.rhs(3)
+    ref = orc.solve(op.Q, b)
+    bd = dev(torch_cuda, b)
+    for pc in (g.GP_PRECOND_JACOBI, g.GP_PRECOND_BLOCK_JACOBI, g.GP_PRECOND_RB_IC0):
+        for prec in (g.GP_PREC_FP64, g.GP_PREC_FP32_REFINE64):
+            x = torch_cuda.zeros_like(bd)
+            g.gp_solve(op.h, 3, bd, x, opts(g, precond=pc, precision=prec))
+            check_solutions(x.cpu().numpy(), ref, w.K, w.N)
+    z1, z2 = w.z(2)
+    out = torch_cuda.zeros((2, w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+    g.gp_sample(op.h, 2, dev(torch_cuda, w.bw), dev(torch_cuda, z1), dev(torch_cuda, z2), out, opts(g))
+    check_solutions(out.cpu().numpy(), orc.sample(op.grid, w.alpha, w.B, w.bw, z1, z2), w.K, w.N)
+    d = g.gp_data_create(op.h, w.X.shape[0], 2, w.X, dev(torch_cuda, w.Y))
+    try:
+        lam = 1.0 / w.sigma2
+        bw = torch_cuda.empty((w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+        g.gp_data_assemble(d, dev(torch_cuda, lam), 1, dev(torch_cuda, w.ar[None, :2]), bw)
+        B_ref, b_ref = orc.data_term_mc(w.X, w.Y, w.ar[None, :2], lam)
+        assert np.abs(bw.cpu().numpy() - b_ref).max() <= 1e-10 * np.abs(b_ref).max()
+        Q = orc.precision(op.grid, w.alpha, B_ref)
+        xv = np.random.default_rng(3).standard_normal((1, w.K, w.N))
+        y = torch_cuda.empty((1, w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+        g.gp_apply(op.h, 1, dev(torch_cuda, xv), y)
+        yr = orc.apply(Q, xv)
+        assert np.abs(y.cpu().numpy() - yr).max() <= 1e-10 * np.abs(yr).max()
+    finally:
+        g.gp_data_destroy(d)
+
+
 def test_not_spd_block_is_reported(g, ctx, torch_cuda):
     w = synth.tiny((8, 7, 5), 6, 3, seed=15)
     B = w.B.copy()
@@ -406,7 +442,7 @@ def test_invalid_arguments_and_budget(g, torch_cuda):
         g.gp_op_create(h, np.zeros((3, 3, 3), np.uint8), 6, 2)
     assert e.value.status == g.GP_ERR_INVALID_ARG
     with pytest.raises(g.GmrfError) as e:
-        g.gp_op_create(h, mask, 6, 17)
+        g.gp_op_create(h, mask, 6, 25)
     assert e.value.status == g.GP_ERR_INVALID_ARG
     assert g.gp_ctx_memory(h)[0] == 0
     g.gp_ctx_destroy(h)
