@@ -203,11 +203,11 @@ void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, 
   prof_add(c, GP_KERNEL_RB_UPDATE, up * NB,
            (up - fresh) * 7 * K * NB * ts + fresh * 6 * K * NB * ts + pf[PF_UPDATE_ACT] * NBt * NB * ts);
   // c, x_B, u64 read (c alone from a zero start value), r and p written; FP64
-  // Q_mm (not from a zero start value) and Schur inverses
+  // Q_mm and the Schur inverses in the inner precision
   const double x0 = (double)pf[PF_REFINE_X0];
   prof_add(c, GP_KERNEL_RB_REFINE, ref * NB,
            ref * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) - x0 * K * (NB + NR) * 8 +
-               pf[PF_REFINE_ACT] * 2 * NBt * NB * 8);
+               pf[PF_REFINE_ACT] * NBt * NB * (8 + ts));
   // x_B read (not on the first step from a zero start value) and written, d
   // and/or the pending step's p read
   const double ad = (double)pf[PF_ADDSOL_D], ap = (double)pf[PF_ADDSOL_P], af = (double)pf[PF_ADDSOL_FRESH];

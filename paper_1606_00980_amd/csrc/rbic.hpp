@@ -326,7 +326,8 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, 
 
 // FP64 refinement at the black voxels of right-hand sides waiting on it:
 // r64 = c - S x_B (u64 from the red stage on x_B), r = T(r64),
-// p = T(blkdiag(S)^{-1} r64); partials ||r64||^2 (slot 0) and r64' p (slot 2).
+// p = blkdiag(S)^{-1} r in the inner precision (p only starts the next inner
+// solve); partials ||r64||^2 (slot 0) and r'p (slot 2).
 template <typename T, int K, bool HOLD>
 __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
                                                     const double* __restrict__ c, const double* __restrict__ xB,
@@ -345,7 +346,8 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
   int nb[6];
   load_nb(rb.nbB, rb.NB, ii, nb);
   const unsigned o8 = (unsigned)ii * 8u, oT = (unsigned)ii * (unsigned)sizeof(T);
-  const Packed<double, K, HOLD> D(rb.D64, rb.NB, o8), S(rb.S64, rb.NB, o8);
+  const Packed<double, K, HOLD> D(rb.D64, rb.NB, o8);
+  const Packed<T, K, HOLD> S(RbT<T>::S(rb), rb.NB, oT);
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     const RhsState& sr = st[r];
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     const size_t off = (size_t)r * K * rb.NB;
     const Slab<double> cs(c + off, K, rb.NB), xs(xB + off, K, rb.NB), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
     const Slab<T> rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB);
-    double r64[K], z[K];
+    double r64[K];
     if (rb.zero_start && sr.outer == 0) {   // x_B = 0: r = c
 #pragma unroll
       for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8);
@@ -370,19 +372,21 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
       for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8) - (y[k] - rb.alpha64[k] * s[k]);
     }
     double acc[3] = {0.0, 0.0, 0.0};
+    T rt[K], zt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       acc[0] += r64[k] * r64[k];
-      z[k] = 0.0;
+      rt[k] = (T)r64[k];
+      zt[k] = 0;
     }
-    sym_apply<K>(S, r64, z);
+    sym_apply<K>(S, rt, zt);
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[2] += r64[k] * z[k];
+    for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)zt[k];
     if (valid) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        rs.st(k, oT, (T)r64[k]);
-        ps.st(k, oT, (T)z[k]);
+        rs.st(k, oT, rt[k]);
+        ps.st(k, oT, zt[k]);
       }
     } else {
       acc[0] = acc[2] = 0.0;
