@@ -304,6 +304,35 @@ int gp_svb_step_ar(gp_data* d, gp_op* op_a, int Ns, const double* z1w, const dou
                    double* beta_host, const gp_hyper* prior, double* bw_work, double* ba_work,
                    const gp_opts* opts, gp_stats* stats_w, gp_stats* stats_a);
 
+/* gp_gibbs_step: one iteration of the Gibbs sampler of Section 3.2 for W,
+ * alpha and lambda, with the AR coefficients held at A (device [P][N], NULL
+ * when P = 0):
+ *   1. the data term with lambda (device N) and A into the operator and
+ *      bw_work (device [K][N]); alpha_host (K) as the spatial precisions;
+ *   2. one draw of W from its full conditional by Algorithm 2 into W (device
+ *      [K][N], which holds the previous draw as the start value), with the
+ *      random vectors z1, z2 (as in gp_sample) or, when both are NULL, drawn
+ *      on the device from seed ^ (iteration * 0x9E3779B97F4A7C15);
+ *   3. alpha_k ~ Ga(scale_k, N/2 + q2), 1/scale_k = W_k D_w W_k'/2 + 1/q1, by
+ *      gp_rng_gamma(seed, stream 16 + 2 iteration) into alpha_host;
+ *   4. lambda_n ~ Ga(scale_n, (T-P)/2 + u2), 1/scale_n = rss_n/2 + 1/u1 (the
+ *      whitened residual sum of squares of the new W and A), by
+ *      gp_rng_gamma(seed, stream 17 + 2 iteration) into lambda.
+ * prior: NULL for gp_hyper_default.  stats: one entry.  Blocking.           */
+int gp_gibbs_step(gp_data* d, const double* A, const double* z1, const double* z2, double* W, double* lambda,
+                  double* alpha_host, const gp_hyper* prior, double* bw_work, uint64_t seed, uint64_t iteration,
+                  const gp_opts* opts, gp_stats* stats);
+
+/* gp_alpha_extrapolate: the first convergence device of the SVB implementation
+ * (Appendix C): from the posterior means of the last three iterations, a_jm2,
+ * a_jm1 and a_j (host, K each; a_j as the update equation proposed it), put
+ * the quadratic in the iteration number through them; if its vertex lies
+ * after iteration j, the prediction is its value there, otherwise
+ * a_jm1 + 20 (a_j - a_jm1); a_j is replaced by the prediction limited to
+ * [a_j / 5, 5 a_j].  Meant for every other SVB iteration; applies alike to
+ * beta.  Host only (no device work).                                        */
+int gp_alpha_extrapolate(int K, const double* a_jm2, const double* a_jm1, double* a_j);
+
 /* gp_alpha_posterior: the spatial-precision posterior (Section 3.2 full
  * conditional; Section 3.3 and Appendix B for the SVB Monte Carlo form):
  * qf[r][k] = W_k D_w W_k' = ||G_w W_k'||^2 of each of R samples W (device,
@@ -414,10 +443,25 @@ int gp_tune_load(gp_ctx* ctx, const char* path);
  *  gp_rng_rademacher : out[e], device int8; bit e % 128 of block q = e/128
  *                      (w0 least significant) gives +1 when set, else -1.
  *  gp_rng_raw        : the 4 words of blocks 0..nblocks-1, device uint32.
+ *  gp_rng_gamma      : out[e] = scale[e] G_e with G_e ~ Gamma(shape, 1) (the
+ *                      full conditionals of alpha and lambda, Section 3.2 and
+ *                      Appendix A.2, for Gibbs sampling), by Marsaglia and
+ *                      Tsang's rejection method (ACM TOMS 2000): a = shape
+ *                      (shape + 1 below one), d = a - 1/3, c = 1/sqrt(9d);
+ *                      attempt t < 64 of element e takes x, the cosine
+ *                      Box-Muller normal of block 128e + 2t, and u from
+ *                      (w1:w0) of block 128e + 2t + 1; with v = (1 + c x)^3 it
+ *                      accepts d v when v > 0 and u < 1 - 0.0331 x^4 or
+ *                      ln u < x^2/2 + d(1 - v + ln v); after 64 rejections
+ *                      G = d.  For shape < 1, G is multiplied by U^(1/shape)
+ *                      with U from (w3:w2) of block 128e + 1.  scale: device
+ *                      FP64 [n], or NULL for 1; out: device FP64 [n].
  * Stream-ordered.                                                          */
 int gp_rng_normal(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double* out);
 int gp_rng_rademacher(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, int8_t* out);
 int gp_rng_raw(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out);
+int gp_rng_gamma(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double shape, const double* scale,
+                 double* out);
 
 /* ---- serving ---------------------------------------------------------------
  * A request loop over resident operators: requests (solve, sample, trace) are

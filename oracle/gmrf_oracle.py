@@ -41,6 +41,8 @@ It computes, slowly and directly, what the paper (Siden, Eklund, Bolin, Villani,
   and in the tensor form, its Monte Carlo SVB expectation over draws of W, the
   operator with K = P, prior precisions beta and D_a = D_w, and one SVB
   iteration over W, A and the hyperparameters (Section 3.3, Appendix B);
+* one Gibbs iteration of Section 3.2 (W, alpha, lambda) with the Gamma
+  draws of the Philox twin;
 * Hutchinson estimates with Rademacher probes of tr(Q^{-1}), of tr([Q^{-1}]_kk)
   and of tr(D_w [Q^{-1}]_kk), the trace inside E[W_k D_w W_k'] of Section 3.3
   (quadratic-form expectation).
@@ -66,6 +68,7 @@ __all__ = [
     "Grid", "grid", "data_term_whitening", "data_term_mc", "data_tensors", "data_term_from_tensors",
     "data_tensors_noise", "quadform", "residual_ss", "residual_ss_from_tensors", "alpha_posterior",
     "lambda_posterior", "svb_step", "ar_term_residuals", "ar_term_mc", "ar_term_from_tensors", "svb_step_ar",
+    "alpha_extrapolate", "gibbs_step",
     "precision", "apply", "relres",
     "solve", "solve_direct", "solve_pcg", "perturbation_rhs", "perturbation_factor",
     "sample", "hutchinson", "cholesky_mean_and_sample",
@@ -296,6 +299,52 @@ def lambda_posterior(rss_mean: np.ndarray, T: int, P: int, u1: float, u2: float)
     """Ga(u~1n, u~2) of lambda_n: 1/u~1n = rss_n/2 + 1/u1, u~2 = (T-P)/2 + u2."""
     u1t = 1.0 / (0.5 * np.asarray(rss_mean, dtype=float) + 1.0 / u1)
     return u1t, (T - P) / 2.0 + u2
+
+
+def gibbs_step(g: Grid, X, Y, A, z1, z2, alpha, lam, seed: int, iteration: int, q1=10.0, q2=0.1, u1=10.0,
+               u2=0.1, tol: float = 1e-13):
+    """One iteration of the Gibbs sampler of Section 3.2 with the AR
+    coefficients held at A (P, N): W from its full conditional by Algorithm 2
+    with the random vectors z1 (1, K, dirs, N), z2 (1, K, N); then
+    alpha_k ~ Ga(q~1k, N/2 + q2) and lambda_n ~ Ga(u~1n, (T-P)/2 + u2) from
+    their full conditionals, drawn from the Philox streams 16 + 2 iteration and
+    17 + 2 iteration of ``seed`` (Marsaglia-Tsang, see oracle/philox.py).
+    Returns (W (K, N), alpha (K), lam (N))."""
+    from oracle import philox
+    T = X.shape[0]
+    P = A.shape[0]
+    B, bw = data_term_mc(X, Y, A[None], lam)
+    W = sample(g, alpha, B, bw, z1, z2, tol)[0]
+    q1t, q2t = alpha_posterior(quadform(g, W[None])[0], g.N, q1, q2)
+    alpha_new = philox.gamma(seed, 16 + 2 * iteration, q2t, q1t)
+    u1t, u2t = lambda_posterior(residual_ss(X, Y, W, A), T, P, u1, u2)
+    lam_new = philox.gamma(seed, 17 + 2 * iteration, u2t, u1t)
+    return W, alpha_new, lam_new
+
+
+def alpha_extrapolate(a_jm2: np.ndarray, a_jm1: np.ndarray, a_j: np.ndarray) -> np.ndarray:
+    """The first convergence device of the SVB implementation (Appendix C,
+    speeding up SVB): through the posterior means of the last three
+    iterations j-2, j-1, j put the quadratic in the iteration number; if its
+    vertex lies after j, predict the value at the vertex, otherwise
+    a_{j-1} + 20 (a_j - a_{j-1}); keep the prediction within a factor 5 of
+    a_j (the value the update equation proposed).  Elementwise over k."""
+    a2, a1, a0 = (np.asarray(v, dtype=np.float64) for v in (a_jm2, a_jm1, a_j))
+    out = np.empty_like(a0)
+    for k in range(a0.size):
+        # quadratic c0 + c1 t + c2 t^2 through (0, a2), (1, a1), (2, a0)
+        c2 = 0.5 * (a0[k] - 2.0 * a1[k] + a2[k])
+        c1 = (a1[k] - a2[k]) - c2
+        c0 = a2[k]
+        pred = None
+        if c2 != 0.0:
+            tv = -c1 / (2.0 * c2)
+            if tv > 2.0:
+                pred = c0 + c1 * tv + c2 * tv * tv
+        if pred is None:
+            pred = a1[k] + 20.0 * (a0[k] - a1[k])
+        out[k] = min(max(pred, a0[k] / 5.0), a0[k] * 5.0)
+    return out
 
 
 # --------------------------------------------------------- AR coefficients A

@@ -12,6 +12,12 @@ Element layout (identical to the one documented in gmrf.h):
   normals   : pair q gives elements 2q, 2q+1 by Box-Muller from the 53-bit
               uniforms of words (w1:w0) and (w3:w2)
   Rademacher: element e is bit e % 128 of block e // 128 (+1 if set).
+  Gamma     : element e, attempt t (t = 0..63) uses blocks 128 e + 2 t (a
+              Box-Muller normal x from the cosine branch) and 128 e + 2 t + 1
+              (the acceptance uniform u from words (w1:w0); for shape < 1 the
+              boost uniform from words (w3:w2) of attempt 0); Marsaglia and
+              Tsang's squeeze and log tests; after 64 rejections the value is
+              d = shape - 1/3 (for shape >= 1).
 """
 from __future__ import annotations
 
@@ -68,3 +74,45 @@ def rademacher(seed: int, stream: int, n: int) -> np.ndarray:
     e = np.arange(n)
     bits = (w[e // 128, (e % 128) // 32] >> (e % 32).astype(np.uint32)) & 1
     return np.where(bits == 1, 1, -1).astype(np.int8)
+
+
+GAMMA_ATTEMPTS = 64
+
+
+def gamma(seed: int, stream: int, shape: float, scale: np.ndarray) -> np.ndarray:
+    """Gamma(shape, scale) variates, one per entry of scale, by the rejection
+    method of Marsaglia and Tsang ("A simple method for generating gamma
+    variables", ACM TOMS 26, 2000): with d = a - 1/3 and c = 1/sqrt(9 d), draw
+    x ~ N(0, 1), v = (1 + c x)^3, keep d v when v > 0 and either
+    u < 1 - 0.0331 x^4 or log u < x^2/2 + d (1 - v + log v); for a < 1, draw
+    with a + 1 and multiply by U^(1/a)."""
+    scale = np.asarray(scale, dtype=np.float64).ravel()
+    n = scale.size
+    a = float(shape) if shape >= 1.0 else float(shape) + 1.0
+    d = a - 1.0 / 3.0
+    c = 1.0 / np.sqrt(9.0 * d)
+    out = np.full(n, d)
+    done = np.zeros(n, dtype=bool)
+    e = np.arange(n, dtype=np.uint64)
+    for t in range(GAMMA_ATTEMPTS):
+        todo = np.flatnonzero(~done)
+        if todo.size == 0:
+            break
+        qa = e[todo] * np.uint64(128) + np.uint64(2 * t)
+        wa = philox4x32_10(qa, seed, stream)
+        wb = philox4x32_10(qa + np.uint64(1), seed, stream)
+        u1 = uniform53(wa[:, 0], wa[:, 1])
+        u2 = uniform53(wa[:, 2], wa[:, 3])
+        x = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+        u = uniform53(wb[:, 0], wb[:, 1])
+        v = (1.0 + c * x) ** 3
+        ok = v > 0.0
+        vs = np.where(ok, v, 1.0)
+        acc = ok & ((u < 1.0 - 0.0331 * x ** 4) | (np.log(u) < 0.5 * x * x + d * (1.0 - vs + np.log(vs))))
+        idx = todo[acc]
+        out[idx] = d * vs[acc]
+        done[idx] = True
+    if shape < 1.0:
+        wb = philox4x32_10(e * np.uint64(128) + np.uint64(1), seed, stream)
+        out = out * uniform53(wb[:, 2], wb[:, 3]) ** (1.0 / shape)
+    return out * scale

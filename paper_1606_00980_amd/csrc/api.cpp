@@ -1206,6 +1206,15 @@ int gp_rng_rademacher(gp_ctx* c, uint64_t seed, uint64_t stream, size_t n, int8_
   return GP_OK;
 }
 
+int gp_rng_gamma(gp_ctx* c, uint64_t seed, uint64_t stream, size_t n, double shape, const double* scale,
+                 double* out) {
+  if (!c || (n > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
+  if (!(shape > 0.0) || !std::isfinite(shape)) return fail(GP_ERR_INVALID_ARG, "shape must be positive");
+  if (int st = set_device(c)) return st;
+  HIPTRY(launch_rng_gamma(c->stream, seed, stream, n, shape, scale, out));
+  return GP_OK;
+}
+
 int gp_rng_raw(gp_ctx* c, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out) {
   if (!c || (nblocks > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "ctx or out is NULL");
   if (int st = set_device(c)) return st;

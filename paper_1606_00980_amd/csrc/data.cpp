@@ -280,6 +280,73 @@ int gp_svb_step_ar(gp_data* d, gp_op* op_a, int Ns, const double* z1w, const dou
   return GP_OK;
 }
 
+int gp_gibbs_step(gp_data* d, const double* A, const double* z1, const double* z2, double* W, double* lambda,
+                  double* alpha_host, const gp_hyper* prior, double* bw_work, uint64_t seed, uint64_t iteration,
+                  const gp_opts* opts, gp_stats* stats) {
+  if (!d || !W || !lambda || !alpha_host || !bw_work) return fail(GP_ERR_INVALID_ARG, "null argument");
+  if ((z1 == nullptr) != (z2 == nullptr)) return fail(GP_ERR_INVALID_ARG, "z1 and z2 must both be given or both NULL");
+  gp_hyper h;
+  if (prior) h = *prior; else gp_hyper_default(&h);
+  gp_op* op = d->op;
+  gp_ctx* c = op->ctx;
+  // W | lambda, A, alpha: one Algorithm-2 draw, started from the previous one
+  if (int st = gp_data_assemble(d, lambda, 1, A, bw_work, nullptr)) return st;
+  if (int st = gp_op_set_alpha(op, alpha_host)) return st;
+  gp_opts o;
+  if (opts) o = *opts; else gp_opts_default(&o);
+  if (!z1) o.seed = seed ^ (iteration * 0x9E3779B97F4A7C15ull);
+  if (int st = gp_sample(op, 1, bw_work, z1, z2, W, &o, stats)) return st;
+  // alpha | W and lambda | W, A: scales on the device, Gamma draws
+  const int K = op->K, N = op->N;
+  std::vector<double> scale(K), mean(K);
+  if (int st = gp_alpha_posterior(op, 1, W, h.q1, h.q2, nullptr, scale.data(), mean.data())) return st;
+  double* buf = nullptr;
+  const size_t bytes = ((size_t)2 * K + N) * sizeof(double);
+  {
+    BusyGuard guard(c);
+    if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+    if (int st = set_device(c)) return st;
+    if (int st = dev_alloc(c, bytes, (void**)&buf)) return st;
+  }
+  double* a_scale = buf;
+  double* a_draw = buf + K;
+  double* l_scale = buf + 2 * K;
+  int st = GP_OK;
+  hipError_t e = hipMemcpyAsync(a_scale, scale.data(), K * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_rng_gamma(c->stream, seed, 16 + 2 * iteration, K, 0.5 * N + h.q2, a_scale, a_draw);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(alpha_host, a_draw, K * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) st = fail(GP_ERR_DEVICE, std::string("alpha draw: ") + hipGetErrorString(e));
+  if (st == GP_OK) st = gp_data_lambda(d, 1, W, A, h.u1, h.u2, nullptr, l_scale, nullptr);
+  if (st == GP_OK) {
+    e = launch_rng_gamma(c->stream, seed, 17 + 2 * iteration, N, 0.5 * (d->T - d->P) + h.u2, l_scale, lambda);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) st = fail(GP_ERR_DEVICE, std::string("lambda draw: ") + hipGetErrorString(e));
+  }
+  {
+    BusyGuard guard(c);
+    dev_free(c, buf, bytes);
+  }
+  return st;
+}
+
+int gp_alpha_extrapolate(int K, const double* a_jm2, const double* a_jm1, double* a_j) {
+  if (K < 1 || !a_jm2 || !a_jm1 || !a_j) return fail(GP_ERR_INVALID_ARG, "K >= 1 and three arrays required");
+  for (int k = 0; k < K; ++k) {
+    const double d1 = a_jm1[k] - a_jm2[k], d2 = a_j[k] - a_jm1[k];
+    const double curv = d2 - d1;   // second difference: the parabola is a_j + s t + (curv/2) t^2, t from j
+    const double s = d2 + 0.5 * curv;
+    double pred = a_jm1[k] + 20.0 * d2;
+    if (curv != 0.0) {
+      const double tv = -s / curv;   // the vertex, in iterations after j
+      if (tv > 0.0) pred = a_j[k] + s * tv + 0.5 * curv * tv * tv;
+    }
+    a_j[k] = std::min(std::max(pred, a_j[k] / 5.0), 5.0 * a_j[k]);
+  }
+  return GP_OK;
+}
+
 int gp_data_destroy(gp_data* d) {
   if (!d) return GP_OK;
   gp_ctx* c = d->op->ctx;

@@ -11,7 +11,14 @@
 //                e = 2q + 1: sqrt(-2 ln u1) sin(2 pi u2);
 //   Rademacher : block q = e / 128 uses the same counter form; bit (e % 128) of
 //                the 128-bit word string w0 | w1 << 32 | ... selects +1 (set)
-//                or -1 (clear).
+//                or -1 (clear);
+//   Gamma      : element e, attempt t (t < 64) uses blocks 128 e + 2 t (x, the
+//                Box-Muller normal of the cosine branch) and 128 e + 2 t + 1
+//                (the acceptance uniform from (w1:w0)); for shape < 1 the boost
+//                uniform comes from (w3:w2) of block 128 e + 1.  The method is
+//                Marsaglia and Tsang's ("A simple method for generating gamma
+//                variables", ACM TOMS 2000); after 64 rejections the value is
+//                d = a - 1/3.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -80,6 +87,38 @@ __global__ __launch_bounds__(256) void k_rademacher(uint64_t seed, uint64_t stre
   for (size_t i = 0; i < cnt; ++i) out[e0 + i] = ((words[i >> 5] >> (i & 31)) & 1u) ? (int8_t)1 : (int8_t)-1;
 }
 
+// out[e] = scale[e] (1 when scale is null) times a Gamma(shape, 1) variate.
+__global__ __launch_bounds__(256) void k_gamma(uint64_t seed, uint64_t stream, size_t n, double shape,
+                                               const double* __restrict__ scale, double* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double a = shape >= 1.0 ? shape : shape + 1.0;
+  const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
+  double g = d;
+  for (int t = 0; t < 64; ++t) {
+    const uint64_t q = (uint64_t)e * 128u + 2u * (uint64_t)t;
+    const U4 wa = draw(q, seed, stream), wb = draw(q + 1, seed, stream);
+    const double u1 = uniform53(wa.x, wa.y), u2 = uniform53(wa.z, wa.w);
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    const double x = sqrt(-2.0 * log(u1)) * cs;
+    const double u = uniform53(wb.x, wb.y);
+    const double b = 1.0 + c * x;
+    const double v = b * b * b;
+    if (!(v > 0.0)) continue;
+    const double x2 = x * x;
+    if (u < 1.0 - 0.0331 * x2 * x2 || log(u) < 0.5 * x2 + d * (1.0 - v + log(v))) {
+      g = d * v;
+      break;
+    }
+  }
+  if (shape < 1.0) {
+    const U4 wb = draw((uint64_t)e * 128u + 1u, seed, stream);
+    g *= pow(uniform53(wb.z, wb.w), 1.0 / shape);
+  }
+  out[e] = g * (scale ? scale[e] : 1.0);
+}
+
 __global__ __launch_bounds__(256) void k_philox_raw(uint64_t seed, uint64_t stream, size_t nblocks,
                                                     uint32_t* __restrict__ out) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,6 +136,13 @@ hipError_t launch_rng_normal(hipStream_t s, uint64_t seed, uint64_t stream, size
   if (n == 0) return hipSuccess;
   const size_t pairs = (n + 1) / 2;
   hipLaunchKernelGGL(k_normal, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, seed, stream, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_gamma(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double shape,
+                            const double* scale, double* out) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gamma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, stream, n, shape, scale, out);
   return hipGetLastError();
 }
 

@@ -50,6 +50,9 @@ hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, cons
 // k_rng.hip: Philox4x32-10 normals, Rademacher signs and raw words
 hipError_t launch_rng_normal(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double* out);
 hipError_t launch_rng_rademacher(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, int8_t* out);
+// out[e] = scale[e] (or 1) * Gamma(shape, 1), Marsaglia-Tsang on the Philox streams
+hipError_t launch_rng_gamma(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double shape,
+                            const double* scale, double* out);
 hipError_t launch_rng_raw(hipStream_t s, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out);
 
 // k_pcg_f64.hip / k_pcg_f32.hip: grouped launches over `nprob` problems that

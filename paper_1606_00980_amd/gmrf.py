@@ -48,7 +48,8 @@ EXPORTS = [
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
     "gp_autotune", "gp_tune_save", "gp_tune_load",
     "gp_data_create", "gp_data_assemble", "gp_data_lambda", "gp_data_destroy", "gp_alpha_posterior",
-    "gp_hyper_default", "gp_svb_step", "gp_data_assemble_ar", "gp_svb_step_ar",
+    "gp_hyper_default", "gp_svb_step", "gp_data_assemble_ar", "gp_svb_step_ar", "gp_alpha_extrapolate",
+    "gp_rng_gamma", "gp_gibbs_step",
 ]
 
 GP_REQ_SOLVE, GP_REQ_SAMPLE, GP_REQ_TRACE = 0, 1, 2
@@ -176,6 +177,10 @@ def _load() -> ctypes.CDLL:
         "gp_hyper_default": (None, [P(GpHyper)]),
         "gp_svb_step": (i32, [vp, i32, vp, vp, vp, vp, vp, P(dbl), P(GpHyper), vp, P(GpOpts), P(GpStats)]),
         "gp_data_assemble_ar": (i32, [vp, vp, vp, i32, vp, vp, P(i64)]),
+        "gp_alpha_extrapolate": (i32, [i32, P(dbl), P(dbl), P(dbl)]),
+        "gp_rng_gamma": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_size_t, dbl, vp, vp]),
+        "gp_gibbs_step": (i32, [vp, vp, vp, vp, vp, vp, P(dbl), P(GpHyper), vp, ctypes.c_uint64, ctypes.c_uint64,
+                                P(GpOpts), P(GpStats)]),
         "gp_svb_step_ar": (i32, [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, P(dbl), P(dbl), P(GpHyper), vp, vp,
                                  P(GpOpts), P(GpStats), P(GpStats)]),
     }
@@ -321,6 +326,38 @@ def gp_svb_step_ar(d: int, op_a: int, Ns: int, z1w, z2w, W, z1a, z2a, A, lam, al
     alpha[:] = a
     beta[:] = b
     return st, _stats_list(sw, Ns), _stats_list(sa, Ns)
+
+
+def gp_rng_gamma(ctx: int, seed: int, stream: int, n: int, shape: float, scale, out) -> None:
+    _check(lib.gp_rng_gamma(ctx, seed, stream, n, shape, _ptr(scale), _ptr(out)), "gp_rng_gamma")
+
+
+def gp_gibbs_step(d: int, A, z1, z2, W, lam, alpha, bw_work, seed: int, iteration: int,
+                  prior: GpHyper | None = None, opts: GpOpts | None = None, check: bool = True):
+    """One Gibbs iteration for W, alpha, lambda; alpha (numpy) and W, lam
+    (device) are updated in place.  Returns (status, stats of the W draw)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    st_arr = _stats_array(1)
+    o = opts if opts is not None else gp_opts_default()
+    st = lib.gp_gibbs_step(d, _ptr(A), _ptr(z1), _ptr(z2), _ptr(W), _ptr(lam),
+                           a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           ctypes.byref(prior) if prior is not None else None, _ptr(bw_work), seed, iteration,
+                           ctypes.byref(o), st_arr)
+    if check:
+        _check(st, "gp_gibbs_step")
+    alpha[:] = a
+    return st, _stats_list(st_arr, 1)
+
+
+def gp_alpha_extrapolate(a_jm2, a_jm1, a_j) -> np.ndarray:
+    """Returns the extrapolated a_j (numpy) from the last three posterior means."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    x2 = np.ascontiguousarray(a_jm2, dtype=np.float64)
+    x1 = np.ascontiguousarray(a_jm1, dtype=np.float64)
+    x0 = np.array(a_j, dtype=np.float64)
+    _check(lib.gp_alpha_extrapolate(x0.size, x2.ctypes.data_as(dp), x1.ctypes.data_as(dp), x0.ctypes.data_as(dp)),
+           "gp_alpha_extrapolate")
+    return x0
 
 
 def gp_data_lambda(d: int, Ns: int, W, A, u1: float, u2: float, rss=None, scale=None, mean=None) -> None:

@@ -329,3 +329,61 @@ def test_svb_steps_with_ar_match_oracle(g, ctx, torch_cuda):
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op_a)
         g.gp_op_destroy(op)
+
+
+def test_alpha_extrapolation_matches_oracle(g):
+    """The host-side SVB convergence device against the oracle, over random
+    triples (both branches and both limits)."""
+    rng = np.random.default_rng(8)
+    a = rng.uniform(0.2, 8.0, (3, 500))
+    got = g.gp_alpha_extrapolate(a[0], a[1], a[2])
+    want = orc.alpha_extrapolate(a[0], a[1], a[2])
+    assert np.allclose(got, want, rtol=1e-12)
+    with pytest.raises(g.GmrfError):
+        g.gp_alpha_extrapolate(a[0][:0], a[1][:0], a[2][:0])
+
+
+# ------------------------------------------------------------------ Gibbs
+def test_gamma_draws_match_the_philox_twin(g, ctx, torch_cuda):
+    from oracle import philox
+    for shape in (0.3, 1.0, 3.7, 26371.1):
+        n = 5000
+        scale = np.random.default_rng(4).uniform(0.1, 2.0, n)
+        out = torch_cuda.empty(n, dtype=torch_cuda.float64, device="cuda")
+        g.gp_rng_gamma(ctx, 123, 45, n, shape, dev(torch_cuda, scale), out)
+        want = philox.gamma(123, 45, shape, scale)
+        assert np.allclose(out.cpu().numpy(), want, rtol=1e-12, atol=0), shape
+    with pytest.raises(g.GmrfError):
+        g.gp_rng_gamma(ctx, 1, 1, 10, 0.0, None, out)
+
+
+def test_gibbs_steps_match_oracle(g, ctx, torch_cuda):
+    """Three Gibbs iterations (W, alpha, lambda; AR(2) held) against the
+    oracle fed the same random vectors, seed and iteration numbers."""
+    w = synth.tiny((12, 10, 6), 6, 3, seed=101, T=60, P=2)
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    try:
+        d = g.gp_data_create(op, w.X.shape[0], 2, w.X, dev(torch_cuda, w.Y))
+        try:
+            rng = np.random.default_rng(12)
+            A = w.ar[:2]
+            grid = orc.grid(w.mask, w.conn)
+            alpha, lam = np.array([1.0, 1.0, 1.0]), 1.0 / w.sigma2.copy()
+            a_ref, l_ref = alpha.copy(), lam.copy()
+            Wd = torch_cuda.zeros((w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            lam_d = dev(torch_cuda, lam)
+            bw = torch_cuda.empty((w.K, w.N), dtype=torch_cuda.float64, device="cuda")
+            for it in range(3):
+                z1 = rng.standard_normal((1, w.K, 3, w.N))
+                z2 = rng.standard_normal((1, w.K, w.N))
+                st, stats = g.gp_gibbs_step(d, dev(torch_cuda, A), dev(torch_cuda, z1), dev(torch_cuda, z2), Wd,
+                                            lam_d, alpha, bw, 77, it, opts=g.gp_opts_default(tol=1e-10))
+                W_ref, a_ref, l_ref = orc.gibbs_step(grid, w.X, w.Y, A, z1, z2, a_ref, l_ref, 77, it)
+                assert np.linalg.norm(Wd.cpu().numpy() - W_ref) <= 1e-7 * np.linalg.norm(W_ref), it
+                assert np.allclose(alpha, a_ref, rtol=1e-6), (it, alpha, a_ref)
+                assert np.allclose(lam_d.cpu().numpy(), l_ref, rtol=1e-6), it
+        finally:
+            g.gp_data_destroy(d)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)

@@ -113,3 +113,26 @@ def test_svb_step_ar_lands_on_conditional_modes_for_zero_vectors():
     assert np.allclose(bm, (N / 2 + 0.1) / (qb / 2 + 1 / 10000.0), rtol=1e-12)
     rss = orc.residual_ss(w.X, w.Y, Wn[0], An[0])
     assert np.allclose(lm, ((T - P) / 2 + 0.1) / (rss / 2 + 1 / 10.0), rtol=1e-12)
+
+
+# ------------------------------------------------- SVB convergence device
+def test_alpha_extrapolation_against_a_fitted_parabola():
+    """The vertex branch against numpy's least-squares parabola through the
+    three points (exact for three points), the linear branch, and the factor-5
+    limits."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        a = rng.uniform(0.5, 5.0, 3)
+        out = orc.alpha_extrapolate(a[:1], a[1:2], a[2:])[0]
+        c2, c1, c0 = np.polyfit([0.0, 1.0, 2.0], a, 2)
+        tv = -c1 / (2 * c2) if c2 != 0 else -np.inf
+        pred = np.polyval([c2, c1, c0], tv) if tv > 2.0 else a[1] + 20.0 * (a[2] - a[1])
+        want = min(max(pred, a[2] / 5), 5 * a[2])
+        assert out == pytest.approx(want, rel=1e-9, abs=1e-12)
+    # a parabola whose vertex lies ahead: 1 + 1.75 t - 0.25 t^2 through (0, 1), (1, 2.5),
+    # (2, 3.5) peaks at t = 3.5 with the value 4.0625
+    a = np.array([1.0, 2.5, 3.5])
+    assert orc.alpha_extrapolate(a[:1], a[1:2], a[2:])[0] == pytest.approx(4.0625)
+    # a straight line: the factor-20 step, limited to 5 a_j
+    assert orc.alpha_extrapolate([1.0], [2.0], [3.0])[0] == pytest.approx(15.0)
+    assert orc.alpha_extrapolate([3.0], [2.0], [1.0])[0] == pytest.approx(0.2)
