@@ -585,25 +585,27 @@ def main():
         log(f"autotuned: {tuned}")
     for _ in range(args.warmup):
         wl.step()
-    torch.cuda.synchronize()
-    g.gp_ctx_profile(ctx, True)
+    # the timed steps: the library as it runs in production (solver rounds
+    # replayed as graphs, no per-launch timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         wl.step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = g.gp_ctx_profile_read(ctx)
-    g.gp_ctx_profile(ctx, False)
-    dt = t1 - t0
-    # the same steps without per-launch event timing (solver rounds replayed as graphs)
+    dt = time.perf_counter() - t0
+    stats = wl.last_stats
+    # the same steps again with per-launch HIP-event timing (eager launches),
+    # for the per-kernel figures and the roofline
+    g.gp_ctx_profile(ctx, True)
     torch.cuda.synchronize()
-    tg0 = time.perf_counter()
+    tp0 = time.perf_counter()
     for _ in range(args.steps):
         wl.step()
     torch.cuda.synchronize()
-    dt_graph = time.perf_counter() - tg0
-    stats = wl.last_stats
+    dt_prof = time.perf_counter() - tp0
+    prof = g.gp_ctx_profile_read(ctx)
+    g.gp_ctx_profile(ctx, False)
+    stats = stats + wl.last_stats
     ok = all(s["status"] == 0 and s["relres"] <= 1e-8 for s in stats)
     result = {
         "metric": "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency",
@@ -625,7 +627,7 @@ def main():
         "max_relres": max(s["relres"] for s in stats),
         "inner_iters_mean": round(sum(s["inner_iters"] for s in stats) / len(stats), 2),
         "outer_steps_mean": round(sum(s["outer_steps"] for s in stats) / len(stats), 2),
-        "value_unprofiled": round(wl.solves * args.steps / dt_graph, 2),
+        "value_profiled": round(wl.solves * args.steps / dt_prof, 2),
         "kernels": {k: {"launches": v["launches"],
                         "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
                         "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
