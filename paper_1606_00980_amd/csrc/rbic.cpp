@@ -158,7 +158,7 @@ struct Round {
   // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
   int outer(hipStream_t q) const {
     PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, Rco, st, xB, dv, pv));
-    PROFILED(c, GP_KERNEL_RB_RED64, launch_rb_red(q, h, d.d_desc, R, Rco, st, PH_OUTER, xB, u64));
+    PROFILED(c, GP_KERNEL_RB_RED64, launch_rb_red(q, h, d.d_desc, R, Rc, st, PH_OUTER, xB, u64));
     PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, Rco, st, c64, xB, u64, rv, pv, part, pstride));
     HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
     return GP_OK;
@@ -323,8 +323,9 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
         break;
       }
   Rc = std::max(1, std::min(Rc, R));
-  // the FP64 outer step holds no blocks across right-hand sides (register
-  // pressure): one per workgroup
+  // the FP64 refinement and x_B += d take one right-hand side per workgroup
+  // (holding the FP64 blocks across several costs the refinement occupancy);
+  // the FP64 red stage takes the inner chunks
   const int Rco = 1;
   const bool graphs = c->use_graphs && !c->prof_on;
   const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
