@@ -41,7 +41,7 @@ struct RhsState {
   double beta;      // direction update coefficient of the next iteration
   double target2;   // inner stop threshold on ||r||^2
   double relres;    // last FP64 relative residual
-  double spare;
+  unsigned long long slots;   // bit i: an outer step came after i of this right-hand side's own iterations
   int phase, status, inner_it, total_it;
   int outer;
   int has_d;        // the inner correction d holds a valid sum

@@ -317,6 +317,7 @@ __device__ inline void finalize_refine(const Prob& pr, int r, const double (&v)[
   prof_add(pr, PF_ADDSOL_P, s.pend);
   prof_add(pr, PF_REFINE_X0, pr.cfg.zero_guess && s.outer == 0);
   prof_add(pr, PF_ADDSOL_FRESH, pr.cfg.zero_guess && s.outer == 1);
+  s.slots |= 1ull << (s.total_it < 63 ? s.total_it : 63);
   if (s.outer == 0) s.bnorm2 = bb;
   s.has_d = 0;
   s.pend = 0;
@@ -661,13 +662,21 @@ __global__ __launch_bounds__(TILE, (OccMV<T, K>::v)) void k_update(const Prob* _
       const size_t off = (size_t)r * K * N;
       const Slab<T> ps((T*)pr.p + off, K, N), qs((const T*)pr.q + off, K, N), ds((T*)pr.d + off, K, N),
           rs((T*)pr.r + off, K, N);
-      T pv[K], rv[K], z[K];
+      // every load of the voxel ahead of its first store: a wait for a load
+      // also waits for the stores issued before it (one counter for both)
+      T pv[K], rv[K], qv[K], dv[K], z[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
         pv[k] = ps.ld(k, o);
-        const T dv = fresh ? a * pv[k] : ds.ld(k, o) + a * pv[k];
-        rv[k] = rs.ld(k, o) - a * qs.ld(k, o);
-        ds.st(k, o, dv);
+        rv[k] = rs.ld(k, o);
+        qv[k] = qs.ld(k, o);
+        dv[k] = fresh ? (T)0 : ds.ld(k, o);
+      }
+  #pragma unroll
+      for (int k = 0; k < K; ++k) {
+        dv[k] += a * pv[k];
+        rv[k] -= a * qv[k];
+        ds.st(k, o, dv[k]);
         rs.st(k, o, rv[k]);
       }
       if constexpr (hold)
@@ -702,13 +711,15 @@ __global__ __launch_bounds__(TILE) void k_addsol(const Prob* __restrict__ probs,
       const size_t off = (size_t)r * K * N;
       const Slab<T> ds((const T*)pr.d + off, K, N), ps((const T*)pr.p + off, K, N);
       const Slab<double> xs(pr.x + off, K, N);
+      double v[K];
   #pragma unroll
       for (int k = 0; k < K; ++k) {
-        double v = fresh ? 0.0 : xs.ld(k, o8);
-        if (hd) v += (double)ds.ld(k, oT);
-        if (hp) v += a * (double)ps.ld(k, oT);
-        xs.st(k, o8, v);
+        v[k] = fresh ? 0.0 : xs.ld(k, o8);
+        if (hd) v[k] += (double)ds.ld(k, oT);
+        if (hp) v[k] += a * (double)ps.ld(k, oT);
       }
+  #pragma unroll
+      for (int k = 0; k < K; ++k) xs.st(k, o8, v[k]);
     }
   }
 }

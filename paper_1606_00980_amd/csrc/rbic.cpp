@@ -29,9 +29,13 @@ struct RbData {
   Prob* d_prob = nullptr;
   RbDev h_desc{};            // their host sources (kept alive for the asynchronous copies)
   Prob h_prob{};
-  // shape of the last FP32 solve: mean inner-solve length and refinements
-  // (the first round of the next solve is planned from it)
-  int hist_est = 0, hist_outer = 0;
+  // shape of the last solve in each inner precision (0 FP64, 1 FP32) at the
+  // tolerances it had: the union over its right-hand sides of the iteration
+  // counts after which they took an outer step, and the largest such count.
+  // The first round of the next solve at the same settings replays it.
+  uint64_t hist_mask[2] = {0, 0};
+  int hist_len[2] = {0, 0};
+  double hist_tol[2][2] = {{0, 0}, {0, 0}};
   std::vector<std::pair<void*, size_t>> allocs;
 };
 
@@ -172,14 +176,16 @@ struct Round {
     return GP_OK;
   }
   // `len` iterations, iteration i preceded by the outer step when bit i of
-  // `mask` is set; len = 0: the outer step alone.
-  int round(hipStream_t q, int len, uint64_t mask) const {
+  // `mask` is set, and with `tail` one more outer step after the last when bit
+  // len is set; len = 0: the outer step alone.
+  int round(hipStream_t q, int len, uint64_t mask, bool tail = false) const {
     if (len == 0) return outer(q);
     for (int i = 0; i < len; ++i) {
       if (i < 64 && ((mask >> i) & 1))
         if (int e = outer(q)) return e;
       if (int e = inner(q)) return e;
     }
+    if (tail && len < 64 && ((mask >> len) & 1)) return outer(q);
     return GP_OK;
   }
 };
@@ -331,21 +337,21 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
                           std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
                           std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(Rc);
-  auto run_round = [&](int len, uint64_t mask) -> int {
+  auto run_round = [&](int len, uint64_t mask, bool tail) -> int {
     auto enq = [&](hipStream_t q) -> int {
       if (f32) {
         const Round<float> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                               (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
                               (float*)(ws + o_u)};
-        return rd.round(q, len, mask);
+        return rd.round(q, len, mask, tail);
       }
       const Round<double> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                              (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
                              (double*)(ws + o_u)};
-      return rd.round(q, len, mask);
+      return rd.round(q, len, mask, tail);
     };
     if (!graphs) return enq(s);
-    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask), enq);
+    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask) + (tail ? "t" : ""), enq);
   };
 
   // rounds planned as for the main solver: the outer step first, then
@@ -354,25 +360,22 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   int n_outer = R, n_inner = 0;
   int round_len = chunk;
   uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
-  if (f32 && o.chunk <= 0 && d.hist_est > 0) {
-    // the previous solve's shape: refinements expected every hist_est
-    // iterations, the outer step placed around each (as the planned rounds do)
-    uint64_t mask = 1;
-    int need = 1;
-    for (int k = 1; k < d.hist_outer; ++k) {
-      const int slot = k * d.hist_est + 1;
-      for (int t = slot - 1; t <= slot + 1; ++t)
-        if (t >= 1 && t <= 64) mask |= 1ull << (t - 1);
-      need = slot;
-    }
-    round_len = std::max(1, std::min(need, 2 * chunk));
-    round_mask = mask;
+  bool tail = false;
+  const int hp = f32 ? 1 : 0;
+  if (o.chunk <= 0 && d.hist_mask[hp] && d.hist_tol[hp][0] == o.tol && d.hist_tol[hp][1] == o.inner_tol) {
+    // the previous solve's shape: its outer steps where they were taken, and
+    // the last of them (the final refinement) after the round's iterations
+    round_len = d.hist_len[hp];
+    round_mask = d.hist_mask[hp];
+    tail = true;
   }
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
-    if (int st = (!f32 && n_inner == 0) ? run_round(0, 1) : run_round(round_len, round_mask)) return st;
+    if (int st = (!f32 && n_inner == 0 && !tail) ? run_round(0, 1, false) : run_round(round_len, round_mask, tail))
+      return st;
+    tail = false;
     HIPTRY(hipMemcpyAsync(hs.data(), sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
     n_outer = n_inner = 0;
@@ -398,14 +401,17 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
     rb_account(c, op, R, tsz, o.zero_guess != 0, pf);
     if (int e = prof_resolve(c)) return e;
   }
-  if (f32) {
-    int est = 0, outer = 0;
-    for (const RhsState& h : hs) {
-      if (h.outer >= 2) est = std::max(est, (h.total_it + h.outer - 2) / (h.outer - 1));
-      outer = std::max(outer, h.outer);
-    }
-    d.hist_est = est;
-    d.hist_outer = outer;
+  {
+    uint64_t m = 0;
+    for (const RhsState& h : hs) m |= h.slots;
+    int len = 0;
+    while (len < 63 && (m >> (len + 1)) != 0) ++len;
+    // a shape that reaches the last bit (outer steps after 63 or more
+    // iterations) is not replayed
+    d.hist_mask[hp] = len < 63 ? m : 0;
+    d.hist_len[hp] = len;
+    d.hist_tol[hp][0] = o.tol;
+    d.hist_tol[hp][1] = o.inner_tol;
   }
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   int ret = GP_OK;

@@ -147,6 +147,41 @@ template <typename T, int K, int NBLK> struct HoldRb {
   static constexpr bool v = NBLK * Tri<K>::NB * (int)sizeof(T) <= 384;
 };
 
+// One right-hand side's [K][n] vector of T (right-hand side r of a batch starts
+// at r * K * n), a voxel's K values moved together: a kernel issues all loads
+// of a voxel before its first store, since a wait for a load also waits for
+// every store issued before it (one counter for both).
+template <typename T, int K> struct RbVec {
+  Slab<T> s;
+  __device__ __forceinline__ RbVec(const T* base, int n) : s(base, K, n) {}
+  __device__ __forceinline__ void load(int i, T (&v)[K]) const {
+    const unsigned o = (unsigned)i * (unsigned)sizeof(T);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = s.ld(k, o);
+  }
+  __device__ __forceinline__ void store(int i, const T (&v)[K]) const {
+    const unsigned o = (unsigned)i * (unsigned)sizeof(T);
+#pragma unroll
+    for (int k = 0; k < K; ++k) s.st(k, o, v[k]);
+  }
+};
+
+// sum over the six neighbour slots of the vector v, a missing neighbour (-1)
+// contributing zero
+template <typename T, int K>
+__device__ __forceinline__ void neighbour_sum_v(const int (&nb)[6], const RbVec<T, K>& v, T (&s)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if (nb[d] < 0) continue;
+    T t[K];
+    v.load(nb[d], t);
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] += t[k];
+  }
+}
+
 __device__ __forceinline__ void load_nb(const int* tab, int n, int i, int (&nb)[6]) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = tab[(size_t)d * n + i];
@@ -260,8 +295,11 @@ __global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, const double
       for (int k = 0; k < K; ++k) cs.st(k, op, bv[k]);
       if (!zero_guess) {   // from a zero start value x_B is first written by x_B = d (+ a p)
         const Slab<double> xu(x + ur, K, rb.N), xs(xB + (size_t)r * K * rb.NB, K, rb.NB);
+        double xv[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) xs.st(k, op, xu.ld(k, on));
+        for (int k = 0; k < K; ++k) xv[k] = xu.ld(k, on);
+#pragma unroll
+        for (int k = 0; k < K; ++k) xs.st(k, op, xv[k]);
       }
     }
   }
@@ -279,10 +317,12 @@ __global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double*
   load_nb(rb.nbB, rb.NB, i, nb);
   const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), cs(c + (size_t)r * K * rb.NB, K, rb.NB);
   const unsigned oi = (unsigned)i * 8u;
-  double s[K];
+  double s[K], cv[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) cv[k] = cs.ld(k, oi);
   neighbour_sum<double, K>(nb, ts, s);
 #pragma unroll
-  for (int k = 0; k < K; ++k) cs.st(k, oi, cs.ld(k, oi) + rb.alpha64[k] * s[k]);
+  for (int k = 0; k < K; ++k) cs.st(k, oi, cv[k] + rb.alpha64[k] * s[k]);
 }
 
 // Right-hand side r takes part in the red stage of phase `want` (nothing to do
@@ -310,17 +350,16 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, 
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     if (!red_active(rb, st[r], want)) continue;
-    const Slab<T> vs(v + (size_t)r * K * rb.NB, K, rb.NB), us(u + (size_t)r * K * rb.NR, K, rb.NR);
+    const RbVec<T, K> vs(v + (size_t)r * K * rb.NB, rb.NB), us(u + (size_t)r * K * rb.NR, rb.NR);
     T s[K], y[K];
-    neighbour_sum<T, K>(nb, vs, s);
+    neighbour_sum_v<T, K>(nb, vs, s);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       s[k] *= RbT<T>::alpha(rb, k);
       y[k] = 0;
     }
     sym_apply<K>(P, s, y);
-#pragma unroll
-    for (int k = 0; k < K; ++k) us.st(k, oj, y[k]);
+    us.store(j, y);
   }
 }
 
@@ -354,7 +393,7 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     if (sr.phase != PH_OUTER) continue;
     const size_t off = (size_t)r * K * rb.NB;
     const Slab<double> cs(c + off, K, rb.NB), xs(xB + off, K, rb.NB), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
-    const Slab<T> rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB);
+    const RbVec<T, K> rs(rv + (size_t)r * K * rb.NB, rb.NB), ps(pv + (size_t)r * K * rb.NB, rb.NB);
     double r64[K];
     if (rb.zero_start && sr.outer == 0) {   // x_B = 0: r = c
 #pragma unroll
@@ -383,11 +422,8 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)zt[k];
     if (valid) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        rs.st(k, oT, rt[k]);
-        ps.st(k, oT, zt[k]);
-      }
+      rs.store(ii, rt);
+      ps.store(ii, zt);
     } else {
       acc[0] = acc[2] = 0.0;
     }
@@ -420,26 +456,21 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
   for (int r = w.r0; r < w.r1; ++r) {
     if (st[r].phase != PH_INNER) continue;
     const size_t off = (size_t)r * K * rb.NB;
-    const Slab<T> ps(pv + off, K, rb.NB), rs(rv + off, K, rb.NB), qs(qv + off, K, rb.NB);
-    const Slab<T> us(u + (size_t)r * K * rb.NR, K, rb.NR);
+    const RbVec<T, K> ps(pv + off, rb.NB), rs(rv + off, rb.NB), qs(qv + off, rb.NB);
+    const RbVec<T, K> us(u + (size_t)r * K * rb.NR, rb.NR);
     T p[K], y[K], s[K], q[K], rr[K], z[K], t[K];
+    ps.load(ii, p);
+    rs.load(ii, rr);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      p[k] = ps.ld(k, oT);
-      y[k] = 0;
-    }
+    for (int k = 0; k < K; ++k) y[k] = 0;
     sym_apply<K>(D, p, y);
-    neighbour_sum<T, K>(nb, us, s);
+    neighbour_sum_v<T, K>(nb, us, s);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       q[k] = y[k] - RbT<T>::alpha(rb, k) * s[k];
-      rr[k] = rs.ld(k, oT);
       z[k] = t[k] = 0;
     }
-    if (valid) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) qs.st(k, oT, q[k]);
-    }
+    if (valid) qs.store(ii, q);
     sym_apply<K>(S, rr, z);
     sym_apply<K>(S, q, t);
     T a[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -481,19 +512,30 @@ __global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rb
     const T a = (T)s.a, beta = (T)s.beta;
     const bool fresh = s.inner_it == 1;
     const size_t off = (size_t)r * K * rb.NB;
-    const Slab<T> ds(dv + off, K, rb.NB), rs(rv + off, K, rb.NB), ps(pv + off, K, rb.NB), qs(qv + off, K, rb.NB);
-    T p[K], rn[K], z[K];
+    const RbVec<T, K> ds(dv + off, rb.NB), rs(rv + off, rb.NB), ps(pv + off, rb.NB), qs(qv + off, rb.NB);
+    T p[K], dd[K], rn[K], q[K], z[K];
+    ps.load(i, p);
+    rs.load(i, rn);
+    qs.load(i, q);
+    if (fresh) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) dd[k] = a * p[k];
+    } else {
+      ds.load(i, dd);
+#pragma unroll
+      for (int k = 0; k < K; ++k) dd[k] += a * p[k];
+    }
+    ds.store(i, dd);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      p[k] = ps.ld(k, oT);
-      ds.st(k, oT, fresh ? a * p[k] : ds.ld(k, oT) + a * p[k]);
-      rn[k] = rs.ld(k, oT) - a * qs.ld(k, oT);
-      rs.st(k, oT, rn[k]);
+      rn[k] -= a * q[k];
       z[k] = 0;
     }
+    rs.store(i, rn);
     sym_apply<K>(S, rn, z);
 #pragma unroll
-    for (int k = 0; k < K; ++k) ps.st(k, oT, z[k] + beta * p[k]);
+    for (int k = 0; k < K; ++k) z[k] += beta * p[k];
+    ps.store(i, z);
   }
 }
 
@@ -507,7 +549,7 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
   const RbWork w = rb_work(rb.ntB, R, Rc);
   const int i = w.tile * TILE + threadIdx.x;
   if (i >= rb.NB) return;
-  const unsigned o8 = (unsigned)i * 8u, oT = (unsigned)i * (unsigned)sizeof(T);
+  const unsigned o8 = (unsigned)i * 8u;
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     const RhsState& s = st[r];
@@ -516,15 +558,19 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
     if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh)) continue;
     const bool hd = s.has_d != 0, hp = s.pend != 0;
     const double a = s.a;
-    const size_t off = (size_t)r * K * rb.NB;
-    const Slab<double> xs(xB + off, K, rb.NB);
-    const Slab<T> ds(dv + off, K, rb.NB), ps(pv + off, K, rb.NB);
+    const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB);
+    const RbVec<T, K> ds(dv + (size_t)r * K * rb.NB, rb.NB), ps(pv + (size_t)r * K * rb.NB, rb.NB);
+    T dt[K], pt[K];
+    double v[K];
+    if (hd) ds.load(i, dt);
+    if (hp) ps.load(i, pt);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = fresh ? 0.0 : xs.ld(k, o8);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      double v = fresh ? 0.0 : xs.ld(k, o8);
-      if (hd) v += (double)ds.ld(k, oT);
-      if (hp) v += a * (double)ps.ld(k, oT);
-      xs.st(k, o8, v);
+      if (hd) v[k] += (double)dt[k];
+      if (hp) v[k] += a * (double)pt[k];
+      xs.st(k, o8, v[k]);
     }
   }
 }
