@@ -283,19 +283,36 @@ __global__ __launch_bounds__(TILE) void k_perturb(OpDev op, const double* __rest
   double zz[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) zz[j] = z2[((size_t)r * K + j) * N + n];
+  // every z1 load issued unconditionally before any use (a missing neighbour
+  // is the voxel itself, so each address is valid; its term is dropped by a
+  // select), so the loads of all regressors and directions are in flight together
+  double hv[K][3], lv[K][3];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const double* zk = z1 + ((size_t)r * K + k) * dirs * N;
-    double pr = 0.0;
-    for (int d = 0; d < dirs; ++d) {
-      const int lo = nb[2 * d], hi = nb[2 * d + 1];
-      if (hi != n) pr += zk[(size_t)d * N + n];
-      if (lo != n) pr -= zk[(size_t)d * N + lo];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int dd = d < dirs ? d : 0;
+      hv[k][d] = zk[(size_t)dd * N + n];
+      lv[k][d] = zk[(size_t)dd * N + nb[2 * dd]];
     }
+  }
+  double pr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    pr[k] = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pr[k] += d < dirs && nb[2 * d + 1] != n ? hv[k][d] : 0.0;
+      pr[k] -= d < dirs && nb[2 * d] != n ? lv[k][d] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     double dt = 0.0;
 #pragma unroll
     for (int j = 0; j <= k; ++j) dt += L[pk(k, j)] * zz[j];
-    b[((size_t)r * K + k) * N + n] = bw[(size_t)k * N + n] + sqrt(op.alpha64[k]) * pr + dt;
+    b[((size_t)r * K + k) * N + n] = bw[(size_t)k * N + n] + sqrt(op.alpha64[k]) * pr[k] + dt;
   }
 }
 

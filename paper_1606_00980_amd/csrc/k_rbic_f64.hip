@@ -34,11 +34,11 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
 
 RB_INST(double)
 
-hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
-                             const double* xB, double* x) {
+hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* t,
+                             const double* u64, const double* xB, double* x) {
   if (rb.ntN == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, b, xB, x); break;
+  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, t, u64, xB, x); break;
   RB_K_SWITCH(rb.K, X)
 #undef X
   return hipGetLastError();

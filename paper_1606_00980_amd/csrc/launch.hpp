@@ -98,8 +98,8 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
 GP_RB_DECL(double)
 GP_RB_DECL(float)
 #undef GP_RB_DECL
-hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* b,
-                             const double* xB, double* x);
+hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* t,
+                             const double* u64, const double* xB, double* x);
 hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
                               int ntN);
 

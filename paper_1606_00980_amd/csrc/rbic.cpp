@@ -220,10 +220,10 @@ void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, 
   const double an = std::max(std::max(ad, ap), af);
   prof_add(c, GP_KERNEL_RB_ADDSOL, an * NB, an * K * NB * 16 - af * K * NB * 8 + (ad + ap) * K * NB * ts);
   // split: b read, t written and read, x read and x_B written (unless the start
-  // value is zero), c written; recovery: x_B and red b read, x written; the
-  // red inverses twice
+  // value is zero), c written, the red inverses read; recovery: x_B, t and u
+  // read, x written
   prof_add(c, GP_KERNEL_RB_EDGE, 2.0 * R * N,
-           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + R * K * 8 * (NB + NR + N) + 2 * NBt * NR * 8);
+           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + R * K * 8 * (NB + 2 * NR + N) + NBt * NR * 8);
 }
 
 }  // namespace
@@ -279,7 +279,7 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   };
   const size_t o_st = take((size_t)R * sizeof(RhsState)), o_part = take((size_t)NPART * R * pstride * 8),
                o_bb = take((size_t)R * std::max(ntN, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
-               o_u64 = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
+               o_u64 = take(nrv * 8), o_t = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
                o_q = take(nbv * tsz), o_u = take(nrv * tsz), o_prof = take(NPROF * sizeof(long long));
   if (int st = ensure_ws(c, off)) return st;
   char* ws = (char*)c->ws;
@@ -290,6 +290,7 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   double* c64 = (double*)(ws + o_c);
   double* xB = (double*)(ws + o_x);
   double* u64 = (double*)(ws + o_u64);
+  double* t64 = (double*)(ws + o_t);   // t = Q_nn^{-1} b_n of the split, kept for the recovery
 
   long long* prof = c->prof_on ? (long long*)(ws + o_prof) : nullptr;
   d.h_desc = rb_dev(op);
@@ -306,13 +307,13 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   HIPTRY(hipMemcpyAsync(d.d_prob, &d.h_prob, sizeof(Prob), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
   if (prof) HIPTRY(hipMemsetAsync(prof, 0, NPROF * sizeof(long long), s));
-  // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials (t = D_R^{-1} b_R borrows u64)
+  // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials, t = D_R^{-1} b_R
   {
     size_t r0 = 0;
     for (const RbItem& it : items) {
       if (it.R > 0)
         PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_split(s, d.h_desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, u64 + r0 * K * d.NR,
+                 launch_rb_split(s, d.h_desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, t64 + r0 * K * d.NR,
                                  c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN));
       r0 += (size_t)it.R;
     }
@@ -390,7 +391,8 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
     for (const RbItem& it : items) {
       if (it.R > 0)
         PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_recover(s, d.h_desc, it.R, sts + r0, it.b, xB + r0 * K * d.NB, it.x));
+                 launch_rb_recover(s, d.h_desc, it.R, sts + r0, t64 + r0 * K * d.NR, u64 + r0 * K * d.NR,
+                                   xB + r0 * K * d.NB, it.x));
       r0 += (size_t)it.R;
     }
   }

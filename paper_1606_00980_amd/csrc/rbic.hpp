@@ -76,17 +76,24 @@ __device__ __forceinline__ void packed_apply(const Slab<T>& A, unsigned voff, co
 }
 
 // sum over the six neighbour slots of vector v (rows of one right-hand side),
-// a missing neighbour (-1) contributing zero
+// a missing neighbour (-1) contributing zero.  Branch free: a missing slot
+// loads entry 0 (a valid address) and drops it with a select, so the loads of
+// all six neighbours are in flight together.
 template <typename T, int K>
 __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>& v, T (&s)[K]) {
+  T t[6][K];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const unsigned o = nb[d] < 0 ? 0u : (unsigned)nb[d] * (unsigned)sizeof(T);
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[d][k] = v.ld(k, o);
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) s[k] = 0;
 #pragma unroll
   for (int d = 0; d < 6; ++d) {
-    if (nb[d] < 0) continue;
-    const unsigned o = (unsigned)nb[d] * (unsigned)sizeof(T);
 #pragma unroll
-    for (int k = 0; k < K; ++k) s[k] += v.ld(k, o);
+    for (int k = 0; k < K; ++k) s[k] += nb[d] < 0 ? (T)0 : t[d][k];
   }
 }
 
@@ -167,19 +174,10 @@ template <typename T, int K> struct RbVec {
 };
 
 // sum over the six neighbour slots of the vector v, a missing neighbour (-1)
-// contributing zero
+// contributing zero (branch free, as neighbour_sum)
 template <typename T, int K>
 __device__ __forceinline__ void neighbour_sum_v(const int (&nb)[6], const RbVec<T, K>& v, T (&s)[K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) s[k] = 0;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    if (nb[d] < 0) continue;
-    T t[K];
-    v.load(nb[d], t);
-#pragma unroll
-    for (int k = 0; k < K; ++k) s[k] += t[k];
-  }
+  neighbour_sum<T, K>(nb, v.s, s);
 }
 
 __device__ __forceinline__ void load_nb(const int* tab, int n, int i, int (&nb)[6]) {
@@ -577,46 +575,43 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
 
 // Writes the solution in the caller's layout, in voxel order (writes of x
 // coalesced): x_m = x_B at the black voxels, x_n = Q_nn^{-1} (b_n + alpha .*
-// sum_{m ~ n} x_m) at the red ones; zero for a right-hand side with b = 0.
+// sum_{m ~ n} x_m) = t_n + u_n at the red ones, t = Q_nn^{-1} b_n from the
+// split and u = Q_nn^{-1} (alpha .* sum x_m) from the red stage of the last
+// outer step (which followed the last change of x_B); zero for b = 0.
 template <int K>
 __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* __restrict__ st,
-                                                     const double* __restrict__ b, const double* __restrict__ xB,
-                                                     double* __restrict__ x) {
+                                                     const double* __restrict__ t, const double* __restrict__ u64,
+                                                     const double* __restrict__ xB, double* __restrict__ x) {
   const int r = blockIdx.y, n = blockIdx.x * TILE + threadIdx.x;
   if (n >= rb.N) return;
   const bool zero = st[r].zero_b != 0;
-  // from a zero start value, x_B holds nothing until the first x_B += d
+  // from a zero start value, x_B holds nothing (and u was not formed) until
+  // the first x_B += d
   const bool xzero = rb.zero_start && st[r].outer <= 1;
-  const size_t ur = (size_t)r * K * rb.N;
-  const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB), xu(x + ur, K, rb.N);
+  const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB), xu(x + (size_t)r * K * rb.N, K, rb.N);
   const unsigned on = (unsigned)n * 8u;
   const int vp = rb.vpos[n], pos = vp >> 1;
   const unsigned op = (unsigned)pos * 8u;
   double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
   if (zero) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
   } else if (vp & 1) {   // black
+    if (!xzero) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = xzero ? 0.0 : xs.ld(k, op);
+      for (int k = 0; k < K; ++k) v[k] = xs.ld(k, op);
+    }
   } else {               // red
-    const Slab<double> bs(b + ur, K, rb.N);
-    double s[K];
-    if (xzero) {
+    const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
 #pragma unroll
-      for (int k = 0; k < K; ++k) s[k] = 0.0;
-    } else {
-      int nb[6];
-      load_nb(rb.nbR, rb.NR, pos, nb);
-      neighbour_sum<double, K>(nb, xs, s);
-    }
+    for (int k = 0; k < K; ++k) v[k] = ts.ld(k, op);
+    if (!xzero) {
+      double u[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      s[k] = bs.ld(k, on) + rb.alpha64[k] * s[k];
-      v[k] = 0.0;
+      for (int k = 0; k < K; ++k) u[k] = us.ld(k, op);
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] += u[k];
     }
-    const Packed<double, K, false> P(rb.P64, rb.NR, op);
-    sym_apply<K>(P, s, v);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) xu.st(k, on, v[k]);
