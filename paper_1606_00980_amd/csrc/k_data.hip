@@ -93,8 +93,13 @@ __global__ __launch_bounds__(DT) void k_data_tensors(int T, int K, int P, int N,
   }
 }
 
-// blockIdx.y = output entry: packed (k, l), l <= k, of B_n, then k of b_n.
-// Globals in LDS.
+// One thread per (voxel, row k): row k of B_n and entry k of b_n.  The draws
+// enter through their first two moments at the voxel, m1 = mean_j a and
+// m2 = mean_j a a' (both brackets are linear in them):
+//   B_kl = lambda (XX_kl - sum_p (R_klp + R_lkp) m1_p + sum_pq S_pklq m2_pq)
+//   b_k  = lambda (YX_k - sum_p Bt_pk m1_p + sum_pq Dt_pkq m2_pq).
+constexpr int PMAX = 4;   // largest AR order
+
 __global__ __launch_bounds__(DT) void k_data_assemble(int K, int P, int N, int Ns, const double* __restrict__ G,
                                                       const double* __restrict__ YX, const double* __restrict__ Bt,
                                                       const double* __restrict__ Dt,
@@ -110,38 +115,58 @@ __global__ __launch_bounds__(DT) void k_data_assemble(int K, int P, int N, int N
   const double* XX = sG;
   const double* R = sG + K * K;
   const double* S = R + K * K * P;
-  const int e = blockIdx.y, NB = K * (K + 1) / 2;
+  const int k = blockIdx.y;
   const double lam = lambda[n];
-  double acc = 0.0;   // sum over draws of the subtracted AR part
-  if (e < NB) {
-    int k = 0;
-    while ((k + 1) * (k + 2) / 2 <= e) ++k;
-    const int l = e - k * (k + 1) / 2;
-    for (int j = 0; j < Ns; ++j) {
-      double ra = 0.0, asa = 0.0;
-      for (int p = 0; p < P; ++p) {
-        const double ap = A[((size_t)j * P + p) * N + n];
-        ra += (R[(k * K + l) * P + p] + R[(l * K + k) * P + p]) * ap;
-        for (int q = 0; q < P; ++q) asa += ap * S[((p * K + k) * K + l) * P + q] * A[((size_t)j * P + q) * N + n];
-      }
-      acc += ra - asa;
+  double m1[PMAX] = {0.0, 0.0, 0.0, 0.0}, m2[PMAX][PMAX] = {};
+  for (int j = 0; j < Ns; ++j) {
+    double a[PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) a[p] = p < P ? A[((size_t)j * P + p) * N + n] : 0.0;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+      m1[p] += a[p];
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) m2[p][q] += a[p] * a[q];
     }
-    const double v = lam * (XX[k * K + l] - acc / Ns);
-    Bout[((size_t)n * K + k) * K + l] = v;
-    Bout[((size_t)n * K + l) * K + k] = v;
-  } else {
-    const int k = e - NB;
-    for (int j = 0; j < Ns; ++j) {
-      double ab = 0.0, ada = 0.0;
-      for (int p = 0; p < P; ++p) {
-        const double ap = A[((size_t)j * P + p) * N + n];
-        ab += ap * Bt[((size_t)p * K + k) * N + n];
-        for (int q = 0; q < P; ++q)
-          ada += ap * Dt[(((size_t)p * K + k) * P + q) * N + n] * A[((size_t)j * P + q) * N + n];
-      }
-      acc += ab - ada;
+  }
+  const double inv = Ns > 0 ? 1.0 / Ns : 0.0;
+#pragma unroll
+  for (int p = 0; p < PMAX; ++p) {
+    m1[p] *= inv;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) m2[p][q] *= inv;
+  }
+  // b_k first: its loads are independent of each other
+  if (bw) {
+    double bt[PMAX], dt[PMAX][PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+      bt[p] = p < P ? Bt[((size_t)p * K + k) * N + n] : 0.0;
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) dt[p][q] = p < P && q < P ? Dt[(((size_t)p * K + k) * P + q) * N + n] : 0.0;
     }
-    if (bw) bw[(size_t)k * N + n] = lam * (YX[(size_t)k * N + n] - acc / Ns);
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+      acc += bt[p] * m1[p];
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) acc -= dt[p][q] * m2[p][q];
+    }
+    bw[(size_t)k * N + n] = lam * (YX[(size_t)k * N + n] - acc);
+  }
+  double* row = Bout + ((size_t)n * K + k) * K;
+  for (int l = 0; l < K; ++l) {
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+      if (p < P) {
+        acc += (R[(k * K + l) * P + p] + R[(l * K + k) * P + p]) * m1[p];
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q)
+          if (q < P) acc -= S[((p * K + k) * K + l) * P + q] * m2[p][q];
+      }
+    }
+    row[l] = lam * (XX[k * K + l] - acc);
   }
 }
 
@@ -342,8 +367,8 @@ hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, cons
                                 const double* Bt, const double* Dt, const double* lambda, const double* A,
                                 double* Bout, double* bw) {
   const int nG = K * K + K * K * P + P * K * K * P;
-  const int entries = K * (K + 1) / 2 + K;
-  hipLaunchKernelGGL(k_data_assemble, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)nG * sizeof(double), s, K,
+  if (P > PMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_data_assemble, dim3((N + DT - 1) / DT, K), dim3(DT), (size_t)nG * sizeof(double), s, K,
                      P, N, Ns, G, YX, Bt, Dt, lambda, A, Bout, bw);
   return hipGetLastError();
 }

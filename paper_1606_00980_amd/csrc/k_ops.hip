@@ -334,7 +334,11 @@ template <int K>
 __global__ __launch_bounds__(TILE) void k_trace_partials(OpDev op, const int8_t* __restrict__ v,
                                                          const double* __restrict__ u,
                                                          double* __restrict__ part, int m) {
-  __shared__ double s_red[2 * K * (TILE / WAVE)];
+  // per-thread terms, then block reductions of them through LDS, G terms at a
+  // time (24 KB of LDS)
+  constexpr int NV = 2 * K, G = NV < 12 ? NV : 12;
+  __shared__ double s_val[G][TILE];
+  __shared__ double s_mid[G][TILE / 16];
   const int N = op.N, nt = op.ntiles;
   const int tile = blockIdx.x, i = blockIdx.y;
   const int n = tile * TILE + threadIdx.x;
@@ -343,29 +347,51 @@ __global__ __launch_bounds__(TILE) void k_trace_partials(OpDev op, const int8_t*
   int nb[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = op.nbr[(size_t)d * N + nn];
-  const int wv = threadIdx.x / WAVE, nw = TILE / WAVE;
+  // every load of the voxel issued before any use
+  int vv[K][7];
+  double un[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const size_t off = ((size_t)i * K + k) * N;
-    const double vn = v[off + nn];
+    vv[k][6] = v[off + nn];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) vv[k][d] = v[off + nb[d]];
+    un[k] = u[off + nn];
+  }
+  double val[NV];   // [0, K): v_k u_k, [K, 2K): (G v)_k u_k
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     double gv = 0.0;
 #pragma unroll
-    for (int d = 0; d < 6; ++d) gv += vn - (double)v[off + nb[d]];
-    const double un = u[off + nn];
-    const double a = valid ? vn * un : 0.0;
-    const double g = valid ? gv * un : 0.0;
-    const double sa = wave_sum(a), sg = wave_sum(g);
-    if (threadIdx.x % WAVE == 0) {
-      s_red[(0 * K + k) * nw + wv] = sa;
-      s_red[(1 * K + k) * nw + wv] = sg;
-    }
+    for (int d = 0; d < 6; ++d) gv += (double)(vv[k][6] - vv[k][d]);
+    val[k] = valid ? (double)vv[k][6] * un[k] : 0.0;
+    val[K + k] = valid ? gv * un[k] : 0.0;
   }
-  __syncthreads();
-  if (threadIdx.x < 2 * K) {
-    const int which = threadIdx.x / K, k = threadIdx.x % K;
-    double t = 0.0;
-    for (int j = 0; j < nw; ++j) t += s_red[(which * K + k) * nw + j];
-    part[(((size_t)which * m + i) * K + k) * nt + tile] = t;
+#pragma unroll
+  for (int g0 = 0; g0 < NV; g0 += G) {
+    const int ng = NV - g0 < G ? NV - g0 : G;
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (j < ng) s_val[j][threadIdx.x] = val[g0 + j];
+    __syncthreads();
+    // ng x 16 partial sums of 16 terms, then ng sums of 16 partials, each in
+    // a fixed order
+    for (int t = threadIdx.x; t < ng * (TILE / 16); t += TILE) {
+      const int q = t / (TILE / 16), c = t % (TILE / 16);
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc += s_val[q][c * 16 + j];
+      s_mid[q][c] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < ng) {
+      const int e = g0 + threadIdx.x, which = e / K, k = e % K;
+      double t = 0.0;
+#pragma unroll
+      for (int c = 0; c < TILE / 16; ++c) t += s_mid[threadIdx.x][c];
+      part[(((size_t)which * m + i) * K + k) * nt + tile] = t;
+    }
+    __syncthreads();
   }
 }
 
