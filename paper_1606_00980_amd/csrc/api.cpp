@@ -212,8 +212,7 @@ int read_bad(gp_op* op, int* bad) {
 }
 
 int reset_bad(gp_op* op) {
-  static const int big = INT_MAX;
-  HIPTRY(hipMemcpyAsync(op->d_bad, &big, sizeof(int), hipMemcpyHostToDevice, op->ctx->stream));
+  HIPTRY(hipMemsetD32Async((hipDeviceptr_t)op->d_bad, INT_MAX, 1, op->ctx->stream));
   return GP_OK;
 }
 

@@ -25,10 +25,18 @@ struct RbData {
   int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr, *vpos = nullptr;
   double *D64 = nullptr, *S64 = nullptr, *P64 = nullptr;
   float *D32 = nullptr, *S32 = nullptr, *P32 = nullptr;
-  RbDev* d_desc = nullptr;   // device copies of the descriptors a solver round reads
-  Prob* d_prob = nullptr;
-  RbDev h_desc{};            // their host sources (kept alive for the asynchronous copies)
-  Prob h_prob{};
+  // the descriptors a solver round reads, uploaded in one copy per solve
+  struct Desc {
+    RbDev desc;
+    Prob prob;
+  };
+  Desc* d_blob = nullptr;
+  RbDev* d_desc = nullptr;   // &d_blob->desc
+  Prob* d_prob = nullptr;    // &d_blob->prob
+  Desc h{};                  // host source
+  // the set-up's positive-definiteness flag has not been read yet (it is read
+  // with the first states of the next solve)
+  bool check_bad = false;
   // shape of the last solve in each inner precision (0 FP64, 1 FP32) at the
   // tolerances it had: the union over its right-hand sides of the iteration
   // counts after which they took an outer step, and the largest such count.
@@ -133,8 +141,10 @@ int build_lists(gp_op* op) {
       (st = rb_alloc(c, d, NBt * d->NB, &d->D64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->D32)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->S64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->S32)) ||
       (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)) ||
-      (st = rb_alloc(c, d, 1, &d->d_desc)) || (st = rb_alloc(c, d, 1, &d->d_prob)))
+      (st = rb_alloc(c, d, 1, &d->d_blob)))
     return st;
+  d->d_desc = &d->d_blob->desc;
+  d->d_prob = &d->d_blob->prob;
   auto up = [&](int* dst, const std::vector<int>& src) {
     return src.empty() ? hipSuccess
                        : hipMemcpyAsync(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
@@ -248,12 +258,9 @@ int rb_build(gp_op* op) {
   if (int st = reset_bad(op)) return st;
   PROFILED(c, GP_KERNEL_PRECOND, launch_rb_setup(c->stream, h, op->B64, d.P64, d.P32, d.D64, d.D32, d.S64, d.S32,
                                                   op->d_bad));
-  int bad = INT_MAX;
-  if (int st = read_bad(op, &bad)) return st;
-  if (bad != INT_MAX) {
-    op->pc_built = -1;
-    return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(bad) + " is not positive definite");
-  }
+  // the flag is read with the first states of the solve that follows (one
+  // wait fewer); that solve then fails with GP_ERR_NOT_SPD
+  d.check_bad = true;
   op->pc_built = GP_PRECOND_RB_IC0;
   return GP_OK;
 }
@@ -293,18 +300,17 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   double* t64 = (double*)(ws + o_t);   // t = Q_nn^{-1} b_n of the split, kept for the recovery
 
   long long* prof = c->prof_on ? (long long*)(ws + o_prof) : nullptr;
-  d.h_desc = rb_dev(op);
-  d.h_desc.prof = prof;
-  d.h_desc.zero_start = o.zero_guess ? 1 : 0;
-  std::memset(&d.h_prob, 0, sizeof(Prob));
-  d.h_prob.prof = prof;
-  d.h_prob.st = sts;
-  d.h_prob.part = part;
-  d.h_prob.R = R;
-  d.h_prob.pstride = pstride;
-  d.h_prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
-  HIPTRY(hipMemcpyAsync(d.d_desc, &d.h_desc, sizeof(RbDev), hipMemcpyHostToDevice, s));
-  HIPTRY(hipMemcpyAsync(d.d_prob, &d.h_prob, sizeof(Prob), hipMemcpyHostToDevice, s));
+  d.h.desc = rb_dev(op);
+  d.h.desc.prof = prof;
+  d.h.desc.zero_start = o.zero_guess ? 1 : 0;
+  std::memset(&d.h.prob, 0, sizeof(Prob));
+  d.h.prob.prof = prof;
+  d.h.prob.st = sts;
+  d.h.prob.part = part;
+  d.h.prob.R = R;
+  d.h.prob.pstride = pstride;
+  d.h.prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
+  HIPTRY(hipMemcpyAsync(d.d_blob, &d.h, sizeof(RbData::Desc), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
   if (prof) HIPTRY(hipMemsetAsync(prof, 0, NPROF * sizeof(long long), s));
   // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials, t = D_R^{-1} b_R
@@ -313,7 +319,7 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
     for (const RbItem& it : items) {
       if (it.R > 0)
         PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_split(s, d.h_desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, t64 + r0 * K * d.NR,
+                 launch_rb_split(s, d.h.desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, t64 + r0 * K * d.NR,
                                  c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN));
       r0 += (size_t)it.R;
     }
@@ -341,12 +347,12 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   auto run_round = [&](int len, uint64_t mask, bool tail) -> int {
     auto enq = [&](hipStream_t q) -> int {
       if (f32) {
-        const Round<float> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
+        const Round<float> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                               (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
                               (float*)(ws + o_u)};
         return rd.round(q, len, mask, tail);
       }
-      const Round<double> rd{c, d.h_desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
+      const Round<double> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                              (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
                              (double*)(ws + o_u)};
       return rd.round(q, len, mask, tail);
@@ -372,30 +378,50 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   }
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
+  // x in the caller's layout (repeated if a later round changes x_B)
+  auto recover = [&]() -> int {
+    size_t r0 = 0;
+    for (const RbItem& it : items) {
+      if (it.R > 0)
+        PROFILED(c, GP_KERNEL_RB_EDGE,
+                 launch_rb_recover(s, d.h.desc, it.R, sts + r0, t64 + r0 * K * d.NR, u64 + r0 * K * d.NR,
+                                   xB + r0 * K * d.NB, it.x));
+      r0 += (size_t)it.R;
+    }
+    return GP_OK;
+  };
+  bool recovered = false;
+  int bad = INT_MAX;
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
     if (int st = (!f32 && n_inner == 0 && !tail) ? run_round(0, 1, false) : run_round(round_len, round_mask, tail))
       return st;
+    // a replayed shape usually ends the solve: recover before waiting
+    if (tail)
+      if (int st = recover()) return st;
+    recovered = tail;
     tail = false;
     HIPTRY(hipMemcpyAsync(hs.data(), sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+    const bool check = d.check_bad;
+    if (check) HIPTRY(hipMemcpyAsync(&bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
+    if (check) {
+      d.check_bad = false;
+      if (bad != INT_MAX) {
+        op->pc_built = -1;
+        return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(bad) + " is not positive definite");
+      }
+    }
     n_outer = n_inner = 0;
     for (const RhsState& h : hs) {
       n_outer += h.phase == PH_OUTER;
       n_inner += h.phase == PH_INNER;
     }
+    if (n_outer > 0 || n_inner > 0) recovered = false;
     plan_round(hs, o, f32, chunk, &round_len, &round_mask);
   }
-  {
-    size_t r0 = 0;
-    for (const RbItem& it : items) {
-      if (it.R > 0)
-        PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_recover(s, d.h_desc, it.R, sts + r0, t64 + r0 * K * d.NR, u64 + r0 * K * d.NR,
-                                   xB + r0 * K * d.NB, it.x));
-      r0 += (size_t)it.R;
-    }
-  }
+  if (!recovered)
+    if (int st = recover()) return st;
   HIPTRY(hipStreamSynchronize(s));
   if (prof) {
     std::vector<long long> pf(NPROF);
