@@ -75,6 +75,41 @@ __device__ __forceinline__ void packed_apply(const Slab<T>& A, unsigned voff, co
   sym_apply<K>([&](int i) { return A.ld(i, voff); }, x, y);
 }
 
+// Block sums of NV values for each right-hand side of a work item, with the
+// cross-wavefront step done once for the whole item: add() reduces within the
+// wavefront and parks the result in LDS; flush() waits once and writes
+// part[v * vstride + r * pstride + tile] for the right-hand sides added.
+template <int NV>
+struct ItemSums {
+  double (*sh)[NV][TILE / WAVE];
+  unsigned mask = 0;   // right-hand sides (relative to r0) added
+  __device__ ItemSums() {
+    __shared__ double buf[RCMAX][NV][TILE / WAVE];
+    sh = buf;
+  }
+  __device__ void add(int rl, double (&v)[NV]) {
+    const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh[rl][i][wv] = v[i];
+    }
+    mask |= 1u << rl;
+  }
+  __device__ void flush(double* part, size_t vstride, int r0, int nr, int pstride, int tile) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < nr * NV; t += TILE) {
+      const int rl = t / NV, i = t % NV;
+      if (!((mask >> rl) & 1u)) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < TILE / WAVE; ++w) s += sh[rl][i][w];
+      part[(size_t)i * vstride + (size_t)(r0 + rl) * pstride + tile] = s;
+    }
+  }
+};
+
 // sum over the six neighbour slots of vector v (rows of one right-hand side),
 // a missing neighbour (-1) contributing zero.  Branch free: a missing slot
 // loads entry 0 (a valid address) and drops it with a select, so the loads of
@@ -385,6 +420,7 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
   const unsigned o8 = (unsigned)ii * 8u, oT = (unsigned)ii * (unsigned)sizeof(T);
   const Packed<double, K, HOLD> D(rb.D64, rb.NB, o8);
   const Packed<T, K, HOLD> S(RbT<T>::S(rb), rb.NB, oT);
+  ItemSums<3> sums;
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     const RhsState& sr = st[r];
@@ -425,8 +461,9 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     } else {
       acc[0] = acc[2] = 0.0;
     }
-    block_sums<3>(acc, part, (size_t)R * pstride, (size_t)r * pstride + w.tile);
+    sums.add(r - w.r0, acc);
   }
+  sums.flush(part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
 
 // Black stage of q = S p with the seven inner products of the one-reduction
@@ -450,6 +487,7 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
   load_nb(rb.nbB, rb.NB, ii, nb);
   const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
   const Packed<T, K, HOLD> D(RbT<T>::D(rb), rb.NB, oT), S(RbT<T>::S(rb), rb.NB, oT);
+  ItemSums<7> sums;
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     if (st[r].phase != PH_INNER) continue;
@@ -485,8 +523,9 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
     double acc[7];
 #pragma unroll
     for (int e = 0; e < 7; ++e) acc[e] = valid ? (double)a[e] : 0.0;
-    block_sums<7>(acc, part, (size_t)R * pstride, (size_t)r * pstride + w.tile);
+    sums.add(r - w.r0, acc);
   }
+  sums.flush(part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
 
 // d += a p (d = a p on the first step), r -= a q, p = blkdiag(S)^{-1} r + beta p.
