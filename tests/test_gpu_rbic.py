@@ -265,3 +265,43 @@ def test_items_of_one_operator_are_solved_together(g, ctx, torch_cuda, precision
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_replayed_round_shape_continues_and_repeats_exactly(g, ctx, torch_cuda, precision):
+    """The first round of a solve replays the previous solve's outer-step
+    positions.  After a solve of b = 0 only (one outer step each) the next
+    solve needs far more than that shape and must go on in planned rounds to
+    the same answer; a third solve of the same right-hand sides, now replayed
+    in one round, must give the same x bit for bit (each right-hand side takes
+    the same steps whatever the round boundaries)."""
+    w = synth.tiny((23, 19, 9), 6, 3, seed=29)
+    op = make_op(g, ctx, torch_cuda, w)
+    try:
+        R, tol = 4, 1e-10
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, zero_guess=1)
+        zero = np.zeros((R, w.K, w.N))
+        x = dev(torch_cuda, zero)
+        _, stats0 = g.gp_solve(op, R, dev(torch_cuda, zero), x, o)
+        assert all(s["outer_steps"] == 1 and s["inner_iters"] == 0 for s in stats0)
+        b = rhs(w, R, 31)
+        xs = []
+        stats = []
+        for _ in range(2):
+            x = dev(torch_cuda, zero)
+            _, st = g.gp_solve(op, R, dev(torch_cuda, b), x, o)
+            xs.append(x.cpu().numpy())
+            stats.append(st)
+        Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
+        ref = orc.solve_direct(Q, b)
+        assert np.all(orc.relres(Q, xs[0], b) <= tol)
+        for r in range(R - 1):
+            assert np.linalg.norm(xs[0][r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), r
+        assert np.all(xs[0][R - 1] == 0.0)
+        assert np.array_equal(xs[0], xs[1])
+        for a, c in zip(stats[0], stats[1]):
+            assert (a["inner_iters"], a["outer_steps"]) == (c["inner_iters"], c["outer_steps"])
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
