@@ -305,3 +305,56 @@ def test_replayed_round_shape_continues_and_repeats_exactly(g, ctx, torch_cuda, 
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+def test_whole_brain_step_in_the_benchmark_configuration(g, ctx, torch_cuda):
+    """The benchmark's solve at full size and in its launch configuration:
+    whole-brain operator (N = 52,740, K = 6), 32 Algorithm-2 samples and 32
+    Rademacher probes in one grouped solve, red-black incomplete Cholesky, FP32
+    inner iterations with FP64 refinement to 1e-8 from a zero start, graphs
+    on.  Every right-hand side's residual is recomputed by the oracle; sampled
+    solutions and the trace estimates are checked against the oracle's; the
+    repeated solve (its first round replayed from the first) gives the same x."""
+    torch = torch_cuda
+    w = synth.brain_3d()
+    op = make_op(g, ctx, torch, w)
+    try:
+        S = M = 32
+        z1, z2 = w.z(S)
+        v = w.probes(M)
+        bs = torch.empty((S, w.K, w.N), dtype=torch.float64, device="cuda")
+        g.gp_perturb_rhs(op, S, dev(torch, w.bw), dev(torch, z1), dev(torch, z2), bs)
+        vd = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+        bp = torch.empty((M, w.K, w.N), dtype=torch.float64, device="cuda")
+        g.gp_probe_rhs(op, M, vd, bp)
+        o = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=g.GP_PRECOND_RB_IC0,
+                              precision=g.GP_PREC_FP32_REFINE64)
+        runs = []
+        for _ in range(2):
+            xs = torch.zeros_like(bs)
+            xp = torch.zeros_like(bp)
+            _, stats = g.gp_solve_batch(ctx, [(op, S, bs, xs), (op, M, bp, xp)], o)
+            assert all(s["status"] == g.GP_OK and s["relres"] <= 1e-8 for s in stats)
+            t = g.gp_trace_reduce(op, M, vd, xp, w.K)
+            runs.append((xs.cpu().numpy(), xp.cpu().numpy(), t))
+        grid = orc.grid(w.mask, w.conn)
+        Q = orc.precision(grid, w.alpha, w.B)
+        b_ref = orc.perturbation_rhs(grid, w.alpha, w.B, w.bw, z1, z2)
+        xs_h, xp_h, (t, tk, gk) = runs[0]
+        assert np.max(np.abs(bs.cpu().numpy() - b_ref)) <= 1e-12 * np.max(np.abs(b_ref))
+        assert np.all(orc.relres(Q, xs_h, b_ref) <= 1e-8)
+        assert np.all(orc.relres(Q, xp_h, v.astype(np.float64)) <= 1e-8)
+        pick = [0, 13, 31]
+        xs_ref = orc.solve(Q, b_ref[pick], tol=1e-13)
+        u_ref = orc.solve(Q, v.astype(np.float64), tol=1e-12)
+        for r_i, r in enumerate(pick):
+            assert np.linalg.norm(xs_h[r] - xs_ref[r_i]) <= 1e-6 * np.linalg.norm(xs_ref[r_i]), r
+            assert np.linalg.norm(xp_h[r] - u_ref[r]) <= 1e-6 * np.linalg.norm(u_ref[r]), r
+        t_ref, tk_ref, gk_ref, _ = orc.hutchinson(grid, Q, v, u=u_ref)
+        assert abs(t - t_ref) <= 1e-6 * abs(t_ref)
+        assert np.all(np.abs(np.asarray(tk) - tk_ref) <= 1e-6 * np.abs(tk_ref))
+        assert np.all(np.abs(np.asarray(gk) - gk_ref) <= 1e-6 * np.abs(gk_ref))
+        assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    finally:
+        torch.cuda.synchronize()
+        g.gp_op_destroy(op)
