@@ -37,6 +37,11 @@ struct RbData {
   // the set-up's positive-definiteness flag has not been read yet (it is read
   // with the first states of the next solve)
   bool check_bad = false;
+  // pinned host copies of the states and of that flag: both readbacks are
+  // asynchronous, so one wait covers them
+  RhsState* h_sts = nullptr;
+  size_t h_sts_cap = 0;
+  int* h_bad = nullptr;
   // shape of the last solve in each inner precision (0 FP64, 1 FP32) at the
   // tolerances it had: the union over its right-hand sides of the iteration
   // counts after which they took an outer step, and the largest such count.
@@ -241,6 +246,8 @@ void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, 
 void rb_release(gp_op* op) {
   if (!op->rb) return;
   for (auto& a : op->rb->allocs) dev_free(op->ctx, a.first, a.second);
+  if (op->rb->h_sts) (void)hipHostFree(op->rb->h_sts);
+  if (op->rb->h_bad) (void)hipHostFree(op->rb->h_bad);
   delete op->rb;
   op->rb = nullptr;
 }
@@ -364,6 +371,14 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   // rounds planned as for the main solver: the outer step first, then
   // iterations with the outer step where inner solves are expected to end
   std::vector<RhsState> hs(R);
+  if (d.h_sts_cap < (size_t)R) {
+    if (d.h_sts) HIPTRY(hipHostFree(d.h_sts));
+    d.h_sts = nullptr;
+    d.h_sts_cap = 0;
+    HIPTRY(hipHostMalloc((void**)&d.h_sts, (size_t)R * sizeof(RhsState), hipHostMallocDefault));
+    d.h_sts_cap = (size_t)R;
+  }
+  if (!d.h_bad) HIPTRY(hipHostMalloc((void**)&d.h_bad, sizeof(int), hipHostMallocDefault));
   int n_outer = R, n_inner = 0;
   int round_len = chunk;
   uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
@@ -401,10 +416,12 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
       if (int st = recover()) return st;
     recovered = tail;
     tail = false;
-    HIPTRY(hipMemcpyAsync(hs.data(), sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(d.h_sts, sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
     const bool check = d.check_bad;
-    if (check) HIPTRY(hipMemcpyAsync(&bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (check) HIPTRY(hipMemcpyAsync(d.h_bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPTRY(hipStreamSynchronize(s));
+    std::memcpy(hs.data(), d.h_sts, (size_t)R * sizeof(RhsState));
+    if (check) bad = *d.h_bad;
     if (check) {
       d.check_bad = false;
       if (bad != INT_MAX) {
