@@ -206,8 +206,10 @@ OpDev op_dev(const gp_op* op) {
 }
 
 int read_bad(gp_op* op, int* bad) {
-  HIPTRY(hipMemcpyAsync(bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, op->ctx->stream));
+  if (!op->h_bad) HIPTRY(hipHostMalloc((void**)&op->h_bad, sizeof(int), hipHostMallocDefault));
+  HIPTRY(hipMemcpyAsync(op->h_bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, op->ctx->stream));
   HIPTRY(hipStreamSynchronize(op->ctx->stream));
+  *bad = *op->h_bad;
   return GP_OK;
 }
 
@@ -987,6 +989,8 @@ int gp_op_destroy(gp_op* op) {
   op_free(op, op->d_bad, 1);
   op_free(op, op->gmap, op->ncell);
   op_free(op, op->tr_part, op->tr_cap);
+  if (op->h_bad) (void)hipHostFree(op->h_bad);
+  if (op->h_out) (void)hipHostFree(op->h_out);
   rb_release(op);
   delete op;
   return GP_OK;
@@ -1180,8 +1184,9 @@ static int trace_reduce_impl(gp_op* op, int m, const int8_t* probes, const doubl
   double* out = pairbuf + (size_t)2 * m * op->K;
   PROFILED(c, GP_KERNEL_TRACE, launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
   prof_add(c, GP_KERNEL_TRACE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
-  std::vector<double> h(1 + 2 * op->K);
-  HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (!op->h_out) HIPTRY(hipHostMalloc((void**)&op->h_out, (1 + 2 * KMAX) * sizeof(double), hipHostMallocDefault));
+  const double* h = op->h_out;
+  HIPTRY(hipMemcpyAsync(op->h_out, out, (1 + 2 * op->K) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
   if (tr_total) *tr_total = h[0];
   for (int k = 0; k < op->K; ++k) {

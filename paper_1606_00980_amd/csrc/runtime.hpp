@@ -91,6 +91,8 @@ struct gp_op {
   double* P64 = nullptr;
   float* P32 = nullptr;
   int* d_bad = nullptr;
+  int* h_bad = nullptr;      // pinned host copy of d_bad
+  double* h_out = nullptr;   // pinned host buffer of the trace results (1 + 2 KMAX)
   int* gmap = nullptr;      // [nz][ny][nx] voxel number or -1
   size_t ncell = 0;
   double* tr_part = nullptr;
