@@ -215,14 +215,18 @@ def roofline(prof):
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
     d = kinds[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    traffic = None
+    # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), while
+    # the kernel sources are those the counters were taken on
+    traffic, detail = None, None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tf = json.load(f)
         if tf.get("kernel_source_hash") == kernel_source_hash() and dom in tf.get("kernels", {}):
-            traffic = tf["kernels"][dom]
+            detail = tf["kernels"][dom]
+            traffic = detail["bytes_per_launch"]
     return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_detail": detail,
             "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 2),
             "bytes_per_launch": round(d["bytes"] / d["launches"])}
 
