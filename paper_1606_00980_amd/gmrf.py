@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from collections.abc import Sequence
 
 import numpy as np
 
@@ -431,10 +432,50 @@ def _stats_array(n: int):
     return (GpStats * max(n, 1))()
 
 
+_STATS_DTYPE = np.dtype([("status", np.int32), ("inner_iters", np.int32), ("outer_steps", np.int32),
+                         ("reserved", np.int32), ("relres", np.float64), ("time_us", np.float64)])
+
+
+class StatsList(Sequence):
+    """Per-right-hand-side statistics as a read-only sequence of dicts with
+    the fields of gp_stats; entries are built on access (a solve's caller
+    often looks at few of them)."""
+
+    __slots__ = ("_a",)
+
+    def __init__(self, arr, n: int):
+        self._a = np.frombuffer(arr, dtype=_STATS_DTYPE, count=n)
+
+    def __len__(self):
+        return len(self._a)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        e = self._a[i]
+        return {"status": int(e["status"]), "inner_iters": int(e["inner_iters"]),
+                "outer_steps": int(e["outer_steps"]), "relres": float(e["relres"]),
+                "time_us": float(e["time_us"])}
+
+    def __add__(self, other):
+        return list(self) + list(other)
+
+    def __radd__(self, other):
+        return list(other) + list(self)
+
+    def __eq__(self, other):
+        if isinstance(other, (list, tuple, StatsList)):
+            return list(self) == list(other)
+        return NotImplemented
+
+    __hash__ = None
+
+    def __repr__(self):
+        return repr(list(self))
+
+
 def _stats_list(arr, n: int):
-    return [{"status": arr[i].status, "inner_iters": arr[i].inner_iters,
-             "outer_steps": arr[i].outer_steps, "relres": arr[i].relres,
-             "time_us": arr[i].time_us} for i in range(n)]
+    return StatsList(arr, n)
 
 
 def gp_solve(op: int, R: int, b, x, opts: GpOpts | None = None, check: bool = True):
