@@ -20,12 +20,21 @@ hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, do
 }
 
 hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
-                           double* t, double* c, double* xB, double* bbpart) {
+                           double* t, double* c, double* xB, double* bbpart, const RbSplitFirst& first) {
+  const RbFirst<float> f32{first.f32 ? (float*)first.r : nullptr, (float*)first.p, first.part, first.vstride,
+                           first.pstride, first.r0};
+  const RbFirst<double> f64{first.f32 ? nullptr : (double*)first.r, (double*)first.p, first.part, first.vstride,
+                            first.pstride, first.r0};
 #define X(KK)                                                                                              \
   case KK:                                                                                                 \
     hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, xB, \
                        bbpart);                                                                            \
-    if (rb.ntB > 0) hipLaunchKernelGGL(k_rb_split_black<KK>, grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c);  \
+    if (rb.ntB > 0) {                                                                                      \
+      if (first.f32)                                                                                       \
+        hipLaunchKernelGGL((k_rb_split_black<KK, float>), grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c, f32); \
+      else                                                                                                 \
+        hipLaunchKernelGGL((k_rb_split_black<KK, double>), grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c, f64); \
+    }                                                                                                      \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X

@@ -79,8 +79,19 @@ int zm_rhs_per_block(int K);
 // graphs while alpha or buffers change.
 hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, double* P64, float* P32,
                            double* D64, float* D32, double* S64, float* S32, int* bad);
+// With r set (a zero start value), the split also takes the first refinement:
+// r = c, p = S_m^{-1} r in the inner precision (f32: float vectors, else
+// double), and its partials at right-hand side r0 + i of the solve.
+struct RbSplitFirst {
+  void* r;
+  void* p;
+  double* part;
+  size_t vstride;
+  int pstride, r0;
+  bool f32;
+};
 hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
-                           double* t, double* c, double* xB, double* bbpart);
+                           double* t, double* c, double* xB, double* bbpart, const RbSplitFirst& first);
 // Rc: right-hand sides per workgroup in the solver-round launches.
 #define GP_RB_DECL(T)                                                                                      \
   hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,                \

@@ -223,22 +223,24 @@ void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, 
   const double up = (double)pf[PF_UPDATE_RHS], fresh = (double)pf[PF_UPDATE_FRESH];
   prof_add(c, GP_KERNEL_RB_UPDATE, up * NB,
            (up - fresh) * 7 * K * NB * ts + fresh * 6 * K * NB * ts + pf[PF_UPDATE_ACT] * NBt * NB * ts);
-  // c, x_B, u64 read (c alone from a zero start value), r and p written; FP64
-  // Q_mm and the Schur inverses in the inner precision
+  // c, x_B, u64 read, r and p written; FP64 Q_mm and the Schur inverses in
+  // the inner precision (the first step from a zero start value is the
+  // split's)
   const double x0 = (double)pf[PF_REFINE_X0];
-  prof_add(c, GP_KERNEL_RB_REFINE, ref * NB,
-           ref * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) - x0 * K * (NB + NR) * 8 +
-               pf[PF_REFINE_ACT] * NBt * NB * (8 + ts));
+  prof_add(c, GP_KERNEL_RB_REFINE, (ref - x0) * NB,
+           (ref - x0) * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) + pf[PF_REFINE_ACT] * NBt * NB * (8 + ts));
   // x_B read (not on the first step from a zero start value) and written, d
   // and/or the pending step's p read
   const double ad = (double)pf[PF_ADDSOL_D], ap = (double)pf[PF_ADDSOL_P], af = (double)pf[PF_ADDSOL_FRESH];
   const double an = std::max(std::max(ad, ap), af);
   prof_add(c, GP_KERNEL_RB_ADDSOL, an * NB, an * K * NB * 16 - af * K * NB * 8 + (ad + ap) * K * NB * ts);
   // split: b read, t written and read, x read and x_B written (unless the start
-  // value is zero), c written, the red inverses read; recovery: x_B, t and u
+  // value is zero), c written, the red inverses read, and from a zero start
+  // value r and p of the first refinement written; recovery: x_B, t and u
   // read, x written
   prof_add(c, GP_KERNEL_RB_EDGE, 2.0 * R * N,
-           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + R * K * 8 * (NB + 2 * NR + N) + NBt * NR * 8);
+           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + x0 * K * 2 * NB * ts +
+               R * K * 8 * (NB + 2 * NR + N) + NBt * NR * 8);
 }
 
 }  // namespace
@@ -320,14 +322,20 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   HIPTRY(hipMemcpyAsync(d.d_blob, &d.h, sizeof(RbData::Desc), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
   if (prof) HIPTRY(hipMemsetAsync(prof, 0, NPROF * sizeof(long long), s));
-  // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials, t = D_R^{-1} b_R
+  // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials, t = D_R^{-1} b_R;
+  // from a zero start value also the first refinement (r = c, p = S_m^{-1} r)
   {
     size_t r0 = 0;
     for (const RbItem& it : items) {
+      RbSplitFirst first{nullptr, nullptr, part, (size_t)R * pstride, pstride, (int)r0, f32};
+      if (o.zero_guess) {
+        first.r = ws + o_r + r0 * K * d.NB * tsz;
+        first.p = ws + o_p + r0 * K * d.NB * tsz;
+      }
       if (it.R > 0)
         PROFILED(c, GP_KERNEL_RB_EDGE,
                  launch_rb_split(s, d.h.desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, t64 + r0 * K * d.NR,
-                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN));
+                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN, first));
       r0 += (size_t)it.R;
     }
   }

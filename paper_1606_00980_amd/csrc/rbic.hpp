@@ -154,6 +154,24 @@ __device__ inline void count_launch(const RbDev& rb, const RhsState* st, int R, 
 struct RbWork {
   int tile, r0, r1;
 };
+
+// Where the split writes the first refinement of a zero start value (r, p of
+// the item's right-hand sides, and the refinement partials of right-hand side
+// r0 + r of the solve); r == nullptr: not taken.
+template <typename T>
+struct RbFirst {
+  T* r;
+  T* p;
+  double* part;
+  size_t vstride;
+  int pstride, r0;
+};
+
+// Right-hand sides the refinement step works on: those in the outer phase,
+// except the first step from a zero start value, which the split takes.
+__device__ __forceinline__ bool refine_active(const RbDev& rb, const RhsState& s) {
+  return s.phase == PH_OUTER && !(rb.zero_start && s.outer == 0);
+}
 __device__ inline RbWork rb_work(int ntiles, int R, int Rc) {
   const int nch = (R + Rc - 1) / Rc;
   const int wi = xcd_remap(blockIdx.x, ntiles * nch);
@@ -341,21 +359,49 @@ __global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, const double
 
 // Black voxels: c += alpha .* sum_{n ~ m} t_n, which makes
 // c = b_B - E' D_R^{-1} b_R.
-template <int K>
+template <int K, typename T>
 __global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double* __restrict__ t,
-                                                         double* __restrict__ c) {
+                                                         double* __restrict__ c, RbFirst<T> first) {
   const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
-  if (i >= rb.NB) return;
+  const bool valid = i < rb.NB;
+  const int ii = valid ? i : 0;   // lanes past the end compute on voxel 0 and store nothing
   int nb[6];
-  load_nb(rb.nbB, rb.NB, i, nb);
+  load_nb(rb.nbB, rb.NB, ii, nb);
   const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), cs(c + (size_t)r * K * rb.NB, K, rb.NB);
-  const unsigned oi = (unsigned)i * 8u;
+  const unsigned oi = (unsigned)ii * 8u;
   double s[K], cv[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) cv[k] = cs.ld(k, oi);
   neighbour_sum<double, K>(nb, ts, s);
 #pragma unroll
-  for (int k = 0; k < K; ++k) cs.st(k, oi, cv[k] + rb.alpha64[k] * s[k]);
+  for (int k = 0; k < K; ++k) cv[k] += rb.alpha64[k] * s[k];
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) cs.st(k, oi, cv[k]);
+  }
+  if (first.r) {
+    // the first refinement from x_B = 0: its residual is c itself
+    const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
+    const Packed<T, K, false> S(RbT<T>::S(rb), rb.NB, oT);
+    double acc[3] = {0.0, 0.0, 0.0};
+    T rt[K], zt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc[0] += cv[k] * cv[k];
+      rt[k] = (T)cv[k];
+      zt[k] = 0;
+    }
+    sym_apply<K>(S, rt, zt);
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)zt[k];
+    if (valid) {
+      RbVec<T, K>(first.r + (size_t)r * K * rb.NB, rb.NB).store(ii, rt);
+      RbVec<T, K>(first.p + (size_t)r * K * rb.NB, rb.NB).store(ii, zt);
+    } else {
+      acc[0] = acc[2] = 0.0;
+    }
+    block_sums<3>(acc, first.part, first.vstride, (size_t)(first.r0 + r) * first.pstride + blockIdx.x);
+  }
 }
 
 // Right-hand side r takes part in the red stage of phase `want` (nothing to do
@@ -407,10 +453,14 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
                                                     T* __restrict__ pv, double* __restrict__ part, int R, int Rc,
                                                     int pstride) {
   const RbDev& rb = *rbp;
-  count_launch(rb, st, R, PH_OUTER, PF_REFINE_ACT);
+  if (rb.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    bool act = false;
+    for (int r = 0; r < R; ++r) act = act || refine_active(rb, st[r]);
+    if (act) atomicAdd((unsigned long long*)&rb.prof[PF_REFINE_ACT], 1ull);
+  }
   const RbWork w = rb_work(rb.ntB, R, Rc);
   bool any = false;
-  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_OUTER;
+  for (int r = w.r0; r < w.r1; ++r) any = any || refine_active(rb, st[r]);
   if (!any) return;
   const int i = w.tile * TILE + threadIdx.x;
   const bool valid = i < rb.NB;
@@ -424,15 +474,12 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     const RhsState& sr = st[r];
-    if (sr.phase != PH_OUTER) continue;
+    if (!refine_active(rb, sr)) continue;
     const size_t off = (size_t)r * K * rb.NB;
     const Slab<double> cs(c + off, K, rb.NB), xs(xB + off, K, rb.NB), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
     const RbVec<T, K> rs(rv + (size_t)r * K * rb.NB, rb.NB), ps(pv + (size_t)r * K * rb.NB, rb.NB);
     double r64[K];
-    if (rb.zero_start && sr.outer == 0) {   // x_B = 0: r = c
-#pragma unroll
-      for (int k = 0; k < K; ++k) r64[k] = cs.ld(k, o8);
-    } else {
+    {
       double xv[K], y[K], s[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
