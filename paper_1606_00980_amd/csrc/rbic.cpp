@@ -175,6 +175,12 @@ struct Round {
   T *dv, *rv, *pv, *qv, *uv;
 
   // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
+  // the first outer step of a solve from a zero start value: the split has
+  // done its refinement, so only the finalisation is left
+  int outer_first(hipStream_t q) const {
+    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
+    return GP_OK;
+  }
   int outer(hipStream_t q) const {
     PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, Rco, st, xB, dv, pv));
     PROFILED(c, GP_KERNEL_RB_RED64, launch_rb_red(q, h, d.d_desc, R, Rc, st, PH_OUTER, xB, u64));
@@ -193,11 +199,13 @@ struct Round {
   // `len` iterations, iteration i preceded by the outer step when bit i of
   // `mask` is set, and with `tail` one more outer step after the last when bit
   // len is set; len = 0: the outer step alone.
-  int round(hipStream_t q, int len, uint64_t mask, bool tail = false) const {
-    if (len == 0) return outer(q);
+  // With first (the solve's first round from a zero start value) the round's
+  // first outer step is outer_first.
+  int round(hipStream_t q, int len, uint64_t mask, bool tail = false, bool first = false) const {
+    if (len == 0) return first ? outer_first(q) : outer(q);
     for (int i = 0; i < len; ++i) {
       if (i < 64 && ((mask >> i) & 1))
-        if (int e = outer(q)) return e;
+        if (int e = (first && i == 0) ? outer_first(q) : outer(q)) return e;
       if (int e = inner(q)) return e;
     }
     if (tail && len < 64 && ((mask >> len) & 1)) return outer(q);
@@ -359,21 +367,23 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
                           std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
                           std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(Rc);
-  auto run_round = [&](int len, uint64_t mask, bool tail) -> int {
+  auto run_round = [&](int len, uint64_t mask, bool tail, bool first) -> int {
     auto enq = [&](hipStream_t q) -> int {
       if (f32) {
         const Round<float> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                               (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
                               (float*)(ws + o_u)};
-        return rd.round(q, len, mask, tail);
+        return rd.round(q, len, mask, tail, first);
       }
       const Round<double> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
                              (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
                              (double*)(ws + o_u)};
-      return rd.round(q, len, mask, tail);
+      return rd.round(q, len, mask, tail, first);
     };
     if (!graphs) return enq(s);
-    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask) + (tail ? "t" : ""), enq);
+    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask) + (tail ? "t" : "") +
+                               (first ? "f" : ""),
+                        enq);
   };
 
   // rounds planned as for the main solver: the outer step first, then
@@ -417,7 +427,11 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   int bad = INT_MAX;
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
-    if (int st = (!f32 && n_inner == 0 && !tail) ? run_round(0, 1, false) : run_round(round_len, round_mask, tail))
+    // the first round's first outer step (mask bit 0, set in every first round)
+    // is the finalisation alone when the split took the refinement
+    const bool first = rounds == 1 && o.zero_guess;
+    if (int st = (!f32 && n_inner == 0 && !tail) ? run_round(0, 1, false, first)
+                                                 : run_round(round_len, round_mask, tail, first))
       return st;
     // a replayed shape usually ends the solve: recover before waiting
     if (tail)
