@@ -16,6 +16,45 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// NV values summed over the wavefront together, every lane receiving all NV
+// totals: M halving exchanges (distances 32, 16, ... for the next power of two
+// 2^M >= NV) leave each lane a partial of value lane >> (6 - M), a butterfly
+// over the remaining distances completes it, and the totals are read back
+// from one lane per value.  The order of the additions is fixed.
+template <int NV>
+__device__ inline void wave_sums(double (&a)[NV]) {
+  constexpr int M = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : 3;
+  constexpr int NP = 1 << M;
+  static_assert(NV <= 8, "at most 8 values");
+  const int lane = threadIdx.x % WAVE;
+  double b[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) b[i] = i < NV ? a[i] : 0.0;
+#pragma unroll
+  for (int st = 0; st < M; ++st) {
+    const int dist = 32 >> st;
+    const int half = NP >> (st + 1);
+    const bool hi = (lane & dist) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double keep = hi ? b[i + half] : b[i];
+      const double send = hi ? b[i] : b[i + half];
+      b[i] = keep + __shfl_xor(send, dist, WAVE);
+    }
+  }
+  double e = b[0];
+#pragma unroll
+  for (int dist = 32 >> M; dist > 0; dist >>= 1) e += __shfl_xor(e, dist, WAVE);
+  const long long eb = __builtin_bit_cast(long long, e);
+  const int lo = (int)eb, hi = (int)(eb >> 32);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, i * (64 >> M));
+    const unsigned h = (unsigned)__builtin_amdgcn_readlane(hi, i * (64 >> M));
+    a[i] = __builtin_bit_cast(double, ((unsigned long long)h << 32) | l);
+  }
+}
+
 __device__ inline int wave_sum_int(int v) {
 #pragma unroll
   for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
@@ -91,8 +130,7 @@ __device__ inline void sum_partials(const double* part, int R, int stride, int n
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v] += g[((size_t)v * R + r) * stride + t];
   }
-#pragma unroll
-  for (int v = 0; v < NV; ++v) s[v] = wave_sum(s[v]);
+  wave_sums<NV>(s);
 }
 
 }  // namespace gp

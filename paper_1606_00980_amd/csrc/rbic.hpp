@@ -87,14 +87,9 @@ struct ItemSums {
     __shared__ double buf[RCMAX][NV][TILE / WAVE];
     sh = buf;
   }
-  __device__ void add(int rl, double (&v)[NV]) {
-    const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0) {
-#pragma unroll
-      for (int i = 0; i < NV; ++i) sh[rl][i][wv] = v[i];
-    }
+  __device__ void add(int rl, const double (&v)[NV]) {
+    // the NV values summed over the wavefront together (halving exchanges)
+    wave_deposit<NV>(&sh[0][0][0], rl, v);
     mask |= 1u << rl;
   }
   __device__ void flush(double* part, size_t vstride, int r0, int nr, int pstride, int tile) {
