@@ -50,14 +50,8 @@ template <> struct RbT<float> {
 template <int NV>
 __device__ inline void block_sums(double (&v)[NV], double* part, size_t vstride, size_t at) {
   __shared__ double sh[NV][TILE / WAVE];
-  const int wv = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   __syncthreads();   // a previous call's readers are done with sh
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) sh[i][wv] = v[i];
-  }
+  wave_deposit<NV>(&sh[0][0], 0, v);
   __syncthreads();
   if (threadIdx.x < NV) {
     double s = 0.0;
