@@ -62,3 +62,23 @@ def test_ctx_without_device_reports_device_error(g):
     h = ctypes.c_void_p()
     assert g.lib.gp_ctx_create(0, None, 0, ctypes.byref(h)) == g.GP_ERR_DEVICE
     assert h.value is None
+
+
+def test_stats_view_reads_the_c_array(g):
+    """Per-right-hand-side statistics come back as a read-only view over the
+    gp_stats array the library filled: fields, negative indices, slices,
+    concatenation with lists and equality behave like a list of dicts."""
+    arr = g._stats_array(5)
+    for i in range(5):
+        arr[i].status, arr[i].inner_iters, arr[i].outer_steps = -i, 10 + i, 3
+        arr[i].relres, arr[i].time_us = 1e-9 * (i + 1), 2.5
+    s = g._stats_list(arr, 4)   # only the first four were solved
+    assert len(s) == 4
+    assert s[1] == {"status": -1, "inner_iters": 11, "outer_steps": 3, "relres": 2e-9, "time_us": 2.5}
+    assert s[-1]["inner_iters"] == 13 and [e["status"] for e in s] == [0, -1, -2, -3]
+    assert s[1:3] == [s[1], s[2]]
+    both = s + g._stats_list(arr, 2)
+    assert isinstance(both, list) and len(both) == 6 and both[4] == s[0]
+    assert [] + s == list(s) and s == list(s)
+    with pytest.raises(IndexError):
+        s[4]
