@@ -25,15 +25,26 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
                            first.pstride, first.r0};
   const RbFirst<double> f64{first.f32 ? nullptr : (double*)first.r, (double*)first.p, first.part, first.vstride,
                             first.pstride, first.r0};
+  // right-hand sides per workgroup of the voxel pass (the red inverse held
+  // across them): the largest of 4, 2, 1 that leaves 1024 workgroups; the
+  // black pass (its time is in the gathers of t) takes one
+  int rcv = 1;
+  for (int cand : {4, 2})
+    if ((long)rb.ntN * ((R + cand - 1) / cand) >= 1024) {
+      rcv = cand;
+      break;
+    }
+  const int rcb = 1;
+  const int nchv = (R + rcv - 1) / rcv, nchb = (R + rcb - 1) / rcb;
 #define X(KK)                                                                                              \
   case KK:                                                                                                 \
-    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, b, x, zero_guess, t, c, xB, \
-                       bbpart);                                                                            \
+    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, nchv), dim3(TILE), 0, s, rb, R, rcv, b, x, zero_guess, t, c, \
+                       xB, bbpart);                                                                        \
     if (rb.ntB > 0) {                                                                                      \
       if (first.f32)                                                                                       \
-        hipLaunchKernelGGL((k_rb_split_black<KK, float>), grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c, f32); \
+        hipLaunchKernelGGL((k_rb_split_black<KK, float>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f32); \
       else                                                                                                 \
-        hipLaunchKernelGGL((k_rb_split_black<KK, double>), grid2(rb.ntB, R), dim3(TILE), 0, s, rb, t, c, f64); \
+        hipLaunchKernelGGL((k_rb_split_black<KK, double>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f64); \
     }                                                                                                      \
     break;
   RB_K_SWITCH(rb.K, X)

@@ -144,6 +144,7 @@ struct RbWork {
   int tile, r0, r1;
 };
 
+
 // Where the split writes the first refinement of a zero start value (r, p of
 // the item's right-hand sides, and the refinement partials of right-hand side
 // r0 + r of the solve); r == nullptr: not taken.
@@ -302,34 +303,44 @@ __global__ __launch_bounds__(TILE) void k_rb_setup_black(RbDev rb, const double*
 // b_n, black voxels c = b_m and x_B = x_m (x_B not written for a zero start
 // value); the per-tile partials of ||b||^2 into bbpart[r][tile].
 template <int K>
-__global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, const double* __restrict__ b,
+__global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, int R, int rc, const double* __restrict__ b,
                                                           const double* __restrict__ x, int zero_guess,
                                                           double* __restrict__ t, double* __restrict__ c,
                                                           double* __restrict__ xB, double* __restrict__ bbpart) {
-  const int r = blockIdx.y, n = blockIdx.x * TILE + threadIdx.x;
-  double acc[1] = {0.0};
-  if (n < rb.N) {
+  const int n = blockIdx.x * TILE + threadIdx.x;
+  const int r0 = blockIdx.y * rc, r1 = min(R, r0 + rc);
+  const bool valid = n < rb.N;
+  const int nn = valid ? n : rb.N - 1;   // lanes past the end compute on the last voxel and store nothing
+  const unsigned on = (unsigned)nn * 8u;
+  const int vp = rb.vpos[nn], pos = vp >> 1;
+  const bool red = (vp & 1) == 0;
+  const unsigned op = (unsigned)pos * 8u;
+  // the red inverse, held across the work item's right-hand sides (black
+  // lanes hold red block 0 and do not use it)
+  const Packed<double, K, HoldRb<double, K, 1>::v> P(rb.P64, rb.NR, red ? op : 0u);
+  ItemSums<1> sums;
+#pragma unroll 1
+  for (int r = r0; r < r1; ++r) {
     const size_t ur = (size_t)r * K * rb.N;
     const Slab<double> bs(b + ur, K, rb.N);
-    const unsigned on = (unsigned)n * 8u;
-    const int vp = rb.vpos[n], pos = vp >> 1;
-    const unsigned op = (unsigned)pos * 8u;
-    double bv[K];
+    double acc[1] = {0.0}, bv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       bv[k] = bs.ld(k, on);
       acc[0] += bv[k] * bv[k];
     }
-    if ((vp & 1) == 0) {   // red
-      const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR);
-      const Packed<double, K, false> P(rb.P64, rb.NR, op);
+    if (!valid) acc[0] = 0.0;
+    if (red) {
       double tv[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) tv[k] = 0.0;
       sym_apply<K>(P, bv, tv);
+      if (valid) {
+        const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR);
 #pragma unroll
-      for (int k = 0; k < K; ++k) ts.st(k, op, tv[k]);
-    } else {               // black
+        for (int k = 0; k < K; ++k) ts.st(k, op, tv[k]);
+      }
+    } else if (valid) {
       const Slab<double> cs(c + (size_t)r * K * rb.NB, K, rb.NB);
 #pragma unroll
       for (int k = 0; k < K; ++k) cs.st(k, op, bv[k]);
@@ -342,55 +353,62 @@ __global__ __launch_bounds__(TILE) void k_rb_split_voxels(RbDev rb, const double
         for (int k = 0; k < K; ++k) xs.st(k, op, xv[k]);
       }
     }
+    sums.add(r - r0, acc);
   }
-  block_sums<1>(acc, bbpart, 0, (size_t)r * rb.ntN + blockIdx.x);
+  sums.flush(bbpart, 0, r0, r1 - r0, rb.ntN, blockIdx.x);
 }
 
 // Black voxels: c += alpha .* sum_{n ~ m} t_n, which makes
 // c = b_B - E' D_R^{-1} b_R.
 template <int K, typename T>
-__global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, const double* __restrict__ t,
+__global__ __launch_bounds__(TILE) void k_rb_split_black(RbDev rb, int R, int rc, const double* __restrict__ t,
                                                          double* __restrict__ c, RbFirst<T> first) {
-  const int r = blockIdx.y, i = blockIdx.x * TILE + threadIdx.x;
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  const int r0 = blockIdx.y * rc, r1 = min(R, r0 + rc);
   const bool valid = i < rb.NB;
   const int ii = valid ? i : 0;   // lanes past the end compute on voxel 0 and store nothing
   int nb[6];
   load_nb(rb.nbB, rb.NB, ii, nb);
-  const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), cs(c + (size_t)r * K * rb.NB, K, rb.NB);
-  const unsigned oi = (unsigned)ii * 8u;
-  double s[K], cv[K];
+  const unsigned oi = (unsigned)ii * 8u, oT = (unsigned)ii * (unsigned)sizeof(T);
+  // the Schur inverse for the first refinement, held across the work item
+  const Packed<T, K, HoldRb<T, K, 1>::v> S(RbT<T>::S(rb), rb.NB, oT);
+  ItemSums<3> sums;
+#pragma unroll 1
+  for (int r = r0; r < r1; ++r) {
+    const Slab<double> ts(t + (size_t)r * K * rb.NR, K, rb.NR), cs(c + (size_t)r * K * rb.NB, K, rb.NB);
+    double s[K], cv[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) cv[k] = cs.ld(k, oi);
-  neighbour_sum<double, K>(nb, ts, s);
+    for (int k = 0; k < K; ++k) cv[k] = cs.ld(k, oi);
+    neighbour_sum<double, K>(nb, ts, s);
 #pragma unroll
-  for (int k = 0; k < K; ++k) cv[k] += rb.alpha64[k] * s[k];
-  if (valid) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) cs.st(k, oi, cv[k]);
-  }
-  if (first.r) {
-    // the first refinement from x_B = 0: its residual is c itself
-    const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
-    const Packed<T, K, false> S(RbT<T>::S(rb), rb.NB, oT);
-    double acc[3] = {0.0, 0.0, 0.0};
-    T rt[K], zt[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      acc[0] += cv[k] * cv[k];
-      rt[k] = (T)cv[k];
-      zt[k] = 0;
-    }
-    sym_apply<K>(S, rt, zt);
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)zt[k];
+    for (int k = 0; k < K; ++k) cv[k] += rb.alpha64[k] * s[k];
     if (valid) {
-      RbVec<T, K>(first.r + (size_t)r * K * rb.NB, rb.NB).store(ii, rt);
-      RbVec<T, K>(first.p + (size_t)r * K * rb.NB, rb.NB).store(ii, zt);
-    } else {
-      acc[0] = acc[2] = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) cs.st(k, oi, cv[k]);
     }
-    block_sums<3>(acc, first.part, first.vstride, (size_t)(first.r0 + r) * first.pstride + blockIdx.x);
+    if (first.r) {
+      // the first refinement from x_B = 0: its residual is c itself
+      double acc[3] = {0.0, 0.0, 0.0};
+      T rt[K], zt[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc[0] += cv[k] * cv[k];
+        rt[k] = (T)cv[k];
+        zt[k] = 0;
+      }
+      sym_apply<K>(S, rt, zt);
+#pragma unroll
+      for (int k = 0; k < K; ++k) acc[2] += (double)rt[k] * (double)zt[k];
+      if (valid) {
+        RbVec<T, K>(first.r + (size_t)r * K * rb.NB, rb.NB).store(ii, rt);
+        RbVec<T, K>(first.p + (size_t)r * K * rb.NB, rb.NB).store(ii, zt);
+      } else {
+        acc[0] = acc[2] = 0.0;
+      }
+      sums.add(r - r0, acc);
+    }
   }
+  if (first.r) sums.flush(first.part, first.vstride, first.r0 + r0, r1 - r0, first.pstride, blockIdx.x);
 }
 
 // Right-hand side r takes part in the red stage of phase `want` (nothing to do
