@@ -358,3 +358,43 @@ def test_whole_brain_step_in_the_benchmark_configuration(g, ctx, torch_cuda):
     finally:
         torch.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cells", [[(1, 1, 1)], [(2, 1, 1)], [(1, 1, 1), (2, 1, 1)],
+                                   [(1, 1, 1), (2, 1, 1), (1, 2, 1), (2, 2, 1), (1, 1, 2)]])
+def test_degenerate_colourings(g, ctx, torch_cuda, precision, cells):
+    """Masks with no red voxel (one odd voxel), no black voxel (one even
+    voxel), one of each, and a small cluster: the black system may be empty
+    (the red voxels are then solved directly by the recovery) or the red one
+    may be (nothing to eliminate).  Compared with the oracle's direct solve."""
+    mask = np.zeros((4, 4, 4), dtype=np.uint8)   # [z][y][x]
+    for (x, y, z) in cells:
+        mask[z, y, x] = 1
+    K = 3
+    rng = np.random.default_rng(len(cells))
+    N = int(mask.sum())
+    M = rng.standard_normal((N, K, K))
+    B = np.einsum("nij,nkj->nik", M, M) + 2.0 * np.eye(K)
+    alpha = np.array([0.5, 1.5, 3.0])
+    op = g.gp_op_create(ctx, mask, 6, K)
+    try:
+        g.gp_op_set_blocks(op, dev(torch_cuda, B))
+        g.gp_op_set_alpha(op, alpha)
+        R = 3
+        b = rng.standard_normal((R, K, N))
+        b[R - 1] = 0.0
+        x = dev(torch_cuda, np.zeros((R, K, N)))
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        o = g.gp_opts_default(tol=1e-10, precond=g.GP_PRECOND_RB_IC0, precision=prec, zero_guess=1)
+        _, stats = g.gp_solve(op, R, dev(torch_cuda, b), x, o)
+        assert all(s["status"] == g.GP_OK for s in stats)
+        Q = orc.precision(orc.grid(mask, 6), alpha, B)
+        ref = orc.solve_direct(Q, b)
+        xs = x.cpu().numpy()
+        for r in range(R - 1):
+            assert np.linalg.norm(xs[r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), r
+        assert np.all(xs[R - 1] == 0.0)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
