@@ -51,8 +51,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven", "serve"])
     ap.add_argument("--precond", default="rb_ic0", choices=["rb_ic0", "block_jacobi"],
-                    help="batch64: the incomplete Cholesky factor on the red-black order (default) "
-                         "or block Jacobi")
+                    help="batch64 and uneven: the incomplete Cholesky factor on the red-black order "
+                         "(default) or block Jacobi (autotuned)")
     ap.add_argument("--no-precond-compare", action="store_true",
                     help="batch64: skip the solve-only comparison of preconditioners and precisions")
     ap.add_argument("--no-ar-step", action="store_true",
@@ -145,7 +145,7 @@ class Workload:
                 xs, xp = torch.zeros_like(bs), torch.zeros_like(bp)
                 self.pert.append((op, dev(w.bw), dev(z1), dev(z2), v, bs, bp, xs, xp))
                 self.items += [(op, 4, bs, xs), (op, 4, bp, xp)]
-            self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
+            self.opts = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=pc)
             self.solves = 16 * 8
         self.last_stats = []
         self.trace = None
@@ -198,7 +198,7 @@ class Workload:
             return {"workload": "uneven16_ellipsoids_32x32x20_to_96x96x60_K2to10_R8",
                     "operators": 16, "N_total": int(sum(Ns)), "N_min": int(min(Ns)),
                     "N_max": int(max(Ns)), "K": Ks, "R_per_operator": 8,
-                    "tol": 1e-8, "precond": "block_jacobi", "precision": "fp32_inner_fp64_refine"}
+                    "tol": 1e-8, "precond": self.precond, "precision": "fp32_inner_fp64_refine"}
         w = self.ws[0]
         if self.name == "brain_fp64":
             return {"workload": "brain3d_64x64x33_ellipsoid_K6_R1_fp64", "N": w.N, "K": w.K, "R": 1,
@@ -582,7 +582,7 @@ def main():
     if args.workload == "serve":
         main_serve(args, g, torch, ctx)
         return
-    wl = Workload(args.workload, g, torch, ctx, args.precond if args.workload == "batch64" else "block_jacobi")
+    wl = Workload(args.workload, g, torch, ctx, args.precond if args.workload in ("batch64", "uneven") else "block_jacobi")
     tuned = None
     if not args.no_autotune and wl.precond != "rb_ic0":
         tuned = wl.autotune()
