@@ -57,6 +57,10 @@ extern "C" {
 #define GP_ERR_BREAKDOWN     -6  /* non-finite value or loss of definiteness  */
 #define GP_ERR_DEVICE        -7  /* a HIP runtime call failed                 */
 
+/* Largest number of regressors K of an operator (and of the per-regressor
+ * arrays of gp_result).                                                      */
+#define GP_KMAX 24
+
 /* ---- preconditioners and precision modes ----------------------------- */
 #define GP_PRECOND_JACOBI        0  /* inverse of diag(Q)                      */
 #define GP_PRECOND_BLOCK_JACOBI  1  /* inverse of each voxel's K x K block of Q */
@@ -508,8 +512,8 @@ typedef struct gp_result {
   double   latency_us;     /* submit -> result available                             */
   double   queue_us;       /* submit -> admitted                                     */
   double   trace_total;    /* GP_REQ_TRACE: estimates as in gp_trace_reduce          */
-  double   trace_kk[16];
-  double   trace_Gkk[16];
+  double   trace_kk[GP_KMAX];   /* entries k < K of the operator are set           */
+  double   trace_Gkk[GP_KMAX];
 } gp_result;
 
 typedef struct gp_server_stats {

@@ -29,6 +29,8 @@
 using namespace gp;
 using namespace gp::rt;
 
+static_assert(KMAX == GP_KMAX, "gp_result holds one trace entry per regressor");
+
 namespace {
 
 using Clock = std::chrono::steady_clock;

@@ -25,6 +25,7 @@ GP_ERR_BUSY = -4
 GP_ERR_NOT_CONVERGED = -5
 GP_ERR_BREAKDOWN = -6
 GP_ERR_DEVICE = -7
+GP_KMAX = 24          # largest K; length of gp_result's per-regressor arrays
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "OOM", -4: "BUSY",
                 -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "DEVICE"}
 
@@ -101,8 +102,8 @@ class GpResult(ctypes.Structure):
                 ("status", ctypes.c_int), ("rhs", ctypes.c_int), ("iters_max", ctypes.c_int),
                 ("reserved", ctypes.c_int), ("relres_max", ctypes.c_double),
                 ("latency_us", ctypes.c_double), ("queue_us", ctypes.c_double),
-                ("trace_total", ctypes.c_double), ("trace_kk", ctypes.c_double * 16),
-                ("trace_Gkk", ctypes.c_double * 16)]
+                ("trace_total", ctypes.c_double), ("trace_kk", ctypes.c_double * GP_KMAX),
+                ("trace_Gkk", ctypes.c_double * GP_KMAX)]
 
 
 class GpServerStats(ctypes.Structure):

@@ -343,3 +343,35 @@ def _intercept_only(mask, conn, T, P, seed, alpha) -> Workload:
     return Workload(name=f"tiny_K1_s{seed}", mask=mask, conn=conn, K=1, T=T, P=P, X=X,
                     ar=ar, sigma2=sigma2, W_true=W, Y=Y, B=B, bw=bw,
                     alpha=np.asarray(alpha, dtype=np.float64), config_id=900 + seed)
+
+
+# ----------------------------------------------------------- named workloads
+def from_spec(spec) -> Workload:
+    """The workload a spec names: ("slice",), ("brain",) or
+    ("uneven", config_id, instance)."""
+    kind = spec[0]
+    if kind == "slice":
+        return slice_2d(keep_y=False)
+    if kind == "brain":
+        return brain_3d()
+    if kind == "uneven":
+        return uneven_instance(int(spec[1]), int(spec[2]))
+    raise ValueError(f"unknown workload spec {spec!r}")
+
+
+def generate(specs, workers: int | None = None) -> list:
+    """[from_spec(s) for s in specs], made by a pool of ``spawn`` worker
+    processes (at most 16, and at most the cores this process may use)."""
+    import multiprocessing as mp
+    import os
+    specs = list(specs)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:                     # pragma: no cover
+        cores = os.cpu_count() or 1
+    workers = max(1, min(workers or 16, cores, len(specs)))
+    if workers == 1:
+        return [from_spec(s) for s in specs]
+    with mp.get_context("spawn").Pool(workers, maxtasksperchild=1) as pool:
+        return pool.map(from_spec, specs, chunksize=1)
+

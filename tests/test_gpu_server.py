@@ -117,3 +117,31 @@ def test_server_admission_budget(env):
         assert e.value.status == g.GP_ERR_OOM
     finally:
         g.gp_server_destroy(srv)
+
+
+def test_server_trace_on_k20_operator(env):
+    """A trace request on an operator with K = 20 (more regressors than 16):
+    every t_k and g_k of Section 3.3's trace term is returned and matches the
+    oracle with the same Philox probes; the entries past K stay zero."""
+    g, torch, ctx, _, _, _ = env
+    w = synth.tiny((12, 10, 6), 6, 20, seed=34, T=80)
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    B = torch.from_numpy(w.B).cuda()
+    bw = torch.from_numpy(w.bw).cuda()
+    try:
+        g.gp_op_set_blocks(op, B)
+        g.gp_op_set_alpha(op, w.alpha)
+        res, outs, _ = run(g, torch, ctx, [w], [op], [bw], [(g.GP_REQ_TRACE, 0, 4242)])
+    finally:
+        torch.cuda.synchronize()
+        g.gp_op_destroy(op)
+    r = res[0]
+    assert r["status"] == 0 and r["kind"] == g.GP_REQ_TRACE and r["op_index"] == 0 and r["rhs"] == PROBES
+    u_ref, (t, tk, gk) = oracle_result(g, w, g.GP_REQ_TRACE, 4242)
+    for i in range(PROBES):
+        assert np.linalg.norm(outs[0][i] - u_ref[i]) <= 1e-6 * np.linalg.norm(u_ref[i])
+    assert abs(r["trace_total"] - t) <= 1e-6 * abs(t)
+    assert len(r["trace_kk"]) == g.GP_KMAX and len(r["trace_Gkk"]) == g.GP_KMAX
+    assert np.allclose(r["trace_kk"][:w.K], tk, rtol=1e-6)
+    assert np.allclose(r["trace_Gkk"][:w.K], gk, rtol=1e-6)
+    assert all(v == 0.0 for v in r["trace_kk"][w.K:]) and all(v == 0.0 for v in r["trace_Gkk"][w.K:])
