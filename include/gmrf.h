@@ -415,6 +415,22 @@ int gp_probe_rhs(gp_op* op, int m, const int8_t* probes, double* b);
 int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u,
                     double* tr_total, double* tr_kk, double* tr_Gkk);
 
+/* gp_trace_reduce_static: gp_trace_reduce for callers that cannot allocate
+ * memory -- code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, same results (bitwise: the same
+ * kernels in the same order), but the call makes no device or host
+ * allocation: its device scratch (the per-tile partials, the per-probe sums
+ * and the 1 + 2K totals) is a library-owned static device array of 16 MiB per
+ * GPU, held until the process ends, and the results reach the host through a
+ * pinned buffer the operator allocated at gp_op_create.  Requires
+ * 2 m K ceil(N/256) + 2 m K + 49 <= 2097152 (doubles in 16 MiB), else
+ * GP_ERR_INVALID_ARG with nothing launched.  Every call on one GPU uses that
+ * GPU's one array (each call writes every value it reads, so nothing carries
+ * over): calls that overlap on one GPU -- from two contexts, threads or
+ * streams -- race and may return each other's values.  Blocking.          */
+int gp_trace_reduce_static(gp_op* op, int m, const int8_t* probes, const double* u,
+                           double* tr_total, double* tr_kk, double* tr_Gkk);
+
 /* gp_trace: gp_probe_rhs, gp_solve from u = 0, gp_trace_reduce.  u: device
  * FP64 [m][K][N] workspace that receives the solutions.  When probes is NULL
  * they are drawn on the device: gp_rng_rademacher(opts->seed, stream 3).

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,8 +22,40 @@
 using namespace gp;
 using namespace gp::rt;
 
+// Device scratch of the allocation-free trace reduction
+// (gp_trace_reduce_static): a fixed array in every GPU's memory, held until
+// the process ends.  Host code never passes `scratch` itself (its name is a
+// host-side stand-in); it uses the address hipGetSymbolAddress returns for the
+// current device, looked up once per device by gp_ctx_create.
+constexpr size_t TRACE_SCRATCH_DOUBLES = ((size_t)16 << 20) / sizeof(double);   // 16 MiB
+static __device__ __align__(256) double scratch[TRACE_SCRATCH_DOUBLES];
+
 namespace gp {
 namespace rt {
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};   // device address of `scratch`, per device
+}  // namespace
+
+// The device address of `scratch` on device `dev` (which must be current),
+// looked up on the first call for that device.
+int scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(GP_ERR_INVALID_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(GP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GP_OK;
+}
 
 thread_local std::string g_err;
 
@@ -802,6 +835,10 @@ int gp_ctx_create(int device, void* hip_stream, size_t hbm_budget, gp_ctx** out)
     delete c;
     return st;
   }
+  if (int st = scratch_address(device, &c->scratch)) {
+    delete c;
+    return st;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->cus = cus;
@@ -953,6 +990,12 @@ int gp_op_create(gp_ctx* c, const uint8_t* mask_host, int nx, int ny, int nz, in
     if ((st = op_alloc(op, NB * N, &op->P64))) break;
     if ((st = op_alloc(op, NB * N, &op->P32))) break;
     if ((st = op_alloc(op, 1, &op->d_bad))) break;
+    if ((e = hipHostMalloc((void**)&op->h_out, (1 + 2 * KMAX) * sizeof(double), hipHostMallocDefault)) !=
+        hipSuccess) {
+      op->h_out = nullptr;
+      st = fail(GP_ERR_OOM, std::string("pinned trace buffer: ") + hipGetErrorString(e));
+      break;
+    }
     unsigned long long E = 0;
     if ((e = hipMemsetAsync(d_edges, 0, sizeof(unsigned long long), s)) != hipSuccess ||
         (e = launch_grid_index(s, d_mask, ncell, d_offsets, nblocks, d_gridmap, op->lin, op->N, nx, ny, nz, conn,
@@ -1184,7 +1227,6 @@ static int trace_reduce_impl(gp_op* op, int m, const int8_t* probes, const doubl
   double* out = pairbuf + (size_t)2 * m * op->K;
   PROFILED(c, GP_KERNEL_TRACE, launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
   prof_add(c, GP_KERNEL_TRACE, (double)m * op->N, (double)m * op->N * op->K * 9.0);
-  if (!op->h_out) HIPTRY(hipHostMalloc((void**)&op->h_out, (1 + 2 * KMAX) * sizeof(double), hipHostMallocDefault));
   const double* h = op->h_out;
   HIPTRY(hipMemcpyAsync(op->h_out, out, (1 + 2 * op->K) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
@@ -1236,6 +1278,38 @@ int gp_trace_reduce(gp_op* op, int m, const int8_t* probes, const double* u, dou
   if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
   if (int st = set_device(c)) return st;
   return trace_reduce_impl(op, m, probes, u, tr_total, tr_kk, tr_Gkk);
+}
+
+int gp_trace_reduce_static(gp_op* op, int m, const int8_t* probes, const double* u, double* tr_total,
+                           double* tr_kk, double* tr_Gkk) {
+  if (!op) return fail(GP_ERR_INVALID_ARG, "op is NULL");
+  if (m < 1 || m > 65535) return fail(GP_ERR_INVALID_ARG, "m out of range");
+  if (!probes || !u) return fail(GP_ERR_INVALID_ARG, "null buffer");
+  const size_t need = (size_t)2 * m * op->K * op->ntiles + (size_t)2 * m * op->K + 1 + 2 * KMAX;
+  if (need > TRACE_SCRATCH_DOUBLES)
+    return fail(GP_ERR_INVALID_ARG, "2 m K ceil(N/256) + 2 m K + 49 doubles exceed the 16 MiB static scratch (" +
+                                        std::to_string(need) + " > " + std::to_string(TRACE_SCRATCH_DOUBLES) + ")");
+  gp_ctx* c = op->ctx;
+  BusyGuard guard(c);
+  if (!guard.ok) return fail(GP_ERR_BUSY, "context busy");
+  if (int st = set_device(c)) return st;
+  if (!c->scratch) return fail(GP_ERR_DEVICE, "static scratch address unknown");
+  double* part = c->scratch;
+  double* pairbuf = part + (size_t)2 * m * op->K * op->ntiles;
+  double* out = pairbuf + (size_t)2 * m * op->K;
+  // every scratch value is written before it is read within this call
+  // (per-tile partials for all tiles, probes and regressors; per-probe sums;
+  // the 1 + 2K totals), so nothing is cleared
+  HIPTRY(launch_trace(c->stream, op_dev(op), m, probes, u, part, pairbuf, out));
+  HIPTRY(hipMemcpyAsync(op->h_out, out, (1 + 2 * op->K) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPTRY(hipStreamSynchronize(c->stream));
+  const double* h = op->h_out;
+  if (tr_total) *tr_total = h[0];
+  for (int k = 0; k < op->K; ++k) {
+    if (tr_kk) tr_kk[k] = h[1 + k];
+    if (tr_Gkk) tr_Gkk[k] = h[1 + op->K + k];
+  }
+  return GP_OK;
 }
 
 int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total, double* tr_kk, double* tr_Gkk,

@@ -37,6 +37,7 @@ struct TuneEntry {
 
 struct gp_ctx {
   int device = 0;
+  double* scratch = nullptr;   // device address of the library's static scratch array on this device
   int cus = 256;     // compute units of the device
   hipStream_t stream = nullptr;
   size_t budget = 0, used = 0;

@@ -44,7 +44,7 @@ EXPORTS = [
     "gp_op_create", "gp_op_set_blocks", "gp_op_set_alpha", "gp_op_query",
     "gp_op_voxel_index", "gp_op_destroy",
     "gp_apply", "gp_solve", "gp_solve_batch", "gp_perturb_rhs", "gp_sample",
-    "gp_probe_rhs", "gp_trace_reduce", "gp_trace",
+    "gp_probe_rhs", "gp_trace_reduce", "gp_trace_reduce_static", "gp_trace",
     "gp_rng_normal", "gp_rng_rademacher", "gp_rng_raw",
     "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
     "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
@@ -157,6 +157,7 @@ def _load() -> ctypes.CDLL:
         "gp_sample": (i32, [vp, i32, vp, vp, vp, vp, P(GpOpts), P(GpStats)]),
         "gp_probe_rhs": (i32, [vp, i32, vp, vp]),
         "gp_trace_reduce": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl)]),
+        "gp_trace_reduce_static": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl)]),
         "gp_trace": (i32, [vp, i32, vp, vp, P(dbl), P(dbl), P(dbl), P(GpOpts), P(GpStats)]),
         "gp_rng_normal": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
         "gp_rng_rademacher": (i32, [vp, ctypes.c_uint64, ctypes.c_uint64, sz, vp]),
@@ -529,6 +530,13 @@ def gp_trace_reduce(op: int, m: int, probes, u, K: int):
     t, tk, gk = _trace_out(K)
     _check(lib.gp_trace_reduce(op, m, _ptr(probes), _ptr(u), ctypes.byref(t), tk, gk),
            "gp_trace_reduce")
+    return t.value, np.array(tk[:]), np.array(gk[:])
+
+
+def gp_trace_reduce_static(op: int, m: int, probes, u, K: int):
+    t, tk, gk = _trace_out(K)
+    _check(lib.gp_trace_reduce_static(op, m, _ptr(probes), _ptr(u), ctypes.byref(t), tk, gk),
+           "gp_trace_reduce_static")
     return t.value, np.array(tk[:]), np.array(gk[:])
 
 
