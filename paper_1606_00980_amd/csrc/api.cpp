@@ -346,15 +346,6 @@ void size_groups(std::vector<LaunchGroup>& gs, int cus) {
   }
 }
 
-#define PROFILED_IF(on, ctx, kind, launch)                    \
-  do {                                                        \
-    if (on) {                                                 \
-      PROFILED(ctx, kind, launch);                            \
-    } else {                                                  \
-      HIPTRY(launch);                                         \
-    }                                                         \
-  } while (0)
-
 int enqueue_outer(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                   const Prob* d_probs, bool profiled) {
   const bool pf = profiled && c->prof_on;
@@ -406,19 +397,54 @@ int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
   return GP_OK;
 }
 
-int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
-                           const Prob* d_probs, int chunk, uint64_t outer_mask) {
-  if (gs.size() <= 1) return enqueue_round(c, q, f32, pc, gs, d_probs, chunk, outer_mask, false);
-  while (c->branch.size() < gs.size()) {
+int ensure_branches(gp_ctx* c, size_t n) {
+  while (c->branch.size() < n) {
     hipStream_t b = nullptr;
     HIPTRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
     c->branch.push_back(b);
   }
-  while (c->branch_ev.size() < gs.size() + 1) {
+  while (c->branch_ev.size() < n + 1) {
     hipEvent_t e = nullptr;
     HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     c->branch_ev.push_back(e);
   }
+  return GP_OK;
+}
+
+int ensure_rb_probs(gp_ctx* c, size_t n) {
+  if (n <= c->rbp_cap) return GP_OK;
+  if (c->d_rbp) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    dev_free(c, c->d_rbp, c->rbp_cap * sizeof(RbProb));
+    (void)hipHostFree(c->h_rbp);
+    c->d_rbp = nullptr;
+    c->h_rbp = nullptr;
+    c->rbp_cap = 0;
+  }
+  const size_t cap = std::max<size_t>(n, 16);
+  if (int st = dev_alloc(c, cap * sizeof(RbProb), (void**)&c->d_rbp)) return st;
+  HIPTRY(hipHostMalloc((void**)&c->h_rbp, cap * sizeof(RbProb), hipHostMallocDefault));
+  c->rbp_cap = cap;
+  return GP_OK;
+}
+
+int ensure_rb_states(gp_ctx* c, size_t n) {
+  if (n <= c->rbst_cap) return GP_OK;
+  if (c->h_rbst) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    (void)hipHostFree(c->h_rbst);
+    c->h_rbst = nullptr;
+    c->rbst_cap = 0;
+  }
+  HIPTRY(hipHostMalloc((void**)&c->h_rbst, n * sizeof(RhsState), hipHostMallocDefault));
+  c->rbst_cap = n;
+  return GP_OK;
+}
+
+int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
+                           const Prob* d_probs, int chunk, uint64_t outer_mask) {
+  if (gs.size() <= 1) return enqueue_round(c, q, f32, pc, gs, d_probs, chunk, outer_mask, false);
+  if (int e = ensure_branches(c, gs.size())) return e;
   HIPTRY(hipEventRecord(c->branch_ev[0], q));
   for (size_t g = 0; g < gs.size(); ++g) {
     hipStream_t b = c->branch[g];
@@ -534,36 +560,25 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       it.op->pc_want = o.precond;
     }
   }
-  // the red-black incomplete Cholesky preconditioner has a solver of its own,
-  // run operator by operator
+  // the red-black incomplete Cholesky preconditioner has a solver of its own:
+  // every operator's items stacked in one member, members grouped by K
   if (o.precond == GP_PRECOND_RB_IC0) {
     std::vector<gp_stats> all(totalR);
-    std::vector<gp_op*> ops;
-    std::vector<std::vector<RbItem>> per_op;
+    std::vector<RbOpItems> ops;
     size_t base = 0;
     for (const Item& it : items) {
       if (it.R > 0) {
-        const size_t gi = std::find(ops.begin(), ops.end(), it.op) - ops.begin();
-        if (gi == ops.size()) {
-          ops.push_back(it.op);
-          per_op.emplace_back();
-        }
-        per_op[gi].push_back(RbItem{it.R, it.b, it.x, all.data() + base});
+        size_t gi = 0;
+        while (gi < ops.size() && ops[gi].op != it.op) ++gi;
+        if (gi == ops.size()) ops.push_back(RbOpItems{it.op, {}});
+        ops[gi].items.push_back(RbItem{it.R, it.b, it.x, all.data() + base});
       }
       base += (size_t)it.R;
     }
-    int ret = GP_OK;
-    std::string msg;
-    for (size_t gi = 0; gi < ops.size(); ++gi) {
-      const int st = rb_solve(c, ops[gi], per_op[gi], o);
-      if (st != GP_OK && st != GP_ERR_NOT_CONVERGED && st != GP_ERR_BREAKDOWN) return st;
-      if (st != GP_OK && ret == GP_OK) {
-        ret = st;
-        msg = gp_last_error();
-      }
-    }
+    const int st = rb_solve_group(c, ops, o);
+    if (st != GP_OK && st != GP_ERR_NOT_CONVERGED && st != GP_ERR_BREAKDOWN) return st;
     if (stats) std::memcpy(stats, all.data(), totalR * sizeof(gp_stats));
-    return ret == GP_OK ? GP_OK : fail(ret, msg);
+    return st;
   }
   // problems, ordered by K so that each K forms one grouped launch
   std::vector<int> order;
@@ -899,6 +914,9 @@ int gp_ctx_destroy(gp_ctx* c) {
   if (c->pbuf) dev_free(c, c->pbuf, c->pcap * sizeof(int8_t));
   if (c->d_probs) dev_free(c, c->d_probs, c->probs_cap * sizeof(Prob));
   if (c->h_probs) (void)hipHostFree(c->h_probs);
+  if (c->d_rbp) dev_free(c, c->d_rbp, c->rbp_cap * sizeof(RbProb));
+  if (c->h_rbp) (void)hipHostFree(c->h_rbp);
+  if (c->h_rbst) (void)hipHostFree(c->h_rbst);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

@@ -108,12 +108,41 @@ struct RbDev {
   const float* S32;
   const double* P64;     // [NBt][NR] packed inverse of Q_nn (red)
   const float* P32;
+  // fused red-black stage: black tile t (256 consecutive black positions)
+  // needs u at the red positions tlist[tbeg[t] .. tbeg[t+1]); nbS[d][i] is the
+  // index in that list of black i's neighbour in direction d, or -1
+  const int* tlist;
+  const int* tbeg;       // [ntB + 1]
+  const int* nbS;        // [6][NB]
   long long* prof;       // [NPROF] work counters while profiling, else null
   int NB, NR, ntB, ntR, N, K;
   int ntN;               // tiles of 256 voxels over all N (split, recovery, ||b||^2 partials)
   int zero_start;        // the start value is zero: x is not read
+  int maxRw;             // longest tile list (u entries a fused workgroup holds)
+  int spare;
   double alpha64[KMAX];
   float alpha32[KMAX];
+};
+
+// One member of a grouped red-black launch: an operator's colour split and
+// preconditioner with R right-hand sides, their states and vectors, and where
+// its work items start in the launches of its group (all members of a group
+// have the same K).
+struct RbProb {
+  RbDev rb;
+  Prob pr;               // st, part, R, pstride, cfg, prof, fin_begin (the finalisers' view)
+  const double* bb;      // [R][ntN] ||b||^2 partials of the split
+  const double* c64;     // [R][K][NB] black right-hand side of the Schur system
+  double* xB;            // [R][K][NB] black solution (FP64)
+  double* u64;           // [R][K][NR] red stage of the FP64 refinement
+  void* d;               // inner vectors [R][K][NB]
+  void* r;
+  void* p;
+  void* q;
+  void* u;               // [R][K][NR] red stage of an inner step (unfused)
+  int Rc, nch;           // right-hand sides per inner work item, chunks of them
+  int wB, wR, wO;        // first black-tile, red-tile and outer (one right-hand side) work item
+  int spare;
 };
 
 // Packed index of the symmetric (k, j) entry, lower triangle row-major.

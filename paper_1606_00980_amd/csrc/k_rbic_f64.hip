@@ -1,6 +1,7 @@
 // Red-black incomplete Cholesky: set-up, split, recovery and finalisation
-// launches, and the solver-round launches with FP64 inner vectors (the
-// kernels are in rbic.hpp; the FP32 round launches are in k_rbic_f32.hip).
+// launches, the FP64 red stage of the refinement, and the grouped solver-round
+// launches with FP64 inner vectors (the kernels are in rbic.hpp; the FP32
+// round launches are in k_rbic_f32.hip).
 #include "rbic.hpp"
 
 namespace gp {
@@ -64,13 +65,26 @@ hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsSta
   return hipGetLastError();
 }
 
-hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
-                              int ntN) {
-  const int g = (R + FIN_WAVES - 1) / FIN_WAVES;
+hipError_t launch_rbg_red64(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
+#define X(KK)                                                                                               \
+  case KK:                                                                                                  \
+    if constexpr (HoldRb<double, KK, 1>::v)                                                                 \
+      hipLaunchKernelGGL((k_rb_red<double, KK, true, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);     \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_rb_red<double, KK, false, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+    break;
+  RB_K_SWITCH(K, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_rbg_finalize(hipStream_t s, int kind, const RbProb* probs, int nprob, int nblocks) {
+  if (nblocks == 0) return hipSuccess;
   if (kind == 0)
-    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
+    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
   else
-    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(g), dim3(FIN_WAVES * WAVE), 0, s, prd, bbpart, ntB, ntN);
+    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
   return hipGetLastError();
 }
 

@@ -72,11 +72,12 @@ hipError_t launch_addsol_f32(hipStream_t s, int K, const Prob* probs, int nprob,
 // right-hand sides per z-marching workgroup for K regressors
 int zm_rhs_per_block(int K);
 
-// k_rbic_f32.hip / k_rbic_f64.hip: red-black incomplete Cholesky.  Vectors of the black system are
-// [R][K][NB], red ones [R][K][NR]; grids are (tiles of 256 voxels, R).  rb is
-// the host copy (grid sizes, K), rbd the same descriptor in device memory,
-// which the kernels of a solver round read so that rounds can be replayed as
-// graphs while alpha or buffers change.
+// k_rbic_f32.hip / k_rbic_f64.hip: red-black incomplete Cholesky.  Vectors of
+// the black system are [R][K][NB], red ones [R][K][NR].  Set-up, split and
+// recovery take one operator's descriptor by value; the solver-round launches
+// are grouped over several operators and read their descriptors from device
+// memory, so that rounds can be replayed as graphs while alpha or buffers
+// change.
 hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, double* P64, float* P32,
                            double* D64, float* D32, double* S64, float* S32, int* bad);
 // With r set (a zero start value), the split also takes the first refinement:
@@ -92,26 +93,36 @@ struct RbSplitFirst {
 };
 hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* b, const double* x, int zero_guess,
                            double* t, double* c, double* xB, double* bbpart, const RbSplitFirst& first);
-// Rc: right-hand sides per workgroup in the solver-round launches.
-#define GP_RB_DECL(T)                                                                                      \
-  hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,                \
-                           const RhsState* st, int want, const T* v, T* u);                                \
-  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
-                              const RhsState* st, const double* c, const double* xB, const double* u64, T* r, \
-                              T* p, double* part, int pstride);                                            \
-  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
-                              const RhsState* st, const T* p, const T* u, const T* r, T* q, double* part,   \
-                              int pstride);                                                                \
-  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
-                              const RhsState* st, T* d, T* r, T* p, const T* q);                           \
-  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,             \
-                              const RhsState* st, double* xB, const T* d, const T* p);
-GP_RB_DECL(double)
-GP_RB_DECL(float)
-#undef GP_RB_DECL
+// Grouped solver-round launches over the nprob members of one K group (device
+// descriptors probs, every member with K regressors); W = the launch's work
+// items: black-tile items (tiles x chunks of Rc right-hand sides) for matvec,
+// fused stage and update, red-tile items for the red stages, black-tile items
+// of one right-hand side for refine and addsol.  T is the inner precision.
+template <typename T> hipError_t launch_rbg_red(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+template <typename T> hipError_t launch_rbg_matvec(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+// red and black stage in one launch, u in LDS: cap entries of K values of T
+// per workgroup (cap >= every member's maxRw, cap * K * sizeof(T) <= RB_FUSED_LDS_MAX)
+constexpr size_t RB_FUSED_LDS_MAX = 64 * 1024;
+template <typename T> hipError_t launch_rbg_fused(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap);
+template <typename T> hipError_t launch_rbg_update(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+template <typename T> hipError_t launch_rbg_refine(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+template <typename T> hipError_t launch_rbg_addsol(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+#define GP_RBG_DECL(T)                                                                                       \
+  template <> hipError_t launch_rbg_red<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);        \
+  template <> hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
+  template <> hipError_t launch_rbg_fused<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap); \
+  template <> hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
+  template <> hipError_t launch_rbg_refine<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
+  template <> hipError_t launch_rbg_addsol<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+GP_RBG_DECL(float)
+GP_RBG_DECL(double)
+#undef GP_RBG_DECL
+// the FP64 red stage of the refinement (u64 from x_B), red-tile items
+hipError_t launch_rbg_red64(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+// finalisation after refine (kind 0) or the black stage (1): nblocks =
+// sum over members of ceil(R / 4)
+hipError_t launch_rbg_finalize(hipStream_t s, int kind, const RbProb* probs, int nprob, int nblocks);
 hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsState* st, const double* t,
                              const double* u64, const double* xB, double* x);
-hipError_t launch_rb_finalize(hipStream_t s, int kind, int R, const Prob* prd, const double* bbpart, int ntB,
-                              int ntN);
 
 }  // namespace gp

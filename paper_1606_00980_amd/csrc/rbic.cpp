@@ -3,7 +3,9 @@
 // two-colour voxel order): the colour split of an operator, the set-up of the
 // red inverses and black Schur blocks, and the driver of the half-size PCG on
 // the black Schur complement that PCG with this M reduces to (the algebra is
-// stated at the top of rbic.hpp).
+// stated at the top of rbic.hpp).  Several operators are solved together: the
+// members of one solve are grouped by K and every solver-round kernel is one
+// launch per group over the members' descriptors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,27 +23,15 @@ namespace gp {
 namespace rt {
 
 struct RbData {
-  int NB = 0, NR = 0, ntB = 0, ntR = 0, ntN = 0;
+  int NB = 0, NR = 0, ntB = 0, ntR = 0, ntN = 0, maxRw = 0;
   int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr, *vpos = nullptr;
+  int *tlist = nullptr, *tbeg = nullptr, *nbS = nullptr;
   double *D64 = nullptr, *S64 = nullptr, *P64 = nullptr;
   float *D32 = nullptr, *S32 = nullptr, *P32 = nullptr;
-  // the descriptors a solver round reads, uploaded in one copy per solve
-  struct Desc {
-    RbDev desc;
-    Prob prob;
-  };
-  Desc* d_blob = nullptr;
-  RbDev* d_desc = nullptr;   // &d_blob->desc
-  Prob* d_prob = nullptr;    // &d_blob->prob
-  Desc h{};                  // host source
   // the set-up's positive-definiteness flag has not been read yet (it is read
   // with the first states of the next solve)
   bool check_bad = false;
-  // pinned host copies of the states and of that flag: both readbacks are
-  // asynchronous, so one wait covers them
-  RhsState* h_sts = nullptr;
-  size_t h_sts_cap = 0;
-  int* h_bad = nullptr;
+  int* h_bad = nullptr;   // pinned host copy of that flag
   // shape of the last solve in each inner precision (0 FP64, 1 FP32) at the
   // tolerances it had: the union over its right-hand sides of the iteration
   // counts after which they took an outer step, and the largest such count.
@@ -64,38 +54,25 @@ int rb_alloc(gp_ctx* c, RbData* d, size_t count, P** p) {
   return GP_OK;
 }
 
-RbDev rb_dev(const gp_op* op) {
-  const RbData& d = *op->rb;
-  RbDev v;
-  std::memset(&v, 0, sizeof(v));
-  v.blk = d.blk;
-  v.red = d.red;
-  v.nbB = d.nbB;
-  v.nbR = d.nbR;
-  v.vpos = d.vpos;
-  v.D64 = d.D64;
-  v.D32 = d.D32;
-  v.S64 = d.S64;
-  v.S32 = d.S32;
-  v.P64 = d.P64;
-  v.P32 = d.P32;
-  v.NB = d.NB;
-  v.NR = d.NR;
-  v.ntB = d.ntB;
-  v.ntR = d.ntR;
-  v.ntN = d.ntN;
-  v.N = op->N;
-  v.K = op->K;
-  for (int k = 0; k < op->K; ++k) {
-    v.alpha64[k] = op->alpha[k];
-    v.alpha32[k] = (float)op->alpha[k];
+// Bricks of the voxel numbering inside each colour: 8 x 8 x 8 in 3D,
+// 16 x 16 in 2D.  A black tile (256 consecutive black positions) then covers
+// a compact region, so that the red voxels it touches -- the list its fused
+// stage forms in LDS -- are few (about 1.8 per black voxel on the whole-brain
+// mask against 3.1 in raster order).
+void brick_dims(const gp_op* op, int* bx, int* by, int* bz) {
+  if (op->nz == 1) {
+    *bx = *by = 16;
+    *bz = 1;
+  } else {
+    *bx = *by = *bz = 8;
   }
-  return v;
 }
 
-// Colour every voxel by the parity of x + y + z, number each colour in
-// increasing voxel order, and tabulate each voxel's neighbours by their
-// position in the other colour.
+// Colour every voxel by the parity of x + y + z, number each colour brick by
+// brick (bricks in raster order, voxels in raster order inside a brick),
+// tabulate each voxel's neighbours by their position in the other colour, and
+// for the fused stage list, per black tile, the red positions its voxels
+// touch, with each black voxel's neighbours as indices into its tile's list.
 int build_lists(gp_op* op) {
   gp_ctx* c = op->ctx;
   const int N = op->N;
@@ -103,12 +80,24 @@ int build_lists(gp_op* op) {
   HIPTRY(hipMemcpyAsync(lin.data(), op->lin, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipMemcpyAsync(nbr.data(), op->nbr, (size_t)6 * N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
-  std::vector<int> colour(N), pos(N), blk, red;
   const long nx = op->nx, ny = op->ny;
+  int bx, by, bz;
+  brick_dims(op, &bx, &by, &bz);
+  const long nbx = (nx + bx - 1) / bx, nby = (ny + by - 1) / by;
+  std::vector<long> key(N);
+  std::vector<int> colour(N), order(N);
   for (int n = 0; n < N; ++n) {
     const long l = lin[n];
     const long x = l % nx, y = (l / nx) % ny, z = l / (nx * ny);
     colour[n] = (int)((x + y + z) & 1);
+    key[n] = (x / bx) + nbx * ((y / by) + nby * (z / bz));
+    order[n] = n;
+  }
+  // voxel numbers increase with the linear index, so a stable sort by brick
+  // keeps raster order inside each brick
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+  std::vector<int> pos(N), blk, red;
+  for (int n : order) {
     std::vector<int>& list = colour[n] ? blk : red;
     pos[n] = (int)list.size();
     list.push_back(n);
@@ -138,18 +127,36 @@ int build_lists(gp_op* op) {
   };
   std::vector<int> nbB, nbR;
   if (!table(blk, nbB) || !table(red, nbR)) return fail(GP_ERR_INVALID_ARG, "voxel graph is not two-colourable");
+  // fused-stage lists: per black tile, its red neighbours in first-touch order
+  std::vector<int> tbeg(d->ntB + 1, 0), tlist, nbS((size_t)6 * d->NB, -1), slot(std::max(d->NR, 1), -1);
+  for (int t = 0; t < d->ntB; ++t) {
+    tbeg[t] = (int)tlist.size();
+    const int i0 = t * TILE, i1 = std::min(d->NB, i0 + TILE);
+    for (int i = i0; i < i1; ++i)
+      for (int dd = 0; dd < 6; ++dd) {
+        const int rj = nbB[(size_t)dd * d->NB + i];
+        if (rj < 0) continue;
+        if (slot[rj] < 0) {
+          slot[rj] = (int)tlist.size() - tbeg[t];
+          tlist.push_back(rj);
+        }
+        nbS[(size_t)dd * d->NB + i] = slot[rj];
+      }
+    for (size_t j = tbeg[t]; j < tlist.size(); ++j) slot[tlist[j]] = -1;
+    d->maxRw = std::max(d->maxRw, (int)tlist.size() - tbeg[t]);
+  }
+  tbeg[d->ntB] = (int)tlist.size();
   const size_t NBt = (size_t)op->K * (op->K + 1) / 2;
   int st = GP_OK;
   if ((st = rb_alloc(c, d, blk.size(), &d->blk)) || (st = rb_alloc(c, d, red.size(), &d->red)) ||
       (st = rb_alloc(c, d, nbB.size(), &d->nbB)) || (st = rb_alloc(c, d, nbR.size(), &d->nbR)) ||
-      (st = rb_alloc(c, d, vpos.size(), &d->vpos)) ||
+      (st = rb_alloc(c, d, vpos.size(), &d->vpos)) || (st = rb_alloc(c, d, tlist.size(), &d->tlist)) ||
+      (st = rb_alloc(c, d, tbeg.size(), &d->tbeg)) || (st = rb_alloc(c, d, nbS.size(), &d->nbS)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->D64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->D32)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->S64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->S32)) ||
-      (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)) ||
-      (st = rb_alloc(c, d, 1, &d->d_blob)))
+      (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)))
     return st;
-  d->d_desc = &d->d_blob->desc;
-  d->d_prob = &d->d_blob->prob;
+  HIPTRY(hipHostMalloc((void**)&d->h_bad, sizeof(int), hipHostMallocDefault));
   auto up = [&](int* dst, const std::vector<int>& src) {
     return src.empty() ? hipSuccess
                        : hipMemcpyAsync(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
@@ -159,104 +166,51 @@ int build_lists(gp_op* op) {
   HIPTRY(up(d->nbB, nbB));
   HIPTRY(up(d->nbR, nbR));
   HIPTRY(up(d->vpos, vpos));
+  HIPTRY(up(d->tlist, tlist));
+  HIPTRY(up(d->tbeg, tbeg));
+  HIPTRY(up(d->nbS, nbS));
   HIPTRY(hipStreamSynchronize(c->stream));
   return GP_OK;
 }
 
-// The launches of one solver round for inner precision T.
-template <typename T>
-struct Round {
-  gp_ctx* c;
-  const RbDev& h;
-  const RbData& d;
-  int R, Rc, Rco, pstride, ntN;   // Rco: right-hand sides per workgroup of the outer step
-  RhsState* st;
-  double *part, *bb, *c64, *xB, *u64;
-  T *dv, *rv, *pv, *qv, *uv;
-
-  // x_B += d, refinement r = c - S x_B, finalise (right-hand sides waiting on it)
-  // the first outer step of a solve from a zero start value: the split has
-  // done its refinement, so only the finalisation is left
-  int outer_first(hipStream_t q) const {
-    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
-    return GP_OK;
-  }
-  int outer(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_RB_ADDSOL, launch_rb_addsol(q, h, d.d_desc, R, Rco, st, xB, dv, pv));
-    PROFILED(c, GP_KERNEL_RB_RED64, launch_rb_red(q, h, d.d_desc, R, Rc, st, PH_OUTER, xB, u64));
-    PROFILED(c, GP_KERNEL_RB_REFINE, launch_rb_refine(q, h, d.d_desc, R, Rco, st, c64, xB, u64, rv, pv, part, pstride));
-    HIPTRY(launch_rb_finalize(q, 0, R, d.d_prob, bb, h.ntB, ntN));
-    return GP_OK;
-  }
-  // q = S p with the seven inner products, finalise, update
-  int inner(hipStream_t q) const {
-    PROFILED(c, GP_KERNEL_RB_RED, launch_rb_red(q, h, d.d_desc, R, Rc, st, PH_INNER, pv, uv));
-    PROFILED(c, GP_KERNEL_RB_MATVEC, launch_rb_matvec(q, h, d.d_desc, R, Rc, st, pv, uv, rv, qv, part, pstride));
-    HIPTRY(launch_rb_finalize(q, 1, R, d.d_prob, bb, h.ntB, ntN));
-    PROFILED(c, GP_KERNEL_RB_UPDATE, launch_rb_update(q, h, d.d_desc, R, Rc, st, dv, rv, pv, qv));
-    return GP_OK;
-  }
-  // `len` iterations, iteration i preceded by the outer step when bit i of
-  // `mask` is set, and with `tail` one more outer step after the last when bit
-  // len is set; len = 0: the outer step alone.
-  // With first (the solve's first round from a zero start value) the round's
-  // first outer step is outer_first.
-  int round(hipStream_t q, int len, uint64_t mask, bool tail = false, bool first = false) const {
-    if (len == 0) return first ? outer_first(q) : outer(q);
-    for (int i = 0; i < len; ++i) {
-      if (i < 64 && ((mask >> i) & 1))
-        if (int e = (first && i == 0) ? outer_first(q) : outer(q)) return e;
-      if (int e = inner(q)) return e;
-    }
-    if (tail && len < 64 && ((mask >> len) & 1)) return outer(q);
-    return GP_OK;
-  }
-};
-
-// Algorithmic HBM bytes of the launches of one solve, from the work counters:
-// every vector entry a launch needs read or written once (a gathered
-// neighbour vector counted once), the blocks once per launch with work.
-void rb_account(gp_ctx* c, const gp_op* op, int R, size_t tsz, bool zero_guess, const std::vector<long long>& pf) {
-  const RbData& d = *op->rb;
-  const double K = op->K, NB = d.NB, NR = d.NR, N = op->N, ts = (double)tsz, NBt = K * (K + 1) / 2;
-  const double mv = (double)pf[PF_MATVEC_RHS], ref = (double)pf[PF_REFINE_RHS];
-  // red stage: the black vector read, u written; the red inverses
-  prof_add(c, GP_KERNEL_RB_RED, mv * NR, mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts);
-  // the same in FP64 on x_B for refinements from a non-zero x
-  const double ref_x = ref - (double)pf[PF_REFINE_X0];
-  prof_add(c, GP_KERNEL_RB_RED64, ref_x * NR, ref_x * K * (NB + NR) * 8 + pf[PF_REFINE_ACT] * NBt * NR * 8);
-  // black stage: p, u, r read, q written; Q_mm and the Schur inverses
-  prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
-  // p, q, r, d read (d not on the first step), d, r, p written; Schur inverses
-  const double up = (double)pf[PF_UPDATE_RHS], fresh = (double)pf[PF_UPDATE_FRESH];
-  prof_add(c, GP_KERNEL_RB_UPDATE, up * NB,
-           (up - fresh) * 7 * K * NB * ts + fresh * 6 * K * NB * ts + pf[PF_UPDATE_ACT] * NBt * NB * ts);
-  // c, x_B, u64 read, r and p written; FP64 Q_mm and the Schur inverses in
-  // the inner precision (the first step from a zero start value is the
-  // split's)
-  const double x0 = (double)pf[PF_REFINE_X0];
-  prof_add(c, GP_KERNEL_RB_REFINE, (ref - x0) * NB,
-           (ref - x0) * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) + pf[PF_REFINE_ACT] * NBt * NB * (8 + ts));
-  // x_B read (not on the first step from a zero start value) and written, d
-  // and/or the pending step's p read
-  const double ad = (double)pf[PF_ADDSOL_D], ap = (double)pf[PF_ADDSOL_P], af = (double)pf[PF_ADDSOL_FRESH];
-  const double an = std::max(std::max(ad, ap), af);
-  prof_add(c, GP_KERNEL_RB_ADDSOL, an * NB, an * K * NB * 16 - af * K * NB * 8 + (ad + ap) * K * NB * ts);
-  // split: b read, t written and read, x read and x_B written (unless the start
-  // value is zero), c written, the red inverses read, and from a zero start
-  // value r and p of the first refinement written; recovery: x_B, t and u
-  // read, x written
-  prof_add(c, GP_KERNEL_RB_EDGE, 2.0 * R * N,
-           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + x0 * K * 2 * NB * ts +
-               R * K * 8 * (NB + 2 * NR + N) + NBt * NR * 8);
-}
-
 }  // namespace
+
+RbDev rb_dev(const gp_op* op) {
+  const RbData& d = *op->rb;
+  RbDev v;
+  std::memset(&v, 0, sizeof(v));
+  v.blk = d.blk;
+  v.red = d.red;
+  v.nbB = d.nbB;
+  v.nbR = d.nbR;
+  v.vpos = d.vpos;
+  v.D64 = d.D64;
+  v.D32 = d.D32;
+  v.S64 = d.S64;
+  v.S32 = d.S32;
+  v.P64 = d.P64;
+  v.P32 = d.P32;
+  v.tlist = d.tlist;
+  v.tbeg = d.tbeg;
+  v.nbS = d.nbS;
+  v.NB = d.NB;
+  v.NR = d.NR;
+  v.ntB = d.ntB;
+  v.ntR = d.ntR;
+  v.ntN = d.ntN;
+  v.maxRw = d.maxRw;
+  v.N = op->N;
+  v.K = op->K;
+  for (int k = 0; k < op->K; ++k) {
+    v.alpha64[k] = op->alpha[k];
+    v.alpha32[k] = (float)op->alpha[k];
+  }
+  return v;
+}
 
 void rb_release(gp_op* op) {
   if (!op->rb) return;
   for (auto& a : op->rb->allocs) dev_free(op->ctx, a.first, a.second);
-  if (op->rb->h_sts) (void)hipHostFree(op->rb->h_sts);
   if (op->rb->h_bad) (void)hipHostFree(op->rb->h_bad);
   delete op->rb;
   op->rb = nullptr;
@@ -282,149 +236,429 @@ int rb_build(gp_op* op) {
   return GP_OK;
 }
 
-int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_opts& o) {
-  const auto t0 = std::chrono::steady_clock::now();
-  long Rl = 0;
-  for (const RbItem& it : items) Rl += it.R;
-  if (Rl > 65535) return fail(GP_ERR_INVALID_ARG, "at most 65535 right-hand sides per operator with the red-black preconditioner");
-  const int R = (int)Rl;
-  if (R == 0) return GP_OK;
-  if (!op->rb || op->pc_built != GP_PRECOND_RB_IC0) return fail(GP_ERR_INVALID_ARG, "preconditioner not built");
+int rb_check_built(gp_op* op) {
   RbData& d = *op->rb;
-  const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
+  if (!d.check_bad) return GP_OK;
+  HIPTRY(hipMemcpyAsync(d.h_bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, op->ctx->stream));
+  HIPTRY(hipStreamSynchronize(op->ctx->stream));
+  d.check_bad = false;
+  if (*d.h_bad != INT_MAX) {
+    op->pc_built = -1;
+    return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(*d.h_bad) + " is not positive definite");
+  }
+  return GP_OK;
+}
+
+// ------------------------------------------------------------ members
+int rb_maxrw(const gp_op* op) { return op->rb ? op->rb->maxRw : 0; }
+
+bool rb_fusable(const gp_op* op, bool f32) {
+  return op->rb && op->rb->maxRw > 0 &&
+         (size_t)op->rb->maxRw * op->K * (f32 ? sizeof(float) : sizeof(double)) <= RB_FUSED_LDS_MAX;
+}
+
+size_t rb_member_bytes(const gp_op* op, int R, bool f32, bool fused) {
+  const RbData& d = *op->rb;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
-  const int K = op->K, ntN = d.ntN, pstride = std::max(d.ntB, 1);
-  const size_t nbv = (size_t)R * K * d.NB, nrv = (size_t)R * K * d.NR;
+  const size_t nbv = (size_t)R * op->K * d.NB, nrv = (size_t)R * op->K * d.NR;
+  const int pstride = std::max(d.ntB, 1);
+  size_t b = 0;
+  b += align_up((size_t)NPART * R * pstride * 8, 256);        // partials
+  b += align_up((size_t)R * std::max(d.ntN, 1) * 8, 256);     // ||b||^2 partials
+  b += 2 * align_up(nbv * 8, 256);                            // c64, xB
+  b += 2 * align_up(nrv * 8, 256);                            // u64, t64
+  b += 4 * align_up(nbv * tsz, 256);                          // d, r, p, q
+  if (!fused) b += align_up(nrv * tsz, 256);                  // u of the separate red stage
+  b += align_up(NPROF * sizeof(long long), 256);              // work counters
+  return b;
+}
+
+void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, const SolveCfg& cfg, bool prof,
+               RbMember* out) {
+  const RbData& d = *op->rb;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  const size_t nbv = (size_t)R * op->K * d.NB, nrv = (size_t)R * op->K * d.NR;
+  const int pstride = std::max(d.ntB, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align_up(off + std::max<size_t>(bytes, 1), 256);
+    char* at = mem + off;
+    off += align_up(std::max<size_t>(bytes, 1), 256);
     return at;
   };
-  const size_t o_st = take((size_t)R * sizeof(RhsState)), o_part = take((size_t)NPART * R * pstride * 8),
-               o_bb = take((size_t)R * std::max(ntN, 1) * 8), o_c = take(nbv * 8), o_x = take(nbv * 8),
-               o_u64 = take(nrv * 8), o_t = take(nrv * 8), o_d = take(nbv * tsz), o_r = take(nbv * tsz), o_p = take(nbv * tsz),
-               o_q = take(nbv * tsz), o_u = take(nrv * tsz), o_prof = take(NPROF * sizeof(long long));
+  RbProb& P = out->desc;
+  std::memset(&P, 0, sizeof(P));
+  P.rb = rb_dev(op);
+  P.pr.part = (double*)take((size_t)NPART * R * pstride * 8);
+  P.bb = (double*)take((size_t)R * std::max(d.ntN, 1) * 8);
+  P.c64 = (double*)take(nbv * 8);
+  P.xB = (double*)take(nbv * 8);
+  P.u64 = (double*)take(nrv * 8);
+  out->t64 = (double*)take(nrv * 8);
+  P.d = take(nbv * tsz);
+  P.r = take(nbv * tsz);
+  P.p = take(nbv * tsz);
+  P.q = take(nbv * tsz);
+  P.u = fused ? nullptr : take(nrv * tsz);
+  long long* pf = (long long*)take(NPROF * sizeof(long long));
+  out->prof = prof ? pf : nullptr;
+  P.rb.prof = out->prof;
+  P.rb.zero_start = cfg.zero_guess;
+  P.pr.prof = out->prof;
+  P.pr.st = st;
+  P.pr.R = R;
+  P.pr.pstride = pstride;
+  P.pr.cfg = cfg;
+  out->op = op;
+  out->R = R;
+}
+
+std::vector<RbGroup> rb_groups(RbProb* h, int n, bool f32, bool allow_fused, int rhs_tile) {
+  std::vector<RbGroup> gs;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  const int fpb = finalize_rhs_per_block();
+  for (int j = 0; j < n; ++j) {
+    if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0, 0, false});
+    gs.back().count += 1;
+  }
+  for (RbGroup& g : gs) {
+    // right-hand sides per inner work item: the tuned or requested value, else
+    // the largest of 8, 4, 2 that still leaves at least 1024 workgroups in the
+    // group's launch (four per compute unit)
+    int Rc = rhs_tile > 0 ? std::min(rhs_tile, RCMAX) : 1;
+    if (rhs_tile <= 0)
+      for (int cand : {8, 4, 2}) {
+        long items = 0;
+        for (int j = g.first; j < g.first + g.count; ++j)
+          items += (long)h[j].rb.ntB * ((h[j].pr.R + cand - 1) / cand);
+        if (items >= 1024) {
+          Rc = cand;
+          break;
+        }
+      }
+    int cap = 0;
+    for (int j = g.first; j < g.first + g.count; ++j) cap = std::max(cap, h[j].rb.maxRw);
+    g.cap = cap;
+    g.fused = allow_fused && cap > 0 && (size_t)cap * g.K * tsz <= RB_FUSED_LDS_MAX;
+    int F = 0;
+    for (int j = g.first; j < g.first + g.count; ++j) {
+      RbProb& P = h[j];
+      P.Rc = std::max(1, std::min(Rc, P.pr.R));
+      P.nch = (P.pr.R + P.Rc - 1) / P.Rc;
+      P.wB = g.WB;
+      g.WB += P.rb.ntB * P.nch;
+      P.wR = g.WR;
+      g.WR += P.rb.ntR * P.nch;
+      P.wO = g.WO;
+      g.WO += P.rb.ntB * P.pr.R;
+      P.pr.fin_begin = F;
+      F += (P.pr.R + fpb - 1) / fpb;
+    }
+    g.F = F;
+  }
+  return gs;
+}
+
+// ------------------------------------------------------------ rounds
+namespace {
+
+template <typename T>
+int outer_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, bool pf) {
+  PROFILED_IF(pf, c, GP_KERNEL_RB_ADDSOL, launch_rbg_addsol<T>(q, g.K, dp, g.count, g.WO));
+  PROFILED_IF(pf, c, GP_KERNEL_RB_RED64, launch_rbg_red64(q, g.K, dp, g.count, g.WR));
+  PROFILED_IF(pf, c, GP_KERNEL_RB_REFINE, launch_rbg_refine<T>(q, g.K, dp, g.count, g.WO));
+  HIPTRY(launch_rbg_finalize(q, 0, dp, g.count, g.F));
+  return GP_OK;
+}
+
+template <typename T>
+int inner_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, bool pf) {
+  if (g.fused) {
+    PROFILED_IF(pf, c, GP_KERNEL_RB_FUSED, launch_rbg_fused<T>(q, g.K, dp, g.count, g.WB, g.cap));
+  } else {
+    PROFILED_IF(pf, c, GP_KERNEL_RB_RED, launch_rbg_red<T>(q, g.K, dp, g.count, g.WR));
+    PROFILED_IF(pf, c, GP_KERNEL_RB_MATVEC, launch_rbg_matvec<T>(q, g.K, dp, g.count, g.WB));
+  }
+  HIPTRY(launch_rbg_finalize(q, 1, dp, g.count, g.F));
+  PROFILED_IF(pf, c, GP_KERNEL_RB_UPDATE, launch_rbg_update<T>(q, g.K, dp, g.count, g.WB));
+  return GP_OK;
+}
+
+// One group's round: `len` iterations, iteration i preceded by the outer step
+// when bit i of `mask` is set, and with `tail` one more outer step after the
+// last when bit len is set; len = 0: the outer step alone.  With `first` (the
+// solve's first round from a zero start value) the round's first outer step
+// is the finalisation alone: the split has taken the first refinement.
+template <typename T>
+int group_round(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, int len, uint64_t mask, bool tail,
+                bool first, bool pf) {
+  if (len == 0) {
+    if (first) {
+      HIPTRY(launch_rbg_finalize(q, 0, dp, g.count, g.F));
+      return GP_OK;
+    }
+    return outer_step<T>(c, q, g, dp, pf);
+  }
+  for (int i = 0; i < len; ++i) {
+    if (i < 64 && ((mask >> i) & 1)) {
+      if (first && i == 0) {
+        HIPTRY(launch_rbg_finalize(q, 0, dp, g.count, g.F));
+      } else if (int e = outer_step<T>(c, q, g, dp, pf)) {
+        return e;
+      }
+    }
+    if (int e = inner_step<T>(c, q, g, dp, pf)) return e;
+  }
+  if (tail && len < 64 && ((mask >> len) & 1)) return outer_step<T>(c, q, g, dp, pf);
+  return GP_OK;
+}
+
+}  // namespace
+
+int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGroup>& gs, const RbProb* d_probs,
+                     int len, uint64_t mask, bool tail, bool first, bool profiled, bool branched) {
+  const bool pf = profiled && c->prof_on;
+  auto one = [&](hipStream_t s, const RbGroup& g) -> int {
+    const RbProb* dp = d_probs + g.first;
+    return f32 ? group_round<float>(c, s, g, dp, len, mask, tail, first, pf)
+               : group_round<double>(c, s, g, dp, len, mask, tail, first, pf);
+  };
+  if (!branched || gs.size() <= 1) {
+    for (const RbGroup& g : gs)
+      if (int e = one(q, g)) return e;
+    return GP_OK;
+  }
+  // each group on a branch stream forked from q and joined back into it, so
+  // that a captured round runs the groups as parallel graph branches
+  if (int e = ensure_branches(c, gs.size())) return e;
+  HIPTRY(hipEventRecord(c->branch_ev[0], q));
+  for (size_t g = 0; g < gs.size(); ++g) {
+    hipStream_t b = c->branch[g];
+    HIPTRY(hipStreamWaitEvent(b, c->branch_ev[0], 0));
+    if (int e = one(b, gs[g])) return e;
+    HIPTRY(hipEventRecord(c->branch_ev[1 + g], b));
+  }
+  for (size_t g = 0; g < gs.size(); ++g) HIPTRY(hipStreamWaitEvent(q, c->branch_ev[1 + g], 0));
+  return GP_OK;
+}
+
+int rb_split_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, const double* b, const double* x,
+                    bool zero_guess) {
+  const RbProb& P = m.desc;
+  const int K = m.op->K, NB = P.rb.NB, NR = P.rb.NR;
+  const bool f32 = m.f32;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  RbSplitFirst first{nullptr, nullptr, P.pr.part, (size_t)P.pr.R * P.pr.pstride, P.pr.pstride, r0, f32};
+  if (zero_guess) {
+    first.r = (char*)P.r + (size_t)r0 * K * NB * tsz;
+    first.p = (char*)P.p + (size_t)r0 * K * NB * tsz;
+  }
+  if (R > 0)
+    PROFILED(c, GP_KERNEL_RB_EDGE,
+             launch_rb_split(s, P.rb, R, b, x, zero_guess ? 1 : 0, m.t64 + (size_t)r0 * K * NR,
+                             (double*)P.c64 + (size_t)r0 * K * NB, P.xB + (size_t)r0 * K * NB,
+                             (double*)P.bb + (size_t)r0 * P.rb.ntN, first));
+  return GP_OK;
+}
+
+int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x) {
+  const RbProb& P = m.desc;
+  const int K = m.op->K, NB = P.rb.NB, NR = P.rb.NR;
+  if (R > 0)
+    PROFILED(c, GP_KERNEL_RB_EDGE,
+             launch_rb_recover(s, P.rb, R, P.pr.st + r0, m.t64 + (size_t)r0 * K * NR, P.u64 + (size_t)r0 * K * NR,
+                               P.xB + (size_t)r0 * K * NB, x));
+  return GP_OK;
+}
+
+// Algorithmic HBM bytes of a member's launches, from its work counters: every
+// vector entry a launch needs read or written once (a gathered neighbour
+// vector counted once), the blocks once per launch with work.
+void rb_account(gp_ctx* c, const RbMember& m, bool fused, size_t tsz, bool zero_guess,
+                const std::vector<long long>& pf) {
+  const gp_op* op = m.op;
+  const RbData& d = *op->rb;
+  const int R = m.R;
+  const double K = op->K, NB = d.NB, NR = d.NR, N = op->N, ts = (double)tsz, NBt = K * (K + 1) / 2;
+  const double mv = (double)pf[PF_MATVEC_RHS], ref = (double)pf[PF_REFINE_RHS];
+  if (fused) {
+    // p and r read, q written at the black voxels; Q_mm and the Schur inverses
+    // at the black voxels and the red inverses once per launch with work (u
+    // stays in LDS)
+    prof_add(c, GP_KERNEL_RB_FUSED, mv * NB,
+             mv * K * 3 * NB * ts + pf[PF_MATVEC_ACT] * NBt * (2 * NB + NR) * ts);
+  } else {
+    // red stage: the black vector read, u written; the red inverses
+    prof_add(c, GP_KERNEL_RB_RED, mv * NR, mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts);
+    // black stage: p, u, r read, q written; Q_mm and the Schur inverses
+    prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
+  }
+  // the FP64 red stage on x_B for refinements from a non-zero x
+  const double ref_x = ref - (double)pf[PF_REFINE_X0];
+  prof_add(c, GP_KERNEL_RB_RED64, ref_x * NR, ref_x * K * (NB + NR) * 8 + pf[PF_REFINE_ACT] * NBt * NR * 8);
+  // p, q, r, d read (d not on the first step), d, r, p written; Schur inverses
+  const double up = (double)pf[PF_UPDATE_RHS], fresh = (double)pf[PF_UPDATE_FRESH];
+  prof_add(c, GP_KERNEL_RB_UPDATE, up * NB,
+           (up - fresh) * 7 * K * NB * ts + fresh * 6 * K * NB * ts + pf[PF_UPDATE_ACT] * NBt * NB * ts);
+  // c, x_B, u64 read, r and p written; FP64 Q_mm and the Schur inverses in
+  // the inner precision (the first step from a zero start value is the
+  // split's)
+  const double x0 = (double)pf[PF_REFINE_X0];
+  prof_add(c, GP_KERNEL_RB_REFINE, (ref - x0) * NB,
+           (ref - x0) * K * (2 * NB * 8 + NR * 8 + 2 * NB * ts) + pf[PF_REFINE_ACT] * NBt * NB * (8 + ts));
+  // x_B read (not on the first step from a zero start value) and written, d
+  // and/or the pending step's p read
+  const double ad = (double)pf[PF_ADDSOL_D], ap = (double)pf[PF_ADDSOL_P], af = (double)pf[PF_ADDSOL_FRESH];
+  const double an = std::max(std::max(ad, ap), af);
+  prof_add(c, GP_KERNEL_RB_ADDSOL, an * NB, an * K * NB * 16 - af * K * NB * 8 + (ad + ap) * K * NB * ts);
+  // split: b read, t written and read, x read and x_B written (unless the start
+  // value is zero), c written, the red inverses read, and from a zero start
+  // value r and p of the first refinement written; recovery: x_B, t and u
+  // read, x written
+  prof_add(c, GP_KERNEL_RB_EDGE, 2.0 * R * N,
+           R * K * 8 * (N + 2 * NR + (zero_guess ? 0 : 2 * NB) + NB) + x0 * K * 2 * NB * ts +
+               R * K * 8 * (NB + 2 * NR + N) + NBt * NR * 8);
+}
+
+// ------------------------------------------------------------ grouped solve
+int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opts& o) {
+  const auto t0 = std::chrono::steady_clock::now();
+  // members ordered by K (one launch group per K)
+  std::vector<const RbOpItems*> ops;
+  for (const RbOpItems& oi : ops_in) {
+    long Rl = 0;
+    for (const RbItem& it : oi.items) Rl += it.R;
+    if (Rl > 65535)
+      return fail(GP_ERR_INVALID_ARG, "at most 65535 right-hand sides per operator with the red-black preconditioner");
+    if (Rl > 0) ops.push_back(&oi);
+  }
+  if (ops.empty()) return GP_OK;
+  std::stable_sort(ops.begin(), ops.end(), [](const RbOpItems* a, const RbOpItems* b) { return a->op->K < b->op->K; });
+  for (const RbOpItems* oi : ops)
+    if (!oi->op->rb || oi->op->pc_built != GP_PRECOND_RB_IC0) return fail(GP_ERR_INVALID_ARG, "preconditioner not built");
+  const int n = (int)ops.size();
+  const bool f32 = o.precision == GP_PREC_FP32_REFINE64;
+  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
+  std::vector<int> Rm(n);
+  long totalR = 0;
+  for (int j = 0; j < n; ++j) {
+    int R = 0;
+    for (const RbItem& it : ops[j]->items) R += it.R;
+    Rm[j] = R;
+    totalR += R;
+  }
+  // a lone operator takes its tuned launch configuration (right-hand sides per
+  // work item; fused or separate red stage), if any
+  const gp_opts ot = n == 1 ? tuned_opts(c, ops[0]->op, Rm[0], o) : o;
+  const bool allow_fused = ot.matvec != GP_MATVEC_RASTER;
+  // the fused stage per K group: when every member's tile lists fit in LDS
+  std::vector<bool> fusedm(n);
+  for (int j = 0; j < n;) {
+    int e = j, cap = 0;
+    while (e < n && ops[e]->op->K == ops[j]->op->K) cap = std::max(cap, rb_maxrw(ops[e++]->op));
+    const bool f = allow_fused && cap > 0 && (size_t)cap * ops[j]->op->K * tsz <= RB_FUSED_LDS_MAX;
+    for (int k = j; k < e; ++k) fusedm[k] = f;
+    j = e;
+  }
+  // workspace: every member's states contiguous (one copy brings them all to
+  // the host), then each member's vectors
+  std::vector<size_t> at(n);
+  size_t off = align_up((size_t)totalR * sizeof(RhsState), 256);
+  for (int j = 0; j < n; ++j) {
+    at[j] = off;
+    off += rb_member_bytes(ops[j]->op, Rm[j], f32, fusedm[j]);
+  }
   if (int st = ensure_ws(c, off)) return st;
+  if (int st = ensure_rb_probs(c, n)) return st;
   char* ws = (char*)c->ws;
   hipStream_t s = c->stream;
-  RhsState* sts = (RhsState*)(ws + o_st);
-  double* part = (double*)(ws + o_part);
-  double* bb = (double*)(ws + o_bb);
-  double* c64 = (double*)(ws + o_c);
-  double* xB = (double*)(ws + o_x);
-  double* u64 = (double*)(ws + o_u64);
-  double* t64 = (double*)(ws + o_t);   // t = Q_nn^{-1} b_n of the split, kept for the recovery
-
-  long long* prof = c->prof_on ? (long long*)(ws + o_prof) : nullptr;
-  d.h.desc = rb_dev(op);
-  d.h.desc.prof = prof;
-  d.h.desc.zero_start = o.zero_guess ? 1 : 0;
-  std::memset(&d.h.prob, 0, sizeof(Prob));
-  d.h.prob.prof = prof;
-  d.h.prob.st = sts;
-  d.h.prob.part = part;
-  d.h.prob.R = R;
-  d.h.prob.pstride = pstride;
-  d.h.prob.cfg = SolveCfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
-  HIPTRY(hipMemcpyAsync(d.d_blob, &d.h, sizeof(RbData::Desc), hipMemcpyHostToDevice, s));
-  HIPTRY(hipMemsetAsync(sts, 0, (size_t)R * sizeof(RhsState), s));
-  if (prof) HIPTRY(hipMemsetAsync(prof, 0, NPROF * sizeof(long long), s));
+  RhsState* sts = (RhsState*)ws;
+  const SolveCfg cfg{o.tol, f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, o.zero_guess ? 1 : 0, 0};
+  std::vector<RbMember> mem(n);
+  {
+    long r0 = 0;
+    for (int j = 0; j < n; ++j) {
+      rb_member(ops[j]->op, Rm[j], f32, fusedm[j], ws + at[j], sts + r0, cfg, c->prof_on, &mem[j]);
+      mem[j].f32 = f32;
+      c->h_rbp[j] = mem[j].desc;
+      r0 += Rm[j];
+    }
+  }
+  std::vector<RbGroup> groups = rb_groups(c->h_rbp, n, f32, allow_fused, ot.rhs_tile);
+  for (int j = 0; j < n; ++j) mem[j].desc = c->h_rbp[j];
+  HIPTRY(hipMemcpyAsync(c->d_rbp, c->h_rbp, n * sizeof(RbProb), hipMemcpyHostToDevice, s));
+  HIPTRY(hipMemsetAsync(sts, 0, (size_t)totalR * sizeof(RhsState), s));
+  for (int j = 0; j < n; ++j)
+    if (mem[j].prof) HIPTRY(hipMemsetAsync(mem[j].prof, 0, NPROF * sizeof(long long), s));
   // per item: c = b_B - E' D_R^{-1} b_R, x_B, ||b||^2 partials, t = D_R^{-1} b_R;
   // from a zero start value also the first refinement (r = c, p = S_m^{-1} r)
-  {
-    size_t r0 = 0;
-    for (const RbItem& it : items) {
-      RbSplitFirst first{nullptr, nullptr, part, (size_t)R * pstride, pstride, (int)r0, f32};
-      if (o.zero_guess) {
-        first.r = ws + o_r + r0 * K * d.NB * tsz;
-        first.p = ws + o_p + r0 * K * d.NB * tsz;
-      }
-      if (it.R > 0)
-        PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_split(s, d.h.desc, it.R, it.b, it.x, o.zero_guess ? 1 : 0, t64 + r0 * K * d.NR,
-                                 c64 + r0 * K * d.NB, xB + r0 * K * d.NB, bb + r0 * ntN, first));
-      r0 += (size_t)it.R;
+  for (int j = 0; j < n; ++j) {
+    int r0 = 0;
+    for (const RbItem& it : ops[j]->items) {
+      if (int st = rb_split_member(c, s, mem[j], r0, it.R, it.b, it.x, o.zero_guess != 0)) return st;
+      r0 += it.R;
     }
   }
 
   const int chunk = o.chunk > 0 ? o.chunk : 8;
-  // right-hand sides per workgroup: the largest of 8, 4, 2 that still leaves
-  // at least 1024 workgroups (four per compute unit), else 1
-  int Rc = o.rhs_tile > 0 ? std::min(o.rhs_tile, RCMAX) : 1;
-  if (o.rhs_tile <= 0)
-    for (int cand : {8, 4, 2})
-      if ((long)d.ntB * ((R + cand - 1) / cand) >= 1024) {
-        Rc = cand;
-        break;
-      }
-  Rc = std::max(1, std::min(Rc, R));
-  // the FP64 refinement and x_B += d take one right-hand side per workgroup
-  // (holding the FP64 blocks across several costs the refinement occupancy);
-  // the FP64 red stage takes the inner chunks
-  const int Rco = 1;
   const bool graphs = c->use_graphs && !c->prof_on;
-  const std::string key = "rb|" + std::to_string((uintptr_t)d.d_desc) + "|" + std::to_string((uintptr_t)ws) + "|" +
-                          std::to_string(K) + "," + std::to_string(d.NB) + "," + std::to_string(d.NR) + "," +
-                          std::to_string(R) + "," + (f32 ? "f" : "d") + std::to_string(Rc);
+  std::string key = "rb|" + std::to_string((uintptr_t)c->d_rbp) + "|" + std::to_string((uintptr_t)ws) + "|" +
+                    (f32 ? "f" : "d");
+  for (const RbGroup& g : groups)
+    key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.WB) + "," +
+           std::to_string(g.WR) + "," + std::to_string(g.WO) + "," + std::to_string(g.F) + "," +
+           std::to_string(g.cap) + (g.fused ? "F" : "S");
   auto run_round = [&](int len, uint64_t mask, bool tail, bool first) -> int {
-    auto enq = [&](hipStream_t q) -> int {
-      if (f32) {
-        const Round<float> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
-                              (float*)(ws + o_d), (float*)(ws + o_r), (float*)(ws + o_p), (float*)(ws + o_q),
-                              (float*)(ws + o_u)};
-        return rd.round(q, len, mask, tail, first);
-      }
-      const Round<double> rd{c, d.h.desc, d, R, Rc, Rco, pstride, ntN, sts, part, bb, c64, xB, u64,
-                             (double*)(ws + o_d), (double*)(ws + o_r), (double*)(ws + o_p), (double*)(ws + o_q),
-                             (double*)(ws + o_u)};
-      return rd.round(q, len, mask, tail, first);
-    };
-    if (!graphs) return enq(s);
-    return graph_replay(c, key + "|" + std::to_string(len) + "/" + std::to_string(mask) + (tail ? "t" : "") +
-                               (first ? "f" : ""),
-                        enq);
+    if (!graphs) return rb_enqueue_round(c, s, f32, groups, c->d_rbp, len, mask, tail, first, true, false);
+    return graph_replay(c,
+                        key + "|" + std::to_string(len) + "/" + std::to_string(mask) + (tail ? "t" : "") +
+                            (first ? "f" : ""),
+                        [&](hipStream_t q) {
+                          return rb_enqueue_round(c, q, f32, groups, c->d_rbp, len, mask, tail, first, false, true);
+                        });
   };
 
   // rounds planned as for the main solver: the outer step first, then
   // iterations with the outer step where inner solves are expected to end
-  std::vector<RhsState> hs(R);
-  if (d.h_sts_cap < (size_t)R) {
-    if (d.h_sts) HIPTRY(hipHostFree(d.h_sts));
-    d.h_sts = nullptr;
-    d.h_sts_cap = 0;
-    HIPTRY(hipHostMalloc((void**)&d.h_sts, (size_t)R * sizeof(RhsState), hipHostMallocDefault));
-    d.h_sts_cap = (size_t)R;
-  }
-  if (!d.h_bad) HIPTRY(hipHostMalloc((void**)&d.h_bad, sizeof(int), hipHostMallocDefault));
-  int n_outer = R, n_inner = 0;
+  std::vector<RhsState> hs(totalR);
+  if (int st = ensure_rb_states(c, (size_t)totalR)) return st;
+  int n_outer = (int)totalR, n_inner = 0;
   int round_len = chunk;
   uint64_t round_mask = f32 && o.chunk > 0 ? ~0ull : 1ull;
   bool tail = false;
   const int hp = f32 ? 1 : 0;
-  if (o.chunk <= 0 && d.hist_mask[hp] && d.hist_tol[hp][0] == o.tol && d.hist_tol[hp][1] == o.inner_tol) {
-    // the previous solve's shape: its outer steps where they were taken, and
-    // the last of them (the final refinement) after the round's iterations
-    round_len = d.hist_len[hp];
-    round_mask = d.hist_mask[hp];
-    tail = true;
+  if (o.chunk <= 0) {
+    // every member's previous solve at these settings: their outer steps where
+    // they were taken, and the last of them (the final refinement) after the
+    // round's iterations
+    bool have = true;
+    uint64_t m = 0;
+    int len = 0;
+    for (const RbOpItems* oi : ops) {
+      const RbData& d = *oi->op->rb;
+      if (!d.hist_mask[hp] || d.hist_tol[hp][0] != o.tol || d.hist_tol[hp][1] != o.inner_tol) have = false;
+      m |= d.hist_mask[hp];
+      len = std::max(len, d.hist_len[hp]);
+    }
+    if (have) {
+      round_len = len;
+      round_mask = m;
+      tail = true;
+    }
   }
   const long max_rounds = (long)o.max_iter + 4L * o.max_outer + 8;
   long rounds = 0;
   // x in the caller's layout (repeated if a later round changes x_B)
   auto recover = [&]() -> int {
-    size_t r0 = 0;
-    for (const RbItem& it : items) {
-      if (it.R > 0)
-        PROFILED(c, GP_KERNEL_RB_EDGE,
-                 launch_rb_recover(s, d.h.desc, it.R, sts + r0, t64 + r0 * K * d.NR, u64 + r0 * K * d.NR,
-                                   xB + r0 * K * d.NB, it.x));
-      r0 += (size_t)it.R;
+    for (int j = 0; j < n; ++j) {
+      int r0 = 0;
+      for (const RbItem& it : ops[j]->items) {
+        if (int st = rb_recover_member(c, s, mem[j], r0, it.R, it.x)) return st;
+        r0 += it.R;
+      }
     }
     return GP_OK;
   };
   bool recovered = false;
-  int bad = INT_MAX;
   while (n_outer > 0 || n_inner > 0) {
     if (++rounds > max_rounds) return fail(GP_ERR_DEVICE, "solver driver made no progress");
     // the first round's first outer step (mask bit 0, set in every first round)
@@ -438,17 +672,24 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
       if (int st = recover()) return st;
     recovered = tail;
     tail = false;
-    HIPTRY(hipMemcpyAsync(d.h_sts, sts, (size_t)R * sizeof(RhsState), hipMemcpyDeviceToHost, s));
-    const bool check = d.check_bad;
-    if (check) HIPTRY(hipMemcpyAsync(d.h_bad, op->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPTRY(hipMemcpyAsync(c->h_rbst, sts, (size_t)totalR * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+    std::vector<int> checking;
+    for (int j = 0; j < n; ++j) {
+      RbData& d = *ops[j]->op->rb;
+      if (d.check_bad) {
+        HIPTRY(hipMemcpyAsync(d.h_bad, ops[j]->op->d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        checking.push_back(j);
+      }
+    }
     HIPTRY(hipStreamSynchronize(s));
-    std::memcpy(hs.data(), d.h_sts, (size_t)R * sizeof(RhsState));
-    if (check) bad = *d.h_bad;
-    if (check) {
+    std::memcpy(hs.data(), c->h_rbst, (size_t)totalR * sizeof(RhsState));
+    for (int j : checking) {
+      RbData& d = *ops[j]->op->rb;
       d.check_bad = false;
-      if (bad != INT_MAX) {
-        op->pc_built = -1;
-        return fail(GP_ERR_NOT_SPD, "preconditioner block of voxel " + std::to_string(bad) + " is not positive definite");
+      if (*d.h_bad != INT_MAX) {
+        ops[j]->op->pc_built = -1;
+        return fail(GP_ERR_NOT_SPD,
+                    "preconditioner block of voxel " + std::to_string(*d.h_bad) + " is not positive definite");
       }
     }
     n_outer = n_inner = 0;
@@ -462,35 +703,44 @@ int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_op
   if (!recovered)
     if (int st = recover()) return st;
   HIPTRY(hipStreamSynchronize(s));
-  if (prof) {
-    std::vector<long long> pf(NPROF);
-    HIPTRY(hipMemcpy(pf.data(), prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
-    rb_account(c, op, R, tsz, o.zero_guess != 0, pf);
+  if (c->prof_on) {
+    for (int j = 0; j < n; ++j) {
+      std::vector<long long> pf(NPROF);
+      HIPTRY(hipMemcpy(pf.data(), mem[j].prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
+      rb_account(c, mem[j], fusedm[j], tsz, o.zero_guess != 0, pf);
+    }
     if (int e = prof_resolve(c)) return e;
   }
   {
-    uint64_t m = 0;
-    for (const RhsState& h : hs) m |= h.slots;
-    int len = 0;
-    while (len < 63 && (m >> (len + 1)) != 0) ++len;
-    // a shape that reaches the last bit (outer steps after 63 or more
-    // iterations) is not replayed
-    d.hist_mask[hp] = len < 63 ? m : 0;
-    d.hist_len[hp] = len;
-    d.hist_tol[hp][0] = o.tol;
-    d.hist_tol[hp][1] = o.inner_tol;
+    long r0 = 0;
+    for (int j = 0; j < n; ++j) {
+      uint64_t m = 0;
+      for (int r = 0; r < Rm[j]; ++r) m |= hs[r0 + r].slots;
+      r0 += Rm[j];
+      int len = 0;
+      while (len < 63 && (m >> (len + 1)) != 0) ++len;
+      // a shape that reaches the last bit (outer steps after 63 or more
+      // iterations) is not replayed
+      RbData& d = *ops[j]->op->rb;
+      d.hist_mask[hp] = len < 63 ? m : 0;
+      d.hist_len[hp] = len;
+      d.hist_tol[hp][0] = o.tol;
+      d.hist_tol[hp][1] = o.inner_tol;
+    }
   }
   const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   int ret = GP_OK;
-  size_t r0 = 0;
-  for (const RbItem& it : items) {
-    for (int r = 0; r < it.R; ++r) {
-      const RhsState& h = hs[r0 + r];
-      const int status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
-      if (it.stats) it.stats[r] = gp_stats{status, h.total_it, h.outer, 0, h.relres, us};
-      if (status != GP_OK && ret == GP_OK) ret = status;
+  long r0 = 0;
+  for (int j = 0; j < n; ++j) {
+    for (const RbItem& it : ops[j]->items) {
+      for (int r = 0; r < it.R; ++r) {
+        const RhsState& h = hs[r0 + r];
+        const int status = h.phase == PH_DONE ? h.status : GP_ERR_NOT_CONVERGED;
+        if (it.stats) it.stats[r] = gp_stats{status, h.total_it, h.outer, 0, h.relres, us};
+        if (status != GP_OK && ret == GP_OK) ret = status;
+      }
+      r0 += it.R;
     }
-    r0 += (size_t)it.R;
   }
   if (ret == GP_ERR_NOT_CONVERGED) return fail(ret, "some right-hand sides did not reach the tolerance");
   if (ret == GP_ERR_BREAKDOWN) return fail(ret, "PCG breakdown (non-finite value or loss of definiteness)");

@@ -121,29 +121,57 @@ __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>&
   }
 }
 
+// Work items of a grouped solver-round launch over the members of one K group:
+// black-tile items (256 black positions, a chunk of Rc right-hand sides) for the
+// inner stages, red-tile items for the red stage, and black-tile items of one
+// right-hand side for the outer step.  A member's items are numbered tile-major
+// (the chunks of a tile adjacent, so that they share the tile's blocks) from
+// its first item, and the launch's items are dealt to the XCDs in contiguous
+// ranges, so that neighbouring tiles, whose vectors the stencil gathers, share
+// an XCD's L2.
+enum RbWhich : int { RBW_BLACK = 0, RBW_RED = 1, RBW_OUTER = 2 };
+
+struct RbWork {
+  int p, tile, r0, r1;
+  bool first;   // the member's first item (takes the profiling counts)
+};
+
+template <int WHICH>
+__device__ __forceinline__ int rb_first_item(const RbProb& P) {
+  return WHICH == RBW_BLACK ? P.wB : WHICH == RBW_RED ? P.wR : P.wO;
+}
+
+template <int WHICH>
+__device__ inline RbWork rb_item(const RbProb* __restrict__ probs, int nprob) {
+  const int wi = xcd_remap(blockIdx.x, gridDim.x);
+  int p = 0;
+  while (p + 1 < nprob && wi >= rb_first_item<WHICH>(probs[p + 1])) ++p;
+  const RbProb& P = probs[p];
+  const int loc = wi - rb_first_item<WHICH>(P);
+  const int rc = WHICH == RBW_OUTER ? 1 : P.Rc;
+  const int nch = WHICH == RBW_OUTER ? P.pr.R : P.nch;
+  RbWork w;
+  w.p = p;
+  w.tile = loc / nch;
+  w.r0 = (loc % nch) * rc;
+  w.r1 = min(P.pr.R, w.r0 + rc);
+  w.first = loc == 0;
+  return w;
+}
+
 // While profiling: one count in `slot` per launch in which some right-hand
-// side is in `phase` (the launches that move the blocks), taken by workgroup
-// 0 before any state can change.
-__device__ inline void count_launch(const RbDev& rb, const RhsState* st, int R, int phase, int slot) {
-  if (rb.prof && blockIdx.x == 0 && threadIdx.x == 0) {
-    for (int r = 0; r < R; ++r) {
-      if (st[r].phase == phase) {
-        atomicAdd((unsigned long long*)&rb.prof[slot], 1ull);
+// side of the member is in `phase` (the launches that move its blocks), taken
+// by the member's first item before any state can change.
+__device__ inline void count_launch(const RbProb& P, const RbWork& w, int phase, int slot) {
+  if (P.rb.prof && w.first && threadIdx.x == 0) {
+    for (int r = 0; r < P.pr.R; ++r) {
+      if (P.pr.st[r].phase == phase) {
+        atomicAdd((unsigned long long*)&P.rb.prof[slot], 1ull);
         break;
       }
     }
   }
 }
-
-// Work item of a solver-round launch: one tile of 256 voxels of one colour and
-// a chunk of Rc right-hand sides.  Items are numbered tile-major (the chunks of
-// a tile adjacent) and dealt to the XCDs in contiguous ranges, so that the
-// chunks of a tile, which read the same blocks, and neighbouring tiles, whose
-// vectors the stencil gathers, share an XCD's L2.
-struct RbWork {
-  int tile, r0, r1;
-};
-
 
 // Where the split writes the first refinement of a zero start value (r, p of
 // the item's right-hand sides, and the refinement partials of right-hand side
@@ -162,16 +190,6 @@ struct RbFirst {
 __device__ __forceinline__ bool refine_active(const RbDev& rb, const RhsState& s) {
   return s.phase == PH_OUTER && !(rb.zero_start && s.outer == 0);
 }
-__device__ inline RbWork rb_work(int ntiles, int R, int Rc) {
-  const int nch = (R + Rc - 1) / Rc;
-  const int wi = xcd_remap(blockIdx.x, ntiles * nch);
-  RbWork o;
-  o.tile = wi / nch;
-  o.r0 = (wi % nch) * Rc;
-  o.r1 = min(R, o.r0 + Rc);
-  return o;
-}
-
 // A voxel's packed symmetric K x K block, held in registers across the
 // right-hand sides of a work item when HOLD, else read per use.
 template <typename T, int K, bool HOLD>
@@ -417,22 +435,27 @@ __device__ __forceinline__ bool red_active(const RbDev& rb, const RhsState& s, i
   return s.phase == want && !(want == PH_OUTER && rb.zero_start && s.outer == 0);
 }
 
-// Red stage of S v for right-hand sides in phase `want`:
-// u_n = Q_nn^{-1} (alpha .* sum_{m ~ n} v_m).
-template <typename T, int K, bool HOLD>
-__global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
-                                                 int want, const T* __restrict__ v, T* __restrict__ u, int R,
-                                                 int Rc) {
-  const RbDev& rb = *rbp;
-  const RbWork w = rb_work(rb.ntR, R, Rc);
+// Red stage of S v: u_n = Q_nn^{-1} (alpha .* sum_{m ~ n} v_m) at the red voxels,
+// for the right-hand sides of an inner step (v = p, u in the inner precision)
+// or, with OUTER, of the FP64 refinement (v = x_B, u = u64; T = double).
+template <typename T, int K, bool HOLD, bool OUTER>
+__global__ __launch_bounds__(TILE) void k_rb_red(const RbProb* __restrict__ probs, int nprob) {
+  static_assert(!OUTER || sizeof(T) == 8, "the refinement's red stage is FP64");
+  const RbWork w = rb_item<RBW_RED>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
+  const int want = OUTER ? PH_OUTER : PH_INNER;
   const int j = w.tile * TILE + threadIdx.x;
   bool any = false;
   for (int r = w.r0; r < w.r1; ++r) any = any || red_active(rb, st[r], want);
   if (!any || j >= rb.NR) return;
+  const T* v = OUTER ? (const T*)P.xB : (const T*)P.p;
+  T* u = OUTER ? (T*)P.u64 : (T*)P.u;
   int nb[6];
   load_nb(rb.nbR, rb.NR, j, nb);
   const unsigned oj = (unsigned)j * (unsigned)sizeof(T);
-  const Packed<T, K, HOLD> P(RbT<T>::P(rb), rb.NR, oj);
+  const Packed<T, K, HOLD> Pn(RbT<T>::P(rb), rb.NR, oj);
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
     if (!red_active(rb, st[r], want)) continue;
@@ -444,7 +467,7 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, 
       s[k] *= RbT<T>::alpha(rb, k);
       y[k] = 0;
     }
-    sym_apply<K>(P, s, y);
+    sym_apply<K>(Pn, s, y);
     us.store(j, y);
   }
 }
@@ -454,21 +477,20 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbDev* __restrict__ rbp, 
 // p = blkdiag(S)^{-1} r in the inner precision (p only starts the next inner
 // solve); partials ||r64||^2 (slot 0) and r'p (slot 2).
 template <typename T, int K, bool HOLD>
-__global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
-                                                    const double* __restrict__ c, const double* __restrict__ xB,
-                                                    const double* __restrict__ u64, T* __restrict__ rv,
-                                                    T* __restrict__ pv, double* __restrict__ part, int R, int Rc,
-                                                    int pstride) {
-  const RbDev& rb = *rbp;
-  if (rb.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+__global__ __launch_bounds__(TILE) void k_rb_refine(const RbProb* __restrict__ probs, int nprob) {
+  const RbWork w = rb_item<RBW_OUTER>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
+  if (rb.prof && w.first && threadIdx.x == 0) {
     bool act = false;
-    for (int r = 0; r < R; ++r) act = act || refine_active(rb, st[r]);
+    for (int r = 0; r < P.pr.R; ++r) act = act || refine_active(rb, st[r]);
     if (act) atomicAdd((unsigned long long*)&rb.prof[PF_REFINE_ACT], 1ull);
   }
-  const RbWork w = rb_work(rb.ntB, R, Rc);
   bool any = false;
   for (int r = w.r0; r < w.r1; ++r) any = any || refine_active(rb, st[r]);
   if (!any) return;
+  const int R = P.pr.R, pstride = P.pr.pstride;
   const int i = w.tile * TILE + threadIdx.x;
   const bool valid = i < rb.NB;
   const int ii = valid ? i : 0;   // lanes past the end compute on voxel 0 and contribute nothing
@@ -483,8 +505,9 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     const RhsState& sr = st[r];
     if (!refine_active(rb, sr)) continue;
     const size_t off = (size_t)r * K * rb.NB;
-    const Slab<double> cs(c + off, K, rb.NB), xs(xB + off, K, rb.NB), us(u64 + (size_t)r * K * rb.NR, K, rb.NR);
-    const RbVec<T, K> rs(rv + (size_t)r * K * rb.NB, rb.NB), ps(pv + (size_t)r * K * rb.NB, rb.NB);
+    const Slab<double> cs(P.c64 + off, K, rb.NB), xs(P.xB + off, K, rb.NB),
+        us(P.u64 + (size_t)r * K * rb.NR, K, rb.NR);
+    const RbVec<T, K> rs((T*)P.r + off, rb.NB), ps((T*)P.p + off, rb.NB);
     double r64[K];
     {
       double xv[K], y[K], s[K];
@@ -517,23 +540,56 @@ __global__ __launch_bounds__(TILE) void k_rb_refine(const RbDev* __restrict__ rb
     }
     sums.add(r - w.r0, acc);
   }
-  sums.flush(part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
+  sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
 
-// Black stage of q = S p with the seven inner products of the one-reduction
-// iteration, z = blkdiag(S)^{-1} r and t = blkdiag(S)^{-1} q at the voxel:
-// p'q, r'z, q'z, q't, r'r, q'r, q'q.
+// The black stage at voxel ii for one right-hand side, given the neighbour sum
+// s = sum_{n ~ m} u_n: q = Q_mm p - alpha .* s (stored), and the seven inner
+// products of the one-reduction iteration with z = blkdiag(S)^{-1} r and
+// t = blkdiag(S)^{-1} q at the voxel: p'q, r'z, q'z, q't, r'r, q'r, q'q.
+template <typename T, int K, typename BD, typename BS>
+__device__ __forceinline__ void black_stage(const RbDev& rb, const BD& D, const BS& S, const T (&p)[K],
+                                            const T (&rr)[K], const T (&s)[K], bool valid, int ii,
+                                            const RbVec<T, K>& qs, double (&acc)[7]) {
+  T y[K], q[K], z[K], t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) y[k] = 0;
+  sym_apply<K>(D, p, y);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    q[k] = y[k] - RbT<T>::alpha(rb, k) * s[k];
+    z[k] = t[k] = 0;
+  }
+  if (valid) qs.store(ii, q);
+  sym_apply<K>(S, rr, z);
+  sym_apply<K>(S, q, t);
+  T a[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    a[0] += p[k] * q[k];
+    a[1] += rr[k] * z[k];
+    a[2] += q[k] * z[k];
+    a[3] += q[k] * t[k];
+    a[4] += rr[k] * rr[k];
+    a[5] += q[k] * rr[k];
+    a[6] += q[k] * q[k];
+  }
+#pragma unroll
+  for (int e = 0; e < 7; ++e) acc[e] = valid ? (double)a[e] : 0.0;
+}
+
+// Black stage of q = S p after a separate red stage (u read from memory).
 template <typename T, int K, bool HOLD>
-__global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
-                                                    const T* __restrict__ pv, const T* __restrict__ u,
-                                                    const T* __restrict__ rv, T* __restrict__ qv,
-                                                    double* __restrict__ part, int R, int Rc, int pstride) {
-  const RbDev& rb = *rbp;
-  count_launch(rb, st, R, PH_INNER, PF_MATVEC_ACT);
-  const RbWork w = rb_work(rb.ntB, R, Rc);
+__global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ probs, int nprob) {
+  const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
+  count_launch(P, w, PH_INNER, PF_MATVEC_ACT);
   bool any = false;
   for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
   if (!any) return;
+  const int R = P.pr.R, pstride = P.pr.pstride;
   const int i = w.tile * TILE + threadIdx.x;
   const bool valid = i < rb.NB;
   const int ii = valid ? i : 0;
@@ -546,50 +602,103 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbDev* __restrict__ rb
   for (int r = w.r0; r < w.r1; ++r) {
     if (st[r].phase != PH_INNER) continue;
     const size_t off = (size_t)r * K * rb.NB;
-    const RbVec<T, K> ps(pv + off, rb.NB), rs(rv + off, rb.NB), qs(qv + off, rb.NB);
-    const RbVec<T, K> us(u + (size_t)r * K * rb.NR, rb.NR);
-    T p[K], y[K], s[K], q[K], rr[K], z[K], t[K];
+    const RbVec<T, K> ps((const T*)P.p + off, rb.NB), rs((const T*)P.r + off, rb.NB), qs((T*)P.q + off, rb.NB);
+    const RbVec<T, K> us((const T*)P.u + (size_t)r * K * rb.NR, rb.NR);
+    T p[K], rr[K], s[K];
+    ps.load(ii, p);
+    rs.load(ii, rr);
+    neighbour_sum_v<T, K>(nb, us, s);
+    double acc[7];
+    black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qs, acc);
+    sums.add(r - w.r0, acc);
+  }
+  sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
+}
+
+// Red and black stage of q = S p fused in one workgroup per black tile: for
+// each right-hand side, the workgroup first forms u_n = Q_nn^{-1} (alpha .*
+// sum_{m ~ n} p_m) for every red voxel its tile touches (the tile's list, its
+// one-voxel halo included) into LDS ([K][cap] of T), then the black stage
+// gathers u from LDS.  u never goes through HBM; a red voxel on the boundary
+// of two tiles is formed by both.
+template <typename T, int K, bool HOLD>
+__global__ __launch_bounds__(TILE) void k_rb_fused(const RbProb* __restrict__ probs, int nprob, int cap) {
+  extern __shared__ __align__(16) unsigned char rb_lds[];
+  T* su = (T*)rb_lds;
+  const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
+  count_launch(P, w, PH_INNER, PF_MATVEC_ACT);
+  bool any = false;
+  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
+  if (!any) return;
+  const int R = P.pr.R, pstride = P.pr.pstride;
+  const int i = w.tile * TILE + threadIdx.x;
+  const bool valid = i < rb.NB;
+  const int ii = valid ? i : 0;
+  int sl[6];
+  load_nb(rb.nbS, rb.NB, ii, sl);
+  const int lb = rb.tbeg[w.tile], lc = rb.tbeg[w.tile + 1] - lb;
+  const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
+  const Packed<T, K, HOLD> D(RbT<T>::D(rb), rb.NB, oT), S(RbT<T>::S(rb), rb.NB, oT);
+  const Slab<T> Pr(RbT<T>::P(rb), Tri<K>::NB, rb.NR);
+  ItemSums<7> sums;
+#pragma unroll 1
+  for (int r = w.r0; r < w.r1; ++r) {
+    if (st[r].phase != PH_INNER) continue;   // uniform over the workgroup
+    const size_t off = (size_t)r * K * rb.NB;
+    const RbVec<T, K> ps((const T*)P.p + off, rb.NB), rs((const T*)P.r + off, rb.NB), qs((T*)P.q + off, rb.NB);
+    // red stage of the tile's list
+#pragma unroll 1
+    for (int j = threadIdx.x; j < lc; j += TILE) {
+      const int n = rb.tlist[lb + j];
+      int nb[6];
+      load_nb(rb.nbR, rb.NR, n, nb);
+      T s[K], y[K];
+      neighbour_sum_v<T, K>(nb, ps, s);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s[k] *= RbT<T>::alpha(rb, k);
+        y[k] = 0;
+      }
+      const unsigned on = (unsigned)n * (unsigned)sizeof(T);
+      sym_apply<K>([&](int e) { return Pr.ld(e, on); }, s, y);
+#pragma unroll
+      for (int k = 0; k < K; ++k) su[k * cap + j] = y[k];
+    }
+    __syncthreads();
+    // black stage, u gathered from LDS
+    T p[K], rr[K], s[K];
     ps.load(ii, p);
     rs.load(ii, rr);
 #pragma unroll
-    for (int k = 0; k < K; ++k) y[k] = 0;
-    sym_apply<K>(D, p, y);
-    neighbour_sum_v<T, K>(nb, us, s);
+    for (int k = 0; k < K; ++k) s[k] = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      q[k] = y[k] - RbT<T>::alpha(rb, k) * s[k];
-      z[k] = t[k] = 0;
-    }
-    if (valid) qs.store(ii, q);
-    sym_apply<K>(S, rr, z);
-    sym_apply<K>(S, q, t);
-    T a[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int d = 0; d < 6; ++d) {
+      const int o = sl[d] < 0 ? 0 : sl[d];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      a[0] += p[k] * q[k];
-      a[1] += rr[k] * z[k];
-      a[2] += q[k] * z[k];
-      a[3] += q[k] * t[k];
-      a[4] += rr[k] * rr[k];
-      a[5] += q[k] * rr[k];
-      a[6] += q[k] * q[k];
+      for (int k = 0; k < K; ++k) {
+        const T v = su[k * cap + o];
+        s[k] += sl[d] < 0 ? (T)0 : v;
+      }
     }
     double acc[7];
-#pragma unroll
-    for (int e = 0; e < 7; ++e) acc[e] = valid ? (double)a[e] : 0.0;
+    black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qs, acc);
     sums.add(r - w.r0, acc);
+    __syncthreads();   // the next right-hand side's red stage overwrites su
   }
-  sums.flush(part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
+  sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
 
 // d += a p (d = a p on the first step), r -= a q, p = blkdiag(S)^{-1} r + beta p.
 template <typename T, int K, bool HOLD>
-__global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
-                                                    T* __restrict__ dv, T* __restrict__ rv, T* __restrict__ pv,
-                                                    const T* __restrict__ qv, int R, int Rc) {
-  const RbDev& rb = *rbp;
-  count_launch(rb, st, R, PH_INNER, PF_UPDATE_ACT);
-  const RbWork w = rb_work(rb.ntB, R, Rc);
+__global__ __launch_bounds__(TILE) void k_rb_update(const RbProb* __restrict__ probs, int nprob) {
+  const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
+  count_launch(P, w, PH_INNER, PF_UPDATE_ACT);
   const int i = w.tile * TILE + threadIdx.x;
   bool any = false;
   for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
@@ -603,7 +712,8 @@ __global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rb
     const T a = (T)s.a, beta = (T)s.beta;
     const bool fresh = s.inner_it == 1;
     const size_t off = (size_t)r * K * rb.NB;
-    const RbVec<T, K> ds(dv + off, rb.NB), rs(rv + off, rb.NB), ps(pv + off, rb.NB), qs(qv + off, rb.NB);
+    const RbVec<T, K> ds((T*)P.d + off, rb.NB), rs((T*)P.r + off, rb.NB), ps((T*)P.p + off, rb.NB),
+        qs((T*)P.q + off, rb.NB);
     T p[K], dd[K], rn[K], q[K], z[K];
     ps.load(i, p);
     rs.load(i, rn);
@@ -633,11 +743,11 @@ __global__ __launch_bounds__(TILE) void k_rb_update(const RbDev* __restrict__ rb
 // x_B += d (when valid) + a p (when the last step is pending) for right-hand
 // sides whose inner solve has ended.
 template <typename T, int K>
-__global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rbp, const RhsState* __restrict__ st,
-                                                    double* __restrict__ xB, const T* __restrict__ dv,
-                                                    const T* __restrict__ pv, int R, int Rc) {
-  const RbDev& rb = *rbp;
-  const RbWork w = rb_work(rb.ntB, R, Rc);
+__global__ __launch_bounds__(TILE) void k_rb_addsol(const RbProb* __restrict__ probs, int nprob) {
+  const RbWork w = rb_item<RBW_OUTER>(probs, nprob);
+  const RbProb& P = probs[w.p];
+  const RbDev& rb = P.rb;
+  const RhsState* st = P.pr.st;
   const int i = w.tile * TILE + threadIdx.x;
   if (i >= rb.NB) return;
   const unsigned o8 = (unsigned)i * 8u;
@@ -649,8 +759,8 @@ __global__ __launch_bounds__(TILE) void k_rb_addsol(const RbDev* __restrict__ rb
     if (s.phase != PH_OUTER || !(s.has_d || s.pend || fresh)) continue;
     const bool hd = s.has_d != 0, hp = s.pend != 0;
     const double a = s.a;
-    const Slab<double> xs(xB + (size_t)r * K * rb.NB, K, rb.NB);
-    const RbVec<T, K> ds(dv + (size_t)r * K * rb.NB, rb.NB), ps(pv + (size_t)r * K * rb.NB, rb.NB);
+    const Slab<double> xs(P.xB + (size_t)r * K * rb.NB, K, rb.NB);
+    const RbVec<T, K> ds((const T*)P.d + (size_t)r * K * rb.NB, rb.NB), ps((const T*)P.p + (size_t)r * K * rb.NB, rb.NB);
     T dt[K], pt[K];
     double v[K];
     if (hd) ds.load(i, dt);
@@ -710,22 +820,26 @@ __global__ __launch_bounds__(TILE) void k_rb_recover(RbDev rb, const RhsState* _
   for (int k = 0; k < K; ++k) xu.st(k, on, v[k]);
 }
 
-// One wavefront per right-hand side: reduce the black tiles' partials in a
-// fixed order and advance the state with the main solver's rules.  For the
-// refinement the ||b||^2 slot comes from the split partials (ntN voxel tiles).
+// One wavefront per right-hand side of a member: reduce its black tiles'
+// partials in a fixed order and advance the state with the main solver's
+// rules.  For the refinement the ||b||^2 slot comes from the split partials
+// (ntN voxel tiles).
 template <int KIND>
-__global__ __launch_bounds__(FIN_WAVES * WAVE) void k_rb_finalize(const Prob* __restrict__ prp,
-                                                                  const double* __restrict__ bbpart, int ntB,
-                                                                  int ntN) {
-  const Prob& pr = *prp;
-  const int r = blockIdx.x * FIN_WAVES + (int)(threadIdx.x / WAVE);
+__global__ __launch_bounds__(FIN_WAVES * WAVE) void k_rb_finalize(const RbProb* __restrict__ probs, int nprob) {
+  const int b = blockIdx.x;
+  int p = 0;
+  while (p + 1 < nprob && b >= probs[p + 1].pr.fin_begin) ++p;
+  const RbProb& P = probs[p];
+  const Prob& pr = P.pr;
+  const int r = (b - pr.fin_begin) * FIN_WAVES + (int)(threadIdx.x / WAVE);
   if (r >= pr.R) return;
   if (pr.st[r].phase != (KIND == 0 ? PH_OUTER : PH_INNER)) return;
   const int lane = threadIdx.x % WAVE;
+  const int ntB = P.rb.ntB, ntN = P.rb.ntN;
   if constexpr (KIND == 0) {
     double v[3], bb[1];
     sum_partials<3>(pr.part, pr.R, pr.pstride, ntB, r, v);
-    sum_partials<1>(bbpart, 1, ntN, ntN, r, bb);
+    sum_partials<1>(P.bb, 1, ntN, ntN, r, bb);
     v[1] = bb[0];
     if (lane == 0) finalize_refine(pr, r, v);
   } else {
@@ -746,114 +860,107 @@ inline dim3 grid2(int tiles, int R) { return dim3((unsigned)tiles, (unsigned)R);
     default: return hipErrorInvalidValue;                                                            \
   }
 
-inline unsigned rb_grid(int ntiles, int R, int Rc) { return (unsigned)ntiles * (unsigned)((R + Rc - 1) / Rc); }
-
-// Launches KERN<T, KK, true> (blocks held across a work item's right-hand
-// sides) when a work item has several right-hand sides and NBLK blocks of
-// element type TB fit the register budget, else KERN<T, KK, false>; the held
-// variant is only instantiated where it can be chosen.
+// Grouped launches over the nprob members (device descriptors) of one K
+// group; W = the launch's work items.  Blocks are held in registers across a
+// work item's right-hand sides where NBLK of them fit (HoldRb).
 #define RB_HOLD_LAUNCH(KERN, KK, NBLK, TB, ...)                                  \
   do {                                                                           \
-    if constexpr (HoldRb<TB, KK, NBLK>::v) {                                     \
-      if (Rc > 1) {                                                              \
-        hipLaunchKernelGGL((KERN<T, KK, true>), __VA_ARGS__);                    \
-        break;                                                                   \
-      }                                                                          \
-    }                                                                            \
-    hipLaunchKernelGGL((KERN<T, KK, false>), __VA_ARGS__);                       \
+    if constexpr (HoldRb<TB, KK, NBLK>::v)                                       \
+      hipLaunchKernelGGL((KERN<T, KK, true>), __VA_ARGS__);                      \
+    else                                                                         \
+      hipLaunchKernelGGL((KERN<T, KK, false>), __VA_ARGS__);                     \
   } while (0)
 
 template <typename T>
-hipError_t launch_rb_red_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
-                           int want, const T* v, T* u) {
-  if (rb.ntR == 0) return hipSuccess;
-  const dim3 g(rb_grid(rb.ntR, R, Rc));
-#define X(KK)                                                                                   \
-  case KK:                                                                                      \
-    RB_HOLD_LAUNCH(k_rb_red, KK, 1, T, g, dim3(TILE), 0, s, rbd, st, want, v, u, R, Rc);         \
+hipError_t launch_rbg_red_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
+#define X(KK)                                                                                                    \
+  case KK:                                                                                                       \
+    if constexpr (HoldRb<T, KK, 1>::v)                                                                           \
+      hipLaunchKernelGGL((k_rb_red<T, KK, true, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);              \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_rb_red<T, KK, false, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);             \
     break;
-  RB_K_SWITCH(rb.K, X)
+  RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_rb_refine_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
-                              const double* c, const double* xB, const double* u64, T* r, T* p, double* part,
-                              int pstride) {
-  if (rb.ntB == 0) return hipSuccess;
-  const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK)                                                                                                 \
-  case KK:                                                                                                    \
-    RB_HOLD_LAUNCH(k_rb_refine, KK, 2, double, g, dim3(TILE), 0, s, rbd, st, c, xB, u64, r, p, part, R, Rc,    \
-                   pstride);                                                                                  \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_rb_matvec_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
-                              const T* p, const T* u, const T* r, T* q, double* part, int pstride) {
-  if (rb.ntB == 0) return hipSuccess;
-  const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK)                                                                                             \
-  case KK:                                                                                                \
-    RB_HOLD_LAUNCH(k_rb_matvec, KK, 2, T, g, dim3(TILE), 0, s, rbd, st, p, u, r, q, part, R, Rc, pstride); \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_rb_update_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
-                              T* d, T* r, T* p, const T* q) {
-  if (rb.ntB == 0) return hipSuccess;
-  const dim3 g(rb_grid(rb.ntB, R, Rc));
-#define X(KK)                                                                                 \
-  case KK:                                                                                    \
-    RB_HOLD_LAUNCH(k_rb_update, KK, 1, T, g, dim3(TILE), 0, s, rbd, st, d, r, p, q, R, Rc);    \
-    break;
-  RB_K_SWITCH(rb.K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_rb_addsol_t(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st,
-                              double* xB, const T* d, const T* p) {
-  if (rb.ntB == 0) return hipSuccess;
-  const dim3 g(rb_grid(rb.ntB, R, Rc));
+hipError_t launch_rbg_refine_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_addsol<T, KK>), g, dim3(TILE), 0, s, rbd, st, xB, d, p, R, Rc); break;
-  RB_K_SWITCH(rb.K, X)
+  case KK: RB_HOLD_LAUNCH(k_rb_refine, KK, 2, double, dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();
 }
 
-#define RB_INST(T)                                                                                           \
-  hipError_t launch_rb_red(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc, const RhsState* st, \
-                           int want, const T* v, T* u) {                                                     \
-    return launch_rb_red_t<T>(s, rb, rbd, R, Rc, st, want, v, u);                                            \
-  }                                                                                                          \
-  hipError_t launch_rb_refine(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
-                              const RhsState* st, const double* c, const double* xB, const double* u64, T* r, \
-                              T* p, double* part, int pstride) {                                             \
-    return launch_rb_refine_t<T>(s, rb, rbd, R, Rc, st, c, xB, u64, r, p, part, pstride);                    \
-  }                                                                                                          \
-  hipError_t launch_rb_matvec(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
-                              const RhsState* st, const T* p, const T* u, const T* r, T* q, double* part,     \
-                              int pstride) {                                                                 \
-    return launch_rb_matvec_t<T>(s, rb, rbd, R, Rc, st, p, u, r, q, part, pstride);                          \
-  }                                                                                                          \
-  hipError_t launch_rb_update(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
-                              const RhsState* st, T* d, T* r, T* p, const T* q) {                            \
-    return launch_rb_update_t<T>(s, rb, rbd, R, Rc, st, d, r, p, q);                                         \
-  }                                                                                                          \
-  hipError_t launch_rb_addsol(hipStream_t s, const RbDev& rb, const RbDev* rbd, int R, int Rc,               \
-                              const RhsState* st, double* xB, const T* d, const T* p) {                      \
-    return launch_rb_addsol_t<T>(s, rb, rbd, R, Rc, st, xB, d, p);                                           \
+template <typename T>
+hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
+#define X(KK) \
+  case KK: RB_HOLD_LAUNCH(k_rb_matvec, KK, 2, T, dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  RB_K_SWITCH(K, X)
+#undef X
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rbg_fused_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap) {
+  if (W == 0) return hipSuccess;
+  const size_t lds = (size_t)cap * K * sizeof(T);
+  if (cap < 1 || lds > RB_FUSED_LDS_MAX) return hipErrorInvalidValue;
+#define X(KK) \
+  case KK: RB_HOLD_LAUNCH(k_rb_fused, KK, 2, T, dim3(W), dim3(TILE), lds, s, probs, nprob, cap); break;
+  RB_K_SWITCH(K, X)
+#undef X
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rbg_update_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
+#define X(KK) \
+  case KK: RB_HOLD_LAUNCH(k_rb_update, KK, 1, T, dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  RB_K_SWITCH(K, X)
+#undef X
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rbg_addsol_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+  if (W == 0) return hipSuccess;
+#define X(KK) \
+  case KK: hipLaunchKernelGGL((k_rb_addsol<T, KK>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  RB_K_SWITCH(K, X)
+#undef X
+  return hipGetLastError();
+}
+
+#define RB_INST(T)                                                                                          \
+  template <>                                                                                               \
+  hipError_t launch_rbg_red<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {              \
+    return launch_rbg_red_t<T>(s, K, probs, nprob, W);                                                      \
+  }                                                                                                         \
+  template <>                                                                                               \
+  hipError_t launch_rbg_refine<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
+    return launch_rbg_refine_t<T>(s, K, probs, nprob, W);                                                   \
+  }                                                                                                         \
+  template <>                                                                                               \
+  hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
+    return launch_rbg_matvec_t<T>(s, K, probs, nprob, W);                                                   \
+  }                                                                                                         \
+  template <>                                                                                               \
+  hipError_t launch_rbg_fused<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap) {   \
+    return launch_rbg_fused_t<T>(s, K, probs, nprob, W, cap);                                               \
+  }                                                                                                         \
+  template <>                                                                                               \
+  hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
+    return launch_rbg_update_t<T>(s, K, probs, nprob, W);                                                   \
+  }                                                                                                         \
+  template <>                                                                                               \
+  hipError_t launch_rbg_addsol<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
+    return launch_rbg_addsol_t<T>(s, K, probs, nprob, W);                                                   \
   }
 }  // namespace gp

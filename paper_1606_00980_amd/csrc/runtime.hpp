@@ -72,6 +72,12 @@ struct gp_ctx {
   bool use_graphs = true;
   // autotuned configurations keyed by tune_key()
   std::map<std::string, TuneEntry> tuned;
+  // red-black solver: grouped-launch descriptors and a pinned copy of the states
+  gp::RbProb* d_rbp = nullptr;
+  gp::RbProb* h_rbp = nullptr;
+  size_t rbp_cap = 0;
+  gp::RhsState* h_rbst = nullptr;
+  size_t rbst_cap = 0;
 };
 
 namespace gp {
@@ -174,6 +180,10 @@ int enqueue_round(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<
 int enqueue_round_branched(gp_ctx* c, hipStream_t q, bool f32, int pc, const std::vector<LaunchGroup>& gs,
                            const Prob* d_probs, int chunk, uint64_t outer_mask);
 
+// Branch streams (and fork/join events) for capturing n launch groups as
+// parallel graph branches.
+int ensure_branches(gp_ctx* c, size_t n);
+
 // Per-launch event timing while profiling is on (gp_ctx_profile).
 int prof_begin(gp_ctx* c, size_t* slot);
 int prof_end(gp_ctx* c, int kind, size_t slot);
@@ -189,6 +199,15 @@ void prof_add(gp_ctx* c, int kind, double units, double bytes);
     if ((ctx)->prof_on) {                                            \
       if (int st_ = prof_end((ctx), (kind), slot_)) return st_;      \
     }                                                                \
+  } while (0)
+
+#define PROFILED_IF(on, ctx, kind, launch) \
+  do {                                      \
+    if (on) {                               \
+      PROFILED(ctx, kind, launch);          \
+    } else {                                \
+      HIPTRY(launch);                       \
+    }                                       \
   } while (0)
 
 int set_device(gp_ctx* c);
@@ -213,8 +232,16 @@ void plan_round(const std::vector<RhsState>& hs, const gp_opts& o, bool f32, int
 // first from enqueue(capture stream) when absent (at most 64 are kept).
 int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue);
 // Red-black incomplete Cholesky preconditioner (rbic.cpp): set-up for op, the
-// solve of R right-hand sides, and release of its data.
+// grouped solves, and release of its data.
 int rb_build(gp_op* op);
+// Reads the set-up's positive-definiteness flag if it has not been read yet
+// (waits for the stream); GP_ERR_NOT_SPD when a block failed.
+int rb_check_built(gp_op* op);
+void rb_release(gp_op* op);
+RbDev rb_dev(const gp_op* op);
+int rb_maxrw(const gp_op* op);
+// Whether op's fused red-black stage fits in LDS in the inner precision.
+bool rb_fusable(const gp_op* op, bool f32);
 // One caller batch item of an operator: R right-hand sides b, solutions x,
 // and where their statistics go.
 struct RbItem {
@@ -223,10 +250,52 @@ struct RbItem {
   double* x;
   gp_stats* stats;
 };
-// Solves every item of op in one red-black PCG run (their right-hand sides
-// stacked, at most 65535).
-int rb_solve(gp_ctx* c, gp_op* op, const std::vector<RbItem>& items, const gp_opts& o);
-void rb_release(gp_op* op);
+struct RbOpItems {
+  gp_op* op;
+  std::vector<RbItem> items;
+};
+// Solves every item of every operator together: the right-hand sides of an
+// operator stacked in one member (at most 65535), the members grouped by K,
+// one launch per group and kernel.
+int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops, const gp_opts& o);
+// A member of a grouped red-black solve: its descriptor and the buffers
+// outside it.
+struct RbMember {
+  gp_op* op = nullptr;
+  int R = 0;
+  bool f32 = true;
+  RbProb desc{};
+  double* t64 = nullptr;       // [R][K][NR] t = Q_nn^{-1} b_n of the split (for the recovery)
+  long long* prof = nullptr;   // work counters while profiling
+};
+// One launch group: members [first, first + count) of the descriptor array,
+// all with K regressors; work items of the black, red and outer launches,
+// finalising workgroups, LDS entries of the fused stage and whether it runs.
+struct RbGroup {
+  int K, first, count, WB, WR, WO, F, cap;
+  bool fused;
+};
+// Device bytes of a member's vectors and partials (states excluded).
+size_t rb_member_bytes(const gp_op* op, int R, bool f32, bool fused);
+// Lays out a member's buffers in mem (rb_member_bytes long) and fills its
+// descriptor, except the work ranges that rb_groups sets.
+void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, const SolveCfg& cfg, bool prof,
+               RbMember* out);
+// Groups the n descriptors h (sorted by K) and sets their work ranges and
+// finalisation blocks.
+std::vector<RbGroup> rb_groups(RbProb* h, int n, bool f32, bool allow_fused, int rhs_tile);
+// Enqueues one solver round (see rbic.cpp) for every group on q; with
+// `branched` each group on a branch stream forked from q and joined back.
+int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGroup>& gs, const RbProb* d_probs,
+                     int len, uint64_t mask, bool tail, bool first, bool profiled, bool branched);
+// Split of right-hand sides [r0, r0 + R) of a member (b, x in the caller's
+// layout), and the recovery of their solutions into x.
+int rb_split_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, const double* b, const double* x,
+                    bool zero_guess);
+int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x);
+// Grow the context's red-black descriptor array and pinned state copy.
+int ensure_rb_probs(gp_ctx* c, size_t n);
+int ensure_rb_states(gp_ctx* c, size_t n);
 
 }  // namespace rt
 }  // namespace gp

@@ -398,3 +398,75 @@ def test_degenerate_colourings(g, ctx, torch_cuda, precision, cells):
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,conn,K", [((29, 23, 17), 6, 3), ((37, 35, 1), 4, 2), ((21, 19, 13), 6, 10)])
+def test_fused_and_separate_red_stage_agree_bitwise(g, ctx, torch_cuda, precision, dims, conn, K):
+    """The fused red/black stage (u formed per black tile in LDS) and the
+    separate red and black launches (u through memory) do the same
+    arithmetic in the same order: bitwise equal solutions, and both match
+    the oracle's direct solve."""
+    w = synth.tiny(dims, conn, K, seed=70 + K)
+    op = make_op(g, ctx, torch_cuda, w)
+    try:
+        R, tol = 5, 1e-10
+        b = rhs(w, R, 71)
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        out = {}
+        for name, mv in (("fused", g.GP_MATVEC_AUTO), ("separate", g.GP_MATVEC_RASTER)):
+            x = torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda")
+            o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, matvec=mv, zero_guess=1)
+            _, stats = g.gp_solve(op, R, dev(torch_cuda, b), x, o)
+            assert all(s["status"] == g.GP_OK for s in stats)
+            out[name] = (x.cpu().numpy(), [(s["inner_iters"], s["outer_steps"]) for s in stats])
+        assert np.array_equal(out["fused"][0], out["separate"][0])
+        assert out["fused"][1] == out["separate"][1]
+        Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
+        ref = orc.solve_direct(Q, b)
+        for r in range(R - 1):
+            assert np.linalg.norm(out["fused"][0][r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), r
+        assert np.all(out["fused"][0][R - 1] == 0.0)
+    finally:
+        torch_cuda.cuda.synchronize()
+        g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grouped_operators_match_alone_bitwise(g, ctx, torch_cuda, precision):
+    """Five operators of three different K (two launch groups share K = 3)
+    solved in one grouped batch give bitwise the solutions each gives alone
+    (the reductions are per right-hand side and tile, whatever the company),
+    and match the oracle."""
+    ws = [synth.tiny((31, 27, 14), 6, 3, seed=81), synth.tiny((18, 16, 11), 6, 5, seed=82),
+          synth.tiny((25, 21, 12), 6, 3, seed=83), synth.tiny((44, 39, 1), 4, 2, seed=84),
+          synth.tiny((15, 14, 13), 6, 5, seed=85)]
+    ops = [make_op(g, ctx, torch_cuda, w) for w in ws]
+    try:
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        o = g.gp_opts_default(tol=1e-10, precond=g.GP_PRECOND_RB_IC0, precision=prec, zero_guess=1)
+        Rs = [3, 2, 4, 1, 2]
+        bs = [rhs(w, R, 90 + i) if R > 1 else np.random.default_rng(9).standard_normal((1, w.K, w.N))
+              for i, (w, R) in enumerate(zip(ws, Rs))]
+        alone = []
+        for op, b, R in zip(ops, bs, Rs):
+            x = torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda")
+            g.gp_solve(op, R, dev(torch_cuda, b), x, o)
+            alone.append(x.cpu().numpy())
+        xs = [torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda") for b in bs]
+        bd = [dev(torch_cuda, b) for b in bs]
+        _, stats = g.gp_solve_batch(ctx, [(op, R, b, x) for op, R, b, x in zip(ops, Rs, bd, xs)], o)
+        assert len(stats) == sum(Rs) and all(s["status"] == g.GP_OK for s in stats)
+        for i, (w, b, x, a) in enumerate(zip(ws, bs, xs, alone)):
+            xh = x.cpu().numpy()
+            assert np.array_equal(xh, a), i
+            Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
+            assert np.all(orc.relres(Q, xh, b) <= 1e-10), i
+            ref = orc.solve_direct(Q, b) if w.N * w.K <= 20000 else orc.solve(Q, b)
+            for r in range(b.shape[0]):
+                if np.any(b[r]):
+                    assert np.linalg.norm(xh[r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), (i, r)
+    finally:
+        torch_cuda.cuda.synchronize()
+        for op in ops:
+            g.gp_op_destroy(op)
