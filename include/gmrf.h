@@ -148,8 +148,7 @@ typedef struct gp_item {
 #define GP_KERNEL_RB_ADDSOL  15  /* FP64 odd-voxel solution += correction      */
 #define GP_KERNEL_RB_EDGE    16  /* split of b and x, recovery of the solution */
 #define GP_KERNEL_RB_RED64   17  /* even-voxel stage of the FP64 refinement     */
-#define GP_KERNEL_RB_FUSED   18  /* even- and odd-voxel stages of q = S p in one launch (u in LDS) */
-#define GP_KERNEL_KINDS   19
+#define GP_KERNEL_KINDS   18
 
 /* Accumulated per kernel kind while profiling is enabled.  `units` counts
  * (right-hand side, voxel) pairs processed; `bytes` is the algorithmic HBM

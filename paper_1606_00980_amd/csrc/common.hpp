@@ -108,18 +108,10 @@ struct RbDev {
   const float* S32;
   const double* P64;     // [NBt][NR] packed inverse of Q_nn (red)
   const float* P32;
-  // fused red-black stage: black tile t (256 consecutive black positions)
-  // needs u at the red positions tlist[tbeg[t] .. tbeg[t+1]); nbS[d][i] is the
-  // index in that list of black i's neighbour in direction d, or -1
-  const int* tlist;
-  const int* tbeg;       // [ntB + 1]
-  const int* nbS;        // [6][NB]
   long long* prof;       // [NPROF] work counters while profiling, else null
   int NB, NR, ntB, ntR, N, K;
   int ntN;               // tiles of 256 voxels over all N (split, recovery, ||b||^2 partials)
   int zero_start;        // the start value is zero: x is not read
-  int maxRw;             // longest tile list (u entries a fused workgroup holds)
-  int spare;
   double alpha64[KMAX];
   float alpha32[KMAX];
 };
@@ -139,7 +131,7 @@ struct RbProb {
   void* r;
   void* p;
   void* q;
-  void* u;               // [R][K][NR] red stage of an inner step (unfused)
+  void* u;               // [R][K][NR] red stage of an inner step
   int Rc, nch;           // right-hand sides per inner work item, chunks of them
   int wB, wR, wO;        // first black-tile, red-tile and outer (one right-hand side) work item
   int spare;

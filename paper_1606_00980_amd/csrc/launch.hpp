@@ -95,22 +95,17 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
                            double* t, double* c, double* xB, double* bbpart, const RbSplitFirst& first);
 // Grouped solver-round launches over the nprob members of one K group (device
 // descriptors probs, every member with K regressors); W = the launch's work
-// items: black-tile items (tiles x chunks of Rc right-hand sides) for matvec,
-// fused stage and update, red-tile items for the red stages, black-tile items
+// items: black-tile items (tiles x chunks of Rc right-hand sides) for matvec
+// and update, red-tile items for the red stages, black-tile items
 // of one right-hand side for refine and addsol.  T is the inner precision.
 template <typename T> hipError_t launch_rbg_red(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 template <typename T> hipError_t launch_rbg_matvec(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
-// red and black stage in one launch, u in LDS: cap entries of K values of T
-// per workgroup (cap >= every member's maxRw, cap * K * sizeof(T) <= RB_FUSED_LDS_MAX)
-constexpr size_t RB_FUSED_LDS_MAX = 64 * 1024;
-template <typename T> hipError_t launch_rbg_fused(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap);
 template <typename T> hipError_t launch_rbg_update(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 template <typename T> hipError_t launch_rbg_refine(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 template <typename T> hipError_t launch_rbg_addsol(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 #define GP_RBG_DECL(T)                                                                                       \
   template <> hipError_t launch_rbg_red<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);        \
   template <> hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
-  template <> hipError_t launch_rbg_fused<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap); \
   template <> hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
   template <> hipError_t launch_rbg_refine<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
   template <> hipError_t launch_rbg_addsol<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);

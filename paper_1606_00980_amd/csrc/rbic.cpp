@@ -23,9 +23,8 @@ namespace gp {
 namespace rt {
 
 struct RbData {
-  int NB = 0, NR = 0, ntB = 0, ntR = 0, ntN = 0, maxRw = 0;
+  int NB = 0, NR = 0, ntB = 0, ntR = 0, ntN = 0;
   int *blk = nullptr, *red = nullptr, *nbB = nullptr, *nbR = nullptr, *vpos = nullptr;
-  int *tlist = nullptr, *tbeg = nullptr, *nbS = nullptr;
   double *D64 = nullptr, *S64 = nullptr, *P64 = nullptr;
   float *D32 = nullptr, *S32 = nullptr, *P32 = nullptr;
   // the set-up's positive-definiteness flag has not been read yet (it is read
@@ -54,25 +53,9 @@ int rb_alloc(gp_ctx* c, RbData* d, size_t count, P** p) {
   return GP_OK;
 }
 
-// Bricks of the voxel numbering inside each colour: 8 x 8 x 8 in 3D,
-// 16 x 16 in 2D.  A black tile (256 consecutive black positions) then covers
-// a compact region, so that the red voxels it touches -- the list its fused
-// stage forms in LDS -- are few (about 1.8 per black voxel on the whole-brain
-// mask against 3.1 in raster order).
-void brick_dims(const gp_op* op, int* bx, int* by, int* bz) {
-  if (op->nz == 1) {
-    *bx = *by = 16;
-    *bz = 1;
-  } else {
-    *bx = *by = *bz = 8;
-  }
-}
-
-// Colour every voxel by the parity of x + y + z, number each colour brick by
-// brick (bricks in raster order, voxels in raster order inside a brick),
-// tabulate each voxel's neighbours by their position in the other colour, and
-// for the fused stage list, per black tile, the red positions its voxels
-// touch, with each black voxel's neighbours as indices into its tile's list.
+// Colour every voxel by the parity of x + y + z, number each colour in
+// increasing voxel order, and tabulate each voxel's neighbours by their
+// position in the other colour.
 int build_lists(gp_op* op) {
   gp_ctx* c = op->ctx;
   const int N = op->N;
@@ -80,24 +63,12 @@ int build_lists(gp_op* op) {
   HIPTRY(hipMemcpyAsync(lin.data(), op->lin, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipMemcpyAsync(nbr.data(), op->nbr, (size_t)6 * N * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPTRY(hipStreamSynchronize(c->stream));
+  std::vector<int> colour(N), pos(N), blk, red;
   const long nx = op->nx, ny = op->ny;
-  int bx, by, bz;
-  brick_dims(op, &bx, &by, &bz);
-  const long nbx = (nx + bx - 1) / bx, nby = (ny + by - 1) / by;
-  std::vector<long> key(N);
-  std::vector<int> colour(N), order(N);
   for (int n = 0; n < N; ++n) {
     const long l = lin[n];
     const long x = l % nx, y = (l / nx) % ny, z = l / (nx * ny);
     colour[n] = (int)((x + y + z) & 1);
-    key[n] = (x / bx) + nbx * ((y / by) + nby * (z / bz));
-    order[n] = n;
-  }
-  // voxel numbers increase with the linear index, so a stable sort by brick
-  // keeps raster order inside each brick
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-  std::vector<int> pos(N), blk, red;
-  for (int n : order) {
     std::vector<int>& list = colour[n] ? blk : red;
     pos[n] = (int)list.size();
     list.push_back(n);
@@ -127,31 +98,11 @@ int build_lists(gp_op* op) {
   };
   std::vector<int> nbB, nbR;
   if (!table(blk, nbB) || !table(red, nbR)) return fail(GP_ERR_INVALID_ARG, "voxel graph is not two-colourable");
-  // fused-stage lists: per black tile, its red neighbours in first-touch order
-  std::vector<int> tbeg(d->ntB + 1, 0), tlist, nbS((size_t)6 * d->NB, -1), slot(std::max(d->NR, 1), -1);
-  for (int t = 0; t < d->ntB; ++t) {
-    tbeg[t] = (int)tlist.size();
-    const int i0 = t * TILE, i1 = std::min(d->NB, i0 + TILE);
-    for (int i = i0; i < i1; ++i)
-      for (int dd = 0; dd < 6; ++dd) {
-        const int rj = nbB[(size_t)dd * d->NB + i];
-        if (rj < 0) continue;
-        if (slot[rj] < 0) {
-          slot[rj] = (int)tlist.size() - tbeg[t];
-          tlist.push_back(rj);
-        }
-        nbS[(size_t)dd * d->NB + i] = slot[rj];
-      }
-    for (size_t j = tbeg[t]; j < tlist.size(); ++j) slot[tlist[j]] = -1;
-    d->maxRw = std::max(d->maxRw, (int)tlist.size() - tbeg[t]);
-  }
-  tbeg[d->ntB] = (int)tlist.size();
   const size_t NBt = (size_t)op->K * (op->K + 1) / 2;
   int st = GP_OK;
   if ((st = rb_alloc(c, d, blk.size(), &d->blk)) || (st = rb_alloc(c, d, red.size(), &d->red)) ||
       (st = rb_alloc(c, d, nbB.size(), &d->nbB)) || (st = rb_alloc(c, d, nbR.size(), &d->nbR)) ||
-      (st = rb_alloc(c, d, vpos.size(), &d->vpos)) || (st = rb_alloc(c, d, tlist.size(), &d->tlist)) ||
-      (st = rb_alloc(c, d, tbeg.size(), &d->tbeg)) || (st = rb_alloc(c, d, nbS.size(), &d->nbS)) ||
+      (st = rb_alloc(c, d, vpos.size(), &d->vpos)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->D64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->D32)) ||
       (st = rb_alloc(c, d, NBt * d->NB, &d->S64)) || (st = rb_alloc(c, d, NBt * d->NB, &d->S32)) ||
       (st = rb_alloc(c, d, NBt * d->NR, &d->P64)) || (st = rb_alloc(c, d, NBt * d->NR, &d->P32)))
@@ -166,9 +117,6 @@ int build_lists(gp_op* op) {
   HIPTRY(up(d->nbB, nbB));
   HIPTRY(up(d->nbR, nbR));
   HIPTRY(up(d->vpos, vpos));
-  HIPTRY(up(d->tlist, tlist));
-  HIPTRY(up(d->tbeg, tbeg));
-  HIPTRY(up(d->nbS, nbS));
   HIPTRY(hipStreamSynchronize(c->stream));
   return GP_OK;
 }
@@ -190,15 +138,11 @@ RbDev rb_dev(const gp_op* op) {
   v.S32 = d.S32;
   v.P64 = d.P64;
   v.P32 = d.P32;
-  v.tlist = d.tlist;
-  v.tbeg = d.tbeg;
-  v.nbS = d.nbS;
   v.NB = d.NB;
   v.NR = d.NR;
   v.ntB = d.ntB;
   v.ntR = d.ntR;
   v.ntN = d.ntN;
-  v.maxRw = d.maxRw;
   v.N = op->N;
   v.K = op->K;
   for (int k = 0; k < op->K; ++k) {
@@ -250,14 +194,7 @@ int rb_check_built(gp_op* op) {
 }
 
 // ------------------------------------------------------------ members
-int rb_maxrw(const gp_op* op) { return op->rb ? op->rb->maxRw : 0; }
-
-bool rb_fusable(const gp_op* op, bool f32) {
-  return op->rb && op->rb->maxRw > 0 &&
-         (size_t)op->rb->maxRw * op->K * (f32 ? sizeof(float) : sizeof(double)) <= RB_FUSED_LDS_MAX;
-}
-
-size_t rb_member_bytes(const gp_op* op, int R, bool f32, bool fused) {
+size_t rb_member_bytes(const gp_op* op, int R, bool f32) {
   const RbData& d = *op->rb;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   const size_t nbv = (size_t)R * op->K * d.NB, nrv = (size_t)R * op->K * d.NR;
@@ -268,13 +205,12 @@ size_t rb_member_bytes(const gp_op* op, int R, bool f32, bool fused) {
   b += 2 * align_up(nbv * 8, 256);                            // c64, xB
   b += 2 * align_up(nrv * 8, 256);                            // u64, t64
   b += 4 * align_up(nbv * tsz, 256);                          // d, r, p, q
-  if (!fused) b += align_up(nrv * tsz, 256);                  // u of the separate red stage
+  b += align_up(nrv * tsz, 256);                              // u of the red stage
   b += align_up(NPROF * sizeof(long long), 256);              // work counters
   return b;
 }
 
-void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, const SolveCfg& cfg, bool prof,
-               RbMember* out) {
+void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveCfg& cfg, bool prof, RbMember* out) {
   const RbData& d = *op->rb;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   const size_t nbv = (size_t)R * op->K * d.NB, nrv = (size_t)R * op->K * d.NR;
@@ -298,7 +234,7 @@ void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, 
   P.r = take(nbv * tsz);
   P.p = take(nbv * tsz);
   P.q = take(nbv * tsz);
-  P.u = fused ? nullptr : take(nrv * tsz);
+  P.u = take(nrv * tsz);
   long long* pf = (long long*)take(NPROF * sizeof(long long));
   out->prof = prof ? pf : nullptr;
   P.rb.prof = out->prof;
@@ -312,12 +248,11 @@ void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, 
   out->R = R;
 }
 
-std::vector<RbGroup> rb_groups(RbProb* h, int n, bool f32, bool allow_fused, int rhs_tile) {
+std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile) {
   std::vector<RbGroup> gs;
-  const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < n; ++j) {
-    if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0, 0, false});
+    if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0});
     gs.back().count += 1;
   }
   for (RbGroup& g : gs) {
@@ -335,10 +270,6 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, bool f32, bool allow_fused, int
           break;
         }
       }
-    int cap = 0;
-    for (int j = g.first; j < g.first + g.count; ++j) cap = std::max(cap, h[j].rb.maxRw);
-    g.cap = cap;
-    g.fused = allow_fused && cap > 0 && (size_t)cap * g.K * tsz <= RB_FUSED_LDS_MAX;
     int F = 0;
     for (int j = g.first; j < g.first + g.count; ++j) {
       RbProb& P = h[j];
@@ -372,12 +303,8 @@ int outer_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, boo
 
 template <typename T>
 int inner_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, bool pf) {
-  if (g.fused) {
-    PROFILED_IF(pf, c, GP_KERNEL_RB_FUSED, launch_rbg_fused<T>(q, g.K, dp, g.count, g.WB, g.cap));
-  } else {
-    PROFILED_IF(pf, c, GP_KERNEL_RB_RED, launch_rbg_red<T>(q, g.K, dp, g.count, g.WR));
-    PROFILED_IF(pf, c, GP_KERNEL_RB_MATVEC, launch_rbg_matvec<T>(q, g.K, dp, g.count, g.WB));
-  }
+  PROFILED_IF(pf, c, GP_KERNEL_RB_RED, launch_rbg_red<T>(q, g.K, dp, g.count, g.WR));
+  PROFILED_IF(pf, c, GP_KERNEL_RB_MATVEC, launch_rbg_matvec<T>(q, g.K, dp, g.count, g.WB));
   HIPTRY(launch_rbg_finalize(q, 1, dp, g.count, g.F));
   PROFILED_IF(pf, c, GP_KERNEL_RB_UPDATE, launch_rbg_update<T>(q, g.K, dp, g.count, g.WB));
   return GP_OK;
@@ -473,25 +400,16 @@ int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R
 // Algorithmic HBM bytes of a member's launches, from its work counters: every
 // vector entry a launch needs read or written once (a gathered neighbour
 // vector counted once), the blocks once per launch with work.
-void rb_account(gp_ctx* c, const RbMember& m, bool fused, size_t tsz, bool zero_guess,
-                const std::vector<long long>& pf) {
+void rb_account(gp_ctx* c, const RbMember& m, size_t tsz, bool zero_guess, const std::vector<long long>& pf) {
   const gp_op* op = m.op;
   const RbData& d = *op->rb;
   const int R = m.R;
   const double K = op->K, NB = d.NB, NR = d.NR, N = op->N, ts = (double)tsz, NBt = K * (K + 1) / 2;
   const double mv = (double)pf[PF_MATVEC_RHS], ref = (double)pf[PF_REFINE_RHS];
-  if (fused) {
-    // p and r read, q written at the black voxels; Q_mm and the Schur inverses
-    // at the black voxels and the red inverses once per launch with work (u
-    // stays in LDS)
-    prof_add(c, GP_KERNEL_RB_FUSED, mv * NB,
-             mv * K * 3 * NB * ts + pf[PF_MATVEC_ACT] * NBt * (2 * NB + NR) * ts);
-  } else {
-    // red stage: the black vector read, u written; the red inverses
-    prof_add(c, GP_KERNEL_RB_RED, mv * NR, mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts);
-    // black stage: p, u, r read, q written; Q_mm and the Schur inverses
-    prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
-  }
+  // red stage: the black vector read, u written; the red inverses
+  prof_add(c, GP_KERNEL_RB_RED, mv * NR, mv * K * (NB + NR) * ts + pf[PF_MATVEC_ACT] * NBt * NR * ts);
+  // black stage: p, u, r read, q written; Q_mm and the Schur inverses
+  prof_add(c, GP_KERNEL_RB_MATVEC, mv * NB, mv * K * (3 * NB + NR) * ts + pf[PF_MATVEC_ACT] * 2 * NBt * NB * ts);
   // the FP64 red stage on x_B for refinements from a non-zero x
   const double ref_x = ref - (double)pf[PF_REFINE_X0];
   prof_add(c, GP_KERNEL_RB_RED64, ref_x * NR, ref_x * K * (NB + NR) * 8 + pf[PF_REFINE_ACT] * NBt * NR * 8);
@@ -546,26 +464,15 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
     Rm[j] = R;
     totalR += R;
   }
-  // a lone operator takes its tuned launch configuration (right-hand sides per
-  // work item; fused or separate red stage), if any
+  // a lone operator takes its tuned right-hand sides per work item, if any
   const gp_opts ot = n == 1 ? tuned_opts(c, ops[0]->op, Rm[0], o) : o;
-  const bool allow_fused = ot.matvec != GP_MATVEC_RASTER;
-  // the fused stage per K group: when every member's tile lists fit in LDS
-  std::vector<bool> fusedm(n);
-  for (int j = 0; j < n;) {
-    int e = j, cap = 0;
-    while (e < n && ops[e]->op->K == ops[j]->op->K) cap = std::max(cap, rb_maxrw(ops[e++]->op));
-    const bool f = allow_fused && cap > 0 && (size_t)cap * ops[j]->op->K * tsz <= RB_FUSED_LDS_MAX;
-    for (int k = j; k < e; ++k) fusedm[k] = f;
-    j = e;
-  }
   // workspace: every member's states contiguous (one copy brings them all to
   // the host), then each member's vectors
   std::vector<size_t> at(n);
   size_t off = align_up((size_t)totalR * sizeof(RhsState), 256);
   for (int j = 0; j < n; ++j) {
     at[j] = off;
-    off += rb_member_bytes(ops[j]->op, Rm[j], f32, fusedm[j]);
+    off += rb_member_bytes(ops[j]->op, Rm[j], f32);
   }
   if (int st = ensure_ws(c, off)) return st;
   if (int st = ensure_rb_probs(c, n)) return st;
@@ -577,13 +484,13 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
   {
     long r0 = 0;
     for (int j = 0; j < n; ++j) {
-      rb_member(ops[j]->op, Rm[j], f32, fusedm[j], ws + at[j], sts + r0, cfg, c->prof_on, &mem[j]);
+      rb_member(ops[j]->op, Rm[j], f32, ws + at[j], sts + r0, cfg, c->prof_on, &mem[j]);
       mem[j].f32 = f32;
       c->h_rbp[j] = mem[j].desc;
       r0 += Rm[j];
     }
   }
-  std::vector<RbGroup> groups = rb_groups(c->h_rbp, n, f32, allow_fused, ot.rhs_tile);
+  std::vector<RbGroup> groups = rb_groups(c->h_rbp, n, ot.rhs_tile);
   for (int j = 0; j < n; ++j) mem[j].desc = c->h_rbp[j];
   HIPTRY(hipMemcpyAsync(c->d_rbp, c->h_rbp, n * sizeof(RbProb), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)totalR * sizeof(RhsState), s));
@@ -605,8 +512,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
                     (f32 ? "f" : "d");
   for (const RbGroup& g : groups)
     key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.WB) + "," +
-           std::to_string(g.WR) + "," + std::to_string(g.WO) + "," + std::to_string(g.F) + "," +
-           std::to_string(g.cap) + (g.fused ? "F" : "S");
+           std::to_string(g.WR) + "," + std::to_string(g.WO) + "," + std::to_string(g.F);
   auto run_round = [&](int len, uint64_t mask, bool tail, bool first) -> int {
     if (!graphs) return rb_enqueue_round(c, s, f32, groups, c->d_rbp, len, mask, tail, first, true, false);
     return graph_replay(c,
@@ -707,7 +613,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
     for (int j = 0; j < n; ++j) {
       std::vector<long long> pf(NPROF);
       HIPTRY(hipMemcpy(pf.data(), mem[j].prof, NPROF * sizeof(long long), hipMemcpyDeviceToHost));
-      rb_account(c, mem[j], fusedm[j], tsz, o.zero_guess != 0, pf);
+      rb_account(c, mem[j], tsz, o.zero_guess != 0, pf);
     }
     if (int e = prof_resolve(c)) return e;
   }

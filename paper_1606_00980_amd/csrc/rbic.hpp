@@ -615,82 +615,6 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ p
   sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
 
-// Red and black stage of q = S p fused in one workgroup per black tile: for
-// each right-hand side, the workgroup first forms u_n = Q_nn^{-1} (alpha .*
-// sum_{m ~ n} p_m) for every red voxel its tile touches (the tile's list, its
-// one-voxel halo included) into LDS ([K][cap] of T), then the black stage
-// gathers u from LDS.  u never goes through HBM; a red voxel on the boundary
-// of two tiles is formed by both.
-template <typename T, int K, bool HOLD>
-__global__ __launch_bounds__(TILE) void k_rb_fused(const RbProb* __restrict__ probs, int nprob, int cap) {
-  extern __shared__ __align__(16) unsigned char rb_lds[];
-  T* su = (T*)rb_lds;
-  const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
-  const RbProb& P = probs[w.p];
-  const RbDev& rb = P.rb;
-  const RhsState* st = P.pr.st;
-  count_launch(P, w, PH_INNER, PF_MATVEC_ACT);
-  bool any = false;
-  for (int r = w.r0; r < w.r1; ++r) any = any || st[r].phase == PH_INNER;
-  if (!any) return;
-  const int R = P.pr.R, pstride = P.pr.pstride;
-  const int i = w.tile * TILE + threadIdx.x;
-  const bool valid = i < rb.NB;
-  const int ii = valid ? i : 0;
-  int sl[6];
-  load_nb(rb.nbS, rb.NB, ii, sl);
-  const int lb = rb.tbeg[w.tile], lc = rb.tbeg[w.tile + 1] - lb;
-  const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
-  const Packed<T, K, HOLD> D(RbT<T>::D(rb), rb.NB, oT), S(RbT<T>::S(rb), rb.NB, oT);
-  const Slab<T> Pr(RbT<T>::P(rb), Tri<K>::NB, rb.NR);
-  ItemSums<7> sums;
-#pragma unroll 1
-  for (int r = w.r0; r < w.r1; ++r) {
-    if (st[r].phase != PH_INNER) continue;   // uniform over the workgroup
-    const size_t off = (size_t)r * K * rb.NB;
-    const RbVec<T, K> ps((const T*)P.p + off, rb.NB), rs((const T*)P.r + off, rb.NB), qs((T*)P.q + off, rb.NB);
-    // red stage of the tile's list
-#pragma unroll 1
-    for (int j = threadIdx.x; j < lc; j += TILE) {
-      const int n = rb.tlist[lb + j];
-      int nb[6];
-      load_nb(rb.nbR, rb.NR, n, nb);
-      T s[K], y[K];
-      neighbour_sum_v<T, K>(nb, ps, s);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        s[k] *= RbT<T>::alpha(rb, k);
-        y[k] = 0;
-      }
-      const unsigned on = (unsigned)n * (unsigned)sizeof(T);
-      sym_apply<K>([&](int e) { return Pr.ld(e, on); }, s, y);
-#pragma unroll
-      for (int k = 0; k < K; ++k) su[k * cap + j] = y[k];
-    }
-    __syncthreads();
-    // black stage, u gathered from LDS
-    T p[K], rr[K], s[K];
-    ps.load(ii, p);
-    rs.load(ii, rr);
-#pragma unroll
-    for (int k = 0; k < K; ++k) s[k] = 0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int o = sl[d] < 0 ? 0 : sl[d];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const T v = su[k * cap + o];
-        s[k] += sl[d] < 0 ? (T)0 : v;
-      }
-    }
-    double acc[7];
-    black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qs, acc);
-    sums.add(r - w.r0, acc);
-    __syncthreads();   // the next right-hand side's red stage overwrites su
-  }
-  sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
-}
-
 // d += a p (d = a p on the first step), r -= a q, p = blkdiag(S)^{-1} r + beta p.
 template <typename T, int K, bool HOLD>
 __global__ __launch_bounds__(TILE) void k_rb_update(const RbProb* __restrict__ probs, int nprob) {
@@ -907,18 +831,6 @@ hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int np
 }
 
 template <typename T>
-hipError_t launch_rbg_fused_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap) {
-  if (W == 0) return hipSuccess;
-  const size_t lds = (size_t)cap * K * sizeof(T);
-  if (cap < 1 || lds > RB_FUSED_LDS_MAX) return hipErrorInvalidValue;
-#define X(KK) \
-  case KK: RB_HOLD_LAUNCH(k_rb_fused, KK, 2, T, dim3(W), dim3(TILE), lds, s, probs, nprob, cap); break;
-  RB_K_SWITCH(K, X)
-#undef X
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_rbg_update_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
   if (W == 0) return hipSuccess;
 #define X(KK) \
@@ -950,10 +862,6 @@ hipError_t launch_rbg_addsol_t(hipStream_t s, int K, const RbProb* probs, int np
   template <>                                                                                               \
   hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
     return launch_rbg_matvec_t<T>(s, K, probs, nprob, W);                                                   \
-  }                                                                                                         \
-  template <>                                                                                               \
-  hipError_t launch_rbg_fused<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W, int cap) {   \
-    return launch_rbg_fused_t<T>(s, K, probs, nprob, W, cap);                                               \
   }                                                                                                         \
   template <>                                                                                               \
   hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \

@@ -239,9 +239,6 @@ int rb_build(gp_op* op);
 int rb_check_built(gp_op* op);
 void rb_release(gp_op* op);
 RbDev rb_dev(const gp_op* op);
-int rb_maxrw(const gp_op* op);
-// Whether op's fused red-black stage fits in LDS in the inner precision.
-bool rb_fusable(const gp_op* op, bool f32);
 // One caller batch item of an operator: R right-hand sides b, solutions x,
 // and where their statistics go.
 struct RbItem {
@@ -269,21 +266,19 @@ struct RbMember {
   long long* prof = nullptr;   // work counters while profiling
 };
 // One launch group: members [first, first + count) of the descriptor array,
-// all with K regressors; work items of the black, red and outer launches,
-// finalising workgroups, LDS entries of the fused stage and whether it runs.
+// all with K regressors; work items of the black, red and outer launches and
+// finalising workgroups.
 struct RbGroup {
-  int K, first, count, WB, WR, WO, F, cap;
-  bool fused;
+  int K, first, count, WB, WR, WO, F;
 };
 // Device bytes of a member's vectors and partials (states excluded).
-size_t rb_member_bytes(const gp_op* op, int R, bool f32, bool fused);
+size_t rb_member_bytes(const gp_op* op, int R, bool f32);
 // Lays out a member's buffers in mem (rb_member_bytes long) and fills its
 // descriptor, except the work ranges that rb_groups sets.
-void rb_member(gp_op* op, int R, bool f32, bool fused, char* mem, RhsState* st, const SolveCfg& cfg, bool prof,
-               RbMember* out);
+void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveCfg& cfg, bool prof, RbMember* out);
 // Groups the n descriptors h (sorted by K) and sets their work ranges and
 // finalisation blocks.
-std::vector<RbGroup> rb_groups(RbProb* h, int n, bool f32, bool allow_fused, int rhs_tile);
+std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile);
 // Enqueues one solver round (see rbic.cpp) for every group on q; with
 // `branched` each group on a branch stream forked from q and joined back.
 int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGroup>& gs, const RbProb* d_probs,

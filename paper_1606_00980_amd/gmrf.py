@@ -79,7 +79,7 @@ class GpProf(ctypes.Structure):
 
 KERNEL_KINDS = ["refine", "matvec", "update", "addsol", "perturb", "precond", "pack",
                 "probe", "trace", "apply", "data", "rb_red", "rb_matvec", "rb_update", "rb_refine",
-                "rb_addsol", "rb_edge", "rb_red64", "rb_fused"]
+                "rb_addsol", "rb_edge", "rb_red64"]
 
 
 class GpItem(ctypes.Structure):

@@ -402,11 +402,11 @@ def test_degenerate_colourings(g, ctx, torch_cuda, precision, cells):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,conn,K", [((29, 23, 17), 6, 3), ((37, 35, 1), 4, 2), ((21, 19, 13), 6, 10)])
-def test_fused_and_separate_red_stage_agree_bitwise(g, ctx, torch_cuda, precision, dims, conn, K):
-    """The fused red/black stage (u formed per black tile in LDS) and the
-    separate red and black launches (u through memory) do the same
-    arithmetic in the same order: bitwise equal solutions, and both match
-    the oracle's direct solve."""
+def test_rhs_per_work_item_does_not_change_results(g, ctx, torch_cuda, precision, dims, conn, K):
+    """The work decomposition (1, 2, 4 or 8 right-hand sides per workgroup of
+    the solver-round launches) changes neither the arithmetic nor its order:
+    bitwise equal solutions and iteration counts, which match the oracle's
+    direct solve."""
     w = synth.tiny(dims, conn, K, seed=70 + K)
     op = make_op(g, ctx, torch_cuda, w)
     try:
@@ -414,19 +414,20 @@ def test_fused_and_separate_red_stage_agree_bitwise(g, ctx, torch_cuda, precisio
         b = rhs(w, R, 71)
         prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
         out = {}
-        for name, mv in (("fused", g.GP_MATVEC_AUTO), ("separate", g.GP_MATVEC_RASTER)):
+        for rt in (1, 2, 4, 8):
             x = torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda")
-            o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, matvec=mv, zero_guess=1)
+            o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, rhs_tile=rt, zero_guess=1)
             _, stats = g.gp_solve(op, R, dev(torch_cuda, b), x, o)
             assert all(s["status"] == g.GP_OK for s in stats)
-            out[name] = (x.cpu().numpy(), [(s["inner_iters"], s["outer_steps"]) for s in stats])
-        assert np.array_equal(out["fused"][0], out["separate"][0])
-        assert out["fused"][1] == out["separate"][1]
+            out[rt] = (x.cpu().numpy(), [(s["inner_iters"], s["outer_steps"]) for s in stats])
+        for rt in (2, 4, 8):
+            assert np.array_equal(out[rt][0], out[1][0]), rt
+            assert out[rt][1] == out[1][1], rt
         Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
         ref = orc.solve_direct(Q, b)
         for r in range(R - 1):
-            assert np.linalg.norm(out["fused"][0][r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), r
-        assert np.all(out["fused"][0][R - 1] == 0.0)
+            assert np.linalg.norm(out[1][0][r] - ref[r]) <= REL_ERR * np.linalg.norm(ref[r]), r
+        assert np.all(out[1][0][R - 1] == 0.0)
     finally:
         torch_cuda.cuda.synchronize()
         g.gp_op_destroy(op)
