@@ -56,6 +56,8 @@ extern "C" {
 #define GP_ERR_NOT_CONVERGED -5  /* iteration cap reached before tolerance    */
 #define GP_ERR_BREAKDOWN     -6  /* non-finite value or loss of definiteness  */
 #define GP_ERR_DEVICE        -7  /* a HIP runtime call failed                 */
+#define GP_ERR_TIMEOUT       -8  /* a served request passed its deadline      */
+#define GP_ERR_CANCELLED     -9  /* a served request was cancelled            */
 
 /* Largest number of regressors K of an operator (and of the per-regressor
  * arrays of gp_result).                                                      */
@@ -71,8 +73,7 @@ extern "C" {
  * half-size PCG on the Schur complement of the odd voxels with its diagonal
  * blocks as preconditioner; the even voxels are solved exactly from their rows
  * (start values included), so the reported residual is that of the whole
- * system.  Needs R <= 65535 per call; not available to gp_autotune or the
- * serving loop.                                                           */
+ * system.  Needs R <= 65535 per operator and call.                        */
 #define GP_PRECOND_RB_IC0        2
 
 #define GP_MATVEC_AUTO    0  /* the tuned choice, else the raster kernel        */
@@ -440,8 +441,9 @@ int gp_trace(gp_op* op, int m, const int8_t* probes, double* u, double* tr_total
 
 /* ---- autotuning -----------------------------------------------------------
  * gp_autotune: time every launch configuration (right-hand sides per
- * workgroup 1/2/4/8, persistent workgroups per compute unit 4/8, raster or
- * z-marching matvec) with full solves of R random right-hand sides on this
+ * workgroup 1/2/4/8/16, persistent workgroups per compute unit 4/8, raster or
+ * z-marching matvec; with GP_PRECOND_RB_IC0 the right-hand sides per work
+ * item alone) with full solves of R random right-hand sides on this
  * operator under *base (host; NULL = defaults), keep the fastest in the
  * context for (K, log2 N, R rounded up to a power of two, precision,
  * preconditioner) and copy it into *best (host, may be NULL).  Later solves
@@ -491,14 +493,24 @@ int gp_rng_gamma(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double s
  * server runs on its own thread and HIP stream and holds its context busy
  * until destroyed; its operators must not be modified meanwhile.  Results do
  * not depend on which other requests share a round (batch-invariant
- * reductions).
+ * reductions): a request's result is bitwise the same alone and in the mix.
+ * Every preconditioner is served (with GP_PRECOND_RB_IC0 each request is a
+ * member of the grouped red-black solve).
+ *
+ * A server round: admit waiting requests (their right-hand sides prepared on
+ * the device), run `chunk` iterations of every admitted right-hand side (the
+ * FP64 refinement step before each iteration for those waiting on it), read
+ * the states, retire finished requests.  A request that fails (breakdown,
+ * iteration cap, its deadline, cancellation, or an allocation error at
+ * admission) retires with that status alone; the others go on unchanged.
  *
  * Request kinds, all on operator `op_index` with b_w = bw[op_index]:
  *  GP_REQ_SOLVE : x = Q^{-1}(b_w + n), n = gp_rng_normal(seed, stream 4)   (R = 1)
  *  GP_REQ_SAMPLE: Algorithm 2 with z1, z2 = gp_rng_normal(seed, 1), (seed, 2)  (R = 1)
  *  GP_REQ_TRACE : Hutchinson with cfg.probes Rademacher probes
- *                 gp_rng_rademacher(seed, 3); u = Q^{-1} v                 (R = probes)
- * `out` (device FP64 [R][K][N], may be NULL) receives x, the sample or u.   */
+ *                 gp_rng_rademacher(seed, 3); u = Q^{-1} v (Section 3.3)   (R = probes)
+ * `out` (device FP64 [R][K][N], may be NULL) receives x, the sample or u; it
+ * is written only when the request succeeds.                                */
 #define GP_REQ_SOLVE  0
 #define GP_REQ_SAMPLE 1
 #define GP_REQ_TRACE  2
@@ -510,6 +522,10 @@ typedef struct gp_server_cfg {
   int     max_active_rhs;  /* right-hand-side slots advanced together (default 1024)   */
   int     chunk;           /* inner iterations per round (default 4)                  */
   int     probes;          /* probes per trace request (default 16)                   */
+  int     manual;          /* 0: rounds run as requests arrive (default); 1: a round
+                              runs only when gp_server_step grants it (deterministic
+                              schedules for replay and testing)                       */
+  int     reserved;
   gp_opts opts;            /* solver options for every request                       */
 } gp_server_cfg;
 
@@ -518,6 +534,9 @@ typedef struct gp_request {
   int      op_index;       /* index into the server's operators                      */
   uint64_t seed;           /* Philox key of the request's random vectors             */
   double*  out;            /* device result buffer or NULL                           */
+  double   timeout_ms;     /* > 0: the request fails with GP_ERR_TIMEOUT if it has not
+                              finished this long after submission (checked at round
+                              boundaries); 0: no deadline                            */
 } gp_request;
 
 typedef struct gp_result {
@@ -526,7 +545,10 @@ typedef struct gp_result {
   int      iters_max, reserved;
   double   relres_max;
   double   latency_us;     /* submit -> result available                             */
-  double   queue_us;       /* submit -> admitted                                     */
+  double   queue_us;       /* submit -> admitted (0 if never admitted)               */
+  int64_t  admit_round;    /* index of the first server round the request took part in
+                              (-1 if never admitted)                                 */
+  int64_t  retire_round;   /* number of server rounds run when it retired            */
   double   trace_total;    /* GP_REQ_TRACE: estimates as in gp_trace_reduce          */
   double   trace_kk[GP_KMAX];   /* entries k < K of the operator are set           */
   double   trace_Gkk[GP_KMAX];
@@ -534,22 +556,36 @@ typedef struct gp_result {
 
 typedef struct gp_server_stats {
   int64_t submitted, completed, rhs_solved, peak_active_rhs;
-  double  p50_us, p99_us, mean_us, max_us;  /* latency over completed requests        */
+  int64_t failed;                           /* completed with a status other than GP_OK */
+  int64_t rounds;                           /* solver rounds run                       */
+  double  p50_us, p99_us, mean_us, max_us;  /* latency over successful requests       */
   double  elapsed_s;                        /* first submit -> last completion        */
   double  solves_per_s, requests_per_s;
 } gp_server_stats;
 
 void gp_server_cfg_default(gp_server_cfg* cfg);
 /* ops: host array of nops operators of ctx (blocks and alpha set); bw: host
- * array of nops device pointers to FP64 [K][N] data right-hand sides.        */
+ * array of nops device pointers to FP64 [K][N] data right-hand sides.
+ * Builds each operator's preconditioner for cfg->opts.precond (GP_ERR_NOT_SPD
+ * if a block fails).                                                        */
 int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* const* bw,
                      const gp_server_cfg* cfg, gp_server** out);
-/* thread-safe; returns at once with a ticket (host out)                      */
+/* thread-safe; returns at once with a ticket (host out).  GP_ERR_OOM if the
+ * request alone exceeds the server's budget.                                */
 int gp_server_submit(gp_server* srv, const gp_request* req, uint64_t* ticket);
+/* thread-safe: a waiting request retires at once with GP_ERR_CANCELLED, a
+ * running one at the next round boundary; GP_ERR_INVALID_ARG if the ticket
+ * is unknown or has already finished.                                       */
+int gp_server_cancel(gp_server* srv, uint64_t ticket);
+/* manual mode only: run `rounds` more server rounds (admission, one solver
+ * round of every admitted right-hand side, retirement) and wait until they
+ * have run; a round with no admitted request does nothing and still counts. */
+int gp_server_step(gp_server* srv, int rounds);
 /* copies up to max finished results into out (host), *n receives the count  */
 int gp_server_poll(gp_server* srv, gp_result* out, int max, int* n);
 /* waits until every submitted request has finished (timeout_ms < 0: no limit);
- * GP_ERR_BUSY on timeout                                                     */
+ * GP_ERR_BUSY on timeout.  In manual mode it returns GP_ERR_BUSY at once
+ * while requests remain (rounds are the caller's).                           */
 int gp_server_drain(gp_server* srv, int timeout_ms);
 int gp_server_get_stats(gp_server* srv, gp_server_stats* out);
 int gp_server_destroy(gp_server* srv);

@@ -369,7 +369,7 @@ int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGro
 }
 
 int rb_split_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, const double* b, const double* x,
-                    bool zero_guess) {
+                    bool zero_guess, bool profiled) {
   const RbProb& P = m.desc;
   const int K = m.op->K, NB = P.rb.NB, NR = P.rb.NR;
   const bool f32 = m.f32;
@@ -380,20 +380,20 @@ int rb_split_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, 
     first.p = (char*)P.p + (size_t)r0 * K * NB * tsz;
   }
   if (R > 0)
-    PROFILED(c, GP_KERNEL_RB_EDGE,
-             launch_rb_split(s, P.rb, R, b, x, zero_guess ? 1 : 0, m.t64 + (size_t)r0 * K * NR,
-                             (double*)P.c64 + (size_t)r0 * K * NB, P.xB + (size_t)r0 * K * NB,
-                             (double*)P.bb + (size_t)r0 * P.rb.ntN, first));
+    PROFILED_IF(profiled && c->prof_on, c, GP_KERNEL_RB_EDGE,
+                launch_rb_split(s, P.rb, R, b, x, zero_guess ? 1 : 0, m.t64 + (size_t)r0 * K * NR,
+                                (double*)P.c64 + (size_t)r0 * K * NB, P.xB + (size_t)r0 * K * NB,
+                                (double*)P.bb + (size_t)r0 * P.rb.ntN, first));
   return GP_OK;
 }
 
-int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x) {
+int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x, bool profiled) {
   const RbProb& P = m.desc;
   const int K = m.op->K, NB = P.rb.NB, NR = P.rb.NR;
   if (R > 0)
-    PROFILED(c, GP_KERNEL_RB_EDGE,
-             launch_rb_recover(s, P.rb, R, P.pr.st + r0, m.t64 + (size_t)r0 * K * NR, P.u64 + (size_t)r0 * K * NR,
-                               P.xB + (size_t)r0 * K * NB, x));
+    PROFILED_IF(profiled && c->prof_on, c, GP_KERNEL_RB_EDGE,
+                launch_rb_recover(s, P.rb, R, P.pr.st + r0, m.t64 + (size_t)r0 * K * NR,
+                                  P.u64 + (size_t)r0 * K * NR, P.xB + (size_t)r0 * K * NB, x));
   return GP_OK;
 }
 
@@ -501,7 +501,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
   for (int j = 0; j < n; ++j) {
     int r0 = 0;
     for (const RbItem& it : ops[j]->items) {
-      if (int st = rb_split_member(c, s, mem[j], r0, it.R, it.b, it.x, o.zero_guess != 0)) return st;
+      if (int st = rb_split_member(c, s, mem[j], r0, it.R, it.b, it.x, o.zero_guess != 0, true)) return st;
       r0 += it.R;
     }
   }
@@ -558,7 +558,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
     for (int j = 0; j < n; ++j) {
       int r0 = 0;
       for (const RbItem& it : ops[j]->items) {
-        if (int st = rb_recover_member(c, s, mem[j], r0, it.R, it.x)) return st;
+        if (int st = rb_recover_member(c, s, mem[j], r0, it.R, it.x, true)) return st;
         r0 += it.R;
       }
     }

@@ -284,10 +284,11 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile);
 int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGroup>& gs, const RbProb* d_probs,
                      int len, uint64_t mask, bool tail, bool first, bool profiled, bool branched);
 // Split of right-hand sides [r0, r0 + R) of a member (b, x in the caller's
-// layout), and the recovery of their solutions into x.
+// layout), and the recovery of their solutions into x, on stream s (timed
+// when `profiled`, s is the context's stream and profiling is on).
 int rb_split_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, const double* b, const double* x,
-                    bool zero_guess);
-int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x);
+                    bool zero_guess, bool profiled);
+int rb_recover_member(gp_ctx* c, hipStream_t s, const RbMember& m, int r0, int R, double* x, bool profiled);
 // Grow the context's red-black descriptor array and pinned state copy.
 int ensure_rb_probs(gp_ctx* c, size_t n);
 int ensure_rb_states(gp_ctx* c, size_t n);

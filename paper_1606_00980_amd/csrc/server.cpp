@@ -1,20 +1,26 @@
 // Serving loop: resident operators, admission by HBM budget, continuous
 // batching of solve / sample / trace requests into the grouped PCG launches,
-// per-request latency.
+// per-request deadlines and cancellation, per-request latency.
 //
-// The worker thread repeats rounds.  A round admits waiting requests (FIFO,
+// The worker thread repeats rounds.  A round retires waiting requests that
+// were cancelled or passed their deadline, admits waiting requests (FIFO,
 // while the byte budget and the right-hand-side slot table allow), prepares
-// their right-hand sides on the device, rebuilds the grouped-launch
-// descriptors when the active set changed, runs one solver round of `chunk`
-// iterations (refinement steps included) for every active right-hand side, copies the
-// state table to the host and retires every request whose right-hand sides
-// are all done.  Requests therefore join and leave the running batch at
+// their right-hand sides on the device, retires running requests that were
+// cancelled or passed their deadline, rebuilds the grouped-launch descriptors
+// when the active set changed, runs one solver round of `chunk` iterations
+// (the refinement step before each) for every active right-hand side, copies
+// the state table to the host and retires every request whose right-hand
+// sides are all done.  Requests therefore join and leave the running batch at
 // round boundaries, and the kernels' batch-invariant reductions make a
-// request's result independent of its company.
+// request's result independent of its company.  A failing request (its own
+// breakdown or iteration cap, deadline, cancellation, or an allocation
+// failure at admission) retires alone with its status.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <climits>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -45,9 +51,13 @@ struct Req {
   char* mem = nullptr;      // one allocation holding every buffer below
   size_t bytes = 0;
   double *b = nullptr, *x = nullptr, *part = nullptr, *tr = nullptr;
-  void* vec[NVEC] = {};
+  void* vec[NVEC] = {};     // inner vectors (Jacobi / block Jacobi)
+  RbMember rbm;             // red-black member (GP_PRECOND_RB_IC0)
   int8_t* probes = nullptr;
-  Clock::time_point t_submit, t_admit;
+  Clock::time_point t_submit, t_admit, deadline;
+  bool has_deadline = false;
+  std::atomic<bool> cancel{false};
+  int64_t admit_round = -1;
 };
 
 double us_between(Clock::time_point a, Clock::time_point b) {
@@ -61,12 +71,12 @@ struct gp_server {
   std::vector<gp_op*> ops;
   std::vector<const double*> bw;
   gp_server_cfg cfg{};
-  bool f32 = true;
+  bool f32 = true, rb = false;
   size_t tsz = 4;
   hipStream_t stream = nullptr;
   std::thread worker;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_step;
   std::deque<Req*> pending;
   std::vector<Req*> active;
   std::deque<gp_result> finished;
@@ -74,7 +84,9 @@ struct gp_server {
   int fatal = GP_OK;
   std::string fatal_msg;
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, completed = 0, rhs_solved = 0, peak_active = 0;
+  int64_t submitted = 0, completed = 0, failed = 0, rhs_solved = 0, peak_active = 0;
+  int64_t rounds = 0;       // solver rounds run
+  int64_t credits = 0;      // manual mode: rounds granted and not yet run
   size_t bytes_in_use = 0;
   std::vector<double> latencies;
   Clock::time_point t_first{}, t_last{};
@@ -83,12 +95,15 @@ struct gp_server {
   RhsState* d_states = nullptr;
   std::vector<RhsState> h_states;
   std::vector<char> slot_used;
-  // grouped-launch descriptors
+  // grouped-launch descriptors (Jacobi / block Jacobi: Prob; red-black: RbProb)
   Prob* d_probs = nullptr;
   Prob* h_probs = nullptr;
+  RbProb* d_rbp = nullptr;
+  RbProb* h_rbp = nullptr;
   int probs_cap = 0;
   bool layout_dirty = true;
   std::vector<LaunchGroup> groups;
+  std::vector<RbGroup> rgroups;
   std::vector<Req*> order;   // active requests in descriptor order
 };
 
@@ -104,27 +119,40 @@ int find_slots(gp_server* s, int R) {
   return -1;
 }
 
+size_t trace_scratch(const gp_op* op, int R) {
+  return ((size_t)2 * R * op->K * op->ntiles + 2 * (size_t)R * op->K + 1 + 2 * KMAX) * sizeof(double);
+}
+
 size_t request_bytes(const gp_server* s, const gp_op* op, int R, int kind) {
   const size_t nv = (size_t)R * op->K * op->N;
-  const Plan pl = plan_problem(op, R, s->cfg.opts, s->ctx->cus);
   size_t b = 0;
   b += align_up(2 * nv * sizeof(double), 256);                                     // b, x
-  b += NVEC * align_up(nv * s->tsz, 256);                                          // inner vectors
-  b += align_up((size_t)NPART * R * pl.pstride * sizeof(double), 256);              // partials
+  if (s->rb) {
+    b += rb_member_bytes(op, R, s->f32);                                           // red-black member
+  } else {
+    const Plan pl = plan_problem(op, R, s->cfg.opts, s->ctx->cus);
+    b += NVEC * align_up(nv * s->tsz, 256);                                        // inner vectors
+    b += align_up((size_t)NPART * R * pl.pstride * sizeof(double), 256);            // partials
+  }
   if (kind == GP_REQ_SAMPLE) b += align_up((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double), 256);
   if (kind == GP_REQ_TRACE) {
     b += align_up(nv, 256);                                                         // probes
-    b += align_up(((size_t)2 * R * op->K * op->ntiles + 2 * (size_t)R * op->K + 1 + 2 * KMAX) * sizeof(double), 256);
+    b += align_up(trace_scratch(op, R), 256);
   }
   return b;
 }
 
-// Allocates a request's buffers and prepares its right-hand sides.
+// Allocates a request's buffers and prepares its right-hand sides.  Returns
+// GP_ERR_OOM (nothing allocated) when the device allocation fails.
 int admit(gp_server* s, Req* q) {
   hipStream_t st = s->stream;
   gp_op* op = q->op;
   const size_t nv = (size_t)q->R * op->K * op->N;
-  HIPTRY(hipMallocAsync((void**)&q->mem, q->bytes, st));
+  if (hipMallocAsync((void**)&q->mem, q->bytes, st) != hipSuccess) {
+    (void)hipGetLastError();
+    q->mem = nullptr;
+    return fail(GP_ERR_OOM, "request workspace could not be allocated");
+  }
   char* p = q->mem;
   auto take = [&](size_t n) {
     char* r = p;
@@ -133,15 +161,22 @@ int admit(gp_server* s, Req* q) {
   };
   q->b = (double*)take(2 * nv * sizeof(double));
   q->x = q->b + nv;
-  for (int v = 0; v < NVEC; ++v) q->vec[v] = take(nv * s->tsz);
-  q->part = (double*)take((size_t)NPART * q->R * plan_problem(op, q->R, s->cfg.opts, s->ctx->cus).pstride *
-                          sizeof(double));
+  const gp_opts& o = s->cfg.opts;
+  if (s->rb) {
+    char* m = p;
+    p += rb_member_bytes(op, q->R, s->f32);
+    const SolveCfg cfg{o.tol, s->f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, 1, 0};   // x starts at zero
+    rb_member(op, q->R, s->f32, m, s->d_states + q->slot0, cfg, false, &q->rbm);
+    q->rbm.f32 = s->f32;
+  } else {
+    for (int v = 0; v < NVEC; ++v) q->vec[v] = take(nv * s->tsz);
+    q->part = (double*)take((size_t)NPART * q->R * plan_problem(op, q->R, o, s->ctx->cus).pstride * sizeof(double));
+  }
   double* z = nullptr;
   if (q->r.kind == GP_REQ_SAMPLE) z = (double*)take((size_t)(op->dirs + 1) * op->K * op->N * sizeof(double));
   if (q->r.kind == GP_REQ_TRACE) {
     q->probes = (int8_t*)take(nv);
-    q->tr = (double*)take(((size_t)2 * q->R * op->K * op->ntiles + 2 * (size_t)q->R * op->K + 1 + 2 * KMAX) *
-                          sizeof(double));
+    q->tr = (double*)take(trace_scratch(op, q->R));
   }
   const OpDev d = op_dev(op);
   const size_t kn = (size_t)op->K * op->N;
@@ -163,6 +198,9 @@ int admit(gp_server* s, Req* q) {
       break;
   }
   HIPTRY(hipMemsetAsync(s->d_states + q->slot0, 0, (size_t)q->R * sizeof(RhsState), st));
+  // red-black: c = b_B - E' D_R^{-1} b_R, t, and the first refinement from zero
+  if (s->rb)
+    if (int e = rb_split_member(s->ctx, st, q->rbm, 0, q->R, q->b, nullptr, true, false)) return e;
   return GP_OK;
 }
 
@@ -171,9 +209,20 @@ int ensure_descriptors(gp_server* s, int n) {
   HIPTRY(hipStreamSynchronize(s->stream));
   if (s->d_probs) (void)hipFree(s->d_probs);
   if (s->h_probs) (void)hipHostFree(s->h_probs);
+  if (s->d_rbp) (void)hipFree(s->d_rbp);
+  if (s->h_rbp) (void)hipHostFree(s->h_rbp);
+  s->d_probs = nullptr;
+  s->h_probs = nullptr;
+  s->d_rbp = nullptr;
+  s->h_rbp = nullptr;
   s->probs_cap = std::max(n, 2 * s->probs_cap);
-  HIPTRY(hipMalloc((void**)&s->d_probs, (size_t)s->probs_cap * sizeof(Prob)));
-  HIPTRY(hipHostMalloc((void**)&s->h_probs, (size_t)s->probs_cap * sizeof(Prob), hipHostMallocDefault));
+  if (s->rb) {
+    HIPTRY(hipMalloc((void**)&s->d_rbp, (size_t)s->probs_cap * sizeof(RbProb)));
+    HIPTRY(hipHostMalloc((void**)&s->h_rbp, (size_t)s->probs_cap * sizeof(RbProb), hipHostMallocDefault));
+  } else {
+    HIPTRY(hipMalloc((void**)&s->d_probs, (size_t)s->probs_cap * sizeof(Prob)));
+    HIPTRY(hipHostMalloc((void**)&s->h_probs, (size_t)s->probs_cap * sizeof(Prob), hipHostMallocDefault));
+  }
   return GP_OK;
 }
 
@@ -181,11 +230,19 @@ int rebuild_layout(gp_server* s) {
   s->order = s->active;
   std::stable_sort(s->order.begin(), s->order.end(), [](Req* a, Req* b) { return a->op->K < b->op->K; });
   if (int st = ensure_descriptors(s, (int)s->order.size())) return st;
-  s->groups.clear();
   const gp_opts& o = s->cfg.opts;
+  const int n = (int)s->order.size();
+  if (s->rb) {
+    for (int j = 0; j < n; ++j) s->h_rbp[j] = s->order[j]->rbm.desc;
+    s->rgroups = rb_groups(s->h_rbp, n, o.rhs_tile);
+    HIPTRY(hipMemcpyAsync(s->d_rbp, s->h_rbp, (size_t)n * sizeof(RbProb), hipMemcpyHostToDevice, s->stream));
+    s->layout_dirty = false;
+    return GP_OK;
+  }
+  s->groups.clear();
   const SolveCfg cfg{o.tol, s->f32 ? o.inner_tol : 0.0, o.max_iter, o.max_outer, 1, 0};   // x starts at zero
   const int fpb = finalize_rhs_per_block();
-  for (int j = 0; j < (int)s->order.size(); ++j) {
+  for (int j = 0; j < n; ++j) {
     Req* q = s->order[j];
     Prob& p = s->h_probs[j];
     std::memset(&p, 0, sizeof(Prob));
@@ -217,7 +274,7 @@ int rebuild_layout(gp_server* s) {
     g.count += 1;
   }
   size_groups(s->groups, s->ctx->cus);
-  HIPTRY(hipMemcpyAsync(s->d_probs, s->h_probs, s->order.size() * sizeof(Prob), hipMemcpyHostToDevice, s->stream));
+  HIPTRY(hipMemcpyAsync(s->d_probs, s->h_probs, (size_t)n * sizeof(Prob), hipMemcpyHostToDevice, s->stream));
   s->layout_dirty = false;
   return GP_OK;
 }
@@ -226,24 +283,59 @@ int run_round(gp_server* s) {
   hipStream_t st = s->stream;
   const int pc = s->cfg.opts.precond;
   // requests join and finish at different times: the outer step precedes every iteration
-  if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk, s->f32 ? ~0ull : 1ull, false))
+  if (s->rb) {
+    if (int e = rb_enqueue_round(s->ctx, st, s->f32, s->rgroups, s->d_rbp, s->cfg.chunk, ~0ull, false, false, false,
+                                 false))
+      return e;
+  } else if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk,
+                                   s->f32 ? ~0ull : 1ull, false)) {
     return e;
+  }
   HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
                         hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
+  s->rounds += 1;
   return GP_OK;
 }
 
-// Finishes request q (all its right-hand sides are done): trace reduction,
-// result copy, statistics; frees its memory and slots.
-int retire(gp_server* s, Req* q, gp_result* res) {
-  hipStream_t st = s->stream;
-  gp_op* op = q->op;
+void base_result(const gp_server* s, const Req* q, gp_result* res) {
   std::memset(res, 0, sizeof(*res));
   res->ticket = q->ticket;
   res->kind = q->r.kind;
   res->op_index = q->r.op_index;
   res->rhs = q->R;
+  res->admit_round = q->admit_round;
+  res->retire_round = s->rounds;
+}
+
+// Releases a request's memory and slots (stream-ordered free).
+int release(gp_server* s, Req* q) {
+  if (q->mem) HIPTRY(hipFreeAsync(q->mem, s->stream));
+  q->mem = nullptr;
+  if (q->slot0 >= 0)
+    for (int r = 0; r < q->R; ++r) s->slot_used[q->slot0 + r] = 0;
+  return GP_OK;
+}
+
+// Finishes request q without a result (cancelled, deadline passed, or its
+// admission failed): status only, nothing is written to its output.
+int retire_failed(gp_server* s, Req* q, int status, gp_result* res) {
+  base_result(s, q, res);
+  res->status = status;
+  if (int e = release(s, q)) return e;
+  const auto now = Clock::now();
+  res->latency_us = us_between(q->t_submit, now);
+  res->queue_us = q->admit_round >= 0 ? us_between(q->t_submit, q->t_admit) : 0.0;
+  return GP_OK;
+}
+
+// Finishes request q (all its right-hand sides are done): recovery of the
+// red-black solution, trace reduction, result copy, statistics; frees its
+// memory and slots.
+int retire(gp_server* s, Req* q, gp_result* res) {
+  hipStream_t st = s->stream;
+  gp_op* op = q->op;
+  base_result(s, q, res);
   res->status = GP_OK;
   for (int r = 0; r < q->R; ++r) {
     const RhsState& h = s->h_states[q->slot0 + r];
@@ -252,36 +344,45 @@ int retire(gp_server* s, Req* q, gp_result* res) {
     res->relres_max = std::max(res->relres_max, h.relres);
   }
   const size_t nv = (size_t)q->R * op->K * op->N;
-  // x starts at zero and is first written by the first x += d: right-hand
-  // sides that ended at their first refinement (b = 0 among them) get zeros
-  const size_t nr = (size_t)op->K * op->N;
-  for (int r = 0; r < q->R; ++r) {
-    const RhsState& h = s->h_states[q->slot0 + r];
-    if (h.zero_b || h.outer <= 1) HIPTRY(hipMemsetAsync(q->x + r * nr, 0, nr * sizeof(double), st));
-  }
-  if (q->r.kind == GP_REQ_TRACE) {
-    double* part = q->tr;
-    double* pairbuf = part + (size_t)2 * q->R * op->K * op->ntiles;
-    double* out = pairbuf + (size_t)2 * q->R * op->K;
-    HIPTRY(launch_trace(st, op_dev(op), q->R, q->probes, q->x, part, pairbuf, out));
-    std::vector<double> h(1 + 2 * op->K);
-    HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    res->trace_total = h[0];
-    for (int k = 0; k < op->K; ++k) {
-      res->trace_kk[k] = h[1 + k];
-      res->trace_Gkk[k] = h[1 + op->K + k];
+  if (res->status == GP_OK) {
+    if (s->rb) {
+      // x from x_B and the red rows (zeros for b = 0 or a solve that ended
+      // at its first refinement)
+      if (int e = rb_recover_member(s->ctx, st, q->rbm, 0, q->R, q->x, false)) return e;
+    } else {
+      // x starts at zero and is first written by the first x += d: right-hand
+      // sides that ended at their first refinement (b = 0 among them) get zeros
+      const size_t nr = (size_t)op->K * op->N;
+      for (int r = 0; r < q->R; ++r) {
+        const RhsState& h = s->h_states[q->slot0 + r];
+        if (h.zero_b || h.outer <= 1) HIPTRY(hipMemsetAsync(q->x + r * nr, 0, nr * sizeof(double), st));
+      }
     }
+    if (q->r.kind == GP_REQ_TRACE) {
+      double* part = q->tr;
+      double* pairbuf = part + (size_t)2 * q->R * op->K * op->ntiles;
+      double* out = pairbuf + (size_t)2 * q->R * op->K;
+      HIPTRY(launch_trace(st, op_dev(op), q->R, q->probes, q->x, part, pairbuf, out));
+      std::vector<double> h(1 + 2 * op->K);
+      HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPTRY(hipStreamSynchronize(st));
+      res->trace_total = h[0];
+      for (int k = 0; k < op->K; ++k) {
+        res->trace_kk[k] = h[1 + k];
+        res->trace_Gkk[k] = h[1 + op->K + k];
+      }
+    }
+    if (q->r.out) HIPTRY(hipMemcpyAsync(q->r.out, q->x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  if (q->r.out) HIPTRY(hipMemcpyAsync(q->r.out, q->x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPTRY(hipFreeAsync(q->mem, st));
+  if (int e = release(s, q)) return e;
   HIPTRY(hipStreamSynchronize(st));
-  for (int r = 0; r < q->R; ++r) s->slot_used[q->slot0 + r] = 0;
   const auto now = Clock::now();
   res->latency_us = us_between(q->t_submit, now);
   res->queue_us = us_between(q->t_submit, q->t_admit);
   return GP_OK;
 }
+
+bool expired(const Req* q, Clock::time_point now) { return q->has_deadline && now >= q->deadline; }
 
 void worker_main(gp_server* s) {
   if (hipSetDevice(s->ctx->device) != hipSuccess) {
@@ -289,14 +390,29 @@ void worker_main(gp_server* s) {
     s->fatal = GP_ERR_DEVICE;
     s->fatal_msg = "server thread could not select the device";
     s->cv_done.notify_all();
+    s->cv_step.notify_all();
     return;
   }
   for (;;) {
     std::vector<Req*> admitted;
+    std::vector<std::pair<Req*, int>> dropped;   // requests that never ran, with their status
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      if (s->active.empty()) s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
-      if (s->stop && s->pending.empty() && s->active.empty()) return;
+      if (s->cfg.manual)
+        s->cv_work.wait(lk, [&] { return s->stop || s->credits > 0; });
+      else if (s->active.empty())
+        s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+      if (s->stop && (s->cfg.manual || (s->pending.empty() && s->active.empty()))) return;
+      const auto now = Clock::now();
+      for (auto it = s->pending.begin(); it != s->pending.end();) {
+        Req* q = *it;
+        if (q->cancel.load() || expired(q, now)) {
+          dropped.emplace_back(q, q->cancel.load() ? GP_ERR_CANCELLED : GP_ERR_TIMEOUT);
+          it = s->pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
       while (!s->pending.empty()) {
         Req* q = s->pending.front();
         if (s->bytes_in_use + q->bytes > s->cfg.hbm_budget) break;
@@ -310,11 +426,48 @@ void worker_main(gp_server* s) {
       }
     }
     int err = GP_OK;
-    for (Req* q : admitted) {
+    std::vector<gp_result> done;
+    for (auto& qd : dropped) {
+      gp_result res;
+      if ((err = retire_failed(s, qd.first, qd.second, &res)) != GP_OK) break;
+      done.push_back(res);
+      delete qd.first;
+    }
+    std::vector<Req*> freed;   // requests whose bytes leave the budget
+    for (size_t i = 0; i < admitted.size() && err == GP_OK; ++i) {
+      Req* q = admitted[i];
       q->t_admit = Clock::now();
-      if ((err = admit(s, q)) != GP_OK) break;
-      s->active.push_back(q);
-      s->layout_dirty = true;
+      q->admit_round = s->rounds;
+      const int st = admit(s, q);
+      if (st == GP_OK) {
+        s->active.push_back(q);
+        s->layout_dirty = true;
+      } else if (st == GP_ERR_OOM) {
+        gp_result res;
+        q->admit_round = -1;
+        if ((err = retire_failed(s, q, GP_ERR_OOM, &res)) != GP_OK) break;
+        done.push_back(res);
+        freed.push_back(q);
+      } else {
+        err = st;
+      }
+    }
+    // running requests cancelled or past their deadline leave at this boundary
+    if (err == GP_OK) {
+      const auto now = Clock::now();
+      std::vector<Req*> keep;
+      for (Req* q : s->active) {
+        if (err == GP_OK && (q->cancel.load() || expired(q, now))) {
+          gp_result res;
+          if ((err = retire_failed(s, q, q->cancel.load() ? GP_ERR_CANCELLED : GP_ERR_TIMEOUT, &res)) != GP_OK) break;
+          done.push_back(res);
+          freed.push_back(q);
+          s->layout_dirty = true;
+        } else {
+          keep.push_back(q);
+        }
+      }
+      if (err == GP_OK) s->active.swap(keep);
     }
     int64_t live = 0;
     for (Req* q : s->active) live += q->R;
@@ -323,7 +476,6 @@ void worker_main(gp_server* s) {
       if (s->layout_dirty) err = rebuild_layout(s);
       if (err == GP_OK) err = run_round(s);
     }
-    std::vector<gp_result> done;
     if (err == GP_OK) {
       std::vector<Req*> still;
       for (Req* q : s->active) {
@@ -336,14 +488,18 @@ void worker_main(gp_server* s) {
         gp_result res;
         if ((err = retire(s, q, &res)) != GP_OK) break;
         done.push_back(res);
+        freed.push_back(q);
         s->layout_dirty = true;
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->bytes_in_use -= q->bytes;
-        delete q;
       }
       if (err == GP_OK) s->active.swap(still);
     }
     std::lock_guard<std::mutex> lk(s->mu);
+    for (Req* q : freed) {
+      s->bytes_in_use -= q->bytes;
+      delete q;
+    }
+    if (s->cfg.manual && s->credits > 0) s->credits -= 1;
+    s->cv_step.notify_all();
     if (err != GP_OK) {
       s->fatal = err;
       s->fatal_msg = gp_last_error();
@@ -352,9 +508,13 @@ void worker_main(gp_server* s) {
       return;
     }
     for (gp_result& r : done) {
-      s->latencies.push_back(r.latency_us);
+      if (r.status == GP_OK) {
+        s->latencies.push_back(r.latency_us);
+        s->rhs_solved += r.rhs;
+      } else {
+        s->failed += 1;
+      }
       s->completed += 1;
-      s->rhs_solved += r.rhs;
       s->finished.push_back(r);
       s->t_last = Clock::now();
     }
@@ -385,13 +545,15 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
   if (cfg) c = *cfg; else gp_server_cfg_default(&c);
   std::string why;
   if (!valid_opts(c.opts, &why)) return fail(GP_ERR_INVALID_ARG, why);
-  if (c.opts.precond == GP_PRECOND_RB_IC0)
-    return fail(GP_ERR_INVALID_ARG, "the serving loop supports the Jacobi and block-Jacobi preconditioners");
   if (c.max_active_rhs < 1 || c.chunk < 1 || c.probes < 1 || c.probes > c.max_active_rhs)
     return fail(GP_ERR_INVALID_ARG, "max_active_rhs >= 1, chunk >= 1 and 1 <= probes <= max_active_rhs required");
+  if (c.opts.precond == GP_PRECOND_RB_IC0 && c.probes > 65535)
+    return fail(GP_ERR_INVALID_ARG, "at most 65535 probes per trace request with the red-black preconditioner");
+  if (c.manual != 0 && c.manual != 1) return fail(GP_ERR_INVALID_ARG, "manual must be 0 or 1");
   for (int i = 0; i < nops; ++i) {
     if (!ops[i] || ops[i]->ctx != ctx || !bw[i]) return fail(GP_ERR_INVALID_ARG, "operator or b_w missing");
     if (!ops[i]->have_blocks || !ops[i]->have_alpha) return fail(GP_ERR_INVALID_ARG, "operator needs blocks and alpha");
+    if (ops[i]->K < 1 || ops[i]->K > KMAX) return fail(GP_ERR_INVALID_ARG, "operator K out of range");
   }
   int expect = 0;
   if (!ctx->busy.compare_exchange_strong(expect, 1)) return fail(GP_ERR_BUSY, "context busy");
@@ -399,6 +561,7 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
   s->ctx = ctx;
   s->cfg = c;
   s->f32 = c.opts.precision == GP_PREC_FP32_REFINE64;
+  s->rb = c.opts.precond == GP_PRECOND_RB_IC0;
   s->tsz = s->f32 ? sizeof(float) : sizeof(double);
   s->ops.assign(ops, ops + nops);
   s->bw.assign(bw, bw + nops);
@@ -412,9 +575,12 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
     return st;
   };
   if (int st = set_device(ctx)) return bail(st);
-  for (gp_op* op : s->ops)
+  for (gp_op* op : s->ops) {
     if (op->pc_built != c.opts.precond)
       if (int st = build_precond(op, c.opts.precond)) return bail(st);
+    if (s->rb)
+      if (int st = rb_check_built(op)) return bail(st);
+  }
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(GP_ERR_DEVICE, "could not create the server stream"));
   if (hipMalloc((void**)&s->d_states, (size_t)c.max_active_rhs * sizeof(RhsState)) != hipSuccess)
@@ -434,6 +600,7 @@ int gp_server_submit(gp_server* s, const gp_request* req, uint64_t* ticket) {
   if (!s || !req) return fail(GP_ERR_INVALID_ARG, "server or request is NULL");
   if (req->kind < GP_REQ_SOLVE || req->kind > GP_REQ_TRACE) return fail(GP_ERR_INVALID_ARG, "unknown request kind");
   if (req->op_index < 0 || req->op_index >= (int)s->ops.size()) return fail(GP_ERR_INVALID_ARG, "op_index out of range");
+  if (!(req->timeout_ms >= 0.0)) return fail(GP_ERR_INVALID_ARG, "timeout_ms must be >= 0");
   Req* q = new Req();
   q->r = *req;
   q->op = s->ops[req->op_index];
@@ -445,6 +612,11 @@ int gp_server_submit(gp_server* s, const gp_request* req, uint64_t* ticket) {
     return fail(GP_ERR_OOM, "request needs more memory than the server's budget");
   }
   q->t_submit = Clock::now();
+  if (req->timeout_ms > 0.0) {
+    q->has_deadline = true;
+    q->deadline = q->t_submit + std::chrono::duration_cast<Clock::duration>(
+                                    std::chrono::duration<double, std::milli>(req->timeout_ms));
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->fatal != GP_OK) {
     delete q;
@@ -466,6 +638,38 @@ int gp_server_submit(gp_server* s, const gp_request* req, uint64_t* ticket) {
   return GP_OK;
 }
 
+int gp_server_cancel(gp_server* s, uint64_t ticket) {
+  if (!s) return fail(GP_ERR_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (Req* q : s->pending)
+    if (q->ticket == ticket) {
+      q->cancel.store(true);
+      s->cv_work.notify_one();
+      return GP_OK;
+    }
+  // the active list is the worker's; a flag set under the lock is read at the
+  // next round boundary
+  for (Req* q : s->active)
+    if (q->ticket == ticket) {
+      q->cancel.store(true);
+      return GP_OK;
+    }
+  return fail(GP_ERR_INVALID_ARG, "unknown or finished ticket");
+}
+
+int gp_server_step(gp_server* s, int rounds) {
+  if (!s) return fail(GP_ERR_INVALID_ARG, "server is NULL");
+  if (!s->cfg.manual) return fail(GP_ERR_INVALID_ARG, "gp_server_step needs a server created with manual = 1");
+  if (rounds < 0) return fail(GP_ERR_INVALID_ARG, "rounds must be >= 0");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->fatal != GP_OK) return fail(s->fatal, "server stopped: " + s->fatal_msg);
+  s->credits += rounds;
+  s->cv_work.notify_one();
+  s->cv_step.wait(lk, [&] { return s->credits == 0 || s->fatal != GP_OK || s->stop; });
+  if (s->fatal != GP_OK) return fail(s->fatal, "server stopped: " + s->fatal_msg);
+  return GP_OK;
+}
+
 int gp_server_poll(gp_server* s, gp_result* out, int max, int* n) {
   if (!s || !n || (max > 0 && !out)) return fail(GP_ERR_INVALID_ARG, "bad arguments");
   std::lock_guard<std::mutex> lk(s->mu);
@@ -483,7 +687,9 @@ int gp_server_drain(gp_server* s, int timeout_ms) {
   if (!s) return fail(GP_ERR_INVALID_ARG, "server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
   auto ready = [&] { return s->fatal != GP_OK || s->completed == s->submitted; };
-  if (timeout_ms < 0) {
+  if (s->cfg.manual) {
+    if (!ready()) return fail(GP_ERR_BUSY, "requests still waiting for rounds (manual mode)");
+  } else if (timeout_ms < 0) {
     s->cv_done.wait(lk, ready);
   } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) {
     return fail(GP_ERR_BUSY, "requests still running");
@@ -498,6 +704,8 @@ int gp_server_get_stats(gp_server* s, gp_server_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->submitted = s->submitted;
   out->completed = s->completed;
+  out->failed = s->failed;
+  out->rounds = s->rounds;
   out->rhs_solved = s->rhs_solved;
   out->peak_active_rhs = s->peak_active;
   if (!s->latencies.empty()) {
@@ -513,6 +721,8 @@ int gp_server_get_stats(gp_server* s, gp_server_stats* out) {
     for (double x : v) sum += x;
     out->mean_us = sum / v.size();
     out->max_us = v.back();
+  }
+  if (s->completed > 0) {
     out->elapsed_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
     if (out->elapsed_s > 0) {
       out->solves_per_s = s->rhs_solved / out->elapsed_s;
@@ -528,6 +738,7 @@ int gp_server_destroy(gp_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
     s->cv_work.notify_all();
+    s->cv_step.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->ctx->device);
@@ -540,6 +751,8 @@ int gp_server_destroy(gp_server* s) {
   (void)hipStreamSynchronize(s->stream);
   if (s->d_probs) (void)hipFree(s->d_probs);
   if (s->h_probs) (void)hipHostFree(s->h_probs);
+  if (s->d_rbp) (void)hipFree(s->d_rbp);
+  if (s->h_rbp) (void)hipHostFree(s->h_rbp);
   if (s->d_states) (void)hipFree(s->d_states);
   (void)hipStreamDestroy(s->stream);
   s->ctx->busy.store(0);

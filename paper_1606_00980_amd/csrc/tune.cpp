@@ -1,5 +1,6 @@
 // Autotuner for the grouped PCG launches: right-hand sides per workgroup,
-// persistent workgroups per compute unit and the inner matvec kernel.
+// persistent workgroups per compute unit and the inner matvec kernel (for the
+// red-black incomplete Cholesky solver, right-hand sides per work item).
 //
 // gp_autotune times every candidate on the caller's operator with R random
 // right-hand sides (full solves to the requested tolerance, one warm-up and
@@ -60,8 +61,6 @@ int gp_autotune(gp_op* op, int R, const gp_opts* base, gp_opts* best) {
   if (base) o = *base; else gp_opts_default(&o);
   std::string why;
   if (!valid_opts(o, &why)) return fail(GP_ERR_INVALID_ARG, why);
-  if (o.precond == GP_PRECOND_RB_IC0)
-    return fail(GP_ERR_INVALID_ARG, "autotuning covers the Jacobi and block-Jacobi solver only");
   gp_ctx* c = op->ctx;
   const size_t nv = (size_t)R * op->K * op->N;
   double* buf = nullptr;
@@ -78,10 +77,17 @@ int gp_autotune(gp_op* op, int R, const gp_opts* base, gp_opts* best) {
     int rc, wpc, mv;
   };
   std::vector<Cand> cands;
-  for (int rc : {1, 2, 4, 8, 16})
-    if (rc <= R || rc == 1)
-      for (int wpc : {4, 8})
-        for (int mv : {GP_MATVEC_RASTER, GP_MATVEC_ZMARCH}) cands.push_back({rc, wpc, mv});
+  for (int rc : {1, 2, 4, 8, 16}) {
+    if (rc > R && rc != 1) continue;
+    if (o.precond == GP_PRECOND_RB_IC0) {
+      // the red-black solver launches one workgroup per work item: only the
+      // right-hand sides per work item are tuned
+      cands.push_back({rc, 0, GP_MATVEC_RASTER});
+      continue;
+    }
+    for (int wpc : {4, 8})
+      for (int mv : {GP_MATVEC_RASTER, GP_MATVEC_ZMARCH}) cands.push_back({rc, wpc, mv});
+  }
   TuneEntry bestE;
   bestE.us = INFINITY;
   int ret = GP_OK;
@@ -156,7 +162,7 @@ int gp_tune_load(gp_ctx* c, const char* path) {
     TuneEntry e;
     if (std::sscanf(line, " {\"key\": \"%95[^\"]\", \"rhs_tile\": %d, \"wg_per_cu\": %d, \"matvec\": %d, \"us\": %lf",
                     key, &e.rhs_tile, &e.wg_per_cu, &e.matvec, &e.us) == 5) {
-      if (e.rhs_tile < 1 || e.rhs_tile > RCMAX || e.wg_per_cu < 1 || e.matvec < GP_MATVEC_RASTER ||
+      if (e.rhs_tile < 1 || e.rhs_tile > RCMAX || e.wg_per_cu < 0 || e.matvec < GP_MATVEC_RASTER ||
           e.matvec > GP_MATVEC_ZMARCH)
         continue;
       c->tuned[key] = e;

@@ -25,9 +25,11 @@ GP_ERR_BUSY = -4
 GP_ERR_NOT_CONVERGED = -5
 GP_ERR_BREAKDOWN = -6
 GP_ERR_DEVICE = -7
+GP_ERR_TIMEOUT = -8
+GP_ERR_CANCELLED = -9
 GP_KMAX = 24          # largest K; length of gp_result's per-regressor arrays
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "NOT_SPD", -3: "OOM", -4: "BUSY",
-                -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "DEVICE"}
+                -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "DEVICE", -8: "TIMEOUT", -9: "CANCELLED"}
 
 GP_PRECOND_JACOBI = 0
 GP_PRECOND_BLOCK_JACOBI = 1
@@ -47,7 +49,7 @@ EXPORTS = [
     "gp_probe_rhs", "gp_trace_reduce", "gp_trace_reduce_static", "gp_trace",
     "gp_rng_normal", "gp_rng_rademacher", "gp_rng_raw",
     "gp_server_cfg_default", "gp_server_create", "gp_server_submit", "gp_server_poll",
-    "gp_server_drain", "gp_server_get_stats", "gp_server_destroy",
+    "gp_server_drain", "gp_server_get_stats", "gp_server_destroy", "gp_server_cancel", "gp_server_step",
     "gp_autotune", "gp_tune_save", "gp_tune_load",
     "gp_data_create", "gp_data_assemble", "gp_data_lambda", "gp_data_destroy", "gp_alpha_posterior",
     "gp_hyper_default", "gp_svb_step", "gp_data_assemble_ar", "gp_svb_step_ar", "gp_alpha_extrapolate",
@@ -89,12 +91,13 @@ class GpItem(ctypes.Structure):
 
 class GpServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active_rhs", ctypes.c_int),
-                ("chunk", ctypes.c_int), ("probes", ctypes.c_int), ("opts", GpOpts)]
+                ("chunk", ctypes.c_int), ("probes", ctypes.c_int), ("manual", ctypes.c_int),
+                ("reserved", ctypes.c_int), ("opts", GpOpts)]
 
 
 class GpRequest(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("op_index", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p), ("timeout_ms", ctypes.c_double)]
 
 
 class GpResult(ctypes.Structure):
@@ -102,6 +105,7 @@ class GpResult(ctypes.Structure):
                 ("status", ctypes.c_int), ("rhs", ctypes.c_int), ("iters_max", ctypes.c_int),
                 ("reserved", ctypes.c_int), ("relres_max", ctypes.c_double),
                 ("latency_us", ctypes.c_double), ("queue_us", ctypes.c_double),
+                ("admit_round", ctypes.c_int64), ("retire_round", ctypes.c_int64),
                 ("trace_total", ctypes.c_double), ("trace_kk", ctypes.c_double * GP_KMAX),
                 ("trace_Gkk", ctypes.c_double * GP_KMAX)]
 
@@ -109,6 +113,7 @@ class GpResult(ctypes.Structure):
 class GpServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("rhs_solved", ctypes.c_int64), ("peak_active_rhs", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("rounds", ctypes.c_int64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("elapsed_s", ctypes.c_double), ("solves_per_s", ctypes.c_double),
@@ -169,6 +174,8 @@ def _load() -> ctypes.CDLL:
         "gp_server_drain": (i32, [vp, i32]),
         "gp_server_get_stats": (i32, [vp, P(GpServerStats)]),
         "gp_server_destroy": (i32, [vp]),
+        "gp_server_cancel": (i32, [vp, ctypes.c_uint64]),
+        "gp_server_step": (i32, [vp, i32]),
         "gp_autotune": (i32, [vp, i32, P(GpOpts), P(GpOpts)]),
         "gp_tune_save": (i32, [vp, ctypes.c_char_p]),
         "gp_tune_load": (i32, [vp, ctypes.c_char_p]),
@@ -582,17 +589,26 @@ def gp_server_create(ctx: int, ops, bws, cfg: GpServerCfg | None = None) -> int:
     return h.value
 
 
-def gp_server_submit(srv: int, kind: int, op_index: int, seed: int, out=None) -> int:
-    r = GpRequest(kind, op_index, seed, _ptr(out))
+def gp_server_submit(srv: int, kind: int, op_index: int, seed: int, out=None, timeout_ms: float = 0.0) -> int:
+    r = GpRequest(kind, op_index, seed, _ptr(out), timeout_ms)
     t = ctypes.c_uint64()
     _check(lib.gp_server_submit(srv, ctypes.byref(r), ctypes.byref(t)), "gp_server_submit")
     return t.value
 
 
+def gp_server_cancel(srv: int, ticket: int) -> None:
+    _check(lib.gp_server_cancel(srv, ticket), "gp_server_cancel")
+
+
+def gp_server_step(srv: int, rounds: int = 1) -> None:
+    _check(lib.gp_server_step(srv, rounds), "gp_server_step")
+
+
 def _result_dict(r: GpResult) -> dict:
     return {"ticket": r.ticket, "kind": r.kind, "op_index": r.op_index, "status": r.status,
             "rhs": r.rhs, "iters_max": r.iters_max, "relres_max": r.relres_max,
-            "latency_us": r.latency_us, "queue_us": r.queue_us, "trace_total": r.trace_total,
+            "latency_us": r.latency_us, "queue_us": r.queue_us, "admit_round": r.admit_round,
+            "retire_round": r.retire_round, "trace_total": r.trace_total,
             "trace_kk": list(r.trace_kk), "trace_Gkk": list(r.trace_Gkk)}
 
 

@@ -1,6 +1,11 @@
 """Serving loop: every result equals the oracle's, and is bitwise the same
 whether the request ran alone or among others (continuous batching with
-batch-invariant reductions); admission by HBM budget."""
+batch-invariant reductions), with the block-Jacobi and the red-black
+incomplete Cholesky preconditioners; admission by HBM budget; requests that
+join while others are running (manual rounds make the schedule exact);
+failing, cancelled and timed-out requests retire alone."""
+import time
+
 import numpy as np
 import pytest
 
@@ -9,6 +14,8 @@ from oracle import philox
 from paper_1606_00980_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+PRECONDS = ["block_jacobi", "rb_ic0"]
 
 
 @pytest.fixture(scope="module")
@@ -39,10 +46,17 @@ def env(built_library):
 PROBES = 4
 
 
-def run(g, torch, ctx, ws, ops, bws, reqs, budget=1 << 30):
-    cfg = g.gp_server_cfg_default(probes=PROBES, hbm_budget=budget,
-                                  opts=g.gp_opts_default(tol=1e-9))
-    srv = g.gp_server_create(ctx, ops, bws, cfg)
+def pc_of(g, name):
+    return {"block_jacobi": g.GP_PRECOND_BLOCK_JACOBI, "rb_ic0": g.GP_PRECOND_RB_IC0}[name]
+
+
+def server_cfg(g, precond, budget=1 << 30, **kw):
+    opts = g.gp_opts_default(tol=1e-9, precond=pc_of(g, precond), **kw.pop("opts", {}))
+    return g.gp_server_cfg_default(probes=PROBES, hbm_budget=budget, opts=opts, **kw)
+
+
+def run(g, torch, ctx, ws, ops, bws, reqs, precond="block_jacobi", budget=1 << 30):
+    srv = g.gp_server_create(ctx, ops, bws, server_cfg(g, precond, budget))
     outs, tickets = [], []
     try:
         for kind, oi, seed in reqs:
@@ -60,7 +74,7 @@ def run(g, torch, ctx, ws, ops, bws, reqs, budget=1 << 30):
     return [res[t] for t in tickets], [o.cpu().numpy() for o in outs], stats
 
 
-def oracle_result(g, w, kind, seed):
+def oracle_result(g, w, kind, seed, probes=PROBES):
     grid = orc.grid(w.mask, w.conn)
     Q = orc.precision(grid, w.alpha, w.B)
     n = w.K * w.N
@@ -71,20 +85,21 @@ def oracle_result(g, w, kind, seed):
         z1 = philox.normal(seed, 1, grid.ndirs * n).reshape(1, w.K, grid.ndirs, w.N)
         z2 = philox.normal(seed, 2, n).reshape(1, w.K, w.N)
         return orc.sample(grid, w.alpha, w.B, w.bw, z1, z2), None
-    v = philox.rademacher(seed, 3, PROBES * n).reshape(PROBES, w.K, w.N)
+    v = philox.rademacher(seed, 3, probes * n).reshape(probes, w.K, w.N)
     t, tk, gk, u = orc.hutchinson(grid, Q, v)
     return u, (t, tk, gk)
 
 
-def test_server_mix_matches_alone_and_oracle(env):
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_server_mix_matches_alone_and_oracle(env, precond):
     g, torch, ctx, ws, ops, bws = env
     kinds = [g.GP_REQ_SOLVE, g.GP_REQ_SAMPLE, g.GP_REQ_TRACE]
     reqs = [(kinds[i % 3], (i * 7) % 3, 1000 + i) for i in range(15)]
-    res, outs, stats = run(g, torch, ctx, ws, ops, bws, reqs)
-    assert stats["completed"] == len(reqs) and stats["p99_us"] >= stats["p50_us"] > 0
+    res, outs, stats = run(g, torch, ctx, ws, ops, bws, reqs, precond)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0 and stats["p99_us"] >= stats["p50_us"] > 0
     assert all(r["status"] == 0 and r["relres_max"] <= 1e-9 for r in res)
     for (kind, oi, seed), r, out in zip(reqs, res, outs):
-        alone_res, alone_out, _ = run(g, torch, ctx, ws, ops, bws, [(kind, oi, seed)])
+        alone_res, alone_out, _ = run(g, torch, ctx, ws, ops, bws, [(kind, oi, seed)], precond)
         assert np.array_equal(alone_out[0], out), (kind, oi, seed)
         if kind == g.GP_REQ_TRACE:
             assert alone_res[0]["trace_total"] == r["trace_total"]
@@ -100,17 +115,19 @@ def test_server_mix_matches_alone_and_oracle(env):
             assert np.allclose(r["trace_Gkk"][:w.K], tr[2], rtol=1e-6)
 
 
-def test_server_admission_budget(env):
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_server_admission_budget(env, precond):
     g, torch, ctx, ws, ops, bws = env
     reqs = [(g.GP_REQ_SAMPLE, i % 3, 2000 + i) for i in range(6)]
-    full, full_out, _ = run(g, torch, ctx, ws, ops, bws, reqs)
+    full, full_out, _ = run(g, torch, ctx, ws, ops, bws, reqs, precond)
     # a budget that holds about one request at a time still completes all of them
-    tight, tight_out, st = run(g, torch, ctx, ws, ops, bws, reqs, budget=300_000)
+    # (a red-black request holds the split system's vectors besides b and x)
+    tight_budget = {"block_jacobi": 300_000, "rb_ic0": 400_000}[precond]
+    tight, tight_out, st = run(g, torch, ctx, ws, ops, bws, reqs, precond, budget=tight_budget)
     assert st["completed"] == 6 and st["peak_active_rhs"] <= 2
     for a, b in zip(full_out, tight_out):
         assert np.array_equal(a, b)
-    cfg = g.gp_server_cfg_default(probes=PROBES, hbm_budget=1000)
-    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    srv = g.gp_server_create(ctx, ops, bws, server_cfg(g, precond, budget=1000))
     try:
         with pytest.raises(g.GmrfError) as e:
             g.gp_server_submit(srv, g.GP_REQ_SOLVE, 0, 1)
@@ -119,7 +136,8 @@ def test_server_admission_budget(env):
         g.gp_server_destroy(srv)
 
 
-def test_server_trace_on_k20_operator(env):
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_server_trace_on_k20_operator(env, precond):
     """A trace request on an operator with K = 20 (more regressors than 16):
     every t_k and g_k of Section 3.3's trace term is returned and matches the
     oracle with the same Philox probes; the entries past K stay zero."""
@@ -131,7 +149,7 @@ def test_server_trace_on_k20_operator(env):
     try:
         g.gp_op_set_blocks(op, B)
         g.gp_op_set_alpha(op, w.alpha)
-        res, outs, _ = run(g, torch, ctx, [w], [op], [bw], [(g.GP_REQ_TRACE, 0, 4242)])
+        res, outs, _ = run(g, torch, ctx, [w], [op], [bw], [(g.GP_REQ_TRACE, 0, 4242)], precond)
     finally:
         torch.cuda.synchronize()
         g.gp_op_destroy(op)
@@ -145,3 +163,134 @@ def test_server_trace_on_k20_operator(env):
     assert np.allclose(r["trace_kk"][:w.K], tk, rtol=1e-6)
     assert np.allclose(r["trace_Gkk"][:w.K], gk, rtol=1e-6)
     assert all(v == 0.0 for v in r["trace_kk"][w.K:]) and all(v == 0.0 for v in r["trace_Gkk"][w.K:])
+
+
+def manual_server(g, ctx, ops, bws, precond, chunk=1, probes=PROBES, fp64=True):
+    opts = {"precision": g.GP_PREC_FP64} if fp64 else {}
+    cfg = server_cfg(g, precond, manual=1, chunk=chunk, opts=opts)
+    cfg.probes = probes
+    return g.gp_server_create(ctx, ops, bws, cfg)
+
+
+def step_until_done(g, srv, n_expected, limit=5000):
+    got = []
+    for _ in range(limit):
+        got += g.gp_server_poll(srv, 64)
+        if len(got) >= n_expected:
+            return {r["ticket"]: r for r in got}
+        g.gp_server_step(srv, 1)
+    raise AssertionError("requests did not finish")
+
+
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_request_joins_while_another_runs(env, precond):
+    """Continuous batching, deterministically: with rounds granted one at a
+    time (one FP64 iteration each), trace request A is admitted in round 0
+    and still running when solve request B is submitted after two rounds; B
+    is admitted in round 2, before A retires, and both results are bitwise
+    those of the same requests served alone."""
+    g, torch, ctx, ws, ops, bws = env
+    wa, wb = ws[1], ws[0]
+    outs = {}
+
+    def serve(schedule):
+        srv = manual_server(g, ctx, ops, bws, precond)
+        try:
+            tickets = {}
+            for name, kind, oi, seed, at_round in schedule:
+                while g.gp_server_get_stats(srv)["rounds"] < at_round:
+                    g.gp_server_step(srv, 1)
+                w = ws[oi]
+                R = PROBES if kind == g.GP_REQ_TRACE else 1
+                out = torch.zeros((R, w.K, w.N), dtype=torch.float64, device="cuda")
+                outs[name] = out
+                tickets[name] = g.gp_server_submit(srv, kind, oi, seed, out)
+            res = step_until_done(g, srv, len(schedule))
+        finally:
+            g.gp_server_destroy(srv)
+        torch.cuda.synchronize()
+        return {name: res[t] for name, t in tickets.items()}, {k: v.cpu().numpy() for k, v in outs.items()}
+
+    A = ("A", g.GP_REQ_TRACE, 1, 777, 0)
+    Bq = ("B", g.GP_REQ_SOLVE, 0, 778, 2)
+    mix, mix_out = serve([A, Bq])
+    ra, rb = mix["A"], mix["B"]
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert ra["admit_round"] == 0 and rb["admit_round"] == 2
+    assert rb["admit_round"] < ra["retire_round"], (ra, rb)   # B joined while A was running
+    assert ra["iters_max"] > 2
+    alone_a, out_a = serve([("A",) + A[1:4] + (0,)])
+    alone_b, out_b = serve([("B",) + Bq[1:4] + (0,)])
+    assert np.array_equal(mix_out["A"], out_a["A"]) and mix["A"]["trace_total"] == alone_a["A"]["trace_total"]
+    assert np.array_equal(mix_out["B"], out_b["B"])
+    ref, _ = oracle_result(g, wb, g.GP_REQ_SOLVE, 778)
+    assert np.linalg.norm(mix_out["B"][0] - ref[0]) <= 1e-6 * np.linalg.norm(ref[0])
+
+
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_failed_request_leaves_the_others_unchanged(env, precond):
+    """An operator whose b_w holds a NaN: its solve request breaks down alone
+    (GP_ERR_BREAKDOWN, nothing written to its output), while the requests it
+    shared rounds with return bitwise what they return without it."""
+    g, torch, ctx, ws, ops, bws = env
+    bad = bws[2].clone()
+    bad[0, 3] = float("nan")
+    bws_bad = [bws[0], bws[1], bad]
+    reqs = [(g.GP_REQ_SOLVE, 0, 3001), (g.GP_REQ_SOLVE, 2, 3002), (g.GP_REQ_TRACE, 1, 3003),
+            (g.GP_REQ_SAMPLE, 2, 3004), (g.GP_REQ_SAMPLE, 0, 3005)]
+    res, outs, st = run(g, torch, ctx, ws, ops, bws_bad, reqs, precond)
+    assert st["completed"] == 5 and st["failed"] == 2
+    for (kind, oi, seed), r, out in zip(reqs, res, outs):
+        if oi == 2:
+            assert r["status"] == g.GP_ERR_BREAKDOWN, r
+            assert np.all(out == 0.0)
+        else:
+            assert r["status"] == 0
+    good = [(q, o) for q, o in zip(reqs, outs) if q[1] != 2]
+    ref_res, ref_outs, _ = run(g, torch, ctx, ws, ops, bws, [q for q, _ in good], precond)
+    for (q, o), ro in zip(good, ref_outs):
+        assert np.array_equal(o, ro), q
+
+
+@pytest.mark.parametrize("precond", PRECONDS)
+def test_cancel_and_timeout(env, precond):
+    """Cancellation of a waiting and of a running request, and deadlines that
+    pass before admission and while running: each retires with its status
+    (nothing written to its output), the others complete unchanged."""
+    g, torch, ctx, ws, ops, bws = env
+    srv = manual_server(g, ctx, ops, bws, precond)
+    outs = {}
+    try:
+        def submit(name, kind, oi, seed, timeout_ms=0.0):
+            w = ws[oi]
+            R = PROBES if kind == g.GP_REQ_TRACE else 1
+            outs[name] = torch.zeros((R, w.K, w.N), dtype=torch.float64, device="cuda")
+            return g.gp_server_submit(srv, kind, oi, seed, outs[name], timeout_ms)
+
+        t_run = submit("running_cancel", g.GP_REQ_TRACE, 1, 4001)
+        t_keep = submit("keep", g.GP_REQ_SOLVE, 0, 4002)
+        t_late = submit("running_timeout", g.GP_REQ_TRACE, 1, 4003, timeout_ms=200.0)
+        g.gp_server_step(srv, 1)                      # all three admitted and iterating
+        t_wait = submit("waiting_cancel", g.GP_REQ_SOLVE, 2, 4004)
+        t_exp = submit("waiting_timeout", g.GP_REQ_SOLVE, 2, 4005, timeout_ms=1.0)
+        g.gp_server_cancel(srv, t_run)
+        g.gp_server_cancel(srv, t_wait)
+        time.sleep(0.25)                              # both deadlines pass
+        res = step_until_done(g, srv, 5)
+        with pytest.raises(g.GmrfError):
+            g.gp_server_cancel(srv, t_keep)           # already finished
+        st = g.gp_server_get_stats(srv)
+    finally:
+        g.gp_server_destroy(srv)
+    torch.cuda.synchronize()
+    assert res[t_run]["status"] == g.GP_ERR_CANCELLED and res[t_run]["admit_round"] == 0
+    assert res[t_wait]["status"] == g.GP_ERR_CANCELLED and res[t_wait]["admit_round"] == -1
+    assert res[t_late]["status"] == g.GP_ERR_TIMEOUT and res[t_late]["admit_round"] == 0
+    assert res[t_exp]["status"] == g.GP_ERR_TIMEOUT and res[t_exp]["admit_round"] == -1
+    assert res[t_keep]["status"] == 0
+    assert st["failed"] == 4 and st["completed"] == 5
+    for name in ("running_cancel", "waiting_cancel", "running_timeout", "waiting_timeout"):
+        assert np.all(outs[name].cpu().numpy() == 0.0), name
+    ref, _ = oracle_result(g, ws[0], g.GP_REQ_SOLVE, 4002)
+    keep = outs["keep"].cpu().numpy()
+    assert np.linalg.norm(keep[0] - ref[0]) <= 1e-6 * np.linalg.norm(ref[0])
