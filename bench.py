@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the posterior-precision hot path on one MI355X.
 
-One step is one pass of the whole path over one batch of synthetic input on
-the 52,740-voxel whole-brain operator (64x64x33 ellipsoid, K = 6, AR(3)):
-assemble the data term on the device (blocks packed and factored), set alpha
-(preconditioner set-up), form 32 perturbed right-hand sides (Algorithm 2) and
-32 Rademacher probe right-hand sides, solve all 64 in one batch (FP32 inner
-PCG, FP64 refinement to relative residual 1e-8, every right-hand side from
-zero) preconditioned by the incomplete Cholesky factor on the red-black voxel
-order (--precond block_jacobi for the block-Jacobi solver), and reduce the
-Hutchinson trace estimates.  `value` is solves/s over the
-timed steps with inputs resident in HBM.
+The headline step is one pass of the whole path over one batch of synthetic
+input on the 52,740-voxel whole-brain operator (64x64x33 ellipsoid, K = 6,
+AR(3)): assemble the data term on the device (blocks packed and factored),
+set alpha (preconditioner set-up), form 32 perturbed right-hand sides
+(Algorithm 2) and 32 Rademacher probe right-hand sides, solve all 64 in one
+batch (FP32 inner PCG, FP64 refinement to relative residual 1e-8, every
+right-hand side from zero) preconditioned by the incomplete Cholesky factor on
+the red-black voxel order (--precond block_jacobi for the block-Jacobi
+solver), and reduce the Hutchinson trace estimates.  `value` is solves/s over
+the timed steps with inputs resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--workload batch64|brain_fp64|uneven]
+Beside it the default run measures, each as a sub-record under "configs":
+the 2D slice in FP64 (Jacobi, 1e-10), the whole brain as one plain FP64
+right-hand side, the 16 uneven operators in one grouped solve, a bounded
+Poisson stream over the 24 serving operators (with a rate sweep and the same
+stream replayed through sequential plain FP64 PCG), the headline step with
+alpha changing every step, and a working-set sweep of both solvers beyond the
+256 MB Infinity Cache.  The CPU leg then runs the FP64 oracle on the host (one
+thread, and one process per right-hand-side group on all cores) on the same
+inputs and reports each configuration's error against it.
+
+    python bench.py [--steps K] [--warmup W] [--workload batch64|brain_fp64|uneven|serve]
 """
 from __future__ import annotations
 
@@ -30,6 +40,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+METRIC = "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00980_amd", "csrc", f)
                   for f in ("pcg.hpp", "device.hpp", "common.hpp", "rbic.hpp", "k_rbic_f32.hip", "k_rbic_f64.hip",
@@ -52,17 +63,22 @@ def parse():
     ap.add_argument("--workload", default="batch64", choices=["batch64", "brain_fp64", "uneven", "serve"])
     ap.add_argument("--precond", default="rb_ic0", choices=["rb_ic0", "block_jacobi"],
                     help="batch64 and uneven: the incomplete Cholesky factor on the red-black order "
-                         "(default) or block Jacobi (autotuned)")
-    ap.add_argument("--no-precond-compare", action="store_true",
-                    help="batch64: skip the solve-only comparison of preconditioners and precisions")
-    ap.add_argument("--no-ar-step", action="store_true",
-                    help="batch64: skip the timing of the AR-coefficient step")
+                         "(default) or block Jacobi")
+    ap.add_argument("--quick", action="store_true",
+                    help="batch64: the headline step and its CPU baseline only (no sub-records)")
+    ap.add_argument("--no-precond-compare", action="store_true")
+    ap.add_argument("--no-ar-step", action="store_true")
+    ap.add_argument("--no-alpha-varying", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="batch64: skip the 16-operator sub-record")
+    ap.add_argument("--no-serve", action="store_true", help="batch64: skip the serving sub-record")
+    ap.add_argument("--no-rate-sweep", action="store_true")
     ap.add_argument("--duration", type=float, default=20.0,
-                    help="serve: seconds of Poisson arrivals (the full stream is 300)")
-    ap.add_argument("--rate", type=float, default=200.0, help="serve: requests per second")
+                    help="serving: seconds of Poisson arrivals (the full stream is 300)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
     ap.add_argument("--no-sequential", action="store_true",
-                    help="serve: skip the sequential FP64 replay of the same stream")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+                    help="serving: skip the sequential FP64 replay of the same stream")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU leg (oracle timings and the errors against the oracle)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default launch configuration instead of autotuning it first")
     ap.add_argument("--no-baseline-gpu", action="store_true",
@@ -87,6 +103,15 @@ def load_library():
     return gmrf
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def pc_code(g, name):
+    return g.GP_PRECOND_RB_IC0 if name == "rb_ic0" else g.GP_PRECOND_BLOCK_JACOBI
+
+
 class Workload:
     """Device-resident inputs and the step function of one benchmark workload."""
 
@@ -94,9 +119,10 @@ class Workload:
         from paper_1606_00980_amd import synth
         self.name, self.g, self.torch, self.ctx = name, g, torch, ctx
         self.precond = precond
-        pc = g.GP_PRECOND_RB_IC0 if precond == "rb_ic0" else g.GP_PRECOND_BLOCK_JACOBI
-        dev = lambda a: torch.from_numpy(a).cuda()
+        pc = pc_code(g, precond)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         self.data = None
+        self.alpha_scale = None
         if name in ("batch64", "brain_fp64"):
             w = synth.brain_3d(keep_y=(name == "batch64"))
             self.ws = [w]
@@ -112,9 +138,10 @@ class Workload:
                 self.A = dev(np.ascontiguousarray(w.ar[None]))
                 w.Y = None
                 self.S = self.M = 32
-                z1, z2 = w.z(self.S)
-                self.v = dev(w.probes(self.M))
-                self.bw, self.z1, self.z2 = dev(w.bw), dev(z1), dev(z2)
+                self.z1h, self.z2h = w.z(self.S)
+                self.vh = w.probes(self.M)
+                self.v = dev(self.vh)
+                self.bw, self.z1, self.z2 = dev(w.bw), dev(self.z1h), dev(self.z2h)
                 self.bs = torch.empty((self.S, w.K, w.N), dtype=torch.float64, device="cuda")
                 self.bp = torch.empty((self.M, w.K, w.N), dtype=torch.float64, device="cuda")
                 self.xs = torch.zeros_like(self.bs)
@@ -127,10 +154,8 @@ class Workload:
                 self.opts = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64, zero_guess=1)
                 self.solves = 1
         else:   # 16 uneven operators, 8 right-hand sides each (4 samples + 4 probes)
-            self.ws = []
-            for i in range(16):
-                self.ws.append(synth.uneven_instance(synth.CFG_UNEVEN, i))
-                log(f"operator {i + 1}/16 generated: N={self.ws[-1].N} K={self.ws[-1].K}")
+            self.ws = synth.generate([("uneven", synth.CFG_UNEVEN, i) for i in range(16)])
+            log("16 uneven operators generated: N " + " ".join(str(w.N) for w in self.ws))
             self.ops, self.B, self.alpha, self.items = [], [], [], []
             self.pert = []
             for w in self.ws:
@@ -149,12 +174,16 @@ class Workload:
             self.solves = 16 * 8
         self.last_stats = []
         self.trace = None
+        self.nstep = 0
 
     def step(self):
         g = self.g
         if self.data is not None:
             g.gp_data_assemble(self.data, self.lam, 1, self.A, self.bw)
-            g.gp_op_set_alpha(self.op, self.alpha[0])
+            a = self.alpha[0]
+            if self.alpha_scale is not None:
+                a = a * self.alpha_scale(self.nstep)
+            g.gp_op_set_alpha(self.op, a)
         else:
             for op, B, a in zip(self.ops, self.B, self.alpha):
                 g.gp_op_set_blocks(op, B)
@@ -173,8 +202,9 @@ class Workload:
                 g.gp_perturb_rhs(op, 4, bw, z1, z2, bs)
                 g.gp_probe_rhs(op, 4, v, bp)
             _, self.last_stats = g.gp_solve_batch(self.ctx, self.items, self.opts, check=False)
-            for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(self.pert, self.ws):
-                g.gp_trace_reduce(op, 4, v, xp, w.K)
+            self.trace = [g.gp_trace_reduce(op, 4, v, xp, w.K)
+                          for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(self.pert, self.ws)]
+        self.nstep += 1
 
     def autotune(self):
         """Tune the launch configuration for each (operator, right-hand-side
@@ -183,7 +213,7 @@ class Workload:
         for op, B, a in zip(self.ops, self.B, self.alpha):
             g.gp_op_set_blocks(op, B)
             g.gp_op_set_alpha(op, a)
-        R = {"batch64": 32, "brain_fp64": 1, "uneven": 4}[self.name]
+        R = {"batch64": 64, "brain_fp64": 1, "uneven": 8}[self.name]
         out = []
         for op in self.ops:
             b = g.gp_autotune(op, R, self.opts)
@@ -198,7 +228,10 @@ class Workload:
             return {"workload": "uneven16_ellipsoids_32x32x20_to_96x96x60_K2to10_R8",
                     "operators": 16, "N_total": int(sum(Ns)), "N_min": int(min(Ns)),
                     "N_max": int(max(Ns)), "K": Ks, "R_per_operator": 8,
-                    "tol": 1e-8, "precond": self.precond, "precision": "fp32_inner_fp64_refine"}
+                    "tol": 1e-8, "precond": self.precond, "precision": "fp32_inner_fp64_refine",
+                    "launch": "one grouped launch per kernel and distinct K, solver rounds as HIP graphs",
+                    "step": "set_blocks+set_alpha+perturb_rhs(4)+probe_rhs(4) per operator+solve_batch(128)+"
+                            "trace_reduce per operator"}
         w = self.ws[0]
         if self.name == "brain_fp64":
             return {"workload": "brain3d_64x64x33_ellipsoid_K6_R1_fp64", "N": w.N, "K": w.K, "R": 1,
@@ -207,6 +240,30 @@ class Workload:
                 "R": 64, "samples": 32, "probes": 32, "tol": 1e-8, "precond": self.precond,
                 "precision": "fp32_inner_fp64_refine",
                 "step": "data_assemble+set_alpha+perturb_rhs(32)+probe_rhs(32)+solve_batch(64)+trace_reduce"}
+
+    def destroy(self):
+        self.torch.cuda.synchronize()
+        if self.data is not None:
+            self.g.gp_data_destroy(self.data)
+        for op in self.ops:
+            self.g.gp_op_destroy(op)
+
+
+def run_steps(torch, wl, steps, warmup):
+    for _ in range(warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        wl.step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernels_of(prof):
+    return {k: {"launches": v["launches"], "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
+            for k, v in prof.items() if v["launches"] > 0}
 
 
 def roofline(prof):
@@ -228,7 +285,9 @@ def roofline(prof):
             "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "traffic_detail": detail,
             "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 2),
-            "bytes_per_launch": round(d["bytes"] / d["launches"])}
+            "bytes_per_launch": round(d["bytes"] / d["launches"]),
+            "working_set": "effective: the 64-RHS whole-brain vectors are partly served by the 256 MB "
+                           "Infinity Cache; see roofline_beyond_mall for a 2 GB working set"}
 
 
 KERNEL_KIND_OF = [("k_rb_red<double", "rb_red64"), ("k_rb_red", "rb_red"), ("k_rb_matvec", "rb_matvec"),
@@ -292,10 +351,11 @@ def traffic_from(fetch_csv, write_csv, copy_mib):
 
 
 def bandwidth_sweep(g, torch, ctx):
-    """Matvec and update bandwidth over a working-set sweep on the largest
-    uneven operator (96x96x60 grid, 60% ellipsoid fill, K = 10), R = 1..64
-    right-hand sides b = b_w + N(0, 1) drawn on the device; the 256 MB MALL
-    boundary is marked.  One full FP32+FP64 solve per R, profiled."""
+    """Solver-kernel bandwidth over a working-set sweep on the largest uneven
+    operator (96x96x60 grid, 60% ellipsoid fill, K = 10), R = 1..64
+    right-hand sides b = b_w + N(0, 1) drawn on the device, with block Jacobi
+    and with the red-black incomplete Cholesky factor; the 256 MB MALL
+    boundary is marked.  One full FP32+FP64 solve per point, profiled."""
     from paper_1606_00980_amd import synth
     w = synth.uneven_instance(synth.CFG_UNEVEN, 0, dims=(96, 96, 60), fill=0.6, K=10)
     log(f"bandwidth sweep operator: N={w.N} K={w.K}")
@@ -303,31 +363,34 @@ def bandwidth_sweep(g, torch, ctx):
     g.gp_op_set_blocks(op, torch.from_numpy(w.B).cuda())
     g.gp_op_set_alpha(op, w.alpha)
     bw = torch.from_numpy(w.bw).cuda()
-    opts = g.gp_opts_default(tol=1e-8, zero_guess=1)
     rows = []
-    for R in (1, 4, 16, 64):
-        b = torch.empty((R, w.K, w.N), dtype=torch.float64, device="cuda")
-        g.gp_rng_normal(ctx, 7, 4, b.numel(), b)
-        b += bw
-        x = torch.empty_like(b)
-        g.gp_solve(op, R, b, x, opts, check=False)
-        torch.cuda.synchronize()
-        g.gp_ctx_profile(ctx, True)
-        _, stats = g.gp_solve(op, R, b, x, opts, check=False)
-        prof = g.gp_ctx_profile_read(ctx)
-        g.gp_ctx_profile(ctx, False)
-        row = {"R": R, "converged": all(s_["status"] == 0 for s_ in stats)}
-        for kind in ("matvec", "update", "refine"):
-            v = prof[kind]
-            if v["launches"]:
-                gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
-                row[kind] = {"avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
-                             "bytes_per_launch": round(v["bytes"] / v["launches"]),
-                             "GBps": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
-        row["beyond_mall"] = row["matvec"]["bytes_per_launch"] > 256e6
-        rows.append(row)
-        log(f"bandwidth sweep R={R}: matvec {row['matvec']['GBps']} GB/s, update {row['update']['GBps']} GB/s")
-        del b, x
+    for precond, kinds in (("block_jacobi", ("matvec", "update", "refine")),
+                           ("rb_ic0", ("rb_matvec", "rb_red", "rb_update", "rb_refine"))):
+        opts = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=pc_code(g, precond))
+        for R in (1, 4, 16, 64):
+            b = torch.empty((R, w.K, w.N), dtype=torch.float64, device="cuda")
+            g.gp_rng_normal(ctx, 7, 4, b.numel(), b)
+            b += bw
+            x = torch.empty_like(b)
+            g.gp_solve(op, R, b, x, opts, check=False)
+            torch.cuda.synchronize()
+            g.gp_ctx_profile(ctx, True)
+            _, stats = g.gp_solve(op, R, b, x, opts, check=False)
+            prof = g.gp_ctx_profile_read(ctx)
+            g.gp_ctx_profile(ctx, False)
+            row = {"precond": precond, "R": R, "converged": all(s_["status"] == 0 for s_ in stats)}
+            for kind in kinds:
+                v = prof[kind]
+                if v["launches"]:
+                    gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+                    row[kind] = {"avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
+                                 "bytes_per_launch": round(v["bytes"] / v["launches"]),
+                                 "GBps": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            mv = row[kinds[0]]
+            row["beyond_mall"] = mv["bytes_per_launch"] > 256e6
+            rows.append(row)
+            log(f"bandwidth sweep {precond} R={R}: {kinds[0]} {mv['GBps']} GB/s")
+            del b, x
     g.gp_op_destroy(op)
     return {"workload": f"uneven_largest_96x96x60_fill0.6_K10_N{w.N}", "N": w.N, "K": w.K,
             "mall_bytes": 256e6, "sweep": rows}
@@ -335,9 +398,8 @@ def bandwidth_sweep(g, torch, ctx):
 
 def precond_compare(g, torch, ctx, wl):
     """The step's 64-right-hand-side solve alone (graphs, no profiling) with
-    each preconditioner and inner precision: time, solves/s and iterations.
-    Block Jacobi runs with its autotuned launch configuration."""
-    w = wl.ws[0]
+    each preconditioner and inner precision: time, solves/s and iterations
+    (both solvers with their autotuned launch configuration)."""
     g.gp_data_assemble(wl.data, wl.lam, 1, wl.A, wl.bw)
     g.gp_op_set_alpha(wl.op, wl.alpha[0])
     g.gp_perturb_rhs(wl.op, wl.S, wl.bw, wl.z1, wl.z2, wl.bs)
@@ -348,8 +410,7 @@ def precond_compare(g, torch, ctx, wl):
                            ("block_jacobi", g.GP_PRECOND_BLOCK_JACOBI, g.GP_PREC_FP32_REFINE64),
                            ("block_jacobi", g.GP_PRECOND_BLOCK_JACOBI, g.GP_PREC_FP64)):
         o = g.gp_opts_default(tol=1e-8, zero_guess=1, precond=pc, precision=prec)
-        if pc == g.GP_PRECOND_BLOCK_JACOBI:
-            g.gp_autotune(wl.op, wl.S, o)
+        g.gp_autotune(wl.op, wl.S + wl.M, o)
         items = [(wl.op, wl.S, wl.bs, wl.xs), (wl.op, wl.M, wl.bp, wl.xp)]
         for _ in range(3):
             g.gp_solve_batch(ctx, items, o)
@@ -414,119 +475,239 @@ def ar_step(g, torch, ctx, wl, n=10):
         g.gp_op_destroy(op_a)
 
 
-def cpu_baseline():
-    """The oracle on the host: Algorithm 2 right-hand sides and FP64 PCG to 1e-13
-    for 16 samples and 16 probes of the same operator, one thread."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
+def alpha_varying(g, torch, wl, steps, warmup):
+    """The headline step with alpha changing every step (alpha_k scaled by
+    exp(0.3 sin(step))), as in every SVB or Gibbs iteration: the red-black
+    solver's first round replays the previous solve's shape, which may no
+    longer fit, so this costs the round plan without a matching history."""
+    wl.alpha_scale = lambda s: np.exp(0.3 * np.sin(1.0 + s))
+    try:
+        dt = run_steps(torch, wl, steps, warmup)
+        st = wl.last_stats
+    finally:
+        wl.alpha_scale = None
+    return {"what": "headline step, alpha_k x exp(0.3 sin(step)) each step",
+            "value": round(wl.solves * steps / dt, 2), "unit": "solves/s",
+            "ms_per_step": round(dt * 1e3 / steps, 3),
+            "inner_iters_mean": round(sum(s["inner_iters"] for s in st) / len(st), 2),
+            "converged": all(s["status"] == 0 and s["relres"] <= 1e-8 for s in st)}
 
-    from oracle import gmrf_oracle as orc
+
+def slice_fp64(g, torch, ctx, n=50):
+    """The 2D slice (64x64 disc of radius 28, K = 2, alpha = (1, 1)) in plain
+    FP64 with the Jacobi preconditioner to 1e-10: one solve of b_w and one
+    Algorithm-2 sample (seeded z1, z2), timed over n repetitions."""
     from paper_1606_00980_amd import synth
-    with threadpool_limits(limits=1):
-        w = synth.brain_3d()
-        z1, z2 = w.z(16)
-        v = w.probes(16).astype(np.float64)
+    w = synth.slice_2d(keep_y=False)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+    try:
+        g.gp_op_set_blocks(op, dev(w.B))
+        g.gp_op_set_alpha(op, w.alpha)
+        o = g.gp_opts_default(tol=1e-10, precond=g.GP_PRECOND_JACOBI, precision=g.GP_PREC_FP64, zero_guess=1)
+        b = dev(w.bw[None])
+        x = torch.zeros_like(b)
+        z1, z2 = w.z(1)
+        z1d, z2d, bwd = dev(z1), dev(z2), dev(w.bw)
+        xsmp = torch.zeros_like(b)
+        for _ in range(3):
+            g.gp_solve(op, 1, b, x, o)
+            g.gp_sample(op, 1, bwd, z1d, z2d, xsmp, o)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = orc.grid(w.mask, w.conn)
-        Q = orc.precision(g, w.alpha, w.B)
-        b = orc.perturbation_rhs(g, w.alpha, w.B, w.bw, z1, z2)
-        orc.solve(Q, b, tol=1e-13)
-        orc.hutchinson(g, Q, v, tol=1e-13)
-        dt = time.perf_counter() - t0
-    return {"value": round(32 / dt, 3), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "brain3d_64x64x33 K=6: operator assembly, 16 Algorithm-2 samples and 16 "
-                      "Hutchinson probes, FP64 PCG to 1e-13 (scipy, 1 thread)",
-            "seconds": round(dt, 2)}
+        for _ in range(n):
+            _, st = g.gp_solve(op, 1, b, x, o)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / n
+        t0 = time.perf_counter()
+        for _ in range(n):
+            _, st2 = g.gp_sample(op, 1, bwd, z1d, z2d, xsmp, o)
+        torch.cuda.synchronize()
+        t_sample = (time.perf_counter() - t0) / n
+        rec = {"workload": "slice2d_64x64_disc_r28_K2_fp64_jacobi", "N": w.N, "K": w.K, "tol": 1e-10,
+               "us_per_solve": round(t_solve * 1e6, 1), "us_per_sample": round(t_sample * 1e6, 1),
+               "value": round(1.0 / t_solve, 1), "unit": "solves/s",
+               "inner_iters": st[0]["inner_iters"], "relres": max(st[0]["relres"], st2[0]["relres"]),
+               "converged": st[0]["status"] == 0 and st2[0]["status"] == 0}
+        host = {"w": w, "x": x.cpu().numpy(), "sample": xsmp.cpu().numpy(), "z1": z1, "z2": z2}
+        log(f"slice fp64: {rec['us_per_solve']} us per solve, {rec['us_per_sample']} us per sample")
+        return rec, host
+    finally:
+        torch.cuda.synchronize()
+        g.gp_op_destroy(op)
 
 
-def log(msg):
-    """Progress line on stderr (the JSON result alone goes to stdout)."""
-    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+def brain_fp64(g, torch, ctx, n=10):
+    """The whole brain as one right-hand side (b_w) in plain FP64 with block
+    Jacobi: the plain single-RHS GPU PCG the batched and served figures are
+    compared with."""
+    base = Workload("brain_fp64", g, torch, ctx)
+    try:
+        base.step()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(n):
+            base.x.zero_()
+            _, st = g.gp_solve(base.op, 1, base.b, base.x, base.opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - tb) / n
+        rec = dict(base.config(), value=round(1.0 / dt, 2), unit="solves/s", ms_per_solve=round(dt * 1e3, 3),
+                   inner_iters=st[0]["inner_iters"], relres=st[0]["relres"],
+                   what="plain FP64 single-RHS PCG, same operator, block Jacobi")
+        host = {"w": base.ws[0], "x": base.x.cpu().numpy()}
+        return rec, host
+    finally:
+        base.destroy()
 
 
-def serve_schedule(duration, rate, nops):
+def uneven_record(g, torch, ctx, steps, warmup, precond, autotune):
+    """The 16 uneven operators (K = 2..10, 8 right-hand sides each) solved
+    together: every solver-round kernel one grouped launch per distinct K."""
+    wl = Workload("uneven", g, torch, ctx, precond)
+    try:
+        tuned = wl.autotune() if autotune and precond != "rb_ic0" else None
+        dt = run_steps(torch, wl, steps, warmup)
+        st = wl.last_stats
+        g.gp_ctx_profile(ctx, True)
+        wl.step()
+        prof = g.gp_ctx_profile_read(ctx)
+        g.gp_ctx_profile(ctx, False)
+        rec = dict(wl.config(), value=round(wl.solves * steps / dt, 2), unit="solves/s",
+                   ms_per_step=round(dt * 1e3 / steps, 3), steps=steps,
+                   inner_iters_mean=round(sum(s["inner_iters"] for s in st) / len(st), 2),
+                   max_relres=max(s["relres"] for s in st),
+                   converged=all(s["status"] == 0 and s["relres"] <= 1e-8 for s in st),
+                   kernels=kernels_of(prof), launch_config=tuned if tuned is not None else "default")
+        # sample 0 and probe 0 of every operator, for the comparison with the oracle
+        host = []
+        for (op, bw, z1, z2, v, bs, bp, xs, xp), w in zip(wl.pert, wl.ws):
+            host.append({"w": w, "xs0": xs[0:1].cpu().numpy(), "xp0": xp[0:1].cpu().numpy()})
+        log(f"uneven16: {rec['value']} solves/s, {rec['ms_per_step']} ms per step")
+        return rec, host
+    finally:
+        wl.destroy()
+
+
+# ------------------------------------------------------------------ serving
+SERVE_OPS = 24
+
+
+def serve_schedule(duration, rate, nops, seed_base=10_000, rng_instance=0):
     """Poisson arrivals: (arrival s, kind, operator, seed) for the serving run."""
-    import numpy as np
     from paper_1606_00980_amd import synth
-    rng = np.random.default_rng([synth.CFG_SERVE, 6, 0])
+    rng = np.random.default_rng([synth.CFG_SERVE, 6, rng_instance])
     t, out, i = 0.0, [], 0
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= duration:
             return out
-        out.append((t, int(rng.integers(0, 3)), int(rng.integers(0, nops)), 10_000 + i))
+        out.append((t, int(rng.integers(0, 3)), int(rng.integers(0, nops)), seed_base + i))
         i += 1
 
 
-def main_serve(args, g, torch, ctx):
-    """24 resident uneven operators, Poisson requests (solve / sample / 16-probe
-    trace, uniform), served with continuous batching; then the same stream
-    replayed one request at a time through plain FP64 PCG."""
+def serve_stream(g, torch, ctx, ops, bws, sched, cfg, outs=None):
+    """Submit the schedule at its arrival times to a fresh server, drain it,
+    and return (results by schedule index, server stats)."""
+    srv = g.gp_server_create(ctx, ops, bws, cfg)
+    tickets = {}
+    try:
+        t0 = time.perf_counter()
+        for j, (t, kind, oi, seed) in enumerate(sched):
+            now = time.perf_counter() - t0
+            if t > now:
+                time.sleep(t - now)
+            tickets[j] = g.gp_server_submit(srv, kind, oi, seed, outs.get(j) if outs else None)
+        g.gp_server_drain(srv, 600000)
+        res = {r["ticket"]: r for r in g.gp_server_poll(srv, len(sched) + 16)}
+        st = g.gp_server_get_stats(srv)
+    finally:
+        g.gp_server_destroy(srv)
+    return {j: res[t] for j, t in tickets.items()}, st
+
+
+def serve_record(g, torch, ctx, args, n_check=10):
+    """24 resident serving operators, Poisson requests (solve / sample /
+    16-probe trace, uniform) served with continuous batching (red-black
+    incomplete Cholesky, FP32 inner / FP64 refinement): latency percentiles
+    and throughput; a rate sweep to the highest rate the server keeps up
+    with; the same stream replayed one request at a time through plain FP64
+    PCG; a seeded sample of the served results kept for the oracle."""
     from paper_1606_00980_amd import synth
-    ws = []
-    for i in range(24):
-        ws.append(synth.uneven_instance(synth.CFG_SERVE, 100 + i))
-        log(f"operator {i + 1}/24 generated: N={ws[-1].N} K={ws[-1].K}")
+    specs = [("uneven", synth.CFG_SERVE, 100 + i) for i in range(SERVE_OPS)]
+    ws = synth.generate(specs)
+    log("24 serving operators generated")
     ops, bws, keep = [], [], []
-    for w in ws:
-        op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
-        B = torch.from_numpy(w.B).cuda()
-        g.gp_op_set_blocks(op, B)
-        g.gp_op_set_alpha(op, w.alpha)
-        ops.append(op)
-        bws.append(torch.from_numpy(w.bw).cuda())
-        keep.append(B)
-    sched = serve_schedule(args.duration, args.rate, len(ops))
-    cfg = g.gp_server_cfg_default(probes=16, hbm_budget=64 << 30, max_active_rhs=4096)
-    # warm-up: one request of each kind on the largest operator
-    big = max(range(len(ws)), key=lambda i: ws[i].N * ws[i].K)
-    srv = g.gp_server_create(ctx, ops, bws, cfg)
-    for kind in range(3):
-        g.gp_server_submit(srv, kind, big, 1 + kind)
-    g.gp_server_drain(srv, 120000)
-    g.gp_server_destroy(srv)
-    srv = g.gp_server_create(ctx, ops, bws, cfg)
-    log(f"serving {len(sched)} requests over {args.duration} s")
-    t0 = time.perf_counter()
-    for (t, kind, oi, seed) in sched:
-        now = time.perf_counter() - t0
-        if t > now:
-            time.sleep(t - now)
-        g.gp_server_submit(srv, kind, oi, seed)
-    g.gp_server_drain(srv, 600000)
-    res = g.gp_server_poll(srv, len(sched) + 16)
-    st = g.gp_server_get_stats(srv)
-    g.gp_server_destroy(srv)
-    ok = all(r["status"] == 0 and r["relres_max"] <= 1e-8 for r in res) and len(res) == len(sched)
-    out = {
-        "metric": "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency",
-        "value": round(st["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1,
-        "steps": len(sched), "warmup": 3, "ms_per_step": round(st["mean_us"] / 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "serve_poisson_24_uneven_operators", "rate_per_s": args.rate,
-                   "duration_s": args.duration, "requests": len(sched),
-                   "mix": "uniform over solve / Algorithm-2 sample / 16-probe trace",
-                   "N": [w.N for w in ws], "K": [w.K for w in ws], "tol": 1e-8},
-        "serving": {"p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
-                    "mean_ms": round(st["mean_us"] / 1e3, 3), "max_ms": round(st["max_us"] / 1e3, 3),
-                    "requests_per_s": round(st["requests_per_s"], 2),
-                    "peak_active_rhs": st["peak_active_rhs"], "all_converged": ok},
-    }
-    log(f"served: p50 {st['p50_us'] / 1e3:.2f} ms, p99 {st['p99_us'] / 1e3:.2f} ms")
-    if not args.no_sequential:
-        seq = sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s=max(30.0, 2 * args.duration))
-        out["sequential_fp64"] = seq
-    print(json.dumps(out))
-    sys.stdout.flush()
-    if not ok:
-        sys.exit(1)
+    try:
+        for w in ws:
+            op = g.gp_op_create(ctx, w.mask, w.conn, w.K)
+            B = torch.from_numpy(w.B).cuda()
+            g.gp_op_set_blocks(op, B)
+            g.gp_op_set_alpha(op, w.alpha)
+            ops.append(op)
+            bws.append(torch.from_numpy(w.bw).cuda())
+            keep.append(B)
+        cfg = g.gp_server_cfg_default(probes=16, hbm_budget=64 << 30, max_active_rhs=4096,
+                                      opts=g.gp_opts_default(tol=1e-8, precond=g.GP_PRECOND_RB_IC0))
+        # warm-up: one request of each kind on every operator
+        serve_stream(g, torch, ctx, ops, bws, [(0.0, k, i, 1 + 3 * i + k) for i in range(SERVE_OPS)
+                                               for k in range(3)], cfg)
+        sched = serve_schedule(args.duration, args.rate, SERVE_OPS)
+        rng = np.random.default_rng([synth.CFG_SERVE, 7, 0])
+        pick = set()
+        if n_check > 0:
+            pick = {int(rng.choice([j for j, s in enumerate(sched) if s[1] == k])) for k in range(3)}
+            pick |= {int(j) for j in rng.choice(len(sched), size=max(0, n_check - 3), replace=False)}
+        pick = sorted(pick)
+        outs = {}
+        for j in pick:
+            _, kind, oi, _ = sched[j]
+            R = 16 if kind == 2 else 1
+            outs[j] = torch.zeros((R, ws[oi].K, ws[oi].N), dtype=torch.float64, device="cuda")
+        log(f"serving {len(sched)} requests over {args.duration} s at {args.rate}/s")
+        res, st = serve_stream(g, torch, ctx, ops, bws, sched, cfg, outs)
+        torch.cuda.synchronize()
+        ok = all(r["status"] == 0 and r["relres_max"] <= 1e-8 for r in res.values()) and len(res) == len(sched)
+        rec = {"workload": "serve_poisson_24_uneven_operators", "rate_per_s": args.rate,
+               "duration_s": args.duration, "requests": len(sched),
+               "mix": "uniform over solve / Algorithm-2 sample / 16-probe trace",
+               "precond": "rb_ic0", "precision": "fp32_inner_fp64_refine", "tol": 1e-8,
+               "N": [w.N for w in ws], "K": [w.K for w in ws],
+               "value": round(st["solves_per_s"], 2), "unit": "solves/s",
+               "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+               "mean_ms": round(st["mean_us"] / 1e3, 3), "max_ms": round(st["max_us"] / 1e3, 3),
+               "requests_per_s": round(st["requests_per_s"], 2), "rounds": st["rounds"],
+               "peak_active_rhs": st["peak_active_rhs"], "all_converged": ok}
+        log(f"served: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, {rec['value']} solves/s")
+        if not args.no_rate_sweep:
+            sweep = []
+            for rate in (400.0, 800.0, 1600.0, 3200.0):
+                sc = serve_schedule(3.0, rate, SERVE_OPS, seed_base=20_000_000 + int(rate), rng_instance=int(rate))
+                r2, s2 = serve_stream(g, torch, ctx, ops, bws, sc, cfg)
+                row = {"offered_per_s": rate, "requests": len(sc), "completed_per_s": round(s2["requests_per_s"], 1),
+                       "p50_ms": round(s2["p50_us"] / 1e3, 3), "p99_ms": round(s2["p99_us"] / 1e3, 3),
+                       "solves_per_s": round(s2["solves_per_s"], 1),
+                       "kept_up": s2["requests_per_s"] >= 0.95 * rate,
+                       "all_ok": all(r["status"] == 0 for r in r2.values())}
+                sweep.append(row)
+                log(f"rate sweep {row}")
+            kept = [r["offered_per_s"] for r in sweep if r["kept_up"]]
+            rec["rate_sweep"] = {"duration_s_each": 3.0, "rows": sweep,
+                                 "max_sustained_offered_per_s": max(kept) if kept else None}
+        if not args.no_sequential:
+            rec["sequential_fp64"] = sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s=15.0)
+        host = {"specs": specs, "ws": ws, "sched": sched, "pick": pick,
+                "outs": {j: o.cpu().numpy() for j, o in outs.items()},
+                "res": {j: res[j] for j in pick}}
+        return rec, host, ok
+    finally:
+        torch.cuda.synchronize()
+        for op in ops:
+            g.gp_op_destroy(op)
 
 
 def sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s):
     """The same arrivals handled one request at a time by plain FP64 PCG
     (block Jacobi): latency = completion - arrival, stopped after budget_s."""
-    import numpy as np
     o = g.gp_opts_default(tol=1e-8, precision=g.GP_PREC_FP64)
     lat, solves, done = [], 0, 0
     t0 = time.perf_counter()
@@ -565,14 +746,175 @@ def sequential_fp64(g, torch, ctx, ws, ops, bws, sched, budget_s):
             "p99_ms": round(1e3 * pct(0.99), 3) if lat else None}
 
 
+# ------------------------------------------------------------ the CPU leg
+def host_record():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model}
+
+
+def err_summary(whole, block):
+    return {"max_rel_err": float(np.max(whole)), "max_block_err": float(np.max(block)), "rhs_checked": int(len(whole))}
+
+
+def cpu_leg(wl, brain_host, slice_host, fp64_host, uneven_host, serve_host):
+    """The FP64 oracle on the host, on the benchmark's own inputs.
+
+    Timed: (i) one thread, the oracle as it stands, on a bounded sample of
+    the headline workload (operator assembly, 16 Algorithm-2 samples and 16
+    probes, PCG to 1e-13); (ii) all cores, one process per group of 4
+    right-hand sides, on all 64 right-hand sides of the headline step (the
+    paper's independent samples on separate cores, Section 3.3).
+
+    Compared: every measured configuration's GPU results against the oracle's
+    on the same inputs (the headline step's 64 right-hand sides and trace
+    estimates, the slice's solve and sample, the whole brain in FP64, sample 0
+    and probe 0 of each uneven operator, a seeded sample of served requests).
+    Returns (cpu_baseline record, errors by configuration)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gmrf_oracle as orc
+    from oracle import jobs
+    out = {"kind": "oracle", "unit": "solves/s", "host": host_record()}
+    w = wl.ws[0]
+    # (i) one thread
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        g_ = orc.grid(w.mask, w.conn)
+        Q = orc.precision(g_, w.alpha, w.B)
+        b = orc.perturbation_rhs(g_, w.alpha, w.B, w.bw, wl.z1h[:16], wl.z2h[:16])
+        orc.solve(Q, b, tol=1e-13)
+        orc.hutchinson(g_, Q, wl.vh[:16].astype(np.float64), tol=1e-13)
+        dt1 = time.perf_counter() - t0
+    out["single_thread"] = {"value": round(32 / dt1, 3), "cores": 1, "seconds": round(dt1, 2),
+                            "sample": "brain3d_64x64x33 K=6: operator assembly, 16 Algorithm-2 samples and 16 "
+                                      "Hutchinson probes, FP64 PCG to 1e-13 (scipy, 1 thread)"}
+    log(f"cpu single thread: {out['single_thread']['value']} solves/s")
+    # (ii) all cores on the whole headline step: 16 jobs of 4 right-hand sides
+    jl = [(w.mask, w.conn, w.alpha, w.B, w.bw, wl.z1h[i:i + 4], wl.z2h[i:i + 4], None, 1e-12)
+          for i in range(0, wl.S, 4)]
+    jl += [(w.mask, w.conn, w.alpha, w.B, w.bw, None, None, wl.vh[i:i + 4], 1e-12) for i in range(0, wl.M, 4)]
+    res, wall, workers = jobs.run_parallel(jobs.algorithm2_solutions, jl)
+    xs_ref = np.concatenate([r[0] for r in res[:wl.S // 4]])
+    u_ref = np.concatenate([r[1] for r in res[wl.S // 4:]])
+    out.update({"value": round((wl.S + wl.M) / wall, 3), "cores": workers, "seconds": round(wall, 2),
+                "oracle_seconds_summed": round(sum(r[2] for r in res), 2),
+                "sample": "brain3d_64x64x33 K=6, the headline step's 64 right-hand sides (32 Algorithm-2 "
+                          "samples, 32 probes): assembly and FP64 PCG to 1e-12 in one process per 4 right-hand "
+                          f"sides ({workers} processes), wall time including process start"})
+    log(f"cpu all cores ({workers}): {out['value']} solves/s")
+    errors = {}
+    # the headline step: all 64 right-hand sides and the trace estimates
+    xs_h, xp_h, tr = brain_host
+    ws_, bs_ = jobs.rel_errors(xs_h, xs_ref)
+    wp_, bp_ = jobs.rel_errors(xp_h, u_ref)
+    e = err_summary(np.r_[ws_, wp_], np.r_[bs_, bp_])
+    t_ref, tk_ref, gk_ref = jobs.hutchinson_from(w.mask, w.conn, wl.vh, u_ref)
+    e["trace_rel_err"] = {"t": abs(tr[0] - t_ref) / abs(t_ref),
+                          "t_k_max": float(np.max(np.abs(np.asarray(tr[1]) - tk_ref) / np.abs(tk_ref))),
+                          "g_k_max": float(np.max(np.abs(np.asarray(tr[2]) - gk_ref) / np.abs(gk_ref))),
+                          "trace_estimate": tr[0], "oracle_trace_estimate": t_ref}
+    errors["batch64"] = e
+    log(f"headline errors: {e['max_rel_err']:.2e}, trace {e['trace_rel_err']['t']:.2e}")
+    if slice_host is not None:
+        sw = slice_host["w"]
+        smp_ref, _, _ = jobs.algorithm2_solutions(sw.mask, sw.conn, sw.alpha, sw.B, sw.bw, slice_host["z1"],
+                                                  slice_host["z2"], None)
+        x_ref, _ = jobs.solve_rhs(sw.mask, sw.conn, sw.alpha, sw.B, sw.bw[None])
+        a1, b1 = jobs.rel_errors(slice_host["x"], x_ref)
+        a2, b2 = jobs.rel_errors(slice_host["sample"], smp_ref)
+        errors["slice2d_fp64"] = err_summary(np.r_[a1, a2], np.r_[b1, b2])
+    if fp64_host is not None:
+        fw = fp64_host["w"]
+        x_ref, _ = jobs.solve_rhs(fw.mask, fw.conn, fw.alpha, fw.B, fw.bw[None])
+        errors["brain_fp64"] = err_summary(*jobs.rel_errors(fp64_host["x"], x_ref))
+    if uneven_host is not None:
+        jl = []
+        for h in uneven_host:
+            uw = h["w"]
+            z1, z2 = uw.z(4)
+            jl.append((uw.mask, uw.conn, uw.alpha, uw.B, uw.bw, z1[:1], z2[:1], uw.probes(4)[:1], 1e-12))
+        order = sorted(range(len(jl)), key=lambda i: -uneven_host[i]["w"].N * uneven_host[i]["w"].K)
+        res, wall, _ = jobs.run_parallel(jobs.algorithm2_solutions, [jl[i] for i in order])
+        whole, block = [], []
+        for i, r in zip(order, res):
+            a, b = jobs.rel_errors(uneven_host[i]["xs0"], r[0])
+            c, d = jobs.rel_errors(uneven_host[i]["xp0"], r[1])
+            whole += [a, c]
+            block += [b, d]
+        e = err_summary(np.concatenate(whole), np.concatenate(block))
+        e.update({"what": "sample 0 and probe 0 of each of the 16 operators", "oracle_wall_s": round(wall, 1)})
+        errors["uneven16"] = e
+        log(f"uneven errors: {e['max_rel_err']:.2e}")
+    if serve_host is not None and serve_host["pick"]:
+        specs, sched, pick = serve_host["specs"], serve_host["sched"], serve_host["pick"]
+        jl, keys = [], []
+        for j in pick:
+            _, kind, oi, seed = sched[j]
+            if kind == 2:
+                for p in range(16):
+                    jl.append((specs[oi], kind, seed, 16, [p]))
+                    keys.append(j)
+            else:
+                jl.append((specs[oi], kind, seed, 16, None))
+                keys.append(j)
+        res, wall, _ = jobs.run_parallel(jobs.served, jl)
+        got = {}
+        for j, r in zip(keys, res):
+            got.setdefault(j, []).append(r["x"])
+        whole, block, tr_err = [], [], 0.0
+        for j in pick:
+            ref = np.concatenate(got[j])
+            a, b = jobs.rel_errors(serve_host["outs"][j], ref)
+            whole.append(a)
+            block.append(b)
+            _, kind, oi, seed = sched[j]
+            if kind == 2:
+                sw = serve_host["ws"][oi]
+                v = jobs.served_probes(seed, 16, sw.K, sw.N)
+                t_ref = jobs.hutchinson_from(sw.mask, sw.conn, v, ref)[0]
+                tr_err = max(tr_err, abs(serve_host["res"][j]["trace_total"] - t_ref) / abs(t_ref))
+        e = err_summary(np.concatenate(whole), np.concatenate(block))
+        e.update({"requests_checked": len(pick), "requests_served": len(sched),
+                  "what": "seeded sample of served requests (at least one of each kind)",
+                  "trace_rel_err_max": tr_err, "oracle_wall_s": round(wall, 1)})
+        errors["serve24"] = e
+        log(f"served-sample errors: {e['max_rel_err']:.2e}")
+    return out, errors
+
+
+# ---------------------------------------------------------------- main
+def main_serve(args, g, torch, ctx):
+    rec, _, ok = serve_record(g, torch, ctx, args, n_check=0)
+    out = {"metric": METRIC, "value": rec["value"], "unit": "solves/s", "n_gpus": 1,
+           "steps": rec["requests"], "warmup": 3 * SERVE_OPS, "ms_per_step": rec["mean_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic", "config": {k: v for k, v in rec.items() if k not in ("value", "unit")}}
+    print(json.dumps(out))
+    sys.stdout.flush()
+    if not ok:
+        sys.exit(1)
+
+
 def main():
     args = parse()
     if args.traffic_from:
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_mib)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
-                                   "supported (one process, one MI355X)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(one process, one MI355X)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     g = load_library()
@@ -582,21 +924,15 @@ def main():
     if args.workload == "serve":
         main_serve(args, g, torch, ctx)
         return
-    wl = Workload(args.workload, g, torch, ctx, args.precond if args.workload in ("batch64", "uneven") else "block_jacobi")
+    wl = Workload(args.workload, g, torch, ctx,
+                  args.precond if args.workload in ("batch64", "uneven") else "block_jacobi")
     tuned = None
-    if not args.no_autotune and wl.precond != "rb_ic0":
+    if not args.no_autotune:
         tuned = wl.autotune()
         log(f"autotuned: {tuned}")
-    for _ in range(args.warmup):
-        wl.step()
     # the timed steps: the library as it runs in production (solver rounds
     # replayed as graphs, no per-launch timing)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        wl.step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = run_steps(torch, wl, args.steps, args.warmup)
     stats = wl.last_stats
     # the same steps again with per-launch HIP-event timing (eager launches),
     # for the per-kernel figures and the roofline
@@ -612,7 +948,7 @@ def main():
     stats = stats + wl.last_stats
     ok = all(s["status"] == 0 and s["relres"] <= 1e-8 for s in stats)
     result = {
-        "metric": "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 latency",
+        "metric": METRIC,
         "value": round(wl.solves * args.steps / dt, 2),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -632,35 +968,44 @@ def main():
         "inner_iters_mean": round(sum(s["inner_iters"] for s in stats) / len(stats), 2),
         "outer_steps_mean": round(sum(s["outer_steps"] for s in stats) / len(stats), 2),
         "value_profiled": round(wl.solves * args.steps / dt_prof, 2),
-        "kernels": {k: {"launches": v["launches"],
-                        "avg_us": round(v["ms"] * 1e3 / v["launches"], 2),
-                        "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)}
-                    for k, v in prof.items() if v["launches"] > 0},
+        "kernels": kernels_of(prof),
     }
-    if wl.trace is not None:
-        result["trace_estimate"] = round(wl.trace[0], 6)
-    if args.workload == "batch64" and not args.no_baseline_gpu:
-        base = Workload("brain_fp64", g, torch, ctx)
-        base.step()
-        torch.cuda.synchronize()
-        n = 10
-        tb = time.perf_counter()
-        for _ in range(n):
-            base.x.zero_()
-            g.gp_solve(base.op, 1, base.b, base.x, base.opts)
-        torch.cuda.synchronize()
-        result["gpu_fp64_single_rhs"] = {"value": round(n / (time.perf_counter() - tb), 2),
-                                         "unit": "solves/s",
-                                         "what": "plain FP64 single-RHS PCG, same operator, block Jacobi"}
-    if args.workload == "batch64" and not args.no_ar_step:
-        result["ar_step"] = ar_step(g, torch, ctx, wl)
-    if args.workload == "batch64" and not args.no_precond_compare:
-        result["precond_compare"] = precond_compare(g, torch, ctx, wl)
-    if args.workload == "batch64" and not args.no_bandwidth_sweep:
-        result["bandwidth_sweep"] = bandwidth_sweep(g, torch, ctx)
-        big = result["bandwidth_sweep"]["sweep"][-1]
-        result["roofline_beyond_mall"] = {"kernel": "matvec", "R": big["R"], **big["matvec"],
-                                          "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    if args.workload != "batch64":
+        if args.workload == "uneven":
+            result["trace_estimates"] = [round(t[0], 6) for t in wl.trace]
+        print(json.dumps(result))
+        sys.stdout.flush()
+        wl.destroy()
+        sys.exit(0 if ok else 1)
+    result["trace_estimate"] = round(wl.trace[0], 6)
+    brain_host = (wl.xs.cpu().numpy(), wl.xp.cpu().numpy(), wl.trace)
+    configs, slice_host, fp64_host, uneven_host, serve_host = {}, None, None, None, None
+    if not args.quick:
+        if not args.no_alpha_varying:
+            configs["batch64_alpha_varying"] = alpha_varying(g, torch, wl, args.steps, 2)
+            log(f"alpha varying: {configs['batch64_alpha_varying']}")
+        if not args.no_ar_step:
+            result["ar_step"] = ar_step(g, torch, ctx, wl)
+        if not args.no_precond_compare:
+            result["precond_compare"] = precond_compare(g, torch, ctx, wl)
+        configs["slice2d_fp64"], slice_host = slice_fp64(g, torch, ctx)
+        if not args.no_baseline_gpu:
+            configs["brain_fp64"], fp64_host = brain_fp64(g, torch, ctx)
+            result["gpu_fp64_single_rhs"] = {"value": configs["brain_fp64"]["value"], "unit": "solves/s",
+                                             "what": configs["brain_fp64"]["what"]}
+        if not args.no_uneven:
+            configs["uneven16"], uneven_host = uneven_record(g, torch, ctx, max(5, args.steps // 2), 2,
+                                                             args.precond, not args.no_autotune)
+        if not args.no_serve:
+            configs["serve24"], serve_host, sok = serve_record(g, torch, ctx, args)
+            ok = ok and sok
+        if not args.no_bandwidth_sweep:
+            result["bandwidth_sweep"] = bandwidth_sweep(g, torch, ctx)
+            kind = "rb_matvec" if args.precond == "rb_ic0" else "matvec"
+            for row in result["bandwidth_sweep"]["sweep"]:
+                if row["R"] == 64 and row["precond"] == args.precond and kind in row:
+                    result["roofline_beyond_mall"] = {"kernel": kind, "R": 64, **row[kind],
+                                                      "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -668,10 +1013,21 @@ def main():
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-    if not args.no_cpu_baseline and args.workload == "batch64":
-        result["cpu_baseline"] = cpu_baseline()
+    if not args.no_cpu_baseline:
+        cpu, errors = cpu_leg(wl, brain_host, slice_host, fp64_host, uneven_host, serve_host)
+        result["cpu_baseline"] = cpu
+        result["errors_vs_oracle"] = errors
+        result["max_rel_err_vs_oracle"] = max(e["max_rel_err"] for e in errors.values())
+        result["max_block_err_vs_oracle"] = max(e["max_block_err"] for e in errors.values())
+        ok = ok and result["max_rel_err_vs_oracle"] <= 1e-6 and result["max_block_err_vs_oracle"] <= 1e-6
+        for name, e in errors.items():
+            if name in configs:
+                configs[name]["max_rel_err_vs_oracle"] = e["max_rel_err"]
+    if configs:
+        result["configs"] = configs
     print(json.dumps(result))
     sys.stdout.flush()
+    wl.destroy()
     if not ok:
         sys.exit(1)
 

@@ -132,6 +132,27 @@ def solve_rhs(mask, conn: int, alpha, B, rhs, tol: float = 1e-12):
     return x, time.perf_counter() - t0
 
 
+def algorithm2_solutions(mask, conn: int, alpha, B, bw, z1, z2, probes, tol: float = 1e-12):
+    """The oracle on raw inputs: Algorithm-2 right-hand sides from z1
+    (R, K, dirs, N) and z2 (R, K, N) and their solutions, and the solutions of
+    the Rademacher probes (m, K, N) (either part may be empty).  Returns
+    (samples (R, K, N), probe solutions (m, K, N), oracle seconds: assembly,
+    right-hand sides and solves)."""
+    from oracle import gmrf_oracle as orc
+    t0 = time.perf_counter()
+    g = orc.grid(mask, conn)
+    Q = orc.precision(g, alpha, B)
+    K, N = np.shape(B)[1], np.shape(B)[0]
+    xs = np.zeros((0, K, N))
+    u = np.zeros((0, K, N))
+    if z2 is not None and len(z2):
+        b = orc.perturbation_rhs(g, alpha, B, bw, z1, z2)
+        xs = orc.solve(Q, b, tol)
+    if probes is not None and len(probes):
+        u = orc.solve(Q, np.asarray(probes, dtype=np.float64), tol)
+    return xs, u, time.perf_counter() - t0
+
+
 def perturbation_rhs(mask, conn: int, alpha, B, bw, z1, z2):
     """The oracle's Algorithm-2 right-hand sides for raw inputs (see
     gmrf_oracle.perturbation_rhs)."""
