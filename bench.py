@@ -680,12 +680,13 @@ def serve_record(g, torch, ctx, args, n_check=10):
         log(f"served: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, {rec['value']} solves/s")
         if not args.no_rate_sweep:
             sweep = []
-            for rate in (400.0, 800.0, 1600.0, 3200.0):
+            for rate in (400.0, 800.0, 1200.0, 1600.0, 2400.0, 3200.0):
                 sc = serve_schedule(3.0, rate, SERVE_OPS, seed_base=20_000_000 + int(rate), rng_instance=int(rate))
                 r2, s2 = serve_stream(g, torch, ctx, ops, bws, sc, cfg)
                 row = {"offered_per_s": rate, "requests": len(sc), "completed_per_s": round(s2["requests_per_s"], 1),
                        "p50_ms": round(s2["p50_us"] / 1e3, 3), "p99_ms": round(s2["p99_us"] / 1e3, 3),
-                       "solves_per_s": round(s2["solves_per_s"], 1),
+                       "solves_per_s": round(s2["solves_per_s"], 1), "rounds": s2["rounds"],
+                       "peak_active_rhs": s2["peak_active_rhs"],
                        "kept_up": s2["requests_per_s"] >= 0.95 * rate,
                        "all_ok": all(r["status"] == 0 for r in r2.values())}
                 sweep.append(row)

@@ -518,7 +518,12 @@ int gp_rng_gamma(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double s
 typedef struct gp_server gp_server;
 
 typedef struct gp_server_cfg {
-  size_t  hbm_budget;      /* bytes of request workspace held at once (default 16 GiB) */
+  size_t  hbm_budget;      /* bytes of request workspace (default 16 GiB): the device
+                              memory the server takes for workspaces, in slabs of
+                              1 GiB (or one request's size) kept until
+                              gp_server_destroy, and the cap on the running
+                              requests' bytes; a request waits while its workspace
+                              does not fit                                           */
   int     max_active_rhs;  /* right-hand-side slots advanced together (default 1024)   */
   int     chunk;           /* inner iterations per round (default 4)                  */
   int     probes;          /* probes per trace request (default 16)                   */

@@ -133,8 +133,8 @@ struct RbProb {
   void* q;
   void* u;               // [R][K][NR] red stage of an inner step
   int Rc, nch;           // right-hand sides per inner work item, chunks of them
-  int wB, wR, wO;        // first black-tile, red-tile and outer (one right-hand side) work item
-  int spare;
+  int Rco, ncho;         // right-hand sides per outer (refine, x_B += d) work item, chunks of them
+  int wB, wR, wO;        // first black-tile, red-tile and outer work item
 };
 
 // Packed index of the symmetric (k, j) entry, lower triangle row-major.

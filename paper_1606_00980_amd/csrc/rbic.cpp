@@ -248,7 +248,7 @@ void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveC
   out->R = R;
 }
 
-std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile) {
+std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile, bool outer_chunks) {
   std::vector<RbGroup> gs;
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < n; ++j) {
@@ -279,8 +279,15 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile) {
       g.WB += P.rb.ntB * P.nch;
       P.wR = g.WR;
       g.WR += P.rb.ntR * P.nch;
+      // the FP64 refinement and x_B += d: one right-hand side per work item
+      // (holding the FP64 blocks across several costs the refinement
+      // occupancy), or the inner chunks when most right-hand sides of a launch
+      // are not in the outer phase (the serving loop), so that the launch does
+      // not consist of empty workgroups
+      P.Rco = outer_chunks ? P.Rc : 1;
+      P.ncho = (P.pr.R + P.Rco - 1) / P.Rco;
       P.wO = g.WO;
-      g.WO += P.rb.ntB * P.pr.R;
+      g.WO += P.rb.ntB * P.ncho;
       P.pr.fin_begin = F;
       F += (P.pr.R + fpb - 1) / fpb;
     }
@@ -490,7 +497,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
       r0 += Rm[j];
     }
   }
-  std::vector<RbGroup> groups = rb_groups(c->h_rbp, n, ot.rhs_tile);
+  std::vector<RbGroup> groups = rb_groups(c->h_rbp, n, ot.rhs_tile, false);
   for (int j = 0; j < n; ++j) mem[j].desc = c->h_rbp[j];
   HIPTRY(hipMemcpyAsync(c->d_rbp, c->h_rbp, n * sizeof(RbProb), hipMemcpyHostToDevice, s));
   HIPTRY(hipMemsetAsync(sts, 0, (size_t)totalR * sizeof(RhsState), s));

@@ -123,8 +123,8 @@ __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>&
 
 // Work items of a grouped solver-round launch over the members of one K group:
 // black-tile items (256 black positions, a chunk of Rc right-hand sides) for the
-// inner stages, red-tile items for the red stage, and black-tile items of one
-// right-hand side for the outer step.  A member's items are numbered tile-major
+// inner stages, red-tile items for the red stage, and black-tile items of a
+// chunk of Rco right-hand sides for the outer step.  A member's items are numbered tile-major
 // (the chunks of a tile adjacent, so that they share the tile's blocks) from
 // its first item, and the launch's items are dealt to the XCDs in contiguous
 // ranges, so that neighbouring tiles, whose vectors the stencil gathers, share
@@ -148,8 +148,8 @@ __device__ inline RbWork rb_item(const RbProb* __restrict__ probs, int nprob) {
   while (p + 1 < nprob && wi >= rb_first_item<WHICH>(probs[p + 1])) ++p;
   const RbProb& P = probs[p];
   const int loc = wi - rb_first_item<WHICH>(P);
-  const int rc = WHICH == RBW_OUTER ? 1 : P.Rc;
-  const int nch = WHICH == RBW_OUTER ? P.pr.R : P.nch;
+  const int rc = WHICH == RBW_OUTER ? P.Rco : P.Rc;
+  const int nch = WHICH == RBW_OUTER ? P.ncho : P.nch;
   RbWork w;
   w.p = p;
   w.tile = loc / nch;

@@ -277,8 +277,9 @@ size_t rb_member_bytes(const gp_op* op, int R, bool f32);
 // descriptor, except the work ranges that rb_groups sets.
 void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveCfg& cfg, bool prof, RbMember* out);
 // Groups the n descriptors h (sorted by K) and sets their work ranges and
-// finalisation blocks.
-std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile);
+// finalisation blocks; with outer_chunks the outer-step work items take the
+// inner chunks of right-hand sides instead of one each.
+std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile, bool outer_chunks);
 // Enqueues one solver round (see rbic.cpp) for every group on q; with
 // `branched` each group on a branch stream forked from q and joined back.
 int rb_enqueue_round(gp_ctx* c, hipStream_t q, bool f32, const std::vector<RbGroup>& gs, const RbProb* d_probs,

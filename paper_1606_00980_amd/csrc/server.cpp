@@ -7,8 +7,9 @@
 // while the byte budget and the right-hand-side slot table allow), prepares
 // their right-hand sides on the device, retires running requests that were
 // cancelled or passed their deadline, rebuilds the grouped-launch descriptors
-// when the active set changed, runs one solver round of `chunk` iterations
-// (the refinement step before each) for every active right-hand side, copies
+// when the active set changed, runs one solver round (about `chunk`
+// iterations, with the refinement step where it is expected to be needed) for
+// every active right-hand side, copies
 // the state table to the host and retires every request whose right-hand
 // sides are all done.  Requests therefore join and leave the running batch at
 // round boundaries, and the kernels' batch-invariant reductions make a
@@ -25,6 +26,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <map>
 #include <thread>
 #include <vector>
 
@@ -88,13 +90,24 @@ struct gp_server {
   int64_t rounds = 0;       // solver rounds run
   int64_t credits = 0;      // manual mode: rounds granted and not yet run
   size_t bytes_in_use = 0;
+  // Request workspaces come from slabs of device memory taken up to the byte
+  // budget and kept until the server is destroyed, carved best-fit and
+  // coalesced on release (worker thread only): once the slabs cover the
+  // working set, admission and retirement make no allocator call.
+  std::vector<std::pair<char*, size_t>> slabs;
+  size_t slab_bytes = 0;
+  std::map<char*, size_t> free_at;         // free ranges by address
+  std::multimap<size_t, char*> free_len;   // the same ranges by length
   std::vector<double> latencies;
   Clock::time_point t_first{}, t_last{};
   bool any_submitted = false;
-  // device state table, one RhsState per right-hand-side slot
+  // device state table, one RhsState per right-hand-side slot, and its pinned
+  // host copy (the slots up to the highest in use are copied each round)
   RhsState* d_states = nullptr;
-  std::vector<RhsState> h_states;
+  RhsState* h_states = nullptr;
+  double* h_trace = nullptr;        // pinned: the trace totals of the requests retiring in a round
   std::vector<char> slot_used;
+  std::vector<RhsState> plan_buf;   // the active right-hand sides' states, for the round plan
   // grouped-launch descriptors (Jacobi / block Jacobi: Prob; red-black: RbProb)
   Prob* d_probs = nullptr;
   Prob* h_probs = nullptr;
@@ -142,17 +155,94 @@ size_t request_bytes(const gp_server* s, const gp_op* op, int R, int kind) {
   return b;
 }
 
-// Allocates a request's buffers and prepares its right-hand sides.  Returns
-// GP_ERR_OOM (nothing allocated) when the device allocation fails.
+constexpr size_t SLAB_BYTES = size_t(1) << 30;
+
+bool slab_start(const gp_server* s, const char* p) {
+  for (const auto& sl : s->slabs)
+    if (sl.first == p) return true;
+  return false;
+}
+
+void free_erase(gp_server* s, std::map<char*, size_t>::iterator it) {
+  auto r = s->free_len.equal_range(it->second);
+  for (auto k = r.first; k != r.second; ++k)
+    if (k->second == it->first) {
+      s->free_len.erase(k);
+      break;
+    }
+  s->free_at.erase(it);
+}
+
+void free_insert(gp_server* s, char* p, size_t n) {
+  s->free_at[p] = n;
+  s->free_len.emplace(n, p);
+}
+
+// Returns [p, p + n) to the free ranges, merged with free neighbours in the
+// same slab.
+void arena_release(gp_server* s, char* p, size_t n) {
+  auto next = s->free_at.find(p + n);
+  if (next != s->free_at.end() && !slab_start(s, p + n)) {
+    n += next->second;
+    free_erase(s, next);
+  }
+  auto prev = s->free_at.lower_bound(p);
+  if (prev != s->free_at.begin() && !slab_start(s, p)) {
+    --prev;
+    if (prev->first + prev->second == p) {
+      p = prev->first;
+      n += prev->second;
+      free_erase(s, prev);
+    }
+  }
+  free_insert(s, p, n);
+}
+
+// Best-fit range of n bytes; a new slab (1 GiB, or n if larger, within the
+// budget) when no free range fits.  nullptr: nothing fits now.
+char* arena_take(gp_server* s, size_t n) {
+  auto it = s->free_len.lower_bound(n);
+  if (it == s->free_len.end()) {
+    if (s->slab_bytes + n > s->cfg.hbm_budget) return nullptr;
+    size_t want = std::max(n, std::min(SLAB_BYTES, s->cfg.hbm_budget - s->slab_bytes));
+    char* m = nullptr;
+    if (hipMalloc((void**)&m, want) != hipSuccess) {
+      (void)hipGetLastError();
+      want = n;
+      if (hipMalloc((void**)&m, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+    }
+    s->slabs.emplace_back(m, want);
+    s->slab_bytes += want;
+    free_insert(s, m, want);
+    it = s->free_len.lower_bound(n);
+  }
+  char* p = it->second;
+  const size_t have = it->first;
+  free_erase(s, s->free_at.find(p));
+  if (have > n) free_insert(s, p + n, have - n);
+  return p;
+}
+
+// With no workspace in use: gives every slab back to the device.
+int arena_reset(gp_server* s) {
+  HIPTRY(hipStreamSynchronize(s->stream));
+  for (const auto& sl : s->slabs) HIPTRY(hipFree(sl.first));
+  s->slabs.clear();
+  s->slab_bytes = 0;
+  s->free_at.clear();
+  s->free_len.clear();
+  return GP_OK;
+}
+
+// Lays out a request's buffers in its workspace and prepares its right-hand
+// sides.
 int admit(gp_server* s, Req* q) {
   hipStream_t st = s->stream;
   gp_op* op = q->op;
   const size_t nv = (size_t)q->R * op->K * op->N;
-  if (hipMallocAsync((void**)&q->mem, q->bytes, st) != hipSuccess) {
-    (void)hipGetLastError();
-    q->mem = nullptr;
-    return fail(GP_ERR_OOM, "request workspace could not be allocated");
-  }
   char* p = q->mem;
   auto take = [&](size_t n) {
     char* r = p;
@@ -234,7 +324,7 @@ int rebuild_layout(gp_server* s) {
   const int n = (int)s->order.size();
   if (s->rb) {
     for (int j = 0; j < n; ++j) s->h_rbp[j] = s->order[j]->rbm.desc;
-    s->rgroups = rb_groups(s->h_rbp, n, o.rhs_tile);
+    s->rgroups = rb_groups(s->h_rbp, n, o.rhs_tile, true);
     HIPTRY(hipMemcpyAsync(s->d_rbp, s->h_rbp, (size_t)n * sizeof(RbProb), hipMemcpyHostToDevice, s->stream));
     s->layout_dirty = false;
     return GP_OK;
@@ -282,17 +372,30 @@ int rebuild_layout(gp_server* s) {
 int run_round(gp_server* s) {
   hipStream_t st = s->stream;
   const int pc = s->cfg.opts.precond;
-  // requests join and finish at different times: the outer step precedes every iteration
+  // The round's plan from the active right-hand sides' states: with FP32
+  // inner solves the outer step is placed where inner solves are expected to
+  // end (and first, for requests just admitted), as in the solver's own
+  // rounds; with FP64 inner solves it opens the round.  The launch groups
+  // (one per K) run on branch streams forked from the server's stream.
+  int len = s->cfg.chunk;
+  uint64_t mask = 1;
+  int top = 0;
+  if (s->f32) {
+    s->plan_buf.clear();
+    for (Req* q : s->active)
+      for (int r = 0; r < q->R; ++r) s->plan_buf.push_back(s->h_states[q->slot0 + r]);
+    gp_opts po = s->cfg.opts;
+    po.chunk = 0;
+    plan_round(s->plan_buf, po, true, s->cfg.chunk, &len, &mask);
+  }
+  for (Req* q : s->active) top = std::max(top, q->slot0 + q->R);
   if (s->rb) {
-    if (int e = rb_enqueue_round(s->ctx, st, s->f32, s->rgroups, s->d_rbp, s->cfg.chunk, ~0ull, false, false, false,
-                                 false))
+    if (int e = rb_enqueue_round(s->ctx, st, s->f32, s->rgroups, s->d_rbp, len, mask, false, false, false, true))
       return e;
-  } else if (int e = enqueue_round(s->ctx, st, s->f32, pc, s->groups, s->d_probs, s->cfg.chunk,
-                                   s->f32 ? ~0ull : 1ull, false)) {
+  } else if (int e = enqueue_round_branched(s->ctx, st, s->f32, pc, s->groups, s->d_probs, len, mask)) {
     return e;
   }
-  HIPTRY(hipMemcpyAsync(s->h_states.data(), s->d_states, s->h_states.size() * sizeof(RhsState),
-                        hipMemcpyDeviceToHost, st));
+  HIPTRY(hipMemcpyAsync(s->h_states, s->d_states, (size_t)top * sizeof(RhsState), hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
   s->rounds += 1;
   return GP_OK;
@@ -308,9 +411,10 @@ void base_result(const gp_server* s, const Req* q, gp_result* res) {
   res->retire_round = s->rounds;
 }
 
-// Releases a request's memory and slots (stream-ordered free).
+// Returns a request's workspace to the arena (its pending work and the next
+// user's are ordered on the server stream) and frees its slots.
 int release(gp_server* s, Req* q) {
-  if (q->mem) HIPTRY(hipFreeAsync(q->mem, s->stream));
+  if (q->mem) arena_release(s, q->mem, q->bytes);
   q->mem = nullptr;
   if (q->slot0 >= 0)
     for (int r = 0; r < q->R; ++r) s->slot_used[q->slot0 + r] = 0;
@@ -329,10 +433,12 @@ int retire_failed(gp_server* s, Req* q, int status, gp_result* res) {
   return GP_OK;
 }
 
-// Finishes request q (all its right-hand sides are done): recovery of the
-// red-black solution, trace reduction, result copy, statistics; frees its
-// memory and slots.
-int retire(gp_server* s, Req* q, gp_result* res) {
+// Enqueues the retirement of request q (all its right-hand sides are done):
+// recovery of the red-black solution, trace reduction (its 1 + 2K totals
+// copied to the pinned slot `trace_host`), result copy, release of its memory
+// and slots.  The result's trace entries and latency are filled by
+// retire_finish once the stream has been waited for.
+int retire_enqueue(gp_server* s, Req* q, gp_result* res, double* trace_host) {
   hipStream_t st = s->stream;
   gp_op* op = q->op;
   base_result(s, q, res);
@@ -363,23 +469,25 @@ int retire(gp_server* s, Req* q, gp_result* res) {
       double* pairbuf = part + (size_t)2 * q->R * op->K * op->ntiles;
       double* out = pairbuf + (size_t)2 * q->R * op->K;
       HIPTRY(launch_trace(st, op_dev(op), q->R, q->probes, q->x, part, pairbuf, out));
-      std::vector<double> h(1 + 2 * op->K);
-      HIPTRY(hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPTRY(hipStreamSynchronize(st));
-      res->trace_total = h[0];
-      for (int k = 0; k < op->K; ++k) {
-        res->trace_kk[k] = h[1 + k];
-        res->trace_Gkk[k] = h[1 + op->K + k];
-      }
+      HIPTRY(hipMemcpyAsync(trace_host, out, (1 + 2 * (size_t)op->K) * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     if (q->r.out) HIPTRY(hipMemcpyAsync(q->r.out, q->x, nv * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  if (int e = release(s, q)) return e;
-  HIPTRY(hipStreamSynchronize(st));
+  return release(s, q);
+}
+
+void retire_finish(const Req* q, gp_result* res, const double* trace_host) {
+  if (res->status == GP_OK && q->r.kind == GP_REQ_TRACE) {
+    const int K = q->op->K;
+    res->trace_total = trace_host[0];
+    for (int k = 0; k < K; ++k) {
+      res->trace_kk[k] = trace_host[1 + k];
+      res->trace_Gkk[k] = trace_host[1 + K + k];
+    }
+  }
   const auto now = Clock::now();
   res->latency_us = us_between(q->t_submit, now);
   res->queue_us = us_between(q->t_submit, q->t_admit);
-  return GP_OK;
 }
 
 bool expired(const Req* q, Clock::time_point now) { return q->has_deadline && now >= q->deadline; }
@@ -418,6 +526,26 @@ void worker_main(gp_server* s) {
         if (s->bytes_in_use + q->bytes > s->cfg.hbm_budget) break;
         const int slot = find_slots(s, q->R);
         if (slot < 0) break;
+        q->mem = arena_take(s, q->bytes);
+        if (!q->mem && s->active.empty() && admitted.empty()) {
+          // nothing holds a workspace: fresh slabs, then out of memory
+          if (int e = arena_reset(s)) {
+            s->fatal = e;
+            s->fatal_msg = gp_last_error();
+            s->stop = true;
+            s->cv_done.notify_all();
+            s->cv_step.notify_all();
+            return;
+          }
+          q->mem = arena_take(s, q->bytes);
+          if (!q->mem) {
+            (void)fail(GP_ERR_OOM, "request workspace could not be allocated");
+            dropped.emplace_back(q, GP_ERR_OOM);
+            s->pending.pop_front();
+            continue;
+          }
+        }
+        if (!q->mem) break;   // waits for running requests to release theirs
         for (int r = 0; r < q->R; ++r) s->slot_used[slot + r] = 1;
         q->slot0 = slot;
         s->bytes_in_use += q->bytes;
@@ -440,14 +568,11 @@ void worker_main(gp_server* s) {
       q->admit_round = s->rounds;
       const int st = admit(s, q);
       if (st == GP_OK) {
+        // the host copy of its states starts as the device's (zero) until the
+        // round reads them back
+        std::memset(s->h_states + q->slot0, 0, (size_t)q->R * sizeof(RhsState));
         s->active.push_back(q);
         s->layout_dirty = true;
-      } else if (st == GP_ERR_OOM) {
-        gp_result res;
-        q->admit_round = -1;
-        if ((err = retire_failed(s, q, GP_ERR_OOM, &res)) != GP_OK) break;
-        done.push_back(res);
-        freed.push_back(q);
       } else {
         err = st;
       }
@@ -477,7 +602,9 @@ void worker_main(gp_server* s) {
       if (err == GP_OK) err = run_round(s);
     }
     if (err == GP_OK) {
-      std::vector<Req*> still;
+      // every finished request's retirement is enqueued, then one wait
+      std::vector<Req*> still, leaving;
+      std::vector<gp_result> out;
       for (Req* q : s->active) {
         bool all = true;
         for (int r = 0; r < q->R && all; ++r) all = s->h_states[q->slot0 + r].phase == PH_DONE;
@@ -485,11 +612,19 @@ void worker_main(gp_server* s) {
           still.push_back(q);
           continue;
         }
-        gp_result res;
-        if ((err = retire(s, q, &res)) != GP_OK) break;
-        done.push_back(res);
-        freed.push_back(q);
+        out.emplace_back();
+        if ((err = retire_enqueue(s, q, &out.back(), s->h_trace + leaving.size() * (1 + 2 * KMAX))) != GP_OK)
+          break;
+        leaving.push_back(q);
         s->layout_dirty = true;
+      }
+      if (err == GP_OK && !leaving.empty()) {
+        if (hipStreamSynchronize(s->stream) != hipSuccess) err = fail(GP_ERR_DEVICE, "server stream failed");
+        for (size_t i = 0; i < leaving.size() && err == GP_OK; ++i) {
+          retire_finish(leaving[i], &out[i], s->h_trace + i * (1 + 2 * KMAX));
+          done.push_back(out[i]);
+          freed.push_back(leaving[i]);
+        }
       }
       if (err == GP_OK) s->active.swap(still);
     }
@@ -565,10 +700,11 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
   s->tsz = s->f32 ? sizeof(float) : sizeof(double);
   s->ops.assign(ops, ops + nops);
   s->bw.assign(bw, bw + nops);
-  s->h_states.resize(c.max_active_rhs);
   s->slot_used.assign(c.max_active_rhs, 0);
   auto bail = [&](int st) {
     if (s->d_states) (void)hipFree(s->d_states);
+    if (s->h_states) (void)hipHostFree(s->h_states);
+    if (s->h_trace) (void)hipHostFree(s->h_trace);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     ctx->busy.store(0);
@@ -585,11 +721,13 @@ int gp_server_create(gp_ctx* ctx, int nops, gp_op* const* ops, const double* con
     return bail(fail(GP_ERR_DEVICE, "could not create the server stream"));
   if (hipMalloc((void**)&s->d_states, (size_t)c.max_active_rhs * sizeof(RhsState)) != hipSuccess)
     return bail(fail(GP_ERR_OOM, "could not allocate the state table"));
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) {
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-  }
+  if (hipHostMalloc((void**)&s->h_states, (size_t)c.max_active_rhs * sizeof(RhsState), hipHostMallocDefault) !=
+      hipSuccess)
+    return bail(fail(GP_ERR_OOM, "could not allocate the host state table"));
+  std::memset(s->h_states, 0, (size_t)c.max_active_rhs * sizeof(RhsState));
+  if (hipHostMalloc((void**)&s->h_trace, (size_t)c.max_active_rhs * (1 + 2 * KMAX) * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
+    return bail(fail(GP_ERR_OOM, "could not allocate the host trace table"));
   (void)hipGetLastError();
   s->worker = std::thread(worker_main, s);
   *out = s;
@@ -743,17 +881,17 @@ int gp_server_destroy(gp_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->ctx->device);
   (void)hipStreamSynchronize(s->stream);
-  for (Req* q : s->active) {
-    if (q->mem) (void)hipFreeAsync(q->mem, s->stream);
-    delete q;
-  }
+  for (Req* q : s->active) delete q;
   for (Req* q : s->pending) delete q;
   (void)hipStreamSynchronize(s->stream);
+  for (const auto& sl : s->slabs) (void)hipFree(sl.first);
   if (s->d_probs) (void)hipFree(s->d_probs);
   if (s->h_probs) (void)hipHostFree(s->h_probs);
   if (s->d_rbp) (void)hipFree(s->d_rbp);
   if (s->h_rbp) (void)hipHostFree(s->h_rbp);
   if (s->d_states) (void)hipFree(s->d_states);
+  if (s->h_states) (void)hipHostFree(s->h_states);
+  if (s->h_trace) (void)hipHostFree(s->h_trace);
   (void)hipStreamDestroy(s->stream);
   s->ctx->busy.store(0);
   delete s;
