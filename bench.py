@@ -612,11 +612,15 @@ def serve_stream(g, torch, ctx, ops, bws, sched, cfg, outs=None):
     tickets = {}
     try:
         t0 = time.perf_counter()
+        next_note = 30.0
         for j, (t, kind, oi, seed) in enumerate(sched):
             now = time.perf_counter() - t0
             if t > now:
                 time.sleep(t - now)
             tickets[j] = g.gp_server_submit(srv, kind, oi, seed, outs.get(j) if outs else None)
+            if t >= next_note:   # long streams report their progress
+                log(f"serving: {j + 1} of {len(sched)} requests submitted at {t:.0f} s")
+                next_note += 30.0
         g.gp_server_drain(srv, 600000)
         res = {r["ticket"]: r for r in g.gp_server_poll(srv, len(sched) + 16)}
         st = g.gp_server_get_stats(srv)

@@ -15,7 +15,8 @@ from collections.abc import Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgmrf.so")
+# GMRF_LIB selects another build of the library (the host-sanitized one)
+LIB_PATH = os.environ.get("GMRF_LIB") or os.path.join(_HERE, "libgmrf.so")
 
 GP_OK = 0
 GP_ERR_INVALID_ARG = -1
