@@ -27,6 +27,7 @@ inputs and reports each configuration's error against it.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -914,6 +915,11 @@ def main_serve(args, g, torch, ctx):
 
 def main():
     args = parse()
+    # the Python collector's pauses (tens of ms, at unpredictable points) are
+    # not the library's time: collect once, then keep it off for the run
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     if args.traffic_from:
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_mib)
         return

@@ -509,14 +509,22 @@ void plan_round(const std::vector<RhsState>& hs, const gp_opts& o, bool f32, int
   *round_mask = mask;
 }
 
+// Captured rounds are kept per launch layout, at most GRAPH_CACHE of them; a
+// new layout in a full cache replaces the least recently replayed one (after
+// the stream has drained, so that no replay of it is in flight).
+constexpr size_t GRAPH_CACHE = 256;
+
 int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue) {
   hipStream_t s = c->stream;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
-    if (c->graphs.size() >= 64) {
+    if (c->graphs.size() >= GRAPH_CACHE) {
+      auto lru = c->graphs.begin();
+      for (auto jt = c->graphs.begin(); jt != c->graphs.end(); ++jt)
+        if (jt->second.used < lru->second.used) lru = jt;
       HIPTRY(hipStreamSynchronize(s));
-      for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-      c->graphs.clear();
+      (void)hipGraphExecDestroy(lru->second.exec);
+      c->graphs.erase(lru);
     }
     HIPTRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     const int est = enqueue(c->cap_stream);
@@ -531,9 +539,10 @@ int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipS
     const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     HIPTRY(ei);
-    it = c->graphs.emplace(key, exec).first;
+    it = c->graphs.emplace(key, gp_ctx::GraphEntry{exec, 0}).first;
   }
-  HIPTRY(hipGraphLaunch(it->second, s));
+  it->second.used = ++c->graph_tick;
+  HIPTRY(hipGraphLaunch(it->second.exec, s));
   return GP_OK;
 }
 
@@ -918,7 +927,7 @@ int gp_ctx_destroy(gp_ctx* c) {
   if (c->h_rbp) (void)hipHostFree(c->h_rbp);
   if (c->h_rbst) (void)hipHostFree(c->h_rbst);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipStream_t b : c->branch) (void)hipStreamDestroy(b);
   for (hipEvent_t e : c->branch_ev) (void)hipEventDestroy(e);

@@ -810,11 +810,15 @@ hipError_t launch_rbg_red_t(hipStream_t s, int K, const RbProb* probs, int nprob
   return hipGetLastError();
 }
 
+// The refinement reads its blocks where they are used: its work items are
+// mostly one right-hand side, and holding the FP64 Q_mm and S_m^{-1} for the
+// whole item cost occupancy (107 against 142 us per launch on the whole-brain
+// 64-RHS solve).
 template <typename T>
 hipError_t launch_rbg_refine_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
   if (W == 0) return hipSuccess;
 #define X(KK) \
-  case KK: RB_HOLD_LAUNCH(k_rb_refine, KK, 2, double, dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  case KK: hipLaunchKernelGGL((k_rb_refine<T, KK, false>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
   RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();

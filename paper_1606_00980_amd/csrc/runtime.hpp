@@ -68,7 +68,12 @@ struct gp_ctx {
   // round as parallel graph branches (default priority, non-blocking)
   std::vector<hipStream_t> branch;
   std::vector<hipEvent_t> branch_ev;   // [0] fork, [1 + g] join of branch g
-  std::map<std::string, hipGraphExec_t> graphs;
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    uint64_t used;   // graph_tick at its last replay
+  };
+  std::map<std::string, GraphEntry> graphs;
+  uint64_t graph_tick = 0;
   bool use_graphs = true;
   // autotuned configurations keyed by tune_key()
   std::map<std::string, TuneEntry> tuned;
