@@ -111,6 +111,7 @@ struct RbDev {
   long long* prof;       // [NPROF] work counters while profiling, else null
   int NB, NR, ntB, ntR, N, K;
   int ntN;               // tiles of 256 voxels over all N (split, recovery, ||b||^2 partials)
+  int tbB, tbR;          // tiles per block of the work order (black, red)
   int zero_start;        // the start value is zero: x is not read
   double alpha64[KMAX];
   float alpha32[KMAX];

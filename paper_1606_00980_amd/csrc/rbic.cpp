@@ -145,6 +145,20 @@ RbDev rb_dev(const gp_op* op) {
   v.ntN = d.ntN;
   v.N = op->N;
   v.K = op->K;
+  // Work items run block by block: within a block of tiles, every chunk of
+  // right-hand sides sweeps the block's tiles before the next chunk starts,
+  // so that a tile's z-neighbours (one plane of colour positions away) were
+  // just gathered for the same chunk and are still in L2, and the block's
+  // voxel blocks stay there across the chunks.  A block spans two planes
+  // and two tiles, and its voxel blocks at most 1.5 MB.
+  const size_t tile_blocks = (size_t)2 * (op->K * (op->K + 1) / 2) * 256 * sizeof(float);
+  const int cap = std::max<int>(4, (int)(((size_t)1536 << 10) / tile_blocks));
+  auto per_block = [&](int npos, int ntiles) {
+    const int reach = (npos / std::max(op->nz, 1) + 255) / 256;   // tiles per z-plane of positions
+    return std::max(1, std::min({2 * reach + 2, cap, std::max(ntiles, 1)}));
+  };
+  v.tbB = per_block(d.NB, d.ntB);
+  v.tbR = per_block(d.NR, d.ntR);
   for (int k = 0; k < op->K; ++k) {
     v.alpha64[k] = op->alpha[k];
     v.alpha32[k] = (float)op->alpha[k];

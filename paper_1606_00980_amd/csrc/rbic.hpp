@@ -124,11 +124,11 @@ __device__ __forceinline__ void neighbour_sum(const int (&nb)[6], const Slab<T>&
 // Work items of a grouped solver-round launch over the members of one K group:
 // black-tile items (256 black positions, a chunk of Rc right-hand sides) for the
 // inner stages, red-tile items for the red stage, and black-tile items of a
-// chunk of Rco right-hand sides for the outer step.  A member's items are numbered tile-major
-// (the chunks of a tile adjacent, so that they share the tile's blocks) from
-// its first item, and the launch's items are dealt to the XCDs in contiguous
-// ranges, so that neighbouring tiles, whose vectors the stencil gathers, share
-// an XCD's L2.
+// chunk of Rco right-hand sides for the outer step.  A member's items are
+// numbered from its first item by block of tiles (tbB or tbR of them), then
+// chunk, then tile, and the launch's items are dealt to the XCDs in contiguous
+// ranges: an XCD sweeps a block's tiles once per chunk, with the block's
+// voxel blocks and the chunk's vectors around the tiles in its L2.
 enum RbWhich : int { RBW_BLACK = 0, RBW_RED = 1, RBW_OUTER = 2 };
 
 struct RbWork {
@@ -150,10 +150,16 @@ __device__ inline RbWork rb_item(const RbProb* __restrict__ probs, int nprob) {
   const int loc = wi - rb_first_item<WHICH>(P);
   const int rc = WHICH == RBW_OUTER ? P.Rco : P.Rc;
   const int nch = WHICH == RBW_OUTER ? P.ncho : P.nch;
+  const int nt = WHICH == RBW_RED ? P.rb.ntR : P.rb.ntB;
+  const int tb = WHICH == RBW_RED ? P.rb.tbR : P.rb.tbB;
+  // block of tb tiles (the last one shorter), then chunk, then tile
+  const int per = tb * nch;
+  const int blk = loc / per, rem = loc - blk * per;
+  const int len = min(tb, nt - blk * tb);
   RbWork w;
   w.p = p;
-  w.tile = loc / nch;
-  w.r0 = (loc % nch) * rc;
+  w.tile = blk * tb + rem % len;
+  w.r0 = (rem / len) * rc;
   w.r1 = min(P.pr.R, w.r0 + rc);
   w.first = loc == 0;
   return w;
