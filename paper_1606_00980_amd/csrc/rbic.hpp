@@ -585,7 +585,10 @@ __device__ __forceinline__ void black_stage(const RbDev& rb, const BD& D, const 
 }
 
 // Black stage of q = S p after a separate red stage (u read from memory).
-template <typename T, int K, bool HOLD>
+// HOLD: the voxel blocks held in registers across the work item's
+// right-hand sides, 2 = Q_mm and S_m^{-1}, 1 = S_m^{-1} only (it is applied
+// twice per right-hand side), 0 = neither.
+template <typename T, int K, int HOLD>
 __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ probs, int nprob) {
   const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
   const RbProb& P = probs[w.p];
@@ -602,7 +605,8 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ p
   int nb[6];
   load_nb(rb.nbB, rb.NB, ii, nb);
   const unsigned oT = (unsigned)ii * (unsigned)sizeof(T);
-  const Packed<T, K, HOLD> D(RbT<T>::D(rb), rb.NB, oT), S(RbT<T>::S(rb), rb.NB, oT);
+  const Packed<T, K, (HOLD >= 2)> D(RbT<T>::D(rb), rb.NB, oT);
+  const Packed<T, K, (HOLD >= 1)> S(RbT<T>::S(rb), rb.NB, oT);
   ItemSums<7> sums;
 #pragma unroll 1
   for (int r = w.r0; r < w.r1; ++r) {
@@ -833,8 +837,15 @@ hipError_t launch_rbg_refine_t(hipStream_t s, int K, const RbProb* probs, int np
 template <typename T>
 hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
   if (W == 0) return hipSuccess;
-#define X(KK) \
-  case KK: RB_HOLD_LAUNCH(k_rb_matvec, KK, 2, T, dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+#define X(KK)                                                                                   \
+  case KK:                                                                                      \
+    if constexpr (HoldRb<T, KK, 2>::v)                                                          \
+      hipLaunchKernelGGL((k_rb_matvec<T, KK, 2>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+    else if constexpr (HoldRb<T, KK, 1>::v)                                                     \
+      hipLaunchKernelGGL((k_rb_matvec<T, KK, 1>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_rb_matvec<T, KK, 0>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+    break;
   RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();
