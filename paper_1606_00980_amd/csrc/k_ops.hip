@@ -11,6 +11,8 @@
 //     (the trace inside E[W_k D_w W_k'], Section 3.3)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "launch.hpp"
 #include "pcg.hpp"
@@ -265,14 +267,21 @@ template <int K>
 __global__ __launch_bounds__(TILE) void k_perturb(OpDev op, const double* __restrict__ bw,
                                                   const double* __restrict__ z1,
                                                   const double* __restrict__ z2,
-                                                  double* __restrict__ b) {
+                                                  double* __restrict__ b, int R, int tb) {
   constexpr int NB = Tri<K>::NB;
   const int N = op.N, dirs = op.dirs;
-  // items (right-hand side, tile), right-hand side major, in contiguous ranges
-  // per XCD: the lower neighbours' z1 values were just read by the same XCD
+  // items (right-hand side, tile) by blocks of tb tiles: every right-hand
+  // side sweeps a block's tiles before the next one starts, and the items go
+  // to the XCDs in contiguous ranges, so that the block's Cholesky factors and
+  // neighbour table stay in the XCD's L2 across the right-hand sides and the
+  // lower neighbours' z1 values (a plane back) were just read for the same
+  // right-hand side
   const int W = gridDim.x;
   const int item = xcd_remap(blockIdx.x, W);
-  const int r = item / op.ntiles, tile = item - r * op.ntiles;
+  const int per = tb * R;
+  const int blk = item / per, rem = item - blk * per;
+  const int len = min(tb, op.ntiles - blk * tb);
+  const int r = rem / len, tile = blk * tb + rem % len;
   const int n = tile * TILE + threadIdx.x;
   if (n >= N) return;
   int nb[6];
@@ -469,9 +478,15 @@ hipError_t launch_apply(hipStream_t s, const OpDev& op, int R, const double* x, 
 
 hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* bw, const double* z1,
                           const double* z2, double* b) {
+  if (op.ntiles == 0 || R == 0) return hipSuccess;
   const dim3 g((unsigned)((long)op.ntiles * R)), bl(TILE);
+  // tiles per block: two planes of voxels and two tiles, the block's packed
+  // factors at most 1.5 MB
+  const long reach = ((long)op.N / (op.nz > 0 ? op.nz : 1) + TILE - 1) / TILE;
+  const long cap = std::max(4L, (long)(1536 << 10) / ((long)(op.K * (op.K + 1) / 2) * TILE * 8));
+  const int tb = (int)std::max(1L, std::min({2 * reach + 2, cap, (long)op.ntiles}));
   switch (op.K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_perturb<KK>, g, bl, 0, s, op, bw, z1, z2, b); break;
+#define X(KK) case KK: hipLaunchKernelGGL(k_perturb<KK>, g, bl, 0, s, op, bw, z1, z2, b, R, tb); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
