@@ -489,7 +489,8 @@ int gp_rng_gamma(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double s
  * A request loop over resident operators: requests (solve, sample, trace) are
  * submitted from any thread, admitted in arrival order while the server's HBM
  * budget and right-hand-side slots allow, join the running grouped solve at
- * the next round boundary (continuous batching) and retire one by one.  The
+ * the next round boundary (continuous batching) and retire at the round
+ * boundary after their last right-hand side is done.  The
  * server runs on its own thread and HIP stream and holds its context busy
  * until destroyed; its operators must not be modified meanwhile.  Results do
  * not depend on which other requests share a round (batch-invariant
@@ -497,10 +498,13 @@ int gp_rng_gamma(gp_ctx* ctx, uint64_t seed, uint64_t stream, size_t n, double s
  * Every preconditioner is served (with GP_PRECOND_RB_IC0 each request is a
  * member of the grouped red-black solve).
  *
- * A server round: admit waiting requests (their right-hand sides prepared on
- * the device), run `chunk` iterations of every admitted right-hand side (the
- * FP64 refinement step before each iteration for those waiting on it), read
- * the states, retire finished requests.  A request that fails (breakdown,
+ * A server round: admit waiting requests (their workspaces carved from the
+ * server's device memory, their right-hand sides prepared on the device), run
+ * a round of iterations of every admitted right-hand side (about `chunk`,
+ * planned from their states as the solvers plan theirs: the FP64 refinement
+ * step first for requests just admitted and where inner solves are expected
+ * to end), read the states, retire finished requests (one wait for all of the
+ * round's retirements).  A request that fails (breakdown,
  * iteration cap, its deadline, cancellation, or an allocation error at
  * admission) retires with that status alone; the others go on unchanged.
  *
