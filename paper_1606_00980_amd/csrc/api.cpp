@@ -172,6 +172,18 @@ int ensure_probs(gp_ctx* c, size_t n) {
 }
 
 // ------------------------------------------------------------ profiling
+}  // namespace rt
+
+LaunchTiming& launch_timing() {
+  static thread_local LaunchTiming t;
+  return t;
+}
+
+namespace rt {
+
+// The launches between prof_begin and prof_end take the slot's two events in
+// their dispatch packets (GP_LAUNCH); a span without a kernel records them
+// back to back.
 int prof_begin(gp_ctx* c, size_t* slot) {
   if (c->ev_used + 2 > c->evpool.size()) {
     for (int i = 0; i < 64; ++i) {
@@ -182,12 +194,21 @@ int prof_begin(gp_ctx* c, size_t* slot) {
   }
   *slot = c->ev_used;
   c->ev_used += 2;
-  HIPTRY(hipEventRecord(c->evpool[*slot], c->stream));
+  LaunchTiming& lt = launch_timing();
+  lt.start = c->evpool[*slot];
+  lt.stop = c->evpool[*slot + 1];
+  lt.first = true;
   return GP_OK;
 }
 
 int prof_end(gp_ctx* c, int kind, size_t slot) {
-  HIPTRY(hipEventRecord(c->evpool[slot + 1], c->stream));
+  LaunchTiming& lt = launch_timing();
+  const bool none = lt.first;
+  lt = LaunchTiming{};
+  if (none) {
+    HIPTRY(hipEventRecord(c->evpool[slot], c->stream));
+    HIPTRY(hipEventRecord(c->evpool[slot + 1], c->stream));
+  }
   c->pending.push_back({kind, slot});
   return GP_OK;
 }

@@ -335,10 +335,10 @@ __global__ __launch_bounds__(64) void k_quadform_final(int nrk, int ntiles, cons
 hipError_t launch_data_tensors(hipStream_t s, int T, int K, int P, int N, const double* X, const double* Y,
                                double* G, double* YX, double* Bt, double* Dt, double* YY, double* dY, double* dd) {
   const int nG = K * K + K * K * P + P * K * K * P;
-  hipLaunchKernelGGL(k_data_globals, dim3((nG + DT - 1) / DT), dim3(DT), 0, s, T, K, P, X, G);
+  GP_LAUNCH(k_data_globals, dim3((nG + DT - 1) / DT), dim3(DT), 0, s, T, K, P, X, G);
   if (hipError_t e = hipGetLastError()) return e;
   const int entries = K + P * K + P * K * P + 1 + P + P * P;
-  hipLaunchKernelGGL(k_data_tensors, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)T * K * sizeof(double), s,
+  GP_LAUNCH(k_data_tensors, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)T * K * sizeof(double), s,
                      T, K, P, N, X, Y, YX, Bt, Dt, YY, dY, dd);
   return hipGetLastError();
 }
@@ -348,7 +348,7 @@ hipError_t launch_data_rss(hipStream_t s, int K, int P, int N, int Ns, const dou
                            const double* W, const double* A, double u1, double u2t, double* rss, double* scale,
                            double* mean) {
   const int nG = K * K + K * K * P + P * K * K * P;
-  hipLaunchKernelGGL(k_data_rss, dim3((N + DT - 1) / DT), dim3(DT), (size_t)nG * sizeof(double), s, K, P, N, Ns, G, YX,
+  GP_LAUNCH(k_data_rss, dim3((N + DT - 1) / DT), dim3(DT), (size_t)nG * sizeof(double), s, K, P, N, Ns, G, YX,
                      Bt, Dt, YY, dY, dd, W, A, u1, u2t, rss, scale, mean);
   return hipGetLastError();
 }
@@ -357,9 +357,9 @@ int quadform_tiles(int N) { return (N + DT - 1) / DT; }
 
 hipError_t launch_quadform(hipStream_t s, const OpDev& op, int R, const double* W, double* part, double* out) {
   const int nt = quadform_tiles(op.N), nrk = R * op.K;
-  hipLaunchKernelGGL(k_quadform_partials, dim3(nt, nrk), dim3(DT), 0, s, op, W, part);
+  GP_LAUNCH(k_quadform_partials, dim3(nt, nrk), dim3(DT), 0, s, op, W, part);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(k_quadform_final, dim3(nrk), dim3(64), 0, s, nrk, nt, part, out);
+  GP_LAUNCH(k_quadform_final, dim3(nrk), dim3(64), 0, s, nrk, nt, part, out);
   return hipGetLastError();
 }
 
@@ -368,7 +368,7 @@ hipError_t launch_data_assemble(hipStream_t s, int K, int P, int N, int Ns, cons
                                 double* Bout, double* bw) {
   const int nG = K * K + K * K * P + P * K * K * P;
   if (P > PMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_data_assemble, dim3((N + DT - 1) / DT, K), dim3(DT), (size_t)nG * sizeof(double), s, K,
+  GP_LAUNCH(k_data_assemble, dim3((N + DT - 1) / DT, K), dim3(DT), (size_t)nG * sizeof(double), s, K,
                      P, N, Ns, G, YX, Bt, Dt, lambda, A, Bout, bw);
   return hipGetLastError();
 }
@@ -378,7 +378,7 @@ hipError_t launch_data_assemble_ar(hipStream_t s, int K, int P, int N, int Ns, c
                                    const double* W, double* Jout, double* ba) {
   const int nG = K * K + K * K * P + P * K * K * P;
   const int entries = P * (P + 1) / 2 + P;
-  hipLaunchKernelGGL(k_data_assemble_ar, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)nG * sizeof(double), s,
+  GP_LAUNCH(k_data_assemble_ar, dim3((N + DT - 1) / DT, entries), dim3(DT), (size_t)nG * sizeof(double), s,
                      K, P, N, Ns, G, Bt, Dt, dY, dd, lambda, W, Jout, ba);
   return hipGetLastError();
 }

@@ -122,17 +122,17 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_neighbours(int N, const int* __r
 
 hipError_t launch_grid_build(hipStream_t s, const uint8_t* mask, long ncell, int* counts, int* offsets,
                              int nblocks) {
-  hipLaunchKernelGGL(k_mask_count, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, mask, ncell, counts);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(SCAN_BLOCK), 0, s, counts, nblocks, offsets);
+  GP_LAUNCH(k_mask_count, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, mask, ncell, counts);
+  GP_LAUNCH(k_scan_counts, dim3(1), dim3(SCAN_BLOCK), 0, s, counts, nblocks, offsets);
   return hipGetLastError();
 }
 
 hipError_t launch_grid_index(hipStream_t s, const uint8_t* mask, long ncell, const int* offsets,
                              int nblocks, int* gridmap, int* lin, int N, int nx, int ny, int nz, int conn,
                              int* nbr, unsigned long long* edges) {
-  hipLaunchKernelGGL(k_mask_index, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, mask, ncell, offsets, gridmap,
+  GP_LAUNCH(k_mask_index, dim3(nblocks), dim3(SCAN_BLOCK), 0, s, mask, ncell, offsets, gridmap,
                      lin);
-  hipLaunchKernelGGL(k_neighbours, dim3((N + SCAN_BLOCK - 1) / SCAN_BLOCK), dim3(SCAN_BLOCK), 0, s, N, lin,
+  GP_LAUNCH(k_neighbours, dim3((N + SCAN_BLOCK - 1) / SCAN_BLOCK), dim3(SCAN_BLOCK), 0, s, N, lin,
                      gridmap, nx, ny, nz, conn, nbr, edges);
   return hipGetLastError();
 }
@@ -446,7 +446,7 @@ hipError_t launch_pack_blocks(hipStream_t s, int K, int N, const double* B, doub
                               double* L64, int* bad) {
   const dim3 g((N + TILE - 1) / TILE), b(TILE);
   switch (K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_pack_blocks<KK>, g, b, 0, s, N, B, B64, B32, L64, bad); break;
+#define X(KK) case KK: GP_LAUNCH(k_pack_blocks<KK>, g, b, 0, s, N, B, B64, B32, L64, bad); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -457,7 +457,7 @@ hipError_t launch_pack_blocks(hipStream_t s, int K, int N, const double* B, doub
 hipError_t launch_precond(hipStream_t s, const OpDev& op, int pc, double* P64, float* P32, int* bad) {
   const dim3 g((op.N + TILE - 1) / TILE), b(TILE);
   switch (op.K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_precond<KK>, g, b, 0, s, op, pc, P64, P32, bad); break;
+#define X(KK) case KK: GP_LAUNCH(k_precond<KK>, g, b, 0, s, op, pc, P64, P32, bad); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -468,7 +468,7 @@ hipError_t launch_precond(hipStream_t s, const OpDev& op, int pc, double* P64, f
 hipError_t launch_apply(hipStream_t s, const OpDev& op, int R, const double* x, double* y) {
   const dim3 g((op.N + TILE - 1) / TILE, R), b(TILE);
   switch (op.K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_apply<KK>, g, b, 0, s, op, x, y); break;
+#define X(KK) case KK: GP_LAUNCH(k_apply<KK>, g, b, 0, s, op, x, y); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -486,7 +486,7 @@ hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* b
   const long cap = std::max(4L, (long)(1536 << 10) / ((long)(op.K * (op.K + 1) / 2) * TILE * 8));
   const int tb = (int)std::max(1L, std::min({2 * reach + 2, cap, (long)op.ntiles}));
   switch (op.K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_perturb<KK>, g, bl, 0, s, op, bw, z1, z2, b, R, tb); break;
+#define X(KK) case KK: GP_LAUNCH(k_perturb<KK>, g, bl, 0, s, op, bw, z1, z2, b, R, tb); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -497,21 +497,21 @@ hipError_t launch_perturb(hipStream_t s, const OpDev& op, int R, const double* b
 hipError_t launch_add_broadcast(hipStream_t s, int R, long kn, const double* bw, double* b) {
   const long total = (long)R * kn;
   const int bs = 256;
-  hipLaunchKernelGGL(k_add_broadcast, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, total, kn, bw, b);
+  GP_LAUNCH(k_add_broadcast, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, total, kn, bw, b);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_rhs(hipStream_t s, long total, const int8_t* v, double* b) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_probe_rhs, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, total, v, b);
+  GP_LAUNCH(k_probe_rhs, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, total, v, b);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(hipStream_t s, int kind, const Prob* probs, int nprob, int nblocks) {
   const dim3 g(nblocks), b(FIN_WAVES * WAVE);
   switch (kind) {
-    case 0: hipLaunchKernelGGL(k_finalize<0>, g, b, 0, s, probs, nprob); break;
-    case 1: hipLaunchKernelGGL(k_finalize<1>, g, b, 0, s, probs, nprob); break;
+    case 0: GP_LAUNCH(k_finalize<0>, g, b, 0, s, probs, nprob); break;
+    case 1: GP_LAUNCH(k_finalize<1>, g, b, 0, s, probs, nprob); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -523,15 +523,15 @@ hipError_t launch_trace(hipStream_t s, const OpDev& op, int m, const int8_t* v, 
                         double* part, double* pairbuf, double* out) {
   const dim3 g(op.ntiles, m), b(TILE);
   switch (op.K) {
-#define X(KK) case KK: hipLaunchKernelGGL(k_trace_partials<KK>, g, b, 0, s, op, v, u, part, m); break;
+#define X(KK) case KK: GP_LAUNCH(k_trace_partials<KK>, g, b, 0, s, op, v, u, part, m); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
   const int pairs = 2 * m * op.K;
-  hipLaunchKernelGGL(k_trace_pairs, dim3((pairs + TILE / WAVE - 1) / (TILE / WAVE)), dim3(TILE), 0, s, part, pairs,
+  GP_LAUNCH(k_trace_pairs, dim3((pairs + TILE / WAVE - 1) / (TILE / WAVE)), dim3(TILE), 0, s, part, pairs,
                      op.ntiles, pairbuf);
-  hipLaunchKernelGGL(k_trace_final, dim3(1), dim3(WAVE), 0, s, pairbuf, m, op.K, out);
+  GP_LAUNCH(k_trace_final, dim3(1), dim3(WAVE), 0, s, pairbuf, m, op.K, out);
   return hipGetLastError();
 }
 

@@ -11,9 +11,9 @@ hipError_t launch_rb_setup(hipStream_t s, const RbDev& rb, const double* B64, do
   const int gr = (rb.NR + TILE - 1) / TILE, gb = (rb.NB + TILE - 1) / TILE;
 #define X(KK)                                                                                         \
   case KK:                                                                                            \
-    if (gr > 0) hipLaunchKernelGGL(k_rb_setup_red<KK>, dim3(gr), dim3(TILE), 0, s, rb, B64, P64, P32, bad); \
+    if (gr > 0) GP_LAUNCH(k_rb_setup_red<KK>, dim3(gr), dim3(TILE), 0, s, rb, B64, P64, P32, bad); \
     if (gb > 0)                                                                                       \
-      hipLaunchKernelGGL(k_rb_setup_black<KK>, dim3(gb), dim3(TILE), 0, s, rb, B64, D64, D32, S64, S32, bad); \
+      GP_LAUNCH(k_rb_setup_black<KK>, dim3(gb), dim3(TILE), 0, s, rb, B64, D64, D32, S64, S32, bad); \
     break;
   RB_K_SWITCH(rb.K, X)
 #undef X
@@ -39,13 +39,13 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
   const int nchv = (R + rcv - 1) / rcv, nchb = (R + rcb - 1) / rcb;
 #define X(KK)                                                                                              \
   case KK:                                                                                                 \
-    hipLaunchKernelGGL(k_rb_split_voxels<KK>, grid2(rb.ntN, nchv), dim3(TILE), 0, s, rb, R, rcv, b, x, zero_guess, t, c, \
+    GP_LAUNCH(k_rb_split_voxels<KK>, grid2(rb.ntN, nchv), dim3(TILE), 0, s, rb, R, rcv, b, x, zero_guess, t, c, \
                        xB, bbpart);                                                                        \
     if (rb.ntB > 0) {                                                                                      \
       if (first.f32)                                                                                       \
-        hipLaunchKernelGGL((k_rb_split_black<KK, float>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f32); \
+        GP_LAUNCH((k_rb_split_black<KK, float>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f32); \
       else                                                                                                 \
-        hipLaunchKernelGGL((k_rb_split_black<KK, double>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f64); \
+        GP_LAUNCH((k_rb_split_black<KK, double>), grid2(rb.ntB, nchb), dim3(TILE), 0, s, rb, R, rcb, t, c, f64); \
     }                                                                                                      \
     break;
   RB_K_SWITCH(rb.K, X)
@@ -59,7 +59,7 @@ hipError_t launch_rb_recover(hipStream_t s, const RbDev& rb, int R, const RhsSta
                              const double* u64, const double* xB, double* x) {
   if (rb.ntN == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, t, u64, xB, x); break;
+  case KK: GP_LAUNCH(k_rb_recover<KK>, grid2(rb.ntN, R), dim3(TILE), 0, s, rb, st, t, u64, xB, x); break;
   RB_K_SWITCH(rb.K, X)
 #undef X
   return hipGetLastError();
@@ -70,9 +70,9 @@ hipError_t launch_rbg_red64(hipStream_t s, int K, const RbProb* probs, int nprob
 #define X(KK)                                                                                               \
   case KK:                                                                                                  \
     if constexpr (HoldRb<double, KK, 1>::v)                                                                 \
-      hipLaunchKernelGGL((k_rb_red<double, KK, true, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);     \
+      GP_LAUNCH((k_rb_red<double, KK, true, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);     \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_rb_red<double, KK, false, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      GP_LAUNCH((k_rb_red<double, KK, false, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
     break;
   RB_K_SWITCH(K, X)
 #undef X
@@ -82,9 +82,9 @@ hipError_t launch_rbg_red64(hipStream_t s, int K, const RbProb* probs, int nprob
 hipError_t launch_rbg_finalize(hipStream_t s, int kind, const RbProb* probs, int nprob, int nblocks) {
   if (nblocks == 0) return hipSuccess;
   if (kind == 0)
-    hipLaunchKernelGGL(k_rb_finalize<0>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
+    GP_LAUNCH(k_rb_finalize<0>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
   else
-    hipLaunchKernelGGL(k_rb_finalize<1>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
+    GP_LAUNCH(k_rb_finalize<1>, dim3(nblocks), dim3(FIN_WAVES * WAVE), 0, s, probs, nprob);
   return hipGetLastError();
 }
 

@@ -135,27 +135,27 @@ __global__ __launch_bounds__(256) void k_philox_raw(uint64_t seed, uint64_t stre
 hipError_t launch_rng_normal(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double* out) {
   if (n == 0) return hipSuccess;
   const size_t pairs = (n + 1) / 2;
-  hipLaunchKernelGGL(k_normal, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, seed, stream, n, out);
+  GP_LAUNCH(k_normal, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, seed, stream, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_rng_gamma(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, double shape,
                             const double* scale, double* out) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gamma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, stream, n, shape, scale, out);
+  GP_LAUNCH(k_gamma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, stream, n, shape, scale, out);
   return hipGetLastError();
 }
 
 hipError_t launch_rng_rademacher(hipStream_t s, uint64_t seed, uint64_t stream, size_t n, int8_t* out) {
   if (n == 0) return hipSuccess;
   const size_t blocks = (n + 127) / 128;
-  hipLaunchKernelGGL(k_rademacher, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s, seed, stream, n, out);
+  GP_LAUNCH(k_rademacher, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s, seed, stream, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_rng_raw(hipStream_t s, uint64_t seed, uint64_t stream, size_t nblocks, uint32_t* out) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_philox_raw, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s, seed, stream, nblocks,
+  GP_LAUNCH(k_philox_raw, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s, seed, stream, nblocks,
                      out);
   return hipGetLastError();
 }

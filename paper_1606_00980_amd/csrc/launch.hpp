@@ -1,10 +1,34 @@
 // Host-side launch entry points of the kernels (one definition per source file).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
 
 namespace gp {
+
+// Per-launch timing while profiling: the launches made between prof_begin
+// and prof_end carry the pair of events in their dispatch packets
+// (hipExtLaunchKernelGGL), the first launch's start and the last one's stop,
+// so that the elapsed time is the kernels' own, without the dispatch of the
+// packets.  Outside such a span `stop` is null and launches are plain.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool first = true;   // no launch has taken the start event yet
+};
+LaunchTiming& launch_timing();
+
+#define GP_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                        \
+  do {                                                                                            \
+    ::gp::LaunchTiming& lt_ = ::gp::launch_timing();                                              \
+    if (lt_.stop) {                                                                               \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, lt_.first ? lt_.start : nullptr,  \
+                            lt_.stop, 0, __VA_ARGS__);                                            \
+      lt_.first = false;                                                                          \
+    } else {                                                                                      \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                        \
+    }                                                                                             \
+  } while (0)
 
 // k_ops.hip
 hipError_t launch_grid_build(hipStream_t s, const uint8_t* mask, long ncell, int* counts, int* offsets,

@@ -24,9 +24,9 @@ namespace gp {
 #define GP_PC_CASE(KERNEL, KK)                                                                 \
   case KK:                                                                                     \
     if (pc == PC_BLOCK)                                                                        \
-      hipLaunchKernelGGL((KERNEL<T, PC_BLOCK, KK>), g, b, 0, s, probs, nprob, W);               \
+      GP_LAUNCH((KERNEL<T, PC_BLOCK, KK>), g, b, 0, s, probs, nprob, W);               \
     else                                                                                       \
-      hipLaunchKernelGGL((KERNEL<T, PC_JACOBI, KK>), g, b, 0, s, probs, nprob, W);              \
+      GP_LAUNCH((KERNEL<T, PC_JACOBI, KK>), g, b, 0, s, probs, nprob, W);              \
     break;
 #define GP_PC_CASE_k_refine(KK) GP_PC_CASE(k_refine, KK)
 #define GP_PC_CASE_k_matvec(KK) GP_PC_CASE(k_matvec, KK)
@@ -57,7 +57,7 @@ template <typename T>
 hipError_t launch_addsol_t(hipStream_t s, int K, const Prob* probs, int nprob, int W, int nblk) {
   const dim3 g(nblk), b(TILE);
   switch (K) {
-#define X(KK) case KK: hipLaunchKernelGGL((k_addsol<T, KK>), g, b, 0, s, probs, nprob, W); break;
+#define X(KK) case KK: GP_LAUNCH((k_addsol<T, KK>), g, b, 0, s, probs, nprob, W); break;
     GP_K_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

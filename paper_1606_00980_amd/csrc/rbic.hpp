@@ -800,9 +800,9 @@ inline dim3 grid2(int tiles, int R) { return dim3((unsigned)tiles, (unsigned)R);
 #define RB_HOLD_LAUNCH(KERN, KK, NBLK, TB, ...)                                  \
   do {                                                                           \
     if constexpr (HoldRb<TB, KK, NBLK>::v)                                       \
-      hipLaunchKernelGGL((KERN<T, KK, true>), __VA_ARGS__);                      \
+      GP_LAUNCH((KERN<T, KK, true>), __VA_ARGS__);                      \
     else                                                                         \
-      hipLaunchKernelGGL((KERN<T, KK, false>), __VA_ARGS__);                     \
+      GP_LAUNCH((KERN<T, KK, false>), __VA_ARGS__);                     \
   } while (0)
 
 template <typename T>
@@ -811,9 +811,9 @@ hipError_t launch_rbg_red_t(hipStream_t s, int K, const RbProb* probs, int nprob
 #define X(KK)                                                                                                    \
   case KK:                                                                                                       \
     if constexpr (HoldRb<T, KK, 1>::v)                                                                           \
-      hipLaunchKernelGGL((k_rb_red<T, KK, true, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);              \
+      GP_LAUNCH((k_rb_red<T, KK, true, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);              \
     else                                                                                                         \
-      hipLaunchKernelGGL((k_rb_red<T, KK, false, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);             \
+      GP_LAUNCH((k_rb_red<T, KK, false, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);             \
     break;
   RB_K_SWITCH(K, X)
 #undef X
@@ -828,7 +828,7 @@ template <typename T>
 hipError_t launch_rbg_refine_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
   if (W == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_refine<T, KK, false>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  case KK: GP_LAUNCH((k_rb_refine<T, KK, false>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
   RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();
@@ -840,11 +840,11 @@ hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int np
 #define X(KK)                                                                                   \
   case KK:                                                                                      \
     if constexpr (HoldRb<T, KK, 2>::v)                                                          \
-      hipLaunchKernelGGL((k_rb_matvec<T, KK, 2>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      GP_LAUNCH((k_rb_matvec<T, KK, 2>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
     else if constexpr (HoldRb<T, KK, 1>::v)                                                     \
-      hipLaunchKernelGGL((k_rb_matvec<T, KK, 1>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      GP_LAUNCH((k_rb_matvec<T, KK, 1>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
     else                                                                                        \
-      hipLaunchKernelGGL((k_rb_matvec<T, KK, 0>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      GP_LAUNCH((k_rb_matvec<T, KK, 0>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
     break;
   RB_K_SWITCH(K, X)
 #undef X
@@ -865,7 +865,7 @@ template <typename T>
 hipError_t launch_rbg_addsol_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
   if (W == 0) return hipSuccess;
 #define X(KK) \
-  case KK: hipLaunchKernelGGL((k_rb_addsol<T, KK>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
+  case KK: GP_LAUNCH((k_rb_addsol<T, KK>), dim3(W), dim3(TILE), 0, s, probs, nprob); break;
   RB_K_SWITCH(K, X)
 #undef X
   return hipGetLastError();

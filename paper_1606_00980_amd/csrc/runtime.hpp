@@ -200,10 +200,11 @@ void prof_add(gp_ctx* c, int kind, double units, double bytes);
     if ((ctx)->prof_on) {                                            \
       if (int st_ = prof_begin((ctx), &slot_)) return st_;           \
     }                                                                \
-    HIPTRY(launch);                                                  \
+    const hipError_t le_ = (launch);                                 \
     if ((ctx)->prof_on) {                                            \
       if (int st_ = prof_end((ctx), (kind), slot_)) return st_;      \
     }                                                                \
+    HIPTRY(le_);                                                     \
   } while (0)
 
 #define PROFILED_IF(on, ctx, kind, launch) \
