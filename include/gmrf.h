@@ -177,9 +177,11 @@ int gp_ctx_set_stream(gp_ctx* ctx, void* hip_stream);
 int gp_ctx_memory(const gp_ctx* ctx, size_t* used, size_t* budget);
 int gp_ctx_destroy(gp_ctx* ctx);
 /* gp_ctx_profile: enable (1) or disable (0) per-launch event timing on this
- * context; enabling clears the accumulated figures.  gp_ctx_profile_read
- * synchronises the stream and copies the figures of one GP_KERNEL_* kind
- * into *out (host).                                                          */
+ * context; enabling clears the accumulated figures.  While it is on, rounds
+ * run eagerly (no graph replay) and each launch's kernels carry a pair of
+ * HIP events in their dispatch packets, so a launch's time is its kernels'
+ * time.  gp_ctx_profile_read synchronises the stream and copies the figures
+ * of one GP_KERNEL_* kind into *out (host).                                  */
 int gp_ctx_profile(gp_ctx* ctx, int enable);
 int gp_ctx_profile_read(gp_ctx* ctx, int kind, gp_prof* out);
 
