@@ -19,6 +19,7 @@ enum ProfSlot : int {
   PF_ADDSOL_FRESH,   // first x += d from a zero start value (x written, not read)
 };
 constexpr int RCMAX = 16;    // right-hand sides per workgroup, upper bound
+constexpr int UPAIR_KMAX = 10;   // FP32 red-stage vectors stored in right-hand-side pairs up to this K
 constexpr int PC_JACOBI = 0; // preconditioner kinds as seen by the kernels
 constexpr int PC_BLOCK = 1;
 
@@ -136,6 +137,7 @@ struct RbProb {
   int Rc, nch;           // right-hand sides per inner work item, chunks of them
   int Rco, ncho;         // right-hand sides per outer (refine, x_B += d) work item, chunks of them
   int wB, wR, wO;        // first black-tile, red-tile and outer work item
+  int uw;                // right-hand sides per row set of u: 2 (pairs) or 1
 };
 
 // Packed index of the symmetric (k, j) entry, lower triangle row-major.

@@ -10,6 +10,11 @@ namespace gp {
 constexpr int WAVE = 64;
 constexpr int NXCD = 8;   // accelerator complex dies; workgroups are dealt to them round-robin
 
+// a * b + c rounded once (explicit, independent of the compiler's choice to
+// contract a product and a sum)
+__device__ __forceinline__ float fma_of(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_of(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);

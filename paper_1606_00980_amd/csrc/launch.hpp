@@ -123,13 +123,16 @@ hipError_t launch_rb_split(hipStream_t s, const RbDev& rb, int R, const double* 
 // and update, red-tile items for the red stages, black-tile items
 // of one right-hand side for refine and addsol.  T is the inner precision.
 template <typename T> hipError_t launch_rbg_red(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
-template <typename T> hipError_t launch_rbg_matvec(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
+// pairs: some member stores the red-stage vector in right-hand-side pairs
+template <typename T>
+hipError_t launch_rbg_matvec(hipStream_t s, int K, const RbProb* probs, int nprob, int W, bool pairs);
 template <typename T> hipError_t launch_rbg_update(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 template <typename T> hipError_t launch_rbg_refine(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 template <typename T> hipError_t launch_rbg_addsol(hipStream_t s, int K, const RbProb* probs, int nprob, int W);
 #define GP_RBG_DECL(T)                                                                                       \
   template <> hipError_t launch_rbg_red<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);        \
-  template <> hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
+  template <> hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W,      \
+                                              bool pairs);                                                    \
   template <> hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
   template <> hipError_t launch_rbg_refine<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);     \
   template <> hipError_t launch_rbg_addsol<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W);

@@ -424,6 +424,8 @@ __device__ __forceinline__ void voxel_offsets(const OpDev& op, int nn, unsigned 
 
 // y += S x for a symmetric K x K block S given by its packed entries
 // s(i) = S[k][j], i = pk(k, j), each read once.
+// Every product-sum is one explicit fused multiply-add, so that the result
+// does not depend on where the compiler inlines the block product.
 template <int K, typename V, typename GetS>
 __device__ __forceinline__ void sym_apply(const GetS& s, const V (&x)[K], V (&y)[K]) {
   #pragma unroll
@@ -431,8 +433,8 @@ __device__ __forceinline__ void sym_apply(const GetS& s, const V (&x)[K], V (&y)
   #pragma unroll
     for (int j = 0; j <= k; ++j) {
       const V v = s(pk(k, j));
-      y[k] += v * x[j];
-      if (j != k) y[j] += v * x[k];
+      y[k] = fma_of(v, x[j], y[k]);
+      if (j != k) y[j] = fma_of(v, x[k], y[j]);
     }
   }
 }

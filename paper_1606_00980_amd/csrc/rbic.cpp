@@ -208,19 +208,32 @@ int rb_check_built(gp_op* op) {
 }
 
 // ------------------------------------------------------------ members
+namespace {
+// bytes of one workspace slot (every slot at least 256, also an empty one)
+size_t slot_bytes(size_t bytes) { return align_up(std::max<size_t>(bytes, 1), 256); }
+// right-hand sides per row set of the red-stage vector u: pairs for an FP32
+// solve of two or more with K <= UPAIR_KMAX, else one
+int u_width(const gp_op* op, int R, bool f32) { return f32 && op->K <= UPAIR_KMAX && R >= 2 ? 2 : 1; }
+// entries of u (an odd R takes a pair's worth for its last one)
+size_t u_entries(const gp_op* op, int R, bool f32) {
+  const int w = u_width(op, R, f32);
+  return (size_t)((R + w - 1) / w * w) * op->K * op->rb->NR;
+}
+}  // namespace
+
 size_t rb_member_bytes(const gp_op* op, int R, bool f32) {
   const RbData& d = *op->rb;
   const size_t tsz = f32 ? sizeof(float) : sizeof(double);
   const size_t nbv = (size_t)R * op->K * d.NB, nrv = (size_t)R * op->K * d.NR;
   const int pstride = std::max(d.ntB, 1);
   size_t b = 0;
-  b += align_up((size_t)NPART * R * pstride * 8, 256);        // partials
-  b += align_up((size_t)R * std::max(d.ntN, 1) * 8, 256);     // ||b||^2 partials
-  b += 2 * align_up(nbv * 8, 256);                            // c64, xB
-  b += 2 * align_up(nrv * 8, 256);                            // u64, t64
-  b += 4 * align_up(nbv * tsz, 256);                          // d, r, p, q
-  b += align_up(nrv * tsz, 256);                              // u of the red stage
-  b += align_up(NPROF * sizeof(long long), 256);              // work counters
+  b += slot_bytes((size_t)NPART * R * pstride * 8);       // partials
+  b += slot_bytes((size_t)R * std::max(d.ntN, 1) * 8);    // ||b||^2 partials
+  b += 2 * slot_bytes(nbv * 8);                           // c64, xB
+  b += 2 * slot_bytes(nrv * 8);                           // u64, t64
+  b += 4 * slot_bytes(nbv * tsz);                         // d, r, p, q
+  b += slot_bytes(u_entries(op, R, f32) * tsz);           // u of the red stage
+  b += slot_bytes(NPROF * sizeof(long long));             // work counters
   return b;
 }
 
@@ -232,7 +245,7 @@ void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveC
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* at = mem + off;
-    off += align_up(std::max<size_t>(bytes, 1), 256);
+    off += slot_bytes(bytes);
     return at;
   };
   RbProb& P = out->desc;
@@ -248,7 +261,8 @@ void rb_member(gp_op* op, int R, bool f32, char* mem, RhsState* st, const SolveC
   P.r = take(nbv * tsz);
   P.p = take(nbv * tsz);
   P.q = take(nbv * tsz);
-  P.u = take(nrv * tsz);
+  P.u = take(u_entries(op, R, f32) * tsz);
+  P.uw = u_width(op, R, f32);
   long long* pf = (long long*)take(NPROF * sizeof(long long));
   out->prof = prof ? pf : nullptr;
   P.rb.prof = out->prof;
@@ -266,8 +280,9 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile, bool outer_chunks
   std::vector<RbGroup> gs;
   const int fpb = finalize_rhs_per_block();
   for (int j = 0; j < n; ++j) {
-    if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0});
+    if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0, 1});
     gs.back().count += 1;
+    gs.back().uw = std::max(gs.back().uw, h[j].uw);
   }
   for (RbGroup& g : gs) {
     // right-hand sides per inner work item: the tuned or requested value, else
@@ -325,7 +340,7 @@ int outer_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, boo
 template <typename T>
 int inner_step(gp_ctx* c, hipStream_t q, const RbGroup& g, const RbProb* dp, bool pf) {
   PROFILED_IF(pf, c, GP_KERNEL_RB_RED, launch_rbg_red<T>(q, g.K, dp, g.count, g.WR));
-  PROFILED_IF(pf, c, GP_KERNEL_RB_MATVEC, launch_rbg_matvec<T>(q, g.K, dp, g.count, g.WB));
+  PROFILED_IF(pf, c, GP_KERNEL_RB_MATVEC, launch_rbg_matvec<T>(q, g.K, dp, g.count, g.WB, g.uw == 2));
   HIPTRY(launch_rbg_finalize(q, 1, dp, g.count, g.F));
   PROFILED_IF(pf, c, GP_KERNEL_RB_UPDATE, launch_rbg_update<T>(q, g.K, dp, g.count, g.WB));
   return GP_OK;

@@ -247,6 +247,94 @@ __device__ __forceinline__ void neighbour_sum_v(const int (&nb)[6], const RbVec<
   neighbour_sum<T, K>(nb, v.s, s);
 }
 
+// The red-stage vector u of an FP32 inner solve of two or more right-hand
+// sides stores them in pairs, [ceil(R/2)][K][NR][2]: row k of red position j
+// holds (u_{2h}, u_{2h+1}) in 8 bytes, so the black stage gathers a pair's two
+// values with one access per neighbour and row (half the gather instructions
+// of two separate rows).  A single right-hand side keeps [K][NR] (pair width
+// 1: its gathers stay contiguous), and so do FP64 inner vectors and K above
+// UPAIR_KMAX (where a pair's gathers would not fit in registers).
+template <typename T, int K> struct UPaired {
+  static constexpr bool v = sizeof(T) == 4 && K <= UPAIR_KMAX;
+};
+
+template <int K> struct UPairs {
+  Rsrc rs;
+  unsigned row;   // NR * 4 * width bytes
+  unsigned sh;    // log2 of the pair width (0 or 1)
+  // the pair (or single row set) holding right-hand side r; w: pair width
+  __device__ __forceinline__ UPairs(const float* u, int r, int NR, int w)
+      : rs(make_rsrc(u + (size_t)(r >> (w >> 1)) * K * NR * w, (size_t)K * NR * 4 * w)),
+        row((unsigned)NR * 4u * (unsigned)w), sh((unsigned)w >> 1) {}
+  // both values of row k at red position j (pair width 2)
+  __device__ __forceinline__ void ld2(int k, int j, float& a, float& b) const {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (unsigned)j * 8u, (unsigned)k * row, 0);
+    // the elements copied out first: a bit cast of a vector element in place
+    // reads the vector's first element
+    const unsigned lo = v[0], hi = v[1];
+    a = __builtin_bit_cast(float, lo);
+    b = __builtin_bit_cast(float, hi);
+  }
+  // the value of right-hand side 2h + half alone (half = 0 at width 1)
+  __device__ __forceinline__ float ld1(int k, int j, int half) const {
+    return bload<float>(rs, ((unsigned)j << (2u + sh)) + 4u * (unsigned)half, (unsigned)k * row);
+  }
+  __device__ __forceinline__ void st2(int k, int j, float a, float b) const {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0));
+    V2 v;
+    v[0] = __builtin_bit_cast(unsigned, a);
+    v[1] = __builtin_bit_cast(unsigned, b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (unsigned)j * 8u, (unsigned)k * row, 0);
+  }
+  __device__ __forceinline__ void st1(int k, int j, int half, float a) const {
+    bstore(rs, ((unsigned)j << (2u + sh)) + 4u * (unsigned)half, (unsigned)k * row, a);
+  }
+};
+
+// neighbour_sum over both right-hand sides of a pair (the additions in
+// neighbour_sum's order, so each sum is bitwise the single one's)
+template <int K>
+__device__ __forceinline__ void neighbour_sum_pair(const int (&nb)[6], const UPairs<K>& u, float (&s0)[K],
+                                                   float (&s1)[K]) {
+  float t0[6][K], t1[6][K];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int j = nb[d] < 0 ? 0 : nb[d];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u.ld2(k, j, t0[d][k], t1[d][k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) s0[k] = s1[k] = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s0[k] += nb[d] < 0 ? 0.0f : t0[d][k];
+      s1[k] += nb[d] < 0 ? 0.0f : t1[d][k];
+    }
+  }
+}
+
+// neighbour_sum of right-hand side 2h + half of a pair alone
+template <int K>
+__device__ __forceinline__ void neighbour_sum_half(const int (&nb)[6], const UPairs<K>& u, int half,
+                                                   float (&s)[K]) {
+  float t[6][K];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int j = nb[d] < 0 ? 0 : nb[d];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[d][k] = u.ld1(k, j, half);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] += nb[d] < 0 ? 0.0f : t[d][k];
+  }
+}
+
 __device__ __forceinline__ void load_nb(const int* tab, int n, int i, int (&nb)[6]) {
 #pragma unroll
   for (int d = 0; d < 6; ++d) nb[d] = tab[(size_t)d * n + i];
@@ -462,11 +550,11 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbProb* __restrict__ prob
   load_nb(rb.nbR, rb.NR, j, nb);
   const unsigned oj = (unsigned)j * (unsigned)sizeof(T);
   const Packed<T, K, HOLD> Pn(RbT<T>::P(rb), rb.NR, oj);
-#pragma unroll 1
-  for (int r = w.r0; r < w.r1; ++r) {
-    if (!red_active(rb, st[r], want)) continue;
-    const RbVec<T, K> vs(v + (size_t)r * K * rb.NB, rb.NB), us(u + (size_t)r * K * rb.NR, rb.NR);
-    T s[K], y[K];
+  // y = Q_nn^{-1} (alpha .* sum_{m ~ n} v_m) for right-hand side r
+  auto stage = [&](int r, T (&y)[K]) {
+#pragma clang fp contract(off)
+    const RbVec<T, K> vs(v + (size_t)r * K * rb.NB, rb.NB);
+    T s[K];
     neighbour_sum_v<T, K>(nb, vs, s);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -474,7 +562,53 @@ __global__ __launch_bounds__(TILE) void k_rb_red(const RbProb* __restrict__ prob
       y[k] = 0;
     }
     sym_apply<K>(Pn, s, y);
-    us.store(j, y);
+  };
+  if constexpr (!OUTER && UPaired<T, K>::v) {
+    // both right-hand sides of a pair in the item: one 8-byte store per row
+    // (an inactive partner's half written as zero: no kernel reads it before
+    // its next red stage)
+#pragma unroll 1
+    for (int r = w.r0; r < w.r1;) {
+      const UPairs<K> up((const float*)u, r, rb.NR, P.uw);
+      const int half = r & (P.uw - 1);
+      if (P.uw == 2 && half == 0 && r + 1 < w.r1) {
+        const bool a0 = red_active(rb, st[r], want), a1 = red_active(rb, st[r + 1], want);
+        if (a0 || a1) {
+          T y0[K], y1[K];
+          if (a0) {
+            stage(r, y0);
+          } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) y0[k] = 0;
+          }
+          if (a1) {
+            stage(r + 1, y1);
+          } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) y1[k] = 0;
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) up.st2(k, j, y0[k], y1[k]);
+        }
+        r += 2;
+      } else {
+        if (red_active(rb, st[r], want)) {
+          T y[K];
+          stage(r, y);
+#pragma unroll
+          for (int k = 0; k < K; ++k) up.st1(k, j, half, y[k]);
+        }
+        r += 1;
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int r = w.r0; r < w.r1; ++r) {
+      if (!red_active(rb, st[r], want)) continue;
+      T y[K];
+      stage(r, y);
+      RbVec<T, K>(u + (size_t)r * K * rb.NR, rb.NR).store(j, y);
+    }
   }
 }
 
@@ -557,13 +691,16 @@ template <typename T, int K, typename BD, typename BS>
 __device__ __forceinline__ void black_stage(const RbDev& rb, const BD& D, const BS& S, const T (&p)[K],
                                             const T (&rr)[K], const T (&s)[K], bool valid, int ii,
                                             const RbVec<T, K>& qs, double (&acc)[7]) {
+  // products and sums written out as fused multiply-adds, nothing contracted
+  // by the compiler: the result is the same in every path that calls this
+#pragma clang fp contract(off)
   T y[K], q[K], z[K], t[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) y[k] = 0;
   sym_apply<K>(D, p, y);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    q[k] = y[k] - RbT<T>::alpha(rb, k) * s[k];
+    q[k] = fma_of(-RbT<T>::alpha(rb, k), s[k], y[k]);
     z[k] = t[k] = 0;
   }
   if (valid) qs.store(ii, q);
@@ -572,13 +709,13 @@ __device__ __forceinline__ void black_stage(const RbDev& rb, const BD& D, const 
   T a[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    a[0] += p[k] * q[k];
-    a[1] += rr[k] * z[k];
-    a[2] += q[k] * z[k];
-    a[3] += q[k] * t[k];
-    a[4] += rr[k] * rr[k];
-    a[5] += q[k] * rr[k];
-    a[6] += q[k] * q[k];
+    a[0] = fma_of(p[k], q[k], a[0]);
+    a[1] = fma_of(rr[k], z[k], a[1]);
+    a[2] = fma_of(q[k], z[k], a[2]);
+    a[3] = fma_of(q[k], t[k], a[3]);
+    a[4] = fma_of(rr[k], rr[k], a[4]);
+    a[5] = fma_of(q[k], rr[k], a[5]);
+    a[6] = fma_of(q[k], q[k], a[6]);
   }
 #pragma unroll
   for (int e = 0; e < 7; ++e) acc[e] = valid ? (double)a[e] : 0.0;
@@ -587,8 +724,10 @@ __device__ __forceinline__ void black_stage(const RbDev& rb, const BD& D, const 
 // Black stage of q = S p after a separate red stage (u read from memory).
 // HOLD: the voxel blocks held in registers across the work item's
 // right-hand sides, 2 = Q_mm and S_m^{-1}, 1 = S_m^{-1} only (it is applied
-// twice per right-hand side), 0 = neither.
-template <typename T, int K, int HOLD>
+// twice per right-hand side), 0 = neither.  PAIRS: some member of the launch
+// stores u in pairs (the pair and single paths; without, the fewer registers
+// of the single path alone).
+template <typename T, int K, int HOLD, bool PAIRS>
 __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ probs, int nprob) {
   const RbWork w = rb_item<RBW_BLACK>(probs, nprob);
   const RbProb& P = probs[w.p];
@@ -608,19 +747,54 @@ __global__ __launch_bounds__(TILE) void k_rb_matvec(const RbProb* __restrict__ p
   const Packed<T, K, (HOLD >= 2)> D(RbT<T>::D(rb), rb.NB, oT);
   const Packed<T, K, (HOLD >= 1)> S(RbT<T>::S(rb), rb.NB, oT);
   ItemSums<7> sums;
+  auto vec = [&](const void* base, int r) { return RbVec<T, K>((const T*)base + (size_t)r * K * rb.NB, rb.NB); };
+  auto qvec = [&](int r) { return RbVec<T, K>((T*)P.q + (size_t)r * K * rb.NB, rb.NB); };
 #pragma unroll 1
-  for (int r = w.r0; r < w.r1; ++r) {
-    if (st[r].phase != PH_INNER) continue;
-    const size_t off = (size_t)r * K * rb.NB;
-    const RbVec<T, K> ps((const T*)P.p + off, rb.NB), rs((const T*)P.r + off, rb.NB), qs((T*)P.q + off, rb.NB);
-    const RbVec<T, K> us((const T*)P.u + (size_t)r * K * rb.NR, rb.NR);
-    T p[K], rr[K], s[K];
-    ps.load(ii, p);
-    rs.load(ii, rr);
-    neighbour_sum_v<T, K>(nb, us, s);
-    double acc[7];
-    black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qs, acc);
-    sums.add(r - w.r0, acc);
+  for (int r = w.r0; r < w.r1;) {
+    if constexpr (PAIRS) {
+      // a pair with both right-hand sides in the item and in the inner phase
+      // gathers u once for the two
+      const int half = r & (P.uw - 1);
+      const bool pair = P.uw == 2 && half == 0 && r + 1 < w.r1;
+      const bool a0 = st[r].phase == PH_INNER, a1 = pair && st[r + 1].phase == PH_INNER;
+      const UPairs<K> up((const float*)P.u, r, rb.NR, P.uw);
+      if (a0 && a1) {
+        T p0[K], r0[K], p1[K], r1[K], s0[K], s1[K];
+        vec(P.p, r).load(ii, p0);
+        vec(P.r, r).load(ii, r0);
+        vec(P.p, r + 1).load(ii, p1);
+        vec(P.r, r + 1).load(ii, r1);
+        neighbour_sum_pair<K>(nb, up, s0, s1);
+        double acc[7];
+        black_stage<T, K>(rb, D, S, p0, r0, s0, valid, ii, qvec(r), acc);
+        sums.add(r - w.r0, acc);
+        black_stage<T, K>(rb, D, S, p1, r1, s1, valid, ii, qvec(r + 1), acc);
+        sums.add(r + 1 - w.r0, acc);
+      } else if (a0 || a1) {
+        // the same in every lane (states are per right-hand side)
+        const int ra = __builtin_amdgcn_readfirstlane(a0 ? r : r + 1);
+        T p[K], rr[K], s[K];
+        vec(P.p, ra).load(ii, p);
+        vec(P.r, ra).load(ii, rr);
+        neighbour_sum_half<K>(nb, up, ra & (P.uw - 1), s);
+        double acc[7];
+        black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qvec(ra), acc);
+        sums.add(ra - w.r0, acc);
+      }
+      r += pair ? 2 : 1;
+    } else {
+      if (st[r].phase == PH_INNER) {
+        const RbVec<T, K> us((const T*)P.u + (size_t)r * K * rb.NR, rb.NR);
+        T p[K], rr[K], s[K];
+        vec(P.p, r).load(ii, p);
+        vec(P.r, r).load(ii, rr);
+        neighbour_sum_v<T, K>(nb, us, s);
+        double acc[7];
+        black_stage<T, K>(rb, D, S, p, rr, s, valid, ii, qvec(r), acc);
+        sums.add(r - w.r0, acc);
+      }
+      r += 1;
+    }
   }
   sums.flush(P.pr.part, (size_t)R * pstride, w.r0, w.r1 - w.r0, pstride, w.tile);
 }
@@ -835,19 +1009,30 @@ hipError_t launch_rbg_refine_t(hipStream_t s, int K, const RbProb* probs, int np
 }
 
 template <typename T>
-hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {
+hipError_t launch_rbg_matvec_t(hipStream_t s, int K, const RbProb* probs, int nprob, int W, bool pairs) {
   if (W == 0) return hipSuccess;
+#define MV(KK, H)                                                                                \
+  do {                                                                                           \
+    if constexpr (UPaired<T, KK>::v) {                                                           \
+      if (pairs) {                                                                               \
+        GP_LAUNCH((k_rb_matvec<T, KK, H, true>), dim3(W), dim3(TILE), 0, s, probs, nprob);     \
+        break;                                                                                   \
+      }                                                                                          \
+    }                                                                                            \
+    GP_LAUNCH((k_rb_matvec<T, KK, H, false>), dim3(W), dim3(TILE), 0, s, probs, nprob);        \
+  } while (0)
 #define X(KK)                                                                                   \
   case KK:                                                                                      \
     if constexpr (HoldRb<T, KK, 2>::v)                                                          \
-      GP_LAUNCH((k_rb_matvec<T, KK, 2>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      MV(KK, 2);                                                                                \
     else if constexpr (HoldRb<T, KK, 1>::v)                                                     \
-      GP_LAUNCH((k_rb_matvec<T, KK, 1>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      MV(KK, 1);                                                                                \
     else                                                                                        \
-      GP_LAUNCH((k_rb_matvec<T, KK, 0>), dim3(W), dim3(TILE), 0, s, probs, nprob);    \
+      MV(KK, 0);                                                                                \
     break;
   RB_K_SWITCH(K, X)
 #undef X
+#undef MV
   return hipGetLastError();
 }
 
@@ -881,8 +1066,8 @@ hipError_t launch_rbg_addsol_t(hipStream_t s, int K, const RbProb* probs, int np
     return launch_rbg_refine_t<T>(s, K, probs, nprob, W);                                                   \
   }                                                                                                         \
   template <>                                                                                               \
-  hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \
-    return launch_rbg_matvec_t<T>(s, K, probs, nprob, W);                                                   \
+  hipError_t launch_rbg_matvec<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W, bool pairs) { \
+    return launch_rbg_matvec_t<T>(s, K, probs, nprob, W, pairs);                                            \
   }                                                                                                         \
   template <>                                                                                               \
   hipError_t launch_rbg_update<T>(hipStream_t s, int K, const RbProb* probs, int nprob, int W) {           \

@@ -276,6 +276,7 @@ struct RbMember {
 // finalising workgroups.
 struct RbGroup {
   int K, first, count, WB, WR, WO, F;
+  int uw;   // 2 when some member stores the red-stage vector in pairs, else 1
 };
 // Device bytes of a member's vectors and partials (states excluded).
 size_t rb_member_bytes(const gp_op* op, int R, bool f32);
