@@ -582,12 +582,21 @@ int run_group(gp_ctx* c, const std::vector<Item>& items, const gp_opts& o, gp_st
       return fail(GP_ERR_INVALID_ARG, "operator needs gp_op_set_blocks and gp_op_set_alpha first");
     totalR += (size_t)it.R;
   }
-  // preconditioners
-  for (const Item& it : items) {
-    if (it.R > 0 && it.op->pc_built != o.precond) {
-      int st = build_precond(it.op, o.precond);
-      if (st) return st;
-      it.op->pc_want = o.precond;
+  // preconditioners (the red-black set-ups of many operators side by side)
+  if (o.precond == GP_PRECOND_RB_IC0) {
+    std::vector<gp_op*> todo;
+    for (const Item& it : items)
+      if (it.R > 0 && it.op->pc_built != o.precond && std::find(todo.begin(), todo.end(), it.op) == todo.end())
+        todo.push_back(it.op);
+    if (int st = rb_build_ops(c, todo)) return st;
+    for (gp_op* op : todo) op->pc_want = o.precond;
+  } else {
+    for (const Item& it : items) {
+      if (it.R > 0 && it.op->pc_built != o.precond) {
+        int st = build_precond(it.op, o.precond);
+        if (st) return st;
+        it.op->pc_want = o.precond;
+      }
     }
   }
   // the red-black incomplete Cholesky preconditioner has a solver of its own:

@@ -174,24 +174,45 @@ void rb_release(gp_op* op) {
   op->rb = nullptr;
 }
 
-int rb_build(gp_op* op) {
-  gp_ctx* c = op->ctx;
-  if (!op->rb) {
-    if (int st = build_lists(op)) {
-      rb_release(op);
-      return st;
-    }
+namespace {
+
+int rb_lists(gp_op* op) {
+  if (op->rb) return GP_OK;
+  if (int st = build_lists(op)) {
+    rb_release(op);
+    return st;
   }
+  return GP_OK;
+}
+
+// The blocks of op's preconditioner, enqueued on q (the colour lists built).
+int rb_setup_on(gp_op* op, hipStream_t q) {
+  gp_ctx* c = op->ctx;
   RbData& d = *op->rb;
   const RbDev h = rb_dev(op);
-  if (int st = reset_bad(op)) return st;
-  PROFILED(c, GP_KERNEL_PRECOND, launch_rb_setup(c->stream, h, op->B64, d.P64, d.P32, d.D64, d.D32, d.S64, d.S32,
-                                                  op->d_bad));
+  HIPTRY(hipMemsetD32Async((hipDeviceptr_t)op->d_bad, INT_MAX, 1, q));
+  PROFILED(c, GP_KERNEL_PRECOND, launch_rb_setup(q, h, op->B64, d.P64, d.P32, d.D64, d.D32, d.S64, d.S32, op->d_bad));
   // the flag is read with the first states of the solve that follows (one
   // wait fewer); that solve then fails with GP_ERR_NOT_SPD
   d.check_bad = true;
   op->pc_built = GP_PRECOND_RB_IC0;
   return GP_OK;
+}
+
+template <typename F>
+int fork_items(gp_ctx* c, hipStream_t s, int n, F&& launch);
+
+}  // namespace
+
+int rb_build(gp_op* op) {
+  if (int st = rb_lists(op)) return st;
+  return rb_setup_on(op, op->ctx->stream);
+}
+
+int rb_build_ops(gp_ctx* c, const std::vector<gp_op*>& ops) {
+  for (gp_op* op : ops)
+    if (int st = rb_lists(op)) return st;
+  return fork_items(c, c->stream, (int)ops.size(), [&](hipStream_t q, int i) { return rb_setup_on(ops[i], q); });
 }
 
 int rb_check_built(gp_op* op) {

@@ -235,11 +235,15 @@ bool valid_opts(const gp_opts& o, std::string* why);
 void plan_round(const std::vector<RhsState>& hs, const gp_opts& o, bool f32, int chunk, int* round_len,
                 uint64_t* round_mask);
 // Launch the graph cached under key on the context's stream, capturing it
-// first from enqueue(capture stream) when absent (at most 64 are kept).
+// first from enqueue(capture stream) when absent (the least recently used is
+// dropped beyond GRAPH_CACHE).
 int graph_replay(gp_ctx* c, const std::string& key, const std::function<int(hipStream_t)>& enqueue);
 // Red-black incomplete Cholesky preconditioner (rbic.cpp): set-up for op, the
 // grouped solves, and release of its data.
 int rb_build(gp_op* op);
+// The set-up of several operators (distinct), their launches side by side on
+// branch streams when there are many.
+int rb_build_ops(gp_ctx* c, const std::vector<gp_op*>& ops);
 // Reads the set-up's positive-definiteness flag if it has not been read yet
 // (waits for the stream); GP_ERR_NOT_SPD when a block failed.
 int rb_check_built(gp_op* op);
