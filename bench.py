@@ -45,7 +45,7 @@ METRIC = "PCG solves/s @ rel-res 1e-8 + matvec HBM GB/s %peak; served p50/p99 la
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1606_00980_amd", "csrc", f)
                   for f in ("pcg.hpp", "device.hpp", "common.hpp", "rbic.hpp", "k_rbic_f32.hip", "k_rbic_f64.hip",
-                            "spd.hpp")]
+                            "spd.hpp", "k_ops.hip")]
 
 
 def kernel_source_hash() -> str:
