@@ -303,7 +303,6 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile, bool outer_chunks
   for (int j = 0; j < n; ++j) {
     if (gs.empty() || gs.back().K != h[j].rb.K) gs.push_back(RbGroup{h[j].rb.K, j, 0, 0, 0, 0, 0, 1});
     gs.back().count += 1;
-    gs.back().uw = std::max(gs.back().uw, h[j].uw);
   }
   for (RbGroup& g : gs) {
     // right-hand sides per inner work item: the tuned or requested value, else
@@ -325,6 +324,11 @@ std::vector<RbGroup> rb_groups(RbProb* h, int n, int rhs_tile, bool outer_chunks
       RbProb& P = h[j];
       P.Rc = std::max(1, std::min(Rc, P.pr.R));
       P.nch = (P.pr.R + P.Rc - 1) / P.Rc;
+      // pairs only where work items hold them: with one right-hand side per
+      // item u keeps one per row (its gathers contiguous; the memory carved
+      // for pairs holds that layout too)
+      if (P.Rc < 2) P.uw = 1;
+      g.uw = std::max(g.uw, P.uw);
       P.wB = g.WB;
       g.WB += P.rb.ntB * P.nch;
       P.wR = g.WR;
@@ -609,7 +613,7 @@ int rb_solve_group(gp_ctx* c, const std::vector<RbOpItems>& ops_in, const gp_opt
                     (f32 ? "f" : "d");
   for (const RbGroup& g : groups)
     key += "|" + std::to_string(g.K) + "," + std::to_string(g.count) + "," + std::to_string(g.WB) + "," +
-           std::to_string(g.WR) + "," + std::to_string(g.WO) + "," + std::to_string(g.F);
+           std::to_string(g.WR) + "," + std::to_string(g.WO) + "," + std::to_string(g.F) + "," + std::to_string(g.uw);
   auto run_round = [&](int len, uint64_t mask, bool tail, bool first) -> int {
     if (!graphs) return rb_enqueue_round(c, s, f32, groups, c->d_rbp, len, mask, tail, first, true, false);
     return graph_replay(c,
