@@ -475,3 +475,45 @@ def test_grouped_operators_match_alone_bitwise(g, ctx, torch_cuda, precision):
         torch_cuda.cuda.synchronize()
         for op in ops:
             g.gp_op_destroy(op)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_many_operators_and_items_match_alone_bitwise(g, ctx, torch_cuda, precision):
+    """Nine operators (K = 2..5) with two items each: enough set-ups and items
+    that the grouped solve runs the preconditioner set-ups, the splits and the
+    recoveries on branch streams side by side.  Every item's solution equals
+    bitwise the one its operator gives alone (one item at a time, everything
+    in order on one stream), and its residual meets the tolerance."""
+    shapes = [((17, 15, 9), 2), ((13, 12, 10), 3), ((19, 11, 8), 4), ((12, 12, 12), 5), ((21, 9, 7), 3),
+              ((14, 16, 6), 2), ((11, 13, 9), 5), ((16, 10, 11), 4), ((15, 15, 5), 3)]
+    ws = [synth.tiny(d, 6, K, seed=120 + i) for i, (d, K) in enumerate(shapes)]
+    ops = [make_op(g, ctx, torch_cuda, w) for w in ws]
+    try:
+        prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
+        o = g.gp_opts_default(tol=1e-10, precond=g.GP_PRECOND_RB_IC0, precision=prec, zero_guess=1)
+        items = []   # (operator index, b) two per operator: 3 and 2 right-hand sides
+        for i, w in enumerate(ws):
+            items.append((i, rhs(w, 3, 130 + 2 * i)))
+            items.append((i, np.random.default_rng(131 + 2 * i).standard_normal((2, w.K, w.N))))
+        alone = []
+        for i, b in items:
+            x = torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda")
+            _, st = g.gp_solve(ops[i], b.shape[0], dev(torch_cuda, b), x, o)
+            assert all(s["status"] == g.GP_OK for s in st)
+            alone.append(x.cpu().numpy())
+        for op, w in zip(ops, ws):
+            g.gp_op_set_alpha(op, w.alpha)   # every factor rebuilt by the grouped solve
+        xs = [torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda") for _, b in items]
+        bd = [dev(torch_cuda, b) for _, b in items]
+        _, stats = g.gp_solve_batch(ctx, [(ops[i], b.shape[0], bb, x) for (i, b), bb, x in zip(items, bd, xs)], o)
+        assert len(stats) == sum(b.shape[0] for _, b in items) and all(s["status"] == g.GP_OK for s in stats)
+        for n, ((i, b), x, a) in enumerate(zip(items, xs, alone)):
+            xh = x.cpu().numpy()
+            assert np.array_equal(xh, a), n
+            w = ws[i]
+            Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
+            assert np.all(orc.relres(Q, xh, b) <= 1e-10), n
+    finally:
+        torch_cuda.cuda.synchronize()
+        for op in ops:
+            g.gp_op_destroy(op)
