@@ -407,10 +407,11 @@ def test_degenerate_colourings(g, ctx, torch_cuda, precision, cells):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,conn,K", [((29, 23, 17), 6, 3), ((37, 35, 1), 4, 2), ((21, 19, 13), 6, 10)])
 def test_rhs_per_work_item_does_not_change_results(g, ctx, torch_cuda, precision, dims, conn, K):
-    """The work decomposition (1, 2, 4 or 8 right-hand sides per workgroup of
-    the solver-round launches) changes neither the arithmetic nor its order:
-    bitwise equal solutions and iteration counts, which match the oracle's
-    direct solve."""
+    """The work decomposition (1, 2, 3, 4 or 8 right-hand sides per workgroup
+    of the solver-round launches; with 3 a pair of the paired red-stage vector
+    is split between two work items) changes neither the arithmetic nor its
+    order: bitwise equal solutions and iteration counts, which match the
+    oracle's direct solve."""
     w = synth.tiny(dims, conn, K, seed=70 + K)
     op = make_op(g, ctx, torch_cuda, w)
     try:
@@ -418,13 +419,13 @@ def test_rhs_per_work_item_does_not_change_results(g, ctx, torch_cuda, precision
         b = rhs(w, R, 71)
         prec = g.GP_PREC_FP64 if precision == "fp64" else g.GP_PREC_FP32_REFINE64
         out = {}
-        for rt in (1, 2, 4, 8):
+        for rt in (1, 2, 3, 4, 8):
             x = torch_cuda.zeros(b.shape, dtype=torch_cuda.float64, device="cuda")
             o = g.gp_opts_default(tol=tol, precond=g.GP_PRECOND_RB_IC0, precision=prec, rhs_tile=rt, zero_guess=1)
             _, stats = g.gp_solve(op, R, dev(torch_cuda, b), x, o)
             assert all(s["status"] == g.GP_OK for s in stats)
             out[rt] = (x.cpu().numpy(), [(s["inner_iters"], s["outer_steps"]) for s in stats])
-        for rt in (2, 4, 8):
+        for rt in (2, 3, 4, 8):
             assert np.array_equal(out[rt][0], out[1][0]), rt
             assert out[rt][1] == out[1][1], rt
         Q = orc.precision(orc.grid(w.mask, w.conn), w.alpha, w.B)
